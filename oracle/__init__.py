@@ -1,0 +1,214 @@
+"""RecSplit CPU oracle (test infrastructure only).
+
+ctypes binding of ``recsplit_oracle.c``: a plain, single-threaded C
+implementation of the whole RecSplit construction and lookup, written from the
+paper (Esposito, Mueller Graf, Vigna 2019).  Only the test-suite, the smoke
+check and the CPU-baseline leg of the benchmark may use this package; the GPU
+library never imports, links or calls it.
+
+Keys are passed either as a ``numpy.uint64`` array, or as a pair
+``(data: uint8[], offsets: uint64[n+1])`` for byte strings.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "recsplit_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+OK, EINVAL, EDUPLICATE, ENOMEM, ESEARCH, EFORMAT = 0, 1, 2, 3, 5, 6
+KEYS_U64, KEYS_BYTES = 1, 2
+
+
+class OracleError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        super().__init__(f"oracle {what} failed with status {code}")
+        self.code = code
+
+
+def compile_library() -> str:
+    """Compile the oracle with gcc (plain -O2, no vectorisation flags)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra", "-o", LIB, SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    return LIB
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+            compile_library()
+        _lib = ctypes.CDLL(LIB)
+        _declare(_lib)
+    return _lib
+
+
+P = ctypes.c_void_p
+U32, U64, F64 = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_double
+
+
+def _declare(L):
+    L.orc_splitmix64_stream.argtypes = [U64, U64, P]
+    L.orc_fingerprint_u64.argtypes = [P, U64, P, P]
+    L.orc_fingerprint_bytes.argtypes = [P, P, U64, P, P]
+    L.orc_phi.argtypes = [U64, U32, U64, U32]
+    L.orc_phi.restype = U32
+    L.orc_ln_success.argtypes = [U32, U32]
+    L.orc_ln_success.restype = F64
+    L.orc_tables.argtypes = [U32, U32, P, P, P]
+    L.orc_strategy.argtypes = [U32, P, P]
+    L.orc_split_parts.argtypes = [U32, U32, P]
+    L.orc_split_parts.restype = U32
+    L.orc_tree.argtypes = [P, U32, U32, U64, P, P, P, P]
+    L.orc_build.argtypes = [U32, P, P, U64, U32, U32, U64, P, U64, P]
+    L.orc_lookup.argtypes = [P, U64, U32, P, P, U64, P]
+    L.orc_bucket_sizes.argtypes = [U32, P, P, U64, U64, P]
+    L.orc_bucket_keys.argtypes = [U32, P, P, U64, U64, U64, P, U64]
+    L.orc_bucket_keys.restype = U64
+    for f in ("orc_tables", "orc_tree", "orc_build", "orc_lookup", "orc_bucket_sizes"):
+        getattr(L, f).restype = ctypes.c_int
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _keys(keys):
+    """-> (kind, data array, offsets array or None, n)"""
+    if isinstance(keys, tuple):
+        data, offsets = keys
+        data = np.ascontiguousarray(data, dtype=np.uint8)
+        offsets = np.ascontiguousarray(offsets, dtype=np.uint64)
+        if data.size == 0:
+            data = np.zeros(1, dtype=np.uint8)
+        return KEYS_BYTES, data, offsets, len(offsets) - 1
+    keys = np.ascontiguousarray(keys, dtype=np.uint64)
+    return KEYS_U64, keys, None, len(keys)
+
+
+def splitmix64_stream(seed: int, count: int) -> np.ndarray:
+    out = np.zeros(count, dtype=np.uint64)
+    lib().orc_splitmix64_stream(seed, count, _ptr(out))
+    return out
+
+
+def fingerprint(keys):
+    kind, data, offs, n = _keys(keys)
+    hi = np.zeros(n, dtype=np.uint64)
+    lo = np.zeros(n, dtype=np.uint64)
+    if kind == KEYS_U64:
+        lib().orc_fingerprint_u64(_ptr(data), n, _ptr(hi), _ptr(lo))
+    else:
+        lib().orc_fingerprint_bytes(_ptr(data), _ptr(offs), n, _ptr(hi), _ptr(lo))
+    return hi, lo
+
+
+def phi(x: int, depth: int, v: int, m: int) -> int:
+    return int(lib().orc_phi(x, depth, v, m))
+
+
+def ln_success(leaf: int, m: int) -> float:
+    return float(lib().orc_ln_success(leaf, m))
+
+
+def strategy(leaf: int):
+    lo, up = U32(), U32()
+    lib().orc_strategy(leaf, ctypes.byref(lo), ctypes.byref(up))
+    return lo.value, up.value
+
+
+def split_parts(leaf: int, m: int) -> list:
+    parts = np.zeros(16, dtype=np.uint32)
+    f = lib().orc_split_parts(leaf, m, _ptr(parts))
+    return [int(x) for x in parts[:f]]
+
+
+def tables(leaf: int, maxm: int):
+    r = np.zeros(maxm + 1, dtype=np.uint32)
+    F = np.zeros(maxm + 1, dtype=np.uint32)
+    N = np.zeros(maxm + 1, dtype=np.uint32)
+    rc = lib().orc_tables(leaf, maxm, _ptr(r), _ptr(F), _ptr(N))
+    if rc:
+        raise OracleError(rc, "tables")
+    return r, F, N
+
+
+def tree(lo: np.ndarray, leaf: int, seed_cap: int = 0):
+    """Splitting tree of one bucket: (v, m, depth) arrays in preorder."""
+    lo = np.ascontiguousarray(lo, dtype=np.uint64)
+    m = len(lo)
+    cap = max(m, 1)
+    v = np.zeros(cap, dtype=np.uint64)
+    mm = np.zeros(cap, dtype=np.uint32)
+    d = np.zeros(cap, dtype=np.uint32)
+    cnt = U64()
+    rc = lib().orc_tree(_ptr(lo if m else np.zeros(1, np.uint64)), m, leaf, seed_cap, _ptr(v), _ptr(mm), _ptr(d),
+                        ctypes.byref(cnt))
+    if rc:
+        raise OracleError(rc, "tree")
+    c = cnt.value
+    return v[:c].copy(), mm[:c].copy(), d[:c].copy()
+
+
+def build(keys, leaf: int, bucket: int, seed_cap: int = 0) -> bytes:
+    kind, data, offs, n = _keys(keys)
+    size = U64()
+    op = _ptr(offs) if offs is not None else None
+    rc = lib().orc_build(kind, _ptr(data), op, n, leaf, bucket, seed_cap, None, 0, ctypes.byref(size))
+    if rc:
+        raise OracleError(rc, "build")
+    out = np.zeros(size.value, dtype=np.uint8)
+    rc = lib().orc_build(kind, _ptr(data), op, n, leaf, bucket, seed_cap, _ptr(out), size.value, ctypes.byref(size))
+    if rc:
+        raise OracleError(rc, "build")
+    return out.tobytes()
+
+
+def lookup(blob: bytes, keys) -> np.ndarray:
+    kind, data, offs, q = _keys(keys)
+    b = np.frombuffer(blob, dtype=np.uint8).copy()
+    ranks = np.zeros(max(q, 1), dtype=np.uint64)
+    rc = lib().orc_lookup(_ptr(b), len(blob), kind, _ptr(data), _ptr(offs) if offs is not None else None, q,
+                          _ptr(ranks))
+    if rc:
+        raise OracleError(rc, "lookup")
+    return ranks[:q]
+
+
+def bucket_sizes(keys, nb: int) -> np.ndarray:
+    kind, data, offs, n = _keys(keys)
+    out = np.zeros(nb, dtype=np.uint64)
+    rc = lib().orc_bucket_sizes(kind, _ptr(data), _ptr(offs) if offs is not None else None, n, nb, _ptr(out))
+    if rc:
+        raise OracleError(rc, "bucket_sizes")
+    return out
+
+
+def bucket_keys(keys, nb: int, bucket: int, cap: int = 1 << 16) -> np.ndarray:
+    """Sorted lower signature words of one bucket."""
+    kind, data, offs, n = _keys(keys)
+    out = np.zeros(cap, dtype=np.uint64)
+    cnt = lib().orc_bucket_keys(kind, _ptr(data), _ptr(offs) if offs is not None else None, n, nb, bucket,
+                                _ptr(out), cap)
+    if cnt > cap:
+        return bucket_keys(keys, nb, bucket, int(cnt))
+    return out[:cnt].copy()
+
+
+def header(blob: bytes) -> dict:
+    w = np.frombuffer(blob[:128], dtype=np.uint64)
+    return {
+        "magic": int(w[0]), "version": int(w[1]) & 0xFFFFFFFF, "kind": int(w[1]) >> 32, "n": int(w[2]),
+        "leaf": int(w[3]), "bucket": int(w[4]), "nb": int(w[5]), "maxm": int(w[6]), "Ws": int(w[7]) & 0xFF,
+        "Wz": (int(w[7]) >> 8) & 0xFF, "delta_s": int(w[8]), "delta_z": int(np.int64(w[9])), "beta": int(w[10]),
+        "us_words": int(w[11]), "uz_words": int(w[12]), "lower_words": int(w[13]), "tree_words": int(w[14]),
+        "tree_bits": int(w[15]),
+    }

@@ -1,0 +1,77 @@
+"""Seeded synthetic key sets.
+
+This module only draws random inputs; it holds none of the method's
+arithmetic.  Every generator uses numpy's PCG64 bit generator with an explicit
+seed, so the test-suite, the benchmark and the smoke check see identical keys.
+
+The paper measures on random 128-bit keys and names no public data set; these
+generators stand in for it with uniformly random 64-bit integers and random
+printable-ASCII strings.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def _rng(seed: int) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def u64_keys(n: int, seed: int) -> np.ndarray:
+    """n distinct uniformly random 64-bit keys (first occurrences kept)."""
+    rng = _rng(seed)
+    keys = rng.integers(0, 2**64, size=n, dtype=np.uint64, endpoint=False)
+    while True:
+        _, first = np.unique(keys, return_index=True)
+        if len(first) == len(keys):
+            return keys
+        keep = np.sort(first)
+        extra = rng.integers(0, 2**64, size=n - len(keep), dtype=np.uint64, endpoint=False)
+        keys = np.concatenate([keys[keep], extra])
+
+
+def ascii_keys(n: int, seed: int, min_len: int = 8, max_len: int = 32):
+    """n distinct random strings of printable ASCII (0x21..0x7e), lengths
+    uniform in [min_len, max_len].  Returns (data uint8[], offsets uint64[n+1])."""
+    rng = _rng(seed)
+    width = max_len + 1
+    rows = np.zeros((0, width), dtype=np.uint8)
+    while rows.shape[0] < n:
+        need = n - rows.shape[0]
+        lens = rng.integers(min_len, max_len + 1, size=need, dtype=np.int64)
+        chars = rng.integers(0x21, 0x7F, size=(need, max_len), dtype=np.uint8)
+        chars[np.arange(max_len)[None, :] >= lens[:, None]] = 0
+        new = np.concatenate([lens.astype(np.uint8)[:, None], chars], axis=1)
+        rows = np.concatenate([rows, new])
+        view = np.ascontiguousarray(rows).view(np.dtype((np.void, width))).ravel()
+        _, first = np.unique(view, return_index=True)
+        rows = rows[np.sort(first)]
+    rows = rows[:n]
+    lens = rows[:, 0].astype(np.uint64)
+    offsets = np.zeros(n + 1, dtype=np.uint64)
+    np.cumsum(lens, out=offsets[1:])
+    mask = np.arange(max_len)[None, :] < lens[:, None].astype(np.int64)
+    data = rows[:, 1:][mask]
+    return np.ascontiguousarray(data, dtype=np.uint8), offsets
+
+
+def permutation(n: int, seed: int) -> np.ndarray:
+    """A uniformly random permutation of range(n) (lookup order)."""
+    return _rng(seed).permutation(n).astype(np.int64)
+
+
+def gather_strings(keys, order: np.ndarray):
+    """Reorder a (data, offsets) string set by an index array."""
+    data, offsets = keys
+    lens = (offsets[1:] - offsets[:-1]).astype(np.int64)[order]
+    starts = offsets[:-1].astype(np.int64)[order]
+    new_off = np.zeros(len(order) + 1, dtype=np.uint64)
+    np.cumsum(lens, out=new_off[1:])
+    idx = np.repeat(starts - new_off[:-1].astype(np.int64), lens) + np.arange(int(new_off[-1]), dtype=np.int64)
+    return np.ascontiguousarray(data[idx]), new_off
+
+
+def log_uniform_sizes(count: int, seed: int, lo: float, hi: float) -> np.ndarray:
+    """count integer sizes floor(exp(U(ln lo, ln hi))) (batched/served builds)."""
+    u = _rng(seed).random(count)
+    return np.floor(np.exp(np.log(lo) + u * (np.log(hi) - np.log(lo)))).astype(np.int64)
