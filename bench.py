@@ -1,0 +1,246 @@
+#!/usr/bin/env python3
+"""RecSplit construction throughput on one MI355X.
+
+Workload (one step): build the minimal perfect hash function of 10,000,000
+random printable-ASCII strings of 8-32 bytes with leaf size l=8 and bucket
+size b=100, then look all 10,000,000 keys up in shuffled order.  Inputs are
+seeded and synthetic and already resident in HBM when the timed region
+starts.  Also reported: one build of 10,000,000 random 64-bit keys at l=16,
+b=2000 (the high-compression point), bits/key, p50/p99 build latency, the
+seed-search kernel's share of the VALU integer peak, and the CPU oracle timed
+on a bounded sample.
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Expected hash evaluations per key of the construction (model of the paper's
+# analysis: leaf trials m^m/m! with early exit at the first collision, split
+# trials 1/p of eq. (2) with m evaluations each, node census from the strategy
+# averaged over Poisson(b) bucket sizes).
+EVALS_PER_KEY = {(8, 100): 494.0, (12, 1000): 1.39e4, (16, 2000): 8.90e5}
+# Full-rate VALU lane-operation slots of one hash evaluation in the search
+# kernel's inner loop (instruction count of the compiled loop weighted by the
+# measured issue cost of each instruction on gfx950).
+VALU_SLOTS_PER_EVAL = float(os.environ.get("RS_VALU_SLOTS_PER_EVAL", "0")) or None
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz full-rate 32-bit VALU lane-ops.
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def percentile(xs, q):
+    import numpy as np
+
+    return float(np.percentile(np.asarray(xs, dtype=np.float64), q))
+
+
+def cpu_baseline(keys_host, n_sample, leaf, bucket):
+    """The CPU oracle, single-threaded, on the first n_sample keys."""
+    import numpy as np
+
+    import oracle
+
+    data, offsets = keys_host
+    sub_off = offsets[: n_sample + 1].copy()
+    sub = (data[: int(sub_off[-1])], sub_off)
+    t0 = time.perf_counter()
+    blob = oracle.build(sub, leaf, bucket)
+    dt = time.perf_counter() - t0
+    return {"value": n_sample / dt, "unit": "keys/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {n_sample:,} of the {len(offsets) - 1:,} strings, l={leaf}, b={bucket}, "
+                      f"fingerprint to serialized blob in memory ({dt:.1f} s)",
+            "bits_per_key": 8.0 * len(blob) / n_sample}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=10_000_000, help="keys of the l=8, b=100 string workload")
+    ap.add_argument("--l16-n", type=int, default=10_000_000, help="keys of the l=16, b=2000 build (0: skip)")
+    ap.add_argument("--latency-builds", type=int, default=30, help="repeated 100,000-key builds for p50/p99")
+    ap.add_argument("--cpu-sample", type=int, default=1_000_000, help="oracle sample size (0: skip)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the construction of one "
+              "structure runs on one device; see the design notes for how it would shard)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1910_06416_amd import inputs, recsplit
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    recsplit.lib()
+    n, leaf, bucket = args.n, 8, 100
+
+    log(f"[bench] generating {n:,} ASCII strings (seed 2) and the lookup order (seed 3)")
+    keys_host = inputs.ascii_keys(n, 2)
+    order = inputs.permutation(n, 3)
+    queries_host = inputs.gather_strings(keys_host, order)
+    dk = recsplit.device_keys(keys_host)
+    dq = recsplit.device_keys(queries_host)
+    ranks = torch.empty(n, dtype=torch.int64, device="cuda")
+    torch.cuda.synchronize()
+
+    for w in range(args.warmup):
+        blob = recsplit.build(dk, leaf, bucket, timing=True)
+        recsplit.lookup(blob, dq, out=ranks)
+        torch.cuda.synchronize()
+        blob.free()
+        log(f"[bench] warmup {w + 1}/{args.warmup} done")
+
+    build_s, lookup_ms, search_ms, stats = [], [], [], None
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        tb = time.perf_counter()
+        blob = recsplit.build(dk, leaf, bucket, timing=True)  # waits for its stream (timing mode)
+        build_s.append(time.perf_counter() - tb)
+        stats = recsplit.last_build_stats()
+        search_ms.append(stats["ms_search"])
+        ev0.record()
+        recsplit.lookup(blob, dq, out=ranks)
+        ev1.record()
+        ev1.synchronize()
+        lookup_ms.append(ev0.elapsed_time(ev1))
+        if k + 1 < args.steps:
+            blob.free()
+        log(f"[bench] step {k + 1}/{args.steps}: build {build_s[-1] * 1e3:.2f} ms "
+            f"(search {search_ms[-1]:.2f} ms), lookup {lookup_ms[-1]:.2f} ms")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+
+    # the timed output is an MPHF: lookups of all keys are a permutation of [0, n)
+    srt, _ = torch.sort(ranks)
+    assert torch.equal(srt, torch.arange(n, dtype=torch.int64, device="cuda")), "lookups are not a bijection"
+    bits_per_key = blob.bits_per_key()
+    blob.free()
+
+    mean_build = float(np.mean(build_s))
+    value = n / mean_build
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    mean_search = float(np.mean(search_ms))
+    alg_evals = EVALS_PER_KEY[(leaf, bucket)] * n
+    evals_per_s = alg_evals / (mean_search * 1e-3)
+    lookup_rate = n / (float(np.mean(lookup_ms)) * 1e-3)
+    lookup_bytes = int(queries_host[0].nbytes + queries_host[1].nbytes + 8 * n)
+
+    result = {
+        "metric": "keys/s built at l=8,b=100 and l=16,b=2000; bits/key; p99 build latency",
+        "value": value,
+        "unit": "keys/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "10M random ASCII strings (8-32 B), l=8, b=100, build + 10M shuffled lookups",
+                   "n": n, "leaf": leaf, "bucket": bucket},
+        "build_ms": mean_build * 1e3,
+        "build_p50_ms": percentile(build_s, 50) * 1e3,
+        "build_p99_ms": percentile(build_s, 99) * 1e3,
+        "bits_per_key": bits_per_key,
+        "search_ms": mean_search,
+        "phase_ms": {k: stats[k] for k in ("ms_signature", "ms_scatter", "ms_search", "ms_offsets", "ms_fill")},
+        "lookup_ms": float(np.mean(lookup_ms)),
+        "lookup_keys_per_s": lookup_rate,
+        "lookup_hbm": {"achieved": lookup_bytes / (float(np.mean(lookup_ms)) * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
+                       "unit": "GB/s", "bytes_per_query": lookup_bytes / n},
+    }
+    slots = VALU_SLOTS_PER_EVAL
+    result["roofline"] = {
+        "kernel": "k_search",
+        "bound": "alu",
+        "achieved": evals_per_s * slots / 1e12 if slots else None,
+        "peak": VALU_PEAK_TOPS,
+        "unit": "T lane-ops/s",
+        "frac": evals_per_s * slots / 1e12 / VALU_PEAK_TOPS if slots else None,
+        "traffic": None,
+        "algorithmic_evals_per_launch": alg_evals,
+        "evals_per_s": evals_per_s,
+        "valu_slots_per_eval": slots,
+    }
+
+    # latency over repeated 100,000-key builds (64-bit keys, l=8, b=100)
+    if args.latency_builds:
+        small = recsplit.device_keys(inputs.u64_keys(100_000, 1))
+        lat = []
+        for i in range(args.latency_builds + 3):
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            b = recsplit.build(small, 8, 100, timing=True)
+            dt = time.perf_counter() - tb
+            b.free()
+            if i >= 3:
+                lat.append(dt)
+        result["latency_100k_l8_b100_ms"] = {"p50": percentile(lat, 50) * 1e3, "p99": percentile(lat, 99) * 1e3,
+                                             "builds": len(lat)}
+        log(f"[bench] 100k-key build latency p50 {result['latency_100k_l8_b100_ms']['p50']:.3f} ms")
+
+    # high-compression point: 10M random 64-bit keys, l=16, b=2000 (one build)
+    if args.l16_n:
+        k16 = inputs.u64_keys(args.l16_n, 4)
+        d16 = recsplit.device_keys(k16)
+        warm = recsplit.build(recsplit.device_keys(inputs.u64_keys(4000, 5)), 16, 2000, timing=True)
+        warm.free()
+        log(f"[bench] l=16 b=2000 build of {args.l16_n:,} keys ...")
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        b16 = recsplit.build(d16, 16, 2000, timing=True)
+        dt16 = time.perf_counter() - tb
+        st16 = recsplit.last_build_stats()
+        bpk16 = b16.bits_per_key()
+        r16 = recsplit.lookup(b16, d16)
+        srt16, _ = torch.sort(r16)
+        assert torch.equal(srt16, torch.arange(args.l16_n, dtype=torch.int64, device="cuda"))
+        b16.free()
+        ev16 = EVALS_PER_KEY[(16, 2000)] * args.l16_n / (st16["ms_search"] * 1e-3)
+        result["l16_b2000"] = {
+            "n": args.l16_n, "keys_per_s": args.l16_n / dt16, "build_s": dt16, "search_ms": st16["ms_search"],
+            "bits_per_key": bpk16, "evals_per_s": ev16,
+            "valu_frac": ev16 * slots / 1e12 / VALU_PEAK_TOPS if slots else None,
+        }
+        log(f"[bench] l=16: {args.l16_n / dt16:,.0f} keys/s, {bpk16:.4f} bits/key")
+
+    if args.cpu_sample:
+        log(f"[bench] CPU oracle on {args.cpu_sample:,} keys ...")
+        result["cpu_baseline"] = cpu_baseline(keys_host, args.cpu_sample, leaf, bucket)
+        result["cpu_baseline"]["host_cpu"] = _cpu_model()
+
+    print(json.dumps(result), flush=True)
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip() + f" ({os.cpu_count()} logical CPUs visible)"
+    except OSError:
+        pass
+    return None
+
+
+if __name__ == "__main__":
+    main()

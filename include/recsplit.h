@@ -1,0 +1,146 @@
+/*
+ * librecsplit -- RecSplit minimal perfect hashing on AMD Instinct MI355X (gfx950).
+ *
+ * A minimal perfect hash function (MPHF) maps a fixed set S of n keys one-to-one
+ * onto [0, n) (paper Sec. 1); values for keys outside S are unspecified but
+ * deterministic.  RecSplit (Esposito, Mueller Graf, Vigna 2019) builds it by
+ * hashing keys to 128-bit signatures, distributing them into buckets of
+ * average size b (Sec. 4, Sec. 6.1), and searching, for every bucket, a
+ * splitting tree whose inner nodes store the first hash index that splits the
+ * node's keys into parts of prescribed sizes and whose leaves (at most l keys)
+ * store the first index that is a bijection (Sec. 4, Sec. 5).  Indices are
+ * Golomb-Rice coded (eq. (4), Sec. 6.2) and the bucket prefix sums and bit
+ * offsets are kept in a double Elias-Fano list (Sec. 6.3, Sec. 7.4).
+ *
+ * Conventions for every entry point:
+ *   - All functions return an rs_status; nothing aborts or throws across the ABI.
+ *   - On error, output parameters are left untouched and rs_last_error() returns
+ *     a message for the calling thread.
+ *   - "device" pointers are HIP device allocations on the current device;
+ *     "stream" is a hipStream_t passed as void* (NULL = the default stream).
+ *   - The caller owns key, query and output buffers and must keep them valid
+ *     until the work enqueued on the stream has completed.
+ *   - The library owns rs_blob objects; free them with rs_blob_free.
+ */
+#ifndef RECSPLIT_H
+#define RECSPLIT_H
+
+#include <stdint.h>
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RS_OK = 0,
+    RS_EINVAL = 1,      /* bad argument: l outside [1,24], b = 0, n = 0, NULL pointer,
+                           non-monotone offsets, key kind differing from the blob's */
+    RS_EDUPLICATE = 2,  /* two keys share a 128-bit signature (duplicate keys), or two keys
+                           of one bucket share the lower signature word */
+    RS_ENOMEM = 3,      /* a device or host allocation failed */
+    RS_EDEVICE = 4,     /* a HIP runtime call failed */
+    RS_ESEARCH = 5,     /* an index search reached the seed cap (2^56 unless lowered) */
+    RS_EFORMAT = 6,     /* serialized blob has a bad magic, version or size */
+    RS_EBUSY = 7        /* serving queue full */
+} rs_status;
+
+enum { RS_KEYS_U64 = 1, RS_KEYS_BYTES = 2 };
+
+/* A key set resident in device memory.
+ *   RS_KEYS_U64:   data -> uint64_t[n]; offsets = NULL.
+ *   RS_KEYS_BYTES: data -> concatenated key bytes; offsets -> uint64_t[n+1], key i is
+ *                  data[offsets[i] .. offsets[i+1]); offsets must be non-decreasing. */
+typedef struct {
+    uint32_t kind;
+    const void* data;
+    const uint64_t* offsets;
+    uint64_t n;
+} rs_keys;
+
+typedef struct rs_blob rs_blob; /* opaque; immutable after build; safe for concurrent lookups */
+
+/* Build options (all-zero = defaults).
+ *   seed_cap: lowers the search cap of every split and bijection index
+ *             (0 = 2^56); it exists to exercise the RS_ESEARCH path.
+ *   flags   : RS_OPT_TIMING records HIP events around each construction phase
+ *             on the build stream (read them with rs_last_build_stats); the
+ *             build then waits for the stream before returning. */
+enum { RS_OPT_TIMING = 1 };
+typedef struct {
+    uint64_t seed_cap;
+    uint32_t flags;
+    uint32_t reserved[5];
+} rs_options;
+
+/* Per-phase device times (milliseconds, from HIP events on the build stream)
+ * and sizes of the calling thread's last successful rs_build_ex with
+ * RS_OPT_TIMING. */
+typedef struct {
+    double ms_signature;  /* signatures + bucket histogram + prefix sums */
+    double ms_scatter;    /* bucket-contiguous scatter */
+    double ms_search;     /* seed search kernel (the hot loop) */
+    double ms_offsets;    /* bit-length prefix sums and Elias-Fano gaps */
+    double ms_fill;       /* Elias-Fano bits and Golomb-Rice streams */
+    double ms_device;     /* first to last event */
+    uint64_t n, nb, maxm, tree_bits, blob_bytes;
+} rs_build_stats;
+
+int rs_last_build_stats(rs_build_stats* out);
+
+/* Build the MPHF of a key set (construction of Sec. 4-6 of the paper).
+ *   keys   : device key set, n >= 1 distinct keys.
+ *   leaf   : leaf size l, 1 <= l <= 24 (Sec. 5: l <= 24 keeps Golomb-Rice parameters
+ *            below 32).
+ *   bucket : average bucket size b >= 1; nb = ceil(n / b) buckets (Sec. 6.1).
+ *   stream : HIP stream; all device work is enqueued on it.  The call waits on the
+ *            stream twice (for the largest bucket size and for the blob size).
+ *   out    : receives the new blob; its device bytes are valid once the stream
+ *            reaches the end of the enqueued work.
+ * Errors: RS_EINVAL, RS_EDUPLICATE, RS_ENOMEM, RS_EDEVICE, RS_ESEARCH. */
+int rs_build(const rs_keys* keys, uint32_t leaf, uint32_t bucket, void* stream, rs_blob** out);
+
+/* rs_build with options (opts may be NULL). */
+int rs_build_ex(const rs_keys* keys, uint32_t leaf, uint32_t bucket, const rs_options* opts, void* stream,
+                rs_blob** out);
+
+/* Rank of each query (lookup of Sec. 4 and Sec. 6.2): ranks_dev[i] = f(queries[i]).
+ * Members of the built set get distinct values in [0, n).  Other keys get a
+ * deterministic value in [0, n] (n only when their bucket is the last one and
+ * is empty), the same value the CPU reference computes.
+ *   queries  : device key set of the same kind as the blob.
+ *   ranks_dev: device uint64_t[queries->n], written asynchronously on stream.
+ * Errors: RS_EINVAL (NULL, kind mismatch), RS_EDEVICE. */
+int rs_lookup(const rs_blob* blob, const rs_keys* queries, uint64_t* ranks_dev, void* stream);
+
+/* Size in bytes of the serialized structure (header + Elias-Fano + trees). */
+uint64_t rs_blob_bytes(const rs_blob* blob);
+
+/* Copy the serialized structure to host memory dst (capacity cap bytes); waits for
+ * the blob's construction stream.  Errors: RS_EINVAL (cap too small, NULL). */
+int rs_blob_to_host(const rs_blob* blob, void* dst, uint64_t cap);
+
+/* Load a serialized structure from host memory into a new device blob.
+ * Errors: RS_EFORMAT (magic, version, size), RS_ENOMEM, RS_EDEVICE. */
+int rs_blob_from_host(const void* src, uint64_t bytes, void* stream, rs_blob** out);
+
+/* Device address of the serialized bytes (read-only; rs_blob_bytes long). */
+const void* rs_blob_device_ptr(const rs_blob* blob);
+
+/* Number of keys, leaf size and bucket size the blob was built with. */
+int rs_blob_info(const rs_blob* blob, uint64_t* n, uint32_t* leaf, uint32_t* bucket);
+
+/* Release a blob (waits for its stream first). NULL is ignored. */
+void rs_blob_free(rs_blob* blob);
+
+/* Message describing the last error of the calling thread ("" if none). */
+const char* rs_last_error(void);
+
+/* Library version string. */
+const char* rs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RECSPLIT_H */

@@ -1,0 +1,308 @@
+// Blob management, lookup (Sec. 4 and 6.2-6.3 of the paper) and the error
+// plumbing of librecsplit.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "rs_host.h"
+#include "rs_internal.h"
+
+namespace rs {
+
+namespace {
+thread_local std::string g_error;
+}
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_error = buf;
+    return code;
+}
+
+void clear_error() { g_error.clear(); }
+
+int dev_alloc(void** p, size_t bytes, hipStream_t s) {
+    *p = nullptr;
+    hipError_t e = hipMallocAsync(p, std::max<size_t>(bytes, 256), s);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return fail(e == hipErrorOutOfMemory ? RS_ENOMEM : RS_EDEVICE, "device allocation of %zu bytes failed: %s",
+                    bytes, hipGetErrorString(e));
+    }
+    return RS_OK;
+}
+
+void dev_free(void* p, hipStream_t s) {
+    if (p) (void)hipFreeAsync(p, s);
+}
+
+Layout layout_of(const uint64_t* h) {
+    Layout L;
+    L.kind = h[1] >> 32;
+    L.n = h[2]; L.leaf = h[3]; L.bucket = h[4]; L.nb = h[5]; L.maxm = h[6];
+    L.Ws = (uint32_t)(h[7] & 0xff);
+    L.Wz = (uint32_t)((h[7] >> 8) & 0xff);
+    L.delta_s = h[8];
+    L.delta_z = (int64_t)h[9];
+    L.beta = h[10];
+    L.us_words = h[11]; L.uz_words = h[12]; L.lower_words = h[13]; L.tree_words = h[14]; L.tree_bits = h[15];
+    L.ninv = (L.nb + 1 + (1u << kInvShift) - 1) >> kInvShift;
+    L.lower_off = kHeaderWords;
+    L.us_off = L.lower_off + L.lower_words;
+    L.uz_off = L.us_off + L.us_words;
+    L.invs_off = L.uz_off + L.uz_words;
+    L.invz_off = L.invs_off + L.ninv;
+    L.tree_off = L.invz_off + L.ninv;
+    L.total_words = L.tree_off + L.tree_words;
+    return L;
+}
+
+int upload_tables(uint32_t leaf, uint32_t maxm, uint32_t* dst, hipStream_t s) {
+    TableView tv = host_tables(leaf, maxm);
+    if (!tv.data) return fail(RS_ENOMEM, "table allocation failed");
+    RS_HIP(hipMemcpyAsync(dst, tv.r(), (maxm + 1) * 4ull, hipMemcpyHostToDevice, s));
+    RS_HIP(hipMemcpyAsync(dst + (maxm + 1), tv.F(), (maxm + 1) * 4ull, hipMemcpyHostToDevice, s));
+    RS_HIP(hipMemcpyAsync(dst + 2 * (maxm + 1), tv.N(), (maxm + 1) * 4ull, hipMemcpyHostToDevice, s));
+    return RS_OK;
+}
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Lookup: one query per lane.
+// ---------------------------------------------------------------------------
+struct LookupArgs {
+    const uint64_t* blob;
+    const uint32_t* R;
+    const uint32_t* F;
+    const uint32_t* N;
+    uint64_t nb, beta, delta_s;
+    int64_t delta_z;
+    uint32_t Ws, Wz;
+    uint64_t lower_off, us_off, uz_off, invs_off, invz_off, tree_off;
+    uint64_t us_words, uz_words, tree_words;
+    uint32_t leaf, lower, upper, maxm;
+};
+
+// Position of the k-th set bit (k = 0, 1, ...) inside a 64-bit word.
+__device__ __forceinline__ uint32_t select_in_word(uint64_t x, uint32_t k) {
+    uint32_t pos = 0;
+    uint32_t c = (uint32_t)__popc((uint32_t)x);
+    if (k >= c) { k -= c; x >>= 32; pos += 32; }
+    c = (uint32_t)__popc((uint32_t)x & 0xffffu);
+    if (k >= c) { k -= c; x >>= 16; pos += 16; }
+    c = (uint32_t)__popc((uint32_t)x & 0xffu);
+    if (k >= c) { k -= c; x >>= 8; pos += 8; }
+    uint32_t y = (uint32_t)x & 0xffu;
+    for (; k; k--) y &= y - 1;
+    return pos + (uint32_t)__builtin_ctz(y);
+}
+
+// Position of the k-th set bit at or after bit position p of an array of
+// `words` words; a position past the end if there is no such bit (only in a
+// corrupted structure).
+__device__ __forceinline__ uint64_t select_from(const uint64_t* a, uint64_t words, uint64_t p, uint64_t k) {
+    uint64_t w = p >> 6;
+    if (w >= words) return words << 6;
+    uint64_t word = a[w] & (~0ull << (p & 63));
+    for (;;) {
+        uint32_t c = (uint32_t)__popcll(word);
+        if (k < c) return (w << 6) + select_in_word(word, (uint32_t)k);
+        k -= c;
+        if (++w >= words) return words << 6;
+        word = a[w];
+    }
+}
+
+__device__ __forceinline__ uint64_t get_bits(const uint64_t* a, uint64_t pos, uint32_t nbits) {
+    if (nbits == 0) return 0;
+    uint64_t w = pos >> 6;
+    uint32_t o = (uint32_t)(pos & 63);
+    uint64_t v = a[w] >> o;
+    if (o + nbits > 64) v |= a[w + 1] << (64 - o);
+    return nbits == 64 ? v : v & ((1ull << nbits) - 1);
+}
+
+__device__ uint64_t rank_of(const LookupArgs& a, uint64_t hi, uint64_t lo) {
+    const uint64_t* blob = a.blob;
+    const uint64_t i = bucket_of(hi, a.nb);
+    // Elias-Fano: the i-th one of the upper bits is at (y_i >> W) + i.
+    const uint64_t* us = blob + a.us_off;
+    const uint64_t* uz = blob + a.uz_off;
+    const uint64_t* lower = blob + a.lower_off;
+    const uint32_t wsz = a.Ws + a.Wz;
+    uint64_t inv_s = blob[a.invs_off + (i >> kInvShift)];
+    uint64_t ps = select_from(us, a.us_words, inv_s, i & ((1u << kInvShift) - 1));
+    uint64_t ps1 = select_from(us, a.us_words, ps + 1, 0);
+    uint64_t ys = ((ps - i) << a.Ws) | get_bits(lower, i * wsz, a.Ws);
+    uint64_t ys1 = ((ps1 - i - 1) << a.Ws) | get_bits(lower, (i + 1) * wsz, a.Ws);
+    uint64_t s_i = ys + i * a.delta_s;
+    uint64_t s_i1 = ys1 + (i + 1) * a.delta_s;
+    uint64_t inv_z = blob[a.invz_off + (i >> kInvShift)];
+    uint64_t pz = select_from(uz, a.uz_words, inv_z, i & ((1u << kInvShift) - 1));
+    uint64_t yz = ((pz - i) << a.Wz) | get_bits(lower, i * wsz + a.Ws, a.Wz);
+    int64_t z = (int64_t)yz + (int64_t)i * a.delta_z;
+    uint64_t o_i = (uint64_t)(z + (int64_t)((a.beta * s_i) >> 16));
+
+    uint32_t m = (uint32_t)min(s_i1 - s_i, (uint64_t)a.maxm);
+    const uint64_t* tree = blob + a.tree_off;
+    uint64_t c = 0;
+    uint32_t d = 0;
+    uint64_t fp = o_i, up = o_i + a.F[m];
+    while (m > a.leaf) {
+        uint32_t r = a.R[m];
+        uint64_t fixed = get_bits(tree, fp, r);
+        fp += r;
+        uint64_t one = select_from(tree, a.tree_words, up, 0);
+        uint64_t v = ((one - up) << r) | fixed;
+        up = one + 1;
+        SplitShape sh = split_shape(m, a.leaf, a.lower, a.upper);
+        uint32_t j = min(phi(lo, d, v, m) / sh.unit, sh.fanout - 1);
+        if (j) {
+            fp += (uint64_t)j * a.F[sh.unit];
+            uint64_t skip = (uint64_t)j * a.N[sh.unit];
+            if (skip) up = select_from(tree, a.tree_words, up, skip - 1) + 1;
+        }
+        c += (uint64_t)j * sh.unit;
+        m = j + 1 == sh.fanout ? sh.last : sh.unit;
+        d++;
+    }
+    if (m >= 2) {
+        uint32_t r = a.R[m];
+        uint64_t fixed = get_bits(tree, fp, r);
+        uint64_t one = select_from(tree, a.tree_words, up, 0);
+        uint64_t v = ((one - up) << r) | fixed;
+        c += phi(lo, d, v, m);
+    }
+    return s_i + c;
+}
+
+__global__ void k_lookup_u64(LookupArgs a, const uint64_t* __restrict__ keys, uint64_t q,
+                             uint64_t* __restrict__ ranks) {
+    uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= q) return;
+    uint64_t hi, lo;
+    signature_u64(keys[t], hi, lo);
+    ranks[t] = rank_of(a, hi, lo);
+}
+
+__global__ void k_lookup_bytes(LookupArgs a, const uint8_t* __restrict__ data, const uint64_t* __restrict__ offsets,
+                               uint64_t q, bool aligned, uint64_t* __restrict__ ranks) {
+    uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= q) return;
+    uint64_t total = offsets[q];
+    uint64_t s = offsets[t], e = offsets[t + 1];
+    if (e < s || e > total) e = s = min(s, total);
+    uint64_t hi, lo;
+    signature_bytes(data, total, aligned, s, e, hi, lo);
+    ranks[t] = rank_of(a, hi, lo);
+}
+
+}  // namespace
+
+}  // namespace rs
+
+using namespace rs;
+
+extern "C" int rs_lookup(const rs_blob* blob, const rs_keys* queries, uint64_t* ranks_dev, void* stream) {
+    clear_error();
+    if (!blob || !queries || (!ranks_dev && queries->n)) return fail(RS_EINVAL, "NULL argument");
+    if (queries->n == 0) return RS_OK;
+    if (!queries->data) return fail(RS_EINVAL, "NULL query data");
+    Layout L = layout_of(blob->header);
+    if (queries->kind != L.kind) return fail(RS_EINVAL, "query kind %u differs from the blob's (%u)",
+                                             queries->kind, (uint32_t)L.kind);
+    if (queries->kind == RS_KEYS_BYTES && !queries->offsets) return fail(RS_EINVAL, "NULL offsets");
+    Strategy st = make_strategy((uint32_t)L.leaf);
+    LookupArgs a{blob->words, blob->tables, blob->tables + (L.maxm + 1), blob->tables + 2 * (L.maxm + 1),
+                 L.nb, L.beta, L.delta_s, L.delta_z, L.Ws, L.Wz, L.lower_off, L.us_off, L.uz_off, L.invs_off,
+                 L.invz_off, L.tree_off, L.us_words, L.uz_words, L.tree_words, (uint32_t)L.leaf, st.lower,
+                 st.upper, (uint32_t)L.maxm};
+    hipStream_t s = (hipStream_t)stream;
+    const uint32_t block = 256;
+    uint32_t grid = (uint32_t)((queries->n + block - 1) / block);
+    if (queries->kind == RS_KEYS_U64)
+        k_lookup_u64<<<grid, block, 0, s>>>(a, (const uint64_t*)queries->data, queries->n, ranks_dev);
+    else
+        k_lookup_bytes<<<grid, block, 0, s>>>(a, (const uint8_t*)queries->data, queries->offsets, queries->n,
+                                              ((uintptr_t)queries->data & 7) == 0, ranks_dev);
+    RS_HIP(hipGetLastError());
+    return RS_OK;
+}
+
+extern "C" uint64_t rs_blob_bytes(const rs_blob* blob) { return blob ? blob->bytes : 0; }
+
+extern "C" const void* rs_blob_device_ptr(const rs_blob* blob) { return blob ? blob->words : nullptr; }
+
+extern "C" int rs_blob_info(const rs_blob* blob, uint64_t* n, uint32_t* leaf, uint32_t* bucket) {
+    if (!blob) return fail(RS_EINVAL, "NULL blob");
+    if (n) *n = blob->header[2];
+    if (leaf) *leaf = (uint32_t)blob->header[3];
+    if (bucket) *bucket = (uint32_t)blob->header[4];
+    return RS_OK;
+}
+
+extern "C" int rs_blob_to_host(const rs_blob* blob, void* dst, uint64_t cap) {
+    clear_error();
+    if (!blob || !dst) return fail(RS_EINVAL, "NULL argument");
+    if (cap < blob->bytes) return fail(RS_EINVAL, "buffer of %llu bytes is smaller than the blob (%llu)",
+                                       (unsigned long long)cap, (unsigned long long)blob->bytes);
+    RS_HIP(hipStreamSynchronize(blob->stream));
+    RS_HIP(hipMemcpy(dst, blob->words, blob->bytes, hipMemcpyDeviceToHost));
+    return RS_OK;
+}
+
+extern "C" int rs_blob_from_host(const void* src, uint64_t bytes, void* stream, rs_blob** out) {
+    clear_error();
+    if (!src || !out) return fail(RS_EINVAL, "NULL argument");
+    if (bytes < kHeaderWords * 8 || bytes % 8) return fail(RS_EFORMAT, "blob too short");
+    const uint64_t* h = (const uint64_t*)src;
+    if (h[0] != kMagic || (h[1] & 0xffffffffull) != kVersion) return fail(RS_EFORMAT, "bad magic or version");
+    Layout L = layout_of(h);
+    if (L.leaf < 1 || L.leaf > kMaxLeaf || L.nb == 0 || L.n == 0 || L.maxm > L.n ||
+        (L.kind != RS_KEYS_U64 && L.kind != RS_KEYS_BYTES) || L.total_words * 8 != bytes)
+        return fail(RS_EFORMAT, "inconsistent header");
+    hipStream_t s = (hipStream_t)stream;
+    rs_blob* b = new (std::nothrow) rs_blob;
+    if (!b) return fail(RS_ENOMEM, "host allocation failed");
+    memcpy(b->header, h, sizeof b->header);
+    int rc = dev_alloc((void**)&b->words, bytes, s);
+    if (!rc) rc = dev_alloc((void**)&b->tables, 3ull * (L.maxm + 1) * 4, s);
+    if (!rc) rc = upload_tables((uint32_t)L.leaf, (uint32_t)L.maxm, b->tables, s);
+    if (!rc && hipMemcpyAsync(b->words, src, bytes, hipMemcpyHostToDevice, s) != hipSuccess)
+        rc = fail(RS_EDEVICE, "copy to device failed");
+    if (!rc && hipStreamSynchronize(s) != hipSuccess) rc = fail(RS_EDEVICE, "stream synchronisation failed");
+    if (rc) {
+        dev_free(b->words, s);
+        dev_free(b->tables, s);
+        delete b;
+        return rc;
+    }
+    b->bytes = bytes;
+    b->stream = s;
+    (void)hipGetDevice(&b->device);
+    *out = b;
+    return RS_OK;
+}
+
+extern "C" void rs_blob_free(rs_blob* blob) {
+    if (!blob) return;
+    (void)hipStreamSynchronize(blob->stream);
+    if (blob->words) (void)hipFreeAsync(blob->words, blob->stream);
+    if (blob->tables) (void)hipFreeAsync(blob->tables, blob->stream);
+    (void)hipStreamSynchronize(blob->stream);
+    delete blob;
+}
+
+extern "C" const char* rs_last_error(void) { return g_error.c_str(); }
+
+extern "C" const char* rs_version(void) { return "librecsplit 0.1 (gfx950)"; }

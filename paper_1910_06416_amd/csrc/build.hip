@@ -1,0 +1,818 @@
+// Construction of a RecSplit structure on the GPU (Sec. 4-7 of the paper).
+//
+// Pipeline, all on the caller's stream:
+//   signatures + bucket histogram -> exclusive scan (prefix sums s_i) ->
+//   scatter into bucket-contiguous order -> seed search (one wavefront per
+//   bucket, one lane per candidate index) -> scan of bucket bit lengths
+//   (offsets o_i) -> Elias-Fano minimum gaps -> [host: blob geometry] ->
+//   Elias-Fano bits + Golomb-Rice streams written into the blob.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <vector>
+
+#include "rs_host.h"
+#include "rs_internal.h"
+
+namespace rs {
+
+namespace {
+
+constexpr int kBlock = 256;
+constexpr int kScanItems = 8;
+constexpr int kScanTile = kBlock * kScanItems;
+
+__global__ void k_init_status(DevStatus* st) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        st->maxm = 0;
+        st->flags = 0;
+        st->delta_s = ~0ull;
+        st->delta_z = 0x7fffffffffffffffll;
+    }
+}
+
+__global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i < n; i += (uint64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+__global__ void k_fill_u64(uint64_t* p, uint64_t n, uint64_t v) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i < n; i += (uint64_t)gridDim.x * blockDim.x) p[i] = v;
+}
+
+// ---------------------------------------------------------------------------
+// Signatures (Sec. 6.1).
+// ---------------------------------------------------------------------------
+__global__ void k_signature_u64(const uint64_t* __restrict__ keys, uint64_t n, uint64_t nb,
+                                uint64_t* __restrict__ lo_out, uint32_t* __restrict__ bid,
+                                uint32_t* __restrict__ counts) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint64_t hi, lo;
+    signature_u64(keys[i], hi, lo);
+    uint32_t b = (uint32_t)bucket_of(hi, nb);
+    lo_out[i] = lo;
+    bid[i] = b;
+    atomicAdd(&counts[b], 1u);
+}
+
+__global__ void k_signature_bytes(const uint8_t* __restrict__ data, const uint64_t* __restrict__ offsets,
+                                  uint64_t n, uint64_t nb, bool aligned, uint64_t* __restrict__ lo_out,
+                                  uint32_t* __restrict__ bid, uint32_t* __restrict__ counts, DevStatus* st) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint64_t s = offsets[i], e = offsets[i + 1], total = offsets[n];
+    if (e < s || e > total) {
+        atomicOr(&st->flags, kFlagOffsets);
+        e = s;
+        if (s > total) s = e = total;
+    }
+    uint64_t hi, lo;
+    signature_bytes(data, total, aligned, s, e, hi, lo);
+    uint32_t b = (uint32_t)bucket_of(hi, nb);
+    lo_out[i] = lo;
+    bid[i] = b;
+    atomicAdd(&counts[b], 1u);
+}
+
+// ---------------------------------------------------------------------------
+// Exclusive scan (three passes: tile sums, scan of tile sums, tile scan).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint64_t wave_inclusive_sum(uint64_t x) {
+    const uint32_t lane = threadIdx.x & 63;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        uint64_t y = __shfl_up(x, off, 64);
+        if (lane >= (uint32_t)off) x += y;
+    }
+    return x;
+}
+
+// Exclusive block sum of v over kBlock threads; *total receives the block sum.
+__device__ uint64_t block_exclusive_sum(uint64_t v, uint64_t* total) {
+    __shared__ uint64_t wsum[kBlock / 64];
+    const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    uint64_t x = wave_inclusive_sum(v);
+    if (lane == 63) wsum[wid] = x;
+    __syncthreads();
+    uint64_t pre = 0, tot = 0;
+#pragma unroll
+    for (uint32_t w = 0; w < kBlock / 64; w++) {
+        uint64_t s = wsum[w];
+        pre += w < wid ? s : 0;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return pre + x - v;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_scan_tiles(const T* __restrict__ in, uint64_t n,
+                                                      uint64_t* __restrict__ tile_sums, uint32_t* maxout) {
+    uint64_t base = (uint64_t)blockIdx.x * kScanTile;
+    uint64_t s = 0;
+    uint32_t mx = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) {
+        uint64_t i = base + (uint64_t)k * kBlock + threadIdx.x;
+        if (i < n) {
+            uint64_t v = (uint64_t)in[i];
+            s += v;
+            mx = max(mx, (uint32_t)min(v, (uint64_t)0xffffffffu));
+        }
+    }
+    uint64_t tot;
+    block_exclusive_sum(s, &tot);
+    if (threadIdx.x == 0) tile_sums[blockIdx.x] = tot;
+    if (maxout) {
+        for (int off = 32; off > 0; off >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, off, 64));
+        if ((threadIdx.x & 63) == 0) atomicMax(maxout, mx);
+    }
+}
+
+// Single block: exclusive scan of the tile sums in place.
+__global__ __launch_bounds__(kBlock) void k_scan_tile_sums(uint64_t* sums, uint64_t ntiles) {
+    __shared__ uint64_t carry_s;
+    if (threadIdx.x == 0) carry_s = 0;
+    __syncthreads();
+    for (uint64_t base = 0; base < ntiles; base += kBlock) {
+        uint64_t i = base + threadIdx.x;
+        uint64_t v = i < ntiles ? sums[i] : 0;
+        uint64_t tot;
+        uint64_t ex = block_exclusive_sum(v, &tot);
+        uint64_t carry = carry_s;
+        if (i < ntiles) sums[i] = carry + ex;
+        __syncthreads();
+        if (threadIdx.x == 0) carry_s = carry + tot;
+        __syncthreads();
+    }
+}
+
+// out[i] = sum_{j<i} in[j] for i in [0, n]; each thread owns kScanItems
+// consecutive items of the block's tile.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_scan_apply(const T* __restrict__ in, uint64_t n,
+                                                      const uint64_t* __restrict__ tile_off,
+                                                      uint64_t* __restrict__ out) {
+    uint64_t base = (uint64_t)blockIdx.x * kScanTile + (uint64_t)threadIdx.x * kScanItems;
+    uint64_t vals[kScanItems];
+    uint64_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) {
+        uint64_t i = base + k;
+        vals[k] = i < n ? (uint64_t)in[i] : 0;
+        s += vals[k];
+    }
+    uint64_t tot;
+    uint64_t run = block_exclusive_sum(s, &tot) + tile_off[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kScanItems; k++) {
+        uint64_t i = base + k;
+        if (i < n) out[i] = run;
+        run += vals[k];
+        if (i + 1 == n) out[n] = run;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Scatter into bucket-contiguous order (order inside a bucket is irrelevant:
+// every later step is a function of the bucket's key set).
+// ---------------------------------------------------------------------------
+__global__ void k_scatter(const uint64_t* __restrict__ lo, const uint32_t* __restrict__ bid, uint64_t n,
+                          const uint64_t* __restrict__ bstart, uint32_t* __restrict__ cursor,
+                          uint64_t* __restrict__ sorted) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t b = bid[i];
+    uint64_t pos = bstart[b] + atomicAdd(&cursor[b], 1u);
+    sorted[pos] = lo[i];
+}
+
+// ---------------------------------------------------------------------------
+// Seed search (Sec. 4, 5): one 64-lane wavefront per bucket walks the bucket's
+// splitting tree in preorder; at each node lane i tests candidate index
+// base + i, and the lowest successful lane of the first successful group of
+// 64 is the first index that works.
+// ---------------------------------------------------------------------------
+struct SearchArgs {
+    const uint64_t* sorted;
+    uint64_t* tmp;
+    const uint64_t* bstart;
+    uint64_t* seeds;
+    uint64_t* blen;
+    const uint32_t* R;
+    DevStatus* status;
+    uint64_t seed_cap;
+    uint32_t leaf, lower, upper;
+};
+
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63; }
+
+// Returned by a search that stopped (seed cap, duplicate keys): the bucket is
+// abandoned and the flag in DevStatus makes the build fail.
+constexpr uint64_t kNoSeed = ~0ull;
+
+__device__ __forceinline__ uint32_t lanes_below(uint64_t mask) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ uint64_t uniform64(uint64_t x) {
+    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Bijection search on a leaf of M keys (Sec. 4): the first v such that
+// x -> phi^M_{d,v}(x) is injective on the leaf.
+template <int M>
+__device__ uint64_t leaf_search(const uint64_t* keys, uint32_t depth, uint64_t cap, DevStatus* st) {
+    uint64_t k[M];
+#pragma unroll
+    for (int i = 0; i < M; i++) k[i] = uniform64(keys[i]);
+    constexpr uint32_t full = (1u << M) - 1u;
+    const uint64_t step = 64ull * kGamma;
+    uint64_t S = stream_offset(depth, lane_id());
+    for (uint64_t base = 0; base < cap; base += 64) {
+        uint32_t mask = 0;
+#pragma unroll
+        for (int i = 0; i < M; i++) mask |= 1u << __umulhi(mix64_hi32(k[i] + S), (uint32_t)M);
+        bool ok = mask == full && base + lane_id() < cap;
+        uint64_t bal = __ballot(ok);
+        if (bal) return base + (uint64_t)__builtin_ctzll(bal);
+        S += step;
+    }
+    if (lane_id() == 0) atomicOr(&st->flags, kFlagSearch);
+    return kNoSeed;
+}
+
+// True if two of the m <= 64 keys are equal (wave-uniform result).
+__device__ bool has_duplicate(const uint64_t* keys, uint32_t m) {
+    uint32_t lane = lane_id();
+    uint64_t mine = lane < m ? keys[lane] : 0;
+    bool dup = false;
+    for (uint32_t j = 0; j < m; j++) dup |= lane < m && lane > j && keys[j] == mine;
+    return __ballot(dup) != 0;
+}
+
+__device__ uint64_t leaf_dispatch(const uint64_t* keys, uint32_t m, uint32_t depth, uint64_t cap,
+                                  DevStatus* st) {
+    // Equal lower words never separate, so they always meet in one leaf, or in a
+    // split whose parts are all single keys: those nodes check every pair first.
+    if (has_duplicate(keys, m)) {
+        if (lane_id() == 0) atomicOr(&st->flags, kFlagDuplicate);
+        return kNoSeed;
+    }
+    switch (m) {
+#define RS_LEAF_CASE(M) \
+    case M:             \
+        return leaf_search<M>(keys, depth, cap, st);
+        RS_LEAF_CASE(2) RS_LEAF_CASE(3) RS_LEAF_CASE(4) RS_LEAF_CASE(5) RS_LEAF_CASE(6) RS_LEAF_CASE(7)
+        RS_LEAF_CASE(8) RS_LEAF_CASE(9) RS_LEAF_CASE(10) RS_LEAF_CASE(11) RS_LEAF_CASE(12) RS_LEAF_CASE(13)
+        RS_LEAF_CASE(14) RS_LEAF_CASE(15) RS_LEAF_CASE(16) RS_LEAF_CASE(17) RS_LEAF_CASE(18) RS_LEAF_CASE(19)
+        RS_LEAF_CASE(20) RS_LEAF_CASE(21) RS_LEAF_CASE(22) RS_LEAF_CASE(23) RS_LEAF_CASE(24)
+#undef RS_LEAF_CASE
+        default:
+            return kNoSeed;
+    }
+}
+
+// Split search (Sec. 4): the first v such that, for t = 1..NT, exactly t*unit
+// keys hash below the part boundary t*unit.  phi >= t*unit holds exactly when
+// the upper 32 hash bits are >= T[t-1] = ceil(t*unit*2^32/m), so the counting
+// compares the raw hash against NT thresholds.
+template <int NT>
+__device__ uint64_t split_search(const uint64_t* keys, uint32_t m, uint32_t depth, const uint32_t* T,
+                                 uint32_t unit, uint64_t cap, DevStatus* st) {
+    uint32_t thr[NT];
+#pragma unroll
+    for (int t = 0; t < NT; t++) thr[t] = T[t];
+    const uint64_t step = 64ull * kGamma;
+    uint64_t S = stream_offset(depth, lane_id());
+    for (uint64_t base = 0; base < cap; base += 64) {
+        uint32_t c[NT];
+#pragma unroll
+        for (int t = 0; t < NT; t++) c[t] = 0;
+        uint32_t i = 0;
+        for (; i + 4 <= m; i += 4) {
+            uint32_t h0 = mix64_hi32(keys[i] + S), h1 = mix64_hi32(keys[i + 1] + S);
+            uint32_t h2 = mix64_hi32(keys[i + 2] + S), h3 = mix64_hi32(keys[i + 3] + S);
+#pragma unroll
+            for (int t = 0; t < NT; t++)
+                c[t] += (uint32_t)(h0 < thr[t]) + (uint32_t)(h1 < thr[t]) + (uint32_t)(h2 < thr[t]) +
+                        (uint32_t)(h3 < thr[t]);
+        }
+        for (; i < m; i++) {
+            uint32_t h = mix64_hi32(keys[i] + S);
+#pragma unroll
+            for (int t = 0; t < NT; t++) c[t] += (uint32_t)(h < thr[t]);
+        }
+        bool ok = base + lane_id() < cap;
+#pragma unroll
+        for (int t = 0; t < NT; t++) ok &= c[t] == (uint32_t)(t + 1) * unit;
+        uint64_t bal = __ballot(ok);
+        if (bal) return base + (uint64_t)__builtin_ctzll(bal);
+        S += step;
+    }
+    if (lane_id() == 0) atomicOr(&st->flags, kFlagSearch);
+    return kNoSeed;
+}
+
+__device__ uint64_t split_dispatch(const uint64_t* keys, uint32_t m, uint32_t depth, const uint32_t* T,
+                                   uint32_t nt, uint32_t unit, uint64_t cap, DevStatus* st) {
+    switch (nt) {
+#define RS_SPLIT_CASE(NT) \
+    case NT:              \
+        return split_search<NT>(keys, m, depth, T, unit, cap, st);
+        RS_SPLIT_CASE(1) RS_SPLIT_CASE(2) RS_SPLIT_CASE(3) RS_SPLIT_CASE(4) RS_SPLIT_CASE(5) RS_SPLIT_CASE(6)
+        RS_SPLIT_CASE(7) RS_SPLIT_CASE(8)
+#undef RS_SPLIT_CASE
+        default:
+            return kNoSeed;
+    }
+}
+
+constexpr uint32_t kMaxThresholds = 8;  // fanout <= max(s, t) = 9 for l <= 24
+
+// Reorder the node's keys so that child j occupies [j*unit, ...): keys go to
+// global scratch at their final place and are copied back.
+__device__ void partition(uint64_t* keys, uint32_t m, uint32_t depth, uint64_t v, const uint32_t* T, uint32_t nt,
+                          uint32_t unit, uint64_t* gtmp) {
+    const uint32_t lane = lane_id();
+    const uint64_t S = stream_offset(depth, v);
+    uint32_t cursor[kMaxThresholds + 1];
+#pragma unroll
+    for (uint32_t q = 0; q <= kMaxThresholds; q++) cursor[q] = q * unit;
+    for (uint32_t c0 = 0; c0 < m; c0 += 64) {
+        uint32_t i = c0 + lane;
+        bool act = i < m;
+        uint64_t x = act ? keys[i] : 0;
+        uint32_t h = mix64_hi32(x + S);
+        uint32_t j = 0;
+        for (uint32_t t = 0; t < nt; t++) j += (uint32_t)(h >= T[t]);
+        uint32_t pos = 0;
+#pragma unroll
+        for (uint32_t q = 0; q <= kMaxThresholds; q++) {
+            if (q <= nt) {
+                uint64_t bal = __ballot(act && j == q);
+                if (act && j == q) pos = cursor[q] + lanes_below(bal);
+                cursor[q] += (uint32_t)__popcll(bal);
+            }
+        }
+        if (act) gtmp[pos] = x;
+    }
+    __syncthreads();
+    for (uint32_t i = lane; i < m; i += 64) keys[i] = gtmp[i];
+    __syncthreads();
+}
+
+__global__ __launch_bounds__(64) void k_search(SearchArgs a) {
+    extern __shared__ uint64_t lds_keys[];
+    __shared__ uint32_t stk_off[kStackDepth], stk_m[kStackDepth], stk_d[kStackDepth];
+    __shared__ uint32_t thr_s[kMaxThresholds];
+    const uint64_t b = blockIdx.x;
+    const uint32_t lane = lane_id();
+    const uint64_t start = a.bstart[b];
+    const uint32_t m0 = (uint32_t)(a.bstart[b + 1] - start);
+    for (uint32_t i = lane; i < m0; i += 64) lds_keys[i] = a.sorted[start + i];
+    if (lane == 0) {
+        stk_off[0] = 0;
+        stk_m[0] = m0;
+        stk_d[0] = 0;
+    }
+    __syncthreads();
+    int sp = 1;
+    uint64_t node = 0, bits = 0;
+    while (sp > 0) {
+        sp--;
+        const uint32_t off = stk_off[sp], m = stk_m[sp], d = stk_d[sp];
+        if (m <= 1) continue;
+        uint64_t v;
+        if (m <= a.leaf) {
+            v = leaf_dispatch(lds_keys + off, m, d, a.seed_cap, a.status);
+            if (v == kNoSeed) break;
+        } else {
+            SplitShape sh = split_shape(m, a.leaf, a.lower, a.upper);
+            if (sh.unit == 1 && has_duplicate(lds_keys + off, m)) {  // l = 1: parts of one key each
+                if (lane == 0) atomicOr(&a.status->flags, kFlagDuplicate);
+                break;
+            }
+            const uint32_t nt = sh.fanout - 1;
+            if (lane < nt) thr_s[lane] = (uint32_t)((((uint64_t)(lane + 1) * sh.unit << 32) + m - 1) / m);
+            __syncthreads();
+            v = split_dispatch(lds_keys + off, m, d, thr_s, nt, sh.unit, a.seed_cap, a.status);
+            if (v == kNoSeed) break;  // counts do not match the parts: no partition
+            partition(lds_keys + off, m, d, v, thr_s, nt, sh.unit, a.tmp + start + off);
+            if (sp + (int)sh.fanout > kStackDepth) {
+                if (lane == 0) atomicOr(&a.status->flags, kFlagStack);
+                break;
+            }
+            __syncthreads();
+            for (int j = (int)sh.fanout - 1; j >= 0; j--) {
+                if (lane == 0) {
+                    stk_off[sp] = off + (uint32_t)j * sh.unit;
+                    stk_m[sp] = (uint32_t)j + 1 == sh.fanout ? sh.last : sh.unit;
+                    stk_d[sp] = d + 1;
+                }
+                sp++;
+            }
+            __syncthreads();
+        }
+        if (lane == 0) a.seeds[start + node] = v;
+        node++;
+        uint32_t r = a.R[m];
+        bits += r + (v >> r) + 1;
+    }
+    if (lane == 0) a.blen[b] = bits;
+}
+
+// ---------------------------------------------------------------------------
+// Elias-Fano of s_i and z_i = o_i - floor(beta s_i / 2^16) (Sec. 6.3, 7.4).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t z_of(uint64_t o, uint64_t s, uint64_t beta) {
+    return (int64_t)o - (int64_t)((beta * s) >> 16);
+}
+
+__global__ void k_ef_gaps(const uint64_t* __restrict__ bstart, const uint64_t* __restrict__ ostart, uint64_t nb,
+                          uint64_t n, DevStatus* st) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t beta = (ostart[nb] << 16) / n;
+    unsigned long long gs = ~0ull;
+    long long gz = 0x7fffffffffffffffll;
+    if (i < nb) {
+        gs = bstart[i + 1] - bstart[i];
+        gz = z_of(ostart[i + 1], bstart[i + 1], beta) - z_of(ostart[i], bstart[i], beta);
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        gs = min(gs, (unsigned long long)__shfl_xor(gs, off, 64));
+        gz = min(gz, (long long)__shfl_xor(gz, off, 64));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMin(&st->delta_s, gs);
+        atomicMin(&st->delta_z, gz);
+    }
+}
+
+__device__ __forceinline__ void or_bits(unsigned long long* a, uint64_t pos, uint64_t val, uint32_t nbits) {
+    if (nbits == 0) return;
+    uint64_t w = pos >> 6;
+    uint32_t o = (uint32_t)(pos & 63);
+    atomicOr(&a[w], (unsigned long long)(val << o));
+    if (o + nbits > 64) atomicOr(&a[w + 1], (unsigned long long)(val >> (64 - o)));
+}
+
+struct FillArgs {
+    const uint64_t* bstart;
+    const uint64_t* ostart;
+    const uint64_t* seeds;
+    const uint32_t* R;
+    const uint32_t* F;
+    unsigned long long* blob;
+    uint64_t nb, beta, delta_s;
+    int64_t delta_z;
+    uint32_t Ws, Wz;
+    uint64_t lower_off, us_off, uz_off, invs_off, invz_off, tree_off;
+    uint32_t leaf, lower, upper;
+};
+
+__global__ void k_ef_fill(FillArgs a) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > a.nb) return;
+    uint64_t s = a.bstart[i];
+    int64_t z = z_of(a.ostart[i], s, a.beta);
+    uint64_t ys = s - i * a.delta_s;
+    uint64_t yz = (uint64_t)(z - (int64_t)i * a.delta_z);
+    uint64_t lpos = i * (uint64_t)(a.Ws + a.Wz);
+    uint64_t ms = a.Ws ? (~0ull >> (64 - a.Ws)) : 0, mz = a.Wz ? (~0ull >> (64 - a.Wz)) : 0;
+    or_bits(a.blob + a.lower_off, lpos, ys & ms, a.Ws);
+    or_bits(a.blob + a.lower_off, lpos + a.Ws, yz & mz, a.Wz);
+    uint64_t ps = (ys >> a.Ws) + i, pz = (yz >> a.Wz) + i;
+    or_bits(a.blob + a.us_off, ps, 1, 1);
+    or_bits(a.blob + a.uz_off, pz, 1, 1);
+    if ((i & ((1u << kInvShift) - 1)) == 0) {
+        a.blob[a.invs_off + (i >> kInvShift)] = ps;
+        a.blob[a.invz_off + (i >> kInvShift)] = pz;
+    }
+}
+
+// Golomb-Rice streams (Sec. 6.2): per bucket, the fixed parts of all coded
+// nodes in preorder, then their unary parts (q zeros and a one) in preorder.
+__global__ void k_tree_bits(FillArgs a) {
+    uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= a.nb) return;
+    uint64_t start = a.bstart[b];
+    uint32_t m0 = (uint32_t)(a.bstart[b + 1] - start);
+    if (m0 <= 1) return;
+    unsigned long long* tree = a.blob + a.tree_off;
+    uint64_t fp = a.ostart[b], up = fp + a.F[m0];
+    uint32_t stk[kStackDepth];
+    int sp = 0;
+    stk[sp++] = m0;
+    uint64_t node = 0;
+    while (sp > 0) {
+        uint32_t m = stk[--sp];
+        if (m <= 1) continue;
+        uint64_t v = a.seeds[start + node++];
+        uint32_t r = a.R[m];
+        or_bits(tree, fp, r ? (v & (~0ull >> (64 - r))) : 0, r);
+        fp += r;
+        up += v >> r;
+        or_bits(tree, up, 1, 1);
+        up++;
+        if (m > a.leaf) {
+            SplitShape sh = split_shape(m, a.leaf, a.lower, a.upper);
+            if (sp + (int)sh.fanout > kStackDepth) return;  // cannot happen: the search flagged it
+            stk[sp++] = sh.last;
+            for (uint32_t j = 1; j < sh.fanout; j++) stk[sp++] = sh.unit;
+        }
+    }
+}
+
+__global__ void k_write_header(uint64_t* blob, uint64_t h0, uint64_t h1, uint64_t h2, uint64_t h3, uint64_t h4,
+                               uint64_t h5, uint64_t h6, uint64_t h7, uint64_t h8, uint64_t h9, uint64_t h10,
+                               uint64_t h11, uint64_t h12, uint64_t h13, uint64_t h14, uint64_t h15) {
+    if (threadIdx.x == 0) {
+        blob[0] = h0; blob[1] = h1; blob[2] = h2; blob[3] = h3; blob[4] = h4; blob[5] = h5; blob[6] = h6;
+        blob[7] = h7; blob[8] = h8; blob[9] = h9; blob[10] = h10; blob[11] = h11; blob[12] = h12;
+        blob[13] = h13; blob[14] = h14; blob[15] = h15;
+    }
+}
+
+uint32_t grid_for(uint64_t n, uint32_t block) { return (uint32_t)std::max<uint64_t>(1, (n + block - 1) / block); }
+
+// Exclusive scan of n values into out[0..n]; tiles holds ceil(n/kScanTile)+1 words.
+template <typename T>
+int scan(const T* in, uint64_t n, uint64_t* out, uint64_t* tiles, uint32_t* maxout, hipStream_t s) {
+    uint64_t ntiles = std::max<uint64_t>(1, (n + kScanTile - 1) / kScanTile);
+    k_scan_tiles<T><<<(uint32_t)ntiles, kBlock, 0, s>>>(in, n, tiles, maxout);
+    k_scan_tile_sums<<<1, kBlock, 0, s>>>(tiles, ntiles);
+    k_scan_apply<T><<<(uint32_t)ntiles, kBlock, 0, s>>>(in, n, tiles, out);
+    RS_HIP(hipGetLastError());
+    return RS_OK;
+}
+
+uint32_t ef_width(uint64_t N, uint64_t U) {
+    uint32_t W = 0;
+    while (W < 62 && (N << (W + 1)) >> (W + 1) == N && (N << (W + 1)) <= U) W++;
+    return W;
+}
+
+struct Pinned {
+    DevStatus st;
+    uint64_t total_bits;
+    uint64_t pad[7];
+};
+
+Pinned* pinned_scratch() {
+    static thread_local Pinned* p = nullptr;
+    if (!p && hipHostMalloc((void**)&p, sizeof(Pinned), hipHostMallocDefault) != hipSuccess) p = nullptr;
+    return p;
+}
+
+thread_local rs_build_stats g_stats;
+thread_local bool g_stats_valid = false;
+
+struct PhaseEvents {
+    hipEvent_t ev[6] = {};
+    bool on = false;
+    int create(bool enable) {
+        on = enable;
+        if (!on) return RS_OK;
+        for (auto& e : ev)
+            if (hipEventCreate(&e) != hipSuccess) return fail(RS_EDEVICE, "hipEventCreate failed");
+        return RS_OK;
+    }
+    void record(int i, hipStream_t s) {
+        if (on) (void)hipEventRecord(ev[i], s);
+    }
+    double ms(int a, int b) {
+        float t = 0;
+        (void)hipEventElapsedTime(&t, ev[a], ev[b]);
+        return t;
+    }
+    ~PhaseEvents() {
+        for (auto& e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
+int max_lds_bytes() {
+    static int v = -1;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        hipDeviceProp_t prop;
+        v = hipGetDeviceProperties(&prop, dev) == hipSuccess ? (int)prop.sharedMemPerBlock : 65536;
+    });
+    return v;
+}
+
+}  // namespace
+
+int build_impl(const rs_keys* keys, uint32_t leaf, uint32_t bucket, const rs_options* opts, hipStream_t s,
+               rs_blob** out) {
+    if (!keys || !out) return fail(RS_EINVAL, "NULL argument");
+    if (keys->n == 0) return fail(RS_EINVAL, "empty key set");
+    if (leaf < 1 || leaf > kMaxLeaf) return fail(RS_EINVAL, "leaf size %u outside [1, 24]", leaf);
+    if (bucket == 0) return fail(RS_EINVAL, "bucket size must be positive");
+    if (!keys->data) return fail(RS_EINVAL, "NULL key data");
+    if (keys->kind != RS_KEYS_U64 && keys->kind != RS_KEYS_BYTES) return fail(RS_EINVAL, "unknown key kind");
+    if (keys->kind == RS_KEYS_BYTES && !keys->offsets) return fail(RS_EINVAL, "NULL offsets for byte keys");
+    const uint64_t n = keys->n;
+    const uint64_t nb = (n + bucket - 1) / bucket;
+    if (nb >= (1ull << 32)) return fail(RS_EINVAL, "too many buckets");
+    const uint64_t cap = opts && opts->seed_cap ? std::min(opts->seed_cap, kDefaultSeedCap) : kDefaultSeedCap;
+    const Strategy st = make_strategy(leaf);
+    Pinned* pin = pinned_scratch();
+    if (!pin) return fail(RS_ENOMEM, "pinned host allocation failed");
+    const bool timing = opts && (opts->flags & RS_OPT_TIMING);
+    PhaseEvents pe;
+    if (int rc0 = pe.create(timing)) return rc0;
+
+    // workspace
+    const uint64_t ntiles_n = (n + kScanTile - 1) / kScanTile + 1;
+    const uint64_t ntiles_b = (nb + 1 + kScanTile - 1) / kScanTile + 1;
+    size_t off = 0;
+    auto carve = [&](size_t bytes) {
+        size_t o = off;
+        off += (bytes + 255) & ~size_t(255);
+        return o;
+    };
+    const size_t o_lo = carve(n * 8), o_bid = carve(n * 4), o_cnt = carve(nb * 4), o_cur = carve(nb * 4);
+    const size_t o_bst = carve((nb + 1) * 8), o_sorted = carve(n * 8), o_tmp = carve(n * 8), o_seeds = carve(n * 8);
+    const size_t o_blen = carve(nb * 8), o_ost = carve((nb + 1) * 8);
+    const size_t o_tiles = carve(std::max(ntiles_n, ntiles_b) * 8), o_st = carve(sizeof(DevStatus));
+    char* ws = nullptr;
+    if (int rc = dev_alloc((void**)&ws, off, s)) return rc;
+    uint64_t* d_lo = (uint64_t*)(ws + o_lo);
+    uint32_t* d_bid = (uint32_t*)(ws + o_bid);
+    uint32_t* d_cnt = (uint32_t*)(ws + o_cnt);
+    uint32_t* d_cur = (uint32_t*)(ws + o_cur);
+    uint64_t* d_bst = (uint64_t*)(ws + o_bst);
+    uint64_t* d_sorted = (uint64_t*)(ws + o_sorted);
+    uint64_t* d_tmp = (uint64_t*)(ws + o_tmp);
+    uint64_t* d_seeds = (uint64_t*)(ws + o_seeds);
+    uint64_t* d_blen = (uint64_t*)(ws + o_blen);
+    uint64_t* d_ost = (uint64_t*)(ws + o_ost);
+    uint64_t* d_tiles = (uint64_t*)(ws + o_tiles);
+    DevStatus* d_st = (DevStatus*)(ws + o_st);
+    uint32_t* d_tab = nullptr;
+    uint64_t* d_blob = nullptr;
+    int rc = RS_OK;
+
+    auto cleanup = [&](int code) {
+        dev_free(ws, s);
+        if (code != RS_OK) {
+            dev_free(d_tab, s);
+            dev_free(d_blob, s);
+        }
+        return code;
+    };
+#define RS_TRY(call)                                                          \
+    do {                                                                      \
+        hipError_t e_ = (call);                                               \
+        if (e_ != hipSuccess)                                                 \
+            return cleanup(fail(RS_EDEVICE, "%s: %s", #call, hipGetErrorString(e_))); \
+    } while (0)
+
+    pe.record(0, s);
+    k_init_status<<<1, 64, 0, s>>>(d_st);
+    k_fill_u32<<<grid_for(nb, kBlock * 4), kBlock, 0, s>>>(d_cnt, nb, 0);
+    k_fill_u32<<<grid_for(nb, kBlock * 4), kBlock, 0, s>>>(d_cur, nb, 0);
+    if (keys->kind == RS_KEYS_U64) {
+        k_signature_u64<<<grid_for(n, kBlock), kBlock, 0, s>>>((const uint64_t*)keys->data, n, nb, d_lo, d_bid,
+                                                               d_cnt);
+    } else {
+        bool aligned = ((uintptr_t)keys->data & 7) == 0;
+        k_signature_bytes<<<grid_for(n, kBlock), kBlock, 0, s>>>((const uint8_t*)keys->data, keys->offsets, n,
+                                                                 nb, aligned, d_lo, d_bid, d_cnt, d_st);
+    }
+    RS_TRY(hipGetLastError());
+    if ((rc = scan<uint32_t>(d_cnt, nb, d_bst, d_tiles, &d_st->maxm, s))) return cleanup(rc);
+    RS_TRY(hipMemcpyAsync(&pin->st, d_st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+    RS_TRY(hipStreamSynchronize(s));
+    if (pin->st.flags & kFlagOffsets) return cleanup(fail(RS_EINVAL, "byte-key offsets are not monotone"));
+    const uint32_t maxm = pin->st.maxm;
+    if ((uint64_t)maxm * 8 > (uint64_t)max_lds_bytes() - 2048)
+        return cleanup(fail(RS_EINVAL, "largest bucket (%u keys) exceeds the local data share", maxm));
+
+    // per-size tables
+    TableView tv = host_tables(leaf, maxm);
+    if (!tv.data) return cleanup(fail(RS_ENOMEM, "table allocation failed"));
+    if ((rc = dev_alloc((void**)&d_tab, 3ull * (maxm + 1) * 4, s))) return cleanup(rc);
+    RS_TRY(hipMemcpyAsync(d_tab, tv.r(), (maxm + 1) * 4ull, hipMemcpyHostToDevice, s));
+    RS_TRY(hipMemcpyAsync(d_tab + (maxm + 1), tv.F(), (maxm + 1) * 4ull, hipMemcpyHostToDevice, s));
+    RS_TRY(hipMemcpyAsync(d_tab + 2 * (maxm + 1), tv.N(), (maxm + 1) * 4ull, hipMemcpyHostToDevice, s));
+
+    pe.record(1, s);
+    k_scatter<<<grid_for(n, kBlock), kBlock, 0, s>>>(d_lo, d_bid, n, d_bst, d_cur, d_sorted);
+    SearchArgs sa{d_sorted, d_tmp, d_bst, d_seeds, d_blen, d_tab, d_st, cap, leaf, st.lower, st.upper};
+    pe.record(2, s);
+    k_search<<<(uint32_t)nb, 64, (size_t)maxm * 8, s>>>(sa);
+    pe.record(3, s);
+    RS_TRY(hipGetLastError());
+    if ((rc = scan<uint64_t>(d_blen, nb, d_ost, d_tiles, nullptr, s))) return cleanup(rc);
+    k_ef_gaps<<<grid_for(nb, kBlock), kBlock, 0, s>>>(d_bst, d_ost, nb, n, d_st);
+    pe.record(4, s);
+    RS_TRY(hipGetLastError());
+    RS_TRY(hipMemcpyAsync(&pin->st, d_st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+    RS_TRY(hipMemcpyAsync(&pin->total_bits, d_ost + nb, 8, hipMemcpyDeviceToHost, s));
+    RS_TRY(hipStreamSynchronize(s));
+    const uint32_t flags = pin->st.flags;
+    if (flags & kFlagDuplicate) return cleanup(fail(RS_EDUPLICATE, "duplicate keys (equal signatures)"));
+    if (flags & kFlagSearch) return cleanup(fail(RS_ESEARCH, "an index search reached the seed cap"));
+    if (flags & kFlagStack) return cleanup(fail(RS_EDEVICE, "splitting tree deeper than supported"));
+
+    // blob geometry
+    const uint64_t total_bits = pin->total_bits;
+    const uint64_t beta = (total_bits << 16) / n;
+    const uint64_t delta_s = pin->st.delta_s;
+    const int64_t delta_z = pin->st.delta_z;
+    const uint64_t N = nb + 1;
+    const uint64_t ys_last = n - nb * delta_s;
+    const int64_t z_last = (int64_t)total_bits - (int64_t)((beta * n) >> 16);
+    const uint64_t yz_last = (uint64_t)(z_last - (int64_t)nb * delta_z);
+    const uint32_t Ws = ef_width(N, ys_last), Wz = ef_width(N, yz_last);
+    const uint64_t us_words = ((ys_last >> Ws) + N + 63) / 64, uz_words = ((yz_last >> Wz) + N + 63) / 64;
+    const uint64_t lower_words = (N * (Ws + Wz) + 63) / 64 + 1;
+    const uint64_t ninv = (N + (1u << kInvShift) - 1) >> kInvShift;
+    const uint64_t tree_words = (total_bits + 63) / 64 + 1;
+    const uint64_t total_words = kHeaderWords + lower_words + us_words + uz_words + 2 * ninv + tree_words;
+    if ((rc = dev_alloc((void**)&d_blob, total_words * 8, s))) return cleanup(rc);
+    k_fill_u64<<<grid_for(total_words, kBlock * 8), kBlock, 0, s>>>(d_blob, total_words, 0);
+
+    rs_blob* blob = new (std::nothrow) rs_blob;
+    if (!blob) return cleanup(fail(RS_ENOMEM, "host allocation failed"));
+    uint64_t* h = blob->header;
+    h[0] = kMagic;
+    h[1] = kVersion | ((uint64_t)keys->kind << 32);
+    h[2] = n; h[3] = leaf; h[4] = bucket; h[5] = nb; h[6] = maxm;
+    h[7] = (uint64_t)Ws | ((uint64_t)Wz << 8);
+    h[8] = delta_s; h[9] = (uint64_t)delta_z; h[10] = beta;
+    h[11] = us_words; h[12] = uz_words; h[13] = lower_words; h[14] = tree_words; h[15] = total_bits;
+    Layout L = layout_of(h);
+    FillArgs fa{d_bst, d_ost, d_seeds, d_tab, d_tab + (maxm + 1), (unsigned long long*)d_blob, nb, beta,
+                delta_s, delta_z, Ws, Wz, L.lower_off, L.us_off, L.uz_off, L.invs_off, L.invz_off, L.tree_off,
+                leaf, st.lower, st.upper};
+    k_write_header<<<1, 64, 0, s>>>(d_blob, h[0], h[1], h[2], h[3], h[4], h[5], h[6], h[7], h[8], h[9], h[10],
+                                    h[11], h[12], h[13], h[14], h[15]);
+    k_ef_fill<<<grid_for(N, kBlock), kBlock, 0, s>>>(fa);
+    k_tree_bits<<<grid_for(nb, 64), 64, 0, s>>>(fa);
+    pe.record(5, s);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        delete blob;
+        return cleanup(fail(RS_EDEVICE, "launch failed: %s", hipGetErrorString(e)));
+    }
+    if (timing) {
+        if (hipStreamSynchronize(s) != hipSuccess) {
+            delete blob;
+            return cleanup(fail(RS_EDEVICE, "stream synchronisation failed"));
+        }
+        g_stats.ms_signature = pe.ms(0, 1);
+        g_stats.ms_scatter = pe.ms(1, 2);
+        g_stats.ms_search = pe.ms(2, 3);
+        g_stats.ms_offsets = pe.ms(3, 4);
+        g_stats.ms_fill = pe.ms(4, 5);
+        g_stats.ms_device = pe.ms(0, 5);
+        g_stats.n = n;
+        g_stats.nb = nb;
+        g_stats.maxm = maxm;
+        g_stats.tree_bits = total_bits;
+        g_stats.blob_bytes = total_words * 8;
+        g_stats_valid = true;
+    }
+    blob->words = d_blob;
+    blob->bytes = total_words * 8;
+    blob->tables = d_tab;
+    blob->stream = s;
+    (void)hipGetDevice(&blob->device);
+    cleanup(RS_OK);
+    *out = blob;
+    return RS_OK;
+#undef RS_TRY
+}
+
+}  // namespace rs
+
+extern "C" int rs_build_ex(const rs_keys* keys, uint32_t leaf, uint32_t bucket, const rs_options* opts, void* stream,
+                           rs_blob** out) {
+    rs::clear_error();
+    return rs::build_impl(keys, leaf, bucket, opts, (hipStream_t)stream, out);
+}
+
+extern "C" int rs_last_build_stats(rs_build_stats* out) {
+    if (!out) return rs::fail(RS_EINVAL, "NULL argument");
+    if (!rs::g_stats_valid) return rs::fail(RS_EINVAL, "no timed build on this thread");
+    *out = rs::g_stats;
+    return RS_OK;
+}
+
+extern "C" int rs_build(const rs_keys* keys, uint32_t leaf, uint32_t bucket, void* stream, rs_blob** out) {
+    return rs_build_ex(keys, leaf, bucket, nullptr, stream, out);
+}

@@ -1,0 +1,56 @@
+// Host-side helpers shared by the translation units of librecsplit.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <string>
+
+#include "rs_internal.h"
+
+struct rs_blob {
+    uint64_t* words = nullptr;   // serialized structure on the device
+    uint64_t bytes = 0;
+    uint32_t* tables = nullptr;  // device r, F, N for sizes 0..maxm (3 * (maxm + 1) u32)
+    uint64_t header[rs::kHeaderWords] = {};
+    hipStream_t stream = nullptr;
+    int device = 0;
+};
+
+namespace rs {
+
+// Sets the calling thread's error message and returns code.
+int fail(int code, const char* fmt, ...);
+void clear_error();
+
+// Stream-ordered device allocation used for every buffer of the library.
+int dev_alloc(void** p, size_t bytes, hipStream_t s);
+void dev_free(void* p, hipStream_t s);
+
+// Blob geometry decoded from a header.
+struct Layout {
+    uint64_t n, leaf, bucket, nb, maxm, kind;
+    uint32_t Ws, Wz;
+    uint64_t delta_s;
+    int64_t delta_z;
+    uint64_t beta;
+    uint64_t us_words, uz_words, lower_words, tree_words, tree_bits;
+    uint64_t ninv;
+    // word offsets from the start of the blob
+    uint64_t lower_off, us_off, uz_off, invs_off, invz_off, tree_off, total_words;
+};
+Layout layout_of(const uint64_t* header);
+
+// Upload the per-size tables of (leaf, maxm) into dst (3 * (maxm + 1) u32).
+int upload_tables(uint32_t leaf, uint32_t maxm, uint32_t* dst, hipStream_t s);
+
+}  // namespace rs
+
+#define RS_HIP(call)                                                                       \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return rs::fail(RS_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_));   \
+    } while (0)

@@ -1,0 +1,222 @@
+"""Python binding of librecsplit (argument marshalling only).
+
+Every step of construction and lookup runs in the HIP kernels of
+``librecsplit.so``; PyTorch only provides device memory and the current
+stream.  There is no CPU fallback: if the library is missing or no GPU is
+present the calls raise.
+
+Keys are either a CUDA tensor of 64-bit integers (int64 or uint64, viewed as
+unsigned) or a pair ``(data, offsets)`` of CUDA tensors for byte strings:
+``data`` uint8 with the concatenated bytes, ``offsets`` int64/uint64 with n+1
+non-decreasing entries.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librecsplit.so")
+
+RS_OK, RS_EINVAL, RS_EDUPLICATE, RS_ENOMEM, RS_EDEVICE, RS_ESEARCH, RS_EFORMAT, RS_EBUSY = range(8)
+RS_KEYS_U64, RS_KEYS_BYTES = 1, 2
+STATUS_NAMES = {0: "RS_OK", 1: "RS_EINVAL", 2: "RS_EDUPLICATE", 3: "RS_ENOMEM", 4: "RS_EDEVICE", 5: "RS_ESEARCH",
+                6: "RS_EFORMAT", 7: "RS_EBUSY"}
+
+
+class RecSplitError(RuntimeError):
+    def __init__(self, code: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {message}")
+        self.code = code
+
+
+class rs_keys(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_uint32), ("data", ctypes.c_void_p), ("offsets", ctypes.c_void_p),
+                ("n", ctypes.c_uint64)]
+
+
+class rs_options(ctypes.Structure):
+    _fields_ = [("seed_cap", ctypes.c_uint64), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 5)]
+
+
+RS_OPT_TIMING = 1
+
+
+class rs_build_stats(ctypes.Structure):
+    _fields_ = [("ms_signature", ctypes.c_double), ("ms_scatter", ctypes.c_double), ("ms_search", ctypes.c_double),
+                ("ms_offsets", ctypes.c_double), ("ms_fill", ctypes.c_double), ("ms_device", ctypes.c_double),
+                ("n", ctypes.c_uint64), ("nb", ctypes.c_uint64), ("maxm", ctypes.c_uint64),
+                ("tree_bits", ctypes.c_uint64), ("blob_bytes", ctypes.c_uint64)]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load librecsplit.so (built in-tree by ``__graft_entry__.build()``)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        L = ctypes.CDLL(LIB_PATH)
+        P, U32, U64 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64
+        L.rs_build.argtypes = [ctypes.POINTER(rs_keys), U32, U32, P, ctypes.POINTER(P)]
+        L.rs_build_ex.argtypes = [ctypes.POINTER(rs_keys), U32, U32, ctypes.POINTER(rs_options), P,
+                                  ctypes.POINTER(P)]
+        L.rs_lookup.argtypes = [P, ctypes.POINTER(rs_keys), P, P]
+        L.rs_blob_bytes.argtypes = [P]
+        L.rs_blob_bytes.restype = U64
+        L.rs_blob_to_host.argtypes = [P, P, U64]
+        L.rs_blob_from_host.argtypes = [P, U64, P, ctypes.POINTER(P)]
+        L.rs_blob_device_ptr.argtypes = [P]
+        L.rs_blob_device_ptr.restype = P
+        L.rs_blob_info.argtypes = [P, ctypes.POINTER(U64), ctypes.POINTER(U32), ctypes.POINTER(U32)]
+        L.rs_blob_free.argtypes = [P]
+        L.rs_blob_free.restype = None
+        L.rs_last_error.restype = ctypes.c_char_p
+        L.rs_version.restype = ctypes.c_char_p
+        L.rs_tables.argtypes = [U32, U32, P, P, P]
+        L.rs_last_build_stats.argtypes = [ctypes.POINTER(rs_build_stats)]
+        for f in ("rs_build", "rs_build_ex", "rs_lookup", "rs_blob_to_host", "rs_blob_from_host", "rs_blob_info",
+                  "rs_tables", "rs_last_build_stats"):
+            getattr(L, f).restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != RS_OK:
+        raise RecSplitError(rc, lib().rs_last_error().decode())
+
+
+def _stream(stream):
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _as_keys(keys) -> rs_keys:
+    import torch
+
+    if isinstance(keys, tuple):
+        data, offsets = keys
+        if not (data.is_cuda and offsets.is_cuda):
+            raise ValueError("keys must be CUDA tensors")
+        if data.dtype != torch.uint8 or offsets.dtype not in (torch.int64, torch.uint64):
+            raise ValueError("byte keys need (uint8 data, int64/uint64 offsets)")
+        if not (data.is_contiguous() and offsets.is_contiguous()):
+            raise ValueError("key tensors must be contiguous")
+        return rs_keys(RS_KEYS_BYTES, data.data_ptr(), offsets.data_ptr(), offsets.numel() - 1)
+    if not keys.is_cuda or keys.dtype not in (torch.int64, torch.uint64) or not keys.is_contiguous():
+        raise ValueError("u64 keys must be a contiguous CUDA int64/uint64 tensor")
+    return rs_keys(RS_KEYS_U64, keys.data_ptr(), None, keys.numel())
+
+
+class Blob:
+    """A built structure resident in device memory."""
+
+    def __init__(self, handle: ctypes.c_void_p):
+        self._h = handle
+
+    @property
+    def handle(self) -> ctypes.c_void_p:
+        if not self._h:
+            raise RuntimeError("blob was freed")
+        return self._h
+
+    @property
+    def nbytes(self) -> int:
+        return int(lib().rs_blob_bytes(self.handle))
+
+    def info(self):
+        n, leaf, bucket = ctypes.c_uint64(), ctypes.c_uint32(), ctypes.c_uint32()
+        _check(lib().rs_blob_info(self.handle, ctypes.byref(n), ctypes.byref(leaf), ctypes.byref(bucket)))
+        return n.value, leaf.value, bucket.value
+
+    def bits_per_key(self) -> float:
+        return 8.0 * self.nbytes / self.info()[0]
+
+    def to_bytes(self) -> bytes:
+        buf = np.zeros(self.nbytes, dtype=np.uint8)
+        _check(lib().rs_blob_to_host(self.handle, buf.ctypes.data, buf.size))
+        return buf.tobytes()
+
+    def lookup(self, keys, out=None, stream=None):
+        return lookup(self, keys, out=out, stream=stream)
+
+    def free(self):
+        if self._h:
+            lib().rs_blob_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def build(keys, leaf: int, bucket: int, seed_cap: int = 0, timing: bool = False, stream=None) -> Blob:
+    """Build the minimal perfect hash function of a device key set.  With
+    timing=True the per-phase device times are available from last_build_stats()."""
+    k = _as_keys(keys)
+    h = ctypes.c_void_p()
+    opts = rs_options(seed_cap, RS_OPT_TIMING if timing else 0)
+    _check(lib().rs_build_ex(ctypes.byref(k), leaf, bucket, ctypes.byref(opts), _stream(stream), ctypes.byref(h)))
+    return Blob(h)
+
+
+def lookup(blob: Blob, keys, out=None, stream=None):
+    """Ranks of the keys (a CUDA int64 tensor holding the unsigned values)."""
+    import torch
+
+    k = _as_keys(keys)
+    if out is None:
+        out = torch.empty(int(k.n), dtype=torch.int64, device="cuda")
+    if out.numel() != k.n or not out.is_contiguous():
+        raise ValueError("output tensor has the wrong shape")
+    _check(lib().rs_lookup(blob.handle, ctypes.byref(k), ctypes.c_void_p(out.data_ptr()), _stream(stream)))
+    return out
+
+
+def from_bytes(data: bytes, stream=None) -> Blob:
+    buf = np.frombuffer(data, dtype=np.uint8).copy()
+    h = ctypes.c_void_p()
+    _check(lib().rs_blob_from_host(buf.ctypes.data, buf.size, _stream(stream), ctypes.byref(h)))
+    return Blob(h)
+
+
+def tables(leaf: int, maxm: int):
+    """The library's per-size tables (Golomb-Rice parameter, fixed bits and
+    coded nodes of a subtree) for sizes 0..maxm."""
+    r = np.zeros(maxm + 1, dtype=np.uint32)
+    F = np.zeros(maxm + 1, dtype=np.uint32)
+    N = np.zeros(maxm + 1, dtype=np.uint32)
+    _check(lib().rs_tables(leaf, maxm, r.ctypes.data, F.ctypes.data, N.ctypes.data))
+    return r, F, N
+
+
+def last_build_stats() -> dict:
+    st = rs_build_stats()
+    _check(lib().rs_last_build_stats(ctypes.byref(st)))
+    return {name: getattr(st, name) for name, _ in rs_build_stats._fields_}
+
+
+def version() -> str:
+    return lib().rs_version().decode()
+
+
+def device_keys(keys):
+    """Copy host keys (numpy uint64 array, or (uint8 data, uint64 offsets)) to the GPU."""
+    import torch
+
+    if isinstance(keys, tuple):
+        data, offsets = keys
+        d = torch.from_numpy(np.ascontiguousarray(data, dtype=np.uint8)).cuda()
+        o = torch.from_numpy(np.ascontiguousarray(offsets, dtype=np.uint64).view(np.int64)).cuda()
+        return d, o
+    return torch.from_numpy(np.ascontiguousarray(keys, dtype=np.uint64).view(np.int64)).cuda()

@@ -1,0 +1,66 @@
+"""The C-ABI library loads on the CPU and exports every entry point its
+header declares; the library's host tables equal the oracle's."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "recsplit.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rs_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1910_06416_amd import recsplit
+
+    return recsplit.lib()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("rs_build", "rs_lookup", "rs_blob_bytes", "rs_blob_to_host", "rs_blob_from_host",
+                     "rs_blob_free", "rs_last_error"):
+        assert required in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [name for name in declared_functions() if not hasattr(lib, name)]
+    assert not missing, missing
+
+
+def test_version_string(lib):
+    assert b"gfx950" in lib.rs_version()
+
+
+@pytest.mark.parametrize("leaf", range(1, 25))
+def test_library_tables_equal_oracle_tables(orc, leaf):
+    from paper_1910_06416_amd import recsplit
+
+    r, F, N = recsplit.tables(leaf, 4096)
+    r2, F2, N2 = orc.tables(leaf, 4096)
+    assert np.array_equal(r, r2) and np.array_equal(F, F2) and np.array_equal(N, N2)
+
+
+def test_argument_validation_without_device(lib):
+    from paper_1910_06416_amd import recsplit
+
+    keys = recsplit.rs_keys(recsplit.RS_KEYS_U64, None, None, 0)
+    out = ctypes.c_void_p()
+    assert lib.rs_build(ctypes.byref(keys), 8, 100, None, ctypes.byref(out)) == recsplit.RS_EINVAL
+    keys.n = 10
+    assert lib.rs_build(ctypes.byref(keys), 8, 100, None, ctypes.byref(out)) == recsplit.RS_EINVAL
+    keys.data = 16
+    assert lib.rs_build(ctypes.byref(keys), 25, 100, None, ctypes.byref(out)) == recsplit.RS_EINVAL
+    assert lib.rs_build(ctypes.byref(keys), 8, 0, None, ctypes.byref(out)) == recsplit.RS_EINVAL
+    assert b"bucket" in lib.rs_last_error()
+    bad = np.zeros(16, dtype=np.uint64)
+    assert lib.rs_blob_from_host(bad.ctypes.data, 128, None, ctypes.byref(out)) == recsplit.RS_EFORMAT
+    assert out.value is None

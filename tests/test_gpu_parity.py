@@ -1,0 +1,139 @@
+"""GPU parity: the HIP path reproduces the oracle's blob byte for byte and its
+ranks element by element, on the same seeded inputs.  Integer work, so the
+bar is bit-exactness."""
+import numpy as np
+import pytest
+
+from paper_1910_06416_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rs():
+    import torch
+
+    assert torch.cuda.is_available()
+    from paper_1910_06416_amd import recsplit
+
+    recsplit.lib()
+    return recsplit
+
+
+def _first_difference(a: bytes, b: bytes, orc):
+    if len(a) != len(b):
+        return f"sizes differ: gpu {len(a)} oracle {len(b)}"
+    x = np.frombuffer(a, dtype=np.uint64)
+    y = np.frombuffer(b, dtype=np.uint64)
+    bad = np.flatnonzero(x != y)
+    h = orc.header(b)
+    return f"{len(bad)} words differ, first at word {bad[0]} (header {h})"
+
+
+def _check_build(rs, orc, keys, leaf, bucket, lookups=True):
+    print(f"case n={len(keys[1]) - 1 if isinstance(keys, tuple) else len(keys)} leaf={leaf} bucket={bucket}",
+          flush=True)
+    blob = rs.build(rs.device_keys(keys), leaf, bucket)
+    got = blob.to_bytes()
+    want = orc.build(keys, leaf, bucket)
+    assert got == want, _first_difference(got, want, orc)
+    if lookups:
+        ranks = rs.lookup(blob, rs.device_keys(keys)).cpu().numpy().view(np.uint64)
+        assert np.array_equal(ranks, orc.lookup(want, keys))
+        n = len(ranks)
+        assert np.array_equal(np.sort(ranks), np.arange(n, dtype=np.uint64))
+    return blob, want
+
+
+@pytest.mark.parametrize(
+    "n,leaf,bucket",
+    [(1, 8, 100), (2, 8, 100), (3, 1, 1), (17, 2, 3), (100, 8, 100), (1000, 5, 5), (3000, 12, 9), (5000, 8, 100),
+     (2000, 4, 2000), (20000, 8, 1000), (4000, 3, 64), (777, 1, 10), (5000, 16, 40), (60, 24, 12), (1234, 7, 1)],
+)
+def test_blob_parity_u64_shapes(rs, orc, n, leaf, bucket):
+    _check_build(rs, orc, inputs.u64_keys(n, 1000 + n + leaf), leaf, bucket)
+
+
+def test_blob_parity_cfg_100k_l8_b100(rs, orc):
+    """100,000 uniform random 64-bit keys, l=8, b=100."""
+    blob, want = _check_build(rs, orc, inputs.u64_keys(100_000, 1), 8, 100)
+    assert 1.78 <= 8 * len(want) / 100_000 <= 1.82
+
+
+@pytest.mark.parametrize("n,leaf,bucket", [(1, 8, 100), (777, 8, 100), (100_000, 8, 100), (5000, 6, 50)])
+def test_blob_parity_strings(rs, orc, n, leaf, bucket):
+    _check_build(rs, orc, inputs.ascii_keys(n, 2000 + n), leaf, bucket)
+
+
+def test_blob_parity_strings_unaligned_and_short(rs, orc):
+    import torch
+
+    strings = [b"", b"a", b"ab", b"abcdefgh", b"abcdefghi", b"\x00", b"\x00\x00", b"x" * 40, b"y" * 17]
+    offs = np.zeros(len(strings) + 2, dtype=np.uint64)
+    offs[2:] = 1 + np.cumsum([len(s) for s in strings])
+    offs[1] = 1
+    data = np.frombuffer(b"Z" + b"".join(strings), dtype=np.uint8)
+    # key 0 is "Z"; data starts on an odd address inside the tensor for the rest
+    keys = (data, offs)
+    _check_build(rs, orc, keys, 2, 3)
+    d, o = rs.device_keys(keys)
+    sub = (d[1:], (o[1:] - 1).contiguous())  # misaligned data pointer
+    blob = rs.build(sub, 2, 3)
+    host = (data[1:].copy(), (offs[1:] - 1).astype(np.uint64))
+    assert blob.to_bytes() == orc.build(host, 2, 3)
+
+
+def test_blob_parity_l16_b2000(rs, orc):
+    """l=16, b=2000 on 3 buckets (the high-compression regime)."""
+    _check_build(rs, orc, inputs.u64_keys(6000, 4), 16, 2000)
+
+
+def test_lookup_non_members_match_oracle(rs, orc):
+    keys = inputs.u64_keys(50_000, 7)
+    blob, want = _check_build(rs, orc, keys, 8, 100, lookups=False)
+    other = inputs.u64_keys(200_000, 8)
+    got = rs.lookup(blob, rs.device_keys(other)).cpu().numpy().view(np.uint64)
+    assert np.array_equal(got, orc.lookup(want, other))
+    assert got.max() <= 50_000
+
+
+def test_roundtrip_from_bytes(rs, orc):
+    keys = inputs.u64_keys(30_000, 9)
+    want = orc.build(keys, 8, 100)
+    blob = rs.from_bytes(want)
+    assert blob.to_bytes() == want
+    ranks = rs.lookup(blob, rs.device_keys(keys)).cpu().numpy().view(np.uint64)
+    assert np.array_equal(ranks, orc.lookup(want, keys))
+
+
+def test_errors(rs, orc):
+    import torch
+
+    keys = inputs.u64_keys(1000, 3)
+    dup = np.concatenate([keys, keys[5:6]])
+    print("case duplicate key l=8", flush=True)
+    with pytest.raises(rs.RecSplitError) as e:
+        rs.build(rs.device_keys(dup), 8, 100)
+    assert e.value.code == rs.RS_EDUPLICATE
+    dup1 = np.concatenate([keys[:40], keys[:1]])
+    print("case duplicate key l=1", flush=True)
+    with pytest.raises(rs.RecSplitError) as e:
+        rs.build(rs.device_keys(dup1), 1, 100)
+    assert e.value.code == rs.RS_EDUPLICATE
+    print("case seed cap", flush=True)
+    with pytest.raises(rs.RecSplitError) as e:
+        rs.build(rs.device_keys(keys[:12]), 12, 100, seed_cap=3)
+    assert e.value.code == rs.RS_ESEARCH
+    with pytest.raises(rs.RecSplitError) as e:
+        rs.build(rs.device_keys(keys), 0, 100)
+    assert e.value.code == rs.RS_EINVAL
+    d = torch.zeros(10, dtype=torch.uint8, device="cuda")
+    o = torch.tensor([0, 5, 3, 10], dtype=torch.int64, device="cuda")
+    with pytest.raises(rs.RecSplitError) as e:
+        rs.build((d, o), 8, 100)
+    assert e.value.code == rs.RS_EINVAL
+    blob = rs.build(rs.device_keys(keys), 8, 100)
+    with pytest.raises(rs.RecSplitError):
+        rs.lookup(blob, (d, o))
+    # the library still works after the errors
+    assert blob.to_bytes() == orc.build(keys, 8, 100)
