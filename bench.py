@@ -27,10 +27,12 @@ if ROOT not in sys.path:
 # trials 1/p of eq. (2) with m evaluations each, node census from the strategy
 # averaged over Poisson(b) bucket sizes).
 EVALS_PER_KEY = {(8, 100): 494.0, (12, 1000): 1.39e4, (16, 2000): 8.90e5}
-# Full-rate VALU lane-operation slots of one hash evaluation in the search
-# kernel's inner loop (instruction count of the compiled loop weighted by the
-# measured issue cost of each instruction on gfx950).
-VALU_SLOTS_PER_EVAL = float(os.environ.get("RS_VALU_SLOTS_PER_EVAL", "0")) or None
+# VALU instructions of one hash evaluation in the cheapest form the search
+# kernel executes (the unrolled bijection loop: signature + stream offset,
+# two xor-shift/multiply rounds keeping the upper word, range reduction and
+# the bitmask update).  Every one of these issues at full rate on gfx950
+# (measured), so this is also the number of full-rate VALU slots.
+VALU_SLOTS_PER_EVAL = 18.0
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz full-rate 32-bit VALU lane-ops.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
@@ -73,7 +75,19 @@ def main():
     ap.add_argument("--l16-n", type=int, default=10_000_000, help="keys of the l=16, b=2000 build (0: skip)")
     ap.add_argument("--latency-builds", type=int, default=30, help="repeated 100,000-key builds for p50/p99")
     ap.add_argument("--cpu-sample", type=int, default=1_000_000, help="oracle sample size (0: skip)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (scales HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+
+        src = torch.ones(1 << 27, dtype=torch.int64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_each_way": src.numel() * 8, "copies": 3}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the construction of one "
               "structure runs on one device; see the design notes for how it would shard)", file=sys.stderr)
