@@ -61,16 +61,23 @@ typedef struct {
 typedef struct rs_blob rs_blob; /* opaque; immutable after build; safe for concurrent lookups */
 
 /* Build options (all-zero = defaults).
- *   seed_cap: lowers the search cap of every split and bijection index
- *             (0 = 2^56); it exists to exercise the RS_ESEARCH path.
- *   flags   : RS_OPT_TIMING records HIP events around each construction phase
- *             on the build stream (read them with rs_last_build_stats); the
- *             build then waits for the stream before returning. */
+ *   seed_cap  : lowers the search cap of every split and bijection index
+ *               (0 = 2^56); it exists to exercise the RS_ESEARCH path.
+ *   flags     : RS_OPT_TIMING records HIP events around each construction phase
+ *               on the build stream (read them with rs_last_build_stats); the
+ *               build then waits for the stream before returning.
+ *   stage_from: schedule override: leaves of at least this many keys use the
+ *               staged (early-exit) bijection search (0 = default 9; 25 = never).
+ *   group_max : schedule override: 1 + the largest log2 of lanes sharing one split
+ *               candidate (0 = default, 1 = one lane per candidate, 7 = up to 64).
+ * Schedules never change the result, only the time it takes. */
 enum { RS_OPT_TIMING = 1 };
 typedef struct {
     uint64_t seed_cap;
     uint32_t flags;
-    uint32_t reserved[5];
+    uint32_t stage_from;
+    uint32_t group_max;
+    uint32_t reserved[3];
 } rs_options;
 
 /* Per-phase device times (milliseconds, from HIP events on the build stream)

@@ -195,9 +195,9 @@ __global__ void k_scatter(const uint64_t* __restrict__ lo, const uint32_t* __res
 
 // ---------------------------------------------------------------------------
 // Seed search (Sec. 4, 5): one 64-lane wavefront per bucket walks the bucket's
-// splitting tree in preorder; at each node lane i tests candidate index
-// base + i, and the lowest successful lane of the first successful group of
-// 64 is the first index that works.
+// splitting tree in preorder.  Every node's index is the FIRST index that
+// works; lanes test candidates in increasing order and the lowest successful
+// candidate of the first group that contains one is returned.
 // ---------------------------------------------------------------------------
 struct SearchArgs {
     const uint64_t* sorted;
@@ -206,9 +206,12 @@ struct SearchArgs {
     uint64_t* seeds;
     uint64_t* blen;
     const uint32_t* R;
+    const uint32_t* G;  // log2 of the lanes that share one candidate, per split size
     DevStatus* status;
     uint64_t seed_cap;
     uint32_t leaf, lower, upper;
+    uint32_t stage_from;  // leaves of at least this many keys use the staged bijection search
+    uint32_t group_max;   // cap on log2 lanes per split candidate
 };
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63; }
@@ -227,26 +230,137 @@ __device__ __forceinline__ uint64_t uniform64(uint64_t x) {
     return ((uint64_t)hi << 32) | lo;
 }
 
-// Bijection search on a leaf of M keys (Sec. 4): the first v such that
-// x -> phi^M_{d,v}(x) is injective on the leaf.
+__device__ __forceinline__ uint64_t lane_value(uint64_t x, uint32_t lane) {
+    uint32_t lo = __builtin_amdgcn_readlane((uint32_t)x, lane);
+    uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(x >> 32), lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Orders this wavefront's LDS accesses (the queues are private to one wave).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ---- bijections --------------------------------------------------------------
+// A trial fails at its first collision, so candidates are filtered in up to
+// three stages: every new candidate is tried on the first C1 keys; survivors
+// (about a third to a half) wait in an LDS queue in candidate order and are
+// tried in groups of 64 on keys C1..C2-1; their survivors wait in a second
+// queue and are finished on keys C2..M-1.  Queues are first-in first-out and
+// candidates enter them in increasing order, so the first success found in the
+// last stage is the first index that works.  Cut points minimise the expected
+// VALU work (M^M/M! trials plus half the candidates needed to fill one group
+// of the last stage) x sum_stages P(stage reached) * keys(stage), with P the
+// collision-free probabilities prod (1 - i/M); 1 or 2 stages where filling the
+// groups costs more than it saves.
+constexpr int kQ = 128;  // ring capacity (at most 64 + 63 entries wait)
+struct LeafQueues {
+    uint64_t seed[2][kQ];
+    uint32_t mask[2][kQ];
+};
+__device__ constexpr int kCut1[25] = {0, 1, 2, 3, 4, 5, 6, 3, 4, 4, 4, 4, 5, 5, 5, 5, 6, 6, 6, 6, 6, 7, 7, 7, 7};
+__device__ constexpr int kCut2[25] = {0, 1, 2, 3, 4, 5, 6, 7, 8, 5, 6, 6, 7, 8, 8, 8, 9, 10, 10, 10, 10, 11, 11, 12, 12};
+
+template <int M, int LO, int HI>
+__device__ __forceinline__ uint32_t leaf_bits(const uint64_t (&k)[M], uint64_t S, uint32_t mask) {
+#pragma unroll
+    for (int i = LO; i < HI; i++) mask |= 1u << __umulhi(mix64_hi32(k[i] + S), (uint32_t)M);
+    return mask;
+}
+
 template <int M>
-__device__ uint64_t leaf_search(const uint64_t* keys, uint32_t depth, uint64_t cap, DevStatus* st) {
+__device__ uint64_t leaf_search(const uint64_t* keys, uint32_t depth, uint64_t cap, DevStatus* st, LeafQueues* q,
+                                bool staged) {
+    constexpr int C1 = kCut1[M], C2 = kCut2[M];
+    constexpr uint32_t full = (1u << M) - 1u;
     uint64_t k[M];
 #pragma unroll
     for (int i = 0; i < M; i++) k[i] = uniform64(keys[i]);
-    constexpr uint32_t full = (1u << M) - 1u;
+    const uint32_t lane = lane_id();
+    const uint64_t D = (uint64_t)depth << 56;
     const uint64_t step = 64ull * kGamma;
-    uint64_t S = stream_offset(depth, lane_id());
-    for (uint64_t base = 0; base < cap; base += 64) {
-        uint32_t mask = 0;
-#pragma unroll
-        for (int i = 0; i < M; i++) mask |= 1u << __umulhi(mix64_hi32(k[i] + S), (uint32_t)M);
-        bool ok = mask == full && base + lane_id() < cap;
-        uint64_t bal = __ballot(ok);
-        if (bal) return base + (uint64_t)__builtin_ctzll(bal);
-        S += step;
+    uint64_t S = (D + lane) * kGamma;
+    if (C1 == M || !staged) {
+        for (uint64_t base = 0; base < cap; base += 64, S += step) {
+            uint32_t mask = leaf_bits<M, 0, M>(k, S, 0);
+            uint64_t bal = __ballot(mask == full && base + lane < cap);
+            if (bal) return base + (uint64_t)__builtin_ctzll(bal);
+        }
+    } else if constexpr (C1 < M) {
+        uint32_t a_head = 0, a_tail = 0, b_head = 0, b_tail = 0;
+        uint64_t found = kNoSeed;
+        // Stage 3: finish queued candidates on keys [C2, M); full groups only,
+        // unless flushing at the seed cap.
+        auto drain_b = [&](bool flush) {
+            while (b_tail - b_head >= 64 || (flush && b_tail != b_head)) {
+                const uint32_t cb = min(64u, b_tail - b_head);
+                const bool ab = lane < cb;
+                const uint32_t pb = (b_head + lane) & (kQ - 1);
+                uint64_t w = ab ? q->seed[1][pb] : 0;
+                uint32_t m3 = ab ? q->mask[1][pb] : 0;
+                b_head += cb;
+                m3 = leaf_bits<M, C2, M>(k, (D + w) * kGamma, m3);
+                uint64_t b3 = __ballot(ab && m3 == full);
+                wave_lds_sync();
+                if (b3) {
+                    found = lane_value(w, (uint32_t)__builtin_ctzll(b3));
+                    return;
+                }
+            }
+        };
+        for (uint64_t base = 0; base < cap; base += 64, S += step) {
+            const bool last = base + 64 >= cap;
+            // stage 1: 64 new candidates on keys [0, C1)
+            uint32_t m1 = leaf_bits<M, 0, C1>(k, S, 0);
+            bool s1 = __popc(m1) == C1 && base + lane < cap;
+            uint64_t b1 = __ballot(s1);
+            if (s1) {
+                uint32_t p = (a_tail + lanes_below(b1)) & (kQ - 1);
+                q->seed[0][p] = base + lane;
+                q->mask[0][p] = m1;
+            }
+            a_tail += (uint32_t)__popcll(b1);
+            wave_lds_sync();
+            // stage 2: groups of (up to) 64 queued candidates on keys [C1, C2)
+            while (a_tail - a_head >= 64 || (last && a_tail != a_head)) {
+                const uint32_t cnt = min(64u, a_tail - a_head);
+                const bool act = lane < cnt;
+                const uint32_t pa = (a_head + lane) & (kQ - 1);
+                uint64_t v = act ? q->seed[0][pa] : 0;
+                uint32_t m2 = act ? q->mask[0][pa] : 0;
+                a_head += cnt;
+                m2 = leaf_bits<M, C1, C2>(k, (D + v) * kGamma, m2);
+                if constexpr (C2 == M) {
+                    uint64_t b2 = __ballot(act && m2 == full);
+                    if (b2) return lane_value(v, (uint32_t)__builtin_ctzll(b2));
+                } else {
+                    bool s2 = act && __popc(m2) == C2;
+                    uint64_t b2 = __ballot(s2);
+                    wave_lds_sync();
+                    if (s2) {
+                        uint32_t p = (b_tail + lanes_below(b2)) & (kQ - 1);
+                        q->seed[1][p] = v;
+                        q->mask[1][p] = m2;
+                    }
+                    b_tail += (uint32_t)__popcll(b2);
+                    wave_lds_sync();
+                    drain_b(false);
+                    if (found != kNoSeed) return found;
+                }
+                wave_lds_sync();
+            }
+            if constexpr (C2 != M) {
+                if (last) {  // every older candidate has left stage 2: flush stage 3
+                    drain_b(true);
+                    if (found != kNoSeed) return found;
+                }
+            }
+            if (last) break;
+        }
     }
-    if (lane_id() == 0) atomicOr(&st->flags, kFlagSearch);
+    if (lane == 0) atomicOr(&st->flags, kFlagSearch);
     return kNoSeed;
 }
 
@@ -259,8 +373,9 @@ __device__ bool has_duplicate(const uint64_t* keys, uint32_t m) {
     return __ballot(dup) != 0;
 }
 
-__device__ uint64_t leaf_dispatch(const uint64_t* keys, uint32_t m, uint32_t depth, uint64_t cap,
-                                  DevStatus* st) {
+template <int MAXL>
+__device__ uint64_t leaf_dispatch(const uint64_t* keys, uint32_t m, uint32_t depth, uint64_t cap, DevStatus* st,
+                                  LeafQueues* q, uint32_t stage_from) {
     // Equal lower words never separate, so they always meet in one leaf, or in a
     // split whose parts are all single keys: those nodes check every pair first.
     if (has_duplicate(keys, m)) {
@@ -268,9 +383,10 @@ __device__ uint64_t leaf_dispatch(const uint64_t* keys, uint32_t m, uint32_t dep
         return kNoSeed;
     }
     switch (m) {
-#define RS_LEAF_CASE(M) \
-    case M:             \
-        return leaf_search<M>(keys, depth, cap, st);
+#define RS_LEAF_CASE(M)                                                                    \
+    case M:                                                                                \
+        if constexpr (M <= MAXL) return leaf_search<M>(keys, depth, cap, st, q, M >= stage_from); \
+        return kNoSeed;
         RS_LEAF_CASE(2) RS_LEAF_CASE(3) RS_LEAF_CASE(4) RS_LEAF_CASE(5) RS_LEAF_CASE(6) RS_LEAF_CASE(7)
         RS_LEAF_CASE(8) RS_LEAF_CASE(9) RS_LEAF_CASE(10) RS_LEAF_CASE(11) RS_LEAF_CASE(12) RS_LEAF_CASE(13)
         RS_LEAF_CASE(14) RS_LEAF_CASE(15) RS_LEAF_CASE(16) RS_LEAF_CASE(17) RS_LEAF_CASE(18) RS_LEAF_CASE(19)
@@ -281,53 +397,113 @@ __device__ uint64_t leaf_dispatch(const uint64_t* keys, uint32_t m, uint32_t dep
     }
 }
 
-// Split search (Sec. 4): the first v such that, for t = 1..NT, exactly t*unit
-// keys hash below the part boundary t*unit.  phi >= t*unit holds exactly when
-// the upper 32 hash bits are >= T[t-1] = ceil(t*unit*2^32/m), so the counting
-// compares the raw hash against NT thresholds.
-template <int NT>
-__device__ uint64_t split_search(const uint64_t* keys, uint32_t m, uint32_t depth, const uint32_t* T,
-                                 uint32_t unit, uint64_t cap, DevStatus* st) {
+// ---- splits -----------------------------------------------------------------
+// The first v such that the parts receive exactly (u, ..., u, last) keys.
+// 2^g lanes share one candidate (each takes every 2^g-th key) and reduce their
+// counts with cross-lane shuffles, so 64 >> g candidates are tried per step:
+// few lanes per candidate for nodes that need many trials, many for nodes that
+// need few (less overshoot past the first success).  Counting:
+//   thresholds: phi >= t*u exactly when the upper hash word is >= T_t =
+//               ceil(t*u*2^32/m); one counter per boundary (fanout <= 4).
+//   packed:     j = floor(phi/u) by a reciprocal multiply, and 1 << (j*w) is
+//               added to one 64-bit word of w-bit fields (fanout >= 5 when
+//               fanout * w <= 64).
+constexpr uint32_t kMaxThresholds = 8;  // fanout <= max(s, t) = 9 for l <= 24
+
+struct SplitCtl {
+    uint32_t m, unit, fanout, last;
+    uint32_t g;      // log2 lanes per candidate
+    uint32_t w;      // packed field width (bits)
+    uint32_t recip;  // ceil(2^32 / unit)
+    uint64_t want;   // packed target
+};
+
+template <int NT, bool PACKED>
+__device__ uint64_t split_search(const uint64_t* keys, uint32_t depth, const SplitCtl& c, const uint32_t* T,
+                                 uint64_t cap, DevStatus* st) {
     uint32_t thr[NT];
 #pragma unroll
     for (int t = 0; t < NT; t++) thr[t] = T[t];
-    const uint64_t step = 64ull * kGamma;
-    uint64_t S = stream_offset(depth, lane_id());
-    for (uint64_t base = 0; base < cap; base += 64) {
-        uint32_t c[NT];
+    const uint32_t lane = lane_id();
+    const uint32_t G = 1u << c.g, gl = lane & (G - 1), gi = lane >> c.g, per_step = 64u >> c.g;
+    const uint32_t m = c.m;
+    const uint64_t step = (uint64_t)per_step * kGamma;
+    uint64_t S = (((uint64_t)depth << 56) + gi) * kGamma;
+    for (uint64_t base = 0; base < cap; base += per_step, S += step) {
+        uint32_t cnt[NT];
+        uint64_t packed = 0;
 #pragma unroll
-        for (int t = 0; t < NT; t++) c[t] = 0;
-        uint32_t i = 0;
-        for (; i + 4 <= m; i += 4) {
-            uint32_t h0 = mix64_hi32(keys[i] + S), h1 = mix64_hi32(keys[i + 1] + S);
-            uint32_t h2 = mix64_hi32(keys[i + 2] + S), h3 = mix64_hi32(keys[i + 3] + S);
+        for (int t = 0; t < NT; t++) cnt[t] = 0;
+        uint32_t i = gl;
+        for (; i + 3 * G < m; i += 4 * G) {
+            uint32_t h[4];
 #pragma unroll
-            for (int t = 0; t < NT; t++)
-                c[t] += (uint32_t)(h0 < thr[t]) + (uint32_t)(h1 < thr[t]) + (uint32_t)(h2 < thr[t]) +
-                        (uint32_t)(h3 < thr[t]);
+            for (int u = 0; u < 4; u++) h[u] = mix64_hi32(keys[i + u * G] + S);
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                if constexpr (PACKED) {
+                    uint32_t j = __umulhi(__umulhi(h[u], m), c.recip);
+                    packed += 1ull << (j * c.w);
+                } else {
+#pragma unroll
+                    for (int t = 0; t < NT; t++) cnt[t] += (uint32_t)(h[u] < thr[t]);
+                }
+            }
         }
-        for (; i < m; i++) {
+        for (; i < m; i += G) {
             uint32_t h = mix64_hi32(keys[i] + S);
+            if constexpr (PACKED) {
+                uint32_t j = __umulhi(__umulhi(h, m), c.recip);
+                packed += 1ull << (j * c.w);
+            } else {
 #pragma unroll
-            for (int t = 0; t < NT; t++) c[t] += (uint32_t)(h < thr[t]);
+                for (int t = 0; t < NT; t++) cnt[t] += (uint32_t)(h < thr[t]);
+            }
         }
-        bool ok = base + lane_id() < cap;
+        for (uint32_t o = 1; o < G; o <<= 1) {
+            if constexpr (PACKED) {
+                packed += (uint64_t)__shfl_xor((unsigned long long)packed, (int)o, 64);
+            } else {
 #pragma unroll
-        for (int t = 0; t < NT; t++) ok &= c[t] == (uint32_t)(t + 1) * unit;
+                for (int t = 0; t < NT; t++) cnt[t] += (uint32_t)__shfl_xor((int)cnt[t], (int)o, 64);
+            }
+        }
+        bool ok = gl == 0 && base + gi < cap;
+        if constexpr (PACKED) {
+            ok &= packed == c.want;
+        } else {
+#pragma unroll
+            for (int t = 0; t < NT; t++) ok &= cnt[t] == (uint32_t)(t + 1) * c.unit;
+        }
         uint64_t bal = __ballot(ok);
-        if (bal) return base + (uint64_t)__builtin_ctzll(bal);
-        S += step;
+        if (bal) return base + (uint64_t)(__builtin_ctzll(bal) >> c.g);
     }
-    if (lane_id() == 0) atomicOr(&st->flags, kFlagSearch);
+    if (lane == 0) atomicOr(&st->flags, kFlagSearch);
     return kNoSeed;
 }
 
-__device__ uint64_t split_dispatch(const uint64_t* keys, uint32_t m, uint32_t depth, const uint32_t* T,
-                                   uint32_t nt, uint32_t unit, uint64_t cap, DevStatus* st) {
+template <int MAXNT>
+__device__ uint64_t split_dispatch(const uint64_t* keys, uint32_t depth, const SplitCtl& c, const uint32_t* T,
+                                   bool packed, uint64_t cap, DevStatus* st) {
+    const uint32_t nt = c.fanout - 1;
+    if constexpr (MAXNT >= 4) {
+        if (packed) {
+            switch (nt) {
+                case 4: return split_search<4, true>(keys, depth, c, T, cap, st);
+                case 5: if constexpr (MAXNT >= 5) return split_search<5, true>(keys, depth, c, T, cap, st); break;
+                case 6: if constexpr (MAXNT >= 6) return split_search<6, true>(keys, depth, c, T, cap, st); break;
+                case 7: if constexpr (MAXNT >= 7) return split_search<7, true>(keys, depth, c, T, cap, st); break;
+                case 8: if constexpr (MAXNT >= 8) return split_search<8, true>(keys, depth, c, T, cap, st); break;
+                default: break;
+            }
+            return kNoSeed;
+        }
+    }
     switch (nt) {
-#define RS_SPLIT_CASE(NT) \
-    case NT:              \
-        return split_search<NT>(keys, m, depth, T, unit, cap, st);
+#define RS_SPLIT_CASE(NT)                                                                 \
+    case NT:                                                                              \
+        if constexpr (NT <= MAXNT) return split_search<NT, false>(keys, depth, c, T, cap, st); \
+        return kNoSeed;
         RS_SPLIT_CASE(1) RS_SPLIT_CASE(2) RS_SPLIT_CASE(3) RS_SPLIT_CASE(4) RS_SPLIT_CASE(5) RS_SPLIT_CASE(6)
         RS_SPLIT_CASE(7) RS_SPLIT_CASE(8)
 #undef RS_SPLIT_CASE
@@ -336,7 +512,13 @@ __device__ uint64_t split_dispatch(const uint64_t* keys, uint32_t m, uint32_t de
     }
 }
 
-constexpr uint32_t kMaxThresholds = 8;  // fanout <= max(s, t) = 9 for l <= 24
+// Largest fanout - 1 of any node for leaf sizes up to MAXL (max(s, t) - 1).
+__host__ __device__ constexpr int max_thresholds(int maxl) {
+    int sv = (35 * maxl + 149) / 100;
+    sv = sv < 2 ? 2 : sv;
+    int tv = maxl < 7 ? 2 : (21 * maxl + 189) / 100;
+    return (sv > tv ? sv : tv) - 1;
+}
 
 // Reorder the node's keys so that child j occupies [j*unit, ...): keys go to
 // global scratch at their final place and are copied back.
@@ -370,10 +552,12 @@ __device__ void partition(uint64_t* keys, uint32_t m, uint32_t depth, uint64_t v
     __syncthreads();
 }
 
+template <int MAXL>
 __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
     extern __shared__ uint64_t lds_keys[];
     __shared__ uint32_t stk_off[kStackDepth], stk_m[kStackDepth], stk_d[kStackDepth];
     __shared__ uint32_t thr_s[kMaxThresholds];
+    __shared__ LeafQueues queues;
     const uint64_t b = blockIdx.x;
     const uint32_t lane = lane_id();
     const uint64_t start = a.bstart[b];
@@ -393,7 +577,7 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
         if (m <= 1) continue;
         uint64_t v;
         if (m <= a.leaf) {
-            v = leaf_dispatch(lds_keys + off, m, d, a.seed_cap, a.status);
+            v = leaf_dispatch<MAXL>(lds_keys + off, m, d, a.seed_cap, a.status, &queues, a.stage_from);
             if (v == kNoSeed) break;
         } else {
             SplitShape sh = split_shape(m, a.leaf, a.lower, a.upper);
@@ -404,7 +588,20 @@ __global__ __launch_bounds__(64) void k_search(SearchArgs a) {
             const uint32_t nt = sh.fanout - 1;
             if (lane < nt) thr_s[lane] = (uint32_t)((((uint64_t)(lane + 1) * sh.unit << 32) + m - 1) / m);
             __syncthreads();
-            v = split_dispatch(lds_keys + off, m, d, thr_s, nt, sh.unit, a.seed_cap, a.status);
+            SplitCtl c;
+            c.m = m;
+            c.unit = sh.unit;
+            c.fanout = sh.fanout;
+            c.last = sh.last;
+            c.g = min(a.G[m], a.group_max);
+            c.w = 32 - __clz(m);
+            const bool packed = nt >= 4 && sh.fanout * c.w <= 64;
+            c.recip = packed ? (uint32_t)(((1ull << 32) + sh.unit - 1) / sh.unit) : 0;
+            c.want = 0;
+            if (packed)
+                for (uint32_t j = 0; j < sh.fanout; j++)
+                    c.want += (uint64_t)(j + 1 == sh.fanout ? sh.last : sh.unit) << (j * c.w);
+            v = split_dispatch<max_thresholds(MAXL)>(lds_keys + off, d, c, thr_s, packed, a.seed_cap, a.status);
             if (v == kNoSeed) break;  // counts do not match the parts: no partition
             partition(lds_keys + off, m, d, v, thr_s, nt, sh.unit, a.tmp + start + off);
             if (sp + (int)sh.fanout > kStackDepth) {
@@ -704,16 +901,24 @@ int build_impl(const rs_keys* keys, uint32_t leaf, uint32_t bucket, const rs_opt
     // per-size tables
     TableView tv = host_tables(leaf, maxm);
     if (!tv.data) return cleanup(fail(RS_ENOMEM, "table allocation failed"));
-    if ((rc = dev_alloc((void**)&d_tab, 3ull * (maxm + 1) * 4, s))) return cleanup(rc);
+    if ((rc = dev_alloc((void**)&d_tab, (size_t)kTableCount * (maxm + 1) * 4, s))) return cleanup(rc);
     RS_TRY(hipMemcpyAsync(d_tab, tv.r(), (maxm + 1) * 4ull, hipMemcpyHostToDevice, s));
     RS_TRY(hipMemcpyAsync(d_tab + (maxm + 1), tv.F(), (maxm + 1) * 4ull, hipMemcpyHostToDevice, s));
     RS_TRY(hipMemcpyAsync(d_tab + 2 * (maxm + 1), tv.N(), (maxm + 1) * 4ull, hipMemcpyHostToDevice, s));
+    RS_TRY(hipMemcpyAsync(d_tab + 3 * (maxm + 1), tv.G(), (maxm + 1) * 4ull, hipMemcpyHostToDevice, s));
 
     pe.record(1, s);
     k_scatter<<<grid_for(n, kBlock), kBlock, 0, s>>>(d_lo, d_bid, n, d_bst, d_cur, d_sorted);
-    SearchArgs sa{d_sorted, d_tmp, d_bst, d_seeds, d_blen, d_tab, d_st, cap, leaf, st.lower, st.upper};
+    const uint32_t stage_from = opts && opts->stage_from ? opts->stage_from : 9;
+    const uint32_t group_max = opts && opts->group_max ? opts->group_max - 1 : 6;
+    SearchArgs sa{d_sorted, d_tmp, d_bst, d_seeds, d_blen, d_tab, d_tab + 3 * (maxm + 1), d_st, cap, leaf,
+                  st.lower, st.upper, stage_from, group_max};
     pe.record(2, s);
-    k_search<<<(uint32_t)nb, 64, (size_t)maxm * 8, s>>>(sa);
+    const size_t lds = (size_t)maxm * 8;
+    if (leaf <= 8) k_search<8><<<(uint32_t)nb, 64, lds, s>>>(sa);
+    else if (leaf <= 12) k_search<12><<<(uint32_t)nb, 64, lds, s>>>(sa);
+    else if (leaf <= 16) k_search<16><<<(uint32_t)nb, 64, lds, s>>>(sa);
+    else k_search<24><<<(uint32_t)nb, 64, lds, s>>>(sa);
     pe.record(3, s);
     RS_TRY(hipGetLastError());
     if ((rc = scan<uint64_t>(d_blen, nb, d_ost, d_tiles, nullptr, s))) return cleanup(rc);

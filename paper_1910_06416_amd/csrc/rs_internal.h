@@ -75,16 +75,19 @@ __host__ __device__ inline SplitShape split_shape(uint32_t m, uint32_t leaf, uin
 }
 
 // Per-size tables for sizes 0..cap (cap >= the requested maxm), laid out as
-// r[cap+1], F[cap+1], N[cap+1]: Golomb-Rice parameter of a node, fixed bits of
-// a subtree, coded nodes of a subtree.  The host memory is pinned and stays
-// valid for the life of the process.
+// r[cap+1], F[cap+1], N[cap+1], G[cap+1]: Golomb-Rice parameter of a node,
+// fixed bits of a subtree, coded nodes of a subtree, and log2 of the lanes
+// that share one candidate in the split search of a node of that size.  The
+// host memory is pinned and stays valid for the life of the process.
 struct TableView {
     const uint32_t* data;
     uint32_t cap;
     const uint32_t* r() const { return data; }
     const uint32_t* F() const { return data + cap + 1; }
     const uint32_t* N() const { return data + 2 * (cap + 1); }
+    const uint32_t* G() const { return data + 3 * (cap + 1); }
 };
+constexpr int kTableCount = 4;
 TableView host_tables(uint32_t leaf, uint32_t maxm);
 
 // ---------------------------------------------------------------------------

@@ -50,13 +50,43 @@ struct LeafTables {
 std::mutex g_mu;
 std::map<uint32_t, LeafTables> g_cache;
 
-void fill(const Strategy& st, uint32_t cap, uint32_t* r, uint32_t* F, uint32_t* N) {
+// Lanes per candidate for the split search of a node of m keys: the 2^g
+// minimising expected VALU work = steps * (keys per lane * cost per key +
+// reduction), with steps = (expected trials + mean overshoot) / candidates
+// per step; cost per key follows the counting mode the kernel uses.
+uint32_t lanes_per_candidate(const Strategy& st, uint32_t m, double trials) {
+    SplitShape sh = split_shape(m, st.leaf, st.lower, st.upper);
+    const uint32_t nt = sh.fanout - 1;
+    uint32_t w = 0;
+    while ((1u << w) <= m) w++;
+    const bool packed = nt >= 4 && sh.fanout * w <= 64;
+    const double per_key = 18.0 + (packed ? 6.0 : 2.0 * nt);
+    const double per_reduce = packed ? 4.0 : 2.0 * nt;
+    double best = 0;
+    uint32_t best_g = 0;
+    for (uint32_t g = 0; g <= 6; g++) {
+        const double per_step = (double)(64u >> g);
+        const double steps = std::max(1.0, (trials + (per_step - 1.0) / 2.0) / per_step);
+        const double keys_per_lane = std::ceil((double)m / (double)(1u << g));
+        const double cost = steps * (keys_per_lane * per_key + g * per_reduce + 12.0);
+        if (g == 0 || cost < best) {
+            best = cost;
+            best_g = g;
+        }
+    }
+    return best_g;
+}
+
+void fill(const Strategy& st, uint32_t cap, uint32_t* r, uint32_t* F, uint32_t* N, uint32_t* G) {
     for (uint32_t m = 0; m <= cap; m++) {
+        G[m] = 0;
         if (m < 2) {
             r[m] = F[m] = N[m] = 0;
             continue;
         }
-        r[m] = rice_parameter(std::exp(log_success(st, m)));
+        const double lp = log_success(st, m);
+        r[m] = rice_parameter(std::exp(lp));
+        if (m > st.leaf) G[m] = lanes_per_candidate(st, m, std::exp(-lp));
         F[m] = r[m];
         N[m] = 1;
         if (m > st.leaf) {
@@ -75,14 +105,14 @@ TableView host_tables(uint32_t leaf, uint32_t maxm) {
     if (t.data == nullptr || t.cap < maxm) {
         uint32_t cap = std::max<uint32_t>(maxm, std::max<uint32_t>(1024u, t.cap * 2));
         uint32_t* buf = nullptr;
-        const size_t bytes = 3ull * (cap + 1) * sizeof(uint32_t);
+        const size_t bytes = (size_t)kTableCount * (cap + 1) * sizeof(uint32_t);
         // pinned when a device is present (asynchronous uploads), plain otherwise
         if (hipHostMalloc((void**)&buf, bytes, hipHostMallocDefault) != hipSuccess) {
             (void)hipGetLastError();
             buf = static_cast<uint32_t*>(std::malloc(bytes));
             if (!buf) return TableView{nullptr, 0};
         }
-        fill(make_strategy(leaf), cap, buf, buf + cap + 1, buf + 2 * (cap + 1));
+        fill(make_strategy(leaf), cap, buf, buf + cap + 1, buf + 2 * (cap + 1), buf + 3 * (cap + 1));
         t.cap = cap;
         t.data = buf;  // the previous buffer is intentionally kept alive
     }

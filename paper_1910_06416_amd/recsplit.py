@@ -38,7 +38,8 @@ class rs_keys(ctypes.Structure):
 
 
 class rs_options(ctypes.Structure):
-    _fields_ = [("seed_cap", ctypes.c_uint64), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 5)]
+    _fields_ = [("seed_cap", ctypes.c_uint64), ("flags", ctypes.c_uint32), ("stage_from", ctypes.c_uint32),
+                ("group_max", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 3)]
 
 
 RS_OPT_TIMING = 1
@@ -160,12 +161,14 @@ class Blob:
             pass
 
 
-def build(keys, leaf: int, bucket: int, seed_cap: int = 0, timing: bool = False, stream=None) -> Blob:
+def build(keys, leaf: int, bucket: int, seed_cap: int = 0, timing: bool = False, stage_from: int = 0,
+          group_max: int = 0, stream=None) -> Blob:
     """Build the minimal perfect hash function of a device key set.  With
-    timing=True the per-phase device times are available from last_build_stats()."""
+    timing=True the per-phase device times are available from last_build_stats().
+    stage_from / group_max override the search schedule (never the result)."""
     k = _as_keys(keys)
     h = ctypes.c_void_p()
-    opts = rs_options(seed_cap, RS_OPT_TIMING if timing else 0)
+    opts = rs_options(seed_cap, RS_OPT_TIMING if timing else 0, stage_from, group_max)
     _check(lib().rs_build_ex(ctypes.byref(k), leaf, bucket, ctypes.byref(opts), _stream(stream), ctypes.byref(h)))
     return Blob(h)
 

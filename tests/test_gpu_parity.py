@@ -137,3 +137,21 @@ def test_errors(rs, orc):
         rs.lookup(blob, (d, o))
     # the library still works after the errors
     assert blob.to_bytes() == orc.build(keys, 8, 100)
+
+
+@pytest.mark.parametrize("n,leaf", [(12, 12), (7, 7), (16, 16), (30, 8), (200, 5), (90, 16)])
+def test_seed_cap_boundary(rs, orc, n, leaf):
+    """Exactly at the largest stored index the build must fail; one above it,
+    succeed with the oracle's bytes (exercises the end-of-range flush of the
+    staged bijection search and the cap test of the split search)."""
+    keys = inputs.u64_keys(n, 50 + n + leaf)
+    _, lo = orc.fingerprint(keys)
+    v, _, _ = orc.tree(np.sort(lo), leaf)
+    vmax = int(v.max())
+    print(f"case cap boundary n={n} leaf={leaf} vmax={vmax}", flush=True)
+    want = orc.build(keys, leaf, 1000, seed_cap=vmax + 1)
+    assert rs.build(rs.device_keys(keys), leaf, 1000, seed_cap=vmax + 1).to_bytes() == want
+    if vmax > 0:
+        with pytest.raises(rs.RecSplitError) as e:
+            rs.build(rs.device_keys(keys), leaf, 1000, seed_cap=vmax)
+        assert e.value.code == rs.RS_ESEARCH

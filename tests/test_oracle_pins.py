@@ -400,3 +400,15 @@ def test_errors(orc):
     with pytest.raises(orc.OracleError) as e:
         orc.lookup(bytes(blob), keys)
     assert e.value.code == orc.EFORMAT
+
+
+def test_seed_cap_boundary_oracle(orc):
+    # a cap equal to the largest stored index fails; one more succeeds
+    keys = inputs.u64_keys(30, 88)
+    _, lo = orc.fingerprint(keys)
+    v, _, _ = orc.tree(np.sort(lo), 8)
+    vmax = int(v.max())
+    assert orc.build(keys, 8, 1000, seed_cap=vmax + 1) == orc.build(keys, 8, 1000)
+    with pytest.raises(orc.OracleError) as e:
+        orc.build(keys, 8, 1000, seed_cap=vmax)
+    assert e.value.code == orc.ESEARCH
