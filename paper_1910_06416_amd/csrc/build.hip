@@ -206,12 +206,14 @@ struct SearchArgs {
     uint64_t* seeds;
     uint64_t* blen;
     const uint32_t* R;
+    const uint32_t* N;  // coded nodes of a subtree, per size
     const uint32_t* G;  // log2 of the lanes that share one candidate, per split size
     DevStatus* status;
     uint64_t seed_cap;
     uint32_t leaf, lower, upper;
     uint32_t stage_from;  // leaves of at least this many keys use the staged bijection search
     uint32_t group_max;   // cap on log2 lanes per split candidate
+    uint32_t key_words;   // 64-bit words of dynamic LDS before the node slots (largest bucket)
 };
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63; }
@@ -520,8 +522,16 @@ __host__ __device__ constexpr int max_thresholds(int maxl) {
     return (sv > tv ? sv : tv) - 1;
 }
 
+// Workgroup-scope ordering of one wavefront's global and LDS accesses (used
+// where a wave hands data to its own lanes through memory).
+__device__ __forceinline__ void wave_mem_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 // Reorder the node's keys so that child j occupies [j*unit, ...): keys go to
-// global scratch at their final place and are copied back.
+// global scratch at their final place and are copied back (one wavefront).
 __device__ void partition(uint64_t* keys, uint32_t m, uint32_t depth, uint64_t v, const uint32_t* T, uint32_t nt,
                           uint32_t unit, uint64_t* gtmp) {
     const uint32_t lane = lane_id();
@@ -547,84 +557,167 @@ __device__ void partition(uint64_t* keys, uint32_t m, uint32_t depth, uint64_t v
         }
         if (act) gtmp[pos] = x;
     }
-    __syncthreads();
+    wave_mem_sync();
     for (uint32_t i = lane; i < m; i += 64) keys[i] = gtmp[i];
-    __syncthreads();
+    wave_mem_sync();
 }
 
-template <int MAXL>
-__global__ __launch_bounds__(64) void k_search(SearchArgs a) {
-    extern __shared__ uint64_t lds_keys[];
-    __shared__ uint32_t stk_off[kStackDepth], stk_m[kStackDepth], stk_d[kStackDepth];
-    __shared__ uint32_t thr_s[kMaxThresholds];
-    __shared__ LeafQueues queues;
+// One workgroup of WAVES wavefronts per bucket.  The bucket's keys sit in LDS.
+// Every coded node of the bucket's tree gets one slot of an LDS queue (the
+// number of coded nodes, N(m), is known from the strategy): wavefronts claim
+// slots in order with an atomic counter, wait until the slot has been
+// published, search the node's index, partition its keys if it is a split and
+// publish its children in later slots.  A parent's slot always precedes its
+// children's, so a claimed slot is always filled by a wavefront that is not
+// waiting, and the bucket is done when every slot has been claimed.  A node's
+// preorder position (where its index is stored) is its parent's position + 1
+// + the coded nodes of its earlier siblings, j * N(u).  Waits end early if
+// another wavefront abandons the bucket, and a bound on waiting turns a
+// scheduling error into a reported failure instead of a hang.
+struct NodeSlot {
+    uint32_t off, d, idx;
+    uint32_t m;  // published last (release); 0 = not yet filled
+};
+
+struct QueueState {
+    uint32_t head;  // next slot to claim
+    uint32_t tail;  // next slot to fill
+    uint32_t abort;
+    uint32_t pad;
+    unsigned long long bits;
+};
+
+constexpr uint32_t kWaitLimit = 1u << 27;  // ~30 s of s_sleep(4) per wait
+
+template <int MAXL, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_search(SearchArgs a) {
+    extern __shared__ uint64_t lds_dyn[];
+    __shared__ QueueState qs;
+    __shared__ uint32_t thr_s[WAVES][kMaxThresholds];
+    __shared__ LeafQueues queues[WAVES];
     const uint64_t b = blockIdx.x;
-    const uint32_t lane = lane_id();
+    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
     const uint64_t start = a.bstart[b];
     const uint32_t m0 = (uint32_t)(a.bstart[b + 1] - start);
-    for (uint32_t i = lane; i < m0; i += 64) lds_keys[i] = a.sorted[start + i];
-    if (lane == 0) {
-        stk_off[0] = 0;
-        stk_m[0] = m0;
-        stk_d[0] = 0;
+    uint64_t* lds_keys = lds_dyn;
+    NodeSlot* slots = reinterpret_cast<NodeSlot*>(lds_dyn + a.key_words);
+    const uint32_t total = a.N[m0];
+    for (uint32_t i = threadIdx.x; i < m0; i += 64 * WAVES) lds_keys[i] = a.sorted[start + i];
+    for (uint32_t i = threadIdx.x; i < total; i += 64 * WAVES) slots[i].m = 0;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        qs.head = 0;
+        qs.tail = total ? 1 : 0;
+        qs.abort = 0;
+        qs.bits = 0;
+        if (total) {
+            slots[0].off = 0;
+            slots[0].d = 0;
+            slots[0].idx = 0;
+            slots[0].m = m0;
+        }
     }
     __syncthreads();
-    int sp = 1;
-    uint64_t node = 0, bits = 0;
-    while (sp > 0) {
-        sp--;
-        const uint32_t off = stk_off[sp], m = stk_m[sp], d = stk_d[sp];
-        if (m <= 1) continue;
+    uint32_t* thr = thr_s[wave];
+    unsigned long long bits = 0;
+    for (;;) {
+        uint32_t h = 0, off = 0, m = 0, d = 0, idx = 0, stop = 0;
+        if (lane == 0) {
+            h = __hip_atomic_fetch_add(&qs.head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (h >= total) {
+                stop = 1;
+            } else {
+                uint32_t spins = 0;
+                for (;;) {
+                    m = __hip_atomic_load(&slots[h].m, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    if (m) break;
+                    if (__hip_atomic_load(&qs.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
+                        stop = 1;
+                        break;
+                    }
+                    if (++spins == kWaitLimit) {
+                        atomicOr(&a.status->flags, kFlagStack);
+                        __hip_atomic_store(&qs.abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        stop = 1;
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(4);
+                }
+                if (!stop) {
+                    off = slots[h].off;
+                    d = slots[h].d;
+                    idx = slots[h].idx;
+                }
+            }
+        }
+        if (__builtin_amdgcn_readfirstlane(stop)) break;
+        off = __builtin_amdgcn_readfirstlane(off);
+        m = __builtin_amdgcn_readfirstlane(m);
+        d = __builtin_amdgcn_readfirstlane(d);
+        idx = __builtin_amdgcn_readfirstlane(idx);
+        wave_mem_sync();
         uint64_t v;
+        bool fail;
+        SplitShape sh{};
         if (m <= a.leaf) {
-            v = leaf_dispatch<MAXL>(lds_keys + off, m, d, a.seed_cap, a.status, &queues, a.stage_from);
-            if (v == kNoSeed) break;
+            v = leaf_dispatch<MAXL>(lds_keys + off, m, d, a.seed_cap, a.status, &queues[wave], a.stage_from);
+            fail = v == kNoSeed;
         } else {
-            SplitShape sh = split_shape(m, a.leaf, a.lower, a.upper);
+            sh = split_shape(m, a.leaf, a.lower, a.upper);
             if (sh.unit == 1 && has_duplicate(lds_keys + off, m)) {  // l = 1: parts of one key each
                 if (lane == 0) atomicOr(&a.status->flags, kFlagDuplicate);
-                break;
+                v = kNoSeed;
+                fail = true;
+            } else {
+                const uint32_t nt = sh.fanout - 1;
+                if (lane < nt) thr[lane] = (uint32_t)((((uint64_t)(lane + 1) * sh.unit << 32) + m - 1) / m);
+                wave_lds_sync();
+                SplitCtl c;
+                c.m = m;
+                c.unit = sh.unit;
+                c.fanout = sh.fanout;
+                c.last = sh.last;
+                c.g = min(a.G[m], a.group_max);
+                c.w = 32 - __clz(m);
+                const bool packed = nt >= 4 && sh.fanout * c.w <= 64;
+                c.recip = packed ? (uint32_t)(((1ull << 32) + sh.unit - 1) / sh.unit) : 0;
+                c.want = 0;
+                if (packed)
+                    for (uint32_t j = 0; j < sh.fanout; j++)
+                        c.want += (uint64_t)(j + 1 == sh.fanout ? sh.last : sh.unit) << (j * c.w);
+                v = split_dispatch<max_thresholds(MAXL)>(lds_keys + off, d, c, thr, packed, a.seed_cap, a.status);
+                fail = v == kNoSeed;  // counts do not match the parts: no partition
+                if (!fail) partition(lds_keys + off, m, d, v, thr, nt, sh.unit, a.tmp + start + off);
             }
-            const uint32_t nt = sh.fanout - 1;
-            if (lane < nt) thr_s[lane] = (uint32_t)((((uint64_t)(lane + 1) * sh.unit << 32) + m - 1) / m);
-            __syncthreads();
-            SplitCtl c;
-            c.m = m;
-            c.unit = sh.unit;
-            c.fanout = sh.fanout;
-            c.last = sh.last;
-            c.g = min(a.G[m], a.group_max);
-            c.w = 32 - __clz(m);
-            const bool packed = nt >= 4 && sh.fanout * c.w <= 64;
-            c.recip = packed ? (uint32_t)(((1ull << 32) + sh.unit - 1) / sh.unit) : 0;
-            c.want = 0;
-            if (packed)
-                for (uint32_t j = 0; j < sh.fanout; j++)
-                    c.want += (uint64_t)(j + 1 == sh.fanout ? sh.last : sh.unit) << (j * c.w);
-            v = split_dispatch<max_thresholds(MAXL)>(lds_keys + off, d, c, thr_s, packed, a.seed_cap, a.status);
-            if (v == kNoSeed) break;  // counts do not match the parts: no partition
-            partition(lds_keys + off, m, d, v, thr_s, nt, sh.unit, a.tmp + start + off);
-            if (sp + (int)sh.fanout > kStackDepth) {
-                if (lane == 0) atomicOr(&a.status->flags, kFlagStack);
-                break;
-            }
-            __syncthreads();
-            for (int j = (int)sh.fanout - 1; j >= 0; j--) {
-                if (lane == 0) {
-                    stk_off[sp] = off + (uint32_t)j * sh.unit;
-                    stk_m[sp] = (uint32_t)j + 1 == sh.fanout ? sh.last : sh.unit;
-                    stk_d[sp] = d + 1;
-                }
-                sp++;
-            }
-            __syncthreads();
         }
-        if (lane == 0) a.seeds[start + node] = v;
-        node++;
-        uint32_t r = a.R[m];
+        if (fail) {
+            if (lane == 0) __hip_atomic_store(&qs.abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            break;
+        }
+        if (lane == 0) a.seeds[start + idx] = v;
+        const uint32_t r = a.R[m];
         bits += r + (v >> r) + 1;
+        if (m > a.leaf && lane == 0) {
+            for (uint32_t j = 0; j < sh.fanout; j++) {
+                const uint32_t cm = j + 1 == sh.fanout ? sh.last : sh.unit;
+                if (cm < 2) continue;
+                const uint32_t t =
+                    __hip_atomic_fetch_add(&qs.tail, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (t >= total) {  // more children than coded nodes: tables and strategy disagree
+                    atomicOr(&a.status->flags, kFlagStack);
+                    __hip_atomic_store(&qs.abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    break;
+                }
+                slots[t].off = off + j * sh.unit;
+                slots[t].d = d + 1;
+                slots[t].idx = idx + 1 + j * a.N[sh.unit];
+                __hip_atomic_store(&slots[t].m, cm, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        }
     }
-    if (lane == 0) a.blen[b] = bits;
+    if (lane == 0) atomicAdd(&qs.bits, bits);
+    __syncthreads();
+    if (threadIdx.x == 0) a.blen[b] = qs.bits;
 }
 
 // ---------------------------------------------------------------------------
@@ -895,12 +988,12 @@ int build_impl(const rs_keys* keys, uint32_t leaf, uint32_t bucket, const rs_opt
     RS_TRY(hipStreamSynchronize(s));
     if (pin->st.flags & kFlagOffsets) return cleanup(fail(RS_EINVAL, "byte-key offsets are not monotone"));
     const uint32_t maxm = pin->st.maxm;
-    if ((uint64_t)maxm * 8 > (uint64_t)max_lds_bytes() - 2048)
-        return cleanup(fail(RS_EINVAL, "largest bucket (%u keys) exceeds the local data share", maxm));
-
     // per-size tables
     TableView tv = host_tables(leaf, maxm);
     if (!tv.data) return cleanup(fail(RS_ENOMEM, "table allocation failed"));
+    // keys + node slots in dynamic LDS; the static part (queues, thresholds) is below 16 KiB
+    if ((uint64_t)maxm * 8 + (uint64_t)tv.N()[maxm] * 16 + 16384 > (uint64_t)max_lds_bytes())
+        return cleanup(fail(RS_EINVAL, "largest bucket (%u keys) exceeds the local data share", maxm));
     if ((rc = dev_alloc((void**)&d_tab, (size_t)kTableCount * (maxm + 1) * 4, s))) return cleanup(rc);
     RS_TRY(hipMemcpyAsync(d_tab, tv.r(), (maxm + 1) * 4ull, hipMemcpyHostToDevice, s));
     RS_TRY(hipMemcpyAsync(d_tab + (maxm + 1), tv.F(), (maxm + 1) * 4ull, hipMemcpyHostToDevice, s));
@@ -911,14 +1004,14 @@ int build_impl(const rs_keys* keys, uint32_t leaf, uint32_t bucket, const rs_opt
     k_scatter<<<grid_for(n, kBlock), kBlock, 0, s>>>(d_lo, d_bid, n, d_bst, d_cur, d_sorted);
     const uint32_t stage_from = opts && opts->stage_from ? opts->stage_from : 9;
     const uint32_t group_max = opts && opts->group_max ? opts->group_max - 1 : 6;
-    SearchArgs sa{d_sorted, d_tmp, d_bst, d_seeds, d_blen, d_tab, d_tab + 3 * (maxm + 1), d_st, cap, leaf,
-                  st.lower, st.upper, stage_from, group_max};
+    SearchArgs sa{d_sorted, d_tmp, d_bst, d_seeds, d_blen, d_tab, d_tab + 2 * (maxm + 1), d_tab + 3 * (maxm + 1),
+                  d_st, cap, leaf, st.lower, st.upper, stage_from, group_max, maxm};
     pe.record(2, s);
-    const size_t lds = (size_t)maxm * 8;
-    if (leaf <= 8) k_search<8><<<(uint32_t)nb, 64, lds, s>>>(sa);
-    else if (leaf <= 12) k_search<12><<<(uint32_t)nb, 64, lds, s>>>(sa);
-    else if (leaf <= 16) k_search<16><<<(uint32_t)nb, 64, lds, s>>>(sa);
-    else k_search<24><<<(uint32_t)nb, 64, lds, s>>>(sa);
+    const size_t lds = (size_t)maxm * 8 + (size_t)tv.N()[maxm] * 16;
+    if (leaf <= 8) k_search<8, 1><<<(uint32_t)nb, 64, lds, s>>>(sa);
+    else if (leaf <= 12) k_search<12, 4><<<(uint32_t)nb, 256, lds, s>>>(sa);
+    else if (leaf <= 16) k_search<16, 4><<<(uint32_t)nb, 256, lds, s>>>(sa);
+    else k_search<24, 4><<<(uint32_t)nb, 256, lds, s>>>(sa);
     pe.record(3, s);
     RS_TRY(hipGetLastError());
     if ((rc = scan<uint64_t>(d_blen, nb, d_ost, d_tiles, nullptr, s))) return cleanup(rc);
