@@ -111,6 +111,20 @@ int rs_build(const rs_keys* keys, uint32_t leaf, uint32_t bucket, void* stream, 
 int rs_build_ex(const rs_keys* keys, uint32_t leaf, uint32_t bucket, const rs_options* opts, void* stream,
                 rs_blob** out);
 
+/* Build many independent MPHFs in one call (buckets of all builds are independent,
+ * Sec. 4): one signature pass, one persistent search launch over the buckets of
+ * every build, one encoding pass; each blob is byte-identical to the one rs_build
+ * makes for the same keys, l and b.
+ *   sets[count]            : device key sets (kinds may differ between builds).
+ *   leaf[count], bucket[count]: per-build l and b.
+ *   outs[count]            : receives one blob per successful build, NULL otherwise.
+ *   per_build_status[count]: optional; an rs_status per build.
+ * Returns RS_OK if every build succeeded, else the status of the first failed build
+ * (the other builds' blobs are still returned).  The blobs of one call share one
+ * device allocation, released when the last of them is freed. */
+int rs_build_batch(const rs_keys* sets, uint32_t count, const uint32_t* leaf, const uint32_t* bucket,
+                   const rs_options* opts, void* stream, rs_blob** outs, int* per_build_status);
+
 /* Rank of each query (lookup of Sec. 4 and Sec. 6.2): ranks_dev[i] = f(queries[i]).
  * Members of the built set get distinct values in [0, n).  Other keys get a
  * deterministic value in [0, n] (n only when their bucket is the last one and

@@ -223,7 +223,7 @@ extern "C" int rs_lookup(const rs_blob* blob, const rs_keys* queries, uint64_t* 
                                              queries->kind, (uint32_t)L.kind);
     if (queries->kind == RS_KEYS_BYTES && !queries->offsets) return fail(RS_EINVAL, "NULL offsets");
     Strategy st = make_strategy((uint32_t)L.leaf);
-    LookupArgs a{blob->words, blob->tables, blob->tables + (L.maxm + 1), blob->tables + 2 * (L.maxm + 1),
+    LookupArgs a{blob->words, blob->tables, blob->tables + blob->tab_stride, blob->tables + 2 * blob->tab_stride,
                  L.nb, L.beta, L.delta_s, L.delta_z, L.Ws, L.Wz, L.lower_off, L.us_off, L.uz_off, L.invs_off,
                  L.invz_off, L.tree_off, L.us_words, L.uz_words, L.tree_words, (uint32_t)L.leaf, st.lower,
                  st.upper, (uint32_t)L.maxm};
@@ -288,6 +288,7 @@ extern "C" int rs_blob_from_host(const void* src, uint64_t bytes, void* stream, 
         return rc;
     }
     b->bytes = bytes;
+    b->tab_stride = (uint32_t)(L.maxm + 1);
     b->stream = s;
     (void)hipGetDevice(&b->device);
     *out = b;
@@ -296,10 +297,14 @@ extern "C" int rs_blob_from_host(const void* src, uint64_t bytes, void* stream, 
 
 extern "C" void rs_blob_free(rs_blob* blob) {
     if (!blob) return;
-    (void)hipStreamSynchronize(blob->stream);
-    if (blob->words) (void)hipFreeAsync(blob->words, blob->stream);
-    if (blob->tables) (void)hipFreeAsync(blob->tables, blob->stream);
-    (void)hipStreamSynchronize(blob->stream);
+    if (blob->arena) {
+        release_arena(blob->arena);
+    } else {
+        (void)hipStreamSynchronize(blob->stream);
+        if (blob->words) (void)hipFreeAsync(blob->words, blob->stream);
+        if (blob->tables) (void)hipFreeAsync(blob->tables, blob->stream);
+        (void)hipStreamSynchronize(blob->stream);
+    }
     delete blob;
 }
 

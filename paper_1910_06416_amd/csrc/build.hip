@@ -1,14 +1,18 @@
 // Construction of a RecSplit structure on the GPU (Sec. 4-7 of the paper).
 //
-// Pipeline, all on the caller's stream:
-//   signatures + bucket histogram -> exclusive scan (prefix sums s_i) ->
-//   scatter into bucket-contiguous order -> seed search (one wavefront per
-//   bucket, one lane per candidate index) -> scan of bucket bit lengths
-//   (offsets o_i) -> Elias-Fano minimum gaps -> [host: blob geometry] ->
-//   Elias-Fano bits + Golomb-Rice streams written into the blob.
+// Pipeline for one or many independent builds at once, all on the caller's
+// stream: signatures + bucket histogram -> exclusive scan (prefix sums s_i) ->
+// scatter into bucket-contiguous order -> seed search (a persistent grid, one
+// workgroup per bucket, one lane per candidate index) -> scan of bucket bit
+// lengths (offsets o_i) -> Elias-Fano minimum gaps per build -> [host: blob
+// geometry] -> Elias-Fano bits + Golomb-Rice streams written into the blobs.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <string>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -45,39 +49,73 @@ __global__ void k_fill_u64(uint64_t* p, uint64_t n, uint64_t v) {
 }
 
 // ---------------------------------------------------------------------------
-// Signatures (Sec. 6.1).
+// Builds of one call.  Several independent key sets are built together: their
+// keys and buckets are numbered consecutively (key_base, bucket_base) and every
+// kernel finds the build of an index by binary search over those bases.
 // ---------------------------------------------------------------------------
-__global__ void k_signature_u64(const uint64_t* __restrict__ keys, uint64_t n, uint64_t nb,
-                                uint64_t* __restrict__ lo_out, uint32_t* __restrict__ bid,
-                                uint32_t* __restrict__ counts) {
+struct BuildDesc {
+    const void* data;
+    const uint64_t* offsets;
+    uint64_t n, key_base, nb, bucket_base;
+    uint32_t kind, leaf, lower, upper;
+    uint32_t tab;      // index of this build's leaf-size tables in the table arena
+    uint32_t aligned;  // byte keys start on an 8-byte boundary
+    // written by the device
+    uint32_t maxm, flags;
+    unsigned long long delta_s;
+    long long delta_z;
+    unsigned long long total_bits;
+    // written by the host once the sizes are known
+    unsigned long long* blob;  // null: no blob for this build
+    uint64_t beta;
+    uint64_t lower_off, us_off, uz_off, invs_off, invz_off, tree_off;
+    uint32_t Ws, Wz;
+};
+
+// Largest j with base[j] <= x (base[0] = 0, strictly increasing, count entries).
+__device__ __forceinline__ uint32_t find_build(const uint64_t* __restrict__ base, uint32_t count, uint64_t x) {
+    uint32_t lo = 0, hi = count;
+    while (hi - lo > 1) {
+        uint32_t mid = (lo + hi) >> 1;
+        if (base[mid] <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// ---------------------------------------------------------------------------
+// Signatures (Sec. 6.1) and bucket histogram.
+// ---------------------------------------------------------------------------
+__global__ void k_signature(const BuildDesc* __restrict__ descs, BuildDesc* __restrict__ wdescs,
+                            const uint64_t* __restrict__ key_base, uint32_t count, uint64_t total,
+                            uint64_t* __restrict__ lo_out, uint32_t* __restrict__ bid,
+                            uint32_t* __restrict__ counts) {
     uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= total) return;
+    const uint32_t j = find_build(key_base, count, i);
+    const BuildDesc& B = descs[j];
+    const uint64_t k = i - B.key_base;
     uint64_t hi, lo;
-    signature_u64(keys[i], hi, lo);
-    uint32_t b = (uint32_t)bucket_of(hi, nb);
+    if (B.kind == RS_KEYS_U64) {
+        signature_u64(static_cast<const uint64_t*>(B.data)[k], hi, lo);
+    } else {
+        const uint64_t* off = B.offsets;
+        uint64_t s = off[k], e = off[k + 1], bytes = off[B.n];
+        if (e < s || e > bytes) {
+            atomicOr(&wdescs[j].flags, kFlagOffsets);
+            e = s = min(s, bytes);
+        }
+        signature_bytes(static_cast<const uint8_t*>(B.data), bytes, B.aligned != 0, s, e, hi, lo);
+    }
+    const uint32_t b = (uint32_t)(bucket_of(hi, B.nb) + B.bucket_base);
     lo_out[i] = lo;
     bid[i] = b;
     atomicAdd(&counts[b], 1u);
 }
 
-__global__ void k_signature_bytes(const uint8_t* __restrict__ data, const uint64_t* __restrict__ offsets,
-                                  uint64_t n, uint64_t nb, bool aligned, uint64_t* __restrict__ lo_out,
-                                  uint32_t* __restrict__ bid, uint32_t* __restrict__ counts, DevStatus* st) {
-    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    uint64_t s = offsets[i], e = offsets[i + 1], total = offsets[n];
-    if (e < s || e > total) {
-        atomicOr(&st->flags, kFlagOffsets);
-        e = s;
-        if (s > total) s = e = total;
-    }
-    uint64_t hi, lo;
-    signature_bytes(data, total, aligned, s, e, hi, lo);
-    uint32_t b = (uint32_t)bucket_of(hi, nb);
-    lo_out[i] = lo;
-    bid[i] = b;
-    atomicAdd(&counts[b], 1u);
-}
+}  // namespace
+
+namespace {
 
 // ---------------------------------------------------------------------------
 // Exclusive scan (three passes: tile sums, scan of tile sums, tile scan).
@@ -205,12 +243,14 @@ struct SearchArgs {
     const uint64_t* bstart;
     uint64_t* seeds;
     uint64_t* blen;
-    const uint32_t* R;
-    const uint32_t* N;  // coded nodes of a subtree, per size
-    const uint32_t* G;  // log2 of the lanes that share one candidate, per split size
-    DevStatus* status;
+    const BuildDesc* descs;
+    BuildDesc* wdescs;
+    const uint64_t* bucket_base;
+    uint32_t count;
+    uint64_t nbuckets;
+    const uint32_t* tables;     // per leaf size: r, F, N, G, each `stride` words
+    uint32_t stride;
     uint64_t seed_cap;
-    uint32_t leaf, lower, upper;
     uint32_t stage_from;  // leaves of at least this many keys use the staged bijection search
     uint32_t group_max;   // cap on log2 lanes per split candidate
     uint32_t key_words;   // 64-bit words of dynamic LDS before the node slots (largest bucket)
@@ -273,7 +313,7 @@ __device__ __forceinline__ uint32_t leaf_bits(const uint64_t (&k)[M], uint64_t S
 }
 
 template <int M>
-__device__ uint64_t leaf_search(const uint64_t* keys, uint32_t depth, uint64_t cap, DevStatus* st, LeafQueues* q,
+__device__ uint64_t leaf_search(const uint64_t* keys, uint32_t depth, uint64_t cap, uint32_t* flags, LeafQueues* q,
                                 bool staged) {
     constexpr int C1 = kCut1[M], C2 = kCut2[M];
     constexpr uint32_t full = (1u << M) - 1u;
@@ -362,7 +402,7 @@ __device__ uint64_t leaf_search(const uint64_t* keys, uint32_t depth, uint64_t c
             if (last) break;
         }
     }
-    if (lane == 0) atomicOr(&st->flags, kFlagSearch);
+    if (lane == 0) atomicOr(flags, kFlagSearch);
     return kNoSeed;
 }
 
@@ -376,18 +416,18 @@ __device__ bool has_duplicate(const uint64_t* keys, uint32_t m) {
 }
 
 template <int MAXL>
-__device__ uint64_t leaf_dispatch(const uint64_t* keys, uint32_t m, uint32_t depth, uint64_t cap, DevStatus* st,
+__device__ uint64_t leaf_dispatch(const uint64_t* keys, uint32_t m, uint32_t depth, uint64_t cap, uint32_t* flags,
                                   LeafQueues* q, uint32_t stage_from) {
     // Equal lower words never separate, so they always meet in one leaf, or in a
     // split whose parts are all single keys: those nodes check every pair first.
     if (has_duplicate(keys, m)) {
-        if (lane_id() == 0) atomicOr(&st->flags, kFlagDuplicate);
+        if (lane_id() == 0) atomicOr(flags, kFlagDuplicate);
         return kNoSeed;
     }
     switch (m) {
 #define RS_LEAF_CASE(M)                                                                    \
     case M:                                                                                \
-        if constexpr (M <= MAXL) return leaf_search<M>(keys, depth, cap, st, q, M >= stage_from); \
+        if constexpr (M <= MAXL) return leaf_search<M>(keys, depth, cap, flags, q, M >= stage_from); \
         return kNoSeed;
         RS_LEAF_CASE(2) RS_LEAF_CASE(3) RS_LEAF_CASE(4) RS_LEAF_CASE(5) RS_LEAF_CASE(6) RS_LEAF_CASE(7)
         RS_LEAF_CASE(8) RS_LEAF_CASE(9) RS_LEAF_CASE(10) RS_LEAF_CASE(11) RS_LEAF_CASE(12) RS_LEAF_CASE(13)
@@ -422,7 +462,7 @@ struct SplitCtl {
 
 template <int NT, bool PACKED>
 __device__ uint64_t split_search(const uint64_t* keys, uint32_t depth, const SplitCtl& c, const uint32_t* T,
-                                 uint64_t cap, DevStatus* st) {
+                                 uint64_t cap, uint32_t* flags) {
     uint32_t thr[NT];
 #pragma unroll
     for (int t = 0; t < NT; t++) thr[t] = T[t];
@@ -480,22 +520,22 @@ __device__ uint64_t split_search(const uint64_t* keys, uint32_t depth, const Spl
         uint64_t bal = __ballot(ok);
         if (bal) return base + (uint64_t)(__builtin_ctzll(bal) >> c.g);
     }
-    if (lane == 0) atomicOr(&st->flags, kFlagSearch);
+    if (lane == 0) atomicOr(flags, kFlagSearch);
     return kNoSeed;
 }
 
 template <int MAXNT>
 __device__ uint64_t split_dispatch(const uint64_t* keys, uint32_t depth, const SplitCtl& c, const uint32_t* T,
-                                   bool packed, uint64_t cap, DevStatus* st) {
+                                   bool packed, uint64_t cap, uint32_t* flags) {
     const uint32_t nt = c.fanout - 1;
     if constexpr (MAXNT >= 4) {
         if (packed) {
             switch (nt) {
-                case 4: return split_search<4, true>(keys, depth, c, T, cap, st);
-                case 5: if constexpr (MAXNT >= 5) return split_search<5, true>(keys, depth, c, T, cap, st); break;
-                case 6: if constexpr (MAXNT >= 6) return split_search<6, true>(keys, depth, c, T, cap, st); break;
-                case 7: if constexpr (MAXNT >= 7) return split_search<7, true>(keys, depth, c, T, cap, st); break;
-                case 8: if constexpr (MAXNT >= 8) return split_search<8, true>(keys, depth, c, T, cap, st); break;
+                case 4: return split_search<4, true>(keys, depth, c, T, cap, flags);
+                case 5: if constexpr (MAXNT >= 5) return split_search<5, true>(keys, depth, c, T, cap, flags); break;
+                case 6: if constexpr (MAXNT >= 6) return split_search<6, true>(keys, depth, c, T, cap, flags); break;
+                case 7: if constexpr (MAXNT >= 7) return split_search<7, true>(keys, depth, c, T, cap, flags); break;
+                case 8: if constexpr (MAXNT >= 8) return split_search<8, true>(keys, depth, c, T, cap, flags); break;
                 default: break;
             }
             return kNoSeed;
@@ -504,7 +544,7 @@ __device__ uint64_t split_dispatch(const uint64_t* keys, uint32_t depth, const S
     switch (nt) {
 #define RS_SPLIT_CASE(NT)                                                                 \
     case NT:                                                                              \
-        if constexpr (NT <= MAXNT) return split_search<NT, false>(keys, depth, c, T, cap, st); \
+        if constexpr (NT <= MAXNT) return split_search<NT, false>(keys, depth, c, T, cap, flags); \
         return kNoSeed;
         RS_SPLIT_CASE(1) RS_SPLIT_CASE(2) RS_SPLIT_CASE(3) RS_SPLIT_CASE(4) RS_SPLIT_CASE(5) RS_SPLIT_CASE(6)
         RS_SPLIT_CASE(7) RS_SPLIT_CASE(8)
@@ -562,7 +602,9 @@ __device__ void partition(uint64_t* keys, uint32_t m, uint32_t depth, uint64_t v
     wave_mem_sync();
 }
 
-// One workgroup of WAVES wavefronts per bucket.  The bucket's keys sit in LDS.
+// One workgroup of WAVES wavefronts per bucket of every build of the call (the
+// hardware hands workgroups to compute units as they free up, so uneven
+// buckets balance dynamically).  The bucket's keys sit in LDS.
 // Every coded node of the bucket's tree gets one slot of an LDS queue (the
 // number of coded nodes, N(m), is known from the strategy): wavefronts claim
 // slots in order with an atomic counter, wait until the slot has been
@@ -595,155 +637,194 @@ __global__ __launch_bounds__(64 * WAVES) void k_search(SearchArgs a) {
     __shared__ QueueState qs;
     __shared__ uint32_t thr_s[WAVES][kMaxThresholds];
     __shared__ LeafQueues queues[WAVES];
-    const uint64_t b = blockIdx.x;
     const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
-    const uint64_t start = a.bstart[b];
-    const uint32_t m0 = (uint32_t)(a.bstart[b + 1] - start);
     uint64_t* lds_keys = lds_dyn;
     NodeSlot* slots = reinterpret_cast<NodeSlot*>(lds_dyn + a.key_words);
-    const uint32_t total = a.N[m0];
-    for (uint32_t i = threadIdx.x; i < m0; i += 64 * WAVES) lds_keys[i] = a.sorted[start + i];
-    for (uint32_t i = threadIdx.x; i < total; i += 64 * WAVES) slots[i].m = 0;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        qs.head = 0;
-        qs.tail = total ? 1 : 0;
-        qs.abort = 0;
-        qs.bits = 0;
-        if (total) {
-            slots[0].off = 0;
-            slots[0].d = 0;
-            slots[0].idx = 0;
-            slots[0].m = m0;
-        }
-    }
-    __syncthreads();
     uint32_t* thr = thr_s[wave];
-    unsigned long long bits = 0;
-    for (;;) {
-        uint32_t h = 0, off = 0, m = 0, d = 0, idx = 0, stop = 0;
-        if (lane == 0) {
-            h = __hip_atomic_fetch_add(&qs.head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            if (h >= total) {
-                stop = 1;
-            } else {
-                uint32_t spins = 0;
-                for (;;) {
-                    m = __hip_atomic_load(&slots[h].m, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
-                    if (m) break;
-                    if (__hip_atomic_load(&qs.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
-                        stop = 1;
-                        break;
+    {
+        const uint64_t b = blockIdx.x;
+        const uint32_t j = find_build(a.bucket_base, a.count, b);
+        const BuildDesc& B = a.descs[j];
+        const uint32_t leaf = B.leaf, lower = B.lower, upper = B.upper;
+        const uint32_t* R = a.tables + (size_t)B.tab * 4 * a.stride;
+        const uint32_t* Nt = R + 2 * a.stride;
+        const uint32_t* Gt = R + 3 * a.stride;
+        uint32_t* bflags = &a.wdescs[j].flags;
+        const uint64_t start = a.bstart[b];
+        const uint32_t m0 = (uint32_t)(a.bstart[b + 1] - start);
+        const uint32_t total = Nt[m0];
+        for (uint32_t i = threadIdx.x; i < m0; i += 64 * WAVES) lds_keys[i] = a.sorted[start + i];
+        for (uint32_t i = threadIdx.x; i < total; i += 64 * WAVES) slots[i].m = 0;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            qs.head = 0;
+            qs.tail = total ? 1 : 0;
+            qs.abort = 0;
+            qs.bits = 0;
+            if (total) {
+                slots[0].off = 0;
+                slots[0].d = 0;
+                slots[0].idx = 0;
+                slots[0].m = m0;
+            }
+        }
+        __syncthreads();
+        unsigned long long bits = 0;
+        for (;;) {
+            uint32_t h = 0, off = 0, m = 0, d = 0, idx = 0, stop = 0;
+            if (lane == 0) {
+                h = __hip_atomic_fetch_add(&qs.head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (h >= total) {
+                    stop = 1;
+                } else {
+                    uint32_t spins = 0;
+                    for (;;) {
+                        m = __hip_atomic_load(&slots[h].m, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        if (m) break;
+                        if (__hip_atomic_load(&qs.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
+                            stop = 1;
+                            break;
+                        }
+                        if (++spins == kWaitLimit) {
+                            atomicOr(bflags, kFlagStack);
+                            __hip_atomic_store(&qs.abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                            stop = 1;
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(4);
                     }
-                    if (++spins == kWaitLimit) {
-                        atomicOr(&a.status->flags, kFlagStack);
+                    if (!stop) {
+                        off = slots[h].off;
+                        d = slots[h].d;
+                        idx = slots[h].idx;
+                    }
+                }
+            }
+            if (__builtin_amdgcn_readfirstlane(stop)) break;
+            off = __builtin_amdgcn_readfirstlane(off);
+            m = __builtin_amdgcn_readfirstlane(m);
+            d = __builtin_amdgcn_readfirstlane(d);
+            idx = __builtin_amdgcn_readfirstlane(idx);
+            wave_mem_sync();
+            uint64_t v;
+            bool fail;
+            SplitShape sh{};
+            if (m <= leaf) {
+                v = leaf_dispatch<MAXL>(lds_keys + off, m, d, a.seed_cap, bflags, &queues[wave], a.stage_from);
+                fail = v == kNoSeed;
+            } else {
+                sh = split_shape(m, leaf, lower, upper);
+                if (sh.unit == 1 && has_duplicate(lds_keys + off, m)) {  // l = 1: parts of one key each
+                    if (lane == 0) atomicOr(bflags, kFlagDuplicate);
+                    v = kNoSeed;
+                    fail = true;
+                } else {
+                    const uint32_t nt = sh.fanout - 1;
+                    if (lane < nt) thr[lane] = (uint32_t)((((uint64_t)(lane + 1) * sh.unit << 32) + m - 1) / m);
+                    wave_lds_sync();
+                    SplitCtl c;
+                    c.m = m;
+                    c.unit = sh.unit;
+                    c.fanout = sh.fanout;
+                    c.last = sh.last;
+                    c.g = min(Gt[m], a.group_max);
+                    c.w = 32 - __clz(m);
+                    const bool packed = nt >= 4 && sh.fanout * c.w <= 64;
+                    c.recip = packed ? (uint32_t)(((1ull << 32) + sh.unit - 1) / sh.unit) : 0;
+                    c.want = 0;
+                    if (packed)
+                        for (uint32_t q = 0; q < sh.fanout; q++)
+                            c.want += (uint64_t)(q + 1 == sh.fanout ? sh.last : sh.unit) << (q * c.w);
+                    v = split_dispatch<max_thresholds(MAXL)>(lds_keys + off, d, c, thr, packed, a.seed_cap, bflags);
+                    fail = v == kNoSeed;  // counts do not match the parts: no partition
+                    if (!fail) partition(lds_keys + off, m, d, v, thr, nt, sh.unit, a.tmp + start + off);
+                }
+            }
+            if (fail) {
+                if (lane == 0) __hip_atomic_store(&qs.abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                break;
+            }
+            if (lane == 0) a.seeds[start + idx] = v;
+            const uint32_t r = R[m];
+            bits += r + (v >> r) + 1;
+            if (m > leaf && lane == 0) {
+                for (uint32_t q = 0; q < sh.fanout; q++) {
+                    const uint32_t cm = q + 1 == sh.fanout ? sh.last : sh.unit;
+                    if (cm < 2) continue;
+                    const uint32_t t =
+                        __hip_atomic_fetch_add(&qs.tail, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    if (t >= total) {  // more children than coded nodes: tables and strategy disagree
+                        atomicOr(bflags, kFlagStack);
                         __hip_atomic_store(&qs.abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                        stop = 1;
                         break;
                     }
-                    __builtin_amdgcn_s_sleep(4);
-                }
-                if (!stop) {
-                    off = slots[h].off;
-                    d = slots[h].d;
-                    idx = slots[h].idx;
+                    slots[t].off = off + q * sh.unit;
+                    slots[t].d = d + 1;
+                    slots[t].idx = idx + 1 + q * Nt[sh.unit];
+                    __hip_atomic_store(&slots[t].m, cm, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
                 }
             }
         }
-        if (__builtin_amdgcn_readfirstlane(stop)) break;
-        off = __builtin_amdgcn_readfirstlane(off);
-        m = __builtin_amdgcn_readfirstlane(m);
-        d = __builtin_amdgcn_readfirstlane(d);
-        idx = __builtin_amdgcn_readfirstlane(idx);
-        wave_mem_sync();
-        uint64_t v;
-        bool fail;
-        SplitShape sh{};
-        if (m <= a.leaf) {
-            v = leaf_dispatch<MAXL>(lds_keys + off, m, d, a.seed_cap, a.status, &queues[wave], a.stage_from);
-            fail = v == kNoSeed;
-        } else {
-            sh = split_shape(m, a.leaf, a.lower, a.upper);
-            if (sh.unit == 1 && has_duplicate(lds_keys + off, m)) {  // l = 1: parts of one key each
-                if (lane == 0) atomicOr(&a.status->flags, kFlagDuplicate);
-                v = kNoSeed;
-                fail = true;
-            } else {
-                const uint32_t nt = sh.fanout - 1;
-                if (lane < nt) thr[lane] = (uint32_t)((((uint64_t)(lane + 1) * sh.unit << 32) + m - 1) / m);
-                wave_lds_sync();
-                SplitCtl c;
-                c.m = m;
-                c.unit = sh.unit;
-                c.fanout = sh.fanout;
-                c.last = sh.last;
-                c.g = min(a.G[m], a.group_max);
-                c.w = 32 - __clz(m);
-                const bool packed = nt >= 4 && sh.fanout * c.w <= 64;
-                c.recip = packed ? (uint32_t)(((1ull << 32) + sh.unit - 1) / sh.unit) : 0;
-                c.want = 0;
-                if (packed)
-                    for (uint32_t j = 0; j < sh.fanout; j++)
-                        c.want += (uint64_t)(j + 1 == sh.fanout ? sh.last : sh.unit) << (j * c.w);
-                v = split_dispatch<max_thresholds(MAXL)>(lds_keys + off, d, c, thr, packed, a.seed_cap, a.status);
-                fail = v == kNoSeed;  // counts do not match the parts: no partition
-                if (!fail) partition(lds_keys + off, m, d, v, thr, nt, sh.unit, a.tmp + start + off);
-            }
-        }
-        if (fail) {
-            if (lane == 0) __hip_atomic_store(&qs.abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-            break;
-        }
-        if (lane == 0) a.seeds[start + idx] = v;
-        const uint32_t r = a.R[m];
-        bits += r + (v >> r) + 1;
-        if (m > a.leaf && lane == 0) {
-            for (uint32_t j = 0; j < sh.fanout; j++) {
-                const uint32_t cm = j + 1 == sh.fanout ? sh.last : sh.unit;
-                if (cm < 2) continue;
-                const uint32_t t =
-                    __hip_atomic_fetch_add(&qs.tail, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                if (t >= total) {  // more children than coded nodes: tables and strategy disagree
-                    atomicOr(&a.status->flags, kFlagStack);
-                    __hip_atomic_store(&qs.abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                    break;
-                }
-                slots[t].off = off + j * sh.unit;
-                slots[t].d = d + 1;
-                slots[t].idx = idx + 1 + j * a.N[sh.unit];
-                __hip_atomic_store(&slots[t].m, cm, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-            }
-        }
+        if (lane == 0) atomicAdd(&qs.bits, bits);
+        __syncthreads();
+        if (threadIdx.x == 0) a.blen[b] = qs.bits;
     }
-    if (lane == 0) atomicAdd(&qs.bits, bits);
-    __syncthreads();
-    if (threadIdx.x == 0) a.blen[b] = qs.bits;
 }
 
 // ---------------------------------------------------------------------------
-// Elias-Fano of s_i and z_i = o_i - floor(beta s_i / 2^16) (Sec. 6.3, 7.4).
+// Elias-Fano of s_i and z_i = o_i - floor(beta s_i / 2^16) (Sec. 6.3, 7.4),
+// per build: minimum gaps, largest bucket and total tree bits.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ int64_t z_of(uint64_t o, uint64_t s, uint64_t beta) {
     return (int64_t)o - (int64_t)((beta * s) >> 16);
 }
 
-__global__ void k_ef_gaps(const uint64_t* __restrict__ bstart, const uint64_t* __restrict__ ostart, uint64_t nb,
-                          uint64_t n, DevStatus* st) {
-    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    uint64_t beta = (ostart[nb] << 16) / n;
+struct GapArgs {
+    const uint64_t* bstart;  // global prefix sums of bucket sizes (nbuckets + 1)
+    const uint64_t* ostart;  // global prefix sums of bucket bit lengths (nbuckets + 1)
+    const BuildDesc* descs;
+    BuildDesc* wdescs;
+    const uint64_t* bucket_base;
+    uint32_t count;
+    uint64_t nbuckets;
+};
+
+__global__ void k_ef_gaps(GapArgs a) {
+    const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint32_t j = 0;
     unsigned long long gs = ~0ull;
     long long gz = 0x7fffffffffffffffll;
-    if (i < nb) {
-        gs = bstart[i + 1] - bstart[i];
-        gz = z_of(ostart[i + 1], bstart[i + 1], beta) - z_of(ostart[i], bstart[i], beta);
+    uint32_t mx = 0;
+    if (g < a.nbuckets) {
+        j = find_build(a.bucket_base, a.count, g);
+        const BuildDesc& B = a.descs[j];
+        const uint64_t bb = B.bucket_base, s0 = a.bstart[bb], o0 = a.ostart[bb];
+        const uint64_t bits = a.ostart[bb + B.nb] - o0;
+        const uint64_t beta = (bits << 16) / B.n;
+        const uint64_t s_i = a.bstart[g] - s0, s_i1 = a.bstart[g + 1] - s0;
+        gs = s_i1 - s_i;
+        gz = z_of(a.ostart[g + 1] - o0, s_i1, beta) - z_of(a.ostart[g] - o0, s_i, beta);
+        mx = (uint32_t)gs;
+        if (g == bb) a.wdescs[j].total_bits = bits;
     }
-    for (int off = 32; off > 0; off >>= 1) {
-        gs = min(gs, (unsigned long long)__shfl_xor(gs, off, 64));
-        gz = min(gz, (long long)__shfl_xor(gz, off, 64));
-    }
-    if ((threadIdx.x & 63) == 0) {
-        atomicMin(&st->delta_s, gs);
-        atomicMin(&st->delta_z, gz);
+    // reduce over the wavefront when all its lanes belong to one build
+    const uint32_t j0 = __builtin_amdgcn_readfirstlane(j);
+    const bool same = __ballot(g < a.nbuckets && j != j0) == 0;
+    if (same) {
+        for (int off = 32; off > 0; off >>= 1) {
+            gs = min(gs, (unsigned long long)__shfl_xor(gs, off, 64));
+            gz = min(gz, (long long)__shfl_xor(gz, off, 64));
+            mx = max(mx, (uint32_t)__shfl_xor((int)mx, off, 64));
+        }
+        if ((threadIdx.x & 63) == 0 && gs != ~0ull) {
+            atomicMin(&a.wdescs[j0].delta_s, gs);
+            atomicMin(&a.wdescs[j0].delta_z, gz);
+            atomicMax(&a.wdescs[j0].maxm, mx);
+        }
+    } else if (g < a.nbuckets) {
+        atomicMin(&a.wdescs[j].delta_s, gs);
+        atomicMin(&a.wdescs[j].delta_z, gz);
+        atomicMax(&a.wdescs[j].maxm, mx);
     }
 }
 
@@ -759,46 +840,58 @@ struct FillArgs {
     const uint64_t* bstart;
     const uint64_t* ostart;
     const uint64_t* seeds;
-    const uint32_t* R;
-    const uint32_t* F;
-    unsigned long long* blob;
-    uint64_t nb, beta, delta_s;
-    int64_t delta_z;
-    uint32_t Ws, Wz;
-    uint64_t lower_off, us_off, uz_off, invs_off, invz_off, tree_off;
-    uint32_t leaf, lower, upper;
+    const BuildDesc* descs;
+    const uint64_t* bucket_base;
+    const uint64_t* entry_base;  // bucket_base[j] + j: nb_j + 1 Elias-Fano entries per build
+    uint32_t count;
+    uint64_t nbuckets;
+    const uint32_t* tables;
+    uint32_t stride;
 };
 
+// One thread per Elias-Fano entry i = 0..nb of every build.
 __global__ void k_ef_fill(FillArgs a) {
-    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i > a.nb) return;
-    uint64_t s = a.bstart[i];
-    int64_t z = z_of(a.ostart[i], s, a.beta);
-    uint64_t ys = s - i * a.delta_s;
-    uint64_t yz = (uint64_t)(z - (int64_t)i * a.delta_z);
-    uint64_t lpos = i * (uint64_t)(a.Ws + a.Wz);
-    uint64_t ms = a.Ws ? (~0ull >> (64 - a.Ws)) : 0, mz = a.Wz ? (~0ull >> (64 - a.Wz)) : 0;
-    or_bits(a.blob + a.lower_off, lpos, ys & ms, a.Ws);
-    or_bits(a.blob + a.lower_off, lpos + a.Ws, yz & mz, a.Wz);
-    uint64_t ps = (ys >> a.Ws) + i, pz = (yz >> a.Wz) + i;
-    or_bits(a.blob + a.us_off, ps, 1, 1);
-    or_bits(a.blob + a.uz_off, pz, 1, 1);
+    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= a.nbuckets + a.count) return;
+    const uint32_t j = find_build(a.entry_base, a.count, e);
+    const BuildDesc& B = a.descs[j];
+    if (!B.blob) return;
+    const uint64_t i = e - a.entry_base[j];
+    const uint64_t bb = B.bucket_base;
+    const uint64_t s = a.bstart[bb + i] - a.bstart[bb];
+    const int64_t z = z_of(a.ostart[bb + i] - a.ostart[bb], s, B.beta);
+    const uint64_t ys = s - i * B.delta_s;
+    const uint64_t yz = (uint64_t)(z - (int64_t)i * B.delta_z);
+    const uint64_t lpos = i * (uint64_t)(B.Ws + B.Wz);
+    const uint64_t ms = B.Ws ? (~0ull >> (64 - B.Ws)) : 0, mz = B.Wz ? (~0ull >> (64 - B.Wz)) : 0;
+    unsigned long long* blob = B.blob;
+    or_bits(blob + B.lower_off, lpos, ys & ms, B.Ws);
+    or_bits(blob + B.lower_off, lpos + B.Ws, yz & mz, B.Wz);
+    const uint64_t ps = (ys >> B.Ws) + i, pz = (yz >> B.Wz) + i;
+    or_bits(blob + B.us_off, ps, 1, 1);
+    or_bits(blob + B.uz_off, pz, 1, 1);
     if ((i & ((1u << kInvShift) - 1)) == 0) {
-        a.blob[a.invs_off + (i >> kInvShift)] = ps;
-        a.blob[a.invz_off + (i >> kInvShift)] = pz;
+        blob[B.invs_off + (i >> kInvShift)] = ps;
+        blob[B.invz_off + (i >> kInvShift)] = pz;
     }
 }
 
 // Golomb-Rice streams (Sec. 6.2): per bucket, the fixed parts of all coded
 // nodes in preorder, then their unary parts (q zeros and a one) in preorder.
 __global__ void k_tree_bits(FillArgs a) {
-    uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= a.nb) return;
-    uint64_t start = a.bstart[b];
-    uint32_t m0 = (uint32_t)(a.bstart[b + 1] - start);
+    const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= a.nbuckets) return;
+    const uint32_t j = find_build(a.bucket_base, a.count, g);
+    const BuildDesc& B = a.descs[j];
+    if (!B.blob) return;
+    const uint64_t start = a.bstart[g];
+    const uint32_t m0 = (uint32_t)(a.bstart[g + 1] - start);
     if (m0 <= 1) return;
-    unsigned long long* tree = a.blob + a.tree_off;
-    uint64_t fp = a.ostart[b], up = fp + a.F[m0];
+    const uint32_t* R = a.tables + (size_t)B.tab * 4 * a.stride;
+    const uint32_t* F = R + a.stride;
+    unsigned long long* tree = B.blob + B.tree_off;
+    const uint64_t o0 = a.ostart[B.bucket_base];
+    uint64_t fp = a.ostart[g] - o0, up = fp + F[m0];
     uint32_t stk[kStackDepth];
     int sp = 0;
     stk[sp++] = m0;
@@ -807,29 +900,27 @@ __global__ void k_tree_bits(FillArgs a) {
         uint32_t m = stk[--sp];
         if (m <= 1) continue;
         uint64_t v = a.seeds[start + node++];
-        uint32_t r = a.R[m];
+        uint32_t r = R[m];
         or_bits(tree, fp, r ? (v & (~0ull >> (64 - r))) : 0, r);
         fp += r;
         up += v >> r;
         or_bits(tree, up, 1, 1);
         up++;
-        if (m > a.leaf) {
-            SplitShape sh = split_shape(m, a.leaf, a.lower, a.upper);
-            if (sp + (int)sh.fanout > kStackDepth) return;  // cannot happen: the search flagged it
+        if (m > B.leaf) {
+            SplitShape sh = split_shape(m, B.leaf, B.lower, B.upper);
+            if (sp + (int)sh.fanout > kStackDepth) return;  // deeper than any tree of <= 2^32 keys
             stk[sp++] = sh.last;
-            for (uint32_t j = 1; j < sh.fanout; j++) stk[sp++] = sh.unit;
+            for (uint32_t q = 1; q < sh.fanout; q++) stk[sp++] = sh.unit;
         }
     }
 }
 
-__global__ void k_write_header(uint64_t* blob, uint64_t h0, uint64_t h1, uint64_t h2, uint64_t h3, uint64_t h4,
-                               uint64_t h5, uint64_t h6, uint64_t h7, uint64_t h8, uint64_t h9, uint64_t h10,
-                               uint64_t h11, uint64_t h12, uint64_t h13, uint64_t h14, uint64_t h15) {
-    if (threadIdx.x == 0) {
-        blob[0] = h0; blob[1] = h1; blob[2] = h2; blob[3] = h3; blob[4] = h4; blob[5] = h5; blob[6] = h6;
-        blob[7] = h7; blob[8] = h8; blob[9] = h9; blob[10] = h10; blob[11] = h11; blob[12] = h12;
-        blob[13] = h13; blob[14] = h14; blob[15] = h15;
-    }
+// Headers: 16 words per build with a blob.
+__global__ void k_write_headers(const BuildDesc* descs, const uint64_t* headers, uint32_t count) {
+    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count * kHeaderWords) return;
+    const uint32_t j = t / kHeaderWords, w = t % kHeaderWords;
+    if (descs[j].blob) descs[j].blob[w] = headers[t];
 }
 
 uint32_t grid_for(uint64_t n, uint32_t block) { return (uint32_t)std::max<uint64_t>(1, (n + block - 1) / block); }
@@ -851,16 +942,45 @@ uint32_t ef_width(uint64_t N, uint64_t U) {
     return W;
 }
 
-struct Pinned {
-    DevStatus st;
-    uint64_t total_bits;
-    uint64_t pad[7];
+// Grow-only pinned host staging buffer of the calling thread.  Copies from it
+// are asynchronous, so an event recorded after the last copy of a call guards
+// its reuse by the next call.
+struct Staging {
+    void* p = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+    bool pending = false;
 };
+thread_local Staging g_staging;
 
-Pinned* pinned_scratch() {
-    static thread_local Pinned* p = nullptr;
-    if (!p && hipHostMalloc((void**)&p, sizeof(Pinned), hipHostMallocDefault) != hipSuccess) p = nullptr;
-    return p;
+void* pinned(size_t bytes) {
+    Staging& st = g_staging;
+    if (st.pending) {
+        (void)hipEventSynchronize(st.done);
+        st.pending = false;
+    }
+    if (st.cap < bytes) {
+        if (st.p) (void)hipHostFree(st.p);
+        size_t want = std::max<size_t>(bytes, 1 << 16);
+        if (hipHostMalloc(&st.p, want, hipHostMallocDefault) != hipSuccess) {
+            st.p = nullptr;
+            st.cap = 0;
+            return nullptr;
+        }
+        st.cap = want;
+    }
+    return st.p;
+}
+
+void pinned_release(hipStream_t s) {
+    Staging& st = g_staging;
+    if (!st.done && hipEventCreateWithFlags(&st.done, hipEventDisableTiming) != hipSuccess) {
+        st.done = nullptr;
+        (void)hipStreamSynchronize(s);
+        return;
+    }
+    if (hipEventRecord(st.done, s) == hipSuccess) st.pending = true;
+    else (void)hipStreamSynchronize(s);
 }
 
 thread_local rs_build_stats g_stats;
@@ -902,43 +1022,144 @@ int max_lds_bytes() {
     return v;
 }
 
+// One launch of the search over every bucket of the call.
+template <int MAXL, int WAVES>
+int launch_search(const SearchArgs& sa, size_t lds, hipStream_t s) {
+    k_search<MAXL, WAVES><<<(uint32_t)sa.nbuckets, 64 * WAVES, lds, s>>>(sa);
+    RS_HIP(hipGetLastError());
+    return RS_OK;
+}
+
 }  // namespace
 
-int build_impl(const rs_keys* keys, uint32_t leaf, uint32_t bucket, const rs_options* opts, hipStream_t s,
-               rs_blob** out) {
-    if (!keys || !out) return fail(RS_EINVAL, "NULL argument");
-    if (keys->n == 0) return fail(RS_EINVAL, "empty key set");
-    if (leaf < 1 || leaf > kMaxLeaf) return fail(RS_EINVAL, "leaf size %u outside [1, 24]", leaf);
-    if (bucket == 0) return fail(RS_EINVAL, "bucket size must be positive");
-    if (!keys->data) return fail(RS_EINVAL, "NULL key data");
-    if (keys->kind != RS_KEYS_U64 && keys->kind != RS_KEYS_BYTES) return fail(RS_EINVAL, "unknown key kind");
-    if (keys->kind == RS_KEYS_BYTES && !keys->offsets) return fail(RS_EINVAL, "NULL offsets for byte keys");
-    const uint64_t n = keys->n;
-    const uint64_t nb = (n + bucket - 1) / bucket;
-    if (nb >= (1ull << 32)) return fail(RS_EINVAL, "too many buckets");
-    const uint64_t cap = opts && opts->seed_cap ? std::min(opts->seed_cap, kDefaultSeedCap) : kDefaultSeedCap;
-    const Strategy st = make_strategy(leaf);
-    Pinned* pin = pinned_scratch();
-    if (!pin) return fail(RS_ENOMEM, "pinned host allocation failed");
+// Shared ownership of the device memory of the blobs of one call.
+struct BlobArena {
+    uint64_t* words = nullptr;
+    uint32_t* tables = nullptr;
+    std::atomic<int> refs{0};
+    hipStream_t stream = nullptr;
+};
+
+void release_arena(BlobArena* a) {
+    if (a && a->refs.fetch_sub(1) == 1) {
+        (void)hipStreamSynchronize(a->stream);
+        if (a->words) (void)hipFreeAsync(a->words, a->stream);
+        if (a->tables) (void)hipFreeAsync(a->tables, a->stream);
+        (void)hipStreamSynchronize(a->stream);
+        delete a;
+    }
+}
+
+// RS_DEBUG=1 in the environment prints the construction phases to stderr.
+bool debug_trace() {
+    static const bool on = [] {
+        const char* e = std::getenv("RS_DEBUG");
+        return e && *e && *e != '0';
+    }();
+    return on;
+}
+#define RS_TRACE(...)                               \
+    do {                                            \
+        if (debug_trace()) {                        \
+            std::fprintf(stderr, "[librecsplit] "); \
+            std::fprintf(stderr, __VA_ARGS__);      \
+            std::fprintf(stderr, "\n");             \
+            std::fflush(stderr);                    \
+        }                                           \
+    } while (0)
+
+int build_batch_impl(const rs_keys* sets, uint32_t count, const uint32_t* leafs, const uint32_t* buckets,
+                     const rs_options* opts, hipStream_t s, rs_blob** outs, int* statuses) {
+    if (!sets || !leafs || !buckets || !outs || count == 0) return fail(RS_EINVAL, "NULL argument or empty batch");
     const bool timing = opts && (opts->flags & RS_OPT_TIMING);
+    const uint64_t cap = opts && opts->seed_cap ? std::min(opts->seed_cap, kDefaultSeedCap) : kDefaultSeedCap;
+    const uint32_t stage_from = opts && opts->stage_from ? opts->stage_from : 9;
+    const uint32_t group_max = opts && opts->group_max ? opts->group_max - 1 : 6;
+    std::vector<int> st(count, RS_OK);
+    std::vector<std::string> why(count);
+
+    // host descriptors of the valid builds
+    std::vector<BuildDesc> hd;
+    std::vector<uint32_t> which;  // desc index -> position in the call
+    std::vector<uint32_t> leaf_of_tab;
+    uint64_t total = 0, nbuckets = 0;
+    uint32_t max_leaf = 1;
+    for (uint32_t c = 0; c < count; c++) {
+        const rs_keys& k = sets[c];
+        const uint32_t leaf = leafs[c], bucket = buckets[c];
+        const char* bad = nullptr;
+        if (k.n == 0) bad = "empty key set";
+        else if (leaf < 1 || leaf > kMaxLeaf) bad = "leaf size outside [1, 24]";
+        else if (bucket == 0) bad = "bucket size must be positive";
+        else if (!k.data) bad = "NULL key data";
+        else if (k.kind != RS_KEYS_U64 && k.kind != RS_KEYS_BYTES) bad = "unknown key kind";
+        else if (k.kind == RS_KEYS_BYTES && !k.offsets) bad = "NULL offsets for byte keys";
+        if (bad) {
+            st[c] = RS_EINVAL;
+            why[c] = bad;
+            continue;
+        }
+        BuildDesc d{};
+        d.data = k.data;
+        d.offsets = k.offsets;
+        d.n = k.n;
+        d.key_base = total;
+        d.nb = (k.n + bucket - 1) / bucket;
+        d.bucket_base = nbuckets;
+        d.kind = k.kind;
+        const Strategy sg = make_strategy(leaf);
+        d.leaf = leaf;
+        d.lower = sg.lower;
+        d.upper = sg.upper;
+        uint32_t t = 0;
+        while (t < leaf_of_tab.size() && leaf_of_tab[t] != leaf) t++;
+        if (t == leaf_of_tab.size()) leaf_of_tab.push_back(leaf);
+        d.tab = t;
+        d.aligned = ((uintptr_t)k.data & 7) == 0;
+        d.delta_s = ~0ull;
+        d.delta_z = 0x7fffffffffffffffll;
+        total += d.n;
+        nbuckets += d.nb;
+        max_leaf = std::max(max_leaf, leaf);
+        hd.push_back(d);
+        which.push_back(c);
+    }
+    auto finish = [&](int rc) {
+        int first = RS_OK;
+        for (uint32_t c = 0; c < count; c++) {
+            if (statuses) statuses[c] = st[c];
+            if (st[c] != RS_OK && first == RS_OK) {
+                first = st[c];
+                fail(st[c], "build %u: %s", c, why[c].c_str());
+            }
+        }
+        return rc != RS_OK ? rc : first;
+    };
+    if (hd.empty()) return finish(RS_OK);
+    if (nbuckets >= (1ull << 32)) return fail(RS_EINVAL, "too many buckets in one call");
+    const uint32_t K = (uint32_t)hd.size();
+    RS_TRACE("build call: %u builds, %llu keys, %llu buckets", K, (unsigned long long)total,
+             (unsigned long long)nbuckets);
+
     PhaseEvents pe;
     if (int rc0 = pe.create(timing)) return rc0;
 
     // workspace
-    const uint64_t ntiles_n = (n + kScanTile - 1) / kScanTile + 1;
-    const uint64_t ntiles_b = (nb + 1 + kScanTile - 1) / kScanTile + 1;
+    const uint64_t ntiles = (nbuckets + 1 + kScanTile - 1) / kScanTile + 1;
     size_t off = 0;
     auto carve = [&](size_t bytes) {
         size_t o = off;
         off += (bytes + 255) & ~size_t(255);
         return o;
     };
-    const size_t o_lo = carve(n * 8), o_bid = carve(n * 4), o_cnt = carve(nb * 4), o_cur = carve(nb * 4);
-    const size_t o_bst = carve((nb + 1) * 8), o_sorted = carve(n * 8), o_tmp = carve(n * 8), o_seeds = carve(n * 8);
-    const size_t o_blen = carve(nb * 8), o_ost = carve((nb + 1) * 8);
-    const size_t o_tiles = carve(std::max(ntiles_n, ntiles_b) * 8), o_st = carve(sizeof(DevStatus));
+    const size_t o_lo = carve(total * 8), o_bid = carve(total * 4), o_cnt = carve(nbuckets * 4),
+                 o_cur = carve(nbuckets * 4), o_bst = carve((nbuckets + 1) * 8), o_sorted = carve(total * 8),
+                 o_tmp = carve(total * 8), o_seeds = carve(total * 8), o_blen = carve(nbuckets * 8),
+                 o_ost = carve((nbuckets + 1) * 8), o_tiles = carve(ntiles * 8), o_st = carve(sizeof(DevStatus)),
+                 o_desc = carve(K * sizeof(BuildDesc)), o_kb = carve(3 * (K + 1) * 8),
+                 o_hdr = carve((size_t)K * kHeaderWords * 8);
     char* ws = nullptr;
-    if (int rc = dev_alloc((void**)&ws, off, s)) return rc;
+    if (int rc0 = dev_alloc((void**)&ws, off, s)) return rc0;
     uint64_t* d_lo = (uint64_t*)(ws + o_lo);
     uint32_t* d_bid = (uint32_t*)(ws + o_bid);
     uint32_t* d_cnt = (uint32_t*)(ws + o_cnt);
@@ -951,11 +1172,16 @@ int build_impl(const rs_keys* keys, uint32_t leaf, uint32_t bucket, const rs_opt
     uint64_t* d_ost = (uint64_t*)(ws + o_ost);
     uint64_t* d_tiles = (uint64_t*)(ws + o_tiles);
     DevStatus* d_st = (DevStatus*)(ws + o_st);
+    BuildDesc* d_desc = (BuildDesc*)(ws + o_desc);
+    uint64_t* d_kb = (uint64_t*)(ws + o_kb);  // key, bucket and entry bases, contiguous like the host copy
+    uint64_t* d_bb = d_kb + (K + 1);
+    uint64_t* d_eb = d_bb + (K + 1);
+    uint64_t* d_hdr = (uint64_t*)(ws + o_hdr);
     uint32_t* d_tab = nullptr;
     uint64_t* d_blob = nullptr;
-    int rc = RS_OK;
 
     auto cleanup = [&](int code) {
+        pinned_release(s);
         dev_free(ws, s);
         if (code != RS_OK) {
             dev_free(d_tab, s);
@@ -963,145 +1189,242 @@ int build_impl(const rs_keys* keys, uint32_t leaf, uint32_t bucket, const rs_opt
         }
         return code;
     };
-#define RS_TRY(call)                                                          \
-    do {                                                                      \
-        hipError_t e_ = (call);                                               \
-        if (e_ != hipSuccess)                                                 \
-            return cleanup(fail(RS_EDEVICE, "%s: %s", #call, hipGetErrorString(e_))); \
+#define RS_TRY(call)                                                                            \
+    do {                                                                                        \
+        hipError_t e_ = (call);                                                                 \
+        if (e_ != hipSuccess)                                                                   \
+            return cleanup(fail(RS_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)));          \
     } while (0)
 
-    pe.record(0, s);
-    k_init_status<<<1, 64, 0, s>>>(d_st);
-    k_fill_u32<<<grid_for(nb, kBlock * 4), kBlock, 0, s>>>(d_cnt, nb, 0);
-    k_fill_u32<<<grid_for(nb, kBlock * 4), kBlock, 0, s>>>(d_cur, nb, 0);
-    if (keys->kind == RS_KEYS_U64) {
-        k_signature_u64<<<grid_for(n, kBlock), kBlock, 0, s>>>((const uint64_t*)keys->data, n, nb, d_lo, d_bid,
-                                                               d_cnt);
-    } else {
-        bool aligned = ((uintptr_t)keys->data & 7) == 0;
-        k_signature_bytes<<<grid_for(n, kBlock), kBlock, 0, s>>>((const uint8_t*)keys->data, keys->offsets, n,
-                                                                 nb, aligned, d_lo, d_bid, d_cnt, d_st);
+    // descriptors and bases to the device through pinned staging
+    const size_t desc_bytes = K * sizeof(BuildDesc);
+    const size_t stage_bytes = desc_bytes + 3 * (K + 1) * 8 + (size_t)K * kHeaderWords * 8 + sizeof(DevStatus);
+    char* pin = (char*)pinned(stage_bytes);
+    if (!pin) return cleanup(fail(RS_ENOMEM, "pinned host allocation failed"));
+    uint64_t* h_kb = (uint64_t*)(pin + desc_bytes);
+    uint64_t* h_bb = h_kb + (K + 1);
+    uint64_t* h_eb = h_bb + (K + 1);
+    uint64_t* h_hdr = h_eb + (K + 1);
+    DevStatus* h_st = (DevStatus*)(h_hdr + (size_t)K * kHeaderWords);
+    memcpy(pin, hd.data(), desc_bytes);
+    for (uint32_t j = 0; j < K; j++) {
+        h_kb[j] = hd[j].key_base;
+        h_bb[j] = hd[j].bucket_base;
+        h_eb[j] = hd[j].bucket_base + j;
     }
+    h_kb[K] = total;
+    h_bb[K] = nbuckets;
+    h_eb[K] = nbuckets + K;
+    pe.record(0, s);
+    RS_TRY(hipMemcpyAsync(d_desc, pin, desc_bytes, hipMemcpyHostToDevice, s));
+    RS_TRY(hipMemcpyAsync(d_kb, h_kb, 3 * (K + 1) * 8, hipMemcpyHostToDevice, s));
+    k_init_status<<<1, 64, 0, s>>>(d_st);
+    k_fill_u32<<<grid_for(nbuckets, kBlock * 4), kBlock, 0, s>>>(d_cnt, nbuckets, 0);
+    k_fill_u32<<<grid_for(nbuckets, kBlock * 4), kBlock, 0, s>>>(d_cur, nbuckets, 0);
+    k_signature<<<grid_for(total, kBlock), kBlock, 0, s>>>(d_desc, d_desc, d_kb, K, total, d_lo, d_bid, d_cnt);
     RS_TRY(hipGetLastError());
-    if ((rc = scan<uint32_t>(d_cnt, nb, d_bst, d_tiles, &d_st->maxm, s))) return cleanup(rc);
-    RS_TRY(hipMemcpyAsync(&pin->st, d_st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+    if (int rc = scan<uint32_t>(d_cnt, nbuckets, d_bst, d_tiles, &d_st->maxm, s)) return cleanup(rc);
+    RS_TRY(hipMemcpyAsync(h_st, d_st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+    RS_TRY(hipMemcpyAsync(pin, d_desc, desc_bytes, hipMemcpyDeviceToHost, s));
+    RS_TRACE("signatures enqueued; waiting for the largest bucket");
     RS_TRY(hipStreamSynchronize(s));
-    if (pin->st.flags & kFlagOffsets) return cleanup(fail(RS_EINVAL, "byte-key offsets are not monotone"));
-    const uint32_t maxm = pin->st.maxm;
-    // per-size tables
-    TableView tv = host_tables(leaf, maxm);
-    if (!tv.data) return cleanup(fail(RS_ENOMEM, "table allocation failed"));
+    BuildDesc* hdesc = (BuildDesc*)pin;
+    for (uint32_t j = 0; j < K; j++)
+        if (hdesc[j].flags & kFlagOffsets) {
+            st[which[j]] = RS_EINVAL;
+            why[which[j]] = "byte-key offsets are not monotone";
+        }
+    const uint32_t maxm = h_st->maxm;
+    RS_TRACE("largest bucket %u", maxm);
+
+    // per-size tables of every leaf size in the call, one block of 4 arrays each
+    const uint32_t stride = maxm + 1;
+    const uint32_t ntab = (uint32_t)leaf_of_tab.size();
+    if (int rc = dev_alloc((void**)&d_tab, (size_t)ntab * kTableCount * stride * 4, s)) return cleanup(rc);
+    uint32_t max_nodes = 0;
+    for (uint32_t t = 0; t < ntab; t++) {
+        TableView tv = host_tables(leaf_of_tab[t], maxm);
+        if (!tv.data) return cleanup(fail(RS_ENOMEM, "table allocation failed"));
+        max_nodes = std::max(max_nodes, tv.N()[maxm]);
+        uint32_t* dst = d_tab + (size_t)t * kTableCount * stride;
+        RS_TRY(hipMemcpyAsync(dst, tv.r(), stride * 4ull, hipMemcpyHostToDevice, s));
+        RS_TRY(hipMemcpyAsync(dst + stride, tv.F(), stride * 4ull, hipMemcpyHostToDevice, s));
+        RS_TRY(hipMemcpyAsync(dst + 2 * stride, tv.N(), stride * 4ull, hipMemcpyHostToDevice, s));
+        RS_TRY(hipMemcpyAsync(dst + 3 * stride, tv.G(), stride * 4ull, hipMemcpyHostToDevice, s));
+    }
     // keys + node slots in dynamic LDS; the static part (queues, thresholds) is below 16 KiB
-    if ((uint64_t)maxm * 8 + (uint64_t)tv.N()[maxm] * 16 + 16384 > (uint64_t)max_lds_bytes())
+    const size_t lds = (size_t)maxm * 8 + (size_t)max_nodes * 16;
+    if (lds + 16384 > (size_t)max_lds_bytes())
         return cleanup(fail(RS_EINVAL, "largest bucket (%u keys) exceeds the local data share", maxm));
-    if ((rc = dev_alloc((void**)&d_tab, (size_t)kTableCount * (maxm + 1) * 4, s))) return cleanup(rc);
-    RS_TRY(hipMemcpyAsync(d_tab, tv.r(), (maxm + 1) * 4ull, hipMemcpyHostToDevice, s));
-    RS_TRY(hipMemcpyAsync(d_tab + (maxm + 1), tv.F(), (maxm + 1) * 4ull, hipMemcpyHostToDevice, s));
-    RS_TRY(hipMemcpyAsync(d_tab + 2 * (maxm + 1), tv.N(), (maxm + 1) * 4ull, hipMemcpyHostToDevice, s));
-    RS_TRY(hipMemcpyAsync(d_tab + 3 * (maxm + 1), tv.G(), (maxm + 1) * 4ull, hipMemcpyHostToDevice, s));
 
     pe.record(1, s);
-    k_scatter<<<grid_for(n, kBlock), kBlock, 0, s>>>(d_lo, d_bid, n, d_bst, d_cur, d_sorted);
-    const uint32_t stage_from = opts && opts->stage_from ? opts->stage_from : 9;
-    const uint32_t group_max = opts && opts->group_max ? opts->group_max - 1 : 6;
-    SearchArgs sa{d_sorted, d_tmp, d_bst, d_seeds, d_blen, d_tab, d_tab + 2 * (maxm + 1), d_tab + 3 * (maxm + 1),
-                  d_st, cap, leaf, st.lower, st.upper, stage_from, group_max, maxm};
+    k_scatter<<<grid_for(total, kBlock), kBlock, 0, s>>>(d_lo, d_bid, total, d_bst, d_cur, d_sorted);
     pe.record(2, s);
-    const size_t lds = (size_t)maxm * 8 + (size_t)tv.N()[maxm] * 16;
-    if (leaf <= 8) k_search<8, 1><<<(uint32_t)nb, 64, lds, s>>>(sa);
-    else if (leaf <= 12) k_search<12, 4><<<(uint32_t)nb, 256, lds, s>>>(sa);
-    else if (leaf <= 16) k_search<16, 4><<<(uint32_t)nb, 256, lds, s>>>(sa);
-    else k_search<24, 4><<<(uint32_t)nb, 256, lds, s>>>(sa);
+    SearchArgs sa{d_sorted, d_tmp, d_bst, d_seeds, d_blen, d_desc, d_desc, d_bb, K, nbuckets,
+                  d_tab, stride, cap, stage_from, group_max, maxm};
+    int rc = RS_OK;
+    if (max_leaf <= 8) rc = launch_search<8, 1>(sa, lds, s);
+    else if (max_leaf <= 12) rc = launch_search<12, 4>(sa, lds, s);
+    else if (max_leaf <= 16) rc = launch_search<16, 4>(sa, lds, s);
+    else rc = launch_search<24, 4>(sa, lds, s);
+    if (rc) return cleanup(rc);
     pe.record(3, s);
-    RS_TRY(hipGetLastError());
-    if ((rc = scan<uint64_t>(d_blen, nb, d_ost, d_tiles, nullptr, s))) return cleanup(rc);
-    k_ef_gaps<<<grid_for(nb, kBlock), kBlock, 0, s>>>(d_bst, d_ost, nb, n, d_st);
+    if ((rc = scan<uint64_t>(d_blen, nbuckets, d_ost, d_tiles, nullptr, s))) return cleanup(rc);
+    GapArgs ga{d_bst, d_ost, d_desc, d_desc, d_bb, K, nbuckets};
+    k_ef_gaps<<<grid_for(nbuckets, kBlock), kBlock, 0, s>>>(ga);
     pe.record(4, s);
     RS_TRY(hipGetLastError());
-    RS_TRY(hipMemcpyAsync(&pin->st, d_st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
-    RS_TRY(hipMemcpyAsync(&pin->total_bits, d_ost + nb, 8, hipMemcpyDeviceToHost, s));
+    RS_TRY(hipMemcpyAsync(pin, d_desc, desc_bytes, hipMemcpyDeviceToHost, s));
+    RS_TRACE("search enqueued (class %u); waiting for the sizes", max_leaf);
     RS_TRY(hipStreamSynchronize(s));
-    const uint32_t flags = pin->st.flags;
-    if (flags & kFlagDuplicate) return cleanup(fail(RS_EDUPLICATE, "duplicate keys (equal signatures)"));
-    if (flags & kFlagSearch) return cleanup(fail(RS_ESEARCH, "an index search reached the seed cap"));
-    if (flags & kFlagStack) return cleanup(fail(RS_EDEVICE, "splitting tree deeper than supported"));
+    RS_TRACE("sizes known");
 
-    // blob geometry
-    const uint64_t total_bits = pin->total_bits;
-    const uint64_t beta = (total_bits << 16) / n;
-    const uint64_t delta_s = pin->st.delta_s;
-    const int64_t delta_z = pin->st.delta_z;
-    const uint64_t N = nb + 1;
-    const uint64_t ys_last = n - nb * delta_s;
-    const int64_t z_last = (int64_t)total_bits - (int64_t)((beta * n) >> 16);
-    const uint64_t yz_last = (uint64_t)(z_last - (int64_t)nb * delta_z);
-    const uint32_t Ws = ef_width(N, ys_last), Wz = ef_width(N, yz_last);
-    const uint64_t us_words = ((ys_last >> Ws) + N + 63) / 64, uz_words = ((yz_last >> Wz) + N + 63) / 64;
-    const uint64_t lower_words = (N * (Ws + Wz) + 63) / 64 + 1;
-    const uint64_t ninv = (N + (1u << kInvShift) - 1) >> kInvShift;
-    const uint64_t tree_words = (total_bits + 63) / 64 + 1;
-    const uint64_t total_words = kHeaderWords + lower_words + us_words + uz_words + 2 * ninv + tree_words;
-    if ((rc = dev_alloc((void**)&d_blob, total_words * 8, s))) return cleanup(rc);
-    k_fill_u64<<<grid_for(total_words, kBlock * 8), kBlock, 0, s>>>(d_blob, total_words, 0);
-
-    rs_blob* blob = new (std::nothrow) rs_blob;
-    if (!blob) return cleanup(fail(RS_ENOMEM, "host allocation failed"));
-    uint64_t* h = blob->header;
-    h[0] = kMagic;
-    h[1] = kVersion | ((uint64_t)keys->kind << 32);
-    h[2] = n; h[3] = leaf; h[4] = bucket; h[5] = nb; h[6] = maxm;
-    h[7] = (uint64_t)Ws | ((uint64_t)Wz << 8);
-    h[8] = delta_s; h[9] = (uint64_t)delta_z; h[10] = beta;
-    h[11] = us_words; h[12] = uz_words; h[13] = lower_words; h[14] = tree_words; h[15] = total_bits;
-    Layout L = layout_of(h);
-    FillArgs fa{d_bst, d_ost, d_seeds, d_tab, d_tab + (maxm + 1), (unsigned long long*)d_blob, nb, beta,
-                delta_s, delta_z, Ws, Wz, L.lower_off, L.us_off, L.uz_off, L.invs_off, L.invz_off, L.tree_off,
-                leaf, st.lower, st.upper};
-    k_write_header<<<1, 64, 0, s>>>(d_blob, h[0], h[1], h[2], h[3], h[4], h[5], h[6], h[7], h[8], h[9], h[10],
-                                    h[11], h[12], h[13], h[14], h[15]);
-    k_ef_fill<<<grid_for(N, kBlock), kBlock, 0, s>>>(fa);
-    k_tree_bits<<<grid_for(nb, 64), 64, 0, s>>>(fa);
-    pe.record(5, s);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) {
-        delete blob;
-        return cleanup(fail(RS_EDEVICE, "launch failed: %s", hipGetErrorString(e)));
-    }
-    if (timing) {
-        if (hipStreamSynchronize(s) != hipSuccess) {
-            delete blob;
-            return cleanup(fail(RS_EDEVICE, "stream synchronisation failed"));
+    // blob geometry of every successful build
+    std::vector<uint64_t> blob_off(K, 0), blob_words(K, 0);
+    uint64_t arena_words = 0;
+    for (uint32_t j = 0; j < K; j++) {
+        BuildDesc& d = hdesc[j];
+        const uint32_t c = which[j];
+        if (st[c] == RS_OK) {
+            if (d.flags & kFlagDuplicate) {
+                st[c] = RS_EDUPLICATE;
+                why[c] = "duplicate keys (equal signatures)";
+            } else if (d.flags & kFlagSearch) {
+                st[c] = RS_ESEARCH;
+                why[c] = "an index search reached the seed cap";
+            } else if (d.flags & kFlagStack) {
+                st[c] = RS_EDEVICE;
+                why[c] = "search scheduling failed";
+            }
         }
+        d.blob = nullptr;
+        if (st[c] != RS_OK) continue;
+        const uint64_t n = d.n, nb = d.nb, N = nb + 1, bits = d.total_bits;
+        const uint64_t beta = (bits << 16) / n;
+        const uint64_t ys_last = n - nb * d.delta_s;
+        const int64_t z_last = (int64_t)bits - (int64_t)((beta * n) >> 16);
+        const uint64_t yz_last = (uint64_t)(z_last - (int64_t)nb * d.delta_z);
+        const uint32_t Ws = ef_width(N, ys_last), Wz = ef_width(N, yz_last);
+        uint64_t* h = h_hdr + (size_t)j * kHeaderWords;
+        h[0] = kMagic;
+        h[1] = kVersion | ((uint64_t)d.kind << 32);
+        h[2] = n; h[3] = d.leaf; h[4] = buckets[c]; h[5] = nb; h[6] = d.maxm;
+        h[7] = (uint64_t)Ws | ((uint64_t)Wz << 8);
+        h[8] = d.delta_s; h[9] = (uint64_t)d.delta_z; h[10] = beta;
+        h[11] = ((ys_last >> Ws) + N + 63) / 64;
+        h[12] = ((yz_last >> Wz) + N + 63) / 64;
+        h[13] = (N * (Ws + Wz) + 63) / 64 + 1;
+        h[14] = (bits + 63) / 64 + 1;
+        h[15] = bits;
+        Layout L = layout_of(h);
+        d.beta = beta;
+        d.Ws = Ws;
+        d.Wz = Wz;
+        d.lower_off = L.lower_off;
+        d.us_off = L.us_off;
+        d.uz_off = L.uz_off;
+        d.invs_off = L.invs_off;
+        d.invz_off = L.invz_off;
+        d.tree_off = L.tree_off;
+        blob_off[j] = arena_words;
+        blob_words[j] = L.total_words;
+        arena_words += (L.total_words + 31) & ~uint64_t(31);  // 256-byte aligned blobs
+    }
+    if (arena_words) {
+        if ((rc = dev_alloc((void**)&d_blob, arena_words * 8, s))) return cleanup(rc);
+        for (uint32_t j = 0; j < K; j++)
+            if (st[which[j]] == RS_OK) hdesc[j].blob = (unsigned long long*)(d_blob + blob_off[j]);
+        RS_TRY(hipMemcpyAsync(d_desc, pin, desc_bytes, hipMemcpyHostToDevice, s));
+        RS_TRY(hipMemcpyAsync(d_hdr, h_hdr, (size_t)K * kHeaderWords * 8, hipMemcpyHostToDevice, s));
+        k_fill_u64<<<grid_for(arena_words, kBlock * 8), kBlock, 0, s>>>(d_blob, arena_words, 0);
+        k_write_headers<<<grid_for((uint64_t)K * kHeaderWords, kBlock), kBlock, 0, s>>>(d_desc, d_hdr, K);
+        FillArgs fa{d_bst, d_ost, d_seeds, d_desc, d_bb, d_eb, K, nbuckets, d_tab, stride};
+        k_ef_fill<<<grid_for(nbuckets + K, kBlock), kBlock, 0, s>>>(fa);
+        k_tree_bits<<<grid_for(nbuckets, 64), 64, 0, s>>>(fa);
+        RS_TRY(hipGetLastError());
+    }
+    pe.record(5, s);
+    RS_TRACE("fill enqueued (%llu blob words)", (unsigned long long)arena_words);
+    if (timing) {
+        RS_TRY(hipStreamSynchronize(s));
         g_stats.ms_signature = pe.ms(0, 1);
         g_stats.ms_scatter = pe.ms(1, 2);
         g_stats.ms_search = pe.ms(2, 3);
         g_stats.ms_offsets = pe.ms(3, 4);
         g_stats.ms_fill = pe.ms(4, 5);
         g_stats.ms_device = pe.ms(0, 5);
-        g_stats.n = n;
-        g_stats.nb = nb;
+        g_stats.n = total;
+        g_stats.nb = nbuckets;
         g_stats.maxm = maxm;
-        g_stats.tree_bits = total_bits;
-        g_stats.blob_bytes = total_words * 8;
+        g_stats.tree_bits = 0;
+        for (uint32_t j = 0; j < K; j++) g_stats.tree_bits += hdesc[j].total_bits;
+        g_stats.blob_bytes = arena_words * 8;
         g_stats_valid = true;
     }
-    blob->words = d_blob;
-    blob->bytes = total_words * 8;
-    blob->tables = d_tab;
-    blob->stream = s;
-    (void)hipGetDevice(&blob->device);
-    cleanup(RS_OK);
-    *out = blob;
-    return RS_OK;
+
+    // blobs share the arena (and the tables); the last one released frees them
+    BlobArena* arena = nullptr;
+    uint32_t made = 0;
+    for (uint32_t j = 0; j < K; j++) made += st[which[j]] == RS_OK;
+    if (made) {
+        arena = new (std::nothrow) BlobArena;
+        if (!arena) return cleanup(fail(RS_ENOMEM, "host allocation failed"));
+        arena->words = d_blob;
+        arena->tables = d_tab;
+        arena->stream = s;
+        arena->refs = (int)made;
+    } else {
+        dev_free(d_tab, s);
+        d_tab = nullptr;
+    }
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    for (uint32_t j = 0; j < K; j++) {
+        const uint32_t c = which[j];
+        outs[c] = nullptr;
+        if (st[c] != RS_OK) continue;
+        rs_blob* b = new (std::nothrow) rs_blob;
+        if (!b) {
+            st[c] = RS_ENOMEM;
+            why[c] = "host allocation failed";
+            release_arena(arena);
+            continue;
+        }
+        b->words = d_blob + blob_off[j];
+        b->bytes = blob_words[j] * 8;
+        b->tables = d_tab + (size_t)hdesc[j].tab * kTableCount * stride;
+        b->tab_stride = stride;
+        memcpy(b->header, h_hdr + (size_t)j * kHeaderWords, sizeof b->header);
+        b->stream = s;
+        b->device = dev;
+        b->arena = arena;
+        outs[c] = b;
+    }
+    for (uint32_t c = 0; c < count; c++)
+        if (st[c] != RS_OK) outs[c] = nullptr;
+    pinned_release(s);
+    dev_free(ws, s);
+    return finish(RS_OK);
 #undef RS_TRY
 }
 
 }  // namespace rs
 
+extern "C" int rs_build_batch(const rs_keys* sets, uint32_t count, const uint32_t* leaf, const uint32_t* bucket,
+                              const rs_options* opts, void* stream, rs_blob** outs, int* per_build_status) {
+    rs::clear_error();
+    return rs::build_batch_impl(sets, count, leaf, bucket, opts, (hipStream_t)stream, outs, per_build_status);
+}
+
 extern "C" int rs_build_ex(const rs_keys* keys, uint32_t leaf, uint32_t bucket, const rs_options* opts, void* stream,
                            rs_blob** out) {
     rs::clear_error();
-    return rs::build_impl(keys, leaf, bucket, opts, (hipStream_t)stream, out);
+    if (!keys || !out) return rs::fail(RS_EINVAL, "NULL argument");
+    rs_blob* b = nullptr;
+    int status = RS_OK;
+    int rc = rs::build_batch_impl(keys, 1, &leaf, &bucket, opts, (hipStream_t)stream, &b, &status);
+    if (rc == RS_OK) *out = b;
+    return rc;
 }
 
 extern "C" int rs_last_build_stats(rs_build_stats* out) {

@@ -10,13 +10,20 @@
 
 #include "rs_internal.h"
 
+namespace rs {
+struct BlobArena;
+void release_arena(BlobArena* a);
+}  // namespace rs
+
 struct rs_blob {
     uint64_t* words = nullptr;   // serialized structure on the device
     uint64_t bytes = 0;
-    uint32_t* tables = nullptr;  // device r, F, N for sizes 0..maxm (3 * (maxm + 1) u32)
+    uint32_t* tables = nullptr;  // device r, F, N for sizes 0..tab_stride-1, tab_stride words each
+    uint32_t tab_stride = 0;
     uint64_t header[rs::kHeaderWords] = {};
     hipStream_t stream = nullptr;
     int device = 0;
+    rs::BlobArena* arena = nullptr;  // shared with the other blobs of one build call (null: own memory)
 };
 
 namespace rs {

@@ -80,8 +80,9 @@ def lib() -> ctypes.CDLL:
         L.rs_version.restype = ctypes.c_char_p
         L.rs_tables.argtypes = [U32, U32, P, P, P]
         L.rs_last_build_stats.argtypes = [ctypes.POINTER(rs_build_stats)]
+        L.rs_build_batch.argtypes = [ctypes.POINTER(rs_keys), U32, P, P, ctypes.POINTER(rs_options), P, P, P]
         for f in ("rs_build", "rs_build_ex", "rs_lookup", "rs_blob_to_host", "rs_blob_from_host", "rs_blob_info",
-                  "rs_tables", "rs_last_build_stats"):
+                  "rs_tables", "rs_last_build_stats", "rs_build_batch"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -171,6 +172,30 @@ def build(keys, leaf: int, bucket: int, seed_cap: int = 0, timing: bool = False,
     opts = rs_options(seed_cap, RS_OPT_TIMING if timing else 0, stage_from, group_max)
     _check(lib().rs_build_ex(ctypes.byref(k), leaf, bucket, ctypes.byref(opts), _stream(stream), ctypes.byref(h)))
     return Blob(h)
+
+
+def build_batch(key_sets, leafs, buckets, seed_cap: int = 0, timing: bool = False, stage_from: int = 0,
+                group_max: int = 0, stream=None):
+    """Build many MPHFs in one call.  Returns (blobs, statuses): blobs[i] is a
+    Blob or None when statuses[i] != RS_OK.  Raises only when the call itself
+    fails (no build could be attempted)."""
+    count = len(key_sets)
+    if isinstance(leafs, int):
+        leafs = [leafs] * count
+    if isinstance(buckets, int):
+        buckets = [buckets] * count
+    arr = (rs_keys * count)(*[_as_keys(k) for k in key_sets])
+    lf = np.ascontiguousarray(leafs, dtype=np.uint32)
+    bk = np.ascontiguousarray(buckets, dtype=np.uint32)
+    outs = (ctypes.c_void_p * count)()
+    status = np.zeros(count, dtype=np.int32)
+    opts = rs_options(seed_cap, RS_OPT_TIMING if timing else 0, stage_from, group_max)
+    rc = lib().rs_build_batch(arr, count, lf.ctypes.data, bk.ctypes.data, ctypes.byref(opts), _stream(stream),
+                              ctypes.cast(outs, ctypes.c_void_p), status.ctypes.data)
+    blobs = [Blob(ctypes.c_void_p(outs[i])) if outs[i] else None for i in range(count)]
+    if rc != RS_OK and not any(b is not None for b in blobs) and not status.any():
+        _check(rc)
+    return blobs, [int(x) for x in status]
 
 
 def lookup(blob: Blob, keys, out=None, stream=None):

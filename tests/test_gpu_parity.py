@@ -155,3 +155,40 @@ def test_seed_cap_boundary(rs, orc, n, leaf):
         with pytest.raises(rs.RecSplitError) as e:
             rs.build(rs.device_keys(keys), leaf, 1000, seed_cap=vmax)
         assert e.value.code == rs.RS_ESEARCH
+
+
+def test_batch_blobs_equal_oracle(rs, orc):
+    """One batched call over uneven builds (sizes, leaf sizes, bucket sizes and
+    key kinds differ) returns each build's oracle bytes."""
+    specs = [(1000, 8, 100, "u64"), (1, 8, 100, "u64"), (7777, 12, 1000, "u64"), (2500, 8, 100, "ascii"),
+             (300, 5, 5, "u64"), (20000, 8, 100, "u64"), (4000, 16, 2000, "u64"), (50, 1, 7, "ascii"),
+             (12345, 12, 9, "u64")]
+    host = [inputs.u64_keys(n, 300 + i) if kind == "u64" else inputs.ascii_keys(n, 300 + i)
+            for i, (n, _, _, kind) in enumerate(specs)]
+    print("case batch of", len(specs), flush=True)
+    blobs, status = rs.build_batch([rs.device_keys(k) for k in host], [s[1] for s in specs], [s[2] for s in specs])
+    assert status == [0] * len(specs)
+    for (n, leaf, bucket, _), k, b in zip(specs, host, blobs):
+        want = orc.build(k, leaf, bucket)
+        assert b.to_bytes() == want, (n, leaf, bucket)
+        ranks = rs.lookup(b, rs.device_keys(k)).cpu().numpy().view(np.uint64)
+        assert np.array_equal(ranks, orc.lookup(want, k))
+    for b in blobs:
+        b.free()
+
+
+def test_batch_isolates_failed_builds(rs, orc):
+    good = inputs.u64_keys(3000, 41)
+    dup = np.concatenate([inputs.u64_keys(500, 42), inputs.u64_keys(500, 42)[:1]])
+    import torch
+
+    empty = torch.zeros(0, dtype=torch.int64, device="cuda")
+    print("case batch with failures", flush=True)
+    blobs, status = rs.build_batch([rs.device_keys(good), rs.device_keys(dup), empty, rs.device_keys(good)],
+                                   [8, 8, 8, 25], [100, 100, 100, 100])
+    assert status == [rs.RS_OK, rs.RS_EDUPLICATE, rs.RS_EINVAL, rs.RS_EINVAL]
+    assert blobs[1] is None and blobs[2] is None and blobs[3] is None
+    assert blobs[0].to_bytes() == orc.build(good, 8, 100)
+    # the surviving blob outlives the others of its call
+    del blobs[1:]
+    assert blobs[0].to_bytes() == orc.build(good, 8, 100)
