@@ -75,6 +75,9 @@ def main():
     ap.add_argument("--l16-n", type=int, default=10_000_000, help="keys of the l=16, b=2000 build (0: skip)")
     ap.add_argument("--latency-builds", type=int, default=30, help="repeated 100,000-key builds for p50/p99")
     ap.add_argument("--cpu-sample", type=int, default=1_000_000, help="oracle sample size (0: skip)")
+    ap.add_argument("--workload", choices=["single", "batch"], default="single",
+                    help="single: 10M strings l=8 b=100 (+ l=16 point); batch: 4096 uneven builds, l=12 b=1000")
+    ap.add_argument("--batch-builds", type=int, default=4096)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (scales HBM byte counters) and exit")
     args = ap.parse_args()
@@ -101,6 +104,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     recsplit.lib()
+    if args.workload == "batch":
+        print(json.dumps(bench_batch(args)), flush=True)
+        return
     n, leaf, bucket = args.n, 8, 100
 
     log(f"[bench] generating {n:,} ASCII strings (seed 2) and the lookup order (seed 3)")
@@ -243,6 +249,79 @@ def main():
         result["cpu_baseline"]["host_cpu"] = _cpu_model()
 
     print(json.dumps(result), flush=True)
+
+
+def bench_batch(args):
+    """4096 independent builds of uniform random 64-bit keys, sizes log-uniform
+    in [1e3, 1e6], l=12, b=1000: one batched call against one call per build."""
+    import numpy as np
+    import torch
+
+    from paper_1910_06416_amd import inputs, recsplit
+
+    leaf, bucket = 12, 1000
+    sizes = inputs.log_uniform_sizes(args.batch_builds, 5, 1e3, 1e6)
+    log(f"[bench] batch: {len(sizes)} builds, {int(sizes.sum()):,} keys; generating keys")
+    rng_keys = inputs.u64_keys(int(sizes.sum()), 5)  # disjoint slices: every build's keys are distinct
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    dall = recsplit.device_keys(rng_keys)
+    sets = [dall[int(offs[i]):int(offs[i + 1])] for i in range(len(sizes))]
+    total = int(sizes.sum())
+    torch.cuda.synchronize()
+
+    # batched: warm-up on a small slice, then the timed call(s)
+    recsplit.build_batch(sets[:8], leaf, bucket)
+    times, stats = [], None
+    for k in range(max(1, args.steps)):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        blobs, status = recsplit.build_batch(sets, leaf, bucket, timing=True)
+        dt = time.perf_counter() - t0
+        stats = recsplit.last_build_stats()
+        assert all(x == 0 for x in status), "batched build failed"
+        times.append(dt)
+        log(f"[bench] batched call {k + 1}: {dt:.3f} s (search {stats['ms_search']:.1f} ms)")
+        bits = sum(b.nbytes for b in blobs) * 8 / total
+        # spot check: some builds' lookups are bijections
+        for i in list(range(0, len(sizes), max(1, len(sizes) // 16))):
+            r = recsplit.lookup(blobs[i], sets[i])
+            srt, _ = torch.sort(r)
+            assert torch.equal(srt, torch.arange(int(sizes[i]), dtype=torch.int64, device="cuda"))
+        for b in blobs:
+            b.free()
+        del blobs
+
+    # plain path: one rs_build call per build, in order
+    log("[bench] plain path: one call per build")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat = []
+    for i, s_ in enumerate(sets):
+        tb = time.perf_counter()
+        b = recsplit.build(s_, leaf, bucket)
+        torch.cuda.synchronize()
+        lat.append(time.perf_counter() - tb)
+        b.free()
+    plain = time.perf_counter() - t0
+    batched = float(np.mean(times))
+    alg = EVALS_PER_KEY[(leaf, bucket)] * total
+    ev = alg / (stats["ms_search"] * 1e-3)
+    return {
+        "metric": "keys/s built, 4096 uneven builds (batched vs one call per build)",
+        "value": total / batched, "unit": "keys/s", "n_gpus": 1, "steps": len(times), "warmup": 1,
+        "ms_per_step": batched * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"{len(sizes)} builds of uniform random 64-bit keys, sizes log-uniform in "
+                               f"[1e3, 1e6], l={leaf}, b={bucket}", "keys": total},
+        "batched_s": batched, "plain_s": plain, "speedup_vs_plain": plain / batched,
+        "plain_keys_per_s": total / plain, "bits_per_key": bits, "search_ms": stats["ms_search"],
+        "phase_ms": {k: stats[k] for k in ("ms_signature", "ms_scatter", "ms_search", "ms_offsets", "ms_fill")},
+        "plain_build_latency_ms": {"p50": percentile(lat, 50) * 1e3, "p99": percentile(lat, 99) * 1e3},
+        "roofline": {"kernel": "k_search", "bound": "alu", "achieved": ev * VALU_SLOTS_PER_EVAL / 1e12,
+                     "peak": VALU_PEAK_TOPS, "unit": "T lane-ops/s",
+                     "frac": ev * VALU_SLOTS_PER_EVAL / 1e12 / VALU_PEAK_TOPS, "traffic": None,
+                     "algorithmic_evals_per_launch": alg, "evals_per_s": ev},
+    }
 
 
 def _cpu_model():
