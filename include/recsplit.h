@@ -130,15 +130,16 @@ int rs_build_batch(const rs_keys* sets, uint32_t count, const uint32_t* leaf, co
  * deterministic value in [0, n] (n only when their bucket is the last one and
  * is empty), the same value the CPU reference computes.
  *   queries  : device key set of the same kind as the blob.
- *   ranks_dev: device uint64_t[queries->n], written asynchronously on stream.
+ *   ranks_dev: device uint64_t[queries->n], written asynchronously on stream (which
+ *              first waits for the blob's construction if that ran on another stream).
  * Errors: RS_EINVAL (NULL, kind mismatch), RS_EDEVICE. */
 int rs_lookup(const rs_blob* blob, const rs_keys* queries, uint64_t* ranks_dev, void* stream);
 
 /* Size in bytes of the serialized structure (header + Elias-Fano + trees). */
 uint64_t rs_blob_bytes(const rs_blob* blob);
 
-/* Copy the serialized structure to host memory dst (capacity cap bytes); waits for
- * the blob's construction stream.  Errors: RS_EINVAL (cap too small, NULL). */
+/* Copy the serialized structure to host memory dst (capacity cap bytes); waits until
+ * the blob is complete.  Errors: RS_EINVAL (cap too small, NULL). */
 int rs_blob_to_host(const rs_blob* blob, void* dst, uint64_t cap);
 
 /* Load a serialized structure from host memory into a new device blob.
@@ -151,11 +152,58 @@ const void* rs_blob_device_ptr(const rs_blob* blob);
 /* Number of keys, leaf size and bucket size the blob was built with. */
 int rs_blob_info(const rs_blob* blob, uint64_t* n, uint32_t* leaf, uint32_t* bucket);
 
-/* Release a blob (waits for its stream first). NULL is ignored. */
+/* Release a blob (waits until it is complete; blobs of one rs_build_batch call share
+ * one allocation, freed with the last of them).  NULL is ignored. */
 void rs_blob_free(rs_blob* blob);
 
 /* Message describing the last error of the calling thread ("" if none). */
 const char* rs_last_error(void);
+
+/* ---- Serving loop ---------------------------------------------------------------
+ * Build and lookup requests of uneven sizes arrive over time.  Build requests wait
+ * in first-in first-out order and are admitted when their estimated device
+ * footprint (about 56 bytes per key) fits in the free part of the budget (one is
+ * always admitted when nothing is in flight).  Each of `build_workers` workers owns
+ * a stream and runs every admissible waiting request as one rs_build_batch call, so
+ * requests that arrive while a batch is on the device overlap with it in the next
+ * worker's batch.  Lookups run on their own stream.  A request's result is the same
+ * as rs_build / rs_lookup on the same inputs.
+ * The caller keeps key and query buffers valid until the request completes. */
+typedef struct rs_server rs_server;
+
+typedef struct {
+    uint64_t batches, batched_requests, max_batch, max_concurrent_batches;
+    uint64_t peak_in_flight_bytes, budget_bytes;
+    uint32_t max_queue;
+} rs_server_stats;
+
+/* Start a server with a device-memory budget for builds in flight (bytes) and
+ * `build_workers` build streams (0 = 2, at most 8); opts as for rs_build_ex (its
+ * RS_OPT_TIMING flag is ignored). */
+int rs_server_create(uint64_t hbm_budget_bytes, uint32_t build_workers, const rs_options* opts, rs_server** out);
+
+/* Enqueue a build; *ticket identifies it.  Errors: RS_EINVAL, RS_EBUSY (stopping). */
+int rs_server_submit_build(rs_server* srv, const rs_keys* keys, uint32_t leaf, uint32_t bucket, uint64_t* ticket);
+
+/* Enqueue a lookup of queries against a built blob; ranks_dev as for rs_lookup. */
+int rs_server_submit_lookup(rs_server* srv, const rs_blob* blob, const rs_keys* queries, uint64_t* ranks_dev,
+                            uint64_t* ticket);
+
+/* Non-blocking: *done = 0 while running; when done, the request's status, its blob
+ * (builds; the caller then owns it), its latency (submission to completion, ms) and
+ * the number of requests of its batch are returned and the ticket is retired. */
+int rs_server_poll(rs_server* srv, uint64_t ticket, int* done, int* status, rs_blob** blob, double* latency_ms,
+                   uint32_t* batch_size);
+
+/* Blocking variant of rs_server_poll. */
+int rs_server_wait(rs_server* srv, uint64_t ticket, int* status, rs_blob** blob, double* latency_ms,
+                   uint32_t* batch_size);
+
+int rs_server_get_stats(rs_server* srv, rs_server_stats* out);
+
+/* Finish every queued request, stop the workers and free the server (blobs that
+ * were never collected are freed). */
+void rs_server_destroy(rs_server* srv);
 
 /* Library version string. */
 const char* rs_version(void);

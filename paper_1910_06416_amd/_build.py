@@ -5,12 +5,12 @@ import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["csrc/build.hip", "csrc/api.hip", "csrc/tables.cpp"]
+SOURCES = ["csrc/build.hip", "csrc/api.hip", "csrc/tables.cpp", "csrc/server.cpp"]
 HEADERS = ["csrc/rs_internal.h", "csrc/rs_host.h", "../include/recsplit.h"]
 LIB = os.path.join(HERE, "librecsplit.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
-    "-O3", "--offload-arch=gfx950", "-fPIC", "-shared", "-std=c++17", "-Wall",
+    "-O3", "--offload-arch=gfx950", "-fPIC", "-shared", "-std=c++17", "-Wall", "-pthread",
     # no packed fp32 instructions anywhere in the library
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]

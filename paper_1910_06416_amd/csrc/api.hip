@@ -228,6 +228,7 @@ extern "C" int rs_lookup(const rs_blob* blob, const rs_keys* queries, uint64_t* 
                  L.invz_off, L.tree_off, L.us_words, L.uz_words, L.tree_words, (uint32_t)L.leaf, st.lower,
                  st.upper, (uint32_t)L.maxm};
     hipStream_t s = (hipStream_t)stream;
+    if (blob->ready) RS_HIP(hipStreamWaitEvent(s, blob->ready, 0));  // built on another stream
     const uint32_t block = 256;
     uint32_t grid = (uint32_t)((queries->n + block - 1) / block);
     if (queries->kind == RS_KEYS_U64)
@@ -256,7 +257,7 @@ extern "C" int rs_blob_to_host(const rs_blob* blob, void* dst, uint64_t cap) {
     if (!blob || !dst) return fail(RS_EINVAL, "NULL argument");
     if (cap < blob->bytes) return fail(RS_EINVAL, "buffer of %llu bytes is smaller than the blob (%llu)",
                                        (unsigned long long)cap, (unsigned long long)blob->bytes);
-    RS_HIP(hipStreamSynchronize(blob->stream));
+    if (blob->ready) RS_HIP(hipEventSynchronize(blob->ready));
     RS_HIP(hipMemcpy(dst, blob->words, blob->bytes, hipMemcpyDeviceToHost));
     return RS_OK;
 }
@@ -289,7 +290,7 @@ extern "C" int rs_blob_from_host(const void* src, uint64_t bytes, void* stream, 
     }
     b->bytes = bytes;
     b->tab_stride = (uint32_t)(L.maxm + 1);
-    b->stream = s;
+    b->ready = nullptr;  // complete: the copy above was waited for
     (void)hipGetDevice(&b->device);
     *out = b;
     return RS_OK;
@@ -300,10 +301,8 @@ extern "C" void rs_blob_free(rs_blob* blob) {
     if (blob->arena) {
         release_arena(blob->arena);
     } else {
-        (void)hipStreamSynchronize(blob->stream);
-        if (blob->words) (void)hipFreeAsync(blob->words, blob->stream);
-        if (blob->tables) (void)hipFreeAsync(blob->tables, blob->stream);
-        (void)hipStreamSynchronize(blob->stream);
+        if (blob->words) (void)hipFree(blob->words);
+        if (blob->tables) (void)hipFree(blob->tables);
     }
     delete blob;
 }

@@ -1032,20 +1032,21 @@ int launch_search(const SearchArgs& sa, size_t lds, hipStream_t s) {
 
 }  // namespace
 
-// Shared ownership of the device memory of the blobs of one call.
+// Shared ownership of the device memory of the blobs of one call.  Blobs may
+// outlive the stream they were built on, so they hold an event, not the stream.
 struct BlobArena {
     uint64_t* words = nullptr;
     uint32_t* tables = nullptr;
     std::atomic<int> refs{0};
-    hipStream_t stream = nullptr;
+    hipEvent_t ready = nullptr;
 };
 
 void release_arena(BlobArena* a) {
     if (a && a->refs.fetch_sub(1) == 1) {
-        (void)hipStreamSynchronize(a->stream);
-        if (a->words) (void)hipFreeAsync(a->words, a->stream);
-        if (a->tables) (void)hipFreeAsync(a->tables, a->stream);
-        (void)hipStreamSynchronize(a->stream);
+        if (a->ready) (void)hipEventSynchronize(a->ready);
+        if (a->words) (void)hipFree(a->words);
+        if (a->tables) (void)hipFree(a->tables);
+        if (a->ready) (void)hipEventDestroy(a->ready);
         delete a;
     }
 }
@@ -1371,8 +1372,13 @@ int build_batch_impl(const rs_keys* sets, uint32_t count, const uint32_t* leafs,
         if (!arena) return cleanup(fail(RS_ENOMEM, "host allocation failed"));
         arena->words = d_blob;
         arena->tables = d_tab;
-        arena->stream = s;
         arena->refs = (int)made;
+        if (hipEventCreateWithFlags(&arena->ready, hipEventDisableTiming) != hipSuccess ||
+            hipEventRecord(arena->ready, s) != hipSuccess) {
+            (void)hipStreamSynchronize(s);  // no event: the blobs are complete once the stream is
+            if (arena->ready) (void)hipEventDestroy(arena->ready);
+            arena->ready = nullptr;
+        }
     } else {
         dev_free(d_tab, s);
         d_tab = nullptr;
@@ -1395,7 +1401,7 @@ int build_batch_impl(const rs_keys* sets, uint32_t count, const uint32_t* leafs,
         b->tables = d_tab + (size_t)hdesc[j].tab * kTableCount * stride;
         b->tab_stride = stride;
         memcpy(b->header, h_hdr + (size_t)j * kHeaderWords, sizeof b->header);
-        b->stream = s;
+        b->ready = arena->ready;
         b->device = dev;
         b->arena = arena;
         outs[c] = b;

@@ -21,7 +21,7 @@ struct rs_blob {
     uint32_t* tables = nullptr;  // device r, F, N for sizes 0..tab_stride-1, tab_stride words each
     uint32_t tab_stride = 0;
     uint64_t header[rs::kHeaderWords] = {};
-    hipStream_t stream = nullptr;
+    hipEvent_t ready = nullptr;      // recorded after the last write of the blob (shared with the arena)
     int device = 0;
     rs::BlobArena* arena = nullptr;  // shared with the other blobs of one build call (null: own memory)
 };

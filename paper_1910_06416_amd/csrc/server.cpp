@@ -1,0 +1,287 @@
+// Serving loop: construction and lookup requests of uneven sizes arrive over
+// time and are run with continuous batching.
+//
+// Build requests wait in a first-in first-out queue.  A request is admitted
+// when its estimated device footprint fits in the free part of the budget (a
+// request is always admitted when nothing else is in flight, so an oversized
+// one cannot wait forever).  Each build worker owns a stream; when it is free
+// it takes every admissible request at the head of the queue and runs them as
+// one batched construction (rs_build_batch).  Requests that arrive while a
+// batch is on the device form the next worker's batch, so their work overlaps
+// on the device.  A lookup worker runs lookup requests on its own stream.  All
+// streams have the default priority.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "rs_host.h"
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+// Device bytes one build holds while in flight: the construction workspace
+// (signatures, bucket ids, scattered keys, partition scratch, indices: 48 B per
+// key), bucket arrays (~24 B per bucket) and the blob (< 1 B per key).
+uint64_t build_footprint(uint64_t n, uint32_t bucket) {
+    return 56 * n + 24 * (n / std::max<uint32_t>(bucket, 1) + 1) + (1u << 20);
+}
+
+struct Request {
+    uint64_t ticket;
+    bool is_build;
+    rs_keys keys;
+    uint32_t leaf = 0, bucket = 0;
+    const rs_blob* blob = nullptr;
+    uint64_t* ranks = nullptr;
+    uint64_t footprint = 0;
+    Clock::time_point arrival;
+};
+
+struct Result {
+    bool done = false;
+    int status = RS_OK;
+    rs_blob* blob = nullptr;
+    double latency_ms = 0;
+    uint32_t batch_size = 0;
+};
+
+}  // namespace
+
+struct rs_server {
+    std::mutex mu;
+    std::condition_variable cv_work;   // workers: new requests or freed budget
+    std::condition_variable cv_done;   // waiters: a request completed
+    std::deque<Request> builds, lookups;
+    std::unordered_map<uint64_t, Result> results;
+    uint64_t next_ticket = 1;
+    uint64_t budget = 0, in_flight = 0, peak_in_flight = 0;
+    uint64_t batches = 0, batched_requests = 0, max_batch = 0, concurrent = 0, max_concurrent = 0;
+    uint32_t max_queue = 0;
+    bool stopping = false;
+    int device = 0;
+    rs_options opts{};
+    std::vector<std::thread> workers;
+};
+
+namespace {
+
+void finish(rs_server* s, const Request& r, int status, rs_blob* blob, uint32_t batch_size) {
+    Result& res = s->results[r.ticket];
+    res.done = true;
+    res.status = status;
+    res.blob = blob;
+    res.batch_size = batch_size;
+    res.latency_ms = std::chrono::duration<double, std::milli>(Clock::now() - r.arrival).count();
+}
+
+void build_worker(rs_server* s) {
+    (void)hipSetDevice(s->device);
+    hipStream_t stream = nullptr;
+    if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) stream = nullptr;
+    for (;;) {
+        std::vector<Request> batch;
+        uint64_t bytes = 0;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            for (;;) {
+                if (!s->builds.empty()) {
+                    // admit from the head while the budget allows (at least one if idle)
+                    while (!s->builds.empty()) {
+                        const Request& r = s->builds.front();
+                        const bool fits = s->in_flight + bytes + r.footprint <= s->budget;
+                        if (!fits && !(s->in_flight == 0 && batch.empty())) break;
+                        bytes += r.footprint;
+                        batch.push_back(r);
+                        s->builds.pop_front();
+                    }
+                    if (!batch.empty()) break;
+                }
+                if (s->stopping && s->builds.empty()) break;
+                s->cv_work.wait(lk);
+            }
+            if (batch.empty()) break;
+            s->in_flight += bytes;
+            s->peak_in_flight = std::max(s->peak_in_flight, s->in_flight);
+            s->batches++;
+            s->batched_requests += batch.size();
+            s->max_batch = std::max<uint64_t>(s->max_batch, batch.size());
+            s->concurrent++;
+            s->max_concurrent = std::max(s->max_concurrent, s->concurrent);
+        }
+        const uint32_t count = (uint32_t)batch.size();
+        std::vector<rs_keys> sets(count);
+        std::vector<uint32_t> leafs(count), buckets(count);
+        std::vector<rs_blob*> outs(count, nullptr);
+        std::vector<int> status(count, RS_OK);
+        for (uint32_t i = 0; i < count; i++) {
+            sets[i] = batch[i].keys;
+            leafs[i] = batch[i].leaf;
+            buckets[i] = batch[i].bucket;
+        }
+        int rc = rs_build_batch(sets.data(), count, leafs.data(), buckets.data(), &s->opts, stream, outs.data(),
+                                status.data());
+        if (hipStreamSynchronize(stream) != hipSuccess) rc = RS_EDEVICE;
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            for (uint32_t i = 0; i < count; i++) {
+                int st = status[i];
+                if (st == RS_OK && !outs[i]) st = rc != RS_OK ? rc : RS_EDEVICE;
+                finish(s, batch[i], st, outs[i], count);
+            }
+            s->in_flight -= bytes;
+            s->concurrent--;
+        }
+        s->cv_work.notify_all();
+        s->cv_done.notify_all();
+    }
+    if (stream) (void)hipStreamDestroy(stream);
+}
+
+void lookup_worker(rs_server* s) {
+    (void)hipSetDevice(s->device);
+    hipStream_t stream = nullptr;
+    if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) stream = nullptr;
+    for (;;) {
+        Request r;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv_work.wait(lk, [&] { return !s->lookups.empty() || s->stopping; });
+            if (s->lookups.empty()) break;
+            r = s->lookups.front();
+            s->lookups.pop_front();
+        }
+        int rc = rs_lookup(r.blob, &r.keys, r.ranks, stream);
+        if (rc == RS_OK && hipStreamSynchronize(stream) != hipSuccess) rc = RS_EDEVICE;
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            finish(s, r, rc, nullptr, 1);
+        }
+        s->cv_done.notify_all();
+    }
+    if (stream) (void)hipStreamDestroy(stream);
+}
+
+}  // namespace
+
+extern "C" int rs_server_create(uint64_t hbm_budget_bytes, uint32_t build_workers, const rs_options* opts,
+                                rs_server** out) {
+    rs::clear_error();
+    if (!out || hbm_budget_bytes == 0) return rs::fail(RS_EINVAL, "NULL argument or zero budget");
+    rs_server* s = new (std::nothrow) rs_server;
+    if (!s) return rs::fail(RS_ENOMEM, "host allocation failed");
+    s->budget = hbm_budget_bytes;
+    if (opts) s->opts = *opts;
+    s->opts.flags &= ~(uint32_t)RS_OPT_TIMING;
+    (void)hipGetDevice(&s->device);
+    const uint32_t nw = std::max<uint32_t>(1, std::min<uint32_t>(build_workers ? build_workers : 2, 8));
+    for (uint32_t i = 0; i < nw; i++) s->workers.emplace_back(build_worker, s);
+    s->workers.emplace_back(lookup_worker, s);
+    *out = s;
+    return RS_OK;
+}
+
+static int submit(rs_server* s, Request r, uint64_t* ticket) {
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stopping) return rs::fail(RS_EBUSY, "server is stopping");
+    r.ticket = s->next_ticket++;
+    r.arrival = Clock::now();
+    s->results[r.ticket] = Result{};
+    if (r.is_build) s->builds.push_back(r);
+    else s->lookups.push_back(r);
+    s->max_queue = std::max<uint32_t>(s->max_queue, (uint32_t)(s->builds.size() + s->lookups.size()));
+    *ticket = r.ticket;
+    s->cv_work.notify_all();
+    return RS_OK;
+}
+
+extern "C" int rs_server_submit_build(rs_server* s, const rs_keys* keys, uint32_t leaf, uint32_t bucket,
+                                      uint64_t* ticket) {
+    rs::clear_error();
+    if (!s || !keys || !ticket) return rs::fail(RS_EINVAL, "NULL argument");
+    Request r;
+    r.is_build = true;
+    r.keys = *keys;
+    r.leaf = leaf;
+    r.bucket = bucket;
+    r.footprint = build_footprint(keys->n, bucket);
+    return submit(s, r, ticket);
+}
+
+extern "C" int rs_server_submit_lookup(rs_server* s, const rs_blob* blob, const rs_keys* queries, uint64_t* ranks_dev,
+                                       uint64_t* ticket) {
+    rs::clear_error();
+    if (!s || !blob || !queries || !ticket) return rs::fail(RS_EINVAL, "NULL argument");
+    Request r;
+    r.is_build = false;
+    r.keys = *queries;
+    r.blob = blob;
+    r.ranks = ranks_dev;
+    return submit(s, r, ticket);
+}
+
+static int take(rs_server* s, uint64_t ticket, bool wait, int* done, int* status, rs_blob** blob, double* latency,
+                uint32_t* batch_size) {
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->results.find(ticket);
+    if (it == s->results.end()) return rs::fail(RS_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    if (wait) s->cv_done.wait(lk, [&] { return s->results[ticket].done; });
+    it = s->results.find(ticket);
+    if (done) *done = it->second.done;
+    if (!it->second.done) return RS_OK;
+    if (status) *status = it->second.status;
+    if (blob) *blob = it->second.blob;
+    if (latency) *latency = it->second.latency_ms;
+    if (batch_size) *batch_size = it->second.batch_size;
+    s->results.erase(it);  // a completed ticket is handed out once
+    return RS_OK;
+}
+
+extern "C" int rs_server_poll(rs_server* s, uint64_t ticket, int* done, int* status, rs_blob** blob,
+                              double* latency_ms, uint32_t* batch_size) {
+    rs::clear_error();
+    if (!s || !done) return rs::fail(RS_EINVAL, "NULL argument");
+    return take(s, ticket, false, done, status, blob, latency_ms, batch_size);
+}
+
+extern "C" int rs_server_wait(rs_server* s, uint64_t ticket, int* status, rs_blob** blob, double* latency_ms,
+                              uint32_t* batch_size) {
+    rs::clear_error();
+    if (!s) return rs::fail(RS_EINVAL, "NULL argument");
+    int done = 0;
+    return take(s, ticket, true, &done, status, blob, latency_ms, batch_size);
+}
+
+extern "C" int rs_server_get_stats(rs_server* s, rs_server_stats* out) {
+    if (!s || !out) return rs::fail(RS_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    out->batches = s->batches;
+    out->batched_requests = s->batched_requests;
+    out->max_batch = s->max_batch;
+    out->max_concurrent_batches = s->max_concurrent;
+    out->peak_in_flight_bytes = s->peak_in_flight;
+    out->budget_bytes = s->budget;
+    out->max_queue = s->max_queue;
+    return RS_OK;
+}
+
+extern "C" void rs_server_destroy(rs_server* s) {
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stopping = true;
+    }
+    s->cv_work.notify_all();
+    for (auto& t : s->workers) t.join();
+    for (auto& kv : s->results)
+        if (kv.second.blob) rs_blob_free(kv.second.blob);  // completed but never collected
+    delete s;
+}

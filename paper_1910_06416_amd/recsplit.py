@@ -52,6 +52,12 @@ class rs_build_stats(ctypes.Structure):
                 ("tree_bits", ctypes.c_uint64), ("blob_bytes", ctypes.c_uint64)]
 
 
+class rs_server_stats(ctypes.Structure):
+    _fields_ = [("batches", ctypes.c_uint64), ("batched_requests", ctypes.c_uint64), ("max_batch", ctypes.c_uint64),
+                ("max_concurrent_batches", ctypes.c_uint64), ("peak_in_flight_bytes", ctypes.c_uint64),
+                ("budget_bytes", ctypes.c_uint64), ("max_queue", ctypes.c_uint32)]
+
+
 _lib = None
 
 
@@ -81,8 +87,19 @@ def lib() -> ctypes.CDLL:
         L.rs_tables.argtypes = [U32, U32, P, P, P]
         L.rs_last_build_stats.argtypes = [ctypes.POINTER(rs_build_stats)]
         L.rs_build_batch.argtypes = [ctypes.POINTER(rs_keys), U32, P, P, ctypes.POINTER(rs_options), P, P, P]
+        PU64, PI, PD, PU32 = (ctypes.POINTER(U64), ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
+                              ctypes.POINTER(U32))
+        L.rs_server_create.argtypes = [U64, U32, ctypes.POINTER(rs_options), ctypes.POINTER(P)]
+        L.rs_server_submit_build.argtypes = [P, ctypes.POINTER(rs_keys), U32, U32, PU64]
+        L.rs_server_submit_lookup.argtypes = [P, P, ctypes.POINTER(rs_keys), P, PU64]
+        L.rs_server_poll.argtypes = [P, U64, PI, PI, ctypes.POINTER(P), PD, PU32]
+        L.rs_server_wait.argtypes = [P, U64, PI, ctypes.POINTER(P), PD, PU32]
+        L.rs_server_get_stats.argtypes = [P, ctypes.POINTER(rs_server_stats)]
+        L.rs_server_destroy.argtypes = [P]
+        L.rs_server_destroy.restype = None
         for f in ("rs_build", "rs_build_ex", "rs_lookup", "rs_blob_to_host", "rs_blob_from_host", "rs_blob_info",
-                  "rs_tables", "rs_last_build_stats", "rs_build_batch"):
+                  "rs_tables", "rs_last_build_stats", "rs_build_batch", "rs_server_create", "rs_server_submit_build",
+                  "rs_server_submit_lookup", "rs_server_poll", "rs_server_wait", "rs_server_get_stats"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -226,6 +243,70 @@ def tables(leaf: int, maxm: int):
     N = np.zeros(maxm + 1, dtype=np.uint32)
     _check(lib().rs_tables(leaf, maxm, r.ctypes.data, F.ctypes.data, N.ctypes.data))
     return r, F, N
+
+
+class Server:
+    """Continuous-batching build/lookup server (see rs_server_* in recsplit.h).
+    Key tensors passed to submit_* must stay alive until the request completes;
+    the server keeps a reference to them until then."""
+
+    def __init__(self, budget_bytes: int, build_workers: int = 2, stage_from: int = 0, group_max: int = 0):
+        self._h = ctypes.c_void_p()
+        opts = rs_options(0, 0, stage_from, group_max)
+        _check(lib().rs_server_create(budget_bytes, build_workers, ctypes.byref(opts), ctypes.byref(self._h)))
+        self._keep = {}
+
+    def submit_build(self, keys, leaf: int, bucket: int) -> int:
+        k = _as_keys(keys)
+        t = ctypes.c_uint64()
+        _check(lib().rs_server_submit_build(self._h, ctypes.byref(k), leaf, bucket, ctypes.byref(t)))
+        self._keep[t.value] = keys
+        return t.value
+
+    def submit_lookup(self, blob: Blob, keys, out) -> int:
+        k = _as_keys(keys)
+        t = ctypes.c_uint64()
+        _check(lib().rs_server_submit_lookup(self._h, blob.handle, ctypes.byref(k), ctypes.c_void_p(out.data_ptr()),
+                                             ctypes.byref(t)))
+        self._keep[t.value] = (keys, out, blob)
+        return t.value
+
+    def _result(self, t, status, h, lat, bs):
+        self._keep.pop(t, None)
+        blob = Blob(ctypes.c_void_p(h.value)) if h.value else None
+        return {"status": status.value, "blob": blob, "latency_ms": lat.value, "batch_size": bs.value}
+
+    def poll(self, ticket: int):
+        done, status, h, lat, bs = ctypes.c_int(), ctypes.c_int(), ctypes.c_void_p(), ctypes.c_double(), U32()
+        _check(lib().rs_server_poll(self._h, ticket, ctypes.byref(done), ctypes.byref(status), ctypes.byref(h),
+                                    ctypes.byref(lat), ctypes.byref(bs)))
+        return self._result(ticket, status, h, lat, bs) if done.value else None
+
+    def wait(self, ticket: int):
+        status, h, lat, bs = ctypes.c_int(), ctypes.c_void_p(), ctypes.c_double(), U32()
+        _check(lib().rs_server_wait(self._h, ticket, ctypes.byref(status), ctypes.byref(h), ctypes.byref(lat),
+                                    ctypes.byref(bs)))
+        return self._result(ticket, status, h, lat, bs)
+
+    def stats(self) -> dict:
+        st = rs_server_stats()
+        _check(lib().rs_server_get_stats(self._h, ctypes.byref(st)))
+        return {name: getattr(st, name) for name, _ in rs_server_stats._fields_}
+
+    def close(self):
+        if self._h:
+            lib().rs_server_destroy(self._h)
+            self._h = None
+            self._keep.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+U32 = ctypes.c_uint32
 
 
 def last_build_stats() -> dict:

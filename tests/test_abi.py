@@ -64,3 +64,12 @@ def test_argument_validation_without_device(lib):
     bad = np.zeros(16, dtype=np.uint64)
     assert lib.rs_blob_from_host(bad.ctypes.data, 128, None, ctypes.byref(out)) == recsplit.RS_EFORMAT
     assert out.value is None
+
+
+def test_server_argument_validation(lib):
+    import ctypes
+
+    from paper_1910_06416_amd import recsplit
+
+    out = ctypes.c_void_p()
+    assert lib.rs_server_create(0, 2, None, ctypes.byref(out)) == recsplit.RS_EINVAL

@@ -192,3 +192,53 @@ def test_batch_isolates_failed_builds(rs, orc):
     # the surviving blob outlives the others of its call
     del blobs[1:]
     assert blobs[0].to_bytes() == orc.build(good, 8, 100)
+
+
+def _server_mix():
+    specs = [(30_000, 8, 100), (5000, 12, 1000), (200_000, 8, 100), (1000, 16, 2000), (77_777, 12, 1000),
+             (12_345, 8, 2000), (3, 8, 100), (50_000, 16, 100), (123_456, 12, 1000), (9999, 8, 100)]
+    return specs, [inputs.u64_keys(n, 700 + i) for i, (n, _, _) in enumerate(specs)]
+
+
+def test_server_results_equal_alone(rs, orc):
+    """Requests submitted together are batched and overlapped; each result is
+    byte-identical to the same build done alone."""
+    specs, host = _server_mix()
+    dev = [rs.device_keys(k) for k in host]
+    print("case server mix", flush=True)
+    srv = rs.Server(budget_bytes=8 << 30, build_workers=2)
+    tickets = [srv.submit_build(d, leaf, bucket) for d, (_, leaf, bucket) in zip(dev, specs)]
+    res = [srv.wait(t) for t in tickets]
+    stats = srv.stats()
+    assert all(r["status"] == 0 for r in res)
+    for (n, leaf, bucket), d, r in zip(specs, dev, res):
+        alone = rs.build(d, leaf, bucket)
+        assert r["blob"].to_bytes() == alone.to_bytes(), (n, leaf, bucket)
+    # lookups through the server equal direct lookups
+    import torch
+
+    outs = [torch.empty(d.numel(), dtype=torch.int64, device="cuda") for d in dev]
+    lt = [srv.submit_lookup(r["blob"], d, o) for r, d, o in zip(res, dev, outs)]
+    for t in lt:
+        assert srv.wait(t)["status"] == 0
+    for r, d, o in zip(res, dev, outs):
+        assert torch.equal(o, rs.lookup(r["blob"], d))
+    srv.close()
+    assert stats["batched_requests"] == len(specs)
+    print("server stats", stats, flush=True)
+
+
+def test_server_tiny_budget_still_completes(rs, orc):
+    specs, host = _server_mix()
+    specs, host = specs[:5], host[:5]
+    dev = [rs.device_keys(k) for k in host]
+    print("case server tiny budget", flush=True)
+    srv = rs.Server(budget_bytes=1, build_workers=3)
+    tickets = [srv.submit_build(d, leaf, bucket) for d, (_, leaf, bucket) in zip(dev, specs)]
+    res = [srv.wait(t) for t in tickets]
+    stats = srv.stats()
+    srv.close()
+    assert all(r["status"] == 0 for r in res)
+    assert stats["max_batch"] == 1 and stats["max_concurrent_batches"] == 1  # admitted one at a time
+    for (n, leaf, bucket), k, r in zip(specs, host, res):
+        assert r["blob"].to_bytes() == orc.build(k, leaf, bucket)
