@@ -75,9 +75,12 @@ def main():
     ap.add_argument("--l16-n", type=int, default=10_000_000, help="keys of the l=16, b=2000 build (0: skip)")
     ap.add_argument("--latency-builds", type=int, default=30, help="repeated 100,000-key builds for p50/p99")
     ap.add_argument("--cpu-sample", type=int, default=1_000_000, help="oracle sample size (0: skip)")
-    ap.add_argument("--workload", choices=["single", "batch"], default="single",
-                    help="single: 10M strings l=8 b=100 (+ l=16 point); batch: 4096 uneven builds, l=12 b=1000")
+    ap.add_argument("--workload", choices=["single", "batch", "serve"], default="single",
+                    help="single: 10M strings l=8 b=100 (+ l=16 point); batch: 4096 uneven builds, l=12 b=1000; "
+                         "serve: Poisson stream of uneven build requests and 1M-key lookups")
     ap.add_argument("--batch-builds", type=int, default=4096)
+    ap.add_argument("--requests", type=int, default=60, help="serve: build requests")
+    ap.add_argument("--load", type=float, default=0.6, help="serve: offered load (fraction of modelled capacity)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (scales HBM byte counters) and exit")
     args = ap.parse_args()
@@ -106,6 +109,9 @@ def main():
     recsplit.lib()
     if args.workload == "batch":
         print(json.dumps(bench_batch(args)), flush=True)
+        return
+    if args.workload == "serve":
+        print(json.dumps(bench_serve(args)), flush=True)
         return
     n, leaf, bucket = args.n, 8, 100
 
@@ -321,6 +327,114 @@ def bench_batch(args):
                      "peak": VALU_PEAK_TOPS, "unit": "T lane-ops/s",
                      "frac": ev * VALU_SLOTS_PER_EVAL / 1e12 / VALU_PEAK_TOPS, "traffic": None,
                      "algorithmic_evals_per_launch": alg, "evals_per_s": ev},
+    }
+
+
+# Expected hash evaluations per key by leaf size (leaf searches dominate; the
+# bucket size moves these by a few tens of percent), used to set arrival rates.
+EVALS_BY_LEAF = {8: 494.0, 12: 1.39e4, 16: 8.90e5}
+
+
+def bench_serve(args):
+    """Poisson arrivals of build requests (sizes log-uniform in [1e4, 1e7], l in
+    {8, 12, 16}, b in {100, 1000, 2000}) interleaved with 1M-key lookup batches,
+    served with continuous batching; the same arrival schedule replayed through
+    one rs_build call per request in arrival order."""
+    import numpy as np
+    import torch
+
+    from paper_1910_06416_amd import inputs, recsplit
+
+    rng = np.random.Generator(np.random.PCG64(6))
+    R = args.requests
+    sizes = inputs.log_uniform_sizes(R, 6, 1e4, 1e7)
+    leafs = rng.choice([8, 12, 16], size=R)
+    buckets = rng.choice([100, 1000, 2000], size=R)
+    work_s = np.array([EVALS_BY_LEAF[int(l)] * int(n) for n, l in zip(sizes, leafs)]) / 1.3e12
+    rate = args.load / work_s.mean()
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=R))
+    lookup_times = np.cumsum(rng.exponential(1.0 / rate, size=R))
+    total = int(sizes.sum())
+    log(f"[bench] serve: {R} requests, {total:,} keys, modelled work {work_s.sum():.1f} s, "
+        f"rate {rate:.2f}/s over {arrivals[-1]:.1f} s")
+    allkeys = recsplit.device_keys(inputs.u64_keys(total, 6))
+    offs = np.concatenate([[0], np.cumsum(sizes)])
+    sets = [allkeys[int(offs[i]):int(offs[i + 1])] for i in range(R)]
+    warm = recsplit.build(sets[0][:1000], 16, 100)
+    warm.free()
+    torch.cuda.synchronize()
+
+    # served run
+    srv = recsplit.Server(budget_bytes=96 << 30, build_workers=3)
+    t0 = time.perf_counter()
+    tickets, lookups, done_blobs = [None] * R, [], {}
+    li = 0
+    for i in range(R):
+        while li < R and lookup_times[li] < arrivals[i]:
+            if done_blobs:  # a 1M-key lookup batch against a completed build
+                j = sorted(done_blobs)[li % len(done_blobs)]
+                q = sets[j][torch.randint(0, int(sizes[j]), (1_000_000,), device="cuda")]
+                out = torch.empty(1_000_000, dtype=torch.int64, device="cuda")
+                lookups.append(srv.submit_lookup(done_blobs[j], q, out))
+            li += 1
+        wait = arrivals[i] - (time.perf_counter() - t0)
+        if wait > 0:
+            time.sleep(wait)
+        tickets[i] = srv.submit_build(sets[i], int(leafs[i]), int(buckets[i]))
+        for j in range(i):  # collect finished builds (lookups use them)
+            if tickets[j] is not None and j not in done_blobs:
+                r = srv.poll(tickets[j])
+                if r is not None:
+                    assert r["status"] == 0
+                    done_blobs[j] = r["blob"]
+                    tickets[j] = r
+    lat = []
+    for j in range(R):
+        r = tickets[j] if isinstance(tickets[j], dict) else srv.wait(tickets[j])
+        assert r["status"] == 0
+        if j not in done_blobs:
+            done_blobs[j] = r["blob"]
+        lat.append(r["latency_ms"])
+    lk_lat = [srv.wait(t)["latency_ms"] for t in lookups]
+    served_s = time.perf_counter() - t0
+    stats = srv.stats()
+    bits = sum(b.nbytes for b in done_blobs.values()) * 8 / total
+    srv.close()
+    for b in done_blobs.values():
+        b.free()
+    log(f"[bench] served: makespan {served_s:.1f} s, p50 {np.percentile(lat, 50):.0f} ms, "
+        f"p99 {np.percentile(lat, 99):.0f} ms, {stats}")
+
+    # plain path: same arrivals, one rs_build per request in arrival order
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plat = []
+    for i in range(R):
+        wait = arrivals[i] - (time.perf_counter() - t0)
+        if wait > 0:
+            time.sleep(wait)
+        b = recsplit.build(sets[i], int(leafs[i]), int(buckets[i]))
+        torch.cuda.synchronize()
+        plat.append((time.perf_counter() - t0 - arrivals[i]) * 1e3)
+        b.free()
+    plain_s = time.perf_counter() - t0
+    log(f"[bench] plain: makespan {plain_s:.1f} s, p50 {np.percentile(plat, 50):.0f} ms, "
+        f"p99 {np.percentile(plat, 99):.0f} ms")
+    return {
+        "metric": "served build latency p50/p99 and keys/s (continuous batching vs one call per request)",
+        "value": total / served_s, "unit": "keys/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": served_s * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"{R} Poisson build requests, sizes log-uniform [1e4, 1e7], l in {{8,12,16}}, "
+                               f"b in {{100,1000,2000}}, offered load {args.load}, plus 1M-key lookup batches",
+                   "keys": total},
+        "served": {"makespan_s": served_s, "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
+                   "lookup_p50_ms": percentile(lk_lat, 50) if lk_lat else None,
+                   "lookup_p99_ms": percentile(lk_lat, 99) if lk_lat else None, "lookups": len(lk_lat),
+                   "stats": stats},
+        "plain": {"makespan_s": plain_s, "p50_ms": percentile(plat, 50), "p99_ms": percentile(plat, 99),
+                  "keys_per_s": total / plain_s},
+        "bits_per_key": bits,
     }
 
 
