@@ -33,6 +33,10 @@ EVALS_PER_KEY = {(8, 100): 494.0, (12, 1000): 1.39e4, (16, 2000): 8.90e5}
 # the bitmask update).  Every one of these issues at full rate on gfx950
 # (measured), so this is also the number of full-rate VALU slots.
 VALU_SLOTS_PER_EVAL = 18.0
+# HBM bytes of one k_search launch on the 10M-string workload, from rocprofv3
+# FETCH_SIZE / WRITE_SIZE scaled by a 1 GiB copy (profiles/k_search_l8_l16_10M.md);
+# must be re-measured (or set to None) whenever the search kernel changes.
+SEARCH_TRAFFIC_BYTES = 286.0e6
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz full-rate 32-bit VALU lane-ops.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
@@ -202,7 +206,7 @@ def main():
         "peak": VALU_PEAK_TOPS,
         "unit": "T lane-ops/s",
         "frac": evals_per_s * slots / 1e12 / VALU_PEAK_TOPS if slots else None,
-        "traffic": None,
+        "traffic": SEARCH_TRAFFIC_BYTES,
         "algorithmic_evals_per_launch": alg_evals,
         "evals_per_s": evals_per_s,
         "valu_slots_per_eval": slots,
