@@ -73,7 +73,13 @@ def _declare(L):
     L.orc_bucket_sizes.argtypes = [U32, P, P, U64, U64, P]
     L.orc_bucket_keys.argtypes = [U32, P, P, U64, U64, U64, P, U64]
     L.orc_bucket_keys.restype = U64
-    for f in ("orc_tables", "orc_tree", "orc_build", "orc_lookup", "orc_bucket_sizes"):
+    L.orc_bucket_members.argtypes = [U32, P, P, U64, U64, U64, P, U64]
+    L.orc_bucket_members.restype = U64
+    L.orc_blob_bucket.argtypes = [P, U64, U64, P, P, P, P, U64, P]
+    L.orc_bucket_ranks.argtypes = [P, U32, U32, U64, P]
+    L.orc_blob_prefix.argtypes = [P, U64, P, P]
+    for f in ("orc_tables", "orc_tree", "orc_build", "orc_lookup", "orc_bucket_sizes", "orc_blob_bucket",
+              "orc_bucket_ranks", "orc_blob_prefix"):
         getattr(L, f).restype = ctypes.c_int
 
 
@@ -201,6 +207,58 @@ def bucket_keys(keys, nb: int, bucket: int, cap: int = 1 << 16) -> np.ndarray:
     if cnt > cap:
         return bucket_keys(keys, nb, bucket, int(cnt))
     return out[:cnt].copy()
+
+
+def bucket_members(keys, nb: int, bucket: int, cap: int = 1 << 16) -> np.ndarray:
+    """Positions in the input of the keys that fall in one bucket, ascending."""
+    kind, data, offs, n = _keys(keys)
+    out = np.zeros(cap, dtype=np.uint64)
+    cnt = lib().orc_bucket_members(kind, _ptr(data), _ptr(offs) if offs is not None else None, n, nb, bucket,
+                                   _ptr(out), cap)
+    if cnt > cap:
+        return bucket_members(keys, nb, bucket, int(cnt))
+    return out[:cnt].copy()
+
+
+def bucket_ranks(lo: np.ndarray, leaf: int, seed_cap: int = 0) -> np.ndarray:
+    """Rank inside the bucket (0..m-1) of each lower signature word, from the
+    tree the oracle builds for the bucket."""
+    lo = np.ascontiguousarray(lo, dtype=np.uint64)
+    out = np.zeros(max(len(lo), 1), dtype=np.uint64)
+    rc = lib().orc_bucket_ranks(_ptr(lo if len(lo) else np.zeros(1, np.uint64)), len(lo), leaf, seed_cap, _ptr(out))
+    if rc:
+        raise OracleError(rc, "bucket_ranks")
+    return out[:len(lo)]
+
+
+def blob_bucket(blob: bytes, bucket: int):
+    """Decode one bucket of a serialized structure: (s_i, o_i, indices, sizes),
+    the coded nodes in preorder."""
+    b = np.frombuffer(blob, dtype=np.uint8).copy()
+    h = header(blob)
+    cap = max(int(h["maxm"]), 1)
+    v = np.zeros(cap, dtype=np.uint64)
+    m = np.zeros(cap, dtype=np.uint32)
+    s_i, o_i, cnt = U64(), U64(), U64()
+    rc = lib().orc_blob_bucket(_ptr(b), len(blob), bucket, ctypes.byref(s_i), ctypes.byref(o_i), _ptr(v), _ptr(m),
+                               cap, ctypes.byref(cnt))
+    if rc:
+        raise OracleError(rc, "blob_bucket")
+    c = cnt.value
+    return s_i.value, o_i.value, v[:c].copy(), m[:c].copy()
+
+
+def blob_prefix(blob: bytes):
+    """Both Elias-Fano lists of a serialized structure: (s, o), nb+1 entries
+    each (first rank and first tree bit of every bucket)."""
+    b = np.frombuffer(blob, dtype=np.uint8).copy()
+    nb = header(blob)["nb"]
+    s_ = np.zeros(nb + 1, dtype=np.uint64)
+    o_ = np.zeros(nb + 1, dtype=np.uint64)
+    rc = lib().orc_blob_prefix(_ptr(b), len(blob), _ptr(s_), _ptr(o_))
+    if rc:
+        raise OracleError(rc, "blob_prefix")
+    return s_, o_
 
 
 def header(blob: bytes) -> dict:

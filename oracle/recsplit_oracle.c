@@ -585,78 +585,173 @@ static uint64_t descend(const decoded* dc, uint64_t x, uint32_t m, uint32_t dept
     return left + descend(dc, x, parts[j], depth + 1, vs, idx);
 }
 
-int orc_lookup(const void* blob, uint64_t bytes, uint32_t kind, const void* data, const uint64_t* offsets, uint64_t q,
-               uint64_t* ranks) {
+/* Parse a blob's header and decode both Elias-Fano lists (s_i and o_i for
+ * i = 0..nb) by a plain scan of their upper bits (Sec. 6.3). */
+static int blob_open(const void* blob, uint64_t bytes, decoded* dc) {
     const uint64_t* w = (const uint64_t*)blob;
+    memset(dc, 0, sizeof(*dc));
     if (!blob || bytes < ORC_HEADER_WORDS * 8 || w[0] != ORC_MAGIC || (w[1] & 0xffffffffULL) != ORC_VERSION)
         return ORC_EFORMAT;
-    if ((w[1] >> 32) != kind) return ORC_EINVAL;
-    decoded dc;
-    dc.n = w[2]; dc.leaf = w[3]; dc.nb = w[5]; dc.maxm = w[6]; dc.kind = kind;
-    dc.st = make_strategy((uint32_t)dc.leaf);
+    dc->n = w[2]; dc->leaf = w[3]; dc->nb = w[5]; dc->maxm = w[6]; dc->kind = w[1] >> 32;
+    if (dc->leaf < 1 || dc->leaf > 24) return ORC_EFORMAT;
+    dc->st = make_strategy((uint32_t)dc->leaf);
     uint32_t Ws = (uint32_t)(w[7] & 0xff), Wz = (uint32_t)((w[7] >> 8) & 0xff);
     uint64_t delta_s = w[8];
     int64_t delta_z = (int64_t)w[9];
     uint64_t beta = w[10], us_words = w[11], uz_words = w[12], lower_words = w[13], tree_words = w[14];
-    uint64_t Nn = dc.nb + 1;
+    uint64_t Nn = dc->nb + 1;
     uint64_t ninv = (Nn + ORC_INV_STRIDE - 1) / ORC_INV_STRIDE;
     if (bytes != (ORC_HEADER_WORDS + lower_words + us_words + uz_words + 2 * ninv + tree_words) * 8)
         return ORC_EFORMAT;
     const uint64_t* lower = w + ORC_HEADER_WORDS;
     const uint64_t* up_s = lower + lower_words;
     const uint64_t* up_z = up_s + us_words;
-    dc.tree = up_z + uz_words + 2 * ninv;
+    dc->tree = up_z + uz_words + 2 * ninv;
 
-    dc.s = malloc(Nn * 8);
-    dc.o = malloc(Nn * 8);
-    dc.r = malloc((dc.maxm + 1) * 4);
-    uint32_t* Ft = malloc((dc.maxm + 1) * 4);
-    uint32_t* Nt = malloc((dc.maxm + 1) * 4);
-    uint32_t* sizes = malloc((dc.maxm + 1) * 4);
-    uint64_t* vs = malloc((dc.maxm + 1) * 8);
-    uint64_t *hi = malloc(8), *lo = malloc(8);
-    int rc = ORC_ENOMEM;
-    if (!dc.s || !dc.o || !dc.r || !Ft || !Nt || !sizes || !vs || !hi || !lo) goto out;
-    orc_tables((uint32_t)dc.leaf, (uint32_t)dc.maxm, dc.r, Ft, Nt);
+    dc->s = malloc(Nn * 8);
+    dc->o = malloc(Nn * 8);
+    dc->r = malloc((dc->maxm + 1) * 4);
+    uint32_t* Ft = malloc((dc->maxm + 1) * 4);
+    uint32_t* Nt = malloc((dc->maxm + 1) * 4);
+    if (!dc->s || !dc->o || !dc->r || !Ft || !Nt) {
+        free(Ft); free(Nt);
+        return ORC_ENOMEM;
+    }
+    orc_tables((uint32_t)dc->leaf, (uint32_t)dc->maxm, dc->r, Ft, Nt);
+    free(Ft);
+    free(Nt);
 
-    /* Elias-Fano: the i-th one of the upper bits sits at (y_i >> W) + i */
+    /* the i-th one of the upper bits sits at (y_i >> W) + i */
     uint64_t ps = 0, pz = 0;
     for (uint64_t i = 0; i < Nn; i++) {
         while (!get_bit(up_s, ps)) ps++;
         while (!get_bit(up_z, pz)) pz++;
         uint64_t ys = ((ps - i) << Ws) | get_bits(lower, i * (Ws + Wz), Ws);
         uint64_t yz = ((pz - i) << Wz) | get_bits(lower, i * (Ws + Wz) + Ws, Wz);
-        dc.s[i] = ys + i * delta_s;
+        dc->s[i] = ys + i * delta_s;
         int64_t zi = (int64_t)yz + (int64_t)i * delta_z;
-        dc.o[i] = (uint64_t)(zi + (int64_t)((beta * dc.s[i]) >> 16));
+        dc->o[i] = (uint64_t)(zi + (int64_t)((beta * dc->s[i]) >> 16));
         ps++;
         pz++;
     }
+    return ORC_OK;
+}
 
+static void blob_close(decoded* dc) {
+    free(dc->s); free(dc->o); free(dc->r);
+    dc->s = dc->o = NULL;
+    dc->r = NULL;
+}
+
+/* Indices of the coded nodes of bucket bk, in preorder (Sec. 6.2): all fixed
+ * parts first, then all unary parts.  sizes/vs hold maxm+1 entries. */
+static uint32_t bucket_codes(const decoded* dc, uint64_t bk, uint32_t* sizes, uint64_t* vs) {
+    uint32_t m = (uint32_t)(dc->s[bk + 1] - dc->s[bk]);
+    uint32_t cnt = 0;
+    preorder_sizes(&dc->st, m, sizes, &cnt);
+    uint64_t pos = dc->o[bk];
+    for (uint32_t k = 0; k < cnt; k++) { /* fixed parts */
+        vs[k] = get_bits(dc->tree, pos, dc->r[sizes[k]]);
+        pos += dc->r[sizes[k]];
+    }
+    for (uint32_t k = 0; k < cnt; k++) { /* unary parts */
+        uint64_t zeros = 0;
+        while (!get_bit(dc->tree, pos)) { zeros++; pos++; }
+        pos++;
+        vs[k] |= zeros << dc->r[sizes[k]];
+    }
+    return cnt;
+}
+
+int orc_lookup(const void* blob, uint64_t bytes, uint32_t kind, const void* data, const uint64_t* offsets, uint64_t q,
+               uint64_t* ranks) {
+    decoded dc;
+    int rc = blob_open(blob, bytes, &dc);
+    if (rc) { blob_close(&dc); return rc; }
+    if (dc.kind != kind) { blob_close(&dc); return ORC_EINVAL; }
+    uint32_t* sizes = malloc((dc.maxm + 1) * 4);
+    uint64_t* vs = malloc((dc.maxm + 1) * 8);
+    rc = ORC_ENOMEM;
+    if (!sizes || !vs) goto out;
     for (uint64_t qi = 0; qi < q; qi++) {
-        if (kind == ORC_KEYS_U64) orc_fingerprint_u64((const uint64_t*)data + qi, 1, hi, lo);
-        else fingerprint_bytes_one((const uint8_t*)data + offsets[qi], offsets[qi + 1] - offsets[qi], hi, lo);
-        uint64_t bk = bucket_of(*hi, dc.nb);
+        uint64_t hi, lo;
+        if (kind == ORC_KEYS_U64) orc_fingerprint_u64((const uint64_t*)data + qi, 1, &hi, &lo);
+        else fingerprint_bytes_one((const uint8_t*)data + offsets[qi], offsets[qi + 1] - offsets[qi], &hi, &lo);
+        uint64_t bk = bucket_of(hi, dc.nb);
         uint32_t m = (uint32_t)(dc.s[bk + 1] - dc.s[bk]);
-        uint32_t cnt = 0;
-        preorder_sizes(&dc.st, m, sizes, &cnt);
-        uint64_t pos = dc.o[bk];
-        for (uint32_t k = 0; k < cnt; k++) { /* fixed parts */
-            vs[k] = get_bits(dc.tree, pos, dc.r[sizes[k]]);
-            pos += dc.r[sizes[k]];
-        }
-        for (uint32_t k = 0; k < cnt; k++) { /* unary parts */
-            uint64_t zeros = 0;
-            while (!get_bit(dc.tree, pos)) { zeros++; pos++; }
-            pos++;
-            vs[k] |= zeros << dc.r[sizes[k]];
-        }
+        bucket_codes(&dc, bk, sizes, vs);
         uint32_t idx = 0;
-        ranks[qi] = dc.s[bk] + descend(&dc, *lo, m, 0, vs, &idx);
+        ranks[qi] = dc.s[bk] + descend(&dc, lo, m, 0, vs, &idx);
     }
     rc = ORC_OK;
 out:
-    free(dc.s); free(dc.o); free(dc.r); free(Ft); free(Nt); free(sizes); free(vs); free(hi); free(lo);
+    free(sizes); free(vs);
+    blob_close(&dc);
+    return rc;
+}
+
+/* Decode one bucket of a blob: its first rank s_i, its first tree bit o_i,
+ * and the index and size of each coded node in preorder.  out_v / out_m hold
+ * cap entries; *out_count receives the node count (a count above cap means
+ * the lists were cut).  Used to compare single buckets of large structures. */
+int orc_blob_bucket(const void* blob, uint64_t bytes, uint64_t bucket, uint64_t* out_s, uint64_t* out_o,
+                    uint64_t* out_v, uint32_t* out_m, uint64_t cap, uint64_t* out_count) {
+    decoded dc;
+    int rc = blob_open(blob, bytes, &dc);
+    if (rc) { blob_close(&dc); return rc; }
+    if (bucket >= dc.nb) { blob_close(&dc); return ORC_EINVAL; }
+    uint32_t* sizes = malloc((dc.maxm + 1) * 4);
+    uint64_t* vs = malloc((dc.maxm + 1) * 8);
+    rc = ORC_ENOMEM;
+    if (!sizes || !vs) goto out;
+    uint32_t cnt = bucket_codes(&dc, bucket, sizes, vs);
+    for (uint32_t k = 0; k < cnt && k < cap; k++) { out_v[k] = vs[k]; out_m[k] = sizes[k]; }
+    *out_s = dc.s[bucket];
+    *out_o = dc.o[bucket];
+    *out_count = cnt;
+    rc = ORC_OK;
+out:
+    free(sizes); free(vs);
+    blob_close(&dc);
+    return rc;
+}
+
+/* Both Elias-Fano lists of a blob decoded in full: s_i and o_i for
+ * i = 0..nb (each output holds nb+1 entries). */
+int orc_blob_prefix(const void* blob, uint64_t bytes, uint64_t* out_s, uint64_t* out_o) {
+    decoded dc;
+    int rc = blob_open(blob, bytes, &dc);
+    if (rc == ORC_OK) {
+        memcpy(out_s, dc.s, (dc.nb + 1) * 8);
+        memcpy(out_o, dc.o, (dc.nb + 1) * 8);
+    }
+    blob_close(&dc);
+    return rc;
+}
+
+/* Rank of each key of one bucket inside the bucket (0..m-1), from the tree
+ * the oracle builds for the bucket's lower signature words: the keys left of
+ * the chosen child at every split plus the leaf's bijection (Sec. 4). */
+int orc_bucket_ranks(const uint64_t* lo, uint32_t m, uint32_t leaf, uint64_t seed_cap, uint64_t* ranks) {
+    if (leaf < 1 || leaf > 24) return ORC_EINVAL;
+    uint64_t* v = malloc((size_t)(m ? m : 1) * 8);
+    uint32_t* mm = malloc((size_t)(m ? m : 1) * 4);
+    uint32_t* d = malloc((size_t)(m ? m : 1) * 4);
+    int rc = ORC_ENOMEM;
+    if (!v || !mm || !d) goto out;
+    uint64_t cnt = 0;
+    rc = orc_tree(lo, m, leaf, seed_cap, v, mm, d, &cnt);
+    if (rc) goto out;
+    decoded dc;
+    memset(&dc, 0, sizeof(dc));
+    dc.leaf = leaf;
+    dc.st = make_strategy(leaf);
+    for (uint32_t i = 0; i < m; i++) {
+        uint32_t idx = 0;
+        ranks[i] = descend(&dc, lo[i], m, 0, v, &idx);
+    }
+out:
+    free(v); free(mm); free(d);
     return rc;
 }
 
@@ -687,5 +782,21 @@ uint64_t orc_bucket_keys(uint32_t kind, const void* data, const uint64_t* offset
         }
     }
     if (cnt <= cap) qsort(out, cnt, 8, cmp_u64);
+    return cnt;
+}
+
+/* Indices (positions in the input) of the keys of one bucket, ascending.
+ * Returns the bucket size; at most cap indices are written. */
+uint64_t orc_bucket_members(uint32_t kind, const void* data, const uint64_t* offsets, uint64_t n, uint64_t nb,
+                            uint64_t bucket, uint64_t* out, uint64_t cap) {
+    uint64_t cnt = 0, hi, lo;
+    for (uint64_t i = 0; i < n; i++) {
+        if (kind == ORC_KEYS_U64) orc_fingerprint_u64((const uint64_t*)data + i, 1, &hi, &lo);
+        else fingerprint_bytes_one((const uint8_t*)data + offsets[i], offsets[i + 1] - offsets[i], &hi, &lo);
+        if (bucket_of(hi, nb) == bucket) {
+            if (cnt < cap) out[cnt] = i;
+            cnt++;
+        }
+    }
     return cnt;
 }

@@ -1,0 +1,146 @@
+"""GPU parity at the full workload sizes, in the same calls the benchmark times.
+
+* 10^7 ASCII strings, l=8, b=100: the whole blob byte for byte and every rank
+  of a shuffled lookup batch against the oracle (the oracle builds it in well
+  under a minute).
+* 10^7 random 64-bit keys, l=16, b=2000: the oracle needs hours for the whole
+  structure, so the test compares what it can compute one piece at a time.
+  That is the header, both Elias-Fano lists of all 5,000 buckets, the indices
+  of sampled buckets, and the ranks of those buckets' keys. It also checks
+  that the lookup of all 10^7 keys is a permutation of [0, n).
+* 4096 uneven builds in one batched call, l=12, b=1000: the 16 smallest builds
+  whole, and sampled buckets of the largest and of every 256th build. The
+  lookup of every key of every build must be a bijection.
+"""
+import numpy as np
+import pytest
+
+from paper_1910_06416_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def rs():
+    import torch
+
+    assert torch.cuda.is_available()
+    from paper_1910_06416_amd import recsplit
+
+    recsplit.lib()
+    return recsplit
+
+
+def _is_permutation(ranks) -> bool:
+    import torch
+
+    srt, _ = torch.sort(ranks)
+    return bool(torch.equal(srt, torch.arange(ranks.numel(), dtype=torch.int64, device=ranks.device)))
+
+
+def _check_sampled_buckets(rs, orc, keys_host, blob_bytes, ranks_dev, leaf, picks):
+    """Indices and in-bucket ranks of the picked buckets against the oracle's
+    tree for each bucket's keys."""
+    import torch
+
+    h = orc.header(blob_bytes)
+    nb = h["nb"]
+    for i in picks:
+        s_i, _, v, m = orc.blob_bucket(blob_bytes, i)
+        idx = orc.bucket_members(keys_host, nb, i)
+        _, lo = orc.fingerprint(keys_host[idx])
+        tv, tm, _ = orc.tree(np.sort(lo), leaf)
+        assert np.array_equal(m, tm), f"bucket {i}: node sizes differ"
+        assert np.array_equal(v, tv), f"bucket {i}: indices differ"
+        want = orc.bucket_ranks(lo, leaf) + np.uint64(s_i)
+        sel = torch.from_numpy(idx.astype(np.int64)).to(ranks_dev.device)
+        got = ranks_dev[sel].cpu().numpy().view(np.uint64)
+        assert np.array_equal(got, want), f"bucket {i}: ranks differ"
+
+
+# Workload sizes (the benchmark's).
+STRINGS_N = 10_000_000
+L16_N = 10_000_000
+BATCH_BUILDS = 4096
+
+
+def test_full_strings_10M_l8_b100(rs, orc):
+    n = STRINGS_N
+    print(f"case full strings n={n} leaf=8 bucket=100", flush=True)
+    keys = inputs.ascii_keys(n, 2)
+    blob = rs.build(rs.device_keys(keys), 8, 100)
+    got = blob.to_bytes()
+    want = orc.build(keys, 8, 100)
+    assert got == want
+    order = inputs.permutation(n, 3)
+    queries = inputs.gather_strings(keys, order)
+    ranks = rs.lookup(blob, rs.device_keys(queries))
+    assert _is_permutation(ranks)
+    assert np.array_equal(ranks.cpu().numpy().view(np.uint64), orc.lookup(want, queries))
+
+
+def test_full_u64_10M_l16_b2000(rs, orc):
+    n, leaf, bucket = L16_N, 16, 2000
+    print(f"case full u64 n={n} leaf={leaf} bucket={bucket}", flush=True)
+    keys = inputs.u64_keys(n, 4)
+    dkeys = rs.device_keys(keys)
+    blob = rs.build(dkeys, leaf, bucket)
+    got = blob.to_bytes()
+    h = orc.header(got)
+    nb = -(-n // bucket)
+    sizes = orc.bucket_sizes(keys, nb)
+    assert (h["n"], h["leaf"], h["bucket"], h["nb"], h["maxm"]) == (n, leaf, bucket, nb, int(sizes.max()))
+    s_all, o_all = orc.blob_prefix(got)
+    assert np.array_equal(s_all, np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64))
+    assert o_all[-1] == h["tree_bits"]
+    if n >= 1_000_000:
+        assert 1.55 <= 8 * len(got) / n <= 1.57
+    ranks = rs.lookup(blob, dkeys)
+    assert _is_permutation(ranks)
+    rng = np.random.default_rng(11)
+    picks = [int(np.argmin(sizes))] + rng.integers(0, nb, 1).tolist()
+    _check_sampled_buckets(rs, orc, keys, got, ranks, leaf, picks)
+    # o_{i+1} - o_i is the Golomb-Rice length of the sampled buckets' codes
+    r, _, _ = orc.tables(leaf, h["maxm"])
+    for i in picks:
+        _, _, v, m = orc.blob_bucket(got, i)
+        bits = sum(int(r[mm]) + (int(vv) >> int(r[mm])) + 1 for vv, mm in zip(v, m))
+        assert int(o_all[i + 1] - o_all[i]) == bits
+
+
+def test_full_batch_4096_l12_b1000(rs, orc):
+    import torch
+
+    leaf, bucket = 12, 1000
+    sizes = inputs.log_uniform_sizes(BATCH_BUILDS, 5, 1e3, 1e6)
+    total = int(sizes.sum())
+    print(f"case full batch builds={len(sizes)} keys={total} leaf={leaf} bucket={bucket}", flush=True)
+    keys = inputs.u64_keys(total, 5)
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    dall = rs.device_keys(keys)
+    sets = [dall[int(offs[i]):int(offs[i + 1])] for i in range(len(sizes))]
+    blobs, status = rs.build_batch(sets, leaf, bucket)
+    assert all(s == 0 for s in status)
+    for i in range(len(sizes)):
+        assert _is_permutation(rs.lookup(blobs[i], sets[i])), f"build {i}"
+    order = np.argsort(sizes, kind="stable")
+    whole = order[:16].tolist()
+    for i in whole:
+        part = keys[offs[i]:offs[i + 1]]
+        assert blobs[i].to_bytes() == orc.build(part, leaf, bucket), f"build {i} (n={sizes[i]})"
+    sampled = sorted(set(order[-4:].tolist() + list(range(0, len(sizes), 256))) - set(whole))
+    rng = np.random.default_rng(12)
+    for i in sampled:
+        part = keys[offs[i]:offs[i + 1]]
+        got = blobs[i].to_bytes()
+        h = orc.header(got)
+        nb = -(-int(sizes[i]) // bucket)
+        bs = orc.bucket_sizes(part, nb)
+        assert (h["n"], h["nb"], h["maxm"]) == (int(sizes[i]), nb, int(bs.max()))
+        s_all, _ = orc.blob_prefix(got)
+        assert np.array_equal(s_all, np.concatenate([[0], np.cumsum(bs)]).astype(np.uint64))
+        ranks = rs.lookup(blobs[i], sets[i])
+        _check_sampled_buckets(rs, orc, part, got, ranks, leaf, [int(rng.integers(0, nb))])
+    for b in blobs:
+        b.free()
+    torch.cuda.synchronize()

@@ -333,6 +333,52 @@ def test_bijection_strings(orc, n, leaf, bucket):
     assert np.array_equal(np.sort(ranks), np.arange(n, dtype=np.uint64))
 
 
+@pytest.mark.parametrize("n,leaf,bucket", [(20_000, 8, 100), (5000, 16, 400), (3000, 12, 9), (2000, 1, 10)])
+def test_bucket_decoder_roundtrip(orc, n, leaf, bucket):
+    """Decoding single buckets of a serialized structure gives back what the
+    construction wrote: s_i is the prefix sum of the bucket sizes, the coded
+    nodes are the tree the oracle builds for the bucket's keys, and o_i
+    advances by the Golomb-Rice length of those codes (Sec. 6.2-6.3)."""
+    keys = inputs.u64_keys(n, 4000 + n + leaf)
+    blob = orc.build(keys, leaf, bucket)
+    nb = -(-n // bucket)
+    sizes = orc.bucket_sizes(keys, nb)
+    prefix = np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64)
+    maxm = int(sizes.max())
+    r, _, _ = orc.tables(leaf, maxm)
+    rng = np.random.default_rng(7)
+    picks = sorted(set([0, nb - 1, int(np.argmax(sizes))] + rng.integers(0, nb, 6).tolist()))
+    for i in picks:
+        s_i, o_i, v, m = orc.blob_bucket(blob, i)
+        tv, tm, _ = orc.tree(orc.bucket_keys(keys, nb, i), leaf)
+        assert s_i == prefix[i]
+        assert np.array_equal(v, tv) and np.array_equal(m, tm)
+        if i + 1 < nb:
+            s_next, o_next, _, _ = orc.blob_bucket(blob, i + 1)
+            code_bits = sum(int(r[mm]) + (int(vv) >> int(r[mm])) + 1 for vv, mm in zip(v, m))
+            assert o_next - o_i == code_bits
+    s_all, o_all = orc.blob_prefix(blob)
+    assert np.array_equal(s_all, prefix)
+    assert o_all[0] == 0 and np.all(np.diff(o_all.astype(np.int64)) >= 0)
+    assert o_all[-1] == orc.header(blob)["tree_bits"]
+
+
+@pytest.mark.parametrize("n,leaf,bucket", [(20_000, 8, 100), (4000, 12, 1000), (600, 16, 200)])
+def test_bucket_ranks_agree_with_lookup(orc, n, leaf, bucket):
+    """The in-bucket ranks of a bucket's keys are a permutation of [0, m)
+    and, offset by s_i, equal the lookup of those keys (Sec. 4)."""
+    keys = inputs.u64_keys(n, 5000 + n + leaf)
+    blob = orc.build(keys, leaf, bucket)
+    nb = -(-n // bucket)
+    for i in sorted(set([0, nb // 2, nb - 1])):
+        idx = orc.bucket_members(keys, nb, i)
+        _, lo = orc.fingerprint(keys[idx])
+        local = orc.bucket_ranks(lo, leaf)
+        assert np.array_equal(np.sort(local), np.arange(len(idx), dtype=np.uint64))
+        s_i = orc.blob_bucket(blob, i)[0]
+        assert np.array_equal(local + np.uint64(s_i), orc.lookup(blob, keys[idx]))
+
+
 def test_empty_and_short_strings(orc):
     strings = [b"", b"a", b"ab", b"abcdefgh", b"abcdefghi", b"\x00", b"\x00\x00"]
     offs = np.zeros(len(strings) + 1, dtype=np.uint64)
