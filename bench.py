@@ -34,9 +34,9 @@ EVALS_PER_KEY = {(8, 100): 494.0, (12, 1000): 1.39e4, (16, 2000): 8.90e5}
 # (measured), so this is also the number of full-rate VALU slots.
 VALU_SLOTS_PER_EVAL = 18.0
 # HBM bytes of one k_search launch on the 10M-string workload, from rocprofv3
-# FETCH_SIZE / WRITE_SIZE scaled by a 1 GiB copy (profiles/k_search_l8_l16_10M.md);
-# must be re-measured (or set to None) whenever the search kernel changes.
-SEARCH_TRAFFIC_BYTES = 286.0e6
+# FETCH_SIZE / WRITE_SIZE scaled by a 1 GiB copy; None until the counters have
+# been taken on the current search kernel.
+SEARCH_TRAFFIC_BYTES = None
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz full-rate 32-bit VALU lane-ops.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
@@ -85,6 +85,9 @@ def main():
     ap.add_argument("--batch-builds", type=int, default=4096)
     ap.add_argument("--requests", type=int, default=60, help="serve: build requests")
     ap.add_argument("--load", type=float, default=0.6, help="serve: offered load (fraction of modelled capacity)")
+    ap.add_argument("--tune-ms", type=float, default=3000.0,
+                    help="autotuner budget (search milliseconds) per (l, b) pair; l=16 pairs get ten times this")
+    ap.add_argument("--no-tune", action="store_true", help="use the built-in search schedule")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (scales HBM byte counters) and exit")
     args = ap.parse_args()
@@ -127,9 +130,13 @@ def main():
     dq = recsplit.device_keys(queries_host)
     ranks = torch.empty(n, dtype=torch.int64, device="cuda")
     torch.cuda.synchronize()
+    schedules = {}
+    if not args.no_tune:
+        schedules["l8_b100"] = tune(recsplit, leaf, bucket, args, n)
+    tuned = not args.no_tune
 
     for w in range(args.warmup):
-        blob = recsplit.build(dk, leaf, bucket, timing=True)
+        blob = recsplit.build(dk, leaf, bucket, timing=True, tuned=tuned)
         recsplit.lookup(blob, dq, out=ranks)
         torch.cuda.synchronize()
         blob.free()
@@ -141,7 +148,7 @@ def main():
     t0 = time.perf_counter()
     for k in range(args.steps):
         tb = time.perf_counter()
-        blob = recsplit.build(dk, leaf, bucket, timing=True)  # waits for its stream (timing mode)
+        blob = recsplit.build(dk, leaf, bucket, timing=True, tuned=tuned)  # waits for its stream (timing mode)
         build_s.append(time.perf_counter() - tb)
         stats = recsplit.last_build_stats()
         search_ms.append(stats["ms_search"])
@@ -219,7 +226,7 @@ def main():
         for i in range(args.latency_builds + 3):
             torch.cuda.synchronize()
             tb = time.perf_counter()
-            b = recsplit.build(small, 8, 100, timing=True)
+            b = recsplit.build(small, 8, 100, timing=True, tuned=tuned)
             dt = time.perf_counter() - tb
             b.free()
             if i >= 3:
@@ -232,12 +239,14 @@ def main():
     if args.l16_n:
         k16 = inputs.u64_keys(args.l16_n, 4)
         d16 = recsplit.device_keys(k16)
-        warm = recsplit.build(recsplit.device_keys(inputs.u64_keys(4000, 5)), 16, 2000, timing=True)
+        if tuned:
+            schedules["l16_b2000"] = tune(recsplit, 16, 2000, args, args.l16_n)
+        warm = recsplit.build(recsplit.device_keys(inputs.u64_keys(4000, 5)), 16, 2000, timing=True, tuned=tuned)
         warm.free()
         log(f"[bench] l=16 b=2000 build of {args.l16_n:,} keys ...")
         torch.cuda.synchronize()
         tb = time.perf_counter()
-        b16 = recsplit.build(d16, 16, 2000, timing=True)
+        b16 = recsplit.build(d16, 16, 2000, timing=True, tuned=tuned)
         dt16 = time.perf_counter() - tb
         st16 = recsplit.last_build_stats()
         bpk16 = b16.bits_per_key()
@@ -253,6 +262,7 @@ def main():
         }
         log(f"[bench] l=16: {args.l16_n / dt16:,.0f} keys/s, {bpk16:.4f} bits/key")
 
+    result["schedules"] = schedules if tuned else "built-in"
     if args.cpu_sample:
         log(f"[bench] CPU oracle on {args.cpu_sample:,} keys ...")
         result["cpu_baseline"] = cpu_baseline(keys_host, args.cpu_sample, leaf, bucket)
@@ -279,13 +289,15 @@ def bench_batch(args):
     total = int(sizes.sum())
     torch.cuda.synchronize()
 
+    tuned = not args.no_tune
+    schedule = tune(recsplit, leaf, bucket, args, total) if tuned else "built-in"
     # batched: warm-up on a small slice, then the timed call(s)
-    recsplit.build_batch(sets[:8], leaf, bucket)
+    recsplit.build_batch(sets[:8], leaf, bucket, tuned=tuned)
     times, stats = [], None
     for k in range(max(1, args.steps)):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        blobs, status = recsplit.build_batch(sets, leaf, bucket, timing=True)
+        blobs, status = recsplit.build_batch(sets, leaf, bucket, timing=True, tuned=tuned)
         dt = time.perf_counter() - t0
         stats = recsplit.last_build_stats()
         assert all(x == 0 for x in status), "batched build failed"
@@ -308,7 +320,7 @@ def bench_batch(args):
     lat = []
     for i, s_ in enumerate(sets):
         tb = time.perf_counter()
-        b = recsplit.build(s_, leaf, bucket)
+        b = recsplit.build(s_, leaf, bucket, tuned=tuned)
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - tb)
         b.free()
@@ -327,6 +339,7 @@ def bench_batch(args):
         "plain_keys_per_s": total / plain, "bits_per_key": bits, "search_ms": stats["ms_search"],
         "phase_ms": {k: stats[k] for k in ("ms_signature", "ms_scatter", "ms_search", "ms_offsets", "ms_fill")},
         "plain_build_latency_ms": {"p50": percentile(lat, 50) * 1e3, "p99": percentile(lat, 99) * 1e3},
+        "schedule": schedule,
         "roofline": {"kernel": "k_search", "bound": "alu", "achieved": ev * VALU_SLOTS_PER_EVAL / 1e12,
                      "peak": VALU_PEAK_TOPS, "unit": "T lane-ops/s",
                      "frac": ev * VALU_SLOTS_PER_EVAL / 1e12 / VALU_PEAK_TOPS, "traffic": None,
@@ -364,12 +377,18 @@ def bench_serve(args):
     allkeys = recsplit.device_keys(inputs.u64_keys(total, 6))
     offs = np.concatenate([[0], np.cumsum(sizes)])
     sets = [allkeys[int(offs[i]):int(offs[i + 1])] for i in range(R)]
-    warm = recsplit.build(sets[0][:1000], 16, 100)
+    tuned = not args.no_tune
+    schedules = {}
+    if tuned:
+        for l_ in (8, 12, 16):
+            for b_ in (100, 1000, 2000):
+                schedules[f"l{l_}_b{b_}"] = tune(recsplit, l_, b_, args, 2e6)
+    warm = recsplit.build(sets[0][:1000], 16, 100, tuned=tuned)
     warm.free()
     torch.cuda.synchronize()
 
     # served run
-    srv = recsplit.Server(budget_bytes=96 << 30, build_workers=3)
+    srv = recsplit.Server(budget_bytes=96 << 30, build_workers=3, tuned=tuned)
     t0 = time.perf_counter()
     tickets, lookups, done_blobs = [None] * R, [], {}
     li = 0
@@ -417,7 +436,7 @@ def bench_serve(args):
         wait = arrivals[i] - (time.perf_counter() - t0)
         if wait > 0:
             time.sleep(wait)
-        b = recsplit.build(sets[i], int(leafs[i]), int(buckets[i]))
+        b = recsplit.build(sets[i], int(leafs[i]), int(buckets[i]), tuned=tuned)
         torch.cuda.synchronize()
         plat.append((time.perf_counter() - t0 - arrivals[i]) * 1e3)
         b.free()
@@ -439,7 +458,19 @@ def bench_serve(args):
         "plain": {"makespan_s": plain_s, "p50_ms": percentile(plat, 50), "p99_ms": percentile(plat, 99),
                   "keys_per_s": total / plain_s},
         "bits_per_key": bits,
+        "schedules": schedules if tuned else "built-in",
     }
+
+
+def tune(recsplit, leaf, bucket, args, keys):
+    """Autotune the search schedule of (leaf, bucket) for builds of `keys` keys
+    before the timed region."""
+    budget = args.tune_ms * (10.0 if leaf >= 16 else 1.0)
+    sc = recsplit.autotune(leaf, bucket, keys_hint=int(keys), budget_ms=budget)
+    log(f"[bench] schedule l={leaf} b={bucket}: waves {sc['waves']}, stage_from {sc['stage_from']}, "
+        f"group_max {sc['group_max']} ({sc['search_ms']:.2f} ms vs {sc['default_ms']:.2f} ms built-in on the "
+        f"calibration sample; {sc['variants']} schedules in {sc['tune_ms'] / 1e3:.1f} s)")
+    return sc
 
 
 def _cpu_model():

@@ -66,19 +66,73 @@ typedef struct rs_blob rs_blob; /* opaque; immutable after build; safe for concu
  *   flags     : RS_OPT_TIMING records HIP events around each construction phase
  *               on the build stream (read them with rs_last_build_stats); the
  *               build then waits for the stream before returning.
- *   stage_from: schedule override: leaves of at least this many keys use the
- *               staged (early-exit) bijection search (0 = default 9; 25 = never).
- *   group_max : schedule override: 1 + the largest log2 of lanes sharing one split
- *               candidate (0 = default, 1 = one lane per candidate, 7 = up to 64).
+ *               RS_OPT_TUNED takes each build's search schedule from the
+ *               process-wide schedule table (rs_autotune, rs_schedule_set) when
+ *               the table has an entry for its (l, b); builds without an entry
+ *               use the built-in schedule.
+ *   stage_from, group_max, waves: schedule overrides for every build of the
+ *               call (0 = keep the table's or built-in value), as in rs_schedule.
  * Schedules never change the result, only the time it takes. */
-enum { RS_OPT_TIMING = 1 };
+enum { RS_OPT_TIMING = 1, RS_OPT_TUNED = 2 };
 typedef struct {
     uint64_t seed_cap;
     uint32_t flags;
     uint32_t stage_from;
     uint32_t group_max;
-    uint32_t reserved[3];
+    uint32_t waves;
+    uint32_t reserved[2];
 } rs_options;
+
+/* Search schedule of one (l, b) pair.  The seed search runs one workgroup per
+ * bucket; these knobs set how its lanes and wavefronts share the work.
+ *   stage_from: leaves of at least this many keys use the staged (early-exit)
+ *               bijection search, smaller ones try 64 candidates on every key
+ *               (2..25; 25 = never staged; built-in 9).
+ *   group_max : 1 + the largest log2 of lanes that share one split candidate
+ *               (1 = one lane per candidate .. 7 = up to 64; built-in 7).  The
+ *               lanes per candidate of each node size come from its expected
+ *               number of trials, capped here.
+ *   waves     : wavefronts per bucket workgroup: 1, 2, 4 or 8 (built-in 1 for
+ *               l <= 8, else 4).
+ *   search_ms : rs_autotune: time of the calibration search with this schedule.
+ *   default_ms: rs_autotune: time of the same search with the built-in schedule.
+ *   tune_ms   : rs_autotune: wall time the tuning took. */
+typedef struct {
+    uint32_t stage_from;
+    uint32_t group_max;
+    uint32_t waves;
+    uint32_t variants;  /* rs_autotune: schedules timed */
+    double search_ms;
+    double default_ms;
+    double tune_ms;
+} rs_schedule;
+
+/* Pick the search schedule of (leaf, bucket) by timing the seed search on a
+ * synthetic calibration key set in device memory (distinct uniform random
+ * 64-bit keys).
+ *   keys_hint: size of the builds the schedule is for (the sum over a batch);
+ *              the calibration set has that many keys, at most 2^25 and at most
+ *              what about ten searches within the budget allow.  0 = ten times
+ *              the bucket workgroups the device holds at once.
+ *   budget_ms: search time to spend (0 = 3000 ms).  The built-in schedule and
+ *              one variant are always timed.
+ * The search runs for at least 100 ms before any timing (clocks ramp up
+ * under load).  The built-in schedule is timed first.  Then each knob is
+ * tried in turn (wavefronts per bucket, stage_from, group_max), and a change
+ * is kept only when it is more than 2% faster.  The winner is stored in the
+ * process-wide table and returned in *out (which may be NULL).  Work is
+ * enqueued on stream, and the call waits for it.
+ * Errors: RS_EINVAL (l outside [1,24], b = 0), RS_ENOMEM, RS_EDEVICE. */
+int rs_autotune(uint32_t leaf, uint32_t bucket, uint64_t keys_hint, double budget_ms, void* stream,
+                rs_schedule* out);
+
+/* Read (RS_EINVAL if the table has no entry) or write the process-wide table
+ * entry of (leaf, bucket); set validates the knobs (RS_EINVAL if out of range)
+ * and is how a caller restores a schedule saved from an earlier process.
+ * Thread-safe.  rs_schedule_clear empties the table. */
+int rs_schedule_get(uint32_t leaf, uint32_t bucket, rs_schedule* out);
+int rs_schedule_set(uint32_t leaf, uint32_t bucket, const rs_schedule* schedule);
+void rs_schedule_clear(void);
 
 /* Per-phase device times (milliseconds, from HIP events on the build stream)
  * and sizes of the calling thread's last successful rs_build_ex with
@@ -112,9 +166,9 @@ int rs_build_ex(const rs_keys* keys, uint32_t leaf, uint32_t bucket, const rs_op
                 rs_blob** out);
 
 /* Build many independent MPHFs in one call (buckets of all builds are independent,
- * Sec. 4): one signature pass, one persistent search launch over the buckets of
- * every build, one encoding pass; each blob is byte-identical to the one rs_build
- * makes for the same keys, l and b.
+ * Sec. 4): one signature pass, one search launch over the buckets of every
+ * build (one workgroup per bucket), one encoding pass; each blob is
+ * byte-identical to the one rs_build makes for the same keys, l and b.
  *   sets[count]            : device key sets (kinds may differ between builds).
  *   leaf[count], bucket[count]: per-build l and b.
  *   outs[count]            : receives one blob per successful build, NULL otherwise.
@@ -206,6 +260,16 @@ int rs_server_get_stats(rs_server* srv, rs_server_stats* out);
 void rs_server_destroy(rs_server* srv);
 
 /* Library version string. */
+/* The per-size tables a structure with leaf size l uses, for node sizes
+ * m = 0..maxm (host arrays of maxm+1 entries each, written by the call):
+ *   r[m]: Golomb-Rice parameter of a node of m keys, eq. (4) with the exact
+ *         success probability of eq. (2) (leaves: m!/m^m, Sec. 5);
+ *   F[m]: fixed-part bits of a whole subtree on m keys (Sec. 6.2);
+ *   N[m]: coded nodes of that subtree (nodes with at least 2 keys).
+ * Host only; no device is needed.  Errors: RS_EINVAL (l outside [1,24], NULL),
+ * RS_ENOMEM. */
+int rs_tables(uint32_t leaf, uint32_t maxm, uint32_t* r, uint32_t* F, uint32_t* N);
+
 const char* rs_version(void);
 
 #ifdef __cplusplus

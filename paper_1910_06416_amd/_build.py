@@ -5,7 +5,7 @@ import os
 import subprocess
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["csrc/build.hip", "csrc/api.hip", "csrc/tables.cpp", "csrc/server.cpp"]
+SOURCES = ["csrc/build.hip", "csrc/api.hip", "csrc/tables.cpp", "csrc/server.cpp", "csrc/schedule.cpp"]
 HEADERS = ["csrc/rs_internal.h", "csrc/rs_host.h", "../include/recsplit.h"]
 LIB = os.path.join(HERE, "librecsplit.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <chrono>
 #include <string>
 #include <cstdio>
 #include <cstdlib>
@@ -60,6 +61,11 @@ struct BuildDesc {
     uint32_t kind, leaf, lower, upper;
     uint32_t tab;      // index of this build's leaf-size tables in the table arena
     uint32_t aligned;  // byte keys start on an 8-byte boundary
+    // search schedule of this build
+    uint32_t stage_from;  // leaves of at least this many keys use the staged bijection search
+    uint32_t group_cap;   // cap on log2 lanes per split candidate
+    uint32_t waves;       // wavefronts of the bucket's workgroup that take nodes
+    uint32_t spare;
     // written by the device
     uint32_t maxm, flags;
     unsigned long long delta_s;
@@ -251,8 +257,6 @@ struct SearchArgs {
     const uint32_t* tables;     // per leaf size: r, F, N, G, each `stride` words
     uint32_t stride;
     uint64_t seed_cap;
-    uint32_t stage_from;  // leaves of at least this many keys use the staged bijection search
-    uint32_t group_max;   // cap on log2 lanes per split candidate
     uint32_t key_words;   // 64-bit words of dynamic LDS before the node slots (largest bucket)
 };
 
@@ -427,7 +431,7 @@ __device__ uint64_t leaf_dispatch(const uint64_t* keys, uint32_t m, uint32_t dep
     switch (m) {
 #define RS_LEAF_CASE(M)                                                                    \
     case M:                                                                                \
-        if constexpr (M <= MAXL) return leaf_search<M>(keys, depth, cap, flags, q, M >= stage_from); \
+        if constexpr (M <= MAXL) return leaf_search<M>(keys, depth, cap, flags, q, M > 16 || M >= stage_from); \
         return kNoSeed;
         RS_LEAF_CASE(2) RS_LEAF_CASE(3) RS_LEAF_CASE(4) RS_LEAF_CASE(5) RS_LEAF_CASE(6) RS_LEAF_CASE(7)
         RS_LEAF_CASE(8) RS_LEAF_CASE(9) RS_LEAF_CASE(10) RS_LEAF_CASE(11) RS_LEAF_CASE(12) RS_LEAF_CASE(13)
@@ -637,7 +641,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_search(SearchArgs a) {
     __shared__ QueueState qs;
     __shared__ uint32_t thr_s[WAVES][kMaxThresholds];
     __shared__ LeafQueues queues[WAVES];
-    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+    const uint32_t lane = lane_id(), wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     uint64_t* lds_keys = lds_dyn;
     NodeSlot* slots = reinterpret_cast<NodeSlot*>(lds_dyn + a.key_words);
     uint32_t* thr = thr_s[wave];
@@ -645,8 +649,16 @@ __global__ __launch_bounds__(64 * WAVES) void k_search(SearchArgs a) {
         const uint64_t b = blockIdx.x;
         const uint32_t j = find_build(a.bucket_base, a.count, b);
         const BuildDesc& B = a.descs[j];
-        const uint32_t leaf = B.leaf, lower = B.lower, upper = B.upper;
-        const uint32_t* R = a.tables + (size_t)B.tab * 4 * a.stride;
+        // the descriptor is also written by this kernel (flags), so its fields are
+        // loaded per lane: make the build's parameters wave-uniform explicitly
+        const uint32_t leaf = __builtin_amdgcn_readfirstlane(B.leaf);
+        const uint32_t lower = __builtin_amdgcn_readfirstlane(B.lower);
+        const uint32_t upper = __builtin_amdgcn_readfirstlane(B.upper);
+        const uint32_t stage_from = __builtin_amdgcn_readfirstlane(B.stage_from);
+        const uint32_t group_cap = __builtin_amdgcn_readfirstlane(B.group_cap);
+        // waves beyond the build's count only join the barriers
+        const uint32_t active = __builtin_amdgcn_readfirstlane(min(B.waves, (uint32_t)WAVES));
+        const uint32_t* R = a.tables + (size_t)__builtin_amdgcn_readfirstlane(B.tab) * 4 * a.stride;
         const uint32_t* Nt = R + 2 * a.stride;
         const uint32_t* Gt = R + 3 * a.stride;
         uint32_t* bflags = &a.wdescs[j].flags;
@@ -670,7 +682,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_search(SearchArgs a) {
         }
         __syncthreads();
         unsigned long long bits = 0;
-        for (;;) {
+        for (; wave < active;) {
             uint32_t h = 0, off = 0, m = 0, d = 0, idx = 0, stop = 0;
             if (lane == 0) {
                 h = __hip_atomic_fetch_add(&qs.head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -710,7 +722,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_search(SearchArgs a) {
             bool fail;
             SplitShape sh{};
             if (m <= leaf) {
-                v = leaf_dispatch<MAXL>(lds_keys + off, m, d, a.seed_cap, bflags, &queues[wave], a.stage_from);
+                v = leaf_dispatch<MAXL>(lds_keys + off, m, d, a.seed_cap, bflags, &queues[wave], stage_from);
                 fail = v == kNoSeed;
             } else {
                 sh = split_shape(m, leaf, lower, upper);
@@ -727,7 +739,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_search(SearchArgs a) {
                     c.unit = sh.unit;
                     c.fanout = sh.fanout;
                     c.last = sh.last;
-                    c.g = min(Gt[m], a.group_max);
+                    c.g = min(Gt[m], group_cap);
                     c.w = 32 - __clz(m);
                     const bool packed = nt >= 4 && sh.fanout * c.w <= 64;
                     c.recip = packed ? (uint32_t)(((1ull << 32) + sh.unit - 1) / sh.unit) : 0;
@@ -1022,11 +1034,38 @@ int max_lds_bytes() {
     return v;
 }
 
-// One launch of the search over every bucket of the call.
-template <int MAXL, int WAVES>
-int launch_search(const SearchArgs& sa, size_t lds, hipStream_t s) {
-    k_search<MAXL, WAVES><<<(uint32_t)sa.nbuckets, 64 * WAVES, lds, s>>>(sa);
-    RS_HIP(hipGetLastError());
+// Search kernel of a (leaf-size class, wavefronts per workgroup) pair.
+using SearchKernel = void (*)(SearchArgs);
+
+template <int MAXL>
+SearchKernel search_kernel_waves(uint32_t waves) {
+    switch (waves) {
+        case 1: return k_search<MAXL, 1>;
+        case 2: return k_search<MAXL, 2>;
+        case 4: return k_search<MAXL, 4>;
+        default: return k_search<MAXL, 8>;
+    }
+}
+
+SearchKernel search_kernel(uint32_t max_leaf, uint32_t waves) {
+    if (max_leaf <= 8) return search_kernel_waves<8>(waves);
+    if (max_leaf <= 12) return search_kernel_waves<12>(waves);
+    if (max_leaf <= 16) return search_kernel_waves<16>(waves);
+    return search_kernel_waves<24>(waves);
+}
+
+// One launch of the search over every bucket of the call: one workgroup of
+// `waves` wavefronts per bucket, `lds` bytes of dynamic LDS (keys + node slots).
+int launch_search(uint32_t max_leaf, uint32_t waves, const SearchArgs& sa, size_t lds, hipStream_t s) {
+    SearchKernel k = search_kernel(max_leaf, waves);
+    hipFuncAttributes attr;
+    RS_HIP(hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(k)));
+    if (lds + attr.sharedSizeBytes > (size_t)max_lds_bytes())
+        return fail(RS_EINVAL, "largest bucket (%u keys) exceeds the local data share", sa.key_words);
+    SearchArgs args = sa;
+    void* params[] = {&args};
+    RS_HIP(hipLaunchKernel(reinterpret_cast<const void*>(k), dim3((uint32_t)sa.nbuckets), dim3(64 * waves), params,
+                           lds, s));
     return RS_OK;
 }
 
@@ -1069,13 +1108,126 @@ bool debug_trace() {
         }                                           \
     } while (0)
 
+// ---------------------------------------------------------------------------
+// Autotuning: the search of one calibration build is launched repeatedly with
+// different schedules (the search only reads the scattered keys and rewrites
+// the same indices, so repeated launches are independent).
+// ---------------------------------------------------------------------------
+struct TuneCtx {
+    bool probe_only = false;  // time the built-in schedule and report residency only
+    double budget_ms = 0;     // search time allowed for the variants
+    // results
+    rs_schedule best{};
+    double default_ms = 0;
+    double spent_ms = 0;
+    uint32_t variants = 0;
+    uint64_t resident = 0;  // workgroups of the built-in kernel resident on the whole device
+};
+
+int tune_search(TuneCtx& t, uint32_t leaf, BuildDesc* hdesc, BuildDesc* d_desc, const SearchArgs& sa, size_t lds,
+                hipStream_t s) {
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    RS_HIP(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(RS_EDEVICE, "hipEventCreate failed");
+    }
+    auto once = [&](const rs_schedule& sc, double* ms) -> int {
+        hdesc[0].stage_from = sc.stage_from;
+        hdesc[0].group_cap = sc.group_max - 1;
+        hdesc[0].waves = sc.waves;
+        RS_HIP(hipMemcpyAsync(d_desc, hdesc, sizeof(BuildDesc), hipMemcpyHostToDevice, s));
+        RS_HIP(hipEventRecord(e0, s));
+        if (int rc = launch_search(leaf, sc.waves, sa, lds, s)) return rc;
+        RS_HIP(hipEventRecord(e1, s));
+        RS_HIP(hipEventSynchronize(e1));
+        float f = 0;
+        RS_HIP(hipEventElapsedTime(&f, e0, e1));
+        *ms = f;
+        t.spent_ms += f;
+        return RS_OK;
+    };
+    // short searches are timed three times (minimum), long ones once
+    auto measure = [&](const rs_schedule& sc, double* ms) -> int {
+        if (int rc = once(sc, ms)) return rc;
+        for (int r = 0; r < 2 && *ms < 30.0; r++) {
+            double again = 0;
+            if (int rc = once(sc, &again)) return rc;
+            *ms = std::min(*ms, again);
+        }
+        return RS_OK;
+    };
+    int rc = RS_OK;
+    rs_schedule cur = builtin_schedule(leaf);
+    double warm = 0, warm_total = 0, best_ms = 0;
+    // warm-up: the first launches run slower (clocks still ramping), so search
+    // for at least 100 ms (at most 20 launches) before timing anything
+    for (int r = 0; r < 20 && warm_total < 100.0; r++) {
+        if ((rc = once(cur, &warm))) goto done;
+        warm_total += warm;
+    }
+    t.spent_ms = 0;
+    if ((rc = measure(cur, &best_ms))) goto done;
+    t.default_ms = best_ms;
+    if (t.probe_only) {
+        int per_cu = 0, cus = 0, dev = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                &per_cu, reinterpret_cast<const void*>(search_kernel(leaf, cur.waves)), 64 * (int)cur.waves, lds) !=
+            hipSuccess)
+            per_cu = 1;
+        t.resident = (uint64_t)std::max(per_cu, 1) * (uint64_t)std::max(cus, 1);
+        goto done;
+    }
+    {
+        // one knob at a time: wavefronts per bucket, staged-search threshold, lanes per split candidate
+        std::vector<uint32_t> waves_list = leaf <= 8 ? std::vector<uint32_t>{1, 2, 4} : std::vector<uint32_t>{2, 4, 8};
+        std::vector<uint32_t> stage_list;
+        for (uint32_t v : {7u, 8u, 9u, 11u, 13u, 16u, 25u})
+            if (v >= 7 && (v <= leaf || v == 25)) stage_list.push_back(v);
+        if (leaf < 7) stage_list.clear();  // no leaf size is ever staged
+        const std::vector<uint32_t> group_list{7, 4, 2, 1};
+        bool out_of_budget = false;
+        for (int knob = 0; knob < 3 && !out_of_budget; knob++) {
+            const std::vector<uint32_t>& vals = knob == 0 ? waves_list : knob == 1 ? stage_list : group_list;
+            const rs_schedule base = cur;
+            for (uint32_t v : vals) {
+                rs_schedule cand = base;
+                uint32_t& field = knob == 0 ? cand.waves : knob == 1 ? cand.stage_from : cand.group_max;
+                if (field == v) continue;
+                if (t.variants >= 1 && t.spent_ms >= t.budget_ms) {
+                    out_of_budget = true;
+                    break;
+                }
+                field = v;
+                double ms = 0;
+                if ((rc = measure(cand, &ms))) goto done;
+                t.variants++;
+                if (ms < best_ms * 0.98) {  // keep a change only beyond timing noise
+                    best_ms = ms;
+                    cur = cand;
+                }
+            }
+        }
+    }
+    t.best = cur;
+    t.best.search_ms = best_ms;
+    t.best.default_ms = t.default_ms;
+    t.best.variants = t.variants + 1;
+done:
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+}
+
 int build_batch_impl(const rs_keys* sets, uint32_t count, const uint32_t* leafs, const uint32_t* buckets,
-                     const rs_options* opts, hipStream_t s, rs_blob** outs, int* statuses) {
+                     const rs_options* opts, hipStream_t s, rs_blob** outs, int* statuses, TuneCtx* tune) {
     if (!sets || !leafs || !buckets || !outs || count == 0) return fail(RS_EINVAL, "NULL argument or empty batch");
     const bool timing = opts && (opts->flags & RS_OPT_TIMING);
     const uint64_t cap = opts && opts->seed_cap ? std::min(opts->seed_cap, kDefaultSeedCap) : kDefaultSeedCap;
-    const uint32_t stage_from = opts && opts->stage_from ? opts->stage_from : 9;
-    const uint32_t group_max = opts && opts->group_max ? opts->group_max - 1 : 6;
+    if (opts && opts->waves && opts->waves != 1 && opts->waves != 2 && opts->waves != 4 && opts->waves != 8)
+        return fail(RS_EINVAL, "waves must be 1, 2, 4 or 8");
     std::vector<int> st(count, RS_OK);
     std::vector<std::string> why(count);
 
@@ -1084,7 +1236,7 @@ int build_batch_impl(const rs_keys* sets, uint32_t count, const uint32_t* leafs,
     std::vector<uint32_t> which;  // desc index -> position in the call
     std::vector<uint32_t> leaf_of_tab;
     uint64_t total = 0, nbuckets = 0;
-    uint32_t max_leaf = 1;
+    uint32_t max_leaf = 1, launch_waves = 1;
     for (uint32_t c = 0; c < count; c++) {
         const rs_keys& k = sets[c];
         const uint32_t leaf = leafs[c], bucket = buckets[c];
@@ -1119,6 +1271,19 @@ int build_batch_impl(const rs_keys* sets, uint32_t count, const uint32_t* leafs,
         d.aligned = ((uintptr_t)k.data & 7) == 0;
         d.delta_s = ~0ull;
         d.delta_z = 0x7fffffffffffffffll;
+        // search schedule: built-in, else the table's (RS_OPT_TUNED), then the overrides
+        rs_schedule sc = builtin_schedule(leaf);
+        if (opts && (opts->flags & RS_OPT_TUNED)) {
+            rs_schedule t;
+            if (schedule_lookup(leaf, bucket, &t)) sc = t;
+        }
+        if (opts && opts->stage_from) sc.stage_from = opts->stage_from;
+        if (opts && opts->group_max) sc.group_max = std::min<uint32_t>(opts->group_max, 7);
+        if (opts && opts->waves) sc.waves = opts->waves;
+        d.stage_from = sc.stage_from;
+        d.group_cap = sc.group_max - 1;
+        d.waves = sc.waves;
+        launch_waves = std::max(launch_waves, sc.waves);
         total += d.n;
         nbuckets += d.nb;
         max_leaf = std::max(max_leaf, leaf);
@@ -1253,21 +1418,21 @@ int build_batch_impl(const rs_keys* sets, uint32_t count, const uint32_t* leafs,
         RS_TRY(hipMemcpyAsync(dst + 2 * stride, tv.N(), stride * 4ull, hipMemcpyHostToDevice, s));
         RS_TRY(hipMemcpyAsync(dst + 3 * stride, tv.G(), stride * 4ull, hipMemcpyHostToDevice, s));
     }
-    // keys + node slots in dynamic LDS; the static part (queues, thresholds) is below 16 KiB
+    // keys + node slots in dynamic LDS (the launch checks the static part too)
     const size_t lds = (size_t)maxm * 8 + (size_t)max_nodes * 16;
-    if (lds + 16384 > (size_t)max_lds_bytes())
-        return cleanup(fail(RS_EINVAL, "largest bucket (%u keys) exceeds the local data share", maxm));
 
     pe.record(1, s);
     k_scatter<<<grid_for(total, kBlock), kBlock, 0, s>>>(d_lo, d_bid, total, d_bst, d_cur, d_sorted);
     pe.record(2, s);
     SearchArgs sa{d_sorted, d_tmp, d_bst, d_seeds, d_blen, d_desc, d_desc, d_bb, K, nbuckets,
-                  d_tab, stride, cap, stage_from, group_max, maxm};
-    int rc = RS_OK;
-    if (max_leaf <= 8) rc = launch_search<8, 1>(sa, lds, s);
-    else if (max_leaf <= 12) rc = launch_search<12, 4>(sa, lds, s);
-    else if (max_leaf <= 16) rc = launch_search<16, 4>(sa, lds, s);
-    else rc = launch_search<24, 4>(sa, lds, s);
+                  d_tab, stride, cap, maxm};
+    if (tune) {  // calibration only: no blob, the tables are not handed to an arena
+        const int trc = tune_search(*tune, max_leaf, hdesc, d_desc, sa, lds, s);
+        dev_free(d_tab, s);
+        d_tab = nullptr;
+        return cleanup(trc);
+    }
+    int rc = launch_search(max_leaf, launch_waves, sa, lds, s);
     if (rc) return cleanup(rc);
     pe.record(3, s);
     if ((rc = scan<uint64_t>(d_blen, nbuckets, d_ost, d_tiles, nullptr, s))) return cleanup(rc);
@@ -1419,7 +1584,8 @@ int build_batch_impl(const rs_keys* sets, uint32_t count, const uint32_t* leafs,
 extern "C" int rs_build_batch(const rs_keys* sets, uint32_t count, const uint32_t* leaf, const uint32_t* bucket,
                               const rs_options* opts, void* stream, rs_blob** outs, int* per_build_status) {
     rs::clear_error();
-    return rs::build_batch_impl(sets, count, leaf, bucket, opts, (hipStream_t)stream, outs, per_build_status);
+    return rs::build_batch_impl(sets, count, leaf, bucket, opts, (hipStream_t)stream, outs, per_build_status,
+                                nullptr);
 }
 
 extern "C" int rs_build_ex(const rs_keys* keys, uint32_t leaf, uint32_t bucket, const rs_options* opts, void* stream,
@@ -1428,7 +1594,7 @@ extern "C" int rs_build_ex(const rs_keys* keys, uint32_t leaf, uint32_t bucket, 
     if (!keys || !out) return rs::fail(RS_EINVAL, "NULL argument");
     rs_blob* b = nullptr;
     int status = RS_OK;
-    int rc = rs::build_batch_impl(keys, 1, &leaf, &bucket, opts, (hipStream_t)stream, &b, &status);
+    int rc = rs::build_batch_impl(keys, 1, &leaf, &bucket, opts, (hipStream_t)stream, &b, &status, nullptr);
     if (rc == RS_OK) *out = b;
     return rc;
 }
@@ -1442,4 +1608,69 @@ extern "C" int rs_last_build_stats(rs_build_stats* out) {
 
 extern "C" int rs_build(const rs_keys* keys, uint32_t leaf, uint32_t bucket, void* stream, rs_blob** out) {
     return rs_build_ex(keys, leaf, bucket, nullptr, stream, out);
+}
+
+namespace rs {
+namespace {
+
+// Calibration keys: distinct uniform random 64-bit words (the SplitMix64
+// stream of a fixed seed).
+__global__ void k_synth_keys(uint64_t* out, uint64_t n, uint64_t seed) {
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = mix64(seed + (i + 1) * kGamma);
+}
+
+int tune_on_sample(uint32_t leaf, uint32_t bucket, uint64_t n, hipStream_t s, TuneCtx& t) {
+    uint64_t* keys = nullptr;
+    if (int rc = dev_alloc((void**)&keys, n * 8, s)) return rc;
+    k_synth_keys<<<(uint32_t)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(keys, n, 0x5eed5eed5eed5eedull + leaf);
+    if (hipGetLastError() != hipSuccess) {
+        dev_free(keys, s);
+        return fail(RS_EDEVICE, "calibration key launch failed");
+    }
+    rs_keys k{RS_KEYS_U64, keys, nullptr, n};
+    rs_blob* unused = nullptr;
+    int status = RS_OK;
+    int rc = build_batch_impl(&k, 1, &leaf, &bucket, nullptr, s, &unused, &status, &t);
+    dev_free(keys, s);
+    return rc;
+}
+
+}  // namespace
+}  // namespace rs
+
+extern "C" int rs_autotune(uint32_t leaf, uint32_t bucket, uint64_t keys_hint, double budget_ms, void* stream,
+                           rs_schedule* out) {
+    rs::clear_error();
+    if (leaf < 1 || leaf > rs::kMaxLeaf || bucket == 0) return rs::fail(RS_EINVAL, "l outside [1, 24] or b = 0");
+    if (!(budget_ms > 0)) budget_ms = 3000.0;
+    hipStream_t s = (hipStream_t)stream;
+    const auto t0 = std::chrono::steady_clock::now();
+    constexpr uint64_t kMaxKeys = 1ull << 25;
+    const uint64_t max_nb = std::max<uint64_t>(1, kMaxKeys / bucket);
+    // buckets of the builds the schedule is for: the hint, else ten times the
+    // workgroups resident at once (a steady state, like a large build)
+    uint64_t nb_target = keys_hint ? (keys_hint + bucket - 1) / bucket : 0;
+    uint64_t nb1 = nb_target ? std::min(nb_target, max_nb) : 0;
+    rs::TuneCtx probe;
+    if (nb1 == 0 || nb1 > 1024) {
+        // probe: 1024 buckets with the built-in schedule (residency, time per round)
+        const uint64_t nb0 = std::min<uint64_t>(1024, max_nb);
+        probe.probe_only = true;
+        if (int rc = rs::tune_on_sample(leaf, bucket, nb0 * bucket, s, probe)) return rc;
+        const double resident = (double)std::max<uint64_t>(probe.resident, 1);
+        const double ms_per_round = probe.default_ms / std::max(1.0, (double)nb0 / resident);
+        if (!nb1) nb1 = std::min<uint64_t>((uint64_t)(10.0 * resident), max_nb);
+        // about ten timed searches must fit the budget
+        const double affordable = budget_ms / 10.0 / std::max(ms_per_round, 1e-3) * resident;
+        if ((double)nb1 > affordable) nb1 = std::max<uint64_t>(nb0, (uint64_t)affordable);
+    }
+    rs::TuneCtx full;
+    full.budget_ms = budget_ms;
+    if (int rc = rs::tune_on_sample(leaf, bucket, nb1 * bucket, s, full)) return rc;
+    rs_schedule best = full.best;
+    best.tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    rs::schedule_store(leaf, bucket, best);
+    if (out) *out = best;
+    return RS_OK;
 }

@@ -1,0 +1,68 @@
+// Process-wide table of seed-search schedules, one entry per (leaf, bucket)
+// pair.  rs_autotune fills it by timing; callers may save entries and restore
+// them in a later process with rs_schedule_set.
+#include <map>
+#include <mutex>
+#include <utility>
+
+#include "rs_host.h"
+
+namespace rs {
+
+namespace {
+std::mutex g_mu;
+std::map<std::pair<uint32_t, uint32_t>, rs_schedule> g_table;
+}  // namespace
+
+rs_schedule builtin_schedule(uint32_t leaf) {
+    rs_schedule s{};
+    s.stage_from = 9;
+    s.group_max = 7;
+    s.waves = leaf <= 8 ? 1 : 4;
+    return s;
+}
+
+bool schedule_valid(const rs_schedule& s) {
+    const bool waves_ok = s.waves == 1 || s.waves == 2 || s.waves == 4 || s.waves == 8;
+    return waves_ok && s.stage_from >= 2 && s.stage_from <= 25 && s.group_max >= 1 && s.group_max <= 7;
+}
+
+bool schedule_lookup(uint32_t leaf, uint32_t bucket, rs_schedule* out) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_table.find({leaf, bucket});
+    if (it == g_table.end()) return false;
+    *out = it->second;
+    return true;
+}
+
+void schedule_store(uint32_t leaf, uint32_t bucket, const rs_schedule& s) {
+    std::lock_guard<std::mutex> lk(g_mu);
+    g_table[{leaf, bucket}] = s;
+}
+
+}  // namespace rs
+
+extern "C" int rs_schedule_get(uint32_t leaf, uint32_t bucket, rs_schedule* out) {
+    rs::clear_error();
+    if (!out) return rs::fail(RS_EINVAL, "NULL argument");
+    rs_schedule s;
+    if (!rs::schedule_lookup(leaf, bucket, &s))
+        return rs::fail(RS_EINVAL, "no schedule for l=%u, b=%u", leaf, bucket);
+    *out = s;
+    return RS_OK;
+}
+
+extern "C" int rs_schedule_set(uint32_t leaf, uint32_t bucket, const rs_schedule* schedule) {
+    rs::clear_error();
+    if (!schedule) return rs::fail(RS_EINVAL, "NULL argument");
+    if (leaf < 1 || leaf > rs::kMaxLeaf || bucket == 0) return rs::fail(RS_EINVAL, "l outside [1, 24] or b = 0");
+    if (!rs::schedule_valid(*schedule))
+        return rs::fail(RS_EINVAL, "schedule out of range (stage_from 2..25, group_max 1..7, waves 1/2/4/8)");
+    rs::schedule_store(leaf, bucket, *schedule);
+    return RS_OK;
+}
+
+extern "C" void rs_schedule_clear(void) {
+    std::lock_guard<std::mutex> lk(rs::g_mu);
+    rs::g_table.clear();
+}

@@ -39,10 +39,16 @@ class rs_keys(ctypes.Structure):
 
 class rs_options(ctypes.Structure):
     _fields_ = [("seed_cap", ctypes.c_uint64), ("flags", ctypes.c_uint32), ("stage_from", ctypes.c_uint32),
-                ("group_max", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 3)]
+                ("group_max", ctypes.c_uint32), ("waves", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 2)]
 
 
-RS_OPT_TIMING = 1
+RS_OPT_TIMING, RS_OPT_TUNED = 1, 2
+
+
+class rs_schedule(ctypes.Structure):
+    _fields_ = [("stage_from", ctypes.c_uint32), ("group_max", ctypes.c_uint32), ("waves", ctypes.c_uint32),
+                ("variants", ctypes.c_uint32), ("search_ms", ctypes.c_double), ("default_ms", ctypes.c_double),
+                ("tune_ms", ctypes.c_double)]
 
 
 class rs_build_stats(ctypes.Structure):
@@ -97,9 +103,15 @@ def lib() -> ctypes.CDLL:
         L.rs_server_get_stats.argtypes = [P, ctypes.POINTER(rs_server_stats)]
         L.rs_server_destroy.argtypes = [P]
         L.rs_server_destroy.restype = None
+        L.rs_autotune.argtypes = [U32, U32, U64, ctypes.c_double, P, ctypes.POINTER(rs_schedule)]
+        L.rs_schedule_get.argtypes = [U32, U32, ctypes.POINTER(rs_schedule)]
+        L.rs_schedule_set.argtypes = [U32, U32, ctypes.POINTER(rs_schedule)]
+        L.rs_schedule_clear.argtypes = []
+        L.rs_schedule_clear.restype = None
         for f in ("rs_build", "rs_build_ex", "rs_lookup", "rs_blob_to_host", "rs_blob_from_host", "rs_blob_info",
                   "rs_tables", "rs_last_build_stats", "rs_build_batch", "rs_server_create", "rs_server_submit_build",
-                  "rs_server_submit_lookup", "rs_server_poll", "rs_server_wait", "rs_server_get_stats"):
+                  "rs_server_submit_lookup", "rs_server_poll", "rs_server_wait", "rs_server_get_stats", "rs_autotune",
+                  "rs_schedule_get", "rs_schedule_set"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -179,20 +191,27 @@ class Blob:
             pass
 
 
+def _options(seed_cap=0, timing=False, tuned=False, stage_from=0, group_max=0, waves=0) -> rs_options:
+    flags = (RS_OPT_TIMING if timing else 0) | (RS_OPT_TUNED if tuned else 0)
+    return rs_options(seed_cap, flags, stage_from, group_max, waves)
+
+
 def build(keys, leaf: int, bucket: int, seed_cap: int = 0, timing: bool = False, stage_from: int = 0,
-          group_max: int = 0, stream=None) -> Blob:
+          group_max: int = 0, waves: int = 0, tuned: bool = False, stream=None) -> Blob:
     """Build the minimal perfect hash function of a device key set.  With
     timing=True the per-phase device times are available from last_build_stats().
-    stage_from / group_max override the search schedule (never the result)."""
+    tuned=True takes the search schedule of (leaf, bucket) from the schedule
+    table (see autotune); stage_from / group_max / waves override it.  Schedules
+    never change the result."""
     k = _as_keys(keys)
     h = ctypes.c_void_p()
-    opts = rs_options(seed_cap, RS_OPT_TIMING if timing else 0, stage_from, group_max)
+    opts = _options(seed_cap, timing, tuned, stage_from, group_max, waves)
     _check(lib().rs_build_ex(ctypes.byref(k), leaf, bucket, ctypes.byref(opts), _stream(stream), ctypes.byref(h)))
     return Blob(h)
 
 
 def build_batch(key_sets, leafs, buckets, seed_cap: int = 0, timing: bool = False, stage_from: int = 0,
-                group_max: int = 0, stream=None):
+                group_max: int = 0, waves: int = 0, tuned: bool = False, stream=None):
     """Build many MPHFs in one call.  Returns (blobs, statuses): blobs[i] is a
     Blob or None when statuses[i] != RS_OK.  Raises only when the call itself
     fails (no build could be attempted)."""
@@ -206,13 +225,44 @@ def build_batch(key_sets, leafs, buckets, seed_cap: int = 0, timing: bool = Fals
     bk = np.ascontiguousarray(buckets, dtype=np.uint32)
     outs = (ctypes.c_void_p * count)()
     status = np.zeros(count, dtype=np.int32)
-    opts = rs_options(seed_cap, RS_OPT_TIMING if timing else 0, stage_from, group_max)
+    opts = _options(seed_cap, timing, tuned, stage_from, group_max, waves)
     rc = lib().rs_build_batch(arr, count, lf.ctypes.data, bk.ctypes.data, ctypes.byref(opts), _stream(stream),
                               ctypes.cast(outs, ctypes.c_void_p), status.ctypes.data)
     blobs = [Blob(ctypes.c_void_p(outs[i])) if outs[i] else None for i in range(count)]
     if rc != RS_OK and not any(b is not None for b in blobs) and not status.any():
         _check(rc)
     return blobs, [int(x) for x in status]
+
+
+def _schedule_dict(sc: rs_schedule) -> dict:
+    return {name: getattr(sc, name) for name, _ in rs_schedule._fields_}
+
+
+def autotune(leaf: int, bucket: int, keys_hint: int = 0, budget_ms: float = 0.0, stream=None) -> dict:
+    """Time the seed search of (leaf, bucket) on synthetic calibration keys
+    (about keys_hint of them) with several schedules, store the fastest in the
+    schedule table and return it."""
+    sc = rs_schedule()
+    _check(lib().rs_autotune(leaf, bucket, keys_hint, float(budget_ms), _stream(stream), ctypes.byref(sc)))
+    return _schedule_dict(sc)
+
+
+def get_schedule(leaf: int, bucket: int):
+    """The table's schedule of (leaf, bucket), or None."""
+    sc = rs_schedule()
+    if lib().rs_schedule_get(leaf, bucket, ctypes.byref(sc)) != RS_OK:
+        return None
+    return _schedule_dict(sc)
+
+
+def set_schedule(leaf: int, bucket: int, stage_from: int, group_max: int, waves: int):
+    """Store a schedule (for example one saved from an earlier autotune)."""
+    sc = rs_schedule(stage_from, group_max, waves)
+    _check(lib().rs_schedule_set(leaf, bucket, ctypes.byref(sc)))
+
+
+def clear_schedules():
+    lib().rs_schedule_clear()
 
 
 def lookup(blob: Blob, keys, out=None, stream=None):
@@ -250,9 +300,10 @@ class Server:
     Key tensors passed to submit_* must stay alive until the request completes;
     the server keeps a reference to them until then."""
 
-    def __init__(self, budget_bytes: int, build_workers: int = 2, stage_from: int = 0, group_max: int = 0):
+    def __init__(self, budget_bytes: int, build_workers: int = 2, stage_from: int = 0, group_max: int = 0,
+                 waves: int = 0, tuned: bool = False):
         self._h = ctypes.c_void_p()
-        opts = rs_options(0, 0, stage_from, group_max)
+        opts = _options(0, False, tuned, stage_from, group_max, waves)
         _check(lib().rs_server_create(budget_bytes, build_workers, ctypes.byref(opts), ctypes.byref(self._h)))
         self._keep = {}
 

@@ -73,3 +73,30 @@ def test_server_argument_validation(lib):
 
     out = ctypes.c_void_p()
     assert lib.rs_server_create(0, 2, None, ctypes.byref(out)) == recsplit.RS_EINVAL
+
+
+def test_schedule_table_roundtrip_and_validation(lib):
+    from paper_1910_06416_amd import recsplit
+
+    recsplit.clear_schedules()
+    assert recsplit.get_schedule(8, 100) is None
+    recsplit.set_schedule(8, 100, stage_from=7, group_max=3, waves=2)
+    got = recsplit.get_schedule(8, 100)
+    assert (got["stage_from"], got["group_max"], got["waves"]) == (7, 3, 2)
+    assert recsplit.get_schedule(8, 101) is None
+    for bad in [(7, 3, 3), (7, 0, 1), (7, 8, 1), (1, 3, 1), (26, 3, 1)]:
+        with pytest.raises(recsplit.RecSplitError):
+            recsplit.set_schedule(8, 100, *bad)
+    with pytest.raises(recsplit.RecSplitError):
+        recsplit.set_schedule(25, 100, 9, 7, 4)
+    with pytest.raises(recsplit.RecSplitError):
+        recsplit.set_schedule(8, 0, 9, 7, 4)
+    recsplit.clear_schedules()
+    assert recsplit.get_schedule(8, 100) is None
+
+
+def test_autotune_argument_validation(lib):
+    from paper_1910_06416_amd import recsplit
+
+    assert lib.rs_autotune(0, 100, 0, 10.0, None, None) == recsplit.RS_EINVAL
+    assert lib.rs_autotune(8, 0, 0, 10.0, None, None) == recsplit.RS_EINVAL

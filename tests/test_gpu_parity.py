@@ -242,3 +242,44 @@ def test_server_tiny_budget_still_completes(rs, orc):
     assert stats["max_batch"] == 1 and stats["max_concurrent_batches"] == 1  # admitted one at a time
     for (n, leaf, bucket), k, r in zip(specs, host, res):
         assert r["blob"].to_bytes() == orc.build(k, leaf, bucket)
+
+
+@pytest.mark.parametrize("n,leaf,bucket", [(20000, 8, 100), (6000, 12, 300), (3000, 16, 200), (60, 24, 12),
+                                           (5000, 5, 5)])
+def test_schedules_never_change_the_result(rs, orc, n, leaf, bucket):
+    """Every wavefront count, staged-search threshold and split lane-group cap
+    gives the oracle's blob."""
+    print(f"case schedules n={n} leaf={leaf} bucket={bucket}", flush=True)
+    keys = inputs.u64_keys(n, 3000 + n + leaf)
+    want = orc.build(keys, leaf, bucket)
+    dk = rs.device_keys(keys)
+    for waves in (1, 2, 4, 8):
+        for stage_from, group_max in [(2, 1), (7, 7), (25, 4), (9, 2)]:
+            got = rs.build(dk, leaf, bucket, waves=waves, stage_from=stage_from, group_max=group_max).to_bytes()
+            assert got == want, (waves, stage_from, group_max)
+
+
+def test_autotuned_schedules_in_builds_and_batches(rs, orc):
+    """The autotuner stores a valid schedule; builds and mixed batches that use
+    the table (different wavefront counts per build in one launch) still give
+    the oracle's blobs."""
+    print("case autotune", flush=True)
+    rs.clear_schedules()
+    sc = rs.autotune(8, 100, keys_hint=200_000, budget_ms=200)
+    assert sc["waves"] in (1, 2, 4, 8) and 2 <= sc["stage_from"] <= 25 and 1 <= sc["group_max"] <= 7
+    assert sc["variants"] >= 2 and sc["search_ms"] <= sc["default_ms"]
+    assert rs.get_schedule(8, 100)["waves"] == sc["waves"]
+    keys = inputs.u64_keys(30000, 77)
+    assert rs.build(rs.device_keys(keys), 8, 100, tuned=True).to_bytes() == orc.build(keys, 8, 100)
+    rs.set_schedule(8, 100, stage_from=7, group_max=3, waves=1)
+    rs.set_schedule(12, 300, stage_from=11, group_max=2, waves=8)
+    specs = [(5000, 8, 100), (7000, 12, 300), (3000, 8, 100), (100, 12, 300)]
+    host = [inputs.u64_keys(n, 500 + i) for i, (n, _, _) in enumerate(specs)]
+    blobs, status = rs.build_batch([rs.device_keys(k) for k in host], [s[1] for s in specs], [s[2] for s in specs],
+                                   tuned=True)
+    assert status == [0] * len(specs)
+    for b, k, (n, leaf, bucket) in zip(blobs, host, specs):
+        assert b.to_bytes() == orc.build(k, leaf, bucket)
+    with pytest.raises(rs.RecSplitError):
+        rs.build(rs.device_keys(keys), 8, 100, waves=3)
+    rs.clear_schedules()
