@@ -90,33 +90,245 @@ __device__ __forceinline__ uint32_t find_build(const uint64_t* __restrict__ base
 }
 
 // ---------------------------------------------------------------------------
-// Signatures (Sec. 6.1) and bucket histogram.
+// Signatures (Sec. 6.1) and the bin histogram.
+//
+// Keys reach bucket order by a two-level counting sort.  Buckets are grouped
+// into bins of 2^shift consecutive global bucket numbers (a few thousand keys
+// each).  The signature pass counts keys per bin in LDS and adds each block's
+// counts to the global bin counters.  The bin scatter moves (lower word, bucket) pairs
+// into bin order, a contiguous run per (block, bin).  One workgroup per bin
+// then counts its buckets in LDS, writes their prefix sums and places each key
+// in its bucket.  Order inside a bucket is irrelevant: every later step is a
+// function of the bucket's key set.
 // ---------------------------------------------------------------------------
-__global__ void k_signature(const BuildDesc* __restrict__ descs, BuildDesc* __restrict__ wdescs,
-                            const uint64_t* __restrict__ key_base, uint32_t count, uint64_t total,
-                            uint64_t* __restrict__ lo_out, uint32_t* __restrict__ bid,
-                            uint32_t* __restrict__ counts) {
-    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= total) return;
-    const uint32_t j = find_build(key_base, count, i);
-    const BuildDesc& B = descs[j];
-    const uint64_t k = i - B.key_base;
-    uint64_t hi, lo;
-    if (B.kind == RS_KEYS_U64) {
-        signature_u64(static_cast<const uint64_t*>(B.data)[k], hi, lo);
-    } else {
-        const uint64_t* off = B.offsets;
-        uint64_t s = off[k], e = off[k + 1], bytes = off[B.n];
-        if (e < s || e > bytes) {
-            atomicOr(&wdescs[j].flags, kFlagOffsets);
-            e = s = min(s, bytes);
+constexpr uint32_t kSigItems = 32;                 // keys per thread in the signature and bin passes
+constexpr uint32_t kSigTile = kBlock * kSigItems;  // keys per block
+constexpr uint32_t kMaxBins = 4096;
+constexpr uint32_t kMaxBinShift = 13;              // at most 8192 buckets per bin
+constexpr uint32_t kSortBlock = 512;               // threads of the per-bin sort
+
+// dynamic LDS: nbins u32 counters
+__global__ __launch_bounds__(kBlock) void k_signature(const BuildDesc* __restrict__ descs, BuildDesc* __restrict__ wdescs,
+                                                     const uint64_t* __restrict__ key_base, uint32_t count,
+                                                     uint64_t total, uint64_t* __restrict__ lo_out,
+                                                     uint32_t* __restrict__ bid, uint32_t shift, uint32_t nbins,
+                                                     uint32_t nxcd, unsigned long long* __restrict__ bin_cnt) {
+    extern __shared__ uint32_t hist[];
+    for (uint32_t c = threadIdx.x; c < nbins; c += kBlock) hist[c] = 0;
+    __syncthreads();
+    const uint64_t tile0 = (uint64_t)blockIdx.x * kSigTile;
+    const uint64_t base = tile0 + threadIdx.x;
+    const uint64_t tile_last = min(total, tile0 + kSigTile) - 1;
+    const uint32_t j0 = __builtin_amdgcn_readfirstlane(find_build(key_base, count, tile0));
+    const uint32_t j1 = __builtin_amdgcn_readfirstlane(find_build(key_base, count, tile_last));
+    auto emit = [&](uint64_t i, const BuildDesc& B, uint64_t hi, uint64_t lo) {
+        const uint32_t b = (uint32_t)(bucket_of(hi, B.nb) + B.bucket_base);
+        lo_out[i] = lo;
+        bid[i] = b;
+        atomicAdd(&hist[b >> shift], 1u);
+    };
+    constexpr uint32_t kGroup = 8;
+    if (j0 == j1) {
+        // the whole tile belongs to one build: groups of independent loads
+        const BuildDesc& B = descs[j0];
+        const uint64_t kb = B.key_base;
+        if (B.kind == RS_KEYS_U64) {
+            const uint64_t* keys = static_cast<const uint64_t*>(B.data);
+#pragma unroll
+            for (uint32_t g = 0; g < kSigItems; g += kGroup) {
+                uint64_t key[kGroup];
+#pragma unroll
+                for (uint32_t u = 0; u < kGroup; u++) {
+                    const uint64_t i = base + (uint64_t)(g + u) * kBlock;
+                    key[u] = i < total ? keys[i - kb] : 0;
+                }
+#pragma unroll
+                for (uint32_t u = 0; u < kGroup; u++) {
+                    const uint64_t i = base + (uint64_t)(g + u) * kBlock;
+                    if (i >= total) continue;
+                    uint64_t hi, lo;
+                    signature_u64(key[u], hi, lo);
+                    emit(i, B, hi, lo);
+                }
+            }
+        } else {
+            const uint64_t* off = B.offsets;
+            const uint8_t* data = static_cast<const uint8_t*>(B.data);
+            const uint64_t bytes = off[B.n];
+            const bool aligned = B.aligned != 0;
+            for (uint32_t g = 0; g < kSigItems; g += kGroup) {
+                uint64_t st[kGroup], en[kGroup], a[kGroup], c[kGroup];
+                uint64_t longest = 0;
+#pragma unroll
+                for (uint32_t u = 0; u < kGroup; u++) {
+                    const uint64_t i = base + (uint64_t)(g + u) * kBlock;
+                    st[u] = en[u] = 0;
+                    if (i < total) {
+                        st[u] = off[i - kb];
+                        en[u] = off[i - kb + 1];
+                    }
+                }
+#pragma unroll
+                for (uint32_t u = 0; u < kGroup; u++) {
+                    if (en[u] < st[u] || en[u] > bytes) {
+                        atomicOr(&wdescs[j0].flags, kFlagOffsets);
+                        en[u] = st[u] = min(st[u], bytes);
+                    }
+                    const uint64_t len = en[u] - st[u];
+                    a[u] = kSigHi ^ len;
+                    c[u] = kSigLo ^ len;
+                    longest = max(longest, len);
+                }
+                for (uint64_t p = 0; p < longest; p += 8) {
+#pragma unroll
+                    for (uint32_t u = 0; u < kGroup; u++) {
+                        if (st[u] + p < en[u]) {
+                            const uint64_t w = string_word(data, bytes, aligned, st[u] + p, en[u]);
+                            a[u] = mix64(a[u] ^ w);
+                            c[u] = mix64(c[u] + w);
+                        }
+                    }
+                }
+#pragma unroll
+                for (uint32_t u = 0; u < kGroup; u++) {
+                    const uint64_t i = base + (uint64_t)(g + u) * kBlock;
+                    if (i < total) emit(i, B, mix64(a[u]), mix64(c[u]));
+                }
+            }
         }
-        signature_bytes(static_cast<const uint8_t*>(B.data), bytes, B.aligned != 0, s, e, hi, lo);
+    } else {
+        for (uint32_t it = 0; it < kSigItems; it++) {
+            const uint64_t i = base + (uint64_t)it * kBlock;
+            if (i >= total) break;
+            const uint32_t j = find_build(key_base, count, i);
+            const BuildDesc& B = descs[j];
+            const uint64_t k = i - B.key_base;
+            uint64_t hi, lo;
+            if (B.kind == RS_KEYS_U64) {
+                signature_u64(static_cast<const uint64_t*>(B.data)[k], hi, lo);
+            } else {
+                const uint64_t* off = B.offsets;
+                uint64_t s = off[k], e = off[k + 1], bytes = off[B.n];
+                if (e < s || e > bytes) {
+                    atomicOr(&wdescs[j].flags, kFlagOffsets);
+                    e = s = min(s, bytes);
+                }
+                signature_bytes(static_cast<const uint8_t*>(B.data), bytes, B.aligned != 0, s, e, hi, lo);
+            }
+            emit(i, B, hi, lo);
+        }
     }
-    const uint32_t b = (uint32_t)(bucket_of(hi, B.nb) + B.bucket_base);
-    lo_out[i] = lo;
-    bid[i] = b;
-    atomicAdd(&counts[b], 1u);
+    __syncthreads();
+    const uint32_t x = blockIdx.x % nxcd;
+    for (uint32_t c = threadIdx.x; c < nbins; c += kBlock)
+        if (hist[c]) atomicAdd(&bin_cnt[c * nxcd + x], (unsigned long long)hist[c]);
+}
+
+// dynamic LDS: nbins u64 bases, then nbins u32 counters
+__global__ __launch_bounds__(kBlock) void k_bin_scatter(const uint64_t* __restrict__ lo, const uint32_t* __restrict__ bid,
+                                                       uint64_t total, uint32_t shift, uint32_t nbins,
+                                                       uint32_t nxcd, unsigned long long* __restrict__ bin_cur,
+                                                       uint64_t* __restrict__ bin_lo, uint32_t* __restrict__ bin_bid) {
+    extern __shared__ unsigned long long bases[];
+    uint32_t* hist = reinterpret_cast<uint32_t*>(bases + nbins);
+    for (uint32_t c = threadIdx.x; c < nbins; c += kBlock) hist[c] = 0;
+    __syncthreads();
+    // every load of the tile is issued before the first use (independent loads
+    // keep the memory pipeline full; a loop of dependent steps would wait on each)
+    const uint64_t base = (uint64_t)blockIdx.x * kSigTile + threadIdx.x;
+    uint32_t b[kSigItems];
+#pragma unroll
+    for (uint32_t it = 0; it < kSigItems; it++) {
+        const uint64_t i = base + (uint64_t)it * kBlock;
+        b[it] = i < total ? bid[i] : ~0u;
+    }
+#pragma unroll
+    for (uint32_t it = 0; it < kSigItems; it++)
+        if (b[it] != ~0u) atomicAdd(&hist[b[it] >> shift], 1u);
+    __syncthreads();
+    // reserve this block's run in every bin it touches, inside the part of the bin
+    // that blocks of its XCD fill (consecutive runs then meet in one L2); the
+    // counters restart as cursors
+    const uint32_t x = blockIdx.x % nxcd;
+    for (uint32_t c = threadIdx.x; c < nbins; c += kBlock) {
+        const uint32_t h = hist[c];
+        if (h) bases[c] = atomicAdd(&bin_cur[c * nxcd + x], (unsigned long long)h);
+        hist[c] = 0;
+    }
+    __syncthreads();
+    constexpr uint32_t kGroup = 8;
+#pragma unroll
+    for (uint32_t g = 0; g < kSigItems; g += kGroup) {
+        uint64_t v[kGroup];
+#pragma unroll
+        for (uint32_t u = 0; u < kGroup; u++) {
+            const uint64_t i = base + (uint64_t)(g + u) * kBlock;
+            v[u] = i < total ? lo[i] : 0;
+        }
+#pragma unroll
+        for (uint32_t u = 0; u < kGroup; u++) {
+            if (b[g + u] == ~0u) continue;
+            const uint32_t c = b[g + u] >> shift;
+            const uint64_t pos = bases[c] + atomicAdd(&hist[c], 1u);
+            bin_lo[pos] = v[u];
+            bin_bid[pos] = b[g + u];
+        }
+    }
+}
+
+// One workgroup per bin: bucket counts in LDS, their prefix sums (bstart of
+// the bin's buckets), the largest bucket, and the keys in bucket order.
+// dynamic LDS: 2 * 2^shift u32 (counts, then offsets inside the bin).
+__global__ __launch_bounds__(kSortBlock) void k_bucket_sort(const uint64_t* __restrict__ bin_start,
+                                                           const uint64_t* __restrict__ bin_lo,
+                                                           const uint32_t* __restrict__ bin_bid, uint32_t shift,
+                                                           uint64_t nbuckets, uint64_t* __restrict__ bstart,
+                                                           uint64_t* __restrict__ sorted, uint32_t* __restrict__ maxm) {
+    extern __shared__ uint32_t cnt[];
+    __shared__ uint32_t wsum[kSortBlock / 64];
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const uint64_t g0 = (uint64_t)blockIdx.x << shift;
+    const uint32_t span = (uint32_t)min<uint64_t>(1ull << shift, nbuckets - g0);
+    uint32_t* offs = cnt + (1u << shift);
+    for (uint32_t j = tid; j < span; j += kSortBlock) cnt[j] = 0;
+    __syncthreads();
+    const uint64_t s = bin_start[blockIdx.x], e = bin_start[blockIdx.x + 1];
+    for (uint64_t i = s + tid; i < e; i += kSortBlock) atomicAdd(&cnt[bin_bid[i] - (uint32_t)g0], 1u);
+    __syncthreads();
+    // exclusive scan of cnt[0, span): each thread sums a chunk, the block scans the chunk sums
+    const uint32_t chunk = (span + kSortBlock - 1) / kSortBlock;
+    const uint32_t j0 = min(span, tid * chunk), j1 = min(span, j0 + chunk);
+    uint32_t sum = 0, mx = 0;
+    for (uint32_t j = j0; j < j1; j++) {
+        sum += cnt[j];
+        mx = max(mx, cnt[j]);
+    }
+    uint32_t x = sum;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= (uint32_t)o) x += y;
+    }
+    if (lane == 63) wsum[wid] = x;
+    for (int o = 32; o > 0; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, o, 64));
+    if (lane == 0 && mx) atomicMax(maxm, mx);
+    __syncthreads();
+    uint32_t pre = 0;
+    for (uint32_t w = 0; w < wid; w++) pre += wsum[w];
+    uint32_t run = pre + x - sum;
+    for (uint32_t j = j0; j < j1; j++) {
+        offs[j] = run;
+        bstart[g0 + j] = s + run;
+        run += cnt[j];
+    }
+    if (blockIdx.x + 1 == gridDim.x && tid == 0) bstart[nbuckets] = e;
+    __syncthreads();
+    for (uint32_t j = tid; j < span; j += kSortBlock) cnt[j] = 0;
+    __syncthreads();
+    for (uint64_t i = s + tid; i < e; i += kSortBlock) {
+        const uint32_t b = bin_bid[i] - (uint32_t)g0;
+        sorted[s + offs[b] + atomicAdd(&cnt[b], 1u)] = bin_lo[i];
+    }
 }
 
 }  // namespace
@@ -197,6 +409,34 @@ __global__ __launch_bounds__(kBlock) void k_scan_tile_sums(uint64_t* sums, uint6
     }
 }
 
+// Single block: exclusive prefix sums of the (bin, XCD) counters in bin-major
+// order.  bin_cur receives them (each XCD's part of each bin starts there) and
+// bin_start[c] the start of bin c (nbins + 1 entries).
+__global__ __launch_bounds__(kBlock) void k_bin_offsets(const unsigned long long* __restrict__ bin_cnt,
+                                                       uint32_t nbins, uint32_t nxcd,
+                                                       uint64_t* __restrict__ bin_start,
+                                                       unsigned long long* __restrict__ bin_cur) {
+    __shared__ uint64_t carry_s;
+    if (threadIdx.x == 0) carry_s = 0;
+    __syncthreads();
+    const uint32_t n = nbins * nxcd;
+    for (uint32_t base = 0; base < n; base += kBlock) {
+        const uint32_t i = base + threadIdx.x;
+        const uint64_t v = i < n ? bin_cnt[i] : 0;
+        uint64_t tot;
+        const uint64_t ex = block_exclusive_sum(v, &tot);
+        const uint64_t carry = carry_s;
+        if (i < n) {
+            bin_cur[i] = carry + ex;
+            if (i % nxcd == 0) bin_start[i / nxcd] = carry + ex;
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) carry_s = carry + tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) bin_start[nbins] = carry_s;
+}
+
 // out[i] = sum_{j<i} in[j] for i in [0, n]; each thread owns kScanItems
 // consecutive items of the block's tile.
 template <typename T>
@@ -223,19 +463,6 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(const T* __restrict__ in,
     }
 }
 
-// ---------------------------------------------------------------------------
-// Scatter into bucket-contiguous order (order inside a bucket is irrelevant:
-// every later step is a function of the bucket's key set).
-// ---------------------------------------------------------------------------
-__global__ void k_scatter(const uint64_t* __restrict__ lo, const uint32_t* __restrict__ bid, uint64_t n,
-                          const uint64_t* __restrict__ bstart, uint32_t* __restrict__ cursor,
-                          uint64_t* __restrict__ sorted) {
-    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    uint32_t b = bid[i];
-    uint64_t pos = bstart[b] + atomicAdd(&cursor[b], 1u);
-    sorted[pos] = lo[i];
-}
 
 // ---------------------------------------------------------------------------
 // Seed search (Sec. 4, 5): one 64-lane wavefront per bucket walks the bucket's
@@ -999,7 +1226,7 @@ thread_local rs_build_stats g_stats;
 thread_local bool g_stats_valid = false;
 
 struct PhaseEvents {
-    hipEvent_t ev[6] = {};
+    hipEvent_t ev[7] = {};
     bool on = false;
     int create(bool enable) {
         on = enable;
@@ -1030,6 +1257,20 @@ int max_lds_bytes() {
         (void)hipGetDevice(&dev);
         hipDeviceProp_t prop;
         v = hipGetDeviceProperties(&prop, dev) == hipSuccess ? (int)prop.sharedMemPerBlock : 65536;
+    });
+    return v;
+}
+
+// Accelerator complex dies (XCDs) of the current device; workgroups of a
+// one-dimensional grid are dealt to them round-robin by workgroup number.
+uint32_t xcd_count() {
+    static uint32_t v = 0;
+    static std::once_flag once;
+    std::call_once(once, [] {
+        int dev = 0, x = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&x, hipDeviceAttributeNumberOfXccs, dev) != hipSuccess) x = 1;
+        v = (uint32_t)std::min(std::max(x, 1), 16);
     });
     return v;
 }
@@ -1310,6 +1551,15 @@ int build_batch_impl(const rs_keys* sets, uint32_t count, const uint32_t* leafs,
     PhaseEvents pe;
     if (int rc0 = pe.create(timing)) return rc0;
 
+    // bins of the two-level bucket sort: about 16k keys each, at most kMaxBins
+    const double keys_per_bucket = (double)total / (double)nbuckets;
+    uint32_t shift = 0;
+    while (shift < kMaxBinShift && (double)(2ull << shift) * keys_per_bucket <= 16384.0) shift++;
+    while (shift < kMaxBinShift && ((nbuckets + (1ull << shift) - 1) >> shift) > kMaxBins) shift++;
+    const uint64_t nbins64 = (nbuckets + (1ull << shift) - 1) >> shift;
+    if (nbins64 > kMaxBins) return fail(RS_EINVAL, "too many buckets in one call");
+    const uint32_t nbins = (uint32_t)nbins64;
+
     // workspace
     const uint64_t ntiles = (nbuckets + 1 + kScanTile - 1) / kScanTile + 1;
     size_t off = 0;
@@ -1318,8 +1568,10 @@ int build_batch_impl(const rs_keys* sets, uint32_t count, const uint32_t* leafs,
         off += (bytes + 255) & ~size_t(255);
         return o;
     };
-    const size_t o_lo = carve(total * 8), o_bid = carve(total * 4), o_cnt = carve(nbuckets * 4),
-                 o_cur = carve(nbuckets * 4), o_bst = carve((nbuckets + 1) * 8), o_sorted = carve(total * 8),
+    const uint32_t nxcd = xcd_count();
+    const size_t o_lo = carve(total * 8), o_bid = carve(total * 4), o_bincnt = carve((size_t)nbins * nxcd * 8),
+                 o_binst = carve((nbins + 1) * 8ull), o_bincur = carve((size_t)nbins * nxcd * 8),
+                 o_bst = carve((nbuckets + 1) * 8), o_sorted = carve(total * 8),
                  o_tmp = carve(total * 8), o_seeds = carve(total * 8), o_blen = carve(nbuckets * 8),
                  o_ost = carve((nbuckets + 1) * 8), o_tiles = carve(ntiles * 8), o_st = carve(sizeof(DevStatus)),
                  o_desc = carve(K * sizeof(BuildDesc)), o_kb = carve(3 * (K + 1) * 8),
@@ -1328,12 +1580,16 @@ int build_batch_impl(const rs_keys* sets, uint32_t count, const uint32_t* leafs,
     if (int rc0 = dev_alloc((void**)&ws, off, s)) return rc0;
     uint64_t* d_lo = (uint64_t*)(ws + o_lo);
     uint32_t* d_bid = (uint32_t*)(ws + o_bid);
-    uint32_t* d_cnt = (uint32_t*)(ws + o_cnt);
-    uint32_t* d_cur = (uint32_t*)(ws + o_cur);
+    unsigned long long* d_bincnt = (unsigned long long*)(ws + o_bincnt);
+    uint64_t* d_binst = (uint64_t*)(ws + o_binst);
+    unsigned long long* d_bincur = (unsigned long long*)(ws + o_bincur);
     uint64_t* d_bst = (uint64_t*)(ws + o_bst);
     uint64_t* d_sorted = (uint64_t*)(ws + o_sorted);
     uint64_t* d_tmp = (uint64_t*)(ws + o_tmp);
     uint64_t* d_seeds = (uint64_t*)(ws + o_seeds);
+    // before the search, the partition scratch and the index array hold the keys in bin order
+    uint64_t* d_binlo = d_tmp;
+    uint32_t* d_binbid = (uint32_t*)d_seeds;
     uint64_t* d_blen = (uint64_t*)(ws + o_blen);
     uint64_t* d_ost = (uint64_t*)(ws + o_ost);
     uint64_t* d_tiles = (uint64_t*)(ws + o_tiles);
@@ -1385,11 +1641,18 @@ int build_batch_impl(const rs_keys* sets, uint32_t count, const uint32_t* leafs,
     RS_TRY(hipMemcpyAsync(d_desc, pin, desc_bytes, hipMemcpyHostToDevice, s));
     RS_TRY(hipMemcpyAsync(d_kb, h_kb, 3 * (K + 1) * 8, hipMemcpyHostToDevice, s));
     k_init_status<<<1, 64, 0, s>>>(d_st);
-    k_fill_u32<<<grid_for(nbuckets, kBlock * 4), kBlock, 0, s>>>(d_cnt, nbuckets, 0);
-    k_fill_u32<<<grid_for(nbuckets, kBlock * 4), kBlock, 0, s>>>(d_cur, nbuckets, 0);
-    k_signature<<<grid_for(total, kBlock), kBlock, 0, s>>>(d_desc, d_desc, d_kb, K, total, d_lo, d_bid, d_cnt);
+    k_fill_u64<<<grid_for((uint64_t)nbins * nxcd, kBlock * 4), kBlock, 0, s>>>((uint64_t*)d_bincnt,
+                                                                               (uint64_t)nbins * nxcd, 0);
+    k_signature<<<grid_for(total, kSigTile), kBlock, nbins * 4, s>>>(d_desc, d_desc, d_kb, K, total, d_lo, d_bid,
+                                                                      shift, nbins, nxcd, d_bincnt);
+    pe.record(1, s);
+    k_bin_offsets<<<1, kBlock, 0, s>>>(d_bincnt, nbins, nxcd, d_binst, d_bincur);
+    k_bin_scatter<<<grid_for(total, kSigTile), kBlock, nbins * 12, s>>>(d_lo, d_bid, total, shift, nbins, nxcd,
+                                                                        d_bincur, d_binlo, d_binbid);
+    k_bucket_sort<<<nbins, kSortBlock, (8u << shift), s>>>(d_binst, d_binlo, d_binbid, shift, nbuckets, d_bst,
+                                                          d_sorted, &d_st->maxm);
+    pe.record(2, s);
     RS_TRY(hipGetLastError());
-    if (int rc = scan<uint32_t>(d_cnt, nbuckets, d_bst, d_tiles, &d_st->maxm, s)) return cleanup(rc);
     RS_TRY(hipMemcpyAsync(h_st, d_st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
     RS_TRY(hipMemcpyAsync(pin, d_desc, desc_bytes, hipMemcpyDeviceToHost, s));
     RS_TRACE("signatures enqueued; waiting for the largest bucket");
@@ -1421,9 +1684,7 @@ int build_batch_impl(const rs_keys* sets, uint32_t count, const uint32_t* leafs,
     // keys + node slots in dynamic LDS (the launch checks the static part too)
     const size_t lds = (size_t)maxm * 8 + (size_t)max_nodes * 16;
 
-    pe.record(1, s);
-    k_scatter<<<grid_for(total, kBlock), kBlock, 0, s>>>(d_lo, d_bid, total, d_bst, d_cur, d_sorted);
-    pe.record(2, s);
+    pe.record(3, s);
     SearchArgs sa{d_sorted, d_tmp, d_bst, d_seeds, d_blen, d_desc, d_desc, d_bb, K, nbuckets,
                   d_tab, stride, cap, maxm};
     if (tune) {  // calibration only: no blob, the tables are not handed to an arena
@@ -1434,11 +1695,11 @@ int build_batch_impl(const rs_keys* sets, uint32_t count, const uint32_t* leafs,
     }
     int rc = launch_search(max_leaf, launch_waves, sa, lds, s);
     if (rc) return cleanup(rc);
-    pe.record(3, s);
+    pe.record(4, s);
     if ((rc = scan<uint64_t>(d_blen, nbuckets, d_ost, d_tiles, nullptr, s))) return cleanup(rc);
     GapArgs ga{d_bst, d_ost, d_desc, d_desc, d_bb, K, nbuckets};
     k_ef_gaps<<<grid_for(nbuckets, kBlock), kBlock, 0, s>>>(ga);
-    pe.record(4, s);
+    pe.record(5, s);
     RS_TRY(hipGetLastError());
     RS_TRY(hipMemcpyAsync(pin, d_desc, desc_bytes, hipMemcpyDeviceToHost, s));
     RS_TRACE("search enqueued (class %u); waiting for the sizes", max_leaf);
@@ -1509,16 +1770,16 @@ int build_batch_impl(const rs_keys* sets, uint32_t count, const uint32_t* leafs,
         k_tree_bits<<<grid_for(nbuckets, 64), 64, 0, s>>>(fa);
         RS_TRY(hipGetLastError());
     }
-    pe.record(5, s);
+    pe.record(6, s);
     RS_TRACE("fill enqueued (%llu blob words)", (unsigned long long)arena_words);
     if (timing) {
         RS_TRY(hipStreamSynchronize(s));
         g_stats.ms_signature = pe.ms(0, 1);
         g_stats.ms_scatter = pe.ms(1, 2);
-        g_stats.ms_search = pe.ms(2, 3);
-        g_stats.ms_offsets = pe.ms(3, 4);
-        g_stats.ms_fill = pe.ms(4, 5);
-        g_stats.ms_device = pe.ms(0, 5);
+        g_stats.ms_search = pe.ms(3, 4);
+        g_stats.ms_offsets = pe.ms(4, 5);
+        g_stats.ms_fill = pe.ms(5, 6);
+        g_stats.ms_device = pe.ms(0, 6);
         g_stats.n = total;
         g_stats.nb = nbuckets;
         g_stats.maxm = maxm;
