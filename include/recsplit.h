@@ -179,6 +179,35 @@ int rs_build_ex(const rs_keys* keys, uint32_t leaf, uint32_t bucket, const rs_op
 int rs_build_batch(const rs_keys* sets, uint32_t count, const uint32_t* leaf, const uint32_t* bucket,
                    const rs_options* opts, void* stream, rs_blob** outs, int* per_build_status);
 
+/* Build plans: the whole construction of a fixed batch shape (the same key
+ * buffers, sizes, l and b) captured once into a HIP graph, for callers that
+ * rebuild the same sets again and again as their contents change.  A run is
+ * one graph launch and one wait, with no host round trip between phases.
+ *   rs_plan_create: makes an ordinary rs_build_batch first; its blobs go to
+ *     first_outs (NULL: freed) and its statuses to per_build_status.  The plan
+ *     then sizes the search for a bucket cap (the largest bucket seen plus
+ *     four standard deviations of a Poisson count, within the local data
+ *     share) and the blob arena for a word cap (the blobs' words plus 1/8),
+ *     and captures every phase on a stream of its own.  Fails, without a plan,
+ *     if any build of the first call fails.  The key buffers in sets must stay
+ *     allocated, at the same addresses and sizes, until rs_plan_destroy.
+ *   rs_plan_run: rebuilds every set from the buffers' current contents on
+ *     stream and returns new blobs, exactly as rs_build_batch would (and owned
+ *     like them).  If a bucket or the blobs exceed the caps, that run falls
+ *     back to an ordinary rs_build_batch (counted in rs_plan_info).  One
+ *     thread at a time per plan.
+ *   rs_plan_info: bucket cap, arena words, runs and fallbacks so far.
+ * Errors: RS_EINVAL, RS_ENOMEM, RS_EDEVICE, and the build errors of
+ * rs_build_batch. */
+typedef struct rs_plan rs_plan;
+int rs_plan_create(const rs_keys* sets, uint32_t count, const uint32_t* leaf, const uint32_t* bucket,
+                   const rs_options* opts, void* stream, rs_plan** out, rs_blob** first_outs,
+                   int* per_build_status);
+int rs_plan_run(rs_plan* plan, void* stream, rs_blob** outs, int* per_build_status);
+int rs_plan_info(const rs_plan* plan, uint32_t* bucket_cap, uint64_t* capacity_words, uint64_t* runs,
+                 uint64_t* fallbacks);
+void rs_plan_destroy(rs_plan* plan);
+
 /* Rank of each query (lookup of Sec. 4 and Sec. 6.2): ranks_dev[i] = f(queries[i]).
  * Members of the built set get distinct values in [0, n).  Other keys get a
  * deterministic value in [0, n] (n only when their bucket is the last one and

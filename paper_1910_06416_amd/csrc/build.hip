@@ -12,6 +12,7 @@
 #include <atomic>
 #include <chrono>
 #include <string>
+#include <type_traits>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
@@ -30,18 +31,16 @@ constexpr int kBlock = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kBlock * kScanItems;
 
-__global__ void k_init_status(DevStatus* st) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
+// Status words of a call and n zeroed counters.
+__global__ void k_reset(DevStatus* st, unsigned long long* counters, uint64_t n) {
+    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) {
         st->maxm = 0;
         st->flags = 0;
         st->delta_s = ~0ull;
         st->delta_z = 0x7fffffffffffffffll;
     }
-}
-
-__global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
-    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (; i < n; i += (uint64_t)gridDim.x * blockDim.x) p[i] = v;
+    for (; i < n; i += (uint64_t)gridDim.x * blockDim.x) counters[i] = 0;
 }
 
 __global__ void k_fill_u64(uint64_t* p, uint64_t n, uint64_t v) {
@@ -65,7 +64,7 @@ struct BuildDesc {
     uint32_t stage_from;  // leaves of at least this many keys use the staged bijection search
     uint32_t group_cap;   // cap on log2 lanes per split candidate
     uint32_t waves;       // wavefronts of the bucket's workgroup that take nodes
-    uint32_t spare;
+    uint32_t bucket;      // the caller's bucket size b (header word)
     // written by the device
     uint32_t maxm, flags;
     unsigned long long delta_s;
@@ -891,6 +890,13 @@ __global__ __launch_bounds__(64 * WAVES) void k_search(SearchArgs a) {
         uint32_t* bflags = &a.wdescs[j].flags;
         const uint64_t start = a.bstart[b];
         const uint32_t m0 = (uint32_t)(a.bstart[b + 1] - start);
+        if (m0 > a.key_words) {  // larger than the LDS this launch was sized for (a reused plan)
+            if (threadIdx.x == 0) {
+                atomicOr(bflags, kFlagTooBig);
+                a.blen[b] = 0;
+            }
+            return;
+        }
         const uint32_t total = Nt[m0];
         for (uint32_t i = threadIdx.x; i < m0; i += 64 * WAVES) lds_keys[i] = a.sorted[start + i];
         for (uint32_t i = threadIdx.x; i < total; i += 64 * WAVES) slots[i].m = 0;
@@ -1028,42 +1034,107 @@ struct GapArgs {
     uint64_t nbuckets;
 };
 
-__global__ void k_ef_gaps(GapArgs a) {
-    const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    uint32_t j = 0;
-    unsigned long long gs = ~0ull;
-    long long gz = 0x7fffffffffffffffll;
-    uint32_t mx = 0;
-    if (g < a.nbuckets) {
-        j = find_build(a.bucket_base, a.count, g);
-        const BuildDesc& B = a.descs[j];
-        const uint64_t bb = B.bucket_base, s0 = a.bstart[bb], o0 = a.ostart[bb];
-        const uint64_t bits = a.ostart[bb + B.nb] - o0;
-        const uint64_t beta = (bits << 16) / B.n;
-        const uint64_t s_i = a.bstart[g] - s0, s_i1 = a.bstart[g + 1] - s0;
-        gs = s_i1 - s_i;
-        gz = z_of(a.ostart[g + 1] - o0, s_i1, beta) - z_of(a.ostart[g] - o0, s_i, beta);
-        mx = (uint32_t)gs;
-        if (g == bb) a.wdescs[j].total_bits = bits;
-    }
-    // reduce over the wavefront when all its lanes belong to one build
-    const uint32_t j0 = __builtin_amdgcn_readfirstlane(j);
-    const bool same = __ballot(g < a.nbuckets && j != j0) == 0;
-    if (same) {
+// Gap, size and bit-length statistics of one bucket g (0 <= g < nbuckets).
+struct GapStat {
+    unsigned long long gs;
+    long long gz;
+    uint32_t mx;
+};
+
+__device__ __forceinline__ GapStat gap_of(const GapArgs& a, uint32_t j, uint64_t g) {
+    const BuildDesc& B = a.descs[j];
+    const uint64_t bb = B.bucket_base, s0 = a.bstart[bb], o0 = a.ostart[bb];
+    const uint64_t bits = a.ostart[bb + B.nb] - o0;
+    const uint64_t beta = (bits << 16) / B.n;
+    const uint64_t s_i = a.bstart[g] - s0, s_i1 = a.bstart[g + 1] - s0;
+    GapStat r;
+    r.gs = s_i1 - s_i;
+    r.gz = z_of(a.ostart[g + 1] - o0, s_i1, beta) - z_of(a.ostart[g] - o0, s_i, beta);
+    r.mx = (uint32_t)r.gs;
+    if (g == bb) a.wdescs[j].total_bits = bits;
+    return r;
+}
+
+constexpr uint32_t kGapItems = 8;  // buckets per thread
+constexpr uint32_t kGapTile = kBlock * kGapItems;
+
+// Minimum gaps of both Elias-Fano sequences, largest bucket and total tree
+// bits of every build.  A block whose buckets all belong to one build reduces
+// in LDS and updates the build with one atomic per statistic (many buckets
+// per build would otherwise all update the same three words).
+__global__ __launch_bounds__(kBlock) void k_ef_gaps(GapArgs a) {
+    __shared__ unsigned long long r_gs[kBlock / 64];
+    __shared__ long long r_gz[kBlock / 64];
+    __shared__ uint32_t r_mx[kBlock / 64];
+    const uint64_t tile = (uint64_t)blockIdx.x * kGapTile;
+    const uint64_t last = min(a.nbuckets, tile + kGapTile) - 1;
+    const uint32_t j0 = __builtin_amdgcn_readfirstlane(find_build(a.bucket_base, a.count, tile));
+    const uint32_t j1 = __builtin_amdgcn_readfirstlane(find_build(a.bucket_base, a.count, last));
+    const uint32_t lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (j0 == j1) {
+        unsigned long long gs = ~0ull;
+        long long gz = 0x7fffffffffffffffll;
+        uint32_t mx = 0;
+        for (uint32_t k = 0; k < kGapItems; k++) {
+            const uint64_t g = tile + (uint64_t)k * kBlock + threadIdx.x;
+            if (g < a.nbuckets) {
+                const GapStat r = gap_of(a, j0, g);
+                gs = min(gs, r.gs);
+                gz = min(gz, r.gz);
+                mx = max(mx, r.mx);
+            }
+        }
         for (int off = 32; off > 0; off >>= 1) {
             gs = min(gs, (unsigned long long)__shfl_xor(gs, off, 64));
             gz = min(gz, (long long)__shfl_xor(gz, off, 64));
             mx = max(mx, (uint32_t)__shfl_xor((int)mx, off, 64));
         }
-        if ((threadIdx.x & 63) == 0 && gs != ~0ull) {
-            atomicMin(&a.wdescs[j0].delta_s, gs);
-            atomicMin(&a.wdescs[j0].delta_z, gz);
-            atomicMax(&a.wdescs[j0].maxm, mx);
+        if (lane == 0) {
+            r_gs[wid] = gs;
+            r_gz[wid] = gz;
+            r_mx[wid] = mx;
         }
-    } else if (g < a.nbuckets) {
-        atomicMin(&a.wdescs[j].delta_s, gs);
-        atomicMin(&a.wdescs[j].delta_z, gz);
-        atomicMax(&a.wdescs[j].maxm, mx);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (uint32_t w = 1; w < kBlock / 64; w++) {
+                gs = min(gs, r_gs[w]);
+                gz = min(gz, r_gz[w]);
+                mx = max(mx, r_mx[w]);
+            }
+            if (gs != ~0ull) {
+                atomicMin(&a.wdescs[j0].delta_s, gs);
+                atomicMin(&a.wdescs[j0].delta_z, gz);
+                atomicMax(&a.wdescs[j0].maxm, mx);
+            }
+        }
+        return;
+    }
+    // the block spans several builds: reduce per wavefront where its lanes share a build
+    for (uint32_t k = 0; k < kGapItems; k++) {
+        const uint64_t g = tile + (uint64_t)k * kBlock + threadIdx.x;
+        uint32_t j = 0;
+        GapStat r{~0ull, 0x7fffffffffffffffll, 0};
+        if (g < a.nbuckets) {
+            j = find_build(a.bucket_base, a.count, g);
+            r = gap_of(a, j, g);
+        }
+        const uint32_t jw = __builtin_amdgcn_readfirstlane(j);
+        if (__ballot(g < a.nbuckets && j != jw) == 0) {
+            for (int off = 32; off > 0; off >>= 1) {
+                r.gs = min(r.gs, (unsigned long long)__shfl_xor(r.gs, off, 64));
+                r.gz = min(r.gz, (long long)__shfl_xor(r.gz, off, 64));
+                r.mx = max(r.mx, (uint32_t)__shfl_xor((int)r.mx, off, 64));
+            }
+            if (lane == 0 && r.gs != ~0ull) {
+                atomicMin(&a.wdescs[jw].delta_s, r.gs);
+                atomicMin(&a.wdescs[jw].delta_z, r.gz);
+                atomicMax(&a.wdescs[jw].maxm, r.mx);
+            }
+        } else if (g < a.nbuckets) {
+            atomicMin(&a.wdescs[j].delta_s, r.gs);
+            atomicMin(&a.wdescs[j].delta_z, r.gz);
+            atomicMax(&a.wdescs[j].maxm, r.mx);
+        }
     }
 }
 
@@ -1162,6 +1233,100 @@ __global__ void k_write_headers(const BuildDesc* descs, const uint64_t* headers,
     if (descs[j].blob) descs[j].blob[w] = headers[t];
 }
 
+// Elias-Fano lower width: the largest W >= 0 with N * 2^W <= U.
+__device__ uint32_t ef_width(uint64_t N, uint64_t U) {
+    uint32_t W = 0;
+    while (W < 62 && (N << (W + 1)) >> (W + 1) == N && (N << (W + 1)) <= U) W++;
+    return W;
+}
+
+// Blob geometry of every build once its sizes are known: beta, the
+// Elias-Fano widths, the header words, the word offsets of the arrays and the
+// blob's size (raw_words; rounded up to 256 bytes in the arena).  Builds with
+// an error flag get no blob (size 0).  One block: builds are taken 256 at a
+// time and their rounded sizes are scanned into the arena offsets off[0..K].
+__device__ uint64_t geometry_of(BuildDesc& d, uint64_t* h) {
+    const uint64_t n = d.n, nb = d.nb, N = nb + 1, bits = d.total_bits;
+    const uint64_t beta = (bits << 16) / n;
+    const uint64_t ys_last = n - nb * (uint64_t)d.delta_s;
+    const int64_t z_last = (int64_t)bits - (int64_t)((beta * n) >> 16);
+    const uint64_t yz_last = (uint64_t)(z_last - (int64_t)nb * (int64_t)d.delta_z);
+    const uint32_t Ws = ef_width(N, ys_last), Wz = ef_width(N, yz_last);
+    h[0] = kMagic;
+    h[1] = kVersion | ((uint64_t)d.kind << 32);
+    h[2] = n;
+    h[3] = d.leaf;
+    h[4] = d.bucket;
+    h[5] = nb;
+    h[6] = d.maxm;
+    h[7] = (uint64_t)Ws | ((uint64_t)Wz << 8);
+    h[8] = d.delta_s;
+    h[9] = (uint64_t)d.delta_z;
+    h[10] = beta;
+    const uint64_t us_words = ((ys_last >> Ws) + N + 63) / 64, uz_words = ((yz_last >> Wz) + N + 63) / 64;
+    const uint64_t lower_words = (N * (Ws + Wz) + 63) / 64 + 1, tree_words = (bits + 63) / 64 + 1;
+    h[11] = us_words;
+    h[12] = uz_words;
+    h[13] = lower_words;
+    h[14] = tree_words;
+    h[15] = bits;
+    const uint64_t ninv = (N + (1u << kInvShift) - 1) >> kInvShift;
+    d.beta = beta;
+    d.Ws = Ws;
+    d.Wz = Wz;
+    d.lower_off = kHeaderWords;
+    d.us_off = d.lower_off + lower_words;
+    d.uz_off = d.us_off + us_words;
+    d.invs_off = d.uz_off + uz_words;
+    d.invz_off = d.invs_off + ninv;
+    d.tree_off = d.invz_off + ninv;
+    return d.tree_off + tree_words;
+}
+
+__global__ __launch_bounds__(kBlock) void k_layout(BuildDesc* __restrict__ descs, uint32_t count,
+                                                  uint64_t* __restrict__ hdr, uint64_t* __restrict__ raw_words,
+                                                  uint64_t* __restrict__ off) {
+    __shared__ uint64_t carry_s;
+    if (threadIdx.x == 0) carry_s = 0;
+    __syncthreads();
+    for (uint32_t base = 0; base < count; base += kBlock) {
+        const uint32_t j = base + threadIdx.x;
+        uint64_t w = 0;
+        if (j < count) {
+            BuildDesc& d = descs[j];
+            uint64_t raw = 0;
+            if (!(d.flags & (kFlagDuplicate | kFlagSearch | kFlagOffsets | kFlagStack | kFlagTooBig)))
+                raw = geometry_of(d, hdr + (size_t)j * kHeaderWords);
+            raw_words[j] = raw;
+            w = (raw + 31) & ~uint64_t(31);
+        }
+        uint64_t tot;
+        const uint64_t ex = block_exclusive_sum(w, &tot);
+        const uint64_t carry = carry_s;
+        if (j < count) off[j] = carry + ex;
+        __syncthreads();
+        if (threadIdx.x == 0) carry_s = carry + tot;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) off[count] = carry_s;
+}
+
+// Blob addresses inside an arena of `capacity` words at the scanned offsets;
+// a build that does not fit gets no blob and raises the capacity flag.
+__global__ void k_set_blobs(BuildDesc* __restrict__ descs, uint32_t count, unsigned long long* arena,
+                            const uint64_t* __restrict__ off, uint64_t capacity, uint32_t* __restrict__ flags) {
+    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= count) return;
+    if (!arena || off[j + 1] == off[j]) {
+        descs[j].blob = nullptr;
+    } else if (off[j + 1] > capacity) {
+        descs[j].blob = nullptr;
+        atomicOr(flags, kFlagCapacity);
+    } else {
+        descs[j].blob = arena + off[j];
+    }
+}
+
 uint32_t grid_for(uint64_t n, uint32_t block) { return (uint32_t)std::max<uint64_t>(1, (n + block - 1) / block); }
 
 // Exclusive scan of n values into out[0..n]; tiles holds ceil(n/kScanTile)+1 words.
@@ -1175,11 +1340,6 @@ int scan(const T* in, uint64_t n, uint64_t* out, uint64_t* tiles, uint32_t* maxo
     return RS_OK;
 }
 
-uint32_t ef_width(uint64_t N, uint64_t U) {
-    uint32_t W = 0;
-    while (W < 62 && (N << (W + 1)) >> (W + 1) == N && (N << (W + 1)) <= U) W++;
-    return W;
-}
 
 // Grow-only pinned host staging buffer of the calling thread.  Copies from it
 // are asynchronous, so an event recorded after the last copy of a call guards
@@ -1297,11 +1457,28 @@ SearchKernel search_kernel(uint32_t max_leaf, uint32_t waves) {
 
 // One launch of the search over every bucket of the call: one workgroup of
 // `waves` wavefronts per bucket, `lds` bytes of dynamic LDS (keys + node slots).
+// Static LDS of a kernel (queried once: a launch may be under graph capture).
+int static_lds(const void* k, size_t* out) {
+    static std::mutex mu;
+    static std::vector<std::pair<const void*, size_t>> known;
+    std::lock_guard<std::mutex> lk(mu);
+    for (auto& e : known)
+        if (e.first == k) {
+            *out = e.second;
+            return RS_OK;
+        }
+    hipFuncAttributes attr;
+    RS_HIP(hipFuncGetAttributes(&attr, k));
+    known.emplace_back(k, attr.sharedSizeBytes);
+    *out = attr.sharedSizeBytes;
+    return RS_OK;
+}
+
 int launch_search(uint32_t max_leaf, uint32_t waves, const SearchArgs& sa, size_t lds, hipStream_t s) {
     SearchKernel k = search_kernel(max_leaf, waves);
-    hipFuncAttributes attr;
-    RS_HIP(hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(k)));
-    if (lds + attr.sharedSizeBytes > (size_t)max_lds_bytes())
+    size_t static_bytes = 0;
+    if (int rc = static_lds(reinterpret_cast<const void*>(k), &static_bytes)) return rc;
+    if (lds + static_bytes > (size_t)max_lds_bytes())
         return fail(RS_EINVAL, "largest bucket (%u keys) exceeds the local data share", sa.key_words);
     SearchArgs args = sa;
     void* params[] = {&args};
@@ -1462,22 +1639,58 @@ done:
     return rc;
 }
 
-int build_batch_impl(const rs_keys* sets, uint32_t count, const uint32_t* leafs, const uint32_t* buckets,
-                     const rs_options* opts, hipStream_t s, rs_blob** outs, int* statuses, TuneCtx* tune) {
-    if (!sets || !leafs || !buckets || !outs || count == 0) return fail(RS_EINVAL, "NULL argument or empty batch");
-    const bool timing = opts && (opts->flags & RS_OPT_TIMING);
-    const uint64_t cap = opts && opts->seed_cap ? std::min(opts->seed_cap, kDefaultSeedCap) : kDefaultSeedCap;
-    if (opts && opts->waves && opts->waves != 1 && opts->waves != 2 && opts->waves != 4 && opts->waves != 8)
-        return fail(RS_EINVAL, "waves must be 1, 2, 4 or 8");
-    std::vector<int> st(count, RS_OK);
-    std::vector<std::string> why(count);
-
-    // host descriptors of the valid builds
+// ---------------------------------------------------------------------------
+// Host orchestration.  A call validates its builds (Batch), carves one device
+// workspace and one pinned staging area for them, and enqueues the phases:
+//   front:    descriptors in, signatures, two-level sort into bucket order
+//   (the host reads the largest bucket: it sizes the tables and the LDS)
+//   back:     seed search, bit-length prefix sums, Elias-Fano statistics,
+//             blob geometry and arena offsets (all on the device)
+//   (the host reads the blob sizes and allocates the arena)
+//   fill:     blob addresses, headers, Elias-Fano bits, Golomb-Rice streams
+// A plan enqueues the same phases without the two host reads (sizes fixed by
+// caps) and captures them into one HIP graph.
+// ---------------------------------------------------------------------------
+struct Batch {
+    uint32_t count = 0;
+    std::vector<int> st;
+    std::vector<std::string> why;
     std::vector<BuildDesc> hd;
     std::vector<uint32_t> which;  // desc index -> position in the call
     std::vector<uint32_t> leaf_of_tab;
-    uint64_t total = 0, nbuckets = 0;
-    uint32_t max_leaf = 1, launch_waves = 1;
+    uint64_t total = 0, nbuckets = 0, seed_cap = kDefaultSeedCap;
+    uint32_t K = 0, max_leaf = 1, launch_waves = 1;
+    uint32_t shift = 0, nbins = 0, nxcd = 1;
+    // device workspace
+    size_t ws_bytes = 0;
+    uint64_t *d_lo = nullptr, *d_bst = nullptr, *d_sorted = nullptr, *d_tmp = nullptr, *d_seeds = nullptr;
+    uint64_t *d_blen = nullptr, *d_ost = nullptr, *d_tiles = nullptr, *d_kb = nullptr, *d_bb = nullptr;
+    uint64_t *d_eb = nullptr, *d_hdr = nullptr, *d_raw = nullptr, *d_boff = nullptr;
+    uint64_t* d_binst = nullptr;
+    uint32_t* d_bid = nullptr;
+    unsigned long long *d_bincnt = nullptr, *d_bincur = nullptr;
+    DevStatus* d_st = nullptr;
+    BuildDesc* d_desc = nullptr;
+    // pinned staging: descriptors and bases going in; descriptors, headers,
+    // blob sizes and offsets and the status words coming back
+    size_t pin_bytes = 0, io_in = 0, io_out = 0;
+    BuildDesc* h_desc = nullptr;
+    uint64_t *h_kb = nullptr, *h_hdr = nullptr, *h_raw = nullptr, *h_boff = nullptr;
+    DevStatus* h_st = nullptr;
+    // per-size tables and the search's LDS
+    uint32_t* d_tab = nullptr;
+    uint32_t stride = 0, table_maxm = 0;
+    size_t lds = 0;
+};
+
+int batch_prepare(Batch& b, const rs_keys* sets, uint32_t count, const uint32_t* leafs, const uint32_t* buckets,
+                  const rs_options* opts) {
+    if (opts && opts->waves && opts->waves != 1 && opts->waves != 2 && opts->waves != 4 && opts->waves != 8)
+        return fail(RS_EINVAL, "waves must be 1, 2, 4 or 8");
+    b.count = count;
+    b.seed_cap = opts && opts->seed_cap ? std::min(opts->seed_cap, kDefaultSeedCap) : kDefaultSeedCap;
+    b.st.assign(count, RS_OK);
+    b.why.assign(count, std::string());
     for (uint32_t c = 0; c < count; c++) {
         const rs_keys& k = sets[c];
         const uint32_t leaf = leafs[c], bucket = buckets[c];
@@ -1489,25 +1702,26 @@ int build_batch_impl(const rs_keys* sets, uint32_t count, const uint32_t* leafs,
         else if (k.kind != RS_KEYS_U64 && k.kind != RS_KEYS_BYTES) bad = "unknown key kind";
         else if (k.kind == RS_KEYS_BYTES && !k.offsets) bad = "NULL offsets for byte keys";
         if (bad) {
-            st[c] = RS_EINVAL;
-            why[c] = bad;
+            b.st[c] = RS_EINVAL;
+            b.why[c] = bad;
             continue;
         }
         BuildDesc d{};
         d.data = k.data;
         d.offsets = k.offsets;
         d.n = k.n;
-        d.key_base = total;
+        d.key_base = b.total;
         d.nb = (k.n + bucket - 1) / bucket;
-        d.bucket_base = nbuckets;
+        d.bucket_base = b.nbuckets;
         d.kind = k.kind;
         const Strategy sg = make_strategy(leaf);
         d.leaf = leaf;
         d.lower = sg.lower;
         d.upper = sg.upper;
+        d.bucket = bucket;
         uint32_t t = 0;
-        while (t < leaf_of_tab.size() && leaf_of_tab[t] != leaf) t++;
-        if (t == leaf_of_tab.size()) leaf_of_tab.push_back(leaf);
+        while (t < b.leaf_of_tab.size() && b.leaf_of_tab[t] != leaf) t++;
+        if (t == b.leaf_of_tab.size()) b.leaf_of_tab.push_back(leaf);
         d.tab = t;
         d.aligned = ((uintptr_t)k.data & 7) == 0;
         d.delta_s = ~0ull;
@@ -1515,8 +1729,8 @@ int build_batch_impl(const rs_keys* sets, uint32_t count, const uint32_t* leafs,
         // search schedule: built-in, else the table's (RS_OPT_TUNED), then the overrides
         rs_schedule sc = builtin_schedule(leaf);
         if (opts && (opts->flags & RS_OPT_TUNED)) {
-            rs_schedule t;
-            if (schedule_lookup(leaf, bucket, &t)) sc = t;
+            rs_schedule tuned;
+            if (schedule_lookup(leaf, bucket, &tuned)) sc = tuned;
         }
         if (opts && opts->stage_from) sc.stage_from = opts->stage_from;
         if (opts && opts->group_max) sc.group_max = std::min<uint32_t>(opts->group_max, 7);
@@ -1524,89 +1738,302 @@ int build_batch_impl(const rs_keys* sets, uint32_t count, const uint32_t* leafs,
         d.stage_from = sc.stage_from;
         d.group_cap = sc.group_max - 1;
         d.waves = sc.waves;
-        launch_waves = std::max(launch_waves, sc.waves);
-        total += d.n;
-        nbuckets += d.nb;
-        max_leaf = std::max(max_leaf, leaf);
-        hd.push_back(d);
-        which.push_back(c);
+        b.launch_waves = std::max(b.launch_waves, sc.waves);
+        b.total += d.n;
+        b.nbuckets += d.nb;
+        b.max_leaf = std::max(b.max_leaf, leaf);
+        b.hd.push_back(d);
+        b.which.push_back(c);
     }
-    auto finish = [&](int rc) {
-        int first = RS_OK;
-        for (uint32_t c = 0; c < count; c++) {
-            if (statuses) statuses[c] = st[c];
-            if (st[c] != RS_OK && first == RS_OK) {
-                first = st[c];
-                fail(st[c], "build %u: %s", c, why[c].c_str());
-            }
+    b.K = (uint32_t)b.hd.size();
+    if (b.K && b.nbuckets >= (1ull << 32)) return fail(RS_EINVAL, "too many buckets in one call");
+    return RS_OK;
+}
+
+// Status of every build of the call (the first failure also becomes the
+// thread's error message).
+int batch_finish(Batch& b, int* statuses, int rc) {
+    int first = RS_OK;
+    for (uint32_t c = 0; c < b.count; c++) {
+        if (statuses) statuses[c] = b.st[c];
+        if (b.st[c] != RS_OK && first == RS_OK) {
+            first = b.st[c];
+            fail(b.st[c], "build %u: %s", c, b.why[c].c_str());
         }
-        return rc != RS_OK ? rc : first;
-    };
-    if (hd.empty()) return finish(RS_OK);
-    if (nbuckets >= (1ull << 32)) return fail(RS_EINVAL, "too many buckets in one call");
-    const uint32_t K = (uint32_t)hd.size();
-    RS_TRACE("build call: %u builds, %llu keys, %llu buckets", K, (unsigned long long)total,
-             (unsigned long long)nbuckets);
+    }
+    return rc != RS_OK ? rc : first;
+}
 
-    PhaseEvents pe;
-    if (int rc0 = pe.create(timing)) return rc0;
-
+// Bin geometry and the sizes of the workspace and of the pinned staging.
+int batch_layout(Batch& b) {
     // bins of the two-level bucket sort: about 16k keys each, at most kMaxBins
-    const double keys_per_bucket = (double)total / (double)nbuckets;
-    uint32_t shift = 0;
-    while (shift < kMaxBinShift && (double)(2ull << shift) * keys_per_bucket <= 16384.0) shift++;
-    while (shift < kMaxBinShift && ((nbuckets + (1ull << shift) - 1) >> shift) > kMaxBins) shift++;
-    const uint64_t nbins64 = (nbuckets + (1ull << shift) - 1) >> shift;
+    const double keys_per_bucket = (double)b.total / (double)b.nbuckets;
+    b.shift = 0;
+    while (b.shift < kMaxBinShift && (double)(2ull << b.shift) * keys_per_bucket <= 16384.0) b.shift++;
+    while (b.shift < kMaxBinShift && ((b.nbuckets + (1ull << b.shift) - 1) >> b.shift) > kMaxBins) b.shift++;
+    const uint64_t nbins64 = (b.nbuckets + (1ull << b.shift) - 1) >> b.shift;
     if (nbins64 > kMaxBins) return fail(RS_EINVAL, "too many buckets in one call");
-    const uint32_t nbins = (uint32_t)nbins64;
-
-    // workspace
-    const uint64_t ntiles = (nbuckets + 1 + kScanTile - 1) / kScanTile + 1;
+    b.nbins = (uint32_t)nbins64;
+    b.nxcd = xcd_count();
+    const uint64_t T = b.total, NB = b.nbuckets, K = b.K;
+    const uint64_t ntiles = (NB + 1 + kScanTile - 1) / kScanTile + 1;
     size_t off = 0;
     auto carve = [&](size_t bytes) {
         size_t o = off;
         off += (bytes + 255) & ~size_t(255);
         return o;
     };
-    const uint32_t nxcd = xcd_count();
-    const size_t o_lo = carve(total * 8), o_bid = carve(total * 4), o_bincnt = carve((size_t)nbins * nxcd * 8),
-                 o_binst = carve((nbins + 1) * 8ull), o_bincur = carve((size_t)nbins * nxcd * 8),
-                 o_bst = carve((nbuckets + 1) * 8), o_sorted = carve(total * 8),
-                 o_tmp = carve(total * 8), o_seeds = carve(total * 8), o_blen = carve(nbuckets * 8),
-                 o_ost = carve((nbuckets + 1) * 8), o_tiles = carve(ntiles * 8), o_st = carve(sizeof(DevStatus)),
-                 o_desc = carve(K * sizeof(BuildDesc)), o_kb = carve(3 * (K + 1) * 8),
-                 o_hdr = carve((size_t)K * kHeaderWords * 8);
-    char* ws = nullptr;
-    if (int rc0 = dev_alloc((void**)&ws, off, s)) return rc0;
-    uint64_t* d_lo = (uint64_t*)(ws + o_lo);
-    uint32_t* d_bid = (uint32_t*)(ws + o_bid);
-    unsigned long long* d_bincnt = (unsigned long long*)(ws + o_bincnt);
-    uint64_t* d_binst = (uint64_t*)(ws + o_binst);
-    unsigned long long* d_bincur = (unsigned long long*)(ws + o_bincur);
-    uint64_t* d_bst = (uint64_t*)(ws + o_bst);
-    uint64_t* d_sorted = (uint64_t*)(ws + o_sorted);
-    uint64_t* d_tmp = (uint64_t*)(ws + o_tmp);
-    uint64_t* d_seeds = (uint64_t*)(ws + o_seeds);
-    // before the search, the partition scratch and the index array hold the keys in bin order
-    uint64_t* d_binlo = d_tmp;
-    uint32_t* d_binbid = (uint32_t*)d_seeds;
-    uint64_t* d_blen = (uint64_t*)(ws + o_blen);
-    uint64_t* d_ost = (uint64_t*)(ws + o_ost);
-    uint64_t* d_tiles = (uint64_t*)(ws + o_tiles);
-    DevStatus* d_st = (DevStatus*)(ws + o_st);
-    BuildDesc* d_desc = (BuildDesc*)(ws + o_desc);
-    uint64_t* d_kb = (uint64_t*)(ws + o_kb);  // key, bucket and entry bases, contiguous like the host copy
-    uint64_t* d_bb = d_kb + (K + 1);
-    uint64_t* d_eb = d_bb + (K + 1);
-    uint64_t* d_hdr = (uint64_t*)(ws + o_hdr);
-    uint32_t* d_tab = nullptr;
-    uint64_t* d_blob = nullptr;
+    b.d_lo = (uint64_t*)carve(T * 8);
+    b.d_bid = (uint32_t*)carve(T * 4);
+    b.d_bincnt = (unsigned long long*)carve((size_t)b.nbins * b.nxcd * 8);
+    b.d_binst = (uint64_t*)carve((b.nbins + 1) * 8ull);
+    b.d_bincur = (unsigned long long*)carve((size_t)b.nbins * b.nxcd * 8);
+    b.d_bst = (uint64_t*)carve((NB + 1) * 8);
+    b.d_sorted = (uint64_t*)carve(T * 8);
+    b.d_tmp = (uint64_t*)carve(T * 8);
+    b.d_seeds = (uint64_t*)carve(T * 8);
+    b.d_blen = (uint64_t*)carve(NB * 8);
+    b.d_ost = (uint64_t*)carve((NB + 1) * 8);
+    b.d_tiles = (uint64_t*)carve(ntiles * 8);
+    // one contiguous block, mirrored in the pinned staging, so that one copy
+    // takes it in (bases, descriptors) and one brings it back (descriptors,
+    // headers, blob sizes and offsets, status words)
+    b.io_in = 3 * (K + 1) * 8 + K * sizeof(BuildDesc);
+    b.io_out = K * sizeof(BuildDesc) + K * kHeaderWords * 8 + K * 8 + (K + 1) * 8 + sizeof(DevStatus);
+    b.pin_bytes = 3 * (K + 1) * 8 + b.io_out;
+    b.d_kb = (uint64_t*)carve(b.pin_bytes);
+    b.ws_bytes = off;
+    return RS_OK;
+}
 
+// Rebase the carved offsets on the workspace and fill the pinned staging.
+void batch_bind(Batch& b, char* ws, char* pin) {
+    auto at = [&](auto& p) { p = reinterpret_cast<std::remove_reference_t<decltype(p)>>(ws + (size_t)p); };
+    at(b.d_lo); at(b.d_bid); at(b.d_bincnt); at(b.d_binst); at(b.d_bincur); at(b.d_bst); at(b.d_sorted);
+    at(b.d_tmp); at(b.d_seeds); at(b.d_blen); at(b.d_ost); at(b.d_tiles); at(b.d_kb);
+    const uint32_t K = b.K;
+    // [key bases | bucket bases | entry bases | descriptors | headers | raw words | offsets | status]
+    auto lay = [K](char* base, uint64_t*& kb, BuildDesc*& desc, uint64_t*& hdr, uint64_t*& raw, uint64_t*& boff,
+                   DevStatus*& st) {
+        kb = (uint64_t*)base;
+        desc = (BuildDesc*)(kb + 3 * (K + 1));
+        hdr = (uint64_t*)(desc + K);
+        raw = hdr + (size_t)K * kHeaderWords;
+        boff = raw + K;
+        st = (DevStatus*)(boff + (K + 1));
+    };
+    lay((char*)b.d_kb, b.d_kb, b.d_desc, b.d_hdr, b.d_raw, b.d_boff, b.d_st);
+    lay(pin, b.h_kb, b.h_desc, b.h_hdr, b.h_raw, b.h_boff, b.h_st);
+    b.d_bb = b.d_kb + (K + 1);
+    b.d_eb = b.d_bb + (K + 1);
+    memcpy(b.h_desc, b.hd.data(), K * sizeof(BuildDesc));
+    uint64_t* h_bb = b.h_kb + (K + 1);
+    uint64_t* h_eb = h_bb + (K + 1);
+    for (uint32_t j = 0; j < K; j++) {
+        b.h_kb[j] = b.hd[j].key_base;
+        h_bb[j] = b.hd[j].bucket_base;
+        h_eb[j] = b.hd[j].bucket_base + j;
+    }
+    b.h_kb[K] = b.total;
+    h_bb[K] = b.nbuckets;
+    h_eb[K] = b.nbuckets + K;
+}
+
+#define RS_ENQ(call)                                                                       \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess) return fail(RS_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+// Descriptors in, signatures, sort into bucket order (bstart, sorted keys,
+// largest bucket in d_st->maxm).  The descriptors are uploaded from h_desc.
+int enqueue_front(Batch& b, hipStream_t s, PhaseEvents* pe) {
+    const uint32_t K = b.K;
+    if (pe) pe->record(0, s);
+    RS_ENQ(hipMemcpyAsync(b.d_kb, b.h_kb, b.io_in, hipMemcpyHostToDevice, s));
+    const uint64_t ncnt = (uint64_t)b.nbins * b.nxcd;
+    k_reset<<<grid_for(ncnt, kBlock * 4), kBlock, 0, s>>>(b.d_st, b.d_bincnt, ncnt);
+    k_signature<<<grid_for(b.total, kSigTile), kBlock, b.nbins * 4, s>>>(
+        b.d_desc, b.d_desc, b.d_kb, K, b.total, b.d_lo, b.d_bid, b.shift, b.nbins, b.nxcd, b.d_bincnt);
+    if (pe) pe->record(1, s);
+    // before the search, the partition scratch and the index array hold the keys in bin order
+    uint64_t* bin_lo = b.d_tmp;
+    uint32_t* bin_bid = (uint32_t*)b.d_seeds;
+    k_bin_offsets<<<1, kBlock, 0, s>>>(b.d_bincnt, b.nbins, b.nxcd, b.d_binst, b.d_bincur);
+    k_bin_scatter<<<grid_for(b.total, kSigTile), kBlock, b.nbins * 12, s>>>(
+        b.d_lo, b.d_bid, b.total, b.shift, b.nbins, b.nxcd, b.d_bincur, bin_lo, bin_bid);
+    k_bucket_sort<<<b.nbins, kSortBlock, (8u << b.shift), s>>>(b.d_binst, bin_lo, bin_bid, b.shift, b.nbuckets,
+                                                              b.d_bst, b.d_sorted, &b.d_st->maxm);
+    if (pe) pe->record(2, s);
+    RS_ENQ(hipGetLastError());
+    return RS_OK;
+}
+
+// Per-size tables of every leaf size of the call for sizes 0..maxm (into
+// b.d_tab, which holds ntab * kTableCount * (maxm + 1) words) and the
+// search's dynamic LDS (keys + node slots of the largest possible bucket).
+int upload_batch_tables(Batch& b, uint32_t maxm, hipStream_t s) {
+    b.table_maxm = maxm;
+    b.stride = maxm + 1;
+    uint32_t max_nodes = 0;
+    for (uint32_t t = 0; t < (uint32_t)b.leaf_of_tab.size(); t++) {
+        TableView tv = host_tables(b.leaf_of_tab[t], maxm);
+        if (!tv.data) return fail(RS_ENOMEM, "table allocation failed");
+        for (uint32_t m = 0; m <= maxm; m++) max_nodes = std::max(max_nodes, tv.N()[m]);
+        uint32_t* dst = b.d_tab + (size_t)t * kTableCount * b.stride;
+        RS_ENQ(hipMemcpyAsync(dst, tv.r(), b.stride * 4ull, hipMemcpyHostToDevice, s));
+        RS_ENQ(hipMemcpyAsync(dst + b.stride, tv.F(), b.stride * 4ull, hipMemcpyHostToDevice, s));
+        RS_ENQ(hipMemcpyAsync(dst + 2 * b.stride, tv.N(), b.stride * 4ull, hipMemcpyHostToDevice, s));
+        RS_ENQ(hipMemcpyAsync(dst + 3 * b.stride, tv.G(), b.stride * 4ull, hipMemcpyHostToDevice, s));
+    }
+    b.lds = (size_t)maxm * 8 + (size_t)max_nodes * 16;
+    return RS_OK;
+}
+
+size_t table_words(const Batch& b, uint32_t maxm) {
+    return b.leaf_of_tab.size() * kTableCount * (size_t)(maxm + 1);
+}
+
+SearchArgs search_args(const Batch& b) {
+    return SearchArgs{b.d_sorted, b.d_tmp, b.d_bst, b.d_seeds, b.d_blen, b.d_desc, b.d_desc, b.d_bb, b.K,
+                      b.nbuckets, b.d_tab, b.stride, b.seed_cap, b.table_maxm};
+}
+
+// Seed search, bit-length prefix sums, Elias-Fano statistics, blob geometry
+// and the arena offsets (d_boff[K] = arena words).
+int enqueue_back(Batch& b, hipStream_t s, PhaseEvents* pe) {
+    if (pe) pe->record(3, s);
+    if (int rc = launch_search(b.max_leaf, b.launch_waves, search_args(b), b.lds, s)) return rc;
+    if (pe) pe->record(4, s);
+    if (int rc = scan<uint64_t>(b.d_blen, b.nbuckets, b.d_ost, b.d_tiles, nullptr, s)) return rc;
+    GapArgs ga{b.d_bst, b.d_ost, b.d_desc, b.d_desc, b.d_bb, b.K, b.nbuckets};
+    k_ef_gaps<<<grid_for(b.nbuckets, kGapTile), kBlock, 0, s>>>(ga);
+    k_layout<<<1, kBlock, 0, s>>>(b.d_desc, b.K, b.d_hdr, b.d_raw, b.d_boff);
+    if (pe) pe->record(5, s);
+    RS_ENQ(hipGetLastError());
+    return RS_OK;
+}
+
+// Blob addresses in `arena` (capacity words), cleared blobs, headers,
+// Elias-Fano bits and Golomb-Rice streams.
+int enqueue_fill(Batch& b, uint64_t* arena, uint64_t capacity, hipStream_t s) {
+    const uint32_t K = b.K;
+    k_set_blobs<<<grid_for(K, kBlock), kBlock, 0, s>>>(b.d_desc, K, (unsigned long long*)arena, b.d_boff, capacity,
+                                                      &b.d_st->flags);
+    if (arena && capacity) k_fill_u64<<<grid_for(capacity, kBlock * 8), kBlock, 0, s>>>(arena, capacity, 0);
+    k_write_headers<<<grid_for((uint64_t)K * kHeaderWords, kBlock), kBlock, 0, s>>>(b.d_desc, b.d_hdr, K);
+    FillArgs fa{b.d_bst, b.d_ost, b.d_seeds, b.d_desc, b.d_bb, b.d_eb, K, b.nbuckets, b.d_tab, b.stride};
+    k_ef_fill<<<grid_for(b.nbuckets + K, kBlock), kBlock, 0, s>>>(fa);
+    k_tree_bits<<<grid_for(b.nbuckets, 64), 64, 0, s>>>(fa);
+    RS_ENQ(hipGetLastError());
+    return RS_OK;
+}
+
+// Descriptors, headers, blob sizes and offsets and the status words back to
+// the pinned staging.
+int enqueue_readback(Batch& b, hipStream_t s) {
+    RS_ENQ(hipMemcpyAsync(b.h_desc, b.d_desc, b.io_out, hipMemcpyDeviceToHost, s));
+    return RS_OK;
+}
+#undef RS_ENQ
+
+// Per-build status from the flags the device raised.
+void collect_status(Batch& b) {
+    for (uint32_t j = 0; j < b.K; j++) {
+        const uint32_t c = b.which[j], f = b.h_desc[j].flags;
+        if (b.st[c] != RS_OK) continue;
+        if (f & kFlagOffsets) {
+            b.st[c] = RS_EINVAL;
+            b.why[c] = "byte-key offsets are not monotone";
+        } else if (f & kFlagDuplicate) {
+            b.st[c] = RS_EDUPLICATE;
+            b.why[c] = "duplicate keys (equal signatures)";
+        } else if (f & kFlagSearch) {
+            b.st[c] = RS_ESEARCH;
+            b.why[c] = "an index search reached the seed cap";
+        } else if (f & kFlagStack) {
+            b.st[c] = RS_EDEVICE;
+            b.why[c] = "search scheduling failed";
+        }
+    }
+}
+
+// Blob objects of the successful builds over `words` (the arena, laid out at
+// h_boff) and `tables`; the arena is freed with the last of them.
+void make_blobs(Batch& b, uint64_t* words, uint32_t* tables, uint32_t stride, hipStream_t s, rs_blob** outs) {
+    uint32_t made = 0;
+    for (uint32_t j = 0; j < b.K; j++) made += b.st[b.which[j]] == RS_OK;
+    for (uint32_t c = 0; c < b.count; c++) outs[c] = nullptr;
+    if (!made) {
+        dev_free(words, s);
+        dev_free(tables, s);
+        return;
+    }
+    BlobArena* arena = new (std::nothrow) BlobArena;
+    if (!arena) {
+        for (uint32_t j = 0; j < b.K; j++)
+            if (b.st[b.which[j]] == RS_OK) {
+                b.st[b.which[j]] = RS_ENOMEM;
+                b.why[b.which[j]] = "host allocation failed";
+            }
+        dev_free(words, s);
+        dev_free(tables, s);
+        return;
+    }
+    arena->words = words;
+    arena->tables = tables;
+    arena->refs = (int)made;
+    if (hipEventCreateWithFlags(&arena->ready, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(arena->ready, s) != hipSuccess) {
+        (void)hipStreamSynchronize(s);  // no event: the blobs are complete once the stream is
+        if (arena->ready) (void)hipEventDestroy(arena->ready);
+        arena->ready = nullptr;
+    }
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    for (uint32_t j = 0; j < b.K; j++) {
+        const uint32_t c = b.which[j];
+        if (b.st[c] != RS_OK) continue;
+        rs_blob* blob = new (std::nothrow) rs_blob;
+        if (!blob) {
+            b.st[c] = RS_ENOMEM;
+            b.why[c] = "host allocation failed";
+            release_arena(arena);
+            continue;
+        }
+        blob->words = words + b.h_boff[j];
+        blob->bytes = b.h_raw[j] * 8;
+        blob->tables = tables + (size_t)b.h_desc[j].tab * kTableCount * stride;
+        blob->tab_stride = stride;
+        memcpy(blob->header, b.h_hdr + (size_t)j * kHeaderWords, sizeof blob->header);
+        blob->ready = arena->ready;
+        blob->device = dev;
+        blob->arena = arena;
+        outs[c] = blob;
+    }
+}
+
+int build_batch_impl(const rs_keys* sets, uint32_t count, const uint32_t* leafs, const uint32_t* buckets,
+                     const rs_options* opts, hipStream_t s, rs_blob** outs, int* statuses, TuneCtx* tune) {
+    if (!sets || !leafs || !buckets || !outs || count == 0) return fail(RS_EINVAL, "NULL argument or empty batch");
+    const bool timing = opts && (opts->flags & RS_OPT_TIMING);
+    Batch b;
+    if (int rc = batch_prepare(b, sets, count, leafs, buckets, opts)) return rc;
+    if (b.K == 0) return batch_finish(b, statuses, RS_OK);
+    if (int rc = batch_layout(b)) return rc;
+    RS_TRACE("build call: %u builds, %llu keys, %llu buckets", b.K, (unsigned long long)b.total,
+             (unsigned long long)b.nbuckets);
+    PhaseEvents pe;
+    if (int rc0 = pe.create(timing)) return rc0;
+
+    char* ws = nullptr;
+    if (int rc0 = dev_alloc((void**)&ws, b.ws_bytes, s)) return rc0;
+    uint64_t* d_blob = nullptr;
     auto cleanup = [&](int code) {
         pinned_release(s);
         dev_free(ws, s);
         if (code != RS_OK) {
-            dev_free(d_tab, s);
+            dev_free(b.d_tab, s);
             dev_free(d_blob, s);
         }
         return code;
@@ -1617,161 +2044,36 @@ int build_batch_impl(const rs_keys* sets, uint32_t count, const uint32_t* leafs,
         if (e_ != hipSuccess)                                                                   \
             return cleanup(fail(RS_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)));          \
     } while (0)
-
-    // descriptors and bases to the device through pinned staging
-    const size_t desc_bytes = K * sizeof(BuildDesc);
-    const size_t stage_bytes = desc_bytes + 3 * (K + 1) * 8 + (size_t)K * kHeaderWords * 8 + sizeof(DevStatus);
-    char* pin = (char*)pinned(stage_bytes);
+    char* pin = (char*)pinned(b.pin_bytes);
     if (!pin) return cleanup(fail(RS_ENOMEM, "pinned host allocation failed"));
-    uint64_t* h_kb = (uint64_t*)(pin + desc_bytes);
-    uint64_t* h_bb = h_kb + (K + 1);
-    uint64_t* h_eb = h_bb + (K + 1);
-    uint64_t* h_hdr = h_eb + (K + 1);
-    DevStatus* h_st = (DevStatus*)(h_hdr + (size_t)K * kHeaderWords);
-    memcpy(pin, hd.data(), desc_bytes);
-    for (uint32_t j = 0; j < K; j++) {
-        h_kb[j] = hd[j].key_base;
-        h_bb[j] = hd[j].bucket_base;
-        h_eb[j] = hd[j].bucket_base + j;
-    }
-    h_kb[K] = total;
-    h_bb[K] = nbuckets;
-    h_eb[K] = nbuckets + K;
-    pe.record(0, s);
-    RS_TRY(hipMemcpyAsync(d_desc, pin, desc_bytes, hipMemcpyHostToDevice, s));
-    RS_TRY(hipMemcpyAsync(d_kb, h_kb, 3 * (K + 1) * 8, hipMemcpyHostToDevice, s));
-    k_init_status<<<1, 64, 0, s>>>(d_st);
-    k_fill_u64<<<grid_for((uint64_t)nbins * nxcd, kBlock * 4), kBlock, 0, s>>>((uint64_t*)d_bincnt,
-                                                                               (uint64_t)nbins * nxcd, 0);
-    k_signature<<<grid_for(total, kSigTile), kBlock, nbins * 4, s>>>(d_desc, d_desc, d_kb, K, total, d_lo, d_bid,
-                                                                      shift, nbins, nxcd, d_bincnt);
-    pe.record(1, s);
-    k_bin_offsets<<<1, kBlock, 0, s>>>(d_bincnt, nbins, nxcd, d_binst, d_bincur);
-    k_bin_scatter<<<grid_for(total, kSigTile), kBlock, nbins * 12, s>>>(d_lo, d_bid, total, shift, nbins, nxcd,
-                                                                        d_bincur, d_binlo, d_binbid);
-    k_bucket_sort<<<nbins, kSortBlock, (8u << shift), s>>>(d_binst, d_binlo, d_binbid, shift, nbuckets, d_bst,
-                                                          d_sorted, &d_st->maxm);
-    pe.record(2, s);
-    RS_TRY(hipGetLastError());
-    RS_TRY(hipMemcpyAsync(h_st, d_st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
-    RS_TRY(hipMemcpyAsync(pin, d_desc, desc_bytes, hipMemcpyDeviceToHost, s));
+    batch_bind(b, ws, pin);
+
+    if (int rc = enqueue_front(b, s, &pe)) return cleanup(rc);
+    RS_TRY(hipMemcpyAsync(b.h_st, b.d_st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
     RS_TRACE("signatures enqueued; waiting for the largest bucket");
     RS_TRY(hipStreamSynchronize(s));
-    BuildDesc* hdesc = (BuildDesc*)pin;
-    for (uint32_t j = 0; j < K; j++)
-        if (hdesc[j].flags & kFlagOffsets) {
-            st[which[j]] = RS_EINVAL;
-            why[which[j]] = "byte-key offsets are not monotone";
-        }
-    const uint32_t maxm = h_st->maxm;
+    const uint32_t maxm = b.h_st->maxm;
     RS_TRACE("largest bucket %u", maxm);
-
-    // per-size tables of every leaf size in the call, one block of 4 arrays each
-    const uint32_t stride = maxm + 1;
-    const uint32_t ntab = (uint32_t)leaf_of_tab.size();
-    if (int rc = dev_alloc((void**)&d_tab, (size_t)ntab * kTableCount * stride * 4, s)) return cleanup(rc);
-    uint32_t max_nodes = 0;
-    for (uint32_t t = 0; t < ntab; t++) {
-        TableView tv = host_tables(leaf_of_tab[t], maxm);
-        if (!tv.data) return cleanup(fail(RS_ENOMEM, "table allocation failed"));
-        max_nodes = std::max(max_nodes, tv.N()[maxm]);
-        uint32_t* dst = d_tab + (size_t)t * kTableCount * stride;
-        RS_TRY(hipMemcpyAsync(dst, tv.r(), stride * 4ull, hipMemcpyHostToDevice, s));
-        RS_TRY(hipMemcpyAsync(dst + stride, tv.F(), stride * 4ull, hipMemcpyHostToDevice, s));
-        RS_TRY(hipMemcpyAsync(dst + 2 * stride, tv.N(), stride * 4ull, hipMemcpyHostToDevice, s));
-        RS_TRY(hipMemcpyAsync(dst + 3 * stride, tv.G(), stride * 4ull, hipMemcpyHostToDevice, s));
-    }
-    // keys + node slots in dynamic LDS (the launch checks the static part too)
-    const size_t lds = (size_t)maxm * 8 + (size_t)max_nodes * 16;
-
-    pe.record(3, s);
-    SearchArgs sa{d_sorted, d_tmp, d_bst, d_seeds, d_blen, d_desc, d_desc, d_bb, K, nbuckets,
-                  d_tab, stride, cap, maxm};
+    if (int rc = dev_alloc((void**)&b.d_tab, table_words(b, maxm) * 4, s)) return cleanup(rc);
+    if (int rc = upload_batch_tables(b, maxm, s)) return cleanup(rc);
     if (tune) {  // calibration only: no blob, the tables are not handed to an arena
-        const int trc = tune_search(*tune, max_leaf, hdesc, d_desc, sa, lds, s);
-        dev_free(d_tab, s);
-        d_tab = nullptr;
+        const int trc = tune_search(*tune, b.max_leaf, b.h_desc, b.d_desc, search_args(b), b.lds, s);
+        dev_free(b.d_tab, s);
+        b.d_tab = nullptr;
         return cleanup(trc);
     }
-    int rc = launch_search(max_leaf, launch_waves, sa, lds, s);
-    if (rc) return cleanup(rc);
-    pe.record(4, s);
-    if ((rc = scan<uint64_t>(d_blen, nbuckets, d_ost, d_tiles, nullptr, s))) return cleanup(rc);
-    GapArgs ga{d_bst, d_ost, d_desc, d_desc, d_bb, K, nbuckets};
-    k_ef_gaps<<<grid_for(nbuckets, kBlock), kBlock, 0, s>>>(ga);
-    pe.record(5, s);
-    RS_TRY(hipGetLastError());
-    RS_TRY(hipMemcpyAsync(pin, d_desc, desc_bytes, hipMemcpyDeviceToHost, s));
-    RS_TRACE("search enqueued (class %u); waiting for the sizes", max_leaf);
+    if (int rc = enqueue_back(b, s, &pe)) return cleanup(rc);
+    if (int rc = enqueue_readback(b, s)) return cleanup(rc);
+    RS_TRACE("search enqueued (class %u); waiting for the sizes", b.max_leaf);
     RS_TRY(hipStreamSynchronize(s));
-    RS_TRACE("sizes known");
-
-    // blob geometry of every successful build
-    std::vector<uint64_t> blob_off(K, 0), blob_words(K, 0);
-    uint64_t arena_words = 0;
-    for (uint32_t j = 0; j < K; j++) {
-        BuildDesc& d = hdesc[j];
-        const uint32_t c = which[j];
-        if (st[c] == RS_OK) {
-            if (d.flags & kFlagDuplicate) {
-                st[c] = RS_EDUPLICATE;
-                why[c] = "duplicate keys (equal signatures)";
-            } else if (d.flags & kFlagSearch) {
-                st[c] = RS_ESEARCH;
-                why[c] = "an index search reached the seed cap";
-            } else if (d.flags & kFlagStack) {
-                st[c] = RS_EDEVICE;
-                why[c] = "search scheduling failed";
-            }
-        }
-        d.blob = nullptr;
-        if (st[c] != RS_OK) continue;
-        const uint64_t n = d.n, nb = d.nb, N = nb + 1, bits = d.total_bits;
-        const uint64_t beta = (bits << 16) / n;
-        const uint64_t ys_last = n - nb * d.delta_s;
-        const int64_t z_last = (int64_t)bits - (int64_t)((beta * n) >> 16);
-        const uint64_t yz_last = (uint64_t)(z_last - (int64_t)nb * d.delta_z);
-        const uint32_t Ws = ef_width(N, ys_last), Wz = ef_width(N, yz_last);
-        uint64_t* h = h_hdr + (size_t)j * kHeaderWords;
-        h[0] = kMagic;
-        h[1] = kVersion | ((uint64_t)d.kind << 32);
-        h[2] = n; h[3] = d.leaf; h[4] = buckets[c]; h[5] = nb; h[6] = d.maxm;
-        h[7] = (uint64_t)Ws | ((uint64_t)Wz << 8);
-        h[8] = d.delta_s; h[9] = (uint64_t)d.delta_z; h[10] = beta;
-        h[11] = ((ys_last >> Ws) + N + 63) / 64;
-        h[12] = ((yz_last >> Wz) + N + 63) / 64;
-        h[13] = (N * (Ws + Wz) + 63) / 64 + 1;
-        h[14] = (bits + 63) / 64 + 1;
-        h[15] = bits;
-        Layout L = layout_of(h);
-        d.beta = beta;
-        d.Ws = Ws;
-        d.Wz = Wz;
-        d.lower_off = L.lower_off;
-        d.us_off = L.us_off;
-        d.uz_off = L.uz_off;
-        d.invs_off = L.invs_off;
-        d.invz_off = L.invz_off;
-        d.tree_off = L.tree_off;
-        blob_off[j] = arena_words;
-        blob_words[j] = L.total_words;
-        arena_words += (L.total_words + 31) & ~uint64_t(31);  // 256-byte aligned blobs
-    }
+    collect_status(b);
+    const uint64_t arena_words = b.h_boff[b.K];
+    RS_TRACE("sizes known (%llu blob words)", (unsigned long long)arena_words);
     if (arena_words) {
-        if ((rc = dev_alloc((void**)&d_blob, arena_words * 8, s))) return cleanup(rc);
-        for (uint32_t j = 0; j < K; j++)
-            if (st[which[j]] == RS_OK) hdesc[j].blob = (unsigned long long*)(d_blob + blob_off[j]);
-        RS_TRY(hipMemcpyAsync(d_desc, pin, desc_bytes, hipMemcpyHostToDevice, s));
-        RS_TRY(hipMemcpyAsync(d_hdr, h_hdr, (size_t)K * kHeaderWords * 8, hipMemcpyHostToDevice, s));
-        k_fill_u64<<<grid_for(arena_words, kBlock * 8), kBlock, 0, s>>>(d_blob, arena_words, 0);
-        k_write_headers<<<grid_for((uint64_t)K * kHeaderWords, kBlock), kBlock, 0, s>>>(d_desc, d_hdr, K);
-        FillArgs fa{d_bst, d_ost, d_seeds, d_desc, d_bb, d_eb, K, nbuckets, d_tab, stride};
-        k_ef_fill<<<grid_for(nbuckets + K, kBlock), kBlock, 0, s>>>(fa);
-        k_tree_bits<<<grid_for(nbuckets, 64), 64, 0, s>>>(fa);
-        RS_TRY(hipGetLastError());
+        if (int rc = dev_alloc((void**)&d_blob, arena_words * 8, s)) return cleanup(rc);
+        if (int rc = enqueue_fill(b, d_blob, arena_words, s)) return cleanup(rc);
     }
     pe.record(6, s);
-    RS_TRACE("fill enqueued (%llu blob words)", (unsigned long long)arena_words);
     if (timing) {
         RS_TRY(hipStreamSynchronize(s));
         g_stats.ms_signature = pe.ms(0, 1);
@@ -1780,65 +2082,238 @@ int build_batch_impl(const rs_keys* sets, uint32_t count, const uint32_t* leafs,
         g_stats.ms_offsets = pe.ms(4, 5);
         g_stats.ms_fill = pe.ms(5, 6);
         g_stats.ms_device = pe.ms(0, 6);
-        g_stats.n = total;
-        g_stats.nb = nbuckets;
+        g_stats.n = b.total;
+        g_stats.nb = b.nbuckets;
         g_stats.maxm = maxm;
         g_stats.tree_bits = 0;
-        for (uint32_t j = 0; j < K; j++) g_stats.tree_bits += hdesc[j].total_bits;
+        for (uint32_t j = 0; j < b.K; j++) g_stats.tree_bits += b.h_desc[j].total_bits;
         g_stats.blob_bytes = arena_words * 8;
         g_stats_valid = true;
     }
-
-    // blobs share the arena (and the tables); the last one released frees them
-    BlobArena* arena = nullptr;
-    uint32_t made = 0;
-    for (uint32_t j = 0; j < K; j++) made += st[which[j]] == RS_OK;
-    if (made) {
-        arena = new (std::nothrow) BlobArena;
-        if (!arena) return cleanup(fail(RS_ENOMEM, "host allocation failed"));
-        arena->words = d_blob;
-        arena->tables = d_tab;
-        arena->refs = (int)made;
-        if (hipEventCreateWithFlags(&arena->ready, hipEventDisableTiming) != hipSuccess ||
-            hipEventRecord(arena->ready, s) != hipSuccess) {
-            (void)hipStreamSynchronize(s);  // no event: the blobs are complete once the stream is
-            if (arena->ready) (void)hipEventDestroy(arena->ready);
-            arena->ready = nullptr;
-        }
-    } else {
-        dev_free(d_tab, s);
-        d_tab = nullptr;
-    }
-    int dev = 0;
-    (void)hipGetDevice(&dev);
-    for (uint32_t j = 0; j < K; j++) {
-        const uint32_t c = which[j];
-        outs[c] = nullptr;
-        if (st[c] != RS_OK) continue;
-        rs_blob* b = new (std::nothrow) rs_blob;
-        if (!b) {
-            st[c] = RS_ENOMEM;
-            why[c] = "host allocation failed";
-            release_arena(arena);
-            continue;
-        }
-        b->words = d_blob + blob_off[j];
-        b->bytes = blob_words[j] * 8;
-        b->tables = d_tab + (size_t)hdesc[j].tab * kTableCount * stride;
-        b->tab_stride = stride;
-        memcpy(b->header, h_hdr + (size_t)j * kHeaderWords, sizeof b->header);
-        b->ready = arena->ready;
-        b->device = dev;
-        b->arena = arena;
-        outs[c] = b;
-    }
-    for (uint32_t c = 0; c < count; c++)
-        if (st[c] != RS_OK) outs[c] = nullptr;
+    make_blobs(b, d_blob, b.d_tab, b.stride, s, outs);
     pinned_release(s);
     dev_free(ws, s);
-    return finish(RS_OK);
+    return batch_finish(b, statuses, RS_OK);
 #undef RS_TRY
 }
+
+// ---------------------------------------------------------------------------
+// Build plans: the construction of a fixed batch shape captured into one HIP
+// graph.  The largest bucket and the blob sizes are not known in advance, so
+// the plan sizes the search's LDS and the tables for a bucket cap and the blob
+// arena for a word cap, both set with a margin from a first ordinary build;
+// the kernels flag buckets or blobs beyond the caps and the run then falls
+// back to an ordinary build.
+// ---------------------------------------------------------------------------
+}  // namespace rs
+
+struct rs_plan {
+    rs::Batch b;
+    std::vector<rs_keys> sets;
+    std::vector<uint32_t> leafs, buckets;
+    rs_options opts{};
+    char* ws = nullptr;
+    char* pin = nullptr;
+    uint64_t* arena = nullptr;
+    uint64_t capacity = 0;
+    uint32_t maxm_cap = 0;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;  // the last run's copies out of the arena
+    bool done_pending = false;
+    uint64_t runs = 0, fallbacks = 0;
+};
+
+namespace rs {
+
+void plan_release(rs_plan* p) {
+    if (!p) return;
+    if (p->done_pending) (void)hipEventSynchronize(p->done);
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    if (p->done) (void)hipEventDestroy(p->done);
+    if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
+    if (p->ws) (void)hipFree(p->ws);
+    if (p->b.d_tab) (void)hipFree(p->b.d_tab);
+    if (p->arena) (void)hipFree(p->arena);
+    if (p->pin) (void)hipHostFree(p->pin);
+    delete p;
+}
+
+// Largest bucket of which the search still fits the LDS with the tables of
+// this batch (binary search over the dynamic LDS the launch would ask for).
+uint32_t lds_bucket_limit(Batch& b) {
+    SearchKernel k = search_kernel(b.max_leaf, b.launch_waves);
+    size_t static_bytes = 0;
+    if (static_lds(reinterpret_cast<const void*>(k), &static_bytes)) return 0;
+    const size_t avail = (size_t)max_lds_bytes() - static_bytes;
+    uint32_t lo = 0, hi = (uint32_t)(avail / 8);
+    while (lo < hi) {
+        const uint32_t mid = (lo + hi + 1) / 2;
+        uint32_t nodes = 0;
+        for (uint32_t leaf : b.leaf_of_tab) {
+            TableView tv = host_tables(leaf, mid);
+            if (!tv.data) return 0;
+            for (uint32_t m = 0; m <= mid; m++) nodes = std::max(nodes, tv.N()[m]);
+        }
+        if ((size_t)mid * 8 + (size_t)nodes * 16 <= avail) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+}  // namespace rs
+
+extern "C" int rs_plan_create(const rs_keys* sets, uint32_t count, const uint32_t* leaf, const uint32_t* bucket,
+                              const rs_options* opts, void* stream, rs_plan** out, rs_blob** first_outs,
+                              int* per_build_status) {
+    rs::clear_error();
+    if (!sets || !leaf || !bucket || !out || count == 0) return rs::fail(RS_EINVAL, "NULL argument or empty batch");
+    hipStream_t s = (hipStream_t)stream;
+    rs_options o{};
+    if (opts) o = *opts;
+    o.flags &= ~(uint32_t)RS_OPT_TIMING;
+    // a first ordinary build: the sizes the caps start from (and the caller's first result)
+    std::vector<rs_blob*> first(count, nullptr);
+    std::vector<int> status(count, RS_OK);
+    int rc = rs::build_batch_impl(sets, count, leaf, bucket, &o, s, first.data(), status.data(), nullptr);
+    if (per_build_status)
+        for (uint32_t c = 0; c < count; c++) per_build_status[c] = status[c];
+    uint32_t maxm0 = 0;
+    uint64_t words0 = 0;
+    for (uint32_t c = 0; c < count; c++)
+        if (first[c]) {
+            maxm0 = std::max<uint32_t>(maxm0, (uint32_t)first[c]->header[6]);
+            words0 += ((first[c]->bytes / 8) + 31) & ~uint64_t(31);
+        }
+    auto give_first = [&]() {
+        for (uint32_t c = 0; c < count; c++) {
+            if (first_outs) first_outs[c] = first[c];
+            else if (first[c]) rs_blob_free(first[c]);
+        }
+    };
+    if (rc != RS_OK) {
+        give_first();
+        return rc;
+    }
+    rs_plan* p = new (std::nothrow) rs_plan;
+    if (!p) {
+        give_first();
+        return rs::fail(RS_ENOMEM, "host allocation failed");
+    }
+    p->sets.assign(sets, sets + count);
+    p->leafs.assign(leaf, leaf + count);
+    p->buckets.assign(bucket, bucket + count);
+    p->opts = o;
+    rs::Batch& b = p->b;
+    auto bail = [&](int code) {
+        rs::plan_release(p);
+        give_first();
+        return code;
+    };
+    if ((rc = rs::batch_prepare(b, sets, count, leaf, bucket, &o))) return bail(rc);
+    if ((rc = rs::batch_layout(b))) return bail(rc);
+    if (hipMalloc((void**)&p->ws, b.ws_bytes) != hipSuccess) return bail(rs::fail(RS_ENOMEM, "device allocation failed"));
+    if (hipHostMalloc((void**)&p->pin, b.pin_bytes, hipHostMallocDefault) != hipSuccess) {
+        p->pin = nullptr;
+        return bail(rs::fail(RS_ENOMEM, "pinned host allocation failed"));
+    }
+    rs::batch_bind(b, p->ws, p->pin);
+    // caps: the first build's largest bucket plus four standard deviations of a
+    // Poisson count (and a few keys), within what the LDS holds; the arena 1/8 larger
+    const uint32_t margin = (uint32_t)std::ceil(4.0 * std::sqrt((double)maxm0)) + 8;
+    p->maxm_cap = std::min(maxm0 + margin, rs::lds_bucket_limit(b));
+    if (p->maxm_cap < maxm0) return bail(rs::fail(RS_EINVAL, "largest bucket exceeds the local data share"));
+    p->capacity = words0 + words0 / 8 + 64ull * b.K + 1024;
+    if (hipMalloc((void**)&b.d_tab, rs::table_words(b, p->maxm_cap) * 4) != hipSuccess ||
+        hipMalloc((void**)&p->arena, p->capacity * 8) != hipSuccess)
+        return bail(rs::fail(RS_ENOMEM, "device allocation failed"));
+    if (hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&p->done, hipEventDisableTiming) != hipSuccess)
+        return bail(rs::fail(RS_EDEVICE, "stream or event creation failed"));
+    if ((rc = rs::upload_batch_tables(b, p->maxm_cap, p->cap_stream))) return bail(rc);
+    if (hipStreamSynchronize(p->cap_stream) != hipSuccess) return bail(rs::fail(RS_EDEVICE, "table upload failed"));
+    // capture: every phase, no host read in between
+    if (hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
+        return bail(rs::fail(RS_EDEVICE, "hipStreamBeginCapture failed"));
+    int crc = rs::enqueue_front(b, p->cap_stream, nullptr);
+    if (!crc) crc = rs::enqueue_back(b, p->cap_stream, nullptr);
+    if (!crc) crc = rs::enqueue_fill(b, p->arena, p->capacity, p->cap_stream);
+    if (!crc) crc = rs::enqueue_readback(b, p->cap_stream);
+    const hipError_t ec = hipStreamEndCapture(p->cap_stream, &p->graph);
+    if (crc) return bail(crc);
+    if (ec != hipSuccess || !p->graph) return bail(rs::fail(RS_EDEVICE, "hipStreamEndCapture failed"));
+    if (hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0) != hipSuccess)
+        return bail(rs::fail(RS_EDEVICE, "hipGraphInstantiate failed"));
+    give_first();
+    *out = p;
+    return RS_OK;
+}
+
+extern "C" int rs_plan_run(rs_plan* p, void* stream, rs_blob** outs, int* per_build_status) {
+    rs::clear_error();
+    if (!p || !outs) return rs::fail(RS_EINVAL, "NULL argument");
+    hipStream_t s = (hipStream_t)stream;
+    rs::Batch& b = p->b;
+    // the previous run's copies read the arena: they finish before it is rewritten
+    if (p->done_pending) RS_HIP(hipStreamWaitEvent(s, p->done, 0));
+    // the descriptors going in are the plan's originals (a run rewrites the staging)
+    memcpy(b.h_desc, b.hd.data(), b.K * sizeof(rs::BuildDesc));
+    RS_HIP(hipGraphLaunch(p->exec, s));
+    RS_HIP(hipStreamSynchronize(s));
+    p->runs++;
+    bool over = (b.h_st->flags & rs::kFlagCapacity) != 0;
+    for (uint32_t j = 0; j < b.K; j++) over |= (b.h_desc[j].flags & rs::kFlagTooBig) != 0;
+    if (over) {  // a bucket or a blob beyond the caps: build this run the ordinary way
+        p->fallbacks++;
+        p->done_pending = false;
+        return rs::build_batch_impl(p->sets.data(), b.count, p->leafs.data(), p->buckets.data(), &p->opts, s, outs,
+                                    per_build_status, nullptr);
+    }
+    // statuses start from validation, then the device flags of this run
+    std::vector<int> st0 = b.st;
+    std::vector<std::string> why0 = b.why;
+    rs::collect_status(b);
+    // copy the blobs (one contiguous range) and the tables out of the plan
+    const uint64_t words = b.h_boff[b.K];
+    uint64_t* dst = nullptr;
+    uint32_t* tab = nullptr;
+    const size_t tab_words = rs::table_words(b, b.table_maxm);
+    int rc = RS_OK;
+    if (words) {
+        if ((rc = rs::dev_alloc((void**)&dst, words * 8, s)) || (rc = rs::dev_alloc((void**)&tab, tab_words * 4, s))) {
+            rs::dev_free(dst, s);
+            b.st = st0;
+            b.why = why0;
+            return rc;
+        }
+        RS_HIP(hipMemcpyAsync(dst, p->arena, words * 8, hipMemcpyDeviceToDevice, s));
+        RS_HIP(hipMemcpyAsync(tab, b.d_tab, tab_words * 4, hipMemcpyDeviceToDevice, s));
+        RS_HIP(hipEventRecord(p->done, s));
+        p->done_pending = true;
+    }
+    rs::make_blobs(b, dst, tab, b.stride, s, outs);
+    rc = rs::batch_finish(b, per_build_status, RS_OK);
+    b.st = st0;
+    b.why = why0;
+    return rc;
+}
+
+extern "C" int rs_plan_info(const rs_plan* p, uint32_t* bucket_cap, uint64_t* capacity_words, uint64_t* runs,
+                            uint64_t* fallbacks) {
+    rs::clear_error();
+    if (!p) return rs::fail(RS_EINVAL, "NULL argument");
+    if (bucket_cap) *bucket_cap = p->maxm_cap;
+    if (capacity_words) *capacity_words = p->capacity;
+    if (runs) *runs = p->runs;
+    if (fallbacks) *fallbacks = p->fallbacks;
+    return RS_OK;
+}
+
+extern "C" void rs_plan_destroy(rs_plan* p) { rs::plan_release(p); }
+
+namespace rs {
 
 }  // namespace rs
 

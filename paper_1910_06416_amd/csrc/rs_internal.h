@@ -37,7 +37,16 @@ constexpr uint64_t kMixB = 0x94d049bb133111ebull;
 constexpr uint64_t kSigHi = 0x243f6a8885a308d3ull;
 constexpr uint64_t kSigLo = 0x13198a2e03707344ull;
 
-enum : uint32_t { kFlagDuplicate = 1, kFlagSearch = 2, kFlagOffsets = 4, kFlagStack = 8 };
+// Build flags set by the device: duplicate keys, seed cap reached, bad byte offsets,
+// search scheduling failure, blob arena too small, bucket larger than the search was sized for.
+enum : uint32_t {
+    kFlagDuplicate = 1,
+    kFlagSearch = 2,
+    kFlagOffsets = 4,
+    kFlagStack = 8,
+    kFlagCapacity = 16,
+    kFlagTooBig = 32
+};
 
 // Device-side status words of one build.
 struct DevStatus {

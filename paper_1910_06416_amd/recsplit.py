@@ -108,10 +108,17 @@ def lib() -> ctypes.CDLL:
         L.rs_schedule_set.argtypes = [U32, U32, ctypes.POINTER(rs_schedule)]
         L.rs_schedule_clear.argtypes = []
         L.rs_schedule_clear.restype = None
+        L.rs_plan_create.argtypes = [ctypes.POINTER(rs_keys), U32, P, P, ctypes.POINTER(rs_options), P,
+                                     ctypes.POINTER(P), P, P]
+        L.rs_plan_run.argtypes = [P, P, P, P]
+        L.rs_plan_info.argtypes = [P, ctypes.POINTER(U32), ctypes.POINTER(U64), ctypes.POINTER(U64),
+                                   ctypes.POINTER(U64)]
+        L.rs_plan_destroy.argtypes = [P]
+        L.rs_plan_destroy.restype = None
         for f in ("rs_build", "rs_build_ex", "rs_lookup", "rs_blob_to_host", "rs_blob_from_host", "rs_blob_info",
                   "rs_tables", "rs_last_build_stats", "rs_build_batch", "rs_server_create", "rs_server_submit_build",
                   "rs_server_submit_lookup", "rs_server_poll", "rs_server_wait", "rs_server_get_stats", "rs_autotune",
-                  "rs_schedule_get", "rs_schedule_set"):
+                  "rs_schedule_get", "rs_schedule_set", "rs_plan_create", "rs_plan_run", "rs_plan_info"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -263,6 +270,60 @@ def set_schedule(leaf: int, bucket: int, stage_from: int, group_max: int, waves:
 
 def clear_schedules():
     lib().rs_schedule_clear()
+
+
+class Plan:
+    """The construction of a fixed batch shape captured into one HIP graph
+    (rs_plan_* in recsplit.h).  The key tensors must stay alive, at the same
+    addresses, until close(); run() rebuilds from their current contents."""
+
+    def __init__(self, key_sets, leafs, buckets, seed_cap: int = 0, stage_from: int = 0, group_max: int = 0,
+                 waves: int = 0, tuned: bool = False, stream=None):
+        count = len(key_sets)
+        if isinstance(leafs, int):
+            leafs = [leafs] * count
+        if isinstance(buckets, int):
+            buckets = [buckets] * count
+        self._keep = list(key_sets)
+        self._count = count
+        arr = (rs_keys * count)(*[_as_keys(k) for k in key_sets])
+        lf = np.ascontiguousarray(leafs, dtype=np.uint32)
+        bk = np.ascontiguousarray(buckets, dtype=np.uint32)
+        first = (ctypes.c_void_p * count)()
+        status = np.zeros(count, dtype=np.int32)
+        opts = _options(seed_cap, False, tuned, stage_from, group_max, waves)
+        self._h = ctypes.c_void_p()
+        _check(lib().rs_plan_create(arr, count, lf.ctypes.data, bk.ctypes.data, ctypes.byref(opts),
+                                    _stream(stream), ctypes.byref(self._h), ctypes.cast(first, ctypes.c_void_p),
+                                    status.ctypes.data))
+        self.first = [Blob(ctypes.c_void_p(first[i])) if first[i] else None for i in range(count)]
+
+    def run(self, stream=None):
+        """Rebuild every set; returns (blobs, statuses) like build_batch."""
+        outs = (ctypes.c_void_p * self._count)()
+        status = np.zeros(self._count, dtype=np.int32)
+        rc = lib().rs_plan_run(self._h, _stream(stream), ctypes.cast(outs, ctypes.c_void_p), status.ctypes.data)
+        blobs = [Blob(ctypes.c_void_p(outs[i])) if outs[i] else None for i in range(self._count)]
+        if rc != RS_OK and not any(b is not None for b in blobs) and not status.any():
+            _check(rc)
+        return blobs, [int(x) for x in status]
+
+    def info(self) -> dict:
+        cap, words, runs, fb = ctypes.c_uint32(), ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().rs_plan_info(self._h, ctypes.byref(cap), ctypes.byref(words), ctypes.byref(runs),
+                                  ctypes.byref(fb)))
+        return {"bucket_cap": cap.value, "capacity_words": words.value, "runs": runs.value, "fallbacks": fb.value}
+
+    def close(self):
+        if self._h:
+            lib().rs_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def lookup(blob: Blob, keys, out=None, stream=None):

@@ -283,3 +283,48 @@ def test_autotuned_schedules_in_builds_and_batches(rs, orc):
     with pytest.raises(rs.RecSplitError):
         rs.build(rs.device_keys(keys), 8, 100, waves=3)
     rs.clear_schedules()
+
+
+def test_plan_runs_equal_oracle_and_fall_back_past_caps(rs, orc):
+    """A captured plan rebuilds from the buffers' current contents: every run
+    equals the oracle for the keys then in the buffers; contents whose largest
+    bucket exceeds the plan's cap take the ordinary path, with the same result."""
+    import torch
+
+    print("case plan", flush=True)
+    specs = [(20000, 8, 100), (5000, 12, 300), (777, 5, 7), (3, 8, 100)]
+    host = [inputs.u64_keys(n, 900 + i) for i, (n, _, _) in enumerate(specs)]
+    dev = [rs.device_keys(k) for k in host]
+    leafs, buckets = [s[1] for s in specs], [s[2] for s in specs]
+    plan = rs.Plan(dev, leafs, buckets)
+    for b, k, (n, leaf, bucket) in zip(plan.first, host, specs):
+        assert b.to_bytes() == orc.build(k, leaf, bucket)
+    for run in range(3):
+        # new contents in the same buffers
+        host = [inputs.u64_keys(n, 1000 * (run + 1) + i) for i, (n, _, _) in enumerate(specs)]
+        for d, k in zip(dev, host):
+            d.copy_(torch.from_numpy(k.view(np.int64)))
+        blobs, status = plan.run()
+        assert status == [0] * len(specs)
+        for b, k, (n, leaf, bucket) in zip(blobs, host, specs):
+            assert b.to_bytes() == orc.build(k, leaf, bucket), (run, n, leaf, bucket)
+            r = rs.lookup(b, rs.device_keys(k)).cpu().numpy().view(np.uint64)
+            assert np.array_equal(np.sort(r), np.arange(n, dtype=np.uint64))
+    info = plan.info()
+    assert info["runs"] == 3 and info["fallbacks"] == 0
+    # skewed contents: one bucket far above the cap (keys chosen by the oracle's bucket function)
+    n, leaf, bucket = specs[0]
+    nb = -(-n // bucket)
+    big = info["bucket_cap"] + 50
+    pool = inputs.u64_keys(4 * big * nb, 4242)
+    hi, _ = orc.fingerprint(pool)
+    in_zero = pool[(hi >> np.uint64(32)).astype(np.float64) * nb < 2.0 ** 32 * 0.9][:big]
+    assert len(in_zero) == big
+    rest = pool[~np.isin(pool, in_zero)][: n - len(in_zero)]
+    skew = np.concatenate([in_zero, rest])
+    assert len(skew) == n and len(np.unique(skew)) == n
+    dev[0].copy_(torch.from_numpy(skew.view(np.int64)))
+    blobs, status = plan.run()
+    assert status[0] == 0 and blobs[0].to_bytes() == orc.build(skew, leaf, bucket)
+    assert plan.info()["fallbacks"] == 1
+    plan.close()
