@@ -234,6 +234,25 @@ def main():
         result["latency_100k_l8_b100_ms"] = {"p50": percentile(lat, 50) * 1e3, "p99": percentile(lat, 99) * 1e3,
                                              "builds": len(lat)}
         log(f"[bench] 100k-key build latency p50 {result['latency_100k_l8_b100_ms']['p50']:.3f} ms")
+        # the same builds through a captured plan (one graph launch and one wait per build)
+        plan = recsplit.Plan([small], 8, 100, tuned=tuned)
+        for b in plan.first:
+            b.free()
+        plat = []
+        for i in range(args.latency_builds + 3):
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            blobs, _ = plan.run()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - tb
+            blobs[0].free()
+            if i >= 3:
+                plat.append(dt)
+        result["latency_100k_l8_b100_plan_ms"] = {"p50": percentile(plat, 50) * 1e3,
+                                                  "p99": percentile(plat, 99) * 1e3, "builds": len(plat),
+                                                  "plan": plan.info()}
+        plan.close()
+        log(f"[bench] 100k-key plan-run latency p50 {result['latency_100k_l8_b100_plan_ms']['p50']:.3f} ms")
 
     # high-compression point: 10M random 64-bit keys, l=16, b=2000 (one build)
     if args.l16_n:
@@ -313,6 +332,23 @@ def bench_batch(args):
             b.free()
         del blobs
 
+    # the same batch through a captured plan: one graph launch per rebuild
+    log("[bench] batched call through a captured plan")
+    plan = recsplit.Plan(sets, leaf, bucket, tuned=tuned)
+    for b in plan.first:
+        if b is not None:
+            b.free()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pblobs, pstatus = plan.run()
+    plan_s = time.perf_counter() - t0
+    assert all(x == 0 for x in pstatus), "plan run failed"
+    plan_info = plan.info()
+    for b in pblobs:
+        b.free()
+    plan.close()
+    log(f"[bench] plan run: {plan_s:.3f} s ({plan_info})")
+
     # plain path: one rs_build call per build, in order
     log("[bench] plain path: one call per build")
     torch.cuda.synchronize()
@@ -336,6 +372,7 @@ def bench_batch(args):
         "config": {"workload": f"{len(sizes)} builds of uniform random 64-bit keys, sizes log-uniform in "
                                f"[1e3, 1e6], l={leaf}, b={bucket}", "keys": total},
         "batched_s": batched, "plain_s": plain, "speedup_vs_plain": plain / batched,
+        "plan_run_s": plan_s, "plan": plan_info,
         "plain_keys_per_s": total / plain, "bits_per_key": bits, "search_ms": stats["ms_search"],
         "phase_ms": {k: stats[k] for k in ("ms_signature", "ms_scatter", "ms_search", "ms_offsets", "ms_fill")},
         "plain_build_latency_ms": {"p50": percentile(lat, 50) * 1e3, "p99": percentile(lat, 99) * 1e3},
