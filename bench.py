@@ -79,12 +79,16 @@ def main():
     ap.add_argument("--l16-n", type=int, default=10_000_000, help="keys of the l=16, b=2000 build (0: skip)")
     ap.add_argument("--latency-builds", type=int, default=30, help="repeated 100,000-key builds for p50/p99")
     ap.add_argument("--cpu-sample", type=int, default=1_000_000, help="oracle sample size (0: skip)")
-    ap.add_argument("--workload", choices=["single", "batch", "serve"], default="single",
+    ap.add_argument("--workload", choices=["single", "batch", "serve", "table"], default="single",
                     help="single: 10M strings l=8 b=100 (+ l=16 point); batch: 4096 uneven builds, l=12 b=1000; "
-                         "serve: Poisson stream of uneven build requests and 1M-key lookups")
+                         "serve: Poisson stream of uneven build requests and 1M-key lookups; "
+                         "table: the paper's Table tab:1M rows (10^6 random keys at four (l, b) points)")
+    ap.add_argument("--table-n", type=int, default=1_000_000, help="table: keys per row")
     ap.add_argument("--batch-builds", type=int, default=4096)
     ap.add_argument("--requests", type=int, default=60, help="serve: build requests")
     ap.add_argument("--load", type=float, default=0.6, help="serve: offered load (fraction of modelled capacity)")
+    ap.add_argument("--lookup-cus", type=int, default=16,
+                    help="serve: compute units the build streams leave to lookups (0: none)")
     ap.add_argument("--tune-ms", type=float, default=3000.0,
                     help="autotuner budget (search milliseconds) per (l, b) pair; l=16 pairs get ten times this")
     ap.add_argument("--no-tune", action="store_true", help="use the built-in search schedule")
@@ -119,6 +123,9 @@ def main():
         return
     if args.workload == "serve":
         print(json.dumps(bench_serve(args)), flush=True)
+        return
+    if args.workload == "table":
+        print(json.dumps(bench_table(args)), flush=True)
         return
     n, leaf, bucket = args.n, 8, 100
 
@@ -425,7 +432,7 @@ def bench_serve(args):
     torch.cuda.synchronize()
 
     # served run
-    srv = recsplit.Server(budget_bytes=96 << 30, build_workers=3, tuned=tuned)
+    srv = recsplit.Server(budget_bytes=96 << 30, build_workers=3, tuned=tuned, lookup_cus=args.lookup_cus)
     t0 = time.perf_counter()
     tickets, lookups, done_blobs = [None] * R, [], {}
     li = 0
@@ -496,6 +503,77 @@ def bench_serve(args):
                   "keys_per_s": total / plain_s},
         "bits_per_key": bits,
         "schedules": schedules if tuned else "built-in",
+    }
+
+
+# Rows of the paper's Table tab:1M (10^6 random keys, one core of its test machine):
+# (l, b) -> bits/key, construction ns/key, lookup ns/key.
+PAPER_TAB_1M = {(8, 100): (1.79, 1027, 67), (12, 9): (2.23, 7245, 39), (5, 5): (2.95, 139, 47),
+                (16, 2000): (1.56, 1733801, 87)}
+
+
+def bench_table(args):
+    """The paper's Table tab:1M points on the GPU: for each (l, b), build the
+    structure of the same random 64-bit keys (steps times, after a warm-up)
+    and look every key up; report bits/key and ns/key next to the paper's."""
+    import numpy as np
+    import torch
+
+    from paper_1910_06416_amd import inputs, recsplit
+
+    n = args.table_n
+    if n <= 100_000_000:
+        keys = recsplit.device_keys(inputs.u64_keys(n, 7))
+    else:  # too many to draw and deduplicate on the host
+        keys = inputs.u64_keys_device(n, 7)
+    ranks = torch.empty(n, dtype=torch.int64, device="cuda")
+    rows = []
+    for (leaf, bucket), (p_bits, p_build, p_lookup) in PAPER_TAB_1M.items():
+        if leaf >= 16 and n > 10_000_000:
+            log(f"[bench] table l={leaf} b={bucket}: skipped at {n:,} keys (about {n / 1.45e6:.0f} s)")
+            continue
+        steps = max(1, args.steps if leaf < 16 else 1)
+        schedule = tune(recsplit, leaf, bucket, args, n) if not args.no_tune else "built-in"
+        recsplit.build(keys, leaf, bucket, tuned=not args.no_tune).free()
+        bt = []
+        for _ in range(steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            blob = recsplit.build(keys, leaf, bucket, tuned=not args.no_tune)
+            torch.cuda.synchronize()
+            bt.append(time.perf_counter() - t0)
+            if len(bt) < steps:
+                blob.free()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        recsplit.lookup(blob, keys, out=ranks)
+        ev0.record()
+        for _ in range(5):
+            recsplit.lookup(blob, keys, out=ranks)
+        ev1.record()
+        ev1.synchronize()
+        lk = ev0.elapsed_time(ev1) / 5 * 1e-3
+        srt, _ = torch.sort(ranks)
+        assert torch.equal(srt, torch.arange(n, dtype=torch.int64, device="cuda")), "lookups are not a bijection"
+        bits = blob.bits_per_key()
+        blob.free()
+        build_s = float(np.median(bt))
+        row = {"leaf": leaf, "bucket": bucket, "bits_per_key": bits, "build_ns_per_key": build_s / n * 1e9,
+               "lookup_ns_per_key": lk / n * 1e9, "keys_per_s": n / build_s,
+               "paper": {"bits_per_key": p_bits, "build_ns_per_key": p_build, "lookup_ns_per_key": p_lookup},
+               "schedule": schedule}
+        rows.append(row)
+        log(f"[bench] table l={leaf} b={bucket}: {bits:.4f} bits/key (paper {p_bits}), "
+            f"build {row['build_ns_per_key']:.3f} ns/key (paper {p_build}), "
+            f"lookup {row['lookup_ns_per_key']:.4f} ns/key (paper {p_lookup})")
+    first = rows[0]
+    return {
+        "metric": "keys/s built at the paper's Table tab:1M points (bits/key, construction and lookup ns/key)",
+        "value": first["keys_per_s"], "unit": "keys/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": first["build_ns_per_key"] * n * 1e-6, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+        "config": {"workload": f"{n:,} uniform random 64-bit keys at (l, b) = (8, 100), (12, 9), (5, 5), (16, 2000)"
+                               + (" (l=16 skipped above 10^7 keys)" if n > 10_000_000 else ""), "keys": n},
+        "rows": rows,
     }
 
 

@@ -87,7 +87,8 @@ typedef struct {
  * bucket; these knobs set how its lanes and wavefronts share the work.
  *   stage_from: leaves of at least this many keys use the staged (early-exit)
  *               bijection search, smaller ones try 64 candidates on every key
- *               (2..25; 25 = never staged; built-in 9).
+ *               (2..25; 25 = none of 16 keys or fewer; built-in 9).  Leaves of
+ *               17 or more keys are always staged.
  *   group_max : 1 + the largest log2 of lanes that share one split candidate
  *               (1 = one lane per candidate .. 7 = up to 64; built-in 7).  The
  *               lanes per candidate of each node size come from its expected
@@ -258,12 +259,29 @@ typedef struct {
     uint64_t batches, batched_requests, max_batch, max_concurrent_batches;
     uint64_t peak_in_flight_bytes, budget_bytes;
     uint32_t max_queue;
+    uint32_t lookup_cus;  /* compute units kept free of build work (0: none) */
 } rs_server_stats;
 
 /* Start a server with a device-memory budget for builds in flight (bytes) and
  * `build_workers` build streams (0 = 2, at most 8); opts as for rs_build_ex (its
  * RS_OPT_TIMING flag is ignored). */
 int rs_server_create(uint64_t hbm_budget_bytes, uint32_t build_workers, const rs_options* opts, rs_server** out);
+
+/* Server configuration for rs_server_create_ex.
+ *   hbm_budget_bytes, build_workers: as for rs_server_create.
+ *   lookup_cus: compute units the build streams never use (a CU mask on
+ *     every build worker's stream), spread evenly over the device's CU
+ *     numbers; lookups run on all CUs and so always find these free, even
+ *     when every other CU runs long seed-search workgroups.  0 = none; at
+ *     most half of the CUs. */
+typedef struct {
+    uint64_t hbm_budget_bytes;
+    uint32_t build_workers;
+    uint32_t lookup_cus;
+    uint32_t reserved[4];
+} rs_server_config;
+
+int rs_server_create_ex(const rs_server_config* config, const rs_options* opts, rs_server** out);
 
 /* Enqueue a build; *ticket identifies it.  Errors: RS_EINVAL, RS_EBUSY (stopping). */
 int rs_server_submit_build(rs_server* srv, const rs_keys* keys, uint32_t leaf, uint32_t bucket, uint64_t* ticket);
@@ -288,7 +306,6 @@ int rs_server_get_stats(rs_server* srv, rs_server_stats* out);
  * were never collected are freed). */
 void rs_server_destroy(rs_server* srv);
 
-/* Library version string. */
 /* The per-size tables a structure with leaf size l uses, for node sizes
  * m = 0..maxm (host arrays of maxm+1 entries each, written by the call):
  *   r[m]: Golomb-Rice parameter of a node of m keys, eq. (4) with the exact
@@ -299,6 +316,7 @@ void rs_server_destroy(rs_server* srv);
  * RS_ENOMEM. */
 int rs_tables(uint32_t leaf, uint32_t maxm, uint32_t* r, uint32_t* F, uint32_t* N);
 
+/* Library version string. */
 const char* rs_version(void);
 
 #ifdef __cplusplus

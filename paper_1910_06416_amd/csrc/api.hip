@@ -109,18 +109,43 @@ __device__ __forceinline__ uint32_t select_in_word(uint64_t x, uint32_t k) {
 
 // Position of the k-th set bit at or after bit position p of an array of
 // `words` words; a position past the end if there is no such bit (only in a
-// corrupted structure).
+// corrupted structure).  Words after the first are read four at a time (the
+// loads are independent, so a long scan costs one memory round trip per four
+// words instead of one per word).
 __device__ __forceinline__ uint64_t select_from(const uint64_t* a, uint64_t words, uint64_t p, uint64_t k) {
     uint64_t w = p >> 6;
     if (w >= words) return words << 6;
-    uint64_t word = a[w] & (~0ull << (p & 63));
-    for (;;) {
-        uint32_t c = (uint32_t)__popcll(word);
-        if (k < c) return (w << 6) + select_in_word(word, (uint32_t)k);
-        k -= c;
-        if (++w >= words) return words << 6;
-        word = a[w];
+    const uint64_t first = a[w] & (~0ull << (p & 63));
+    uint32_t c = (uint32_t)__popcll(first);
+    if (k < c) return (w << 6) + select_in_word(first, (uint32_t)k);
+    k -= c;
+    for (w++; w < words; w += 4) {
+        uint64_t x[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++) x[u] = w + u < words ? a[w + u] : 0;
+#pragma unroll
+        for (int u = 0; u < 4; u++) {
+            c = (uint32_t)__popcll(x[u]);
+            if (k < c) return ((w + u) << 6) + select_in_word(x[u], (uint32_t)k);
+            k -= c;
+        }
     }
+    return words << 6;
+}
+
+// Positions of the k-th and the (k+1)-th set bits at or after bit p (the
+// second one is usually in the same word as the first).
+__device__ __forceinline__ void select_pair(const uint64_t* a, uint64_t words, uint64_t p, uint64_t k,
+                                            uint64_t& first, uint64_t& second) {
+    first = select_from(a, words, p, k);
+    const uint64_t w = first >> 6;
+    if (w >= words) {
+        second = words << 6;
+        return;
+    }
+    const uint32_t b = (uint32_t)(first & 63);
+    const uint64_t rest = b == 63 ? 0 : a[w] & (~0ull << (b + 1));
+    second = rest ? (w << 6) + (uint64_t)__builtin_ctzll(rest) : select_from(a, words, (w + 1) << 6, 0);
 }
 
 __device__ __forceinline__ uint64_t get_bits(const uint64_t* a, uint64_t pos, uint32_t nbits) {
@@ -141,8 +166,8 @@ __device__ uint64_t rank_of(const LookupArgs& a, uint64_t hi, uint64_t lo) {
     const uint64_t* lower = blob + a.lower_off;
     const uint32_t wsz = a.Ws + a.Wz;
     uint64_t inv_s = blob[a.invs_off + (i >> kInvShift)];
-    uint64_t ps = select_from(us, a.us_words, inv_s, i & ((1u << kInvShift) - 1));
-    uint64_t ps1 = select_from(us, a.us_words, ps + 1, 0);
+    uint64_t ps, ps1;
+    select_pair(us, a.us_words, inv_s, i & ((1u << kInvShift) - 1), ps, ps1);
     uint64_t ys = ((ps - i) << a.Ws) | get_bits(lower, i * wsz, a.Ws);
     uint64_t ys1 = ((ps1 - i - 1) << a.Ws) | get_bits(lower, (i + 1) * wsz, a.Ws);
     uint64_t s_i = ys + i * a.delta_s;

@@ -103,7 +103,8 @@ __device__ __forceinline__ uint32_t find_build(const uint64_t* __restrict__ base
 constexpr uint32_t kSigItems = 32;                 // keys per thread in the signature and bin passes
 constexpr uint32_t kSigTile = kBlock * kSigItems;  // keys per block
 constexpr uint32_t kMaxBins = 4096;
-constexpr uint32_t kMaxBinShift = 13;              // at most 8192 buckets per bin
+constexpr uint32_t kMaxBinShift = 16;              // at most 65536 buckets per bin
+constexpr uint32_t kSortSpan = 8192;               // buckets a per-bin sort counts at once in LDS
 constexpr uint32_t kSortBlock = 512;               // threads of the per-bin sort
 
 // dynamic LDS: nbins u32 counters
@@ -276,58 +277,75 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter(const uint64_t* __restri
 }
 
 // One workgroup per bin: bucket counts in LDS, their prefix sums (bstart of
-// the bin's buckets), the largest bucket, and the keys in bucket order.
-// dynamic LDS: 2 * 2^shift u32 (counts, then offsets inside the bin).
+// the bin's buckets), the largest bucket, and the keys in bucket order.  A bin
+// of more than `piece` buckets is done `piece` buckets at a time (each
+// piece reads the bin's keys again and keeps those of its buckets).
+// piece = min(2^shift, kSortSpan, nbuckets); dynamic LDS: 2 * piece u32 (counts,
+// then offsets).
 __global__ __launch_bounds__(kSortBlock) void k_bucket_sort(const uint64_t* __restrict__ bin_start,
                                                            const uint64_t* __restrict__ bin_lo,
                                                            const uint32_t* __restrict__ bin_bid, uint32_t shift,
-                                                           uint64_t nbuckets, uint64_t* __restrict__ bstart,
-                                                           uint64_t* __restrict__ sorted, uint32_t* __restrict__ maxm) {
+                                                           uint32_t piece, uint64_t nbuckets,
+                                                           uint64_t* __restrict__ bstart, uint64_t* __restrict__ sorted,
+                                                           uint32_t* __restrict__ maxm) {
     extern __shared__ uint32_t cnt[];
     __shared__ uint32_t wsum[kSortBlock / 64];
     const uint32_t tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const uint64_t g0 = (uint64_t)blockIdx.x << shift;
     const uint32_t span = (uint32_t)min<uint64_t>(1ull << shift, nbuckets - g0);
-    uint32_t* offs = cnt + (1u << shift);
-    for (uint32_t j = tid; j < span; j += kSortBlock) cnt[j] = 0;
-    __syncthreads();
+    uint32_t* offs = cnt + piece;
     const uint64_t s = bin_start[blockIdx.x], e = bin_start[blockIdx.x + 1];
-    for (uint64_t i = s + tid; i < e; i += kSortBlock) atomicAdd(&cnt[bin_bid[i] - (uint32_t)g0], 1u);
-    __syncthreads();
-    // exclusive scan of cnt[0, span): each thread sums a chunk, the block scans the chunk sums
-    const uint32_t chunk = (span + kSortBlock - 1) / kSortBlock;
-    const uint32_t j0 = min(span, tid * chunk), j1 = min(span, j0 + chunk);
-    uint32_t sum = 0, mx = 0;
-    for (uint32_t j = j0; j < j1; j++) {
-        sum += cnt[j];
-        mx = max(mx, cnt[j]);
-    }
-    uint32_t x = sum;
+    uint64_t base = s;  // sorted position of the first key of the current piece
+    for (uint32_t sub = 0; sub < span; sub += piece) {
+        const uint32_t len = min(piece, span - sub);
+        const uint32_t first = (uint32_t)(g0 + sub);  // global number of the piece's first bucket
+        for (uint32_t j = tid; j < len; j += kSortBlock) cnt[j] = 0;
+        __syncthreads();
+        for (uint64_t i = s + tid; i < e; i += kSortBlock) {
+            const uint32_t b = bin_bid[i] - first;  // wraps above len for buckets outside the piece
+            if (b < len) atomicAdd(&cnt[b], 1u);
+        }
+        __syncthreads();
+        // exclusive scan of cnt[0, len): each thread sums a chunk, the block scans the chunk sums
+        const uint32_t chunk = (len + kSortBlock - 1) / kSortBlock;
+        const uint32_t j0 = min(len, tid * chunk), j1 = min(len, j0 + chunk);
+        uint32_t sum = 0, mx = 0;
+        for (uint32_t j = j0; j < j1; j++) {
+            sum += cnt[j];
+            mx = max(mx, cnt[j]);
+        }
+        uint32_t x = sum;
 #pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        uint32_t y = __shfl_up(x, o, 64);
-        if (lane >= (uint32_t)o) x += y;
-    }
-    if (lane == 63) wsum[wid] = x;
-    for (int o = 32; o > 0; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, o, 64));
-    if (lane == 0 && mx) atomicMax(maxm, mx);
-    __syncthreads();
-    uint32_t pre = 0;
-    for (uint32_t w = 0; w < wid; w++) pre += wsum[w];
-    uint32_t run = pre + x - sum;
-    for (uint32_t j = j0; j < j1; j++) {
-        offs[j] = run;
-        bstart[g0 + j] = s + run;
-        run += cnt[j];
+        for (int o = 1; o < 64; o <<= 1) {
+            uint32_t y = __shfl_up(x, o, 64);
+            if (lane >= (uint32_t)o) x += y;
+        }
+        if (lane == 63) wsum[wid] = x;
+        for (int o = 32; o > 0; o >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, o, 64));
+        if (lane == 0 && mx) atomicMax(maxm, mx);
+        __syncthreads();
+        uint32_t pre = 0, piece_total = 0;
+        for (uint32_t w = 0; w < kSortBlock / 64; w++) {
+            pre += w < wid ? wsum[w] : 0;
+            piece_total += wsum[w];
+        }
+        uint32_t run = pre + x - sum;
+        for (uint32_t j = j0; j < j1; j++) {
+            offs[j] = run;
+            bstart[first + j] = base + run;
+            run += cnt[j];
+        }
+        __syncthreads();
+        for (uint32_t j = tid; j < len; j += kSortBlock) cnt[j] = 0;
+        __syncthreads();
+        for (uint64_t i = s + tid; i < e; i += kSortBlock) {
+            const uint32_t b = bin_bid[i] - first;
+            if (b < len) sorted[base + offs[b] + atomicAdd(&cnt[b], 1u)] = bin_lo[i];
+        }
+        base += piece_total;
+        __syncthreads();
     }
     if (blockIdx.x + 1 == gridDim.x && tid == 0) bstart[nbuckets] = e;
-    __syncthreads();
-    for (uint32_t j = tid; j < span; j += kSortBlock) cnt[j] = 0;
-    __syncthreads();
-    for (uint64_t i = s + tid; i < e; i += kSortBlock) {
-        const uint32_t b = bin_bid[i] - (uint32_t)g0;
-        sorted[s + offs[b] + atomicAdd(&cnt[b], 1u)] = bin_lo[i];
-    }
 }
 
 }  // namespace
@@ -1769,7 +1787,8 @@ int batch_layout(Batch& b) {
     // bins of the two-level bucket sort: about 16k keys each, at most kMaxBins
     const double keys_per_bucket = (double)b.total / (double)b.nbuckets;
     b.shift = 0;
-    while (b.shift < kMaxBinShift && (double)(2ull << b.shift) * keys_per_bucket <= 16384.0) b.shift++;
+    // (a bin of more than kSortSpan buckets only when the bin count requires it)
+    while ((1u << (b.shift + 1)) <= kSortSpan && (double)(2ull << b.shift) * keys_per_bucket <= 16384.0) b.shift++;
     while (b.shift < kMaxBinShift && ((b.nbuckets + (1ull << b.shift) - 1) >> b.shift) > kMaxBins) b.shift++;
     const uint64_t nbins64 = (b.nbuckets + (1ull << b.shift) - 1) >> b.shift;
     if (nbins64 > kMaxBins) return fail(RS_EINVAL, "too many buckets in one call");
@@ -1862,7 +1881,9 @@ int enqueue_front(Batch& b, hipStream_t s, PhaseEvents* pe) {
     k_bin_offsets<<<1, kBlock, 0, s>>>(b.d_bincnt, b.nbins, b.nxcd, b.d_binst, b.d_bincur);
     k_bin_scatter<<<grid_for(b.total, kSigTile), kBlock, b.nbins * 12, s>>>(
         b.d_lo, b.d_bid, b.total, b.shift, b.nbins, b.nxcd, b.d_bincur, bin_lo, bin_bid);
-    k_bucket_sort<<<b.nbins, kSortBlock, (8u << b.shift), s>>>(b.d_binst, bin_lo, bin_bid, b.shift, b.nbuckets,
+    const uint32_t piece = (uint32_t)std::min<uint64_t>(std::min(1u << b.shift, kSortSpan), b.nbuckets);
+    k_bucket_sort<<<b.nbins, kSortBlock, 8u * piece, s>>>(
+        b.d_binst, bin_lo, bin_bid, b.shift, piece, b.nbuckets,
                                                               b.d_bst, b.d_sorted, &b.d_st->maxm);
     if (pe) pe->record(2, s);
     RS_ENQ(hipGetLastError());

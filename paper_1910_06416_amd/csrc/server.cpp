@@ -69,6 +69,8 @@ struct rs_server {
     bool stopping = false;
     int device = 0;
     rs_options opts{};
+    uint32_t lookup_cus = 0;
+    std::vector<uint32_t> build_mask;  // CU mask of the build streams (empty: all CUs)
     std::vector<std::thread> workers;
 };
 
@@ -86,7 +88,12 @@ void finish(rs_server* s, const Request& r, int status, rs_blob* blob, uint32_t 
 void build_worker(rs_server* s) {
     (void)hipSetDevice(s->device);
     hipStream_t stream = nullptr;
-    if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) stream = nullptr;
+    if (!s->build_mask.empty()) {
+        if (hipExtStreamCreateWithCUMask(&stream, (uint32_t)s->build_mask.size(), s->build_mask.data()) != hipSuccess)
+            stream = nullptr;
+    } else if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) {
+        stream = nullptr;
+    }
     for (;;) {
         std::vector<Request> batch;
         uint64_t bytes = 0;
@@ -172,21 +179,46 @@ void lookup_worker(rs_server* s) {
 
 }  // namespace
 
-extern "C" int rs_server_create(uint64_t hbm_budget_bytes, uint32_t build_workers, const rs_options* opts,
-                                rs_server** out) {
+extern "C" int rs_server_create_ex(const rs_server_config* cfg, const rs_options* opts, rs_server** out) {
     rs::clear_error();
-    if (!out || hbm_budget_bytes == 0) return rs::fail(RS_EINVAL, "NULL argument or zero budget");
+    if (!cfg || !out || cfg->hbm_budget_bytes == 0) return rs::fail(RS_EINVAL, "NULL argument or zero budget");
+    int dev = 0, ncu = 0;
+    (void)hipGetDevice(&dev);
+    if (cfg->lookup_cus) {
+        if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
+            return rs::fail(RS_EDEVICE, "cannot read the compute-unit count");
+        if (cfg->lookup_cus > (uint32_t)ncu / 2) return rs::fail(RS_EINVAL, "lookup_cus exceeds half of the CUs");
+    }
     rs_server* s = new (std::nothrow) rs_server;
     if (!s) return rs::fail(RS_ENOMEM, "host allocation failed");
-    s->budget = hbm_budget_bytes;
+    s->budget = cfg->hbm_budget_bytes;
     if (opts) s->opts = *opts;
     s->opts.flags &= ~(uint32_t)RS_OPT_TIMING;
-    (void)hipGetDevice(&s->device);
-    const uint32_t nw = std::max<uint32_t>(1, std::min<uint32_t>(build_workers ? build_workers : 2, 8));
+    s->device = dev;
+    if (cfg->lookup_cus) {
+        // every CU but lookup_cus of them, spread evenly over the CU numbers
+        s->lookup_cus = cfg->lookup_cus;
+        s->build_mask.assign(((uint32_t)ncu + 31) / 32, 0u);
+        const uint32_t step = (uint32_t)ncu / cfg->lookup_cus;
+        for (uint32_t c = 0; c < (uint32_t)ncu; c++) {
+            const bool kept = c % step == 0 && c / step < cfg->lookup_cus;
+            if (!kept) s->build_mask[c / 32] |= 1u << (c % 32);
+        }
+    }
+    const uint32_t bw = cfg->build_workers;
+    const uint32_t nw = std::max<uint32_t>(1, std::min<uint32_t>(bw ? bw : 2, 8));
     for (uint32_t i = 0; i < nw; i++) s->workers.emplace_back(build_worker, s);
     s->workers.emplace_back(lookup_worker, s);
     *out = s;
     return RS_OK;
+}
+
+extern "C" int rs_server_create(uint64_t hbm_budget_bytes, uint32_t build_workers, const rs_options* opts,
+                                rs_server** out) {
+    rs_server_config cfg{};
+    cfg.hbm_budget_bytes = hbm_budget_bytes;
+    cfg.build_workers = build_workers;
+    return rs_server_create_ex(&cfg, opts, out);
 }
 
 static int submit(rs_server* s, Request r, uint64_t* ticket) {
@@ -270,6 +302,7 @@ extern "C" int rs_server_get_stats(rs_server* s, rs_server_stats* out) {
     out->peak_in_flight_bytes = s->peak_in_flight;
     out->budget_bytes = s->budget;
     out->max_queue = s->max_queue;
+    out->lookup_cus = s->lookup_cus;
     return RS_OK;
 }
 

@@ -61,7 +61,12 @@ class rs_build_stats(ctypes.Structure):
 class rs_server_stats(ctypes.Structure):
     _fields_ = [("batches", ctypes.c_uint64), ("batched_requests", ctypes.c_uint64), ("max_batch", ctypes.c_uint64),
                 ("max_concurrent_batches", ctypes.c_uint64), ("peak_in_flight_bytes", ctypes.c_uint64),
-                ("budget_bytes", ctypes.c_uint64), ("max_queue", ctypes.c_uint32)]
+                ("budget_bytes", ctypes.c_uint64), ("max_queue", ctypes.c_uint32), ("lookup_cus", ctypes.c_uint32)]
+
+
+class rs_server_config(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("build_workers", ctypes.c_uint32),
+                ("lookup_cus", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 4)]
 
 
 _lib = None
@@ -96,6 +101,8 @@ def lib() -> ctypes.CDLL:
         PU64, PI, PD, PU32 = (ctypes.POINTER(U64), ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
                               ctypes.POINTER(U32))
         L.rs_server_create.argtypes = [U64, U32, ctypes.POINTER(rs_options), ctypes.POINTER(P)]
+        L.rs_server_create_ex.argtypes = [ctypes.POINTER(rs_server_config), ctypes.POINTER(rs_options),
+                                          ctypes.POINTER(P)]
         L.rs_server_submit_build.argtypes = [P, ctypes.POINTER(rs_keys), U32, U32, PU64]
         L.rs_server_submit_lookup.argtypes = [P, P, ctypes.POINTER(rs_keys), P, PU64]
         L.rs_server_poll.argtypes = [P, U64, PI, PI, ctypes.POINTER(P), PD, PU32]
@@ -116,7 +123,7 @@ def lib() -> ctypes.CDLL:
         L.rs_plan_destroy.argtypes = [P]
         L.rs_plan_destroy.restype = None
         for f in ("rs_build", "rs_build_ex", "rs_lookup", "rs_blob_to_host", "rs_blob_from_host", "rs_blob_info",
-                  "rs_tables", "rs_last_build_stats", "rs_build_batch", "rs_server_create", "rs_server_submit_build",
+                  "rs_tables", "rs_last_build_stats", "rs_build_batch", "rs_server_create", "rs_server_create_ex", "rs_server_submit_build",
                   "rs_server_submit_lookup", "rs_server_poll", "rs_server_wait", "rs_server_get_stats", "rs_autotune",
                   "rs_schedule_get", "rs_schedule_set", "rs_plan_create", "rs_plan_run", "rs_plan_info"):
             getattr(L, f).restype = ctypes.c_int
@@ -362,10 +369,11 @@ class Server:
     the server keeps a reference to them until then."""
 
     def __init__(self, budget_bytes: int, build_workers: int = 2, stage_from: int = 0, group_max: int = 0,
-                 waves: int = 0, tuned: bool = False):
+                 waves: int = 0, tuned: bool = False, lookup_cus: int = 0):
         self._h = ctypes.c_void_p()
         opts = _options(0, False, tuned, stage_from, group_max, waves)
-        _check(lib().rs_server_create(budget_bytes, build_workers, ctypes.byref(opts), ctypes.byref(self._h)))
+        cfg = rs_server_config(budget_bytes, build_workers, lookup_cus)
+        _check(lib().rs_server_create_ex(ctypes.byref(cfg), ctypes.byref(opts), ctypes.byref(self._h)))
         self._keep = {}
 
     def submit_build(self, keys, leaf: int, bucket: int) -> int:

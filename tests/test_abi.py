@@ -73,6 +73,9 @@ def test_server_argument_validation(lib):
 
     out = ctypes.c_void_p()
     assert lib.rs_server_create(0, 2, None, ctypes.byref(out)) == recsplit.RS_EINVAL
+    assert lib.rs_server_create_ex(None, None, ctypes.byref(out)) == recsplit.RS_EINVAL
+    cfg = recsplit.rs_server_config(0, 2, 0)
+    assert lib.rs_server_create_ex(ctypes.byref(cfg), None, ctypes.byref(out)) == recsplit.RS_EINVAL
 
 
 def test_schedule_table_roundtrip_and_validation(lib):

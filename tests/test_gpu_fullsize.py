@@ -144,3 +144,26 @@ def test_full_batch_4096_l12_b1000(rs, orc):
     for b in blobs:
         b.free()
     torch.cuda.synchronize()
+
+
+def test_many_buckets_sorted_in_pieces(rs, orc):
+    """40M keys with b=1: 40M buckets, so each bin of the bucket sort spans
+    more buckets than it counts at once and is sorted in two pieces.  The
+    Elias-Fano lists of every bucket, sampled buckets and the bijection are
+    checked against the oracle."""
+    n, leaf, bucket = 40_000_000, 5, 1
+    print(f"case many buckets n={n} leaf={leaf} bucket={bucket}", flush=True)
+    keys = inputs.u64_keys(n, 8)
+    dkeys = rs.device_keys(keys)
+    blob = rs.build(dkeys, leaf, bucket)
+    got = blob.to_bytes()
+    h = orc.header(got)
+    sizes = orc.bucket_sizes(keys, n)
+    assert (h["n"], h["nb"], h["maxm"]) == (n, n, int(sizes.max()))
+    s_all, o_all = orc.blob_prefix(got)
+    assert np.array_equal(s_all, np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64))
+    assert o_all[-1] == h["tree_bits"]
+    ranks = rs.lookup(blob, dkeys)
+    assert _is_permutation(ranks)
+    picks = [int(np.argmax(sizes)), 16384 + 3, n - 1]
+    _check_sampled_buckets(rs, orc, keys, got, ranks, leaf, picks)

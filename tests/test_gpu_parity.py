@@ -200,13 +200,15 @@ def _server_mix():
     return specs, [inputs.u64_keys(n, 700 + i) for i, (n, _, _) in enumerate(specs)]
 
 
-def test_server_results_equal_alone(rs, orc):
+@pytest.mark.parametrize("lookup_cus", [0, 16])
+def test_server_results_equal_alone(rs, orc, lookup_cus):
     """Requests submitted together are batched and overlapped; each result is
-    byte-identical to the same build done alone."""
+    byte-identical to the same build done alone (also with build streams kept
+    off some compute units)."""
     specs, host = _server_mix()
     dev = [rs.device_keys(k) for k in host]
-    print("case server mix", flush=True)
-    srv = rs.Server(budget_bytes=8 << 30, build_workers=2)
+    print(f"case server mix lookup_cus={lookup_cus}", flush=True)
+    srv = rs.Server(budget_bytes=8 << 30, build_workers=2, lookup_cus=lookup_cus)
     tickets = [srv.submit_build(d, leaf, bucket) for d, (_, leaf, bucket) in zip(dev, specs)]
     res = [srv.wait(t) for t in tickets]
     stats = srv.stats()
@@ -225,6 +227,7 @@ def test_server_results_equal_alone(rs, orc):
         assert torch.equal(o, rs.lookup(r["blob"], d))
     srv.close()
     assert stats["batched_requests"] == len(specs)
+    assert stats["lookup_cus"] == lookup_cus
     print("server stats", stats, flush=True)
 
 
