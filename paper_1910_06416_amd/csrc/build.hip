@@ -276,76 +276,6 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter(const uint64_t* __restri
     }
 }
 
-// The same scatter with the block's keys put in bin order first, so that a
-// wavefront's stores go to consecutive addresses of one run (the per-lane form
-// above sends every lane to a different bin and leaves most lines partly
-// written).  LDS holds only a 16-bit source index per output slot; the second
-// pass rereads the tile's keys, which were just loaded.
-// dynamic LDS: nbins u64 bases, nbins u32 offsets, nbins u32 cursors, kSigTile u16 indices.
-constexpr uint32_t kStagedBinsMax = 3072;  // keeps the dynamic LDS within 64 KiB
-__device__ uint64_t block_exclusive_sum(uint64_t v, uint64_t* total);
-__global__ __launch_bounds__(kBlock) void k_bin_scatter_staged(const uint64_t* __restrict__ lo,
-                                                              const uint32_t* __restrict__ bid, uint64_t total,
-                                                              uint32_t shift, uint32_t nbins, uint32_t nxcd,
-                                                              unsigned long long* __restrict__ bin_cur,
-                                                              uint64_t* __restrict__ bin_lo,
-                                                              uint32_t* __restrict__ bin_bid) {
-    extern __shared__ unsigned long long bases[];
-    uint32_t* loff = reinterpret_cast<uint32_t*>(bases + nbins);
-    uint32_t* cur = loff + nbins;
-    uint16_t* idx = reinterpret_cast<uint16_t*>(cur + nbins);
-    for (uint32_t c = threadIdx.x; c < nbins; c += kBlock) cur[c] = 0;
-    __syncthreads();
-    const uint64_t tile0 = (uint64_t)blockIdx.x * kSigTile;
-    const uint64_t base = tile0 + threadIdx.x;
-    const uint32_t tile_n = (uint32_t)min<uint64_t>(kSigTile, total - tile0);
-    uint32_t b[kSigItems];
-#pragma unroll
-    for (uint32_t it = 0; it < kSigItems; it++) {
-        const uint64_t i = base + (uint64_t)it * kBlock;
-        b[it] = i < total ? bid[i] : ~0u;
-    }
-#pragma unroll
-    for (uint32_t it = 0; it < kSigItems; it++)
-        if (b[it] != ~0u) atomicAdd(&cur[b[it] >> shift], 1u);
-    __syncthreads();
-    // global run of every bin the block touches (inside its XCD's part of the bin),
-    // and the bins' offsets inside the block's bin-ordered tile
-    const uint32_t x = blockIdx.x % nxcd;
-    const uint32_t chunk = (nbins + kBlock - 1) / kBlock;
-    const uint32_t c0 = min(nbins, threadIdx.x * chunk), c1 = min(nbins, c0 + chunk);
-    uint64_t part = 0;
-    for (uint32_t c = c0; c < c1; c++) {
-        const uint32_t h = cur[c];
-        if (h) bases[c] = atomicAdd(&bin_cur[c * nxcd + x], (unsigned long long)h);
-        part += h;
-    }
-    uint64_t tot;
-    uint32_t run = (uint32_t)block_exclusive_sum(part, &tot);
-    for (uint32_t c = c0; c < c1; c++) {
-        loff[c] = run;
-        run += cur[c];
-    }
-    __syncthreads();
-    for (uint32_t c = threadIdx.x; c < nbins; c += kBlock) cur[c] = 0;
-    __syncthreads();
-#pragma unroll
-    for (uint32_t it = 0; it < kSigItems; it++) {
-        if (b[it] == ~0u) continue;
-        const uint32_t c = b[it] >> shift;
-        idx[loff[c] + atomicAdd(&cur[c], 1u)] = (uint16_t)(it * kBlock + threadIdx.x);
-    }
-    __syncthreads();
-    for (uint32_t p = threadIdx.x; p < tile_n; p += kBlock) {
-        const uint64_t i = tile0 + idx[p];
-        const uint32_t bb = bid[i];
-        const uint32_t c = bb >> shift;
-        const uint64_t pos = bases[c] + (p - loff[c]);
-        bin_lo[pos] = lo[i];
-        bin_bid[pos] = bb;
-    }
-}
-
 // One workgroup per bin: bucket counts in LDS, their prefix sums (bstart of
 // the bin's buckets), the largest bucket, and the keys in bucket order.  A bin
 // of more than `piece` buckets is done `piece` buckets at a time (each
@@ -1951,12 +1881,8 @@ int enqueue_front(Batch& b, hipStream_t s, PhaseEvents* pe) {
     uint64_t* bin_lo = b.d_tmp;
     uint32_t* bin_bid = (uint32_t*)b.d_seeds;
     k_bin_offsets<<<1, kBlock, 0, s>>>(b.d_bincnt, b.nbins, b.nxcd, b.d_binst, b.d_bincur);
-    if (b.nbins <= kStagedBinsMax)
-        k_bin_scatter_staged<<<grid_for(b.total, kSigTile), kBlock, b.nbins * 16 + kSigTile * 2, s>>>(
-            b.d_lo, b.d_bid, b.total, b.shift, b.nbins, b.nxcd, b.d_bincur, bin_lo, bin_bid);
-    else
-        k_bin_scatter<<<grid_for(b.total, kSigTile), kBlock, b.nbins * 12, s>>>(
-            b.d_lo, b.d_bid, b.total, b.shift, b.nbins, b.nxcd, b.d_bincur, bin_lo, bin_bid);
+    k_bin_scatter<<<grid_for(b.total, kSigTile), kBlock, b.nbins * 12, s>>>(
+        b.d_lo, b.d_bid, b.total, b.shift, b.nbins, b.nxcd, b.d_bincur, bin_lo, bin_bid);
     const uint32_t piece = (uint32_t)std::min<uint64_t>(std::min(1u << b.shift, kSortSpan), b.nbuckets);
     k_bucket_sort<<<b.nbins, kSortBlock, 8u * piece, s>>>(
         b.d_binst, bin_lo, bin_bid, b.shift, piece, b.nbuckets,

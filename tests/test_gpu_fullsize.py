@@ -148,11 +148,11 @@ def test_full_batch_4096_l12_b1000(rs, orc):
 
 @pytest.mark.parametrize("n", [30_000_000, 40_000_000])
 def test_many_buckets_sorted_in_pieces(rs, orc, n):
-    """b=1, so one bucket per key.  At 30M buckets the bucket sort has more
-    than 3072 bins and takes its per-lane scatter.  At 40M each bin spans more
-    buckets than it counts at once and is sorted in two pieces.  The
-    Elias-Fano lists of every bucket, sampled buckets and the bijection are
-    checked against the oracle."""
+    """b=1, so one bucket per key.  At 30M buckets the bucket sort has 3663
+    bins of 8192 buckets (one piece each); at 40M each bin spans more buckets
+    than it counts at once and is sorted in two pieces.  The Elias-Fano lists
+    of every bucket, sampled buckets and the bijection are checked against the
+    oracle."""
     leaf, bucket = 5, 1
     print(f"case many buckets n={n} leaf={leaf} bucket={bucket}", flush=True)
     keys = inputs.u64_keys(n, 8)
