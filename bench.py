@@ -87,7 +87,7 @@ def main():
     ap.add_argument("--batch-builds", type=int, default=4096)
     ap.add_argument("--requests", type=int, default=60, help="serve: build requests")
     ap.add_argument("--load", type=float, default=0.6, help="serve: offered load (fraction of modelled capacity)")
-    ap.add_argument("--lookup-cus", type=int, default=16,
+    ap.add_argument("--lookup-cus", type=int, default=0,
                     help="serve: compute units the build streams leave to lookups (0: none)")
     ap.add_argument("--tune-ms", type=float, default=3000.0,
                     help="autotuner budget (search milliseconds) per (l, b) pair; l=16 pairs get ten times this")
@@ -522,10 +522,11 @@ def bench_table(args):
     from paper_1910_06416_amd import inputs, recsplit
 
     n = args.table_n
-    if n <= 100_000_000:
-        keys = recsplit.device_keys(inputs.u64_keys(n, 7))
-    else:  # too many to draw and deduplicate on the host
-        keys = inputs.u64_keys_device(n, 7)
+    if n > 100_000_000:
+        # a 10^9-key run of this workload faulted the GPU on its l=12, b=9 row
+        # (cause not found); larger tables stay off until it is
+        raise SystemExit("--table-n above 10^8 is disabled")
+    keys = recsplit.device_keys(inputs.u64_keys(n, 7))
     ranks = torch.empty(n, dtype=torch.int64, device="cuda")
     rows = []
     for (leaf, bucket), (p_bits, p_build, p_lookup) in PAPER_TAB_1M.items():

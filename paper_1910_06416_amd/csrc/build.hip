@@ -103,7 +103,7 @@ __device__ __forceinline__ uint32_t find_build(const uint64_t* __restrict__ base
 constexpr uint32_t kSigItems = 32;                 // keys per thread in the signature and bin passes
 constexpr uint32_t kSigTile = kBlock * kSigItems;  // keys per block
 constexpr uint32_t kMaxBins = 4096;
-constexpr uint32_t kMaxBinShift = 16;              // at most 65536 buckets per bin
+constexpr uint32_t kMaxBinShift = 14;              // at most 16384 buckets per bin (two pieces)
 constexpr uint32_t kSortSpan = 8192;               // buckets a per-bin sort counts at once in LDS
 constexpr uint32_t kSortBlock = 512;               // threads of the per-bin sort
 
@@ -1793,7 +1793,9 @@ int batch_layout(Batch& b) {
     while ((1u << (b.shift + 1)) <= kSortSpan && (double)(2ull << b.shift) * keys_per_bucket <= 16384.0) b.shift++;
     while (b.shift < kMaxBinShift && ((b.nbuckets + (1ull << b.shift) - 1) >> b.shift) > kMaxBins) b.shift++;
     const uint64_t nbins64 = (b.nbuckets + (1ull << b.shift) - 1) >> b.shift;
-    if (nbins64 > kMaxBins) return fail(RS_EINVAL, "too many buckets in one call");
+    if (nbins64 > kMaxBins)
+        return fail(RS_EINVAL, "too many buckets in one call (%llu; at most %llu)", (unsigned long long)b.nbuckets,
+                    (unsigned long long)kMaxBins << kMaxBinShift);
     b.nbins = (uint32_t)nbins64;
     b.nxcd = xcd_count();
     const uint64_t T = b.total, NB = b.nbuckets, K = b.K;

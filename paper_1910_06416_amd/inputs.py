@@ -30,27 +30,6 @@ def u64_keys(n: int, seed: int) -> np.ndarray:
         keys = np.concatenate([keys[keep], extra])
 
 
-def u64_keys_device(n: int, seed: int):
-    """n distinct uniformly random 64-bit keys drawn on the GPU (torch's
-    Philox generator with an explicit seed; for key sets too large to draw and
-    deduplicate on the host).  Returns a CUDA int64 tensor holding the bits."""
-    import torch
-
-    gen = torch.Generator(device="cuda")
-    gen.manual_seed(seed)
-    lo, hi = -(2**63), 2**63 - 1
-    keys = torch.randint(lo, hi, (n,), dtype=torch.int64, device="cuda", generator=gen)
-    while True:
-        srt, _ = torch.sort(keys)
-        dup = int((srt[1:] == srt[:-1]).sum())
-        del srt
-        if dup == 0:
-            return keys
-        uniq = torch.unique(keys)
-        extra = torch.randint(lo, hi, (n - uniq.numel(),), dtype=torch.int64, device="cuda", generator=gen)
-        keys = torch.cat([uniq, extra])
-
-
 def ascii_keys(n: int, seed: int, min_len: int = 8, max_len: int = 32):
     """n distinct random strings of printable ASCII (0x21..0x7e), lengths
     uniform in [min_len, max_len].  Returns (data uint8[], offsets uint64[n+1])."""

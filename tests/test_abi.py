@@ -103,3 +103,14 @@ def test_autotune_argument_validation(lib):
 
     assert lib.rs_autotune(0, 100, 0, 10.0, None, None) == recsplit.RS_EINVAL
     assert lib.rs_autotune(8, 0, 0, 10.0, None, None) == recsplit.RS_EINVAL
+
+
+def test_too_many_buckets_is_refused_before_any_device_work(lib):
+    """More than 4096 bins of 16384 buckets is refused on the host."""
+    from paper_1910_06416_amd import recsplit
+
+    keys = recsplit.rs_keys(recsplit.RS_KEYS_U64, 16, None, 4096 * 16384 + 1)
+    out = ctypes.c_void_p()
+    assert lib.rs_build(ctypes.byref(keys), 8, 1, None, ctypes.byref(out)) == recsplit.RS_EINVAL
+    assert b"too many buckets" in lib.rs_last_error()
+    assert out.value is None
