@@ -270,10 +270,10 @@ int rs_server_create(uint64_t hbm_budget_bytes, uint32_t build_workers, const rs
 /* Server configuration for rs_server_create_ex.
  *   hbm_budget_bytes, build_workers: as for rs_server_create.
  *   lookup_cus: compute units the build streams never use (a CU mask on
- *     every build worker's stream), spread evenly over the device's CU
- *     numbers; lookups run on all CUs and so always find these free, even
- *     when every other CU runs long seed-search workgroups.  0 = none; at
- *     most half of the CUs. */
+ *     every build worker's stream), taken evenly from every XCD; lookups run
+ *     on all CUs and so always find these free, even when every other CU
+ *     runs long seed-search workgroups.  0 = none; at most the CU count of
+ *     one XCD (32 on MI355X), best a multiple of the XCD count (8). */
 typedef struct {
     uint64_t hbm_budget_bytes;
     uint32_t build_workers;

@@ -185,9 +185,12 @@ extern "C" int rs_server_create_ex(const rs_server_config* cfg, const rs_options
     int dev = 0, ncu = 0;
     (void)hipGetDevice(&dev);
     if (cfg->lookup_cus) {
+        int nx = 1;
         if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
             return rs::fail(RS_EDEVICE, "cannot read the compute-unit count");
-        if (cfg->lookup_cus > (uint32_t)ncu / 2) return rs::fail(RS_EINVAL, "lookup_cus exceeds half of the CUs");
+        if (hipDeviceGetAttribute(&nx, hipDeviceAttributeNumberOfXccs, dev) != hipSuccess || nx < 1) nx = 1;
+        if (cfg->lookup_cus > (uint32_t)(ncu / nx))
+            return rs::fail(RS_EINVAL, "lookup_cus exceeds the CUs of one XCD (%d)", ncu / nx);
     }
     rs_server* s = new (std::nothrow) rs_server;
     if (!s) return rs::fail(RS_ENOMEM, "host allocation failed");
@@ -196,14 +199,23 @@ extern "C" int rs_server_create_ex(const rs_server_config* cfg, const rs_options
     s->opts.flags &= ~(uint32_t)RS_OPT_TIMING;
     s->device = dev;
     if (cfg->lookup_cus) {
-        // every CU but lookup_cus of them, spread evenly over the CU numbers
+        // Every CU but lookup_cus of them, taken evenly from every XCD.  Whether
+        // CU numbers run XCD by XCD or alternate between XCDs, CU
+        // per*x + ((x + nxcd*j) mod per) lies on XCD x either way, so no XCD
+        // loses more than its share (an XCD with fewer CUs would finish its
+        // round-robin share of every launch last).
+        int nx = 1;
+        if (hipDeviceGetAttribute(&nx, hipDeviceAttributeNumberOfXccs, dev) != hipSuccess || nx < 1) nx = 1;
+        const uint32_t nxcd = (uint32_t)nx, per = (uint32_t)ncu / nxcd;
+        std::vector<bool> left(ncu, false);
+        for (uint32_t k = 0; k < cfg->lookup_cus; k++) {
+            const uint32_t x = k % nxcd, j = k / nxcd;
+            left[per * x + (x + nxcd * j) % per] = true;
+        }
         s->lookup_cus = cfg->lookup_cus;
         s->build_mask.assign(((uint32_t)ncu + 31) / 32, 0u);
-        const uint32_t step = (uint32_t)ncu / cfg->lookup_cus;
-        for (uint32_t c = 0; c < (uint32_t)ncu; c++) {
-            const bool kept = c % step == 0 && c / step < cfg->lookup_cus;
-            if (!kept) s->build_mask[c / 32] |= 1u << (c % 32);
-        }
+        for (uint32_t c = 0; c < (uint32_t)ncu; c++)
+            if (!left[c]) s->build_mask[c / 32] |= 1u << (c % 32);
     }
     const uint32_t bw = cfg->build_workers;
     const uint32_t nw = std::max<uint32_t>(1, std::min<uint32_t>(bw ? bw : 2, 8));
