@@ -78,8 +78,13 @@ def _declare(L):
     L.orc_blob_bucket.argtypes = [P, U64, U64, P, P, P, P, U64, P]
     L.orc_bucket_ranks.argtypes = [P, U32, U32, U64, P]
     L.orc_blob_prefix.argtypes = [P, U64, P, P]
+    L.orc_blob_check_inventory.argtypes = [P, U64, P]
+    L.orc_inventory_build.argtypes = [P, U64, P, P, U32]
+    L.orc_inventory_build.restype = None
+    L.orc_inventory_select.argtypes = [P, P, P, U32, U64]
+    L.orc_inventory_select.restype = U64
     for f in ("orc_tables", "orc_tree", "orc_build", "orc_lookup", "orc_bucket_sizes", "orc_blob_bucket",
-              "orc_bucket_ranks", "orc_blob_prefix"):
+              "orc_bucket_ranks", "orc_blob_prefix", "orc_blob_check_inventory"):
         getattr(L, f).restype = ctypes.c_int
 
 
@@ -259,6 +264,40 @@ def blob_prefix(blob: bytes):
     if rc:
         raise OracleError(rc, "blob_prefix")
     return s_, o_
+
+
+def blob_check_inventory(blob: bytes) -> int:
+    """Number of ones of the two upper-bit arrays that the inventory search
+    places differently from a plain scan (0 for a correct structure)."""
+    b = np.frombuffer(blob, dtype=np.uint8).copy()
+    bad = U64()
+    rc = lib().orc_blob_check_inventory(_ptr(b), len(blob), ctypes.byref(bad))
+    if rc:
+        raise OracleError(rc, "blob_check_inventory")
+    return bad.value
+
+
+def ones_from_positions(pos: np.ndarray) -> np.ndarray:
+    """A little-endian bit array (uint64 words) with ones at the given positions."""
+    pos = np.asarray(pos, dtype=np.uint64)
+    words = np.zeros(int(pos.max()) // 64 + 2, dtype=np.uint64)
+    np.bitwise_or.at(words, (pos // np.uint64(64)).astype(np.int64), np.left_shift(np.uint64(1), pos % np.uint64(64)))
+    return words
+
+
+def inventory_build(bits: np.ndarray, ones: int):
+    """Two-level inventory of a bit array: (64-bit anchors, 16-bit offsets)."""
+    bits = np.ascontiguousarray(bits, dtype=np.uint64)
+    hi = np.zeros((ones >> 14) + 1, dtype=np.uint64)
+    lo = np.zeros((ones >> 8) + 1, dtype=np.uint16)
+    lib().orc_inventory_build(_ptr(bits), ones, _ptr(hi), _ptr(lo), 1)
+    return hi[: (ones + (1 << 14) - 1) >> 14], lo[: (ones + 255) >> 8]
+
+
+def inventory_select(bits: np.ndarray, hi: np.ndarray, lo: np.ndarray, k: int) -> int:
+    return int(lib().orc_inventory_select(_ptr(np.ascontiguousarray(bits, dtype=np.uint64)),
+                                          _ptr(np.ascontiguousarray(hi, dtype=np.uint64)),
+                                          _ptr(np.ascontiguousarray(lo, dtype=np.uint16)), 1, k))
 
 
 def header(blob: bytes) -> dict:

@@ -18,6 +18,8 @@
  *   strategy + r     Theorem 1 (invariance) and 50-digit evaluation of eq. (4)
  *   whole structure  lookup of every key is a permutation of [0,n)
  *   space            bits/key against the values printed in Table tab:1M
+ *   inventory        every one found through it equals a plain scan, also
+ *                    with 16-bit offsets that overflow       (Sec. 7.4)
  * Exact seeds and blob bytes beyond that are "parity unpinned" by the paper
  * (its worked examples, Figs. 1-2, are not available); they are defined by
  * this file and the format readings.
@@ -31,10 +33,12 @@ enum { ORC_OK = 0, ORC_EINVAL = 1, ORC_EDUPLICATE = 2, ORC_ENOMEM = 3, ORC_ESEAR
 enum { ORC_KEYS_U64 = 1, ORC_KEYS_BYTES = 2 };
 
 #define ORC_MAGIC 0x4648504D4C505352ULL /* "RSPLMPHF" little-endian */
-#define ORC_VERSION 1ULL
+#define ORC_VERSION 2ULL
 #define ORC_HEADER_WORDS 16
 #define ORC_MAX_FANOUT 16
-#define ORC_INV_STRIDE 256
+#define ORC_INV_HI 14 /* a 64-bit anchor for every 2^14-th one (Sec. 7.4) */
+#define ORC_INV_LO 8  /* a 16-bit offset from it for every 2^8-th one */
+#define ORC_INV_OVERFLOW 0xffffu
 #define ORC_DEFAULT_SEED_CAP (1ULL << 56)
 
 /* ------------------------------------------------------------------------ */
@@ -364,6 +368,48 @@ static int cmp_u64(const void* x, const void* y) {
 
 /* Elias-Fano lower width: the largest W >= 0 with N * 2^W <= U, i.e.
  * max{0, floor(lg(U/N))} (Sec. 7.4). */
+/* Two-level inventory of a bit array with `ones` set bits (Sec. 7.4): the
+ * position of every one whose index is a multiple of 2^14 as a 64-bit integer,
+ * and, for every one whose index is a multiple of 2^8, its distance from the
+ * anchor of its 2^14 block as a 16-bit integer; a distance that does not fit
+ * is stored as 0xffff, and a search then starts from the anchor.  The two
+ * Elias-Fano lists of a structure interleave their entries, so the arrays are
+ * written with a stride (hi[j*stride], lo[j*stride]). */
+void orc_inventory_build(const uint64_t* bits, uint64_t ones, uint64_t* hi, uint16_t* lo, uint32_t stride) {
+    uint64_t k = 0, pos = 0, anchor = 0;
+    for (; k < ones; pos++) {
+        if (!((bits[pos / 64] >> (pos % 64)) & 1)) continue;
+        if (k % (1ULL << ORC_INV_HI) == 0) {
+            anchor = pos;
+            hi[(k >> ORC_INV_HI) * stride] = pos;
+        }
+        if (k % (1ULL << ORC_INV_LO) == 0) {
+            uint64_t d = pos - anchor;
+            lo[(k >> ORC_INV_LO) * stride] = (uint16_t)(d < ORC_INV_OVERFLOW ? d : ORC_INV_OVERFLOW);
+        }
+        k++;
+    }
+}
+
+/* Position of the k-th one through the inventory: start at the nearest
+ * recorded one and scan forward bit by bit. */
+uint64_t orc_inventory_select(const uint64_t* bits, const uint64_t* hi, const uint16_t* lo, uint32_t stride,
+                              uint64_t k) {
+    uint64_t pos = hi[(k >> ORC_INV_HI) * stride];
+    uint64_t left = k & ((1ULL << ORC_INV_HI) - 1);
+    uint16_t d = lo[(k >> ORC_INV_LO) * stride];
+    if (d != ORC_INV_OVERFLOW) {
+        pos += d;
+        left = k & ((1ULL << ORC_INV_LO) - 1);
+    }
+    for (;; pos++) {
+        if ((bits[pos / 64] >> (pos % 64)) & 1) {
+            if (left == 0) return pos;
+            left--;
+        }
+    }
+}
+
 static uint32_t ef_width(uint64_t N, uint64_t U) {
     uint32_t W = 0;
     while (W < 62 && (N << (W + 1)) <= U && ((N << (W + 1)) >> (W + 1)) == N) W++;
@@ -491,8 +537,10 @@ int orc_build(uint32_t kind, const void* data, const uint64_t* offsets, uint64_t
     uint64_t us_bits = (ys[Nn - 1] >> Ws) + Nn, uz_bits = (yz[Nn - 1] >> Wz) + Nn;
     uint64_t us_words = (us_bits + 63) / 64, uz_words = (uz_bits + 63) / 64;
     uint64_t lower_words = (Nn * (Ws + Wz) + 63) / 64 + 1;
-    uint64_t ninv = (Nn + ORC_INV_STRIDE - 1) / ORC_INV_STRIDE;
-    uint64_t total_words = ORC_HEADER_WORDS + lower_words + us_words + uz_words + 2 * ninv + tree_words;
+    uint64_t n_hi = (Nn + (1ULL << ORC_INV_HI) - 1) >> ORC_INV_HI;
+    uint64_t n_lo = (Nn + (1ULL << ORC_INV_LO) - 1) >> ORC_INV_LO;
+    uint64_t lo_words = (2 * n_lo + 3) / 4; /* 16-bit entries, four per word */
+    uint64_t total_words = ORC_HEADER_WORDS + lower_words + us_words + uz_words + 2 * n_hi + lo_words + tree_words;
     *size = total_words * 8;
     if (!out || cap < *size) { rc = ORC_OK; goto done; }
 
@@ -507,20 +555,17 @@ int orc_build(uint32_t kind, const void* data, const uint64_t* offsets, uint64_t
     lower = w + ORC_HEADER_WORDS;
     up_s = lower + lower_words;
     up_z = up_s + us_words;
-    uint64_t* inv_s = up_z + uz_words;
-    uint64_t* inv_z = inv_s + ninv;
-    uint64_t* tr = inv_z + ninv;
+    uint64_t* inv_hi = up_z + uz_words;            /* s, z anchors interleaved */
+    uint16_t* inv_lo = (uint16_t*)(inv_hi + 2 * n_hi); /* s, z offsets interleaved */
+    uint64_t* tr = inv_hi + 2 * n_hi + lo_words;
     for (uint64_t i = 0; i < Nn; i++) {
         put_bits(lower, i * (Ws + Wz), ys[i] & ((1ULL << Ws) - 1), Ws);
         put_bits(lower, i * (Ws + Wz) + Ws, yz[i] & ((1ULL << Wz) - 1), Wz);
-        uint64_t ps = (ys[i] >> Ws) + i, pz = (yz[i] >> Wz) + i;
-        put_bits(up_s, ps, 1, 1);
-        put_bits(up_z, pz, 1, 1);
-        if (i % ORC_INV_STRIDE == 0) {
-            inv_s[i / ORC_INV_STRIDE] = ps;
-            inv_z[i / ORC_INV_STRIDE] = pz;
-        }
+        put_bits(up_s, (ys[i] >> Ws) + i, 1, 1);
+        put_bits(up_z, (yz[i] >> Wz) + i, 1, 1);
     }
+    orc_inventory_build(up_s, Nn, inv_hi, inv_lo, 2);
+    orc_inventory_build(up_z, Nn, inv_hi + 1, inv_lo + 1, 2);
     memcpy(tr, tree, tree_words * 8);
     memcpy(out, w, total_words * 8);
     free(w);
@@ -546,6 +591,9 @@ typedef struct {
     uint64_t* o; /* nb+1 bit offsets */
     const uint64_t* tree;
     uint32_t* r;
+    const uint64_t* up[2];    /* upper bits of s and z */
+    const uint64_t* inv_hi;   /* interleaved anchors */
+    const uint16_t* inv_lo;   /* interleaved offsets */
 } decoded;
 
 static uint32_t coded_nodes(const strategy* st, uint32_t m) {
@@ -600,13 +648,18 @@ static int blob_open(const void* blob, uint64_t bytes, decoded* dc) {
     int64_t delta_z = (int64_t)w[9];
     uint64_t beta = w[10], us_words = w[11], uz_words = w[12], lower_words = w[13], tree_words = w[14];
     uint64_t Nn = dc->nb + 1;
-    uint64_t ninv = (Nn + ORC_INV_STRIDE - 1) / ORC_INV_STRIDE;
-    if (bytes != (ORC_HEADER_WORDS + lower_words + us_words + uz_words + 2 * ninv + tree_words) * 8)
+    uint64_t n_hi = (Nn + (1ULL << ORC_INV_HI) - 1) >> ORC_INV_HI;
+    uint64_t lo_words = (2 * ((Nn + (1ULL << ORC_INV_LO) - 1) >> ORC_INV_LO) + 3) / 4;
+    if (bytes != (ORC_HEADER_WORDS + lower_words + us_words + uz_words + 2 * n_hi + lo_words + tree_words) * 8)
         return ORC_EFORMAT;
     const uint64_t* lower = w + ORC_HEADER_WORDS;
     const uint64_t* up_s = lower + lower_words;
     const uint64_t* up_z = up_s + us_words;
-    dc->tree = up_z + uz_words + 2 * ninv;
+    dc->tree = up_z + uz_words + 2 * n_hi + lo_words;
+    dc->up[0] = up_s;
+    dc->up[1] = up_z;
+    dc->inv_hi = up_z + uz_words;
+    dc->inv_lo = (const uint16_t*)(dc->inv_hi + 2 * n_hi);
 
     dc->s = malloc(Nn * 8);
     dc->o = malloc(Nn * 8);
@@ -727,6 +780,26 @@ int orc_blob_prefix(const void* blob, uint64_t bytes, uint64_t* out_s, uint64_t*
     }
     blob_close(&dc);
     return rc;
+}
+
+/* Every k-th one of both upper-bit arrays found through the blob's inventory
+ * against the plain scan the decoder does; returns the number of mismatches
+ * in *bad (a round trip of the inventory, Sec. 7.4). */
+int orc_blob_check_inventory(const void* blob, uint64_t bytes, uint64_t* bad) {
+    decoded dc;
+    int rc = blob_open(blob, bytes, &dc);
+    if (rc) { blob_close(&dc); return rc; }
+    uint64_t miss = 0;
+    for (int list = 0; list < 2; list++) {
+        uint64_t pos = 0;
+        for (uint64_t k = 0; k <= dc.nb; k++, pos++) {
+            while (!get_bit(dc.up[list], pos)) pos++;
+            if (orc_inventory_select(dc.up[list], dc.inv_hi + list, dc.inv_lo + list, 2, k) != pos) miss++;
+        }
+    }
+    *bad = miss;
+    blob_close(&dc);
+    return ORC_OK;
 }
 
 /* Rank of each key of one bucket inside the bucket (0..m-1), from the tree
