@@ -55,13 +55,14 @@ Layout layout_of(const uint64_t* h) {
     L.delta_z = (int64_t)h[9];
     L.beta = h[10];
     L.us_words = h[11]; L.uz_words = h[12]; L.lower_words = h[13]; L.tree_words = h[14]; L.tree_bits = h[15];
-    L.ninv = (L.nb + 1 + (1u << kInvShift) - 1) >> kInvShift;
+    L.hi_words = inv_hi_words(L.nb + 1);
+    L.lo_words = inv_lo_words(L.nb + 1);
     L.lower_off = kHeaderWords;
     L.us_off = L.lower_off + L.lower_words;
     L.uz_off = L.us_off + L.us_words;
-    L.invs_off = L.uz_off + L.uz_words;
-    L.invz_off = L.invs_off + L.ninv;
-    L.tree_off = L.invz_off + L.ninv;
+    L.inv_hi_off = L.uz_off + L.uz_words;
+    L.inv_lo_off = L.inv_hi_off + L.hi_words;
+    L.tree_off = L.inv_lo_off + L.lo_words;
     L.total_words = L.tree_off + L.tree_words;
     return L;
 }
@@ -88,7 +89,7 @@ struct LookupArgs {
     uint64_t nb, beta, delta_s;
     int64_t delta_z;
     uint32_t Ws, Wz;
-    uint64_t lower_off, us_off, uz_off, invs_off, invz_off, tree_off;
+    uint64_t lower_off, us_off, uz_off, inv_hi_off, inv_lo_off, tree_off;
     uint64_t us_words, uz_words, tree_words;
     uint32_t leaf, lower, upper, maxm;
 };
@@ -157,6 +158,22 @@ __device__ __forceinline__ uint64_t get_bits(const uint64_t* a, uint64_t pos, ui
     return nbits == 64 ? v : v & ((1ull << nbits) - 1);
 }
 
+// Where to start looking for the i-th one of list 0 (s) or 1 (z): the
+// recorded one nearest below it in the two-level inventory, and how many ones
+// are left to skip from there (Sec. 7.4).
+__device__ __forceinline__ void inventory_start(const uint64_t* blob, const LookupArgs& a, uint64_t i, uint32_t list,
+                                                uint64_t& start, uint64_t& k) {
+    start = blob[a.inv_hi_off + 2 * (i >> kInvHi) + list];
+    const uint64_t e = 2 * (i >> kInvLo) + list;
+    const uint32_t d = (uint32_t)(blob[a.inv_lo_off + e / 4] >> (16 * (e % 4))) & 0xffffu;
+    if (d != kInvOverflow) {
+        start += d;
+        k = i & ((1u << kInvLo) - 1);
+    } else {
+        k = i & ((1u << kInvHi) - 1);
+    }
+}
+
 __device__ uint64_t rank_of(const LookupArgs& a, uint64_t hi, uint64_t lo) {
     const uint64_t* blob = a.blob;
     const uint64_t i = bucket_of(hi, a.nb);
@@ -165,15 +182,16 @@ __device__ uint64_t rank_of(const LookupArgs& a, uint64_t hi, uint64_t lo) {
     const uint64_t* uz = blob + a.uz_off;
     const uint64_t* lower = blob + a.lower_off;
     const uint32_t wsz = a.Ws + a.Wz;
-    uint64_t inv_s = blob[a.invs_off + (i >> kInvShift)];
+    uint64_t start_s, k_s, start_z, k_z;
+    inventory_start(blob, a, i, 0, start_s, k_s);
+    inventory_start(blob, a, i, 1, start_z, k_z);
     uint64_t ps, ps1;
-    select_pair(us, a.us_words, inv_s, i & ((1u << kInvShift) - 1), ps, ps1);
+    select_pair(us, a.us_words, start_s, k_s, ps, ps1);
     uint64_t ys = ((ps - i) << a.Ws) | get_bits(lower, i * wsz, a.Ws);
     uint64_t ys1 = ((ps1 - i - 1) << a.Ws) | get_bits(lower, (i + 1) * wsz, a.Ws);
     uint64_t s_i = ys + i * a.delta_s;
     uint64_t s_i1 = ys1 + (i + 1) * a.delta_s;
-    uint64_t inv_z = blob[a.invz_off + (i >> kInvShift)];
-    uint64_t pz = select_from(uz, a.uz_words, inv_z, i & ((1u << kInvShift) - 1));
+    uint64_t pz = select_from(uz, a.uz_words, start_z, k_z);
     uint64_t yz = ((pz - i) << a.Wz) | get_bits(lower, i * wsz + a.Ws, a.Wz);
     int64_t z = (int64_t)yz + (int64_t)i * a.delta_z;
     uint64_t o_i = (uint64_t)(z + (int64_t)((a.beta * s_i) >> 16));
@@ -249,8 +267,8 @@ extern "C" int rs_lookup(const rs_blob* blob, const rs_keys* queries, uint64_t* 
     if (queries->kind == RS_KEYS_BYTES && !queries->offsets) return fail(RS_EINVAL, "NULL offsets");
     Strategy st = make_strategy((uint32_t)L.leaf);
     LookupArgs a{blob->words, blob->tables, blob->tables + blob->tab_stride, blob->tables + 2 * blob->tab_stride,
-                 L.nb, L.beta, L.delta_s, L.delta_z, L.Ws, L.Wz, L.lower_off, L.us_off, L.uz_off, L.invs_off,
-                 L.invz_off, L.tree_off, L.us_words, L.uz_words, L.tree_words, (uint32_t)L.leaf, st.lower,
+                 L.nb, L.beta, L.delta_s, L.delta_z, L.Ws, L.Wz, L.lower_off, L.us_off, L.uz_off, L.inv_hi_off,
+                 L.inv_lo_off, L.tree_off, L.us_words, L.uz_words, L.tree_words, (uint32_t)L.leaf, st.lower,
                  st.upper, (uint32_t)L.maxm};
     hipStream_t s = (hipStream_t)stream;
     if (blob->ready) RS_HIP(hipStreamWaitEvent(s, blob->ready, 0));  // built on another stream

@@ -73,7 +73,7 @@ struct BuildDesc {
     // written by the host once the sizes are known
     unsigned long long* blob;  // null: no blob for this build
     uint64_t beta;
-    uint64_t lower_off, us_off, uz_off, invs_off, invz_off, tree_off;
+    uint64_t lower_off, us_off, uz_off, inv_hi_off, inv_lo_off, tree_off;
     uint32_t Ws, Wz;
 };
 
@@ -1200,9 +1200,22 @@ __global__ void k_ef_fill(FillArgs a) {
     const uint64_t ps = (ys >> B.Ws) + i, pz = (yz >> B.Wz) + i;
     or_bits(blob + B.us_off, ps, 1, 1);
     or_bits(blob + B.uz_off, pz, 1, 1);
-    if ((i & ((1u << kInvShift) - 1)) == 0) {
-        blob[B.invs_off + (i >> kInvShift)] = ps;
-        blob[B.invz_off + (i >> kInvShift)] = pz;
+    // two-level inventory (Sec. 7.4), s and z interleaved
+    if ((i & ((1u << kInvHi) - 1)) == 0) {
+        blob[B.inv_hi_off + 2 * (i >> kInvHi)] = ps;
+        blob[B.inv_hi_off + 2 * (i >> kInvHi) + 1] = pz;
+    }
+    if ((i & ((1u << kInvLo) - 1)) == 0) {
+        // the anchor: the one of index i rounded down to a multiple of 2^14
+        const uint64_t an = i & ~(uint64_t)((1u << kInvHi) - 1);
+        const uint64_t sa = a.bstart[bb + an] - a.bstart[bb];
+        const int64_t za = z_of(a.ostart[bb + an] - a.ostart[bb], sa, B.beta);
+        const uint64_t pa_s = ((sa - an * B.delta_s) >> B.Ws) + an;
+        const uint64_t pa_z = ((uint64_t)(za - (int64_t)an * B.delta_z) >> B.Wz) + an;
+        const uint64_t ds = ps - pa_s, dz = pz - pa_z;
+        const uint64_t vs = ds < kInvOverflow ? ds : kInvOverflow, vz = dz < kInvOverflow ? dz : kInvOverflow;
+        const uint64_t e = 2 * (i >> kInvLo);  // s entry; z is e + 1, in the same word
+        atomicOr(&blob[B.inv_lo_off + e / 4], (unsigned long long)((vs | vz << 16) << (16 * (e % 4))));
     }
 }
 
@@ -1290,16 +1303,16 @@ __device__ uint64_t geometry_of(BuildDesc& d, uint64_t* h) {
     h[13] = lower_words;
     h[14] = tree_words;
     h[15] = bits;
-    const uint64_t ninv = (N + (1u << kInvShift) - 1) >> kInvShift;
+
     d.beta = beta;
     d.Ws = Ws;
     d.Wz = Wz;
     d.lower_off = kHeaderWords;
     d.us_off = d.lower_off + lower_words;
     d.uz_off = d.us_off + us_words;
-    d.invs_off = d.uz_off + uz_words;
-    d.invz_off = d.invs_off + ninv;
-    d.tree_off = d.invz_off + ninv;
+    d.inv_hi_off = d.uz_off + uz_words;
+    d.inv_lo_off = d.inv_hi_off + inv_hi_words(N);
+    d.tree_off = d.inv_lo_off + inv_lo_words(N);
     return d.tree_off + tree_words;
 }
 

@@ -44,9 +44,9 @@ struct Layout {
     int64_t delta_z;
     uint64_t beta;
     uint64_t us_words, uz_words, lower_words, tree_words, tree_bits;
-    uint64_t ninv;
+    uint64_t hi_words, lo_words;  // inventory
     // word offsets from the start of the blob
-    uint64_t lower_off, us_off, uz_off, invs_off, invz_off, tree_off, total_words;
+    uint64_t lower_off, us_off, uz_off, inv_hi_off, inv_lo_off, tree_off, total_words;
 };
 Layout layout_of(const uint64_t* header);
 

@@ -19,13 +19,24 @@ namespace rs {
 //   words 8-10  delta_s, delta_z (two's complement), beta (16.16 fixed point)
 //   words 11-15 upper-s words, upper-z words, lower words, tree words, tree bits
 // followed by: interleaved lower bits, upper bits of s, upper bits of z, the
-// inventory of s (position of every 256th one), the inventory of z, and the
+// two-level inventory (Sec. 7.4: for every 2^14-th one of each list its
+// position as a 64-bit word, s and z interleaved; then for every 2^8-th one
+// its distance from that anchor as a 16-bit entry, s and z interleaved, four
+// entries per word, 0xffff when the distance does not fit), and the
 // concatenated Golomb-Rice streams of all buckets (plus one zero guard word).
 // ---------------------------------------------------------------------------
 constexpr uint64_t kMagic = 0x4648504D4C505352ull;
-constexpr uint64_t kVersion = 1;
+constexpr uint64_t kVersion = 2;
 constexpr int kHeaderWords = 16;
-constexpr uint32_t kInvShift = 8;  // one inventory entry per 256 ones
+constexpr uint32_t kInvHi = 14;       // a 64-bit anchor for every 2^14-th one
+constexpr uint32_t kInvLo = 8;        // a 16-bit offset for every 2^8-th one
+constexpr uint32_t kInvOverflow = 0xffff;
+
+// Words of the inventory of N entries per list: anchors, then packed offsets.
+__host__ __device__ inline uint64_t inv_hi_words(uint64_t N) { return 2 * ((N + (1ull << kInvHi) - 1) >> kInvHi); }
+__host__ __device__ inline uint64_t inv_lo_words(uint64_t N) {
+    return (2 * ((N + (1ull << kInvLo) - 1) >> kInvLo) + 3) / 4;
+}
 constexpr uint64_t kDefaultSeedCap = 1ull << 56;
 constexpr int kStackDepth = 64;
 constexpr uint32_t kMaxLeaf = 24;
