@@ -78,6 +78,11 @@ def lib() -> ctypes.CDLL:
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build() first")
+        # torch brings its own HIP runtime; loading it first makes the library
+        # bind to that same runtime, so streams and memory from torch are valid
+        # in the library (two runtimes in one process do not share them)
+        import torch  # noqa: F401
+
         L = ctypes.CDLL(LIB_PATH)
         P, U32, U64 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64
         L.rs_build.argtypes = [ctypes.POINTER(rs_keys), U32, U32, P, ctypes.POINTER(P)]

@@ -1,6 +1,8 @@
 """GPU parity: the HIP path reproduces the oracle's blob byte for byte and its
 ranks element by element, on the same seeded inputs.  Integer work, so the
 bar is bit-exactness."""
+import os
+
 import numpy as np
 import pytest
 
@@ -331,3 +333,25 @@ def test_plan_runs_equal_oracle_and_fall_back_past_caps(rs, orc):
     assert status[0] == 0 and blobs[0].to_bytes() == orc.build(skew, leaf, bucket)
     assert plan.info()["fallbacks"] == 1
     plan.close()
+
+
+def test_library_loaded_before_torch_still_builds(rs, orc):
+    """Loading the library before torch must not leave two HIP runtimes in the
+    process (torch ships its own): a fresh process that loads the library
+    first builds a structure equal to the oracle's."""
+    import subprocess
+    import sys
+
+    print("case load order", flush=True)
+    code = (
+        "import sys; sys.path.insert(0, %r)\n"
+        "from paper_1910_06416_amd import recsplit, inputs\n"
+        "recsplit.lib()\n"
+        "import oracle\n"
+        "keys = inputs.u64_keys(3000, 5)\n"
+        "b = recsplit.build(recsplit.device_keys(keys), 8, 100, timing=True)\n"
+        "assert b.to_bytes() == oracle.build(keys, 8, 100)\n"
+        "print('ok')\n"
+    ) % (os.path.dirname(os.path.dirname(os.path.abspath(__file__))),)
+    res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert res.returncode == 0 and "ok" in res.stdout, res.stderr[-2000:]
