@@ -355,3 +355,15 @@ def test_library_loaded_before_torch_still_builds(rs, orc):
     ) % (os.path.dirname(os.path.dirname(os.path.abspath(__file__))),)
     res = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
     assert res.returncode == 0 and "ok" in res.stdout, res.stderr[-2000:]
+
+
+def test_largest_buckets_that_fit_and_the_error_beyond(rs, orc):
+    """Buckets of ~12,000 keys (the keys and node queue of one bucket in LDS)
+    build and equal the oracle; a bucket too large for the local data share
+    is refused with an error, not run."""
+    print("case large buckets", flush=True)
+    keys = inputs.u64_keys(24_000, 12)
+    _check_build(rs, orc, keys, 8, 12_000)
+    big = rs.device_keys(inputs.u64_keys(60_000, 13))
+    with pytest.raises(rs.RecSplitError, match="local data share"):
+        rs.build(big, 8, 60_000)
