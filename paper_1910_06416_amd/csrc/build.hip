@@ -573,10 +573,27 @@ __device__ uint64_t leaf_search(const uint64_t* keys, uint32_t depth, uint64_t c
     const uint64_t step = 64ull * kGamma;
     uint64_t S = (D + lane) * kGamma;
     if (C1 == M || !staged) {
-        for (uint64_t base = 0; base < cap; base += 64, S += step) {
-            uint32_t mask = leaf_bits<M, 0, M>(k, S, 0);
-            uint64_t bal = __ballot(mask == full && base + lane < cap);
+        // Key i of candidate base + lane is hashed at kl[i] + base * gamma: the
+        // per-lane part is added once, the per-step part is a scalar register
+        // pair (one vector add per evaluation and none per step; the empty asm
+        // keeps the compiler from turning the sum back into one vector
+        // induction variable per key).  Only the step that reaches the cap
+        // checks lanes against it.
+        uint64_t kl[M];
+#pragma unroll
+        for (int i = 0; i < M; i++) kl[i] = k[i] + S;
+        const uint64_t last = cap ? (cap - 1) & ~63ull : 0;
+        uint64_t O = 0;
+        for (uint64_t base = 0; cap; base += 64, O += step) {
+            uint64_t Os = O;
+            asm volatile("" : "+s"(Os));
+            uint32_t mask = leaf_bits<M, 0, M>(kl, Os, 0);
+            bool ok = mask == full;
+            const bool at_end = base == last;
+            if (at_end) ok &= lane < (uint32_t)(cap - base);
+            uint64_t bal = __ballot(ok);
             if (bal) return base + (uint64_t)__builtin_ctzll(bal);
+            if (at_end) break;
         }
     } else if constexpr (C1 < M) {
         uint32_t a_head = 0, a_tail = 0, b_head = 0, b_tail = 0;
@@ -717,20 +734,27 @@ __device__ uint64_t split_search(const uint64_t* keys, uint32_t depth, const Spl
 #pragma unroll
     for (int t = 0; t < NT; t++) thr[t] = T[t];
     const uint32_t lane = lane_id();
-    const uint32_t G = 1u << c.g, gl = lane & (G - 1), gi = lane >> c.g, per_step = 64u >> c.g;
-    const uint32_t m = c.m;
+    const uint32_t g = __builtin_amdgcn_readfirstlane(c.g);
+    const uint32_t G = 1u << g, gl = lane & (G - 1), gi = lane >> g, per_step = 64u >> g;
+    const uint32_t m = __builtin_amdgcn_readfirstlane(c.m);
     const uint64_t step = (uint64_t)per_step * kGamma;
+    // Keys are dealt to the G lanes of a candidate in blocks of 4 consecutive
+    // keys (lane gl takes keys 4 gl .. 4 gl + 3 of every block of 4 G, so one
+    // address serves all four loads); every lane runs the same number of
+    // blocks, and the last m mod 4 G keys are dealt one at a time.
+    const uint32_t quads = m / (4 * G);
+    const uint32_t tail = quads * 4 * G;
     uint64_t S = (((uint64_t)depth << 56) + gi) * kGamma;
     for (uint64_t base = 0; base < cap; base += per_step, S += step) {
         uint32_t cnt[NT];
         uint64_t packed = 0;
 #pragma unroll
         for (int t = 0; t < NT; t++) cnt[t] = 0;
-        uint32_t i = gl;
-        for (; i + 3 * G < m; i += 4 * G) {
+        const uint64_t* kp = keys + 4 * gl;
+        for (uint32_t q4 = 0; q4 < quads; q4++, kp += 4 * G) {
             uint32_t h[4];
 #pragma unroll
-            for (int u = 0; u < 4; u++) h[u] = mix64_hi32(keys[i + u * G] + S);
+            for (int u = 0; u < 4; u++) h[u] = mix64_hi32(kp[u] + S);
 #pragma unroll
             for (int u = 0; u < 4; u++) {
                 if constexpr (PACKED) {
@@ -742,7 +766,7 @@ __device__ uint64_t split_search(const uint64_t* keys, uint32_t depth, const Spl
                 }
             }
         }
-        for (; i < m; i += G) {
+        for (uint32_t i = tail + gl; i < m; i += G) {
             uint32_t h = mix64_hi32(keys[i] + S);
             if constexpr (PACKED) {
                 uint32_t j = __umulhi(__umulhi(h, m), c.recip);
@@ -992,7 +1016,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_search(SearchArgs a) {
                     c.unit = sh.unit;
                     c.fanout = sh.fanout;
                     c.last = sh.last;
-                    c.g = min(Gt[m], group_cap);
+                    c.g = __builtin_amdgcn_readfirstlane(min(Gt[m], group_cap));
                     c.w = 32 - __clz(m);
                     const bool packed = nt >= 4 && sh.fanout * c.w <= 64;
                     c.recip = packed ? (uint32_t)(((1ull << 32) + sh.unit - 1) / sh.unit) : 0;
