@@ -717,7 +717,17 @@ __device__ __forceinline__ uint64_t leaf_dispatch(const uint64_t* keys, uint32_t
 //   packed:     j = floor(phi/u) by a reciprocal multiply, and 1 << (j*w) is
 //               added to one 64-bit word of w-bit fields (fanout >= 5 when
 //               fanout * w <= 64).
+//   one-hot:    fanout 4 and m < 256: as packed, with four 8-bit fields in one
+//               32-bit word (4 vector instructions per key after the hash
+//               against 6 for three thresholds).
 constexpr uint32_t kMaxThresholds = 8;  // fanout <= max(s, t) = 9 for l <= 24
+enum CountMode { kCountThresholds = 0, kCountPacked = 1, kCountOneHot = 2 };
+
+__device__ __forceinline__ uint32_t split_count_mode(uint32_t m, uint32_t fanout) {
+    if (fanout == 4 && m < 256) return kCountOneHot;
+    const uint32_t w = 32 - __clz(m);
+    return fanout >= 5 && fanout * w <= 64 ? kCountPacked : kCountThresholds;
+}
 
 struct SplitCtl {
     uint32_t m, unit, fanout, last;
@@ -727,10 +737,11 @@ struct SplitCtl {
     uint64_t want;   // packed target
 };
 
-template <int NT, bool PACKED>
+template <int NT, int MODE>
 __device__ uint64_t split_search(const uint64_t* keys, uint32_t depth, const SplitCtl& c, const uint32_t* T,
                                  uint64_t cap, uint32_t* flags) {
-    uint32_t thr[NT];
+    constexpr int NA = NT > 0 ? NT : 1;  // NT = 0 in the packed modes
+    uint32_t thr[NA];
 #pragma unroll
     for (int t = 0; t < NT; t++) thr[t] = T[t];
     const uint32_t lane = lane_id();
@@ -746,8 +757,9 @@ __device__ uint64_t split_search(const uint64_t* keys, uint32_t depth, const Spl
     const uint32_t tail = quads * 4 * G;
     uint64_t S = (((uint64_t)depth << 56) + gi) * kGamma;
     for (uint64_t base = 0; base < cap; base += per_step, S += step) {
-        uint32_t cnt[NT];
+        uint32_t cnt[NA];
         uint64_t packed = 0;
+        uint32_t onehot = 0;
 #pragma unroll
         for (int t = 0; t < NT; t++) cnt[t] = 0;
         const uint64_t* kp = keys + 4 * gl;
@@ -757,9 +769,12 @@ __device__ uint64_t split_search(const uint64_t* keys, uint32_t depth, const Spl
             for (int u = 0; u < 4; u++) h[u] = mix64_hi32(kp[u] + S);
 #pragma unroll
             for (int u = 0; u < 4; u++) {
-                if constexpr (PACKED) {
+                if constexpr (MODE == kCountPacked) {
                     uint32_t j = __umulhi(__umulhi(h[u], m), c.recip);
                     packed += 1ull << (j * c.w);
+                } else if constexpr (MODE == kCountOneHot) {
+                    uint32_t j = __umulhi(__umulhi(h[u], m), c.recip);
+                    onehot += 1u << (j * c.w);
                 } else {
 #pragma unroll
                     for (int t = 0; t < NT; t++) cnt[t] += (uint32_t)(h[u] < thr[t]);
@@ -768,25 +783,32 @@ __device__ uint64_t split_search(const uint64_t* keys, uint32_t depth, const Spl
         }
         for (uint32_t i = tail + gl; i < m; i += G) {
             uint32_t h = mix64_hi32(keys[i] + S);
-            if constexpr (PACKED) {
+            if constexpr (MODE == kCountPacked) {
                 uint32_t j = __umulhi(__umulhi(h, m), c.recip);
                 packed += 1ull << (j * c.w);
+            } else if constexpr (MODE == kCountOneHot) {
+                uint32_t j = __umulhi(__umulhi(h, m), c.recip);
+                onehot += 1u << (j * c.w);
             } else {
 #pragma unroll
                 for (int t = 0; t < NT; t++) cnt[t] += (uint32_t)(h < thr[t]);
             }
         }
         for (uint32_t o = 1; o < G; o <<= 1) {
-            if constexpr (PACKED) {
+            if constexpr (MODE == kCountPacked) {
                 packed += (uint64_t)__shfl_xor((unsigned long long)packed, (int)o, 64);
+            } else if constexpr (MODE == kCountOneHot) {
+                onehot += (uint32_t)__shfl_xor((int)onehot, (int)o, 64);
             } else {
 #pragma unroll
                 for (int t = 0; t < NT; t++) cnt[t] += (uint32_t)__shfl_xor((int)cnt[t], (int)o, 64);
             }
         }
         bool ok = gl == 0 && base + gi < cap;
-        if constexpr (PACKED) {
+        if constexpr (MODE == kCountPacked) {
             ok &= packed == c.want;
+        } else if constexpr (MODE == kCountOneHot) {
+            ok &= onehot == (uint32_t)c.want;
         } else {
 #pragma unroll
             for (int t = 0; t < NT; t++) ok &= cnt[t] == (uint32_t)(t + 1) * c.unit;
@@ -800,25 +822,13 @@ __device__ uint64_t split_search(const uint64_t* keys, uint32_t depth, const Spl
 
 template <int MAXNT>
 __device__ uint64_t split_dispatch(const uint64_t* keys, uint32_t depth, const SplitCtl& c, const uint32_t* T,
-                                   bool packed, uint64_t cap, uint32_t* flags) {
-    const uint32_t nt = c.fanout - 1;
-    if constexpr (MAXNT >= 4) {
-        if (packed) {
-            switch (nt) {
-                case 4: return split_search<4, true>(keys, depth, c, T, cap, flags);
-                case 5: if constexpr (MAXNT >= 5) return split_search<5, true>(keys, depth, c, T, cap, flags); break;
-                case 6: if constexpr (MAXNT >= 6) return split_search<6, true>(keys, depth, c, T, cap, flags); break;
-                case 7: if constexpr (MAXNT >= 7) return split_search<7, true>(keys, depth, c, T, cap, flags); break;
-                case 8: if constexpr (MAXNT >= 8) return split_search<8, true>(keys, depth, c, T, cap, flags); break;
-                default: break;
-            }
-            return kNoSeed;
-        }
-    }
-    switch (nt) {
+                                   uint32_t mode, uint64_t cap, uint32_t* flags) {
+    if (mode == kCountPacked) return split_search<0, kCountPacked>(keys, depth, c, T, cap, flags);
+    if (mode == kCountOneHot) return split_search<0, kCountOneHot>(keys, depth, c, T, cap, flags);
+    switch (c.fanout - 1) {
 #define RS_SPLIT_CASE(NT)                                                                 \
     case NT:                                                                              \
-        if constexpr (NT <= MAXNT) return split_search<NT, false>(keys, depth, c, T, cap, flags); \
+        if constexpr (NT <= MAXNT) return split_search<NT, kCountThresholds>(keys, depth, c, T, cap, flags); \
         return kNoSeed;
         RS_SPLIT_CASE(1) RS_SPLIT_CASE(2) RS_SPLIT_CASE(3) RS_SPLIT_CASE(4) RS_SPLIT_CASE(5) RS_SPLIT_CASE(6)
         RS_SPLIT_CASE(7) RS_SPLIT_CASE(8)
@@ -1017,14 +1027,14 @@ __global__ __launch_bounds__(64 * WAVES) void k_search(SearchArgs a) {
                     c.fanout = sh.fanout;
                     c.last = sh.last;
                     c.g = __builtin_amdgcn_readfirstlane(min(Gt[m], group_cap));
-                    c.w = 32 - __clz(m);
-                    const bool packed = nt >= 4 && sh.fanout * c.w <= 64;
-                    c.recip = packed ? (uint32_t)(((1ull << 32) + sh.unit - 1) / sh.unit) : 0;
+                    const uint32_t mode = split_count_mode(m, sh.fanout);
+                    c.w = mode == kCountOneHot ? 8 : 32 - __clz(m);
+                    c.recip = mode != kCountThresholds ? (uint32_t)(((1ull << 32) + sh.unit - 1) / sh.unit) : 0;
                     c.want = 0;
-                    if (packed)
+                    if (mode != kCountThresholds)
                         for (uint32_t q = 0; q < sh.fanout; q++)
                             c.want += (uint64_t)(q + 1 == sh.fanout ? sh.last : sh.unit) << (q * c.w);
-                    v = split_dispatch<max_thresholds(MAXL)>(lds_keys + off, d, c, thr, packed, a.seed_cap, bflags);
+                    v = split_dispatch<max_thresholds(MAXL)>(lds_keys + off, d, c, thr, mode, a.seed_cap, bflags);
                     fail = v == kNoSeed;  // counts do not match the parts: no partition
                     if (!fail) partition(lds_keys + off, m, d, v, thr, nt, sh.unit, a.tmp + start + off);
                 }

@@ -59,9 +59,10 @@ uint32_t lanes_per_candidate(const Strategy& st, uint32_t m, double trials) {
     const uint32_t nt = sh.fanout - 1;
     uint32_t w = 0;
     while ((1u << w) <= m) w++;
-    const bool packed = nt >= 4 && sh.fanout * w <= 64;
-    const double per_key = 18.0 + (packed ? 6.0 : 2.0 * nt);
-    const double per_reduce = packed ? 4.0 : 2.0 * nt;
+    const bool onehot = sh.fanout == 4 && m < 256;
+    const bool packed = !onehot && nt >= 4 && sh.fanout * w <= 64;
+    const double per_key = 18.0 + (packed ? 6.0 : onehot ? 4.0 : 2.0 * nt);
+    const double per_reduce = packed ? 4.0 : onehot ? 2.0 : 2.0 * nt;
     double best = 0;
     uint32_t best_g = 0;
     for (uint32_t g = 0; g <= 6; g++) {
