@@ -93,8 +93,10 @@ typedef struct {
  *               (1 = one lane per candidate .. 7 = up to 64; built-in 7).  The
  *               lanes per candidate of each node size come from its expected
  *               number of trials, capped here.
- *   waves     : wavefronts per bucket workgroup: 1, 2, 4 or 8 (built-in 1 for
- *               l <= 8, else 4).
+ *   waves     : wavefronts per bucket workgroup: 1, 2, 4 or 8.  Built-in, by
+ *               the buckets B of the whole call: for l <= 8, 4 if B <= 4096,
+ *               2 if B <= 40000, else 1; for 9 <= l <= 12, 8 if B <= 256,
+ *               else 4; for l > 12, 4.
  *   search_ms : rs_autotune: time of the calibration search with this schedule.
  *   default_ms: rs_autotune: time of the same search with the built-in schedule.
  *   tune_ms   : rs_autotune: wall time the tuning took. */

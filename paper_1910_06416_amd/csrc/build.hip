@@ -492,6 +492,7 @@ struct SearchArgs {
     uint64_t* tmp;
     const uint64_t* bstart;
     uint64_t* seeds;
+    uint32_t* msz;  // size of every coded node, at the same preorder position as its index
     uint64_t* blen;
     const BuildDesc* descs;
     BuildDesc* wdescs;
@@ -1043,7 +1044,10 @@ __global__ __launch_bounds__(64 * WAVES) void k_search(SearchArgs a) {
                 if (lane == 0) __hip_atomic_store(&qs.abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                 break;
             }
-            if (lane == 0) a.seeds[start + idx] = v;
+            if (lane == 0) {
+                a.seeds[start + idx] = v;
+                a.msz[start + idx] = m;
+            }
             const uint32_t r = R[m];
             bits += r + (v >> r) + 1;
             if (m > leaf && lane == 0) {
@@ -1204,6 +1208,7 @@ struct FillArgs {
     const uint64_t* bstart;
     const uint64_t* ostart;
     const uint64_t* seeds;
+    const uint32_t* msz;
     const BuildDesc* descs;
     const uint64_t* bucket_base;
     const uint64_t* entry_base;  // bucket_base[j] + j: nb_j + 1 Elias-Fano entries per build
@@ -1255,9 +1260,13 @@ __global__ void k_ef_fill(FillArgs a) {
 
 // Golomb-Rice streams (Sec. 6.2): per bucket, the fixed parts of all coded
 // nodes in preorder, then their unary parts (q zeros and a one) in preorder.
-__global__ void k_tree_bits(FillArgs a) {
-    const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= a.nbuckets) return;
+// One wavefront per bucket, one lane per coded node: the search left every
+// node's index and size at its preorder position, so each node's two bit
+// offsets are prefix sums over the nodes before it.
+__global__ __launch_bounds__(kBlock) void k_tree_bits(FillArgs a) {
+    const uint64_t g = (uint64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
+    const uint32_t lane = threadIdx.x & 63;
+    if (g >= a.nbuckets) return;  // the whole wavefront
     const uint32_t j = find_build(a.bucket_base, a.count, g);
     const BuildDesc& B = a.descs[j];
     if (!B.blob) return;
@@ -1266,29 +1275,24 @@ __global__ void k_tree_bits(FillArgs a) {
     if (m0 <= 1) return;
     const uint32_t* R = a.tables + (size_t)B.tab * 4 * a.stride;
     const uint32_t* F = R + a.stride;
+    const uint32_t nodes = R[2 * a.stride + m0];
     unsigned long long* tree = B.blob + B.tree_off;
     const uint64_t o0 = a.ostart[B.bucket_base];
     uint64_t fp = a.ostart[g] - o0, up = fp + F[m0];
-    uint32_t stk[kStackDepth];
-    int sp = 0;
-    stk[sp++] = m0;
-    uint64_t node = 0;
-    while (sp > 0) {
-        uint32_t m = stk[--sp];
-        if (m <= 1) continue;
-        uint64_t v = a.seeds[start + node++];
-        uint32_t r = R[m];
-        or_bits(tree, fp, r ? (v & (~0ull >> (64 - r))) : 0, r);
-        fp += r;
-        up += v >> r;
-        or_bits(tree, up, 1, 1);
-        up++;
-        if (m > B.leaf) {
-            SplitShape sh = split_shape(m, B.leaf, B.lower, B.upper);
-            if (sp + (int)sh.fanout > kStackDepth) return;  // deeper than any tree of <= 2^32 keys
-            stk[sp++] = sh.last;
-            for (uint32_t q = 1; q < sh.fanout; q++) stk[sp++] = sh.unit;
+    for (uint32_t c = 0; c < nodes; c += 64) {
+        const uint32_t k = c + lane;
+        const bool act = k < nodes;
+        const uint64_t v = act ? a.seeds[start + k] : 0;
+        const uint32_t r = act ? R[a.msz[start + k]] : 0;
+        const uint64_t q = v >> r;                  // zeros of the unary part
+        const uint64_t len = act ? q + 1 : 0;       // unary part with its one
+        const uint64_t rs = wave_inclusive_sum(r), us = wave_inclusive_sum(len);
+        if (act) {
+            or_bits(tree, fp + rs - r, r ? (v & (~0ull >> (64 - r))) : 0, r);
+            or_bits(tree, up + us - len + q, 1, 1);
         }
+        fp += lane_value(rs, 63);
+        up += lane_value(us, 63);
     }
 }
 
@@ -1601,6 +1605,7 @@ bool debug_trace() {
 struct TuneCtx {
     bool probe_only = false;  // time the built-in schedule and report residency only
     double budget_ms = 0;     // search time allowed for the variants
+    uint64_t buckets = 0;     // buckets of the calibration build (for the built-in schedule)
     // results
     rs_schedule best{};
     double default_ms = 0;
@@ -1643,7 +1648,7 @@ int tune_search(TuneCtx& t, uint32_t leaf, BuildDesc* hdesc, BuildDesc* d_desc, 
         return RS_OK;
     };
     int rc = RS_OK;
-    rs_schedule cur = builtin_schedule(leaf);
+    rs_schedule cur = builtin_schedule(leaf, t.buckets);
     double warm = 0, warm_total = 0, best_ms = 0;
     // warm-up: the first launches run slower (clocks still ramping), so search
     // for at least 100 ms (at most 20 launches) before timing anything
@@ -1793,8 +1798,11 @@ int batch_prepare(Batch& b, const rs_keys* sets, uint32_t count, const uint32_t*
         d.aligned = ((uintptr_t)k.data & 7) == 0;
         d.delta_s = ~0ull;
         d.delta_z = 0x7fffffffffffffffll;
-        // search schedule: built-in, else the table's (RS_OPT_TUNED), then the overrides
-        rs_schedule sc = builtin_schedule(leaf);
+        // search schedule: built-in, else the table's (RS_OPT_TUNED), then the
+        // overrides; the built-in wavefront count depends on the buckets of the
+        // whole call and is set once they are all known (waves = 0 until then)
+        rs_schedule sc = builtin_schedule(leaf, 0);
+        sc.waves = 0;
         if (opts && (opts->flags & RS_OPT_TUNED)) {
             rs_schedule tuned;
             if (schedule_lookup(leaf, bucket, &tuned)) sc = tuned;
@@ -1805,7 +1813,6 @@ int batch_prepare(Batch& b, const rs_keys* sets, uint32_t count, const uint32_t*
         d.stage_from = sc.stage_from;
         d.group_cap = sc.group_max - 1;
         d.waves = sc.waves;
-        b.launch_waves = std::max(b.launch_waves, sc.waves);
         b.total += d.n;
         b.nbuckets += d.nb;
         b.max_leaf = std::max(b.max_leaf, leaf);
@@ -1814,6 +1821,10 @@ int batch_prepare(Batch& b, const rs_keys* sets, uint32_t count, const uint32_t*
     }
     b.K = (uint32_t)b.hd.size();
     if (b.K && b.nbuckets >= (1ull << 32)) return fail(RS_EINVAL, "too many buckets in one call");
+    for (BuildDesc& d : b.hd) {
+        if (!d.waves) d.waves = builtin_schedule(d.leaf, b.nbuckets).waves;
+        b.launch_waves = std::max(b.launch_waves, d.waves);
+    }
     return RS_OK;
 }
 
@@ -1967,7 +1978,9 @@ size_t table_words(const Batch& b, uint32_t maxm) {
 }
 
 SearchArgs search_args(const Batch& b) {
-    return SearchArgs{b.d_sorted, b.d_tmp, b.d_bst, b.d_seeds, b.d_blen, b.d_desc, b.d_desc, b.d_bb, b.K,
+    // the bucket numbers of the keys are no longer needed once the keys are
+    // in bucket order: their array takes the node sizes
+    return SearchArgs{b.d_sorted, b.d_tmp, b.d_bst, b.d_seeds, b.d_bid, b.d_blen, b.d_desc, b.d_desc, b.d_bb, b.K,
                       b.nbuckets, b.d_tab, b.stride, b.seed_cap, b.table_maxm};
 }
 
@@ -1994,9 +2007,9 @@ int enqueue_fill(Batch& b, uint64_t* arena, uint64_t capacity, hipStream_t s) {
                                                       &b.d_st->flags);
     if (arena && capacity) k_fill_u64<<<grid_for(capacity, kBlock * 8), kBlock, 0, s>>>(arena, capacity, 0);
     k_write_headers<<<grid_for((uint64_t)K * kHeaderWords, kBlock), kBlock, 0, s>>>(b.d_desc, b.d_hdr, K);
-    FillArgs fa{b.d_bst, b.d_ost, b.d_seeds, b.d_desc, b.d_bb, b.d_eb, K, b.nbuckets, b.d_tab, b.stride};
+    FillArgs fa{b.d_bst, b.d_ost, b.d_seeds, b.d_bid, b.d_desc, b.d_bb, b.d_eb, K, b.nbuckets, b.d_tab, b.stride};
     k_ef_fill<<<grid_for(b.nbuckets + K, kBlock), kBlock, 0, s>>>(fa);
-    k_tree_bits<<<grid_for(b.nbuckets, 64), 64, 0, s>>>(fa);
+    k_tree_bits<<<grid_for(b.nbuckets, kBlock / 64), kBlock, 0, s>>>(fa);
     RS_ENQ(hipGetLastError());
     return RS_OK;
 }
@@ -2129,6 +2142,7 @@ int build_batch_impl(const rs_keys* sets, uint32_t count, const uint32_t* leafs,
     if (int rc = dev_alloc((void**)&b.d_tab, table_words(b, maxm) * 4, s)) return cleanup(rc);
     if (int rc = upload_batch_tables(b, maxm, s)) return cleanup(rc);
     if (tune) {  // calibration only: no blob, the tables are not handed to an arena
+        tune->buckets = b.nbuckets;
         const int trc = tune_search(*tune, b.max_leaf, b.h_desc, b.d_desc, search_args(b), b.lds, s);
         dev_free(b.d_tab, s);
         b.d_tab = nullptr;

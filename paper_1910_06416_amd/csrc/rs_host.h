@@ -53,9 +53,10 @@ Layout layout_of(const uint64_t* header);
 // Upload the per-size tables of (leaf, maxm) into dst (3 * (maxm + 1) u32).
 int upload_tables(uint32_t leaf, uint32_t maxm, uint32_t* dst, hipStream_t s);
 
-// Search schedules: the built-in one of a leaf size, range checks, and the
-// process-wide table filled by the autotuner.
-rs_schedule builtin_schedule(uint32_t leaf);
+// Search schedules: the built-in one of a leaf size for a launch over
+// `buckets` buckets in all, range checks, and the process-wide table filled by
+// the autotuner.
+rs_schedule builtin_schedule(uint32_t leaf, uint64_t buckets);
 bool schedule_valid(const rs_schedule& s);
 bool schedule_lookup(uint32_t leaf, uint32_t bucket, rs_schedule* out);
 void schedule_store(uint32_t leaf, uint32_t bucket, const rs_schedule& s);

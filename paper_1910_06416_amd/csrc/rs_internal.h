@@ -38,7 +38,6 @@ __host__ __device__ inline uint64_t inv_lo_words(uint64_t N) {
     return (2 * ((N + (1ull << kInvLo) - 1) >> kInvLo) + 3) / 4;
 }
 constexpr uint64_t kDefaultSeedCap = 1ull << 56;
-constexpr int kStackDepth = 64;
 constexpr uint32_t kMaxLeaf = 24;
 
 // Signature and hash-family constants.

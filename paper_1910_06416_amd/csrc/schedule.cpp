@@ -14,11 +14,19 @@ std::mutex g_mu;
 std::map<std::pair<uint32_t, uint32_t>, rs_schedule> g_table;
 }  // namespace
 
-rs_schedule builtin_schedule(uint32_t leaf) {
+rs_schedule builtin_schedule(uint32_t leaf, uint64_t buckets) {
     rs_schedule s{};
     s.stage_from = 9;
     s.group_max = 7;
-    s.waves = leaf <= 8 ? 1 : 4;
+    // A launch with few buckets ends when its slowest bucket does, so more
+    // wavefronts share each bucket's tree; with many buckets one wavefront per
+    // bucket of small leaves keeps the most candidates in flight.  Measured on
+    // MI355X at l = 8, b = 100: 4 wavefronts best up to ~1,000 buckets, 2 at
+    // 10,000-30,000, 1 at 100,000; at l = 12, b = 1000, 8 at 100 buckets.
+    if (leaf <= 8)
+        s.waves = buckets <= 4096 ? 4 : buckets <= 40000 ? 2 : 1;
+    else
+        s.waves = leaf <= 12 && buckets <= 256 ? 8 : 4;
     return s;
 }
 
