@@ -36,7 +36,7 @@ VALU_SLOTS_PER_EVAL = 18.0
 # HBM bytes of one k_search launch on the 10M-string workload, from rocprofv3
 # FETCH_SIZE (x2.0) / WRITE_SIZE (x1.0), the factors a 1 GiB device copy gives;
 # to be set to None whenever the search kernel changes until re-measured.
-SEARCH_TRAFFIC_BYTES = 285.7e6
+SEARCH_TRAFFIC_BYTES = 135.0e6
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz full-rate 32-bit VALU lane-ops.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0

@@ -855,36 +855,54 @@ __device__ __forceinline__ void wave_mem_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-// Reorder the node's keys so that child j occupies [j*unit, ...): keys go to
-// global scratch at their final place and are copied back (one wavefront).
-__device__ void partition(uint64_t* keys, uint32_t m, uint32_t depth, uint64_t v, const uint32_t* T, uint32_t nt,
-                          uint32_t unit, uint64_t* gtmp) {
+// Reorder the node's keys so that child j occupies [j*unit, ...) (one
+// wavefront): every key goes to its final place in a scratch array and the
+// keys are copied back.  The scratch is the wavefront's LDS area of the
+// bijection queues (free while it works on a split) when the node fits there,
+// else global memory.  The LDS scratch is addressed through an LDS-qualified
+// pointer, so that its stores are LDS stores and not generic ones.
+typedef __attribute__((address_space(3))) uint64_t lds_u64;
+
+__device__ __forceinline__ void partition(uint64_t* keys, uint32_t m, uint32_t depth, uint64_t v, const uint32_t* T,
+                                          uint32_t nt, uint32_t unit, uint64_t* lds_tmp, uint32_t lds_cap,
+                                          uint64_t* gtmp) {
     const uint32_t lane = lane_id();
     const uint64_t S = stream_offset(depth, v);
-    uint32_t cursor[kMaxThresholds + 1];
+    auto scatter = [&](auto* dst) {
+        uint32_t cursor[kMaxThresholds + 1];
 #pragma unroll
-    for (uint32_t q = 0; q <= kMaxThresholds; q++) cursor[q] = q * unit;
-    for (uint32_t c0 = 0; c0 < m; c0 += 64) {
-        uint32_t i = c0 + lane;
-        bool act = i < m;
-        uint64_t x = act ? keys[i] : 0;
-        uint32_t h = mix64_hi32(x + S);
-        uint32_t j = 0;
-        for (uint32_t t = 0; t < nt; t++) j += (uint32_t)(h >= T[t]);
-        uint32_t pos = 0;
+        for (uint32_t q = 0; q <= kMaxThresholds; q++) cursor[q] = q * unit;
+        for (uint32_t c0 = 0; c0 < m; c0 += 64) {
+            uint32_t i = c0 + lane;
+            bool act = i < m;
+            uint64_t x = act ? keys[i] : 0;
+            uint32_t h = mix64_hi32(x + S);
+            uint32_t j = 0;
+            for (uint32_t t = 0; t < nt; t++) j += (uint32_t)(h >= T[t]);
+            uint32_t pos = 0;
 #pragma unroll
-        for (uint32_t q = 0; q <= kMaxThresholds; q++) {
-            if (q <= nt) {
-                uint64_t bal = __ballot(act && j == q);
-                if (act && j == q) pos = cursor[q] + lanes_below(bal);
-                cursor[q] += (uint32_t)__popcll(bal);
+            for (uint32_t q = 0; q <= kMaxThresholds; q++) {
+                if (q <= nt) {
+                    uint64_t bal = __ballot(act && j == q);
+                    if (act && j == q) pos = cursor[q] + lanes_below(bal);
+                    cursor[q] += (uint32_t)__popcll(bal);
+                }
             }
+            if (act) dst[pos] = x;
         }
-        if (act) gtmp[pos] = x;
+    };
+    if (m <= lds_cap) {
+        lds_u64* tmp = (lds_u64*)lds_tmp;
+        scatter(tmp);
+        wave_lds_sync();
+        for (uint32_t i = lane; i < m; i += 64) keys[i] = tmp[i];
+        wave_lds_sync();
+    } else {
+        scatter(gtmp);
+        wave_mem_sync();
+        for (uint32_t i = lane; i < m; i += 64) keys[i] = gtmp[i];
+        wave_mem_sync();
     }
-    wave_mem_sync();
-    for (uint32_t i = lane; i < m; i += 64) keys[i] = gtmp[i];
-    wave_mem_sync();
 }
 
 // One workgroup of WAVES wavefronts per bucket of every build of the call (the
@@ -1037,7 +1055,9 @@ __global__ __launch_bounds__(64 * WAVES) void k_search(SearchArgs a) {
                             c.want += (uint64_t)(q + 1 == sh.fanout ? sh.last : sh.unit) << (q * c.w);
                     v = split_dispatch<max_thresholds(MAXL)>(lds_keys + off, d, c, thr, mode, a.seed_cap, bflags);
                     fail = v == kNoSeed;  // counts do not match the parts: no partition
-                    if (!fail) partition(lds_keys + off, m, d, v, thr, nt, sh.unit, a.tmp + start + off);
+                    if (!fail)
+                        partition(lds_keys + off, m, d, v, thr, nt, sh.unit, reinterpret_cast<uint64_t*>(&queues[wave]),
+                                  (uint32_t)(sizeof(LeafQueues) / sizeof(uint64_t)), a.tmp + start + off);
                 }
             }
             if (fail) {
