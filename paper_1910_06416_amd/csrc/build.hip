@@ -1224,6 +1224,13 @@ __device__ __forceinline__ void or_bits(unsigned long long* a, uint64_t pos, uin
     if (o + nbits > 64) atomicOr(&a[w + 1], (unsigned long long)(val >> (64 - o)));
 }
 
+__device__ __forceinline__ void or_bits_lds(unsigned long long* a, uint64_t pos, uint64_t val, uint32_t nbits) {
+    if (nbits == 0) return;
+    const uint32_t w = (uint32_t)(pos >> 6), o = (uint32_t)(pos & 63);
+    atomicOr(&a[w], (unsigned long long)(val << o));
+    if (o + nbits > 64) atomicOr(&a[w + 1], (unsigned long long)(val >> (64 - o)));
+}
+
 struct FillArgs {
     const uint64_t* bstart;
     const uint64_t* ostart;
@@ -1280,13 +1287,32 @@ __global__ void k_ef_fill(FillArgs a) {
 
 // Golomb-Rice streams (Sec. 6.2): per bucket, the fixed parts of all coded
 // nodes in preorder, then their unary parts (q zeros and a one) in preorder.
-// One wavefront per bucket, one lane per coded node: the search left every
-// node's index and size at its preorder position, so each node's two bit
-// offsets are prefix sums over the nodes before it.
+// A group of kTreeLanes lanes per bucket, one lane per coded node: the search
+// left every node's index and size at its preorder position, so each node's
+// two bit offsets are prefix sums over the nodes before it (segmented
+// shuffles within the group; a group returns or loops as a whole).  The
+// bucket's stream is assembled in an LDS window of kTreeWords words and then
+// ORed into the blob one word at a time (the first and last words may be
+// shared with the neighbouring buckets); a longer stream is ORed into the blob
+// directly.
+constexpr uint32_t kTreeLanes = 16;
+constexpr uint32_t kTreeWords = 64;
+static_assert(64 % kTreeLanes == 0 && kBlock % kTreeLanes == 0, "bucket groups inside one wavefront");
+
+__device__ __forceinline__ uint64_t group_inclusive_sum(uint64_t x, uint32_t gl) {
+#pragma unroll
+    for (uint32_t off = 1; off < kTreeLanes; off <<= 1) {
+        const uint64_t y = __shfl_up(x, off, kTreeLanes);
+        if (gl >= off) x += y;
+    }
+    return x;
+}
+
 __global__ __launch_bounds__(kBlock) void k_tree_bits(FillArgs a) {
-    const uint64_t g = (uint64_t)blockIdx.x * (kBlock / 64) + (threadIdx.x >> 6);
-    const uint32_t lane = threadIdx.x & 63;
-    if (g >= a.nbuckets) return;  // the whole wavefront
+    __shared__ unsigned long long window[kBlock / kTreeLanes][kTreeWords];
+    const uint64_t g = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kTreeLanes;
+    const uint32_t gl = threadIdx.x & (kTreeLanes - 1);
+    if (g >= a.nbuckets) return;
     const uint32_t j = find_build(a.bucket_base, a.count, g);
     const BuildDesc& B = a.descs[j];
     if (!B.blob) return;
@@ -1298,21 +1324,45 @@ __global__ __launch_bounds__(kBlock) void k_tree_bits(FillArgs a) {
     const uint32_t nodes = R[2 * a.stride + m0];
     unsigned long long* tree = B.blob + B.tree_off;
     const uint64_t o0 = a.ostart[B.bucket_base];
-    uint64_t fp = a.ostart[g] - o0, up = fp + F[m0];
-    for (uint32_t c = 0; c < nodes; c += 64) {
-        const uint32_t k = c + lane;
+    const uint64_t first = a.ostart[g] - o0, end = a.ostart[g + 1] - o0;
+    const uint64_t w0 = first >> 6, words = ((end + 63) >> 6) - w0;
+    const bool in_lds = words <= kTreeWords;
+    unsigned long long* win = window[threadIdx.x / kTreeLanes];
+    if (in_lds) {
+        for (uint32_t i = gl; i < kTreeWords; i += kTreeLanes) win[i] = 0;
+        wave_lds_sync();
+    }
+    // bit positions relative to word w0 in the window, absolute in the blob
+    unsigned long long* dst = in_lds ? nullptr : tree;
+    const uint64_t base = in_lds ? w0 << 6 : 0;
+    uint64_t fp = first - base, up = first + F[m0] - base;
+    for (uint32_t c = 0; c < nodes; c += kTreeLanes) {
+        const uint32_t k = c + gl;
         const bool act = k < nodes;
         const uint64_t v = act ? a.seeds[start + k] : 0;
         const uint32_t r = act ? R[a.msz[start + k]] : 0;
-        const uint64_t q = v >> r;                  // zeros of the unary part
-        const uint64_t len = act ? q + 1 : 0;       // unary part with its one
-        const uint64_t rs = wave_inclusive_sum(r), us = wave_inclusive_sum(len);
+        const uint64_t q = v >> r;               // zeros of the unary part
+        const uint64_t len = act ? q + 1 : 0;    // unary part with its one
+        const uint64_t rs = group_inclusive_sum(r, gl), us = group_inclusive_sum(len, gl);
         if (act) {
-            or_bits(tree, fp + rs - r, r ? (v & (~0ull >> (64 - r))) : 0, r);
-            or_bits(tree, up + us - len + q, 1, 1);
+            const uint64_t fixed = r ? (v & (~0ull >> (64 - r))) : 0;
+            if (in_lds) {
+                or_bits_lds(win, fp + rs - r, fixed, r);
+                or_bits_lds(win, up + us - len + q, 1, 1);
+            } else {
+                or_bits(dst, fp + rs - r, fixed, r);
+                or_bits(dst, up + us - len + q, 1, 1);
+            }
         }
-        fp += lane_value(rs, 63);
-        up += lane_value(us, 63);
+        fp += __shfl(rs, kTreeLanes - 1, kTreeLanes);
+        up += __shfl(us, kTreeLanes - 1, kTreeLanes);
+    }
+    if (in_lds) {
+        wave_lds_sync();
+        for (uint32_t i = gl; i < words; i += kTreeLanes) {
+            const unsigned long long x = win[i];
+            if (x) atomicOr(&tree[w0 + i], x);
+        }
     }
 }
 
@@ -2029,7 +2079,7 @@ int enqueue_fill(Batch& b, uint64_t* arena, uint64_t capacity, hipStream_t s) {
     k_write_headers<<<grid_for((uint64_t)K * kHeaderWords, kBlock), kBlock, 0, s>>>(b.d_desc, b.d_hdr, K);
     FillArgs fa{b.d_bst, b.d_ost, b.d_seeds, b.d_bid, b.d_desc, b.d_bb, b.d_eb, K, b.nbuckets, b.d_tab, b.stride};
     k_ef_fill<<<grid_for(b.nbuckets + K, kBlock), kBlock, 0, s>>>(fa);
-    k_tree_bits<<<grid_for(b.nbuckets, kBlock / 64), kBlock, 0, s>>>(fa);
+    k_tree_bits<<<grid_for(b.nbuckets * kTreeLanes, kBlock), kBlock, 0, s>>>(fa);
     RS_ENQ(hipGetLastError());
     return RS_OK;
 }
