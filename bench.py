@@ -226,23 +226,25 @@ def main():
         "valu_slots_per_eval": slots,
     }
 
-    # latency over repeated 100,000-key builds (64-bit keys, l=8, b=100)
+    # latency over repeated 100,000-key builds (64-bit keys, l=8, b=100).  They
+    # take the built-in schedule, whose wavefronts per bucket follow the call's
+    # bucket count; the table's (8, 100) entry was tuned for the 10^7-key build.
     if args.latency_builds:
         small = recsplit.device_keys(inputs.u64_keys(100_000, 1))
         lat = []
         for i in range(args.latency_builds + 3):
             torch.cuda.synchronize()
             tb = time.perf_counter()
-            b = recsplit.build(small, 8, 100, timing=True, tuned=tuned)
+            b = recsplit.build(small, 8, 100)
             dt = time.perf_counter() - tb
             b.free()
             if i >= 3:
                 lat.append(dt)
         result["latency_100k_l8_b100_ms"] = {"p50": percentile(lat, 50) * 1e3, "p99": percentile(lat, 99) * 1e3,
-                                             "builds": len(lat)}
+                                             "builds": len(lat), "schedule": "built-in"}
         log(f"[bench] 100k-key build latency p50 {result['latency_100k_l8_b100_ms']['p50']:.3f} ms")
         # the same builds through a captured plan (one graph launch and one wait per build)
-        plan = recsplit.Plan([small], 8, 100, tuned=tuned)
+        plan = recsplit.Plan([small], 8, 100)
         for b in plan.first:
             b.free()
         plat = []
@@ -356,14 +358,16 @@ def bench_batch(args):
     plan.close()
     log(f"[bench] plan run: {plan_s:.3f} s ({plan_info})")
 
-    # plain path: one rs_build call per build, in order
+    # plain path: one rs_build call per build, in order, each with the built-in
+    # schedule (its wavefronts per bucket follow that build's bucket count, which
+    # suits a lone build better than the schedule tuned for the whole batch)
     log("[bench] plain path: one call per build")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     lat = []
     for i, s_ in enumerate(sets):
         tb = time.perf_counter()
-        b = recsplit.build(s_, leaf, bucket, tuned=tuned)
+        b = recsplit.build(s_, leaf, bucket)
         torch.cuda.synchronize()
         lat.append(time.perf_counter() - tb)
         b.free()
