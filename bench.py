@@ -37,6 +37,10 @@ VALU_SLOTS_PER_EVAL = 18.0
 # FETCH_SIZE (x2.0) / WRITE_SIZE (x1.0), the factors a 1 GiB device copy gives;
 # to be set to None whenever the search kernel changes until re-measured.
 SEARCH_TRAFFIC_BYTES = 135.0e6
+# VALU lane-instructions that k_lookup_bytes executes per string query (rocprofv3
+# SQ_INSTS_VALU x 64 / queries on the 10M-string workload): lookups are bound by
+# the VALU and by dependent loads, not by HBM.
+LOOKUP_VALU_PER_QUERY = 2013.0
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz full-rate 32-bit VALU lane-ops.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
@@ -211,6 +215,10 @@ def main():
         "lookup_keys_per_s": lookup_rate,
         "lookup_hbm": {"achieved": lookup_bytes / (float(np.mean(lookup_ms)) * 1e-3) / 1e9, "peak": HBM_PEAK_GBS,
                        "unit": "GB/s", "bytes_per_query": lookup_bytes / n},
+        # executed (not algorithmic) VALU work of the lookup kernel against the VALU peak
+        "lookup_valu": {"achieved": lookup_rate * LOOKUP_VALU_PER_QUERY / 1e12, "peak": VALU_PEAK_TOPS,
+                        "unit": "T lane-ops/s", "frac": lookup_rate * LOOKUP_VALU_PER_QUERY / 1e12 / VALU_PEAK_TOPS,
+                        "valu_per_query": LOOKUP_VALU_PER_QUERY},
     }
     slots = VALU_SLOTS_PER_EVAL
     result["roofline"] = {
