@@ -149,6 +149,29 @@ __device__ __forceinline__ void select_pair(const uint64_t* a, uint64_t words, u
     second = rest ? (w << 6) + (uint64_t)__builtin_ctzll(rest) : select_from(a, words, (w + 1) << 6, 0);
 }
 
+// Position of the first set bit at or after bit p (the end of a unary code);
+// a position past the end if there is none (only in a corrupted structure).
+__device__ __forceinline__ uint64_t next_one(const uint64_t* a, uint64_t words, uint64_t p) {
+    const uint64_t w = p >> 6;
+    if (w >= words) return words << 6;
+    const uint64_t x = a[w] & (~0ull << (p & 63));
+    if (x) return (w << 6) + (uint64_t)__builtin_ctzll(x);
+    return select_from(a, words, (w + 1) << 6, 0);
+}
+
+// floor(x / d) for 1 <= d and x < 2^21: the single-precision estimate
+// x * rcp(d) is within 0.4 of x / d (relative error below 2^-22), so its
+// truncation is off by at most one, which the remainder corrects.
+__device__ __forceinline__ uint32_t div_small(uint32_t x, uint32_t d) {
+    uint32_t q = (uint32_t)((float)x * __builtin_amdgcn_rcpf((float)d));
+    const int32_t r = (int32_t)(x - q * d);
+    if (r < 0)
+        q--;
+    else if ((uint32_t)r >= d)
+        q++;
+    return q;
+}
+
 __device__ __forceinline__ uint64_t get_bits(const uint64_t* a, uint64_t pos, uint32_t nbits) {
     if (nbits == 0) return 0;
     uint64_t w = pos >> 6;
@@ -198,6 +221,10 @@ __device__ uint64_t rank_of(const LookupArgs& a, uint64_t hi, uint64_t lo) {
 
     uint32_t m = (uint32_t)min(s_i1 - s_i, (uint64_t)a.maxm);
     const uint64_t* tree = blob + a.tree_off;
+    // node sizes below 2^20 (every structure this library builds; every
+    // dividend below is then under 2^21): the split shapes and child indices
+    // take div_small instead of integer division
+    const bool small = a.maxm < (1u << 20);
     uint64_t c = 0;
     uint32_t d = 0;
     uint64_t fp = o_i, up = o_i + a.F[m];
@@ -205,11 +232,25 @@ __device__ uint64_t rank_of(const LookupArgs& a, uint64_t hi, uint64_t lo) {
         uint32_t r = a.R[m];
         uint64_t fixed = get_bits(tree, fp, r);
         fp += r;
-        uint64_t one = select_from(tree, a.tree_words, up, 0);
+        uint64_t one = next_one(tree, a.tree_words, up);
         uint64_t v = ((one - up) << r) | fixed;
         up = one + 1;
-        SplitShape sh = split_shape(m, a.leaf, a.lower, a.upper);
-        uint32_t j = min(phi(lo, d, v, m) / sh.unit, sh.fanout - 1);
+        SplitShape sh;
+        if (small) {
+            if (m > a.upper) {
+                sh.unit = div_small(m / 2 + a.upper - 1, a.upper) * a.upper;
+                sh.fanout = 2;
+                sh.last = m - sh.unit;
+            } else {
+                sh.unit = m > a.lower ? a.lower : a.leaf;
+                sh.fanout = div_small(m + sh.unit - 1, sh.unit);
+                sh.last = m - (sh.fanout - 1) * sh.unit;
+            }
+        } else {
+            sh = split_shape(m, a.leaf, a.lower, a.upper);
+        }
+        const uint32_t ph = phi(lo, d, v, m);
+        uint32_t j = min(small ? div_small(ph, sh.unit) : ph / sh.unit, sh.fanout - 1);
         if (j) {
             fp += (uint64_t)j * a.F[sh.unit];
             uint64_t skip = (uint64_t)j * a.N[sh.unit];
@@ -222,7 +263,7 @@ __device__ uint64_t rank_of(const LookupArgs& a, uint64_t hi, uint64_t lo) {
     if (m >= 2) {
         uint32_t r = a.R[m];
         uint64_t fixed = get_bits(tree, fp, r);
-        uint64_t one = select_from(tree, a.tree_words, up, 0);
+        uint64_t one = next_one(tree, a.tree_words, up);
         uint64_t v = ((one - up) << r) | fixed;
         c += phi(lo, d, v, m);
     }
