@@ -455,7 +455,7 @@ __global__ __launch_bounds__(kBlock) void k_bin_offsets(const unsigned long long
 }
 
 // out[i] = sum_{j<i} in[j] for i in [0, n]; each thread owns kScanItems
-// consecutive items of the block's tile.
+// consecutive items of the block's tile (tile_off = null: a single tile).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_scan_apply(const T* __restrict__ in, uint64_t n,
                                                       const uint64_t* __restrict__ tile_off,
@@ -470,7 +470,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(const T* __restrict__ in,
         s += vals[k];
     }
     uint64_t tot;
-    uint64_t run = block_exclusive_sum(s, &tot) + tile_off[blockIdx.x];
+    uint64_t run = block_exclusive_sum(s, &tot) + (tile_off ? tile_off[blockIdx.x] : 0);
 #pragma unroll
     for (int k = 0; k < kScanItems; k++) {
         uint64_t i = base + k;
@@ -1474,9 +1474,13 @@ uint32_t grid_for(uint64_t n, uint32_t block) { return (uint32_t)std::max<uint64
 template <typename T>
 int scan(const T* in, uint64_t n, uint64_t* out, uint64_t* tiles, uint32_t* maxout, hipStream_t s) {
     uint64_t ntiles = std::max<uint64_t>(1, (n + kScanTile - 1) / kScanTile);
-    k_scan_tiles<T><<<(uint32_t)ntiles, kBlock, 0, s>>>(in, n, tiles, maxout);
-    k_scan_tile_sums<<<1, kBlock, 0, s>>>(tiles, ntiles);
-    k_scan_apply<T><<<(uint32_t)ntiles, kBlock, 0, s>>>(in, n, tiles, out);
+    if (ntiles == 1 && !maxout) {  // one tile: one launch (small builds)
+        k_scan_apply<T><<<1, kBlock, 0, s>>>(in, n, nullptr, out);
+    } else {
+        k_scan_tiles<T><<<(uint32_t)ntiles, kBlock, 0, s>>>(in, n, tiles, maxout);
+        k_scan_tile_sums<<<1, kBlock, 0, s>>>(tiles, ntiles);
+        k_scan_apply<T><<<(uint32_t)ntiles, kBlock, 0, s>>>(in, n, tiles, out);
+    }
     RS_HIP(hipGetLastError());
     return RS_OK;
 }
