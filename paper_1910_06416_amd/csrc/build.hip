@@ -152,15 +152,18 @@ __global__ __launch_bounds__(kBlock) void k_signature(const BuildDesc* __restric
                 }
             }
         } else {
+            // four strings at a time: their words and states in registers (eight
+            // held 158 VGPRs, three wavefronts per SIMD)
+            constexpr uint32_t kGroupS = 4;
             const uint64_t* off = B.offsets;
             const uint8_t* data = static_cast<const uint8_t*>(B.data);
             const uint64_t bytes = off[B.n];
             const bool aligned = B.aligned != 0;
-            for (uint32_t g = 0; g < kSigItems; g += kGroup) {
-                uint64_t st[kGroup], en[kGroup], a[kGroup], c[kGroup];
+            for (uint32_t g = 0; g < kSigItems; g += kGroupS) {
+                uint64_t st[kGroupS], en[kGroupS], a[kGroupS], c[kGroupS];
                 uint64_t longest = 0;
 #pragma unroll
-                for (uint32_t u = 0; u < kGroup; u++) {
+                for (uint32_t u = 0; u < kGroupS; u++) {
                     const uint64_t i = base + (uint64_t)(g + u) * kBlock;
                     st[u] = en[u] = 0;
                     if (i < total) {
@@ -169,7 +172,7 @@ __global__ __launch_bounds__(kBlock) void k_signature(const BuildDesc* __restric
                     }
                 }
 #pragma unroll
-                for (uint32_t u = 0; u < kGroup; u++) {
+                for (uint32_t u = 0; u < kGroupS; u++) {
                     if (en[u] < st[u] || en[u] > bytes) {
                         atomicOr(&wdescs[j0].flags, kFlagOffsets);
                         en[u] = st[u] = min(st[u], bytes);
@@ -181,7 +184,7 @@ __global__ __launch_bounds__(kBlock) void k_signature(const BuildDesc* __restric
                 }
                 for (uint64_t p = 0; p < longest; p += 8) {
 #pragma unroll
-                    for (uint32_t u = 0; u < kGroup; u++) {
+                    for (uint32_t u = 0; u < kGroupS; u++) {
                         if (st[u] + p < en[u]) {
                             const uint64_t w = string_word(data, bytes, aligned, st[u] + p, en[u]);
                             a[u] = mix64(a[u] ^ w);
@@ -190,7 +193,7 @@ __global__ __launch_bounds__(kBlock) void k_signature(const BuildDesc* __restric
                     }
                 }
 #pragma unroll
-                for (uint32_t u = 0; u < kGroup; u++) {
+                for (uint32_t u = 0; u < kGroupS; u++) {
                     const uint64_t i = base + (uint64_t)(g + u) * kBlock;
                     if (i < total) emit(i, B, mix64(a[u]), mix64(c[u]));
                 }
