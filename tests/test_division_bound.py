@@ -1,0 +1,52 @@
+"""The lookup divides node sizes and hash values below 2^21 by the split unit
+with a single-precision reciprocal: q = trunc(float(x) * rcp(float(d))), then
+one correction by the sign and size of x - q*d.  This checks on the CPU that the
+correction always lands on floor(x / d) when the reciprocal is anywhere within
+one unit in the last place of 1/d (the accuracy the hardware reciprocal
+guarantees), for random and boundary operands up to 2^21.  The GPU lookups
+themselves are compared with the oracle in the GPU tests."""
+import numpy as np
+
+
+def _corrected(x, d, rcp):
+    est = (x.astype(np.float32) * rcp).astype(np.float32)
+    q = np.trunc(est).astype(np.int64)
+    r = x.astype(np.int64) - q * d.astype(np.int64)
+    q = np.where(r < 0, q - 1, q)
+    q = np.where(r >= d.astype(np.int64), q + 1, q)
+    return q
+
+
+def _check(x, d):
+    x = np.asarray(x, dtype=np.uint32)
+    d = np.asarray(d, dtype=np.uint32)
+    exact = (x // d).astype(np.int64)
+    r0 = (np.float32(1.0) / d.astype(np.float32)).astype(np.float32)
+    for rcp in (r0, np.nextafter(r0, np.float32(0)), np.nextafter(r0, np.float32(2))):
+        got = _corrected(x, d, rcp.astype(np.float32))
+        bad = np.nonzero(got != exact)[0]
+        assert bad.size == 0, (int(x[bad[0]]), int(d[bad[0]]), int(got[bad[0]]), int(exact[bad[0]]))
+
+
+def test_random_operands():
+    rng = np.random.default_rng(7)
+    x = rng.integers(0, 1 << 21, 2_000_000, dtype=np.uint64)
+    d = np.maximum(1, (rng.random(x.size) * (x + 1)).astype(np.uint64))
+    _check(x, d)
+    d2 = rng.integers(1, 64, x.size, dtype=np.uint64)  # the units of small leaves
+    _check(x, d2)
+
+
+def test_quotient_boundaries():
+    rng = np.random.default_rng(8)
+    d = rng.integers(1, 1 << 20, 500_000, dtype=np.int64)
+    k = rng.integers(0, np.maximum(1, ((1 << 21) - 2) // d))
+    base = k * d
+    for off in (-1, 0, 1):
+        x = base + off
+        keep = (x >= 0) & (x < (1 << 21))
+        _check(x[keep], d[keep])
+    # largest operands
+    x = np.arange((1 << 21) - 4096, 1 << 21, dtype=np.int64)
+    for dd in (1, 2, 3, 7, 8, 96, 112, 560, 1 << 20):
+        _check(x, np.full(x.size, dd))
