@@ -565,8 +565,8 @@ __device__ __forceinline__ uint32_t leaf_bits(const uint64_t (&k)[M], uint64_t S
 }
 
 template <int M>
-__device__ __forceinline__ uint64_t leaf_search(const uint64_t* keys, uint32_t depth, uint64_t cap, uint32_t* flags, LeafQueues* q,
-                                bool staged) {
+__device__ __forceinline__ uint64_t leaf_search(const uint64_t* keys, uint32_t depth, uint64_t cap, uint32_t* flags,
+                                                LeafQueues* q, bool staged) {
     constexpr int C1 = kCut1[M], C2 = kCut2[M];
     constexpr uint32_t full = (1u << M) - 1u;
     uint64_t k[M];
