@@ -573,19 +573,6 @@ __device__ __forceinline__ uint64_t leaf_search(const uint64_t* keys, uint32_t d
 #pragma unroll
     for (int i = 0; i < M; i++) k[i] = uniform64(keys[i]);
     const uint32_t lane = lane_id();
-    // Equal lower words never separate, so they always meet in one leaf (or in
-    // a split whose parts are all single keys, which checks its own keys): the
-    // leaf compares every pair of its keys first.  The keys are wave-uniform,
-    // so the comparisons are scalar instructions.
-    bool dup = false;
-#pragma unroll
-    for (int i = 0; i < M; i++)
-#pragma unroll
-        for (int j = i + 1; j < M; j++) dup |= k[i] == k[j];
-    if (dup) {
-        if (lane == 0) atomicOr(flags, kFlagDuplicate);
-        return kNoSeed;
-    }
     const uint64_t D = (uint64_t)depth << 56;
     const uint64_t step = 64ull * kGamma;
     uint64_t S = (D + lane) * kGamma;
@@ -702,6 +689,12 @@ __device__ bool has_duplicate(const uint64_t* keys, uint32_t m) {
 template <int MAXL>
 __device__ __forceinline__ uint64_t leaf_dispatch(const uint64_t* keys, uint32_t m, uint32_t depth, uint64_t cap, uint32_t* flags,
                                   LeafQueues* q, uint32_t stage_from) {
+    // Equal lower words never separate, so they always meet in one leaf, or in a
+    // split whose parts are all single keys: those nodes check every pair first.
+    if (has_duplicate(keys, m)) {
+        if (lane_id() == 0) atomicOr(flags, kFlagDuplicate);
+        return kNoSeed;
+    }
     switch (m) {
 #define RS_LEAF_CASE(M)                                                                    \
     case M:                                                                                \
