@@ -60,6 +60,29 @@ typedef struct {
 
 typedef struct rs_blob rs_blob; /* opaque; immutable after build; safe for concurrent lookups */
 
+/* Device memory.  Every device buffer of the library (a call's workspace, the
+ * per-size tables, blob arenas, plan buffers, the autotuner's calibration keys)
+ * comes from one process-wide allocator, by default stream-ordered
+ * hipMallocAsync / hipFreeAsync.  rs_set_allocator installs the caller's
+ * instead, e.g. PyTorch's caching allocator (the Python binding does so), so
+ * that the library's memory is counted and reused with the caller's own.
+ *   alloc(bytes, stream, ctx): return 256-byte aligned device memory of at
+ *     least `bytes` bytes on the current device, for work enqueued on `stream`
+ *     (a hipStream_t); NULL = out of memory, and the call fails with RS_ENOMEM.
+ *   release(ptr, stream, ctx): give ptr back.  With a non-NULL stream the
+ *     memory may still be in use by work already enqueued on that stream (it
+ *     is free once that work is done, as with hipFreeAsync); with stream ==
+ *     NULL no device work uses it any more.
+ * Both NULL restores the default; exactly one NULL is RS_EINVAL.  The setting
+ * applies to allocations made after the call, from any thread; memory keeps
+ * the allocator that made it and is released through it, so alloc, release
+ * and ctx must stay valid until every blob, plan and server created while they
+ * were installed has been freed.  The functions may be called from the
+ * library's server threads and must be thread-safe.  No device is needed. */
+typedef void* (*rs_alloc_fn)(size_t bytes, void* stream, void* ctx);
+typedef void (*rs_free_fn)(void* ptr, void* stream, void* ctx);
+int rs_set_allocator(rs_alloc_fn alloc, rs_free_fn release, void* ctx);
+
 /* Build options (all-zero = defaults).
  *   seed_cap  : lowers the search cap of every split and bijection index
  *               (0 = 2^56); it exists to exercise the RS_ESEARCH path.
@@ -72,6 +95,14 @@ typedef struct rs_blob rs_blob; /* opaque; immutable after build; safe for concu
  *               use the built-in schedule.
  *   stage_from, group_max, waves: schedule overrides for every build of the
  *               call (0 = keep the table's or built-in value), as in rs_schedule.
+ *   wait_limit: when several wavefronts share a bucket's tree, a wavefront
+ *               waiting for a node whose parent is still being searched waits
+ *               as long as some wavefront of the bucket reports progress; it
+ *               gives up (and the build fails with RS_EDEVICE, "search
+ *               scheduling failed") only after wait_limit sleeps of about
+ *               0.1 us with no progress at all, which the node order rules out
+ *               in a correct build.  0 = 2^25 (several seconds).  Small values
+ *               exist to exercise that error path.
  * Schedules never change the result, only the time it takes. */
 enum { RS_OPT_TIMING = 1, RS_OPT_TUNED = 2 };
 typedef struct {
@@ -80,7 +111,8 @@ typedef struct {
     uint32_t stage_from;
     uint32_t group_max;
     uint32_t waves;
-    uint32_t reserved[2];
+    uint32_t wait_limit;
+    uint32_t reserved;
 } rs_options;
 
 /* Search schedule of one (l, b) pair.  The seed search runs one workgroup per

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -30,9 +31,24 @@ int fail(int code, const char* fmt, ...) {
 
 void clear_error() { g_error.clear(); }
 
-int dev_alloc(void** p, size_t bytes, hipStream_t s) {
+namespace {
+std::mutex g_alloc_mu;
+Alloc g_alloc;
+}  // namespace
+
+Alloc current_alloc() {
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    return g_alloc;
+}
+
+int Alloc::get(void** p, size_t bytes, hipStream_t s) const {
     *p = nullptr;
-    hipError_t e = hipMallocAsync(p, std::max<size_t>(bytes, 256), s);
+    bytes = std::max<size_t>(bytes, 256);
+    if (alloc) {
+        *p = alloc(bytes, (void*)s, ctx);
+        return *p ? RS_OK : fail(RS_ENOMEM, "the caller's allocator returned no memory for %zu bytes", bytes);
+    }
+    hipError_t e = hipMallocAsync(p, bytes, s);
     if (e != hipSuccess) {
         *p = nullptr;
         return fail(e == hipErrorOutOfMemory ? RS_ENOMEM : RS_EDEVICE, "device allocation of %zu bytes failed: %s",
@@ -41,8 +57,16 @@ int dev_alloc(void** p, size_t bytes, hipStream_t s) {
     return RS_OK;
 }
 
-void dev_free(void* p, hipStream_t s) {
-    if (p) (void)hipFreeAsync(p, s);
+void Alloc::put(void* p, hipStream_t s) const {
+    if (!p) return;
+    if (release) release(p, (void*)s, ctx);
+    else (void)hipFreeAsync(p, s);
+}
+
+void Alloc::put_idle(void* p) const {
+    if (!p) return;
+    if (release) release(p, nullptr, ctx);
+    else (void)hipFree(p);
 }
 
 Layout layout_of(const uint64_t* h) {
@@ -270,9 +294,11 @@ __device__ uint64_t rank_of(const LookupArgs& a, uint64_t hi, uint64_t lo) {
     return s_i + c;
 }
 
-__global__ void k_lookup_u64(LookupArgs a, const uint64_t* __restrict__ keys, uint64_t q,
+// One query per lane; q0 is the launch's first query (lookups of more
+// queries than one grid holds are launched in chunks).
+__global__ void k_lookup_u64(LookupArgs a, const uint64_t* __restrict__ keys, uint64_t q, uint64_t q0,
                              uint64_t* __restrict__ ranks) {
-    uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    uint64_t t = q0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= q) return;
     uint64_t hi, lo;
     signature_u64(keys[t], hi, lo);
@@ -280,8 +306,8 @@ __global__ void k_lookup_u64(LookupArgs a, const uint64_t* __restrict__ keys, ui
 }
 
 __global__ void k_lookup_bytes(LookupArgs a, const uint8_t* __restrict__ data, const uint64_t* __restrict__ offsets,
-                               uint64_t q, bool aligned, uint64_t* __restrict__ ranks) {
-    uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                               uint64_t q, uint64_t q0, bool aligned, uint64_t* __restrict__ ranks) {
+    uint64_t t = q0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= q) return;
     uint64_t total = offsets[q];
     uint64_t s = offsets[t], e = offsets[t + 1];
@@ -314,12 +340,20 @@ extern "C" int rs_lookup(const rs_blob* blob, const rs_keys* queries, uint64_t* 
     hipStream_t s = (hipStream_t)stream;
     if (blob->ready) RS_HIP(hipStreamWaitEvent(s, blob->ready, 0));  // built on another stream
     const uint32_t block = 256;
-    uint32_t grid = (uint32_t)((queries->n + block - 1) / block);
-    if (queries->kind == RS_KEYS_U64)
-        k_lookup_u64<<<grid, block, 0, s>>>(a, (const uint64_t*)queries->data, queries->n, ranks_dev);
-    else
-        k_lookup_bytes<<<grid, block, 0, s>>>(a, (const uint8_t*)queries->data, queries->offsets, queries->n,
-                                              ((uintptr_t)queries->data & 7) == 0, ranks_dev);
+    const uint64_t q = queries->n;
+    // one query per lane, in launches of at most max_grid_blocks() blocks
+    if (int rc = for_each_chunk(q, block, block, [&](uint64_t q0, uint64_t, uint64_t grid) -> int {
+            if (!grid_fits(grid, block))
+                return fail(RS_EINVAL, "lookup grid of %llu blocks does not fit", (unsigned long long)grid);
+            if (queries->kind == RS_KEYS_U64)
+                k_lookup_u64<<<(uint32_t)grid, block, 0, s>>>(a, (const uint64_t*)queries->data, q, q0, ranks_dev);
+            else
+                k_lookup_bytes<<<(uint32_t)grid, block, 0, s>>>(a, (const uint8_t*)queries->data, queries->offsets,
+                                                                q, q0, ((uintptr_t)queries->data & 7) == 0,
+                                                                ranks_dev);
+            return RS_OK;
+        }))
+        return rc;
     RS_HIP(hipGetLastError());
     return RS_OK;
 }
@@ -360,15 +394,16 @@ extern "C" int rs_blob_from_host(const void* src, uint64_t bytes, void* stream, 
     rs_blob* b = new (std::nothrow) rs_blob;
     if (!b) return fail(RS_ENOMEM, "host allocation failed");
     memcpy(b->header, h, sizeof b->header);
-    int rc = dev_alloc((void**)&b->words, bytes, s);
-    if (!rc) rc = dev_alloc((void**)&b->tables, 3ull * (L.maxm + 1) * 4, s);
+    b->al = current_alloc();
+    int rc = b->al.get((void**)&b->words, bytes, s);
+    if (!rc) rc = b->al.get((void**)&b->tables, 3ull * (L.maxm + 1) * 4, s);
     if (!rc) rc = upload_tables((uint32_t)L.leaf, (uint32_t)L.maxm, b->tables, s);
     if (!rc && hipMemcpyAsync(b->words, src, bytes, hipMemcpyHostToDevice, s) != hipSuccess)
         rc = fail(RS_EDEVICE, "copy to device failed");
     if (!rc && hipStreamSynchronize(s) != hipSuccess) rc = fail(RS_EDEVICE, "stream synchronisation failed");
     if (rc) {
-        dev_free(b->words, s);
-        dev_free(b->tables, s);
+        b->al.put(b->words, s);
+        b->al.put(b->tables, s);
         delete b;
         return rc;
     }
@@ -385,10 +420,21 @@ extern "C" void rs_blob_free(rs_blob* blob) {
     if (blob->arena) {
         release_arena(blob->arena);
     } else {
-        if (blob->words) (void)hipFree(blob->words);
-        if (blob->tables) (void)hipFree(blob->tables);
+        blob->al.put_idle(blob->words);
+        blob->al.put_idle(blob->tables);
     }
     delete blob;
+}
+
+extern "C" int rs_set_allocator(rs_alloc_fn alloc, rs_free_fn release, void* ctx) {
+    clear_error();
+    if ((alloc == nullptr) != (release == nullptr))
+        return fail(RS_EINVAL, "set both the allocation and the release function, or neither");
+    std::lock_guard<std::mutex> lk(g_alloc_mu);
+    g_alloc.alloc = alloc;
+    g_alloc.release = release;
+    g_alloc.ctx = alloc ? ctx : nullptr;
+    return RS_OK;
 }
 
 extern "C" const char* rs_last_error(void) { return g_error.c_str(); }

@@ -506,6 +506,8 @@ struct SearchArgs {
     uint32_t stride;
     uint64_t seed_cap;
     uint32_t key_words;   // 64-bit words of dynamic LDS before the node slots (largest bucket)
+    uint32_t wait_limit;  // sleeps a slot wait tolerates without any search progress in the bucket
+    uint64_t bucket0;     // bucket of block 0 of this launch (the search is launched in chunks)
 };
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & 63; }
@@ -537,6 +539,32 @@ __device__ __forceinline__ void wave_lds_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Shared state of one bucket's workgroup (LDS).  Every wavefront that is
+// searching adds to `beat` at regular intervals: a wavefront waiting for a
+// slot gives up only when `beat` stops moving (no wavefront of the bucket is
+// making progress, which the slot order rules out unless the tables and the
+// strategy disagree), never because a search simply takes long.
+struct QueueState {
+    uint32_t head;   // next slot to claim
+    uint32_t tail;   // next slot to fill
+    uint32_t abort;  // set by a wavefront that abandons the bucket
+    uint32_t beat;   // search progress counter
+    unsigned long long bits;
+};
+
+// Default number of s_sleep(4) rounds (about 0.1-0.15 us each) a slot wait
+// tolerates while `beat` does not move: several seconds, against search
+// steps that bump it every few milliseconds at most.
+constexpr uint32_t kDefaultWaitLimit = 1u << 25;
+
+// Progress report of a searching wavefront, and whether the bucket was
+// abandoned meanwhile (wave-uniform).
+__device__ __forceinline__ bool search_poll(QueueState* qs) {
+    if (lane_id() == 0) __hip_atomic_fetch_add(&qs->beat, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    const uint32_t ab = __hip_atomic_load(&qs->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    return __builtin_amdgcn_readfirstlane(ab) != 0;
+}
+
 // ---- bijections --------------------------------------------------------------
 // A trial fails at its first collision, so candidates are filtered in up to
 // three stages: every new candidate is tried on the first C1 keys; survivors
@@ -564,9 +592,12 @@ __device__ __forceinline__ uint32_t leaf_bits(const uint64_t (&k)[M], uint64_t S
     return mask;
 }
 
+// Search steps (of 64 candidates) between two progress reports of a bijection search.
+constexpr uint64_t kLeafPollMask = 64ull * 64 - 1;
+
 template <int M>
 __device__ __forceinline__ uint64_t leaf_search(const uint64_t* keys, uint32_t depth, uint64_t cap, uint32_t* flags,
-                                                LeafQueues* q, bool staged) {
+                                                LeafQueues* q, bool staged, QueueState* qs) {
     constexpr int C1 = kCut1[M], C2 = kCut2[M];
     constexpr uint32_t full = (1u << M) - 1u;
     uint64_t k[M];
@@ -598,6 +629,7 @@ __device__ __forceinline__ uint64_t leaf_search(const uint64_t* keys, uint32_t d
             uint64_t bal = __ballot(ok);
             if (bal) return base + (uint64_t)__builtin_ctzll(bal);
             if (at_end) break;
+            if ((base & kLeafPollMask) == kLeafPollMask - 63 && search_poll(qs)) return kNoSeed;
         }
     } else if constexpr (C1 < M) {
         uint32_t a_head = 0, a_tail = 0, b_head = 0, b_tail = 0;
@@ -669,6 +701,7 @@ __device__ __forceinline__ uint64_t leaf_search(const uint64_t* keys, uint32_t d
                 }
             }
             if (last) break;
+            if ((base & kLeafPollMask) == kLeafPollMask - 63 && search_poll(qs)) return kNoSeed;
         }
     }
     if (lane == 0) atomicOr(flags, kFlagSearch);
@@ -687,10 +720,12 @@ __device__ bool has_duplicate(const uint64_t* keys, uint32_t m) {
 // Inlined into each search kernel: as a call shared by the kernels it costs
 // the calling convention's register saves and the uniformity of its arguments.
 template <int MAXL>
-__device__ __forceinline__ uint64_t leaf_dispatch(const uint64_t* keys, uint32_t m, uint32_t depth, uint64_t cap, uint32_t* flags,
-                                  LeafQueues* q, uint32_t stage_from) {
-    // Equal lower words never separate, so they always meet in one leaf, or in a
-    // split whose parts are all single keys: those nodes check every pair first.
+__device__ __forceinline__ uint64_t leaf_dispatch(const uint64_t* keys, uint32_t m, uint32_t depth, uint64_t cap,
+                                                  uint32_t* flags, LeafQueues* q, uint32_t stage_from,
+                                                  QueueState* qs) {
+    // Equal lower words never separate: copies that reach a leaf together are
+    // caught here (more copies than any part of a split holds stop that split's
+    // search instead, see split_search).
     if (has_duplicate(keys, m)) {
         if (lane_id() == 0) atomicOr(flags, kFlagDuplicate);
         return kNoSeed;
@@ -698,7 +733,7 @@ __device__ __forceinline__ uint64_t leaf_dispatch(const uint64_t* keys, uint32_t
     switch (m) {
 #define RS_LEAF_CASE(M)                                                                    \
     case M:                                                                                \
-        if constexpr (M <= MAXL) return leaf_search<M>(keys, depth, cap, flags, q, M > 16 || M >= stage_from); \
+        if constexpr (M <= MAXL) return leaf_search<M>(keys, depth, cap, flags, q, M > 16 || M >= stage_from, qs); \
         return kNoSeed;
         RS_LEAF_CASE(2) RS_LEAF_CASE(3) RS_LEAF_CASE(4) RS_LEAF_CASE(5) RS_LEAF_CASE(6) RS_LEAF_CASE(7)
         RS_LEAF_CASE(8) RS_LEAF_CASE(9) RS_LEAF_CASE(10) RS_LEAF_CASE(11) RS_LEAF_CASE(12) RS_LEAF_CASE(13)
@@ -741,9 +776,35 @@ struct SplitCtl {
     uint64_t want;   // packed target
 };
 
+// True if two of the m keys are equal (any m; wave-uniform result).  Lane i
+// holds key c0 + i and compares it with every later key (same LDS address for
+// all lanes: one broadcast read per comparison).  m^2/128 comparisons.
+__device__ bool node_has_duplicate(const uint64_t* keys, uint32_t m) {
+    const uint32_t lane = lane_id();
+    bool dup = false;
+    for (uint32_t c0 = 0; c0 < m; c0 += 64) {
+        const uint32_t i = c0 + lane;
+        const uint64_t mine = i < m ? keys[i] : 0;
+        for (uint32_t j = c0 + 1; j < m; j++) dup |= j > i && i < m && keys[j] == mine;
+    }
+    return __ballot(dup) != 0;
+}
+
+// Split search steps between two progress reports.
+constexpr uint32_t kSplitPollSteps = 16;
+
+// Equal keys always land in the same part.  A group of equal keys larger than
+// every part can therefore never be split, and the search would not end; a
+// group that fits travels on and is caught by the leaf that receives it.  So
+// once a split search has tried 64 m candidates (the expected number of
+// trials of every node the strategy makes is far below that for small nodes,
+// and the check then costs well under 1% of the work already spent), and
+// again each time that count doubles, the node's keys are compared pairwise,
+// and equal keys end the search with the duplicate flag.  The check changes
+// no result: without duplicates the search simply goes on.
 template <int NT, int MODE>
 __device__ uint64_t split_search(const uint64_t* keys, uint32_t depth, const SplitCtl& c, const uint32_t* T,
-                                 uint64_t cap, uint32_t* flags) {
+                                 uint64_t cap, uint32_t* flags, QueueState* qs) {
     constexpr int NA = NT > 0 ? NT : 1;  // NT = 0 in the packed modes
     uint32_t thr[NA];
 #pragma unroll
@@ -760,6 +821,8 @@ __device__ uint64_t split_search(const uint64_t* keys, uint32_t depth, const Spl
     const uint32_t quads = m / (4 * G);
     const uint32_t tail = quads * 4 * G;
     uint64_t S = (((uint64_t)depth << 56) + gi) * kGamma;
+    uint64_t next_check = 64ull * m;
+    uint32_t steps = 0;
     for (uint64_t base = 0; base < cap; base += per_step, S += step) {
         uint32_t cnt[NA];
         uint64_t packed = 0;
@@ -819,6 +882,17 @@ __device__ uint64_t split_search(const uint64_t* keys, uint32_t depth, const Spl
         }
         uint64_t bal = __ballot(ok);
         if (bal) return base + (uint64_t)(__builtin_ctzll(bal) >> c.g);
+        if (++steps == kSplitPollSteps) {
+            steps = 0;
+            if (search_poll(qs)) return kNoSeed;
+        }
+        if (base + per_step >= next_check) {
+            if (node_has_duplicate(keys, m)) {
+                if (lane == 0) atomicOr(flags, kFlagDuplicate);
+                return kNoSeed;
+            }
+            next_check *= 2;
+        }
     }
     if (lane == 0) atomicOr(flags, kFlagSearch);
     return kNoSeed;
@@ -826,13 +900,13 @@ __device__ uint64_t split_search(const uint64_t* keys, uint32_t depth, const Spl
 
 template <int MAXNT>
 __device__ uint64_t split_dispatch(const uint64_t* keys, uint32_t depth, const SplitCtl& c, const uint32_t* T,
-                                   uint32_t mode, uint64_t cap, uint32_t* flags) {
-    if (mode == kCountPacked) return split_search<0, kCountPacked>(keys, depth, c, T, cap, flags);
-    if (mode == kCountOneHot) return split_search<0, kCountOneHot>(keys, depth, c, T, cap, flags);
+                                   uint32_t mode, uint64_t cap, uint32_t* flags, QueueState* qs) {
+    if (mode == kCountPacked) return split_search<0, kCountPacked>(keys, depth, c, T, cap, flags, qs);
+    if (mode == kCountOneHot) return split_search<0, kCountOneHot>(keys, depth, c, T, cap, flags, qs);
     switch (c.fanout - 1) {
 #define RS_SPLIT_CASE(NT)                                                                 \
     case NT:                                                                              \
-        if constexpr (NT <= MAXNT) return split_search<NT, kCountThresholds>(keys, depth, c, T, cap, flags); \
+        if constexpr (NT <= MAXNT) return split_search<NT, kCountThresholds>(keys, depth, c, T, cap, flags, qs); \
         return kNoSeed;
         RS_SPLIT_CASE(1) RS_SPLIT_CASE(2) RS_SPLIT_CASE(3) RS_SPLIT_CASE(4) RS_SPLIT_CASE(5) RS_SPLIT_CASE(6)
         RS_SPLIT_CASE(7) RS_SPLIT_CASE(8)
@@ -920,22 +994,16 @@ __device__ __forceinline__ void partition(uint64_t* keys, uint32_t m, uint32_t d
 // waiting, and the bucket is done when every slot has been claimed.  A node's
 // preorder position (where its index is stored) is its parent's position + 1
 // + the coded nodes of its earlier siblings, j * N(u).  Waits end early if
-// another wavefront abandons the bucket, and a bound on waiting turns a
-// scheduling error into a reported failure instead of a hang.
+// another wavefront abandons the bucket.  A wait never times out while some
+// wavefront of the bucket reports search progress (the chain of waits always
+// ends at a searching wavefront, so a long search only means a long wait);
+// if no progress is reported for wait_limit sleeps, which the slot order rules
+// out, the bucket fails with the scheduling flag instead of hanging.
 struct NodeSlot {
     uint32_t off, d, idx;
     uint32_t m;  // published last (release); 0 = not yet filled
 };
 
-struct QueueState {
-    uint32_t head;  // next slot to claim
-    uint32_t tail;  // next slot to fill
-    uint32_t abort;
-    uint32_t pad;
-    unsigned long long bits;
-};
-
-constexpr uint32_t kWaitLimit = 1u << 27;  // ~30 s of s_sleep(4) per wait
 
 template <int MAXL, int WAVES>
 __global__ __launch_bounds__(64 * WAVES) void k_search(SearchArgs a) {
@@ -948,7 +1016,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_search(SearchArgs a) {
     NodeSlot* slots = reinterpret_cast<NodeSlot*>(lds_dyn + a.key_words);
     uint32_t* thr = thr_s[wave];
     {
-        const uint64_t b = blockIdx.x;
+        const uint64_t b = a.bucket0 + blockIdx.x;
         const uint32_t j = find_build(a.bucket_base, a.count, b);
         const BuildDesc& B = a.descs[j];
         // the descriptor is also written by this kernel (flags), so its fields are
@@ -981,6 +1049,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_search(SearchArgs a) {
             qs.head = 0;
             qs.tail = total ? 1 : 0;
             qs.abort = 0;
+            qs.beat = 0;
             qs.bits = 0;
             if (total) {
                 slots[0].off = 0;
@@ -998,7 +1067,9 @@ __global__ __launch_bounds__(64 * WAVES) void k_search(SearchArgs a) {
                 if (h >= total) {
                     stop = 1;
                 } else {
-                    uint32_t spins = 0;
+                    // wait for the slot while some wavefront of the bucket makes progress
+                    uint32_t idle = 0;
+                    uint32_t seen = __hip_atomic_load(&qs.beat, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                     for (;;) {
                         m = __hip_atomic_load(&slots[h].m, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
                         if (m) break;
@@ -1006,7 +1077,11 @@ __global__ __launch_bounds__(64 * WAVES) void k_search(SearchArgs a) {
                             stop = 1;
                             break;
                         }
-                        if (++spins == kWaitLimit) {
+                        const uint32_t now = __hip_atomic_load(&qs.beat, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        if (now != seen) {
+                            seen = now;
+                            idle = 0;
+                        } else if (++idle >= a.wait_limit) {
                             atomicOr(bflags, kFlagStack);
                             __hip_atomic_store(&qs.abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                             stop = 1;
@@ -1031,7 +1106,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_search(SearchArgs a) {
             bool fail;
             SplitShape sh{};
             if (m <= leaf) {
-                v = leaf_dispatch<MAXL>(lds_keys + off, m, d, a.seed_cap, bflags, &queues[wave], stage_from);
+                v = leaf_dispatch<MAXL>(lds_keys + off, m, d, a.seed_cap, bflags, &queues[wave], stage_from, &qs);
                 fail = v == kNoSeed;
             } else {
                 sh = split_shape(m, leaf, lower, upper);
@@ -1056,7 +1131,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_search(SearchArgs a) {
                     if (mode != kCountThresholds)
                         for (uint32_t q = 0; q < sh.fanout; q++)
                             c.want += (uint64_t)(q + 1 == sh.fanout ? sh.last : sh.unit) << (q * c.w);
-                    v = split_dispatch<max_thresholds(MAXL)>(lds_keys + off, d, c, thr, mode, a.seed_cap, bflags);
+                    v = split_dispatch<max_thresholds(MAXL)>(lds_keys + off, d, c, thr, mode, a.seed_cap, bflags,
+                                                             &qs);
                     fail = v == kNoSeed;  // counts do not match the parts: no partition
                     if (!fail)
                         partition(lds_keys + off, m, d, v, thr, nt, sh.unit, reinterpret_cast<uint64_t*>(&queues[wave]),
@@ -1246,6 +1322,7 @@ struct FillArgs {
     uint64_t nbuckets;
     const uint32_t* tables;
     uint32_t stride;
+    uint64_t g0;  // k_tree_bits: bucket of the launch's first lane group
 };
 
 // One thread per Elias-Fano entry i = 0..nb of every build.
@@ -1313,7 +1390,7 @@ __device__ __forceinline__ uint64_t group_inclusive_sum(uint64_t x, uint32_t gl)
 
 __global__ __launch_bounds__(kBlock) void k_tree_bits(FillArgs a) {
     __shared__ unsigned long long window[kBlock / kTreeLanes][kTreeWords];
-    const uint64_t g = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kTreeLanes;
+    const uint64_t g = a.g0 + ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kTreeLanes;
     const uint32_t gl = threadIdx.x & (kTreeLanes - 1);
     if (g >= a.nbuckets) return;
     const uint32_t j = find_build(a.bucket_base, a.count, g);
@@ -1471,18 +1548,28 @@ __global__ void k_set_blobs(BuildDesc* __restrict__ descs, uint32_t count, unsig
     }
 }
 
-uint32_t grid_for(uint64_t n, uint32_t block) { return (uint32_t)std::max<uint64_t>(1, (n + block - 1) / block); }
+uint64_t grid_for(uint64_t n, uint64_t block) { return std::max<uint64_t>(1, (n + block - 1) / block); }
+
+// Launch with the grid checked against the dispatch limits (launch.h).
+#define RS_LAUNCH(kern, blocks, threads, lds, stream, ...)                                            \
+    do {                                                                                              \
+        const uint64_t blocks_ = (blocks);                                                            \
+        if (!grid_fits(blocks_, (threads)))                                                           \
+            return fail(RS_EINVAL, "grid of %llu blocks of %s does not fit one launch",               \
+                        (unsigned long long)blocks_, #kern);                                          \
+        kern<<<dim3((uint32_t)blocks_), dim3((uint32_t)(threads)), (lds), (stream)>>>(__VA_ARGS__);   \
+    } while (0)
 
 // Exclusive scan of n values into out[0..n]; tiles holds ceil(n/kScanTile)+1 words.
 template <typename T>
 int scan(const T* in, uint64_t n, uint64_t* out, uint64_t* tiles, uint32_t* maxout, hipStream_t s) {
     uint64_t ntiles = std::max<uint64_t>(1, (n + kScanTile - 1) / kScanTile);
     if (ntiles == 1 && !maxout) {  // one tile: one launch (small builds)
-        k_scan_apply<T><<<1, kBlock, 0, s>>>(in, n, nullptr, out);
+        RS_LAUNCH(k_scan_apply<T>, 1, kBlock, 0, s, in, n, nullptr, out);
     } else {
-        k_scan_tiles<T><<<(uint32_t)ntiles, kBlock, 0, s>>>(in, n, tiles, maxout);
-        k_scan_tile_sums<<<1, kBlock, 0, s>>>(tiles, ntiles);
-        k_scan_apply<T><<<(uint32_t)ntiles, kBlock, 0, s>>>(in, n, tiles, out);
+        RS_LAUNCH(k_scan_tiles<T>, ntiles, kBlock, 0, s, in, n, tiles, maxout);
+        RS_LAUNCH(k_scan_tile_sums, 1, kBlock, 0, s, tiles, ntiles);
+        RS_LAUNCH(k_scan_apply<T>, ntiles, kBlock, 0, s, in, n, tiles, out);
     }
     RS_HIP(hipGetLastError());
     return RS_OK;
@@ -1628,11 +1715,18 @@ int launch_search(uint32_t max_leaf, uint32_t waves, const SearchArgs& sa, size_
     if (int rc = static_lds(reinterpret_cast<const void*>(k), &static_bytes)) return rc;
     if (lds + static_bytes > (size_t)max_lds_bytes())
         return fail(RS_EINVAL, "largest bucket (%u keys) exceeds the local data share", sa.key_words);
-    SearchArgs args = sa;
-    void* params[] = {&args};
-    RS_HIP(hipLaunchKernel(reinterpret_cast<const void*>(k), dim3((uint32_t)sa.nbuckets), dim3(64 * waves), params,
-                           lds, s));
-    return RS_OK;
+    // one workgroup per bucket, in launches of at most max_grid_blocks() workgroups
+    const uint64_t threads = 64ull * waves;
+    return for_each_chunk(sa.nbuckets, threads, 1, [&](uint64_t first, uint64_t, uint64_t blocks) -> int {
+        if (!grid_fits(blocks, threads))
+            return fail(RS_EINVAL, "search grid of %llu blocks does not fit", (unsigned long long)blocks);
+        SearchArgs args = sa;
+        args.bucket0 = first;
+        void* params[] = {&args};
+        RS_HIP(hipLaunchKernel(reinterpret_cast<const void*>(k), dim3((uint32_t)blocks), dim3((uint32_t)threads),
+                               params, lds, s));
+        return RS_OK;
+    });
 }
 
 }  // namespace
@@ -1644,13 +1738,14 @@ struct BlobArena {
     uint32_t* tables = nullptr;
     std::atomic<int> refs{0};
     hipEvent_t ready = nullptr;
+    Alloc al;  // the allocator that made words and tables
 };
 
 void release_arena(BlobArena* a) {
     if (a && a->refs.fetch_sub(1) == 1) {
         if (a->ready) (void)hipEventSynchronize(a->ready);
-        if (a->words) (void)hipFree(a->words);
-        if (a->tables) (void)hipFree(a->tables);
+        a->al.put_idle(a->words);
+        a->al.put_idle(a->tables);
         if (a->ready) (void)hipEventDestroy(a->ready);
         delete a;
     }
@@ -1808,6 +1903,7 @@ struct Batch {
     std::vector<uint32_t> which;  // desc index -> position in the call
     std::vector<uint32_t> leaf_of_tab;
     uint64_t total = 0, nbuckets = 0, seed_cap = kDefaultSeedCap;
+    uint32_t wait_limit = kDefaultWaitLimit;
     uint32_t K = 0, max_leaf = 1, launch_waves = 1;
     uint32_t shift = 0, nbins = 0, nxcd = 1;
     // device workspace
@@ -1838,6 +1934,7 @@ int batch_prepare(Batch& b, const rs_keys* sets, uint32_t count, const uint32_t*
         return fail(RS_EINVAL, "waves must be 1, 2, 4 or 8");
     b.count = count;
     b.seed_cap = opts && opts->seed_cap ? std::min(opts->seed_cap, kDefaultSeedCap) : kDefaultSeedCap;
+    b.wait_limit = opts && opts->wait_limit ? opts->wait_limit : kDefaultWaitLimit;
     b.st.assign(count, RS_OK);
     b.why.assign(count, std::string());
     for (uint32_t c = 0; c < count; c++) {
@@ -2010,20 +2107,19 @@ int enqueue_front(Batch& b, hipStream_t s, PhaseEvents* pe) {
     if (pe) pe->record(0, s);
     RS_ENQ(hipMemcpyAsync(b.d_kb, b.h_kb, b.io_in, hipMemcpyHostToDevice, s));
     const uint64_t ncnt = (uint64_t)b.nbins * b.nxcd;
-    k_reset<<<grid_for(ncnt, kBlock * 4), kBlock, 0, s>>>(b.d_st, b.d_bincnt, ncnt);
-    k_signature<<<grid_for(b.total, kSigTile), kBlock, b.nbins * 4, s>>>(
-        b.d_desc, b.d_desc, b.d_kb, K, b.total, b.d_lo, b.d_bid, b.shift, b.nbins, b.nxcd, b.d_bincnt);
+    RS_LAUNCH(k_reset, grid_for(ncnt, kBlock * 4), kBlock, 0, s, b.d_st, b.d_bincnt, ncnt);
+    RS_LAUNCH(k_signature, grid_for(b.total, kSigTile), kBlock, b.nbins * 4, s, b.d_desc, b.d_desc, b.d_kb, K,
+              b.total, b.d_lo, b.d_bid, b.shift, b.nbins, b.nxcd, b.d_bincnt);
     if (pe) pe->record(1, s);
     // before the search, the partition scratch and the index array hold the keys in bin order
     uint64_t* bin_lo = b.d_tmp;
     uint32_t* bin_bid = (uint32_t*)b.d_seeds;
-    k_bin_offsets<<<1, kBlock, 0, s>>>(b.d_bincnt, b.nbins, b.nxcd, b.d_binst, b.d_bincur);
-    k_bin_scatter<<<grid_for(b.total, kSigTile), kBlock, b.nbins * 12, s>>>(
-        b.d_lo, b.d_bid, b.total, b.shift, b.nbins, b.nxcd, b.d_bincur, bin_lo, bin_bid);
+    RS_LAUNCH(k_bin_offsets, 1, kBlock, 0, s, b.d_bincnt, b.nbins, b.nxcd, b.d_binst, b.d_bincur);
+    RS_LAUNCH(k_bin_scatter, grid_for(b.total, kSigTile), kBlock, b.nbins * 12, s, b.d_lo, b.d_bid, b.total, b.shift,
+              b.nbins, b.nxcd, b.d_bincur, bin_lo, bin_bid);
     const uint32_t piece = (uint32_t)std::min<uint64_t>(std::min(1u << b.shift, kSortSpan), b.nbuckets);
-    k_bucket_sort<<<b.nbins, kSortBlock, 8u * piece, s>>>(
-        b.d_binst, bin_lo, bin_bid, b.shift, piece, b.nbuckets,
-                                                              b.d_bst, b.d_sorted, &b.d_st->maxm);
+    RS_LAUNCH(k_bucket_sort, b.nbins, kSortBlock, 8u * piece, s, b.d_binst, bin_lo, bin_bid, b.shift, piece,
+              b.nbuckets, b.d_bst, b.d_sorted, &b.d_st->maxm);
     if (pe) pe->record(2, s);
     RS_ENQ(hipGetLastError());
     return RS_OK;
@@ -2058,7 +2154,7 @@ SearchArgs search_args(const Batch& b) {
     // the bucket numbers of the keys are no longer needed once the keys are
     // in bucket order: their array takes the node sizes
     return SearchArgs{b.d_sorted, b.d_tmp, b.d_bst, b.d_seeds, b.d_bid, b.d_blen, b.d_desc, b.d_desc, b.d_bb, b.K,
-                      b.nbuckets, b.d_tab, b.stride, b.seed_cap, b.table_maxm};
+                      b.nbuckets, b.d_tab, b.stride, b.seed_cap, b.table_maxm, b.wait_limit, 0};
 }
 
 // Seed search, bit-length prefix sums, Elias-Fano statistics, blob geometry
@@ -2069,24 +2165,31 @@ int enqueue_back(Batch& b, hipStream_t s, PhaseEvents* pe) {
     if (pe) pe->record(4, s);
     if (int rc = scan<uint64_t>(b.d_blen, b.nbuckets, b.d_ost, b.d_tiles, nullptr, s)) return rc;
     GapArgs ga{b.d_bst, b.d_ost, b.d_desc, b.d_desc, b.d_bb, b.K, b.nbuckets};
-    k_ef_gaps<<<grid_for(b.nbuckets, kGapTile), kBlock, 0, s>>>(ga);
-    k_layout<<<1, kBlock, 0, s>>>(b.d_desc, b.K, b.d_hdr, b.d_raw, b.d_boff);
+    RS_LAUNCH(k_ef_gaps, grid_for(b.nbuckets, kGapTile), kBlock, 0, s, ga);
+    RS_LAUNCH(k_layout, 1, kBlock, 0, s, b.d_desc, b.K, b.d_hdr, b.d_raw, b.d_boff);
     if (pe) pe->record(5, s);
     RS_ENQ(hipGetLastError());
     return RS_OK;
 }
 
-// Blob addresses in `arena` (capacity words), cleared blobs, headers,
-// Elias-Fano bits and Golomb-Rice streams.
-int enqueue_fill(Batch& b, uint64_t* arena, uint64_t capacity, hipStream_t s) {
+// Blob addresses in `arena` (capacity words; the first clear_words words are
+// zeroed first), headers, Elias-Fano bits and Golomb-Rice streams.
+int enqueue_fill(Batch& b, uint64_t* arena, uint64_t capacity, uint64_t clear_words, hipStream_t s) {
     const uint32_t K = b.K;
-    k_set_blobs<<<grid_for(K, kBlock), kBlock, 0, s>>>(b.d_desc, K, (unsigned long long*)arena, b.d_boff, capacity,
-                                                      &b.d_st->flags);
-    if (arena && capacity) k_fill_u64<<<grid_for(capacity, kBlock * 8), kBlock, 0, s>>>(arena, capacity, 0);
-    k_write_headers<<<grid_for((uint64_t)K * kHeaderWords, kBlock), kBlock, 0, s>>>(b.d_desc, b.d_hdr, K);
-    FillArgs fa{b.d_bst, b.d_ost, b.d_seeds, b.d_bid, b.d_desc, b.d_bb, b.d_eb, K, b.nbuckets, b.d_tab, b.stride};
-    k_ef_fill<<<grid_for(b.nbuckets + K, kBlock), kBlock, 0, s>>>(fa);
-    k_tree_bits<<<grid_for(b.nbuckets * kTreeLanes, kBlock), kBlock, 0, s>>>(fa);
+    RS_LAUNCH(k_set_blobs, grid_for(K, kBlock), kBlock, 0, s, b.d_desc, K, (unsigned long long*)arena, b.d_boff,
+              capacity, &b.d_st->flags);
+    if (arena && clear_words)
+        RS_LAUNCH(k_fill_u64, grid_for(clear_words, kBlock * 8), kBlock, 0, s, arena, clear_words, 0);
+    RS_LAUNCH(k_write_headers, grid_for((uint64_t)K * kHeaderWords, kBlock), kBlock, 0, s, b.d_desc, b.d_hdr, K);
+    FillArgs fa{b.d_bst, b.d_ost, b.d_seeds, b.d_bid, b.d_desc, b.d_bb, b.d_eb, K, b.nbuckets, b.d_tab, b.stride, 0};
+    RS_LAUNCH(k_ef_fill, grid_for(b.nbuckets + K, kBlock), kBlock, 0, s, fa);
+    // kTreeLanes lanes per bucket, in launches of at most max_grid_blocks() blocks
+    if (int rc = for_each_chunk(b.nbuckets, kBlock, kBlock / kTreeLanes, [&](uint64_t g0, uint64_t, uint64_t blocks) -> int {
+            fa.g0 = g0;
+            RS_LAUNCH(k_tree_bits, blocks, kBlock, 0, s, fa);
+            return RS_OK;
+        }))
+        return rc;
     RS_ENQ(hipGetLastError());
     return RS_OK;
 }
@@ -2122,13 +2225,14 @@ void collect_status(Batch& b) {
 
 // Blob objects of the successful builds over `words` (the arena, laid out at
 // h_boff) and `tables`; the arena is freed with the last of them.
-void make_blobs(Batch& b, uint64_t* words, uint32_t* tables, uint32_t stride, hipStream_t s, rs_blob** outs) {
+void make_blobs(Batch& b, uint64_t* words, uint32_t* tables, uint32_t stride, const Alloc& al, hipStream_t s,
+                rs_blob** outs) {
     uint32_t made = 0;
     for (uint32_t j = 0; j < b.K; j++) made += b.st[b.which[j]] == RS_OK;
     for (uint32_t c = 0; c < b.count; c++) outs[c] = nullptr;
     if (!made) {
-        dev_free(words, s);
-        dev_free(tables, s);
+        al.put(words, s);
+        al.put(tables, s);
         return;
     }
     BlobArena* arena = new (std::nothrow) BlobArena;
@@ -2138,12 +2242,13 @@ void make_blobs(Batch& b, uint64_t* words, uint32_t* tables, uint32_t stride, hi
                 b.st[b.which[j]] = RS_ENOMEM;
                 b.why[b.which[j]] = "host allocation failed";
             }
-        dev_free(words, s);
-        dev_free(tables, s);
+        al.put(words, s);
+        al.put(tables, s);
         return;
     }
     arena->words = words;
     arena->tables = tables;
+    arena->al = al;
     arena->refs = (int)made;
     if (hipEventCreateWithFlags(&arena->ready, hipEventDisableTiming) != hipSuccess ||
         hipEventRecord(arena->ready, s) != hipSuccess) {
@@ -2188,15 +2293,16 @@ int build_batch_impl(const rs_keys* sets, uint32_t count, const uint32_t* leafs,
     PhaseEvents pe;
     if (int rc0 = pe.create(timing)) return rc0;
 
+    const Alloc al = current_alloc();
     char* ws = nullptr;
-    if (int rc0 = dev_alloc((void**)&ws, b.ws_bytes, s)) return rc0;
+    if (int rc0 = al.get((void**)&ws, b.ws_bytes, s)) return rc0;
     uint64_t* d_blob = nullptr;
     auto cleanup = [&](int code) {
         pinned_release(s);
-        dev_free(ws, s);
+        al.put(ws, s);
         if (code != RS_OK) {
-            dev_free(b.d_tab, s);
-            dev_free(d_blob, s);
+            al.put(b.d_tab, s);
+            al.put(d_blob, s);
         }
         return code;
     };
@@ -2216,12 +2322,12 @@ int build_batch_impl(const rs_keys* sets, uint32_t count, const uint32_t* leafs,
     RS_TRY(hipStreamSynchronize(s));
     const uint32_t maxm = b.h_st->maxm;
     RS_TRACE("largest bucket %u", maxm);
-    if (int rc = dev_alloc((void**)&b.d_tab, table_words(b, maxm) * 4, s)) return cleanup(rc);
+    if (int rc = al.get((void**)&b.d_tab, table_words(b, maxm) * 4, s)) return cleanup(rc);
     if (int rc = upload_batch_tables(b, maxm, s)) return cleanup(rc);
     if (tune) {  // calibration only: no blob, the tables are not handed to an arena
         tune->buckets = b.nbuckets;
         const int trc = tune_search(*tune, b.max_leaf, b.h_desc, b.d_desc, search_args(b), b.lds, s);
-        dev_free(b.d_tab, s);
+        al.put(b.d_tab, s);
         b.d_tab = nullptr;
         return cleanup(trc);
     }
@@ -2233,8 +2339,8 @@ int build_batch_impl(const rs_keys* sets, uint32_t count, const uint32_t* leafs,
     const uint64_t arena_words = b.h_boff[b.K];
     RS_TRACE("sizes known (%llu blob words)", (unsigned long long)arena_words);
     if (arena_words) {
-        if (int rc = dev_alloc((void**)&d_blob, arena_words * 8, s)) return cleanup(rc);
-        if (int rc = enqueue_fill(b, d_blob, arena_words, s)) return cleanup(rc);
+        if (int rc = al.get((void**)&d_blob, arena_words * 8, s)) return cleanup(rc);
+        if (int rc = enqueue_fill(b, d_blob, arena_words, arena_words, s)) return cleanup(rc);
     }
     pe.record(6, s);
     if (timing) {
@@ -2253,9 +2359,9 @@ int build_batch_impl(const rs_keys* sets, uint32_t count, const uint32_t* leafs,
         g_stats.blob_bytes = arena_words * 8;
         g_stats_valid = true;
     }
-    make_blobs(b, d_blob, b.d_tab, b.stride, s, outs);
+    make_blobs(b, d_blob, b.d_tab, b.stride, al, s, outs);
     pinned_release(s);
-    dev_free(ws, s);
+    al.put(ws, s);
     return batch_finish(b, statuses, RS_OK);
 #undef RS_TRY
 }
@@ -2286,6 +2392,7 @@ struct rs_plan {
     hipEvent_t done = nullptr;  // the last run's copies out of the arena
     bool done_pending = false;
     uint64_t runs = 0, fallbacks = 0;
+    rs::Alloc al;  // device memory of the plan and of the blobs its runs return
 };
 
 namespace rs {
@@ -2297,9 +2404,9 @@ void plan_release(rs_plan* p) {
     if (p->graph) (void)hipGraphDestroy(p->graph);
     if (p->done) (void)hipEventDestroy(p->done);
     if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
-    if (p->ws) (void)hipFree(p->ws);
-    if (p->b.d_tab) (void)hipFree(p->b.d_tab);
-    if (p->arena) (void)hipFree(p->arena);
+    p->al.put_idle(p->ws);
+    p->al.put_idle(p->b.d_tab);
+    p->al.put_idle(p->arena);
     if (p->pin) (void)hipHostFree(p->pin);
     delete p;
 }
@@ -2377,7 +2484,11 @@ extern "C" int rs_plan_create(const rs_keys* sets, uint32_t count, const uint32_
     };
     if ((rc = rs::batch_prepare(b, sets, count, leaf, bucket, &o))) return bail(rc);
     if ((rc = rs::batch_layout(b))) return bail(rc);
-    if (hipMalloc((void**)&p->ws, b.ws_bytes) != hipSuccess) return bail(rs::fail(RS_ENOMEM, "device allocation failed"));
+    p->al = rs::current_alloc();
+    if (hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&p->done, hipEventDisableTiming) != hipSuccess)
+        return bail(rs::fail(RS_EDEVICE, "stream or event creation failed"));
+    if ((rc = p->al.get((void**)&p->ws, b.ws_bytes, p->cap_stream))) return bail(rc);
     if (hipHostMalloc((void**)&p->pin, b.pin_bytes, hipHostMallocDefault) != hipSuccess) {
         p->pin = nullptr;
         return bail(rs::fail(RS_ENOMEM, "pinned host allocation failed"));
@@ -2389,12 +2500,9 @@ extern "C" int rs_plan_create(const rs_keys* sets, uint32_t count, const uint32_
     p->maxm_cap = std::min(maxm0 + margin, rs::lds_bucket_limit(b));
     if (p->maxm_cap < maxm0) return bail(rs::fail(RS_EINVAL, "largest bucket exceeds the local data share"));
     p->capacity = words0 + words0 / 8 + 64ull * b.K + 1024;
-    if (hipMalloc((void**)&b.d_tab, rs::table_words(b, p->maxm_cap) * 4) != hipSuccess ||
-        hipMalloc((void**)&p->arena, p->capacity * 8) != hipSuccess)
-        return bail(rs::fail(RS_ENOMEM, "device allocation failed"));
-    if (hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&p->done, hipEventDisableTiming) != hipSuccess)
-        return bail(rs::fail(RS_EDEVICE, "stream or event creation failed"));
+    if ((rc = p->al.get((void**)&b.d_tab, rs::table_words(b, p->maxm_cap) * 4, p->cap_stream)) ||
+        (rc = p->al.get((void**)&p->arena, p->capacity * 8, p->cap_stream)))
+        return bail(rc);
     if ((rc = rs::upload_batch_tables(b, p->maxm_cap, p->cap_stream))) return bail(rc);
     if (hipStreamSynchronize(p->cap_stream) != hipSuccess) return bail(rs::fail(RS_EDEVICE, "table upload failed"));
     // capture: every phase, no host read in between
@@ -2402,7 +2510,7 @@ extern "C" int rs_plan_create(const rs_keys* sets, uint32_t count, const uint32_
         return bail(rs::fail(RS_EDEVICE, "hipStreamBeginCapture failed"));
     int crc = rs::enqueue_front(b, p->cap_stream, nullptr);
     if (!crc) crc = rs::enqueue_back(b, p->cap_stream, nullptr);
-    if (!crc) crc = rs::enqueue_fill(b, p->arena, p->capacity, p->cap_stream);
+    if (!crc) crc = rs::enqueue_fill(b, p->arena, p->capacity, p->capacity, p->cap_stream);
     if (!crc) crc = rs::enqueue_readback(b, p->cap_stream);
     const hipError_t ec = hipStreamEndCapture(p->cap_stream, &p->graph);
     if (crc) return bail(crc);
@@ -2445,8 +2553,8 @@ extern "C" int rs_plan_run(rs_plan* p, void* stream, rs_blob** outs, int* per_bu
     const size_t tab_words = rs::table_words(b, b.table_maxm);
     int rc = RS_OK;
     if (words) {
-        if ((rc = rs::dev_alloc((void**)&dst, words * 8, s)) || (rc = rs::dev_alloc((void**)&tab, tab_words * 4, s))) {
-            rs::dev_free(dst, s);
+        if ((rc = p->al.get((void**)&dst, words * 8, s)) || (rc = p->al.get((void**)&tab, tab_words * 4, s))) {
+            p->al.put(dst, s);
             b.st = st0;
             b.why = why0;
             return rc;
@@ -2456,7 +2564,7 @@ extern "C" int rs_plan_run(rs_plan* p, void* stream, rs_blob** outs, int* per_bu
         RS_HIP(hipEventRecord(p->done, s));
         p->done_pending = true;
     }
-    rs::make_blobs(b, dst, tab, b.stride, s, outs);
+    rs::make_blobs(b, dst, tab, b.stride, p->al, s, outs);
     rc = rs::batch_finish(b, per_build_status, RS_OK);
     b.st = st0;
     b.why = why0;
@@ -2520,18 +2628,23 @@ __global__ void k_synth_keys(uint64_t* out, uint64_t n, uint64_t seed) {
 }
 
 int tune_on_sample(uint32_t leaf, uint32_t bucket, uint64_t n, hipStream_t s, TuneCtx& t) {
+    const Alloc al = current_alloc();
     uint64_t* keys = nullptr;
-    if (int rc = dev_alloc((void**)&keys, n * 8, s)) return rc;
-    k_synth_keys<<<(uint32_t)((n + kBlock - 1) / kBlock), kBlock, 0, s>>>(keys, n, 0x5eed5eed5eed5eedull + leaf);
+    if (int rc = al.get((void**)&keys, n * 8, s)) return rc;
+    if (!grid_fits(grid_for(n, kBlock), kBlock)) {
+        al.put(keys, s);
+        return fail(RS_EINVAL, "calibration set too large");
+    }
+    k_synth_keys<<<(uint32_t)grid_for(n, kBlock), kBlock, 0, s>>>(keys, n, 0x5eed5eed5eed5eedull + leaf);
     if (hipGetLastError() != hipSuccess) {
-        dev_free(keys, s);
+        al.put(keys, s);
         return fail(RS_EDEVICE, "calibration key launch failed");
     }
     rs_keys k{RS_KEYS_U64, keys, nullptr, n};
     rs_blob* unused = nullptr;
     int status = RS_OK;
     int rc = build_batch_impl(&k, 1, &leaf, &bucket, nullptr, s, &unused, &status, &t);
-    dev_free(keys, s);
+    al.put(keys, s);
     return rc;
 }
 

@@ -8,9 +8,29 @@
 #include <cstdio>
 #include <string>
 
+#include "launch.h"
 #include "rs_internal.h"
 
 namespace rs {
+
+// Device memory of the library: the caller's allocator (rs_set_allocator) or,
+// by default, stream-ordered hipMallocAsync / hipFreeAsync.  Every owner of
+// device memory (a call's workspace, a blob arena, a plan) keeps the Alloc
+// that made it and frees through it, so the process-wide choice may change
+// while older memory is alive.
+struct Alloc {
+    rs_alloc_fn alloc = nullptr;  // null: the default
+    rs_free_fn release = nullptr;
+    void* ctx = nullptr;
+    // bytes (at least 256) for use on stream s; RS_ENOMEM or RS_EDEVICE on failure
+    int get(void** p, size_t bytes, hipStream_t s) const;
+    // return p after the work enqueued so far on s (null p is ignored)
+    void put(void* p, hipStream_t s) const;
+    // return p that no stream uses any more
+    void put_idle(void* p) const;
+};
+Alloc current_alloc();
+
 struct BlobArena;
 void release_arena(BlobArena* a);
 }  // namespace rs
@@ -24,6 +44,7 @@ struct rs_blob {
     hipEvent_t ready = nullptr;      // recorded after the last write of the blob (shared with the arena)
     int device = 0;
     rs::BlobArena* arena = nullptr;  // shared with the other blobs of one build call (null: own memory)
+    rs::Alloc al;                    // frees words and tables when the blob owns them
 };
 
 namespace rs {
@@ -32,9 +53,6 @@ namespace rs {
 int fail(int code, const char* fmt, ...);
 void clear_error();
 
-// Stream-ordered device allocation used for every buffer of the library.
-int dev_alloc(void** p, size_t bytes, hipStream_t s);
-void dev_free(void* p, hipStream_t s);
 
 // Blob geometry decoded from a header.
 struct Layout {

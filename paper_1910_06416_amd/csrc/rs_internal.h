@@ -108,6 +108,9 @@ struct TableView {
 };
 constexpr int kTableCount = 4;
 TableView host_tables(uint32_t leaf, uint32_t maxm);
+// The same four tables for sizes 0..maxm written into dst (kTableCount *
+// (maxm + 1) words, r then F then N then G), without any allocation.
+void fill_tables(uint32_t leaf, uint32_t maxm, uint32_t* dst);
 
 // ---------------------------------------------------------------------------
 // Device helpers.

@@ -100,6 +100,10 @@ void fill(const Strategy& st, uint32_t cap, uint32_t* r, uint32_t* F, uint32_t* 
 
 }  // namespace
 
+void fill_tables(uint32_t leaf, uint32_t maxm, uint32_t* dst) {
+    fill(make_strategy(leaf), maxm, dst, dst + maxm + 1, dst + 2 * (maxm + 1), dst + 3 * (maxm + 1));
+}
+
 TableView host_tables(uint32_t leaf, uint32_t maxm) {
     std::lock_guard<std::mutex> lock(g_mu);
     LeafTables& t = g_cache[leaf];

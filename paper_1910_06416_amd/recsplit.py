@@ -19,6 +19,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "librecsplit.so")
+TORCH_ALLOC_PATH = os.path.join(HERE, "libtorchalloc.so")
 
 RS_OK, RS_EINVAL, RS_EDUPLICATE, RS_ENOMEM, RS_EDEVICE, RS_ESEARCH, RS_EFORMAT, RS_EBUSY = range(8)
 RS_KEYS_U64, RS_KEYS_BYTES = 1, 2
@@ -39,7 +40,8 @@ class rs_keys(ctypes.Structure):
 
 class rs_options(ctypes.Structure):
     _fields_ = [("seed_cap", ctypes.c_uint64), ("flags", ctypes.c_uint32), ("stage_from", ctypes.c_uint32),
-                ("group_max", ctypes.c_uint32), ("waves", ctypes.c_uint32), ("reserved", ctypes.c_uint32 * 2)]
+                ("group_max", ctypes.c_uint32), ("waves", ctypes.c_uint32), ("wait_limit", ctypes.c_uint32),
+                ("reserved", ctypes.c_uint32)]
 
 
 RS_OPT_TIMING, RS_OPT_TUNED = 1, 2
@@ -127,13 +129,53 @@ def lib() -> ctypes.CDLL:
                                    ctypes.POINTER(U64)]
         L.rs_plan_destroy.argtypes = [P]
         L.rs_plan_destroy.restype = None
+        L.rs_set_allocator.argtypes = [P, P, P]
         for f in ("rs_build", "rs_build_ex", "rs_lookup", "rs_blob_to_host", "rs_blob_from_host", "rs_blob_info",
                   "rs_tables", "rs_last_build_stats", "rs_build_batch", "rs_server_create", "rs_server_create_ex", "rs_server_submit_build",
                   "rs_server_submit_lookup", "rs_server_poll", "rs_server_wait", "rs_server_get_stats", "rs_autotune",
-                  "rs_schedule_get", "rs_schedule_set", "rs_plan_create", "rs_plan_run", "rs_plan_info"):
+                  "rs_schedule_get", "rs_schedule_set", "rs_plan_create", "rs_plan_run", "rs_plan_info",
+                  "rs_set_allocator"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
+        use_torch_allocator()
     return _lib
+
+
+_torch_alloc = None
+
+
+def use_torch_allocator():
+    """Give the library's device memory to PyTorch's caching allocator (the
+    default of this binding): workspaces and blobs then come from torch's pool
+    and count in torch.cuda.memory_allocated().  The allocation functions are
+    native (libtorchalloc.so), so no Python runs per allocation."""
+    global _torch_alloc
+    import torch
+
+    if torch.cuda.is_available():
+        torch.cuda.init()  # the caching allocator serves devices only after torch's lazy init
+    if _torch_alloc is None:
+        if not os.path.exists(TORCH_ALLOC_PATH):
+            raise RuntimeError(f"{TORCH_ALLOC_PATH} is not built; run __graft_entry__.build() first")
+        _torch_alloc = ctypes.CDLL(TORCH_ALLOC_PATH)
+    alloc = ctypes.cast(_torch_alloc.rs_torch_alloc, ctypes.c_void_p)
+    free = ctypes.cast(_torch_alloc.rs_torch_free, ctypes.c_void_p)
+    _check(lib().rs_set_allocator(alloc, free, None))
+
+
+def use_default_allocator():
+    """The library's own stream-ordered hipMallocAsync / hipFreeAsync."""
+    _check(lib().rs_set_allocator(None, None, None))
+
+
+def set_allocator(alloc, free, ctx=None):
+    """Install an allocator given as ctypes function pointers matching
+    rs_alloc_fn / rs_free_fn (the caller keeps them alive)."""
+    _check(lib().rs_set_allocator(ctypes.cast(alloc, ctypes.c_void_p), ctypes.cast(free, ctypes.c_void_p), ctx))
+
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
 
 
 def _check(rc: int):
@@ -210,21 +252,21 @@ class Blob:
             pass
 
 
-def _options(seed_cap=0, timing=False, tuned=False, stage_from=0, group_max=0, waves=0) -> rs_options:
+def _options(seed_cap=0, timing=False, tuned=False, stage_from=0, group_max=0, waves=0, wait_limit=0) -> rs_options:
     flags = (RS_OPT_TIMING if timing else 0) | (RS_OPT_TUNED if tuned else 0)
-    return rs_options(seed_cap, flags, stage_from, group_max, waves)
+    return rs_options(seed_cap, flags, stage_from, group_max, waves, wait_limit)
 
 
 def build(keys, leaf: int, bucket: int, seed_cap: int = 0, timing: bool = False, stage_from: int = 0,
-          group_max: int = 0, waves: int = 0, tuned: bool = False, stream=None) -> Blob:
+          group_max: int = 0, waves: int = 0, tuned: bool = False, wait_limit: int = 0, stream=None) -> Blob:
     """Build the minimal perfect hash function of a device key set.  With
     timing=True the per-phase device times are available from last_build_stats().
     tuned=True takes the search schedule of (leaf, bucket) from the schedule
     table (see autotune); stage_from / group_max / waves override it.  Schedules
-    never change the result."""
+    never change the result.  wait_limit is rs_options.wait_limit."""
     k = _as_keys(keys)
     h = ctypes.c_void_p()
-    opts = _options(seed_cap, timing, tuned, stage_from, group_max, waves)
+    opts = _options(seed_cap, timing, tuned, stage_from, group_max, waves, wait_limit)
     _check(lib().rs_build_ex(ctypes.byref(k), leaf, bucket, ctypes.byref(opts), _stream(stream), ctypes.byref(h)))
     return Blob(h)
 

@@ -114,3 +114,18 @@ def test_too_many_buckets_is_refused_before_any_device_work(lib):
     assert lib.rs_build(ctypes.byref(keys), 8, 1, None, ctypes.byref(out)) == recsplit.RS_EINVAL
     assert b"too many buckets" in lib.rs_last_error()
     assert out.value is None
+
+
+def test_set_allocator_validation_without_device(lib):
+    """rs_set_allocator takes both functions or neither; no device is needed."""
+    from paper_1910_06416_amd import recsplit
+
+    fake = ctypes.c_void_p(0x1000)
+    assert lib.rs_set_allocator(fake, None, None) == recsplit.RS_EINVAL
+    assert lib.rs_set_allocator(None, fake, None) == recsplit.RS_EINVAL
+    assert b"neither" in lib.rs_last_error()
+    assert lib.rs_set_allocator(None, None, None) == recsplit.RS_OK
+    # the binding's default: PyTorch's caching allocator through the native shim
+    recsplit.use_torch_allocator()
+    assert lib.rs_set_allocator(None, None, None) == recsplit.RS_OK
+    recsplit.use_torch_allocator()

@@ -1,0 +1,158 @@
+"""GPU edge cases: repeated keys, the search's progress-based waits, grids that
+need several launches, and split nodes at leaf sizes 17-24.
+
+* Keys repeated more than a split part holds can never be split; the build
+  must end with RS_EDUPLICATE (as the oracle does), not search forever.
+* A wavefront waiting for a node waits while the bucket's other wavefronts
+  report progress; a tiny wait limit forces the error path, and every kernel
+  still exits.
+* 2e7 buckets of four wavefronts are 5.1e9 work-items: the search is launched
+  in two chunks.  Elias-Fano lists of every bucket, buckets at the chunk
+  boundary and the bijection are checked against the oracle.
+* Leaf sizes 17-24 with split nodes (packed counters, 8 thresholds) against
+  stored oracle structures (tests/golden/large_leaf_blobs.txt).
+"""
+import os
+
+import numpy as np
+import pytest
+
+from paper_1910_06416_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "large_leaf_blobs.txt")
+
+
+@pytest.fixture(scope="module")
+def rs():
+    import torch
+
+    assert torch.cuda.is_available()
+    from paper_1910_06416_amd import recsplit
+
+    recsplit.lib()
+    return recsplit
+
+
+def _is_permutation(ranks) -> bool:
+    import torch
+
+    srt, _ = torch.sort(ranks)
+    return bool(torch.equal(srt, torch.arange(ranks.numel(), dtype=torch.int64, device=ranks.device)))
+
+
+@pytest.mark.parametrize("leaf,copies,bucket", [(1, 2, 10), (1, 3, 10), (2, 3, 10), (2, 5, 100), (8, 9, 100),
+                                                (8, 3, 100), (8, 40, 100), (5, 40, 100), (12, 13, 1000),
+                                                (16, 17, 2000)])
+def test_repeated_keys_fail_with_duplicate(rs, orc, leaf, copies, bucket):
+    """copies equal keys among distinct ones: more copies than l never fit a
+    leaf, so some split can never succeed; the build must stop with
+    RS_EDUPLICATE like the oracle."""
+    base = inputs.u64_keys(2000, 60 + leaf + copies)
+    keys = np.concatenate([base, np.repeat(base[7:8], copies - 1)])
+    print(f"case repeated key leaf={leaf} copies={copies} bucket={bucket}", flush=True)
+    with pytest.raises(orc.OracleError) as oe:
+        orc.build(keys, leaf, bucket)
+    assert oe.value.code == orc.EDUPLICATE
+    for waves in (1, 4):
+        with pytest.raises(rs.RecSplitError) as e:
+            rs.build(rs.device_keys(keys), leaf, bucket, waves=waves)
+        assert e.value.code == rs.RS_EDUPLICATE, (waves, str(e.value))
+    # the library still builds afterwards
+    assert rs.build(rs.device_keys(base), leaf, bucket).to_bytes() == orc.build(base, leaf, bucket)
+
+
+def test_repeated_keys_in_a_batch(rs, orc):
+    good = inputs.u64_keys(5000, 81)
+    bad = np.concatenate([inputs.u64_keys(3000, 82), np.repeat(inputs.u64_keys(3000, 82)[:1], 20)])
+    print("case repeated keys in a batch", flush=True)
+    blobs, status = rs.build_batch([rs.device_keys(good), rs.device_keys(bad), rs.device_keys(good)], [8, 8, 12],
+                                   [100, 100, 1000])
+    assert status == [rs.RS_OK, rs.RS_EDUPLICATE, rs.RS_OK]
+    assert blobs[0].to_bytes() == orc.build(good, 8, 100)
+    assert blobs[2].to_bytes() == orc.build(good, 12, 1000)
+
+
+def test_tiny_wait_limit_reports_scheduling_error_and_exits(rs, orc):
+    """Four wavefronts per bucket; the root split is still being searched when
+    the other three claim its children's slots.  With a wait limit of one sleep
+    and no progress report yet, they give up: the build fails cleanly with
+    RS_EDEVICE (every wavefront leaves the kernel), and the next build works."""
+    keys = inputs.u64_keys(5000, 83)
+    print("case wait limit 1", flush=True)
+    with pytest.raises(rs.RecSplitError) as e:
+        rs.build(rs.device_keys(keys), 8, 1000, waves=4, wait_limit=1)
+    assert e.value.code == rs.RS_EDEVICE and "scheduling" in str(e.value)
+    assert rs.build(rs.device_keys(keys), 8, 1000, waves=4).to_bytes() == orc.build(keys, 8, 1000)
+
+
+def test_search_in_several_launches_2e7_buckets(rs, orc):
+    """l=12, b=1, 2e7 keys: 2e7 buckets, four wavefronts each (the built-in
+    schedule at l=12), so the search runs as two launches (16,777,215 buckets
+    in the first).  Every bucket's s_i, the total tree bits, buckets at the
+    chunk boundary and the bijection are checked."""
+    n, leaf, bucket = 20_000_000, 12, 1
+    print(f"case chunked search n={n} leaf={leaf} bucket={bucket}", flush=True)
+    keys = inputs.u64_keys(n, 84)
+    dkeys = rs.device_keys(keys)
+    blob = rs.build(dkeys, leaf, bucket)
+    got = blob.to_bytes()
+    h = orc.header(got)
+    sizes = orc.bucket_sizes(keys, n)
+    assert (h["n"], h["nb"], h["maxm"]) == (n, n, int(sizes.max()))
+    s_all, o_all = orc.blob_prefix(got)
+    assert np.array_equal(s_all, np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64))
+    assert o_all[-1] == h["tree_bits"]
+    ranks = rs.lookup(blob, dkeys)
+    assert _is_permutation(ranks)
+    per = (2**32 - 1) // 256
+    nonempty = np.flatnonzero(sizes >= 2)
+    near = nonempty[np.searchsorted(nonempty, per) - 3: np.searchsorted(nonempty, per) + 3]
+    picks = sorted(set([int(np.argmax(sizes)), per - 1, per, per + 1, n - 1] + near.tolist()))
+    r, _, _ = orc.tables(leaf, h["maxm"])
+    for i in picks:
+        s_i, _, v, m = orc.blob_bucket(got, i)
+        idx = orc.bucket_members(keys, n, i)
+        _, lo = orc.fingerprint(keys[idx])
+        tv, tm, _ = orc.tree(np.sort(lo), leaf)
+        assert np.array_equal(m, tm) and np.array_equal(v, tv), f"bucket {i}"
+        bits = sum(int(r[mm]) + (int(vv) >> int(r[mm])) + 1 for vv, mm in zip(v, m))
+        assert int(o_all[i + 1] - o_all[i]) == bits, f"bucket {i}"
+        want = orc.bucket_ranks(lo, leaf) + np.uint64(s_i)
+        import torch
+
+        got_r = ranks[torch.from_numpy(idx.astype(np.int64)).cuda()].cpu().numpy().view(np.uint64)
+        assert np.array_equal(got_r, want), f"bucket {i}"
+
+
+def _golden_large_leaves():
+    rows = []
+    if not os.path.exists(GOLDEN):
+        return [pytest.param(None, marks=pytest.mark.skip(reason="run tests/golden/make_large_leaf_blobs.py"))]
+    with open(GOLDEN) as f:
+        for line in f:
+            if line.startswith("#") or not line.strip():
+                continue
+            leaf, bucket, n, seed, hx = line.split()
+            rows.append((int(leaf), int(bucket), int(n), int(seed), bytes.fromhex(hx)))
+    return rows
+
+
+@pytest.mark.parametrize("row", _golden_large_leaves(), ids=lambda r: f"l{r[0]}_b{r[1]}_n{r[2]}" if r else "none")
+def test_split_nodes_at_large_leaf_sizes(rs, orc, row):
+    """Blobs at l = 18, 20, 22, 24 with split nodes equal the stored oracle
+    structures, under the built-in schedule (four wavefronts, so waits through
+    searches of many seconds) and with one wavefront per bucket."""
+    leaf, bucket, n, seed, want = row
+    keys = inputs.u64_keys(n, seed)
+    h = orc.header(want)
+    assert (h["n"], h["leaf"], h["bucket"]) == (n, leaf, bucket)
+    dk = rs.device_keys(keys)
+    for waves in (0, 1):
+        print(f"case large leaf l={leaf} b={bucket} n={n} waves={waves}", flush=True)
+        blob = rs.build(dk, leaf, bucket, waves=waves)
+        assert blob.to_bytes() == want, (leaf, bucket, n, waves)
+        ranks = rs.lookup(blob, dk)
+        assert np.array_equal(ranks.cpu().numpy().view(np.uint64), orc.lookup(want, keys))
+        assert _is_permutation(ranks)
