@@ -83,8 +83,12 @@ def _declare(L):
     L.orc_inventory_build.restype = None
     L.orc_inventory_select.argtypes = [P, P, P, U32, U64]
     L.orc_inventory_select.restype = U64
+    L.orc_trees.argtypes = [P, P, U64, U64, U32, U64, P, P, P, P]
+    L.orc_build_with_trees.argtypes = [U32, P, P, U64, U32, U32, P, P, P, P, U64, P]
+    L.orc_bucket_layout.argtypes = [U32, P, P, U64, U64, P, P]
     for f in ("orc_tables", "orc_tree", "orc_build", "orc_lookup", "orc_bucket_sizes", "orc_blob_bucket",
-              "orc_bucket_ranks", "orc_blob_prefix", "orc_blob_check_inventory"):
+              "orc_bucket_ranks", "orc_blob_prefix", "orc_blob_check_inventory", "orc_trees",
+              "orc_build_with_trees", "orc_bucket_layout"):
         getattr(L, f).restype = ctypes.c_int
 
 
@@ -180,6 +184,57 @@ def build(keys, leaf: int, bucket: int, seed_cap: int = 0) -> bytes:
     rc = lib().orc_build(kind, _ptr(data), op, n, leaf, bucket, seed_cap, _ptr(out), size.value, ctypes.byref(size))
     if rc:
         raise OracleError(rc, "build")
+    return out.tobytes()
+
+
+def bucket_layout(keys, nb: int):
+    """(sorted, s): the lower signature words in bucket order (each bucket
+    ascending) and the nb+1 prefix sums of the bucket sizes."""
+    kind, data, offs, n = _keys(keys)
+    srt = np.zeros(max(n, 1), dtype=np.uint64)
+    s_ = np.zeros(nb + 1, dtype=np.uint64)
+    rc = lib().orc_bucket_layout(kind, _ptr(data), _ptr(offs) if offs is not None else None, n, nb, _ptr(srt),
+                                 _ptr(s_))
+    if rc:
+        raise OracleError(rc, "bucket_layout")
+    return srt[:n], s_
+
+
+def trees(sorted_lo: np.ndarray, s_: np.ndarray, first: int, last: int, leaf: int, seed_cap: int = 0):
+    """Trees of buckets [first, last) of a bucket layout: (node_v, node_m,
+    node_count), node arrays of the layout's length (bucket i's coded nodes
+    from slot s_i on; other slots untouched) and counts for all buckets."""
+    sorted_lo = np.ascontiguousarray(sorted_lo, dtype=np.uint64)
+    s_ = np.ascontiguousarray(s_, dtype=np.uint64)
+    n = max(len(sorted_lo), 1)
+    v = np.zeros(n, dtype=np.uint64)
+    m = np.zeros(n, dtype=np.uint32)
+    d = np.zeros(n, dtype=np.uint32)
+    cnt = np.zeros(max(len(s_) - 1, 1), dtype=np.uint64)
+    src = sorted_lo if len(sorted_lo) else np.zeros(1, np.uint64)
+    rc = lib().orc_trees(_ptr(src), _ptr(s_), first, last, leaf, seed_cap, _ptr(v), _ptr(m), _ptr(d), _ptr(cnt))
+    if rc:
+        raise OracleError(rc, "trees")
+    return v, m, cnt
+
+
+def build_with_trees(keys, leaf: int, bucket: int, node_v, node_m, node_count) -> bytes:
+    """The serialized structure from trees computed elsewhere (same bytes as
+    build() when the trees are the oracle's)."""
+    kind, data, offs, n = _keys(keys)
+    node_v = np.ascontiguousarray(node_v, dtype=np.uint64)
+    node_m = np.ascontiguousarray(node_m, dtype=np.uint32)
+    node_count = np.ascontiguousarray(node_count, dtype=np.uint64)
+    size = U64()
+    op = _ptr(offs) if offs is not None else None
+    args = (kind, _ptr(data), op, n, leaf, bucket, _ptr(node_v), _ptr(node_m), _ptr(node_count))
+    rc = lib().orc_build_with_trees(*args, None, 0, ctypes.byref(size))
+    if rc:
+        raise OracleError(rc, "build_with_trees")
+    out = np.zeros(size.value, dtype=np.uint8)
+    rc = lib().orc_build_with_trees(*args, _ptr(out), size.value, ctypes.byref(size))
+    if rc:
+        raise OracleError(rc, "build_with_trees")
     return out.tobytes()
 
 

@@ -345,6 +345,33 @@ int orc_tree(const uint64_t* lo, uint32_t m, uint32_t leaf, uint64_t seed_cap, u
     return rc;
 }
 
+/* Trees of buckets first..last-1 of a bucket-contiguous array of lower words
+ * (bucket i holds sorted[s[i] .. s[i+1])).  Bucket i's coded nodes go to
+ * node_v / node_m / node_d from slot s[i] on (a tree on m keys has at most m-1
+ * coded nodes) and their count to node_count[i].  This is the tree loop of
+ * orc_build; a test harness may run disjoint bucket ranges in separate
+ * processes and pass the results to orc_build_with_trees. */
+int orc_trees(const uint64_t* sorted, const uint64_t* s, uint64_t first, uint64_t last, uint32_t leaf,
+              uint64_t seed_cap, uint64_t* node_v, uint32_t* node_m, uint32_t* node_d, uint64_t* node_count) {
+    if (leaf < 1 || leaf > 24) return ORC_EINVAL;
+    strategy st = make_strategy(leaf);
+    if (!seed_cap) seed_cap = ORC_DEFAULT_SEED_CAP;
+    for (uint64_t i = first; i < last; i++) {
+        uint64_t m = s[i + 1] - s[i];
+        uint64_t* keys = malloc((m ? m : 1) * 8);
+        uint64_t* scratch = malloc((m ? m : 1) * 8);
+        if (!keys || !scratch) { free(keys); free(scratch); return ORC_ENOMEM; }
+        memcpy(keys, sorted + s[i], m * 8);
+        emitter e = {node_v + s[i], node_m + s[i], node_d + s[i], 0, seed_cap, scratch};
+        int rc = build_tree(&st, keys, (uint32_t)m, 0, &e);
+        free(keys);
+        free(scratch);
+        if (rc) return rc;
+        node_count[i] = e.count;
+    }
+    return ORC_OK;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Bit arrays: bit p lives in word p/64 at bit p%64 (LSB-first).             */
 /* ------------------------------------------------------------------------ */
@@ -422,8 +449,9 @@ static uint32_t ef_width(uint64_t N, uint64_t U) {
 /* The blob is written to out (capacity cap bytes); *size receives its size;  */
 /* if cap is too small only the size is reported.                            */
 /* ------------------------------------------------------------------------ */
-int orc_build(uint32_t kind, const void* data, const uint64_t* offsets, uint64_t n, uint32_t leaf, uint32_t bucket,
-              uint64_t seed_cap, void* out, uint64_t cap, uint64_t* size) {
+static int build_impl(uint32_t kind, const void* data, const uint64_t* offsets, uint64_t n, uint32_t leaf,
+                      uint32_t bucket, uint64_t seed_cap, const uint64_t* given_v, const uint32_t* given_m,
+                      const uint64_t* given_count, void* out, uint64_t cap, uint64_t* size) {
     if (n == 0 || leaf < 1 || leaf > 24 || bucket == 0 || !data || !size) return ORC_EINVAL;
     if (kind != ORC_KEYS_U64 && kind != ORC_KEYS_BYTES) return ORC_EINVAL;
     if (kind == ORC_KEYS_BYTES) {
@@ -432,7 +460,6 @@ int orc_build(uint32_t kind, const void* data, const uint64_t* offsets, uint64_t
             if (offsets[i + 1] < offsets[i]) return ORC_EINVAL;
     }
     if (!seed_cap) seed_cap = ORC_DEFAULT_SEED_CAP;
-    strategy st = make_strategy(leaf);
     uint64_t nb = (n + bucket - 1) / bucket;
     int rc = ORC_ENOMEM;
 
@@ -441,11 +468,10 @@ int orc_build(uint32_t kind, const void* data, const uint64_t* offsets, uint64_t
     uint64_t* node_v = malloc(n * 8);
     uint32_t *node_m = malloc(n * 4), *node_d = malloc(n * 4);
     uint64_t* node_count = calloc(nb, 8);
-    uint64_t* tmp = malloc(n * 8);
     uint32_t *r = NULL, *F = NULL, *N = NULL;
     uint64_t *tree = NULL, *lower = NULL, *up_s = NULL, *up_z = NULL, *ys = NULL, *yz = NULL;
     int64_t* z = NULL;
-    if (!hi || !lo || !sorted || !sz || !s || !o || !cursor || !node_v || !node_m || !node_d || !node_count || !tmp)
+    if (!hi || !lo || !sorted || !sz || !s || !o || !cursor || !node_v || !node_m || !node_d || !node_count)
         goto done;
 
     if (kind == ORC_KEYS_U64) orc_fingerprint_u64((const uint64_t*)data, n, hi, lo);
@@ -474,17 +500,14 @@ int orc_build(uint32_t kind, const void* data, const uint64_t* offsets, uint64_t
     orc_tables(leaf, (uint32_t)maxm, r, F, N);
 
     /* trees; bucket i's coded nodes are stored from slot s_i on (a tree on m
-     * keys has at most m-1 coded nodes) */
-    for (uint64_t i = 0; i < nb; i++) {
-        memcpy(tmp + s[i], sorted + s[i], sz[i] * 8);
-        emitter e = {node_v + s[i], node_m + s[i], node_d + s[i], 0, seed_cap, NULL};
-        uint64_t* scratch = malloc((sz[i] ? sz[i] : 1) * 8);
-        if (!scratch) goto done;
-        e.tmp = scratch;
-        rc = build_tree(&st, tmp + s[i], (uint32_t)sz[i], 0, &e);
-        free(scratch);
+     * keys has at most m-1 coded nodes), or taken as given */
+    if (given_v) {
+        memcpy(node_v, given_v, n * 8);
+        memcpy(node_m, given_m, n * 4);
+        memcpy(node_count, given_count, nb * 8);
+    } else {
+        rc = orc_trees(sorted, s, 0, nb, leaf, seed_cap, node_v, node_m, node_d, node_count);
         if (rc) goto done;
-        node_count[i] = e.count;
         rc = ORC_ENOMEM;
     }
 
@@ -573,8 +596,52 @@ int orc_build(uint32_t kind, const void* data, const uint64_t* offsets, uint64_t
 
 done:
     free(hi); free(lo); free(sorted); free(sz); free(s); free(o); free(cursor);
-    free(node_v); free(node_m); free(node_d); free(node_count); free(tmp);
+    free(node_v); free(node_m); free(node_d); free(node_count);
     free(r); free(F); free(N); free(tree); free(z); free(ys); free(yz);
+    return rc;
+}
+
+int orc_build(uint32_t kind, const void* data, const uint64_t* offsets, uint64_t n, uint32_t leaf, uint32_t bucket,
+              uint64_t seed_cap, void* out, uint64_t cap, uint64_t* size) {
+    return build_impl(kind, data, offsets, n, leaf, bucket, seed_cap, NULL, NULL, NULL, out, cap, size);
+}
+
+/* orc_build with every bucket's tree supplied (as orc_trees writes them, for
+ * all nb buckets of the same key set): the same bytes, with the trees computed
+ * elsewhere (test harnesses run orc_trees over bucket ranges in parallel
+ * processes).  The trees are not checked beyond their node counts. */
+int orc_build_with_trees(uint32_t kind, const void* data, const uint64_t* offsets, uint64_t n, uint32_t leaf,
+                         uint32_t bucket, const uint64_t* node_v, const uint32_t* node_m, const uint64_t* node_count,
+                         void* out, uint64_t cap, uint64_t* size) {
+    if (!node_v || !node_m || !node_count) return ORC_EINVAL;
+    return build_impl(kind, data, offsets, n, leaf, bucket, 0, node_v, node_m, node_count, out, cap, size);
+}
+
+/* Bucket-contiguous lower signature words of a key set (each bucket sorted
+ * ascending) and the prefix sums s[0..nb] of the bucket sizes, as orc_build
+ * arranges them; ORC_EDUPLICATE if a bucket holds two equal lower words. */
+int orc_bucket_layout(uint32_t kind, const void* data, const uint64_t* offsets, uint64_t n, uint64_t nb,
+                      uint64_t* sorted, uint64_t* s) {
+    uint64_t *hi = malloc((n ? n : 1) * 8), *lo = malloc((n ? n : 1) * 8), *cursor = calloc(nb ? nb : 1, 8);
+    int rc = ORC_ENOMEM;
+    if (!hi || !lo || !cursor) goto out;
+    if (kind == ORC_KEYS_U64) orc_fingerprint_u64((const uint64_t*)data, n, hi, lo);
+    else orc_fingerprint_bytes((const uint8_t*)data, offsets, n, hi, lo);
+    memset(s, 0, (nb + 1) * 8);
+    for (uint64_t i = 0; i < n; i++) s[bucket_of(hi[i], nb) + 1]++;
+    for (uint64_t i = 0; i < nb; i++) s[i + 1] += s[i];
+    for (uint64_t i = 0; i < n; i++) {
+        uint64_t bk = bucket_of(hi[i], nb);
+        sorted[s[bk] + cursor[bk]++] = lo[i];
+    }
+    rc = ORC_OK;
+    for (uint64_t i = 0; i < nb; i++) {
+        qsort(sorted + s[i], s[i + 1] - s[i], 8, cmp_u64);
+        for (uint64_t k = s[i] + 1; k < s[i + 1]; k++)
+            if (sorted[k] == sorted[k - 1]) rc = ORC_EDUPLICATE;
+    }
+out:
+    free(hi); free(lo); free(cursor);
     return rc;
 }
 
