@@ -69,6 +69,12 @@ def _declare(L):
     L.orc_split_parts.restype = U32
     L.orc_tree.argtypes = [P, U32, U32, U64, P, P, P, P]
     L.orc_build.argtypes = [U32, P, P, U64, U32, U32, U64, P, U64, P]
+    L.orc_build_ex.argtypes = [U32, P, P, U64, U32, U32, U64, U32, P, U64, P]
+    L.orc_tables_ex.argtypes = [U32, U32, U32, P, P, P]
+    L.orc_lambda.argtypes = [U64]
+    L.orc_lambda.restype = U32
+    L.orc_gr_param_approx.argtypes = [U32, U32]
+    L.orc_gr_param_approx.restype = U32
     L.orc_lookup.argtypes = [P, U64, U32, P, P, U64, P]
     L.orc_bucket_sizes.argtypes = [U32, P, P, U64, U64, P]
     L.orc_bucket_keys.argtypes = [U32, P, P, U64, U64, U64, P, U64]
@@ -86,9 +92,13 @@ def _declare(L):
     L.orc_trees.argtypes = [P, P, U64, U64, U32, U64, P, P, P, P]
     L.orc_build_with_trees.argtypes = [U32, P, P, U64, U32, U32, P, P, P, P, U64, P]
     L.orc_bucket_layout.argtypes = [U32, P, P, U64, U64, P, P]
+    L.orc_ranks_from_tree.argtypes = [P, U32, U32, P, P]
+    L.orc_bucket_ids.argtypes = [P, U64, U64, P]
+    L.orc_bucket_ids.restype = None
     for f in ("orc_tables", "orc_tree", "orc_build", "orc_lookup", "orc_bucket_sizes", "orc_blob_bucket",
               "orc_bucket_ranks", "orc_blob_prefix", "orc_blob_check_inventory", "orc_trees",
-              "orc_build_with_trees", "orc_bucket_layout"):
+              "orc_build_with_trees", "orc_bucket_layout", "orc_ranks_from_tree", "orc_build_ex",
+              "orc_tables_ex"):
         getattr(L, f).restype = ctypes.c_int
 
 
@@ -130,6 +140,17 @@ def phi(x: int, depth: int, v: int, m: int) -> int:
     return int(lib().orc_phi(x, depth, v, m))
 
 
+def lam(x: int) -> int:
+    """lambda(x) = floor(lg x), the index of the highest set bit (Sec. 2)."""
+    return int(lib().orc_lambda(x))
+
+
+def gr_param_approx(leaf: int, m: int) -> int:
+    """The Sec. 7.2 integer approximation of a split node's Golomb-Rice
+    parameter (0 for leaves)."""
+    return int(lib().orc_gr_param_approx(leaf, m))
+
+
 def ln_success(leaf: int, m: int) -> float:
     return float(lib().orc_ln_success(leaf, m))
 
@@ -146,11 +167,13 @@ def split_parts(leaf: int, m: int) -> list:
     return [int(x) for x in parts[:f]]
 
 
-def tables(leaf: int, maxm: int):
+def tables(leaf: int, maxm: int, gr_table_max: int = 0):
+    """Per-size tables r, F, N for sizes 0..maxm; splits of more than
+    gr_table_max keys (if nonzero) take the Sec. 7.2 approximation."""
     r = np.zeros(maxm + 1, dtype=np.uint32)
     F = np.zeros(maxm + 1, dtype=np.uint32)
     N = np.zeros(maxm + 1, dtype=np.uint32)
-    rc = lib().orc_tables(leaf, maxm, _ptr(r), _ptr(F), _ptr(N))
+    rc = lib().orc_tables_ex(leaf, maxm, gr_table_max, _ptr(r), _ptr(F), _ptr(N))
     if rc:
         raise OracleError(rc, "tables")
     return r, F, N
@@ -173,15 +196,18 @@ def tree(lo: np.ndarray, leaf: int, seed_cap: int = 0):
     return v[:c].copy(), mm[:c].copy(), d[:c].copy()
 
 
-def build(keys, leaf: int, bucket: int, seed_cap: int = 0) -> bytes:
+def build(keys, leaf: int, bucket: int, seed_cap: int = 0, gr_table_max: int = 0) -> bytes:
+    """The serialized structure (gr_table_max: splits of more than that many
+    keys take the integer Golomb-Rice approximation of Sec. 7.2; 0 = none)."""
     kind, data, offs, n = _keys(keys)
     size = U64()
     op = _ptr(offs) if offs is not None else None
-    rc = lib().orc_build(kind, _ptr(data), op, n, leaf, bucket, seed_cap, None, 0, ctypes.byref(size))
+    args = (kind, _ptr(data), op, n, leaf, bucket, seed_cap, gr_table_max)
+    rc = lib().orc_build_ex(*args, None, 0, ctypes.byref(size))
     if rc:
         raise OracleError(rc, "build")
     out = np.zeros(size.value, dtype=np.uint8)
-    rc = lib().orc_build(kind, _ptr(data), op, n, leaf, bucket, seed_cap, _ptr(out), size.value, ctypes.byref(size))
+    rc = lib().orc_build_ex(*args, _ptr(out), size.value, ctypes.byref(size))
     if rc:
         raise OracleError(rc, "build")
     return out.tobytes()
@@ -291,6 +317,27 @@ def bucket_ranks(lo: np.ndarray, leaf: int, seed_cap: int = 0) -> np.ndarray:
     return out[:len(lo)]
 
 
+def ranks_from_tree(lo: np.ndarray, leaf: int, v: np.ndarray) -> np.ndarray:
+    """In-bucket ranks of the lower words lo given the bucket tree's indices
+    v in preorder (no search)."""
+    lo = np.ascontiguousarray(lo, dtype=np.uint64)
+    v = np.ascontiguousarray(v, dtype=np.uint64)
+    out = np.zeros(max(len(lo), 1), dtype=np.uint64)
+    rc = lib().orc_ranks_from_tree(_ptr(lo if len(lo) else np.zeros(1, np.uint64)), len(lo), leaf,
+                                   _ptr(v if len(v) else np.zeros(1, np.uint64)), _ptr(out))
+    if rc:
+        raise OracleError(rc, "ranks_from_tree")
+    return out[:len(lo)]
+
+
+def bucket_ids(hi: np.ndarray, nb: int) -> np.ndarray:
+    """Bucket of every upper signature word."""
+    hi = np.ascontiguousarray(hi, dtype=np.uint64)
+    out = np.zeros(max(len(hi), 1), dtype=np.uint64)
+    lib().orc_bucket_ids(_ptr(hi if len(hi) else np.zeros(1, np.uint64)), len(hi), nb, _ptr(out))
+    return out[:len(hi)]
+
+
 def blob_bucket(blob: bytes, bucket: int):
     """Decode one bucket of a serialized structure: (s_i, o_i, indices, sizes),
     the coded nodes in preorder."""
@@ -360,7 +407,7 @@ def header(blob: bytes) -> dict:
     return {
         "magic": int(w[0]), "version": int(w[1]) & 0xFFFFFFFF, "kind": int(w[1]) >> 32, "n": int(w[2]),
         "leaf": int(w[3]), "bucket": int(w[4]), "nb": int(w[5]), "maxm": int(w[6]), "Ws": int(w[7]) & 0xFF,
-        "Wz": (int(w[7]) >> 8) & 0xFF, "delta_s": int(w[8]), "delta_z": int(np.int64(w[9])), "beta": int(w[10]),
+        "Wz": (int(w[7]) >> 8) & 0xFF, "gr_table_max": int(w[7]) >> 16, "delta_s": int(w[8]), "delta_z": int(np.int64(w[9])), "beta": int(w[10]),
         "us_words": int(w[11]), "uz_words": int(w[12]), "lower_words": int(w[13]), "tree_words": int(w[14]),
         "tree_bits": int(w[15]),
     }

@@ -19,7 +19,7 @@ import time
 
 import numpy as np
 
-from . import bucket_layout, build_with_trees, trees
+from . import bucket_layout, build_with_trees, ranks_from_tree, trees
 
 MAX_WORKERS = 16
 
@@ -33,6 +33,13 @@ def _task(args):
     t0 = time.perf_counter()
     v, m, cnt = trees(lo, s_local, 0, len(s_local) - 1, leaf, seed_cap)
     return v, m, cnt, time.perf_counter() - t0
+
+
+def _task_ranks(args):
+    lo, s_local, leaf, seed_cap = args
+    v, m, cnt, dt = _task(args)
+    c = int(cnt[0])
+    return v[:c], m[:c], cnt, dt, ranks_from_tree(lo, leaf, v[:c])
 
 
 def _pool(workers: int):
@@ -62,10 +69,13 @@ def _local(sorted_lo, s_, a, b):
     return sorted_lo[base:int(s_[b])], (s_[a:b + 1] - np.uint64(base)).astype(np.uint64)
 
 
-def bucket_trees(keys, leaf: int, bucket: int, picks, workers: int | None = None, seed_cap: int = 0, layout=None):
+def bucket_trees(keys, leaf: int, bucket: int, picks, workers: int | None = None, seed_cap: int = 0, layout=None,
+                 with_ranks: bool = False):
     """Trees of the picked buckets, one task per bucket, computed in parallel.
     Returns {bucket: (v, m, seconds)}: the coded nodes' indices and sizes in
-    preorder and the single-core time the oracle took for that bucket."""
+    preorder and the single-core time the oracle took for that bucket; with
+    with_ranks, also the in-bucket ranks of the bucket's lower words in
+    ascending order of the words (v, m, seconds, ranks)."""
     workers = workers or default_workers()
     n = len(keys[1]) - 1 if isinstance(keys, tuple) else len(keys)
     nb = -(-n // bucket)
@@ -76,11 +86,11 @@ def bucket_trees(keys, leaf: int, bucket: int, picks, workers: int | None = None
         lo, s_local = _local(sorted_lo, s_, i, i + 1)
         tasks.append((lo, s_local, leaf, seed_cap))
     with _pool(min(workers, max(1, len(tasks)))) as pool:
-        res = pool.map(_task, tasks, chunksize=1)
+        res = pool.map(_task_ranks if with_ranks else _task, tasks, chunksize=1)
     out = {}
-    for i, (v, m, cnt, dt) in zip(picks, res):
-        c = int(cnt[0])
-        out[i] = (v[:c].copy(), m[:c].copy(), dt)
+    for i, r in zip(picks, res):
+        c = int(r[2][0])
+        out[i] = (r[0][:c].copy(), r[1][:c].copy(), r[3]) + ((r[4],) if with_ranks else ())
     return out
 
 

@@ -200,6 +200,37 @@ static uint32_t golomb_rice_param(double p) {
     return x > 0.0 ? (uint32_t)x : 0;
 }
 
+/* lambda(x): the index of the highest set bit of x >= 1, i.e. floor(lg x)
+ * (Sec. 2). */
+static uint32_t lambda_of(uint64_t x) {
+    uint32_t l = 0;
+    while (x > 1) {
+        x >>= 1;
+        l++;
+    }
+    return l;
+}
+
+/* The paper's integer approximation of the Golomb-Rice parameter of a split
+ * of m keys into parts k_0..k_{s-1}, for large buckets (Sec. 7.2):
+ *   ( ((s-1) * 5 >> 1) + sum_i lambda(k_i + (k_i >> 1)) - lambda(m) ) >> 1,
+ * where lambda(x + (x >> 1)) is the integer rounding of lg x of Sec. 7.1.  A
+ * negative value (none occurs for the strategy's splits) reads as 0. */
+static uint32_t gr_param_approx(const strategy* st, uint32_t m) {
+    uint32_t parts[ORC_MAX_FANOUT], unit;
+    uint32_t f = split_parts(st, m, parts, &unit);
+    int64_t acc = (int64_t)(((f - 1) * 5) >> 1) - (int64_t)lambda_of(m);
+    for (uint32_t j = 0; j < f; j++) acc += lambda_of((uint64_t)parts[j] + (parts[j] >> 1));
+    return acc > 0 ? (uint32_t)(acc >> 1) : 0;
+}
+
+uint32_t orc_lambda(uint64_t x) { return x ? lambda_of(x) : 0; }
+
+uint32_t orc_gr_param_approx(uint32_t leaf, uint32_t m) {
+    strategy st = make_strategy(leaf);
+    return m > leaf ? gr_param_approx(&st, m) : 0;
+}
+
 double orc_ln_success(uint32_t leaf, uint32_t m) {
     strategy st = make_strategy(leaf);
     return ln_success(&st, m);
@@ -207,8 +238,11 @@ double orc_ln_success(uint32_t leaf, uint32_t m) {
 
 /* Per-size tables for sizes 0..maxm: r (GR parameter of the node itself, 0
  * for uncoded nodes), F (fixed bits of the whole subtree) and N (coded nodes
- * in the subtree).  Leaves of size 0 or 1 carry no index (Fig. 1 caption). */
-int orc_tables(uint32_t leaf, uint32_t maxm, uint32_t* r, uint32_t* F, uint32_t* N) {
+ * in the subtree).  Leaves of size 0 or 1 carry no index (Fig. 1 caption).
+ * r follows eq. (4) for every leaf and for splits of at most gr_max keys;
+ * splits of more than gr_max keys take the integer approximation of Sec. 7.2
+ * (gr_max = 0: eq. (4) everywhere). */
+int orc_tables_ex(uint32_t leaf, uint32_t maxm, uint32_t gr_max, uint32_t* r, uint32_t* F, uint32_t* N) {
     if (leaf < 1 || leaf > 24) return ORC_EINVAL;
     strategy st = make_strategy(leaf);
     for (uint32_t m = 0; m <= maxm; m++) {
@@ -216,7 +250,8 @@ int orc_tables(uint32_t leaf, uint32_t maxm, uint32_t* r, uint32_t* F, uint32_t*
             r[m] = 0; F[m] = 0; N[m] = 0;
             continue;
         }
-        r[m] = golomb_rice_param(exp(ln_success(&st, m)));
+        if (gr_max && m > leaf && m > gr_max) r[m] = gr_param_approx(&st, m);
+        else r[m] = golomb_rice_param(exp(ln_success(&st, m)));
         F[m] = r[m];
         N[m] = 1;
         if (m > leaf) {
@@ -229,6 +264,10 @@ int orc_tables(uint32_t leaf, uint32_t maxm, uint32_t* r, uint32_t* F, uint32_t*
         }
     }
     return ORC_OK;
+}
+
+int orc_tables(uint32_t leaf, uint32_t maxm, uint32_t* r, uint32_t* F, uint32_t* N) {
+    return orc_tables_ex(leaf, maxm, 0, r, F, N);
 }
 
 void orc_strategy(uint32_t leaf, uint32_t* lower, uint32_t* upper) {
@@ -450,8 +489,9 @@ static uint32_t ef_width(uint64_t N, uint64_t U) {
 /* if cap is too small only the size is reported.                            */
 /* ------------------------------------------------------------------------ */
 static int build_impl(uint32_t kind, const void* data, const uint64_t* offsets, uint64_t n, uint32_t leaf,
-                      uint32_t bucket, uint64_t seed_cap, const uint64_t* given_v, const uint32_t* given_m,
-                      const uint64_t* given_count, void* out, uint64_t cap, uint64_t* size) {
+                      uint32_t bucket, uint64_t seed_cap, uint32_t gr_max, const uint64_t* given_v,
+                      const uint32_t* given_m, const uint64_t* given_count, void* out, uint64_t cap,
+                      uint64_t* size) {
     if (n == 0 || leaf < 1 || leaf > 24 || bucket == 0 || !data || !size) return ORC_EINVAL;
     if (kind != ORC_KEYS_U64 && kind != ORC_KEYS_BYTES) return ORC_EINVAL;
     if (kind == ORC_KEYS_BYTES) {
@@ -497,7 +537,7 @@ static int build_impl(uint32_t kind, const void* data, const uint64_t* offsets, 
 
     r = malloc((maxm + 1) * 4); F = malloc((maxm + 1) * 4); N = malloc((maxm + 1) * 4);
     if (!r || !F || !N) goto done;
-    orc_tables(leaf, (uint32_t)maxm, r, F, N);
+    orc_tables_ex(leaf, (uint32_t)maxm, gr_max, r, F, N);
 
     /* trees; bucket i's coded nodes are stored from slot s_i on (a tree on m
      * keys has at most m-1 coded nodes), or taken as given */
@@ -572,7 +612,7 @@ static int build_impl(uint32_t kind, const void* data, const uint64_t* offsets, 
     w[0] = ORC_MAGIC;
     w[1] = ORC_VERSION | ((uint64_t)kind << 32);
     w[2] = n; w[3] = leaf; w[4] = bucket; w[5] = nb; w[6] = maxm;
-    w[7] = (uint64_t)Ws | ((uint64_t)Wz << 8);
+    w[7] = (uint64_t)Ws | ((uint64_t)Wz << 8) | ((uint64_t)gr_max << 16);
     w[8] = delta_s; w[9] = (uint64_t)delta_z; w[10] = beta;
     w[11] = us_words; w[12] = uz_words; w[13] = lower_words; w[14] = tree_words; w[15] = total_bits;
     lower = w + ORC_HEADER_WORDS;
@@ -603,7 +643,15 @@ done:
 
 int orc_build(uint32_t kind, const void* data, const uint64_t* offsets, uint64_t n, uint32_t leaf, uint32_t bucket,
               uint64_t seed_cap, void* out, uint64_t cap, uint64_t* size) {
-    return build_impl(kind, data, offsets, n, leaf, bucket, seed_cap, NULL, NULL, NULL, out, cap, size);
+    return build_impl(kind, data, offsets, n, leaf, bucket, seed_cap, 0, NULL, NULL, NULL, out, cap, size);
+}
+
+/* orc_build with the Golomb-Rice parameters of splits of more than gr_max keys
+ * from the integer approximation of Sec. 7.2 (recorded in the header, bits
+ * 16.. of word 7). */
+int orc_build_ex(uint32_t kind, const void* data, const uint64_t* offsets, uint64_t n, uint32_t leaf,
+                 uint32_t bucket, uint64_t seed_cap, uint32_t gr_max, void* out, uint64_t cap, uint64_t* size) {
+    return build_impl(kind, data, offsets, n, leaf, bucket, seed_cap, gr_max, NULL, NULL, NULL, out, cap, size);
 }
 
 /* orc_build with every bucket's tree supplied (as orc_trees writes them, for
@@ -614,7 +662,7 @@ int orc_build_with_trees(uint32_t kind, const void* data, const uint64_t* offset
                          uint32_t bucket, const uint64_t* node_v, const uint32_t* node_m, const uint64_t* node_count,
                          void* out, uint64_t cap, uint64_t* size) {
     if (!node_v || !node_m || !node_count) return ORC_EINVAL;
-    return build_impl(kind, data, offsets, n, leaf, bucket, 0, node_v, node_m, node_count, out, cap, size);
+    return build_impl(kind, data, offsets, n, leaf, bucket, 0, 0, node_v, node_m, node_count, out, cap, size);
 }
 
 /* Bucket-contiguous lower signature words of a key set (each bucket sorted
@@ -711,6 +759,7 @@ static int blob_open(const void* blob, uint64_t bytes, decoded* dc) {
     if (dc->leaf < 1 || dc->leaf > 24) return ORC_EFORMAT;
     dc->st = make_strategy((uint32_t)dc->leaf);
     uint32_t Ws = (uint32_t)(w[7] & 0xff), Wz = (uint32_t)((w[7] >> 8) & 0xff);
+    uint32_t gr_max = (uint32_t)(w[7] >> 16);
     uint64_t delta_s = w[8];
     int64_t delta_z = (int64_t)w[9];
     uint64_t beta = w[10], us_words = w[11], uz_words = w[12], lower_words = w[13], tree_words = w[14];
@@ -737,7 +786,7 @@ static int blob_open(const void* blob, uint64_t bytes, decoded* dc) {
         free(Ft); free(Nt);
         return ORC_ENOMEM;
     }
-    orc_tables((uint32_t)dc->leaf, (uint32_t)dc->maxm, dc->r, Ft, Nt);
+    orc_tables_ex((uint32_t)dc->leaf, (uint32_t)dc->maxm, gr_max, dc->r, Ft, Nt);
     free(Ft);
     free(Nt);
 
@@ -872,6 +921,21 @@ int orc_blob_check_inventory(const void* blob, uint64_t bytes, uint64_t* bad) {
 /* Rank of each key of one bucket inside the bucket (0..m-1), from the tree
  * the oracle builds for the bucket's lower signature words: the keys left of
  * the chosen child at every split plus the leaf's bijection (Sec. 4). */
+/* In-bucket ranks of a bucket's m lower words given its tree's indices v (in
+ * preorder, as orc_tree emits them): the descent of the lookup (Sec. 4). */
+int orc_ranks_from_tree(const uint64_t* lo, uint32_t m, uint32_t leaf, const uint64_t* v, uint64_t* ranks) {
+    if (leaf < 1 || leaf > 24) return ORC_EINVAL;
+    decoded dc;
+    memset(&dc, 0, sizeof(dc));
+    dc.leaf = leaf;
+    dc.st = make_strategy(leaf);
+    for (uint32_t i = 0; i < m; i++) {
+        uint32_t idx = 0;
+        ranks[i] = descend(&dc, lo[i], m, 0, v, &idx);
+    }
+    return ORC_OK;
+}
+
 int orc_bucket_ranks(const uint64_t* lo, uint32_t m, uint32_t leaf, uint64_t seed_cap, uint64_t* ranks) {
     if (leaf < 1 || leaf > 24) return ORC_EINVAL;
     uint64_t* v = malloc((size_t)(m ? m : 1) * 8);
@@ -882,17 +946,15 @@ int orc_bucket_ranks(const uint64_t* lo, uint32_t m, uint32_t leaf, uint64_t see
     uint64_t cnt = 0;
     rc = orc_tree(lo, m, leaf, seed_cap, v, mm, d, &cnt);
     if (rc) goto out;
-    decoded dc;
-    memset(&dc, 0, sizeof(dc));
-    dc.leaf = leaf;
-    dc.st = make_strategy(leaf);
-    for (uint32_t i = 0; i < m; i++) {
-        uint32_t idx = 0;
-        ranks[i] = descend(&dc, lo[i], m, 0, v, &idx);
-    }
+    rc = orc_ranks_from_tree(lo, m, leaf, v, ranks);
 out:
     free(v); free(mm); free(d);
     return rc;
+}
+
+/* Bucket of every signature (Sec. 6.1: floor(hi * nb / 2^64)). */
+void orc_bucket_ids(const uint64_t* hi, uint64_t n, uint64_t nb, uint64_t* ids) {
+    for (uint64_t i = 0; i < n; i++) ids[i] = bucket_of(hi[i], nb);
 }
 
 /* Bucket sizes only (for the bucket-distribution pin). */

@@ -4,10 +4,12 @@
   of a shuffled lookup batch against the oracle (the oracle builds it in well
   under a minute).
 * 10^7 random 64-bit keys, l=16, b=2000: the oracle needs hours for the whole
-  structure, so the test compares what it can compute one piece at a time.
-  That is the header, both Elias-Fano lists of all 5,000 buckets, the indices
-  of sampled buckets, and the ranks of those buckets' keys. It also checks
-  that the lookup of all 10^7 keys is a permutation of [0, n).
+  structure, so the test compares the header, both Elias-Fano lists of all
+  5,000 buckets, and for 128 buckets (the largest and the smallest among
+  them) every index, node size, Golomb-Rice length and key rank; the
+  oracle's trees of those buckets are computed in parallel on the host
+  cores (oracle/parallel.py).  It also checks that the lookup of all 10^7
+  keys is a permutation of [0, n).
 * 4096 uneven builds in one batched call, l=12, b=1000: the 16 smallest builds
   whole, and sampled buckets of the largest and of every 256th build. The
   lookup of every key of every build must be a bijection.
@@ -79,7 +81,18 @@ def test_full_strings_10M_l8_b100(rs, orc):
     assert np.array_equal(ranks.cpu().numpy().view(np.uint64), orc.lookup(want, queries))
 
 
+L16_BUCKETS = 128
+
+
 def test_full_u64_10M_l16_b2000(rs, orc):
+    """128 of the 5,000 buckets (the largest, the smallest and 126 drawn at
+    random) against the oracle's trees, computed bucket-parallel on the host
+    cores by the oracle's own tree loop: every index and node size, the
+    bucket's Golomb-Rice length o_{i+1} - o_i and the rank of every key."""
+    import torch
+
+    from oracle import parallel
+
     n, leaf, bucket = L16_N, 16, 2000
     print(f"case full u64 n={n} leaf={leaf} bucket={bucket}", flush=True)
     keys = inputs.u64_keys(n, 4)
@@ -88,7 +101,10 @@ def test_full_u64_10M_l16_b2000(rs, orc):
     got = blob.to_bytes()
     h = orc.header(got)
     nb = -(-n // bucket)
-    sizes = orc.bucket_sizes(keys, nb)
+    hi, lo = orc.fingerprint(keys)
+    ids = orc.bucket_ids(hi, nb).astype(np.int64)
+    sizes = np.bincount(ids, minlength=nb)
+    assert np.array_equal(sizes, orc.bucket_sizes(keys, nb))
     assert (h["n"], h["leaf"], h["bucket"], h["nb"], h["maxm"]) == (n, leaf, bucket, nb, int(sizes.max()))
     s_all, o_all = orc.blob_prefix(got)
     assert np.array_equal(s_all, np.concatenate([[0], np.cumsum(sizes)]).astype(np.uint64))
@@ -98,14 +114,26 @@ def test_full_u64_10M_l16_b2000(rs, orc):
     ranks = rs.lookup(blob, dkeys)
     assert _is_permutation(ranks)
     rng = np.random.default_rng(11)
-    picks = [int(np.argmin(sizes))] + rng.integers(0, nb, 1).tolist()
-    _check_sampled_buckets(rs, orc, keys, got, ranks, leaf, picks)
-    # o_{i+1} - o_i is the Golomb-Rice length of the sampled buckets' codes
+    picks = {int(np.argmax(sizes)), int(np.argmin(sizes))}
+    while len(picks) < min(L16_BUCKETS, nb):
+        picks.add(int(rng.integers(0, nb)))
+    picks = sorted(picks)
+    print(f"oracle trees of {len(picks)} buckets on {parallel.default_workers()} host processes", flush=True)
+    trees = parallel.bucket_trees(keys, leaf, bucket, picks, with_ranks=True)
     r, _, _ = orc.tables(leaf, h["maxm"])
+    order = np.argsort(ids, kind="stable")
+    starts = np.concatenate([[0], np.cumsum(sizes)])
     for i in picks:
-        _, _, v, m = orc.blob_bucket(got, i)
-        bits = sum(int(r[mm]) + (int(vv) >> int(r[mm])) + 1 for vv, mm in zip(v, m))
-        assert int(o_all[i + 1] - o_all[i]) == bits
+        s_i, o_i, v, m = orc.blob_bucket(got, i)
+        tv, tm, _, tranks = trees[i]
+        assert np.array_equal(m, tm), f"bucket {i}: node sizes differ"
+        assert np.array_equal(v, tv), f"bucket {i}: indices differ"
+        bits = sum(int(r[mm]) + (int(vv) >> int(r[mm])) + 1 for vv, mm in zip(tv, tm))
+        assert int(o_all[i + 1] - o_all[i]) == bits, f"bucket {i}: Golomb-Rice length differs"
+        idx = order[starts[i]:starts[i + 1]]
+        by_lo = idx[np.argsort(lo[idx], kind="stable")]  # members in ascending lower word, as the oracle ranks them
+        got_r = ranks[torch.from_numpy(by_lo).to(ranks.device)].cpu().numpy().view(np.uint64)
+        assert np.array_equal(got_r, tranks + np.uint64(s_i)), f"bucket {i}: ranks differ"
 
 
 def test_full_batch_4096_l12_b1000(rs, orc):

@@ -39,3 +39,19 @@ def test_layout_rejects_equal_lower_words(orc):
     with pytest.raises(orc.OracleError) as e:
         orc.bucket_layout(dup, 10)
     assert e.value.code == orc.EDUPLICATE
+
+
+def test_bucket_trees_with_ranks_equal_bucket_ranks(orc):
+    from oracle import parallel
+
+    n, leaf, bucket = 20_000, 8, 100
+    keys = inputs.u64_keys(n, 79)
+    nb = n // bucket
+    got = parallel.bucket_trees(keys, leaf, bucket, [3, 150], workers=2, with_ranks=True)
+    hi, lo = orc.fingerprint(keys)
+    ids = orc.bucket_ids(hi, nb)
+    for i in (3, 150):
+        los = np.sort(lo[ids == i])
+        assert np.array_equal(got[i][3], orc.bucket_ranks(los, leaf))
+        assert np.array_equal(np.sort(got[i][3]), np.arange(len(los), dtype=np.uint64))
+    assert np.array_equal(np.bincount(ids.astype(np.int64), minlength=nb), orc.bucket_sizes(keys, nb))

@@ -488,3 +488,74 @@ def test_seed_cap_boundary_oracle(orc):
     with pytest.raises(orc.OracleError) as e:
         orc.build(keys, 8, 1000, seed_cap=vmax)
     assert e.value.code == orc.ESEARCH
+
+
+# ---------------------------------------------------------------------------
+# Sec. 7.1-7.2: the integer rounding lambda(x + (x >> 1)) of lg x and the
+# integer approximation of a large split's Golomb-Rice parameter.
+# ---------------------------------------------------------------------------
+def test_lambda_is_the_highest_set_bit(orc):
+    for x in list(range(1, 5000)) + [2**k + d for k in range(1, 63) for d in (-1, 0, 1)]:
+        assert orc.lam(x) == x.bit_length() - 1, x
+
+
+def test_lambda_of_x_plus_half_is_floor_lg_three_halves_x(orc):
+    """lambda(x + floor(x/2)) = floor(lg(3x/2)) exactly for every integer x >= 1
+    (3x/2 and x + floor(x/2) differ by 1/2 only for odd x, and 3x is never a
+    power of two), i.e. floor(lg x + lg 3 - 1), the middle of the paper's
+    chain; its last step, floor(lg x + 0.58), is an approximation."""
+    import math
+
+    xs = list(range(1, 1 << 18)) + [int(v) for v in np.random.default_rng(5).integers(1, 2**40, 2000)]
+    for x in xs:
+        assert orc.lam(x + (x >> 1)) == (3 * x).bit_length() - 2, x
+    agree = np.mean([orc.lam(x + (x >> 1)) == math.floor(math.log2(x) + 0.58) for x in range(1, 1 << 16)])
+    assert agree > 0.99
+
+
+def test_large_split_parameter_tracks_stirling_and_eq4(orc):
+    """The approximation estimates lg(1/p) of eq. (2) by Stirling's formula,
+    1/2 ((s-1) lg(2 pi) + sum lg k_i - lg m), with integer logarithms: for the
+    2-way splits of large buckets it stays within [-1.1, 0.7] of that closed
+    form and 0 or 1 above the exact eq. (4) parameter; for every fanout within
+    3 of the closed form."""
+    import math
+
+    for leaf in range(1, 25):
+        r, _, _ = orc.tables(leaf, 4096)
+        for m in range(leaf + 1, 4097, 3):
+            parts = orc.split_parts(leaf, m)
+            s = len(parts)
+            stirling = 0.5 * ((s - 1) * math.log2(2 * math.pi) + sum(math.log2(k) for k in parts) - math.log2(m))
+            a = orc.gr_param_approx(leaf, m)
+            assert abs(a - stirling) < 3, (leaf, m)
+            if s == 2:
+                assert -1.1 <= a - stirling <= 0.7, (leaf, m)
+                assert 0 <= a - int(r[m]) <= 1, (leaf, m)
+    assert orc.gr_param_approx(8, 8) == 0  # leaves keep eq. (4)
+
+
+def test_tables_with_large_split_approximation(orc):
+    """Splits above gr_table_max take the approximation, every other size the
+    exact table; F and N still sum over the subtree."""
+    leaf, cap, T = 8, 3000, 500
+    r0, F0, N0 = orc.tables(leaf, cap)
+    r1, F1, N1 = orc.tables(leaf, cap, T)
+    for m in range(cap + 1):
+        want = orc.gr_param_approx(leaf, m) if (m > T and m > leaf) else int(r0[m])
+        assert int(r1[m]) == want, m
+        if m > leaf:
+            parts = orc.split_parts(leaf, m)
+            assert F1[m] == r1[m] + sum(int(F1[k]) for k in parts)
+            assert N1[m] == N0[m]
+
+
+@pytest.mark.parametrize("n,leaf,bucket,T", [(20000, 8, 1000, 300), (6000, 5, 2000, 31), (3000, 12, 3000, 200)])
+def test_structure_with_approximation_is_a_bijection(orc, n, leaf, bucket, T):
+    keys = inputs.u64_keys(n, 600 + leaf)
+    blob = orc.build(keys, leaf, bucket, gr_table_max=T)
+    assert orc.header(blob)["gr_table_max"] == T
+    ranks = orc.lookup(blob, keys)
+    assert np.array_equal(np.sort(ranks), np.arange(n, dtype=np.uint64))
+    # the exact parameters are optimal (eq. (4)): the approximation never makes the trees smaller
+    assert orc.header(blob)["tree_bits"] >= orc.header(orc.build(keys, leaf, bucket))["tree_bits"] - 64
