@@ -86,6 +86,12 @@ int rs_set_allocator(rs_alloc_fn alloc, rs_free_fn release, void* ctx);
 /* Build options (all-zero = defaults).
  *   seed_cap  : lowers the search cap of every split and bijection index
  *               (0 = 2^56); it exists to exercise the RS_ESEARCH path.
+ *   gr_table_max: splits of more than this many keys take their Golomb-Rice
+ *               parameter from the paper's integer approximation for large
+ *               buckets (Sec. 7.2), every other node from eq. (4) (0 = eq. (4)
+ *               for every node).  The value is recorded in the structure
+ *               (header word 7, bits 16 and up), so lookups and
+ *               rs_blob_from_host follow it.
  *   flags     : RS_OPT_TIMING records HIP events around each construction phase
  *               on the build stream (read them with rs_last_build_stats); the
  *               build then waits for the stream before returning.
@@ -112,7 +118,7 @@ typedef struct {
     uint32_t group_max;
     uint32_t waves;
     uint32_t wait_limit;
-    uint32_t reserved;
+    uint32_t gr_table_max;
 } rs_options;
 
 /* Search schedule of one (l, b) pair.  The seed search runs one workgroup per
@@ -190,7 +196,11 @@ int rs_last_build_stats(rs_build_stats* out);
  *            below 32).
  *   bucket : average bucket size b >= 1; nb = ceil(n / b) buckets (Sec. 6.1).
  *   stream : HIP stream; all device work is enqueued on it.  The call waits on the
- *            stream twice (for the largest bucket size and for the blob size).
+ *            stream once, for the blob size: the search is sized for a
+ *            bucket-size cap estimated from n and b (a bucket count is
+ *            exceeded with probability below 1e-6); if a bucket is larger
+ *            (skewed keys), the construction runs again sized for the
+ *            largest bucket, with the same result.
  *   out    : receives the new blob; its device bytes are valid once the stream
  *            reaches the end of the enqueued work.
  * Errors: RS_EINVAL, RS_EDUPLICATE, RS_ENOMEM, RS_EDEVICE, RS_ESEARCH. */
@@ -282,7 +292,9 @@ const char* rs_last_error(void);
  * in first-in first-out order and are admitted when their estimated device
  * footprint (about 56 bytes per key) fits in the free part of the budget (one is
  * always admitted when nothing is in flight).  Each of `build_workers` workers owns
- * a stream and runs every admissible waiting request as one rs_build_batch call, so
+ * a stream and runs the request at the head of the queue and every admissible
+ * waiting request of the same leaf size as one rs_build_batch call (the requests of
+ * a batch complete together, so short and long searches are not mixed), so
  * requests that arrive while a batch is on the device overlap with it in the next
  * worker's batch.  Lookups run on their own stream.  A request's result is the same
  * as rs_build / rs_lookup on the same inputs.
@@ -349,6 +361,11 @@ void rs_server_destroy(rs_server* srv);
  * Host only; no device is needed.  Errors: RS_EINVAL (l outside [1,24], NULL),
  * RS_ENOMEM. */
 int rs_tables(uint32_t leaf, uint32_t maxm, uint32_t* r, uint32_t* F, uint32_t* N);
+
+/* rs_tables of a structure built with rs_options.gr_table_max = gr_table_max:
+ * r of split nodes above that size follows the integer approximation of
+ * Sec. 7.2 (and F with it). */
+int rs_tables_ex(uint32_t leaf, uint32_t maxm, uint32_t gr_table_max, uint32_t* r, uint32_t* F, uint32_t* N);
 
 /* Library version string. */
 const char* rs_version(void);

@@ -75,6 +75,7 @@ Layout layout_of(const uint64_t* h) {
     L.n = h[2]; L.leaf = h[3]; L.bucket = h[4]; L.nb = h[5]; L.maxm = h[6];
     L.Ws = (uint32_t)(h[7] & 0xff);
     L.Wz = (uint32_t)((h[7] >> 8) & 0xff);
+    L.gr_max = (uint32_t)(h[7] >> 16);
     L.delta_s = h[8];
     L.delta_z = (int64_t)h[9];
     L.beta = h[10];
@@ -91,8 +92,8 @@ Layout layout_of(const uint64_t* h) {
     return L;
 }
 
-int upload_tables(uint32_t leaf, uint32_t maxm, uint32_t* dst, hipStream_t s) {
-    TableView tv = host_tables(leaf, maxm);
+int upload_tables(uint32_t leaf, uint32_t maxm, uint32_t gr_max, uint32_t* dst, hipStream_t s) {
+    TableView tv = host_tables(leaf, maxm, gr_max);
     if (!tv.data) return fail(RS_ENOMEM, "table allocation failed");
     RS_HIP(hipMemcpyAsync(dst, tv.r(), (maxm + 1) * 4ull, hipMemcpyHostToDevice, s));
     RS_HIP(hipMemcpyAsync(dst + (maxm + 1), tv.F(), (maxm + 1) * 4ull, hipMemcpyHostToDevice, s));
@@ -118,69 +119,81 @@ struct LookupArgs {
     uint32_t leaf, lower, upper, maxm;
 };
 
-// Position of the k-th set bit (k = 0, 1, ...) inside a 64-bit word.
+// Position of the k-th set bit (k = 0, 1, ...) inside a 64-bit word (k is
+// less than the word's popcount): a binary search over halves of 32, 16, 8, 4,
+// 2 and 1 bits, each step a popcount and a compare with no branch (the select
+// runs once per lane in a wavefront whose lanes search different words).
 __device__ __forceinline__ uint32_t select_in_word(uint64_t x, uint32_t k) {
-    uint32_t pos = 0;
-    uint32_t c = (uint32_t)__popc((uint32_t)x);
-    if (k >= c) { k -= c; x >>= 32; pos += 32; }
-    c = (uint32_t)__popc((uint32_t)x & 0xffffu);
-    if (k >= c) { k -= c; x >>= 16; pos += 16; }
-    c = (uint32_t)__popc((uint32_t)x & 0xffu);
-    if (k >= c) { k -= c; x >>= 8; pos += 8; }
-    uint32_t y = (uint32_t)x & 0xffu;
-    for (; k; k--) y &= y - 1;
-    return pos + (uint32_t)__builtin_ctz(y);
+    const uint32_t lo = (uint32_t)x;
+    uint32_t c = (uint32_t)__popc(lo);
+    const bool up = k >= c;
+    uint32_t w = up ? (uint32_t)(x >> 32) : lo;
+    k -= up ? c : 0;
+    uint32_t pos = up ? 32 : 0;
+#pragma unroll
+    for (uint32_t half = 16; half >= 1; half >>= 1) {
+        c = (uint32_t)__popc(w & ((1u << half) - 1));
+        const bool hi = k >= c;
+        k -= hi ? c : 0;
+        w = hi ? w >> half : w;
+        pos += hi ? half : 0;
+    }
+    return pos;
 }
 
 // Position of the k-th set bit at or after bit position p of an array of
 // `words` words; a position past the end if there is no such bit (only in a
 // corrupted structure).  Words after the first are read four at a time (the
 // loads are independent, so a long scan costs one memory round trip per four
-// words instead of one per word).
+// words instead of one per word); the loop only finds the word, and the one
+// in-word select runs after it.
 __device__ __forceinline__ uint64_t select_from(const uint64_t* a, uint64_t words, uint64_t p, uint64_t k) {
     uint64_t w = p >> 6;
     if (w >= words) return words << 6;
-    const uint64_t first = a[w] & (~0ull << (p & 63));
-    uint32_t c = (uint32_t)__popcll(first);
-    if (k < c) return (w << 6) + select_in_word(first, (uint32_t)k);
-    k -= c;
-    for (w++; w < words; w += 4) {
-        uint64_t x[4];
+    uint64_t x = a[w] & (~0ull << (p & 63));
+    uint32_t c = (uint32_t)__popcll(x);
+    if (k >= c) {
+        k -= c;
+        for (w++;; w += 4) {
+            if (w >= words) return words << 6;
+            uint64_t y[4];
 #pragma unroll
-        for (int u = 0; u < 4; u++) x[u] = w + u < words ? a[w + u] : 0;
-#pragma unroll
-        for (int u = 0; u < 4; u++) {
-            c = (uint32_t)__popcll(x[u]);
-            if (k < c) return ((w + u) << 6) + select_in_word(x[u], (uint32_t)k);
-            k -= c;
+            for (int u = 0; u < 4; u++) y[u] = w + u < words ? a[w + u] : 0;
+            const uint32_t c0 = (uint32_t)__popcll(y[0]), c1 = (uint32_t)__popcll(y[1]);
+            const uint32_t c2 = (uint32_t)__popcll(y[2]), c3 = (uint32_t)__popcll(y[3]);
+            const uint64_t s1 = c0, s2 = s1 + c1, s3 = s2 + c2, s4 = s3 + c3;
+            if (k < s4) {  // in this group: pick the word without branches
+                const bool b1 = k >= s1, b2 = k >= s2, b3 = k >= s3;
+                x = b3 ? y[3] : b2 ? y[2] : b1 ? y[1] : y[0];
+                k -= b3 ? s3 : b2 ? s2 : b1 ? s1 : 0;
+                w += (uint64_t)b1 + b2 + b3;
+                break;
+            }
+            k -= s4;
         }
     }
-    return words << 6;
+    return (w << 6) + select_in_word(x, (uint32_t)k);
 }
 
-// Positions of the k-th and the (k+1)-th set bits at or after bit p (the
-// second one is usually in the same word as the first).
+// Position of the first set bit at or after bit p (the end of a unary code,
+// or the next one of an Elias-Fano upper-bits array); a position past the end
+// if there is none (only in a corrupted structure).
+__device__ __forceinline__ uint64_t next_one(const uint64_t* a, uint64_t words, uint64_t p) {
+    uint64_t w = p >> 6;
+    if (w >= words) return words << 6;
+    uint64_t x = a[w] & (~0ull << (p & 63));
+    while (!x) {
+        if (++w >= words) return words << 6;
+        x = a[w];
+    }
+    return (w << 6) + (uint64_t)__builtin_ctzll(x);
+}
+
+// Positions of the k-th and the (k+1)-th set bits at or after bit p.
 __device__ __forceinline__ void select_pair(const uint64_t* a, uint64_t words, uint64_t p, uint64_t k,
                                             uint64_t& first, uint64_t& second) {
     first = select_from(a, words, p, k);
-    const uint64_t w = first >> 6;
-    if (w >= words) {
-        second = words << 6;
-        return;
-    }
-    const uint32_t b = (uint32_t)(first & 63);
-    const uint64_t rest = b == 63 ? 0 : a[w] & (~0ull << (b + 1));
-    second = rest ? (w << 6) + (uint64_t)__builtin_ctzll(rest) : select_from(a, words, (w + 1) << 6, 0);
-}
-
-// Position of the first set bit at or after bit p (the end of a unary code);
-// a position past the end if there is none (only in a corrupted structure).
-__device__ __forceinline__ uint64_t next_one(const uint64_t* a, uint64_t words, uint64_t p) {
-    const uint64_t w = p >> 6;
-    if (w >= words) return words << 6;
-    const uint64_t x = a[w] & (~0ull << (p & 63));
-    if (x) return (w << 6) + (uint64_t)__builtin_ctzll(x);
-    return select_from(a, words, (w + 1) << 6, 0);
+    second = first < (words << 6) ? next_one(a, words, first + 1) : words << 6;
 }
 
 // floor(x / d) for 1 <= d and x < 2^21: the single-precision estimate
@@ -397,7 +410,7 @@ extern "C" int rs_blob_from_host(const void* src, uint64_t bytes, void* stream, 
     b->al = current_alloc();
     int rc = b->al.get((void**)&b->words, bytes, s);
     if (!rc) rc = b->al.get((void**)&b->tables, 3ull * (L.maxm + 1) * 4, s);
-    if (!rc) rc = upload_tables((uint32_t)L.leaf, (uint32_t)L.maxm, b->tables, s);
+    if (!rc) rc = upload_tables((uint32_t)L.leaf, (uint32_t)L.maxm, L.gr_max, b->tables, s);
     if (!rc && hipMemcpyAsync(b->words, src, bytes, hipMemcpyHostToDevice, s) != hipSuccess)
         rc = fail(RS_EDEVICE, "copy to device failed");
     if (!rc && hipStreamSynchronize(s) != hipSuccess) rc = fail(RS_EDEVICE, "stream synchronisation failed");

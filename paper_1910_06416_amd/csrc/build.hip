@@ -65,6 +65,7 @@ struct BuildDesc {
     uint32_t group_cap;   // cap on log2 lanes per split candidate
     uint32_t waves;       // wavefronts of the bucket's workgroup that take nodes
     uint32_t bucket;      // the caller's bucket size b (header word)
+    uint32_t gr_max;      // splits above this size use the Sec. 7.2 approximation (0: none; header)
     // written by the device
     uint32_t maxm, flags;
     unsigned long long delta_s;
@@ -1480,7 +1481,7 @@ __device__ uint64_t geometry_of(BuildDesc& d, uint64_t* h) {
     h[4] = d.bucket;
     h[5] = nb;
     h[6] = d.maxm;
-    h[7] = (uint64_t)Ws | ((uint64_t)Wz << 8);
+    h[7] = (uint64_t)Ws | ((uint64_t)Wz << 8) | ((uint64_t)d.gr_max << 16);
     h[8] = d.delta_s;
     h[9] = (uint64_t)d.delta_z;
     h[10] = beta;
@@ -1901,7 +1902,7 @@ struct Batch {
     std::vector<std::string> why;
     std::vector<BuildDesc> hd;
     std::vector<uint32_t> which;  // desc index -> position in the call
-    std::vector<uint32_t> leaf_of_tab;
+    std::vector<std::pair<uint32_t, uint32_t>> tab_keys;  // (leaf, gr_max) of each table set
     uint64_t total = 0, nbuckets = 0, seed_cap = kDefaultSeedCap;
     uint32_t wait_limit = kDefaultWaitLimit;
     uint32_t K = 0, max_leaf = 1, launch_waves = 1;
@@ -1965,9 +1966,11 @@ int batch_prepare(Batch& b, const rs_keys* sets, uint32_t count, const uint32_t*
         d.lower = sg.lower;
         d.upper = sg.upper;
         d.bucket = bucket;
+        d.gr_max = opts ? opts->gr_table_max : 0;
+        const std::pair<uint32_t, uint32_t> key{leaf, d.gr_max};
         uint32_t t = 0;
-        while (t < b.leaf_of_tab.size() && b.leaf_of_tab[t] != leaf) t++;
-        if (t == b.leaf_of_tab.size()) b.leaf_of_tab.push_back(leaf);
+        while (t < b.tab_keys.size() && b.tab_keys[t] != key) t++;
+        if (t == b.tab_keys.size()) b.tab_keys.push_back(key);
         d.tab = t;
         d.aligned = ((uintptr_t)k.data & 7) == 0;
         d.delta_s = ~0ull;
@@ -2132,8 +2135,8 @@ int upload_batch_tables(Batch& b, uint32_t maxm, hipStream_t s) {
     b.table_maxm = maxm;
     b.stride = maxm + 1;
     uint32_t max_nodes = 0;
-    for (uint32_t t = 0; t < (uint32_t)b.leaf_of_tab.size(); t++) {
-        TableView tv = host_tables(b.leaf_of_tab[t], maxm);
+    for (uint32_t t = 0; t < (uint32_t)b.tab_keys.size(); t++) {
+        TableView tv = host_tables(b.tab_keys[t].first, maxm, b.tab_keys[t].second);
         if (!tv.data) return fail(RS_ENOMEM, "table allocation failed");
         for (uint32_t m = 0; m <= maxm; m++) max_nodes = std::max(max_nodes, tv.N()[m]);
         uint32_t* dst = b.d_tab + (size_t)t * kTableCount * b.stride;
@@ -2147,7 +2150,7 @@ int upload_batch_tables(Batch& b, uint32_t maxm, hipStream_t s) {
 }
 
 size_t table_words(const Batch& b, uint32_t maxm) {
-    return b.leaf_of_tab.size() * kTableCount * (size_t)(maxm + 1);
+    return b.tab_keys.size() * kTableCount * (size_t)(maxm + 1);
 }
 
 SearchArgs search_args(const Batch& b) {
@@ -2280,8 +2283,34 @@ void make_blobs(Batch& b, uint64_t* words, uint32_t* tables, uint32_t stride, co
     }
 }
 
+uint32_t lds_bucket_limit(Batch& b);
+
+// Largest bucket that n keys in nb buckets exceed with probability below
+// 1e-6: a bucket's count is Binomial(n, 1/nb), bounded by the heavier-tailed
+// Poisson(n / nb); the tail is summed downward from far above the mean.
+uint32_t bucket_size_cap(uint64_t n, uint64_t nb) {
+    const double lam = (double)n / (double)nb, target = 1e-6 / (double)nb;
+    const uint64_t k0 = (uint64_t)lam;
+    const uint64_t kmax = k0 + (uint64_t)(20.0 * std::sqrt(lam + 1.0)) + 40;
+    std::vector<double> pmf(kmax - k0 + 1);
+    double lp = (double)k0 * std::log(lam) - lam - std::lgamma((double)k0 + 1.0);
+    for (uint64_t k = k0; k <= kmax; k++) {
+        pmf[k - k0] = std::exp(lp);
+        lp += std::log(lam) - std::log((double)k + 1.0);
+    }
+    double tail = 0;  // P(X > c)
+    uint64_t c = kmax;
+    while (c > k0 && tail + pmf[c - k0] < target) tail += pmf[c-- - k0];
+    return (uint32_t)std::min<uint64_t>(std::max<uint64_t>(c, 1), n);
+}
+
+// maxm_hint: 0 = size the tables and the search's LDS for a bucket-size cap
+// estimated from the key and bucket counts, so that the call waits on its
+// stream only once (for the blob sizes); if a bucket exceeds the cap, the call
+// is made again with the largest bucket the first attempt measured.
 int build_batch_impl(const rs_keys* sets, uint32_t count, const uint32_t* leafs, const uint32_t* buckets,
-                     const rs_options* opts, hipStream_t s, rs_blob** outs, int* statuses, TuneCtx* tune) {
+                     const rs_options* opts, hipStream_t s, rs_blob** outs, int* statuses, TuneCtx* tune,
+                     uint32_t maxm_hint = 0) {
     if (!sets || !leafs || !buckets || !outs || count == 0) return fail(RS_EINVAL, "NULL argument or empty batch");
     const bool timing = opts && (opts->flags & RS_OPT_TIMING);
     Batch b;
@@ -2317,11 +2346,19 @@ int build_batch_impl(const rs_keys* sets, uint32_t count, const uint32_t* leafs,
     batch_bind(b, ws, pin);
 
     if (int rc = enqueue_front(b, s, &pe)) return cleanup(rc);
-    RS_TRY(hipMemcpyAsync(b.h_st, b.d_st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
-    RS_TRACE("signatures enqueued; waiting for the largest bucket");
-    RS_TRY(hipStreamSynchronize(s));
-    const uint32_t maxm = b.h_st->maxm;
-    RS_TRACE("largest bucket %u", maxm);
+    uint32_t maxm = maxm_hint;
+    const bool capped = !tune && !maxm_hint;
+    if (capped) {
+        for (const BuildDesc& d : b.hd) maxm = std::max(maxm, bucket_size_cap(d.n, d.nb));
+        maxm = std::min(maxm, lds_bucket_limit(b));
+        RS_TRACE("bucket-size cap %u", maxm);
+    } else if (!maxm) {
+        RS_TRY(hipMemcpyAsync(b.h_st, b.d_st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+        RS_TRACE("signatures enqueued; waiting for the largest bucket");
+        RS_TRY(hipStreamSynchronize(s));
+        maxm = b.h_st->maxm;
+        RS_TRACE("largest bucket %u", maxm);
+    }
     if (int rc = al.get((void**)&b.d_tab, table_words(b, maxm) * 4, s)) return cleanup(rc);
     if (int rc = upload_batch_tables(b, maxm, s)) return cleanup(rc);
     if (tune) {  // calibration only: no blob, the tables are not handed to an arena
@@ -2335,6 +2372,18 @@ int build_batch_impl(const rs_keys* sets, uint32_t count, const uint32_t* leafs,
     if (int rc = enqueue_readback(b, s)) return cleanup(rc);
     RS_TRACE("search enqueued (class %u); waiting for the sizes", b.max_leaf);
     RS_TRY(hipStreamSynchronize(s));
+    if (capped) {
+        bool over = false;
+        for (uint32_t j = 0; j < b.K; j++) over |= (b.h_desc[j].flags & kFlagTooBig) != 0;
+        if (over) {  // a bucket above the cap: again, sized for the largest bucket now known
+            const uint32_t exact = std::max(b.h_st->maxm, maxm + 1);
+            RS_TRACE("a bucket exceeds the cap %u; again with %u", maxm, exact);
+            pinned_release(s);
+            al.put(ws, s);
+            al.put(b.d_tab, s);
+            return build_batch_impl(sets, count, leafs, buckets, opts, s, outs, statuses, nullptr, exact);
+        }
+    }
     collect_status(b);
     const uint64_t arena_words = b.h_boff[b.K];
     RS_TRACE("sizes known (%llu blob words)", (unsigned long long)arena_words);
@@ -2353,7 +2402,7 @@ int build_batch_impl(const rs_keys* sets, uint32_t count, const uint32_t* leafs,
         g_stats.ms_device = pe.ms(0, 6);
         g_stats.n = b.total;
         g_stats.nb = b.nbuckets;
-        g_stats.maxm = maxm;
+        g_stats.maxm = b.h_st->maxm;
         g_stats.tree_bits = 0;
         for (uint32_t j = 0; j < b.K; j++) g_stats.tree_bits += b.h_desc[j].total_bits;
         g_stats.blob_bytes = arena_words * 8;
@@ -2422,8 +2471,8 @@ uint32_t lds_bucket_limit(Batch& b) {
     while (lo < hi) {
         const uint32_t mid = (lo + hi + 1) / 2;
         uint32_t nodes = 0;
-        for (uint32_t leaf : b.leaf_of_tab) {
-            TableView tv = host_tables(leaf, mid);
+        for (const auto& key : b.tab_keys) {
+            TableView tv = host_tables(key.first, mid, key.second);
             if (!tv.data) return 0;
             for (uint32_t m = 0; m <= mid; m++) nodes = std::max(nodes, tv.N()[m]);
         }

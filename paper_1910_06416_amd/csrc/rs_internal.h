@@ -107,10 +107,12 @@ struct TableView {
     const uint32_t* G() const { return data + 3 * (cap + 1); }
 };
 constexpr int kTableCount = 4;
-TableView host_tables(uint32_t leaf, uint32_t maxm);
+// gr_max > 0: split nodes of more than gr_max keys take the integer
+// approximation of their Golomb-Rice parameter (Sec. 7.2) instead of eq. (4).
+TableView host_tables(uint32_t leaf, uint32_t maxm, uint32_t gr_max = 0);
 // The same four tables for sizes 0..maxm written into dst (kTableCount *
 // (maxm + 1) words, r then F then N then G), without any allocation.
-void fill_tables(uint32_t leaf, uint32_t maxm, uint32_t* dst);
+void fill_tables(uint32_t leaf, uint32_t maxm, uint32_t* dst, uint32_t gr_max = 0);
 
 // ---------------------------------------------------------------------------
 // Device helpers.

@@ -35,6 +35,23 @@ double log_success(const Strategy& st, uint32_t m) {
     return lp;
 }
 
+// floor(lg x) for x >= 1 (lambda of Sec. 2).
+uint32_t floor_lg(uint64_t x) { return 63u - (uint32_t)__builtin_clzll(x); }
+
+// Integer approximation of the Golomb-Rice parameter of a large split
+// (Sec. 7.2): with parts k_0..k_{f-1} of m keys, half of
+// ((f-1) * 5 / 2, rounded down) + sum_i lambda(k_i + floor(k_i / 2)) - lambda(m),
+// rounded down; a non-positive sum gives 0.
+uint32_t rice_parameter_large(const Strategy& st, uint32_t m) {
+    const SplitShape sh = split_shape(m, st.leaf, st.lower, st.upper);
+    int64_t sum = (int64_t)((sh.fanout - 1) * 5 / 2) - (int64_t)floor_lg(m);
+    for (uint32_t j = 0; j < sh.fanout; j++) {
+        const uint64_t k = j + 1 == sh.fanout ? sh.last : sh.unit;
+        sum += floor_lg(k + k / 2);
+    }
+    return sum > 0 ? (uint32_t)(sum / 2) : 0u;
+}
+
 // Optimal Golomb-Rice parameter for a geometric source of parameter p (eq. (4)).
 uint32_t rice_parameter(double p) {
     const double log_golden = std::log((1.0 + std::sqrt(5.0)) * 0.5);
@@ -48,7 +65,7 @@ struct LeafTables {
 };
 
 std::mutex g_mu;
-std::map<uint32_t, LeafTables> g_cache;
+std::map<std::pair<uint32_t, uint32_t>, LeafTables> g_cache;  // by (leaf, gr_max)
 
 // Lanes per candidate for the split search of a node of m keys: the 2^g
 // minimising expected VALU work = steps * (keys per lane * cost per key +
@@ -78,7 +95,7 @@ uint32_t lanes_per_candidate(const Strategy& st, uint32_t m, double trials) {
     return best_g;
 }
 
-void fill(const Strategy& st, uint32_t cap, uint32_t* r, uint32_t* F, uint32_t* N, uint32_t* G) {
+void fill(const Strategy& st, uint32_t cap, uint32_t* r, uint32_t* F, uint32_t* N, uint32_t* G, uint32_t gr_max) {
     for (uint32_t m = 0; m <= cap; m++) {
         G[m] = 0;
         if (m < 2) {
@@ -86,7 +103,7 @@ void fill(const Strategy& st, uint32_t cap, uint32_t* r, uint32_t* F, uint32_t* 
             continue;
         }
         const double lp = log_success(st, m);
-        r[m] = rice_parameter(std::exp(lp));
+        r[m] = gr_max && m > st.leaf && m > gr_max ? rice_parameter_large(st, m) : rice_parameter(std::exp(lp));
         if (m > st.leaf) G[m] = lanes_per_candidate(st, m, std::exp(-lp));
         F[m] = r[m];
         N[m] = 1;
@@ -100,13 +117,13 @@ void fill(const Strategy& st, uint32_t cap, uint32_t* r, uint32_t* F, uint32_t* 
 
 }  // namespace
 
-void fill_tables(uint32_t leaf, uint32_t maxm, uint32_t* dst) {
-    fill(make_strategy(leaf), maxm, dst, dst + maxm + 1, dst + 2 * (maxm + 1), dst + 3 * (maxm + 1));
+void fill_tables(uint32_t leaf, uint32_t maxm, uint32_t* dst, uint32_t gr_max) {
+    fill(make_strategy(leaf), maxm, dst, dst + maxm + 1, dst + 2 * (maxm + 1), dst + 3 * (maxm + 1), gr_max);
 }
 
-TableView host_tables(uint32_t leaf, uint32_t maxm) {
+TableView host_tables(uint32_t leaf, uint32_t maxm, uint32_t gr_max) {
     std::lock_guard<std::mutex> lock(g_mu);
-    LeafTables& t = g_cache[leaf];
+    LeafTables& t = g_cache[{leaf, gr_max}];
     if (t.data == nullptr || t.cap < maxm) {
         uint32_t cap = std::max<uint32_t>(maxm, std::max<uint32_t>(1024u, t.cap * 2));
         uint32_t* buf = nullptr;
@@ -117,7 +134,7 @@ TableView host_tables(uint32_t leaf, uint32_t maxm) {
             buf = static_cast<uint32_t*>(std::malloc(bytes));
             if (!buf) return TableView{nullptr, 0};
         }
-        fill(make_strategy(leaf), cap, buf, buf + cap + 1, buf + 2 * (cap + 1), buf + 3 * (cap + 1));
+        fill(make_strategy(leaf), cap, buf, buf + cap + 1, buf + 2 * (cap + 1), buf + 3 * (cap + 1), gr_max);
         t.cap = cap;
         t.data = buf;  // the previous buffer is intentionally kept alive
     }
@@ -127,8 +144,13 @@ TableView host_tables(uint32_t leaf, uint32_t maxm) {
 }  // namespace rs
 
 extern "C" int rs_tables(uint32_t leaf, uint32_t maxm, uint32_t* r, uint32_t* F, uint32_t* N) {
+    return rs_tables_ex(leaf, maxm, 0, r, F, N);
+}
+
+extern "C" int rs_tables_ex(uint32_t leaf, uint32_t maxm, uint32_t gr_table_max, uint32_t* r, uint32_t* F,
+                            uint32_t* N) {
     if (leaf < 1 || leaf > rs::kMaxLeaf || !r || !F || !N) return RS_EINVAL;
-    rs::TableView t = rs::host_tables(leaf, maxm);
+    rs::TableView t = rs::host_tables(leaf, maxm, gr_table_max);
     if (!t.data) return RS_ENOMEM;
     for (uint32_t m = 0; m <= maxm; m++) {
         r[m] = t.r()[m];

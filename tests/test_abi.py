@@ -129,3 +129,16 @@ def test_set_allocator_validation_without_device(lib):
     recsplit.use_torch_allocator()
     assert lib.rs_set_allocator(None, None, None) == recsplit.RS_OK
     recsplit.use_torch_allocator()
+
+
+@pytest.mark.parametrize("leaf,T", [(8, 96), (8, 500), (16, 560), (16, 1200), (5, 31), (1, 4), (24, 216), (12, 97)])
+def test_library_tables_with_large_split_approximation_equal_oracle(orc, leaf, T):
+    """Splits above T take the integer approximation of Sec. 7.2 on both sides
+    (written independently); every table of sizes 0..4096 agrees."""
+    from paper_1910_06416_amd import recsplit
+
+    r, F, N = recsplit.tables(leaf, 4096, T)
+    r2, F2, N2 = orc.tables(leaf, 4096, T)
+    assert np.array_equal(r, r2) and np.array_equal(F, F2) and np.array_equal(N, N2)
+    r0, _, _ = recsplit.tables(leaf, 4096)
+    assert (r != r0).any()  # the approximation is in use above T

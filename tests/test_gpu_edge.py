@@ -156,3 +156,23 @@ def test_split_nodes_at_large_leaf_sizes(rs, orc, row):
         ranks = rs.lookup(blob, dk)
         assert np.array_equal(ranks.cpu().numpy().view(np.uint64), orc.lookup(want, keys))
         assert _is_permutation(ranks)
+
+
+def test_bucket_above_the_estimated_cap_builds_again(rs, orc):
+    """A build waits once: its search is sized for a bucket-size cap estimated
+    from n and b.  Keys crowded into one bucket far above that cap make the
+    first attempt flag the bucket, and the call runs again sized for it; the
+    structure equals the oracle's."""
+    n, leaf, bucket = 20_000, 8, 100
+    nb = n // bucket
+    pool = inputs.u64_keys(40 * n, 86)
+    hi, _ = orc.fingerprint(pool)
+    ids = orc.bucket_ids(hi, nb)
+    crowd = pool[ids == 0][:400]  # four times the mean in bucket 0
+    rest = pool[ids != 0][: n - len(crowd)]
+    keys = np.concatenate([crowd, rest])
+    assert len(crowd) == 400 and len(keys) == n
+    print("case crowded bucket", flush=True)
+    blob = rs.build(rs.device_keys(keys), leaf, bucket, timing=True)
+    assert rs.last_build_stats()["maxm"] == 400
+    assert blob.to_bytes() == orc.build(keys, leaf, bucket)

@@ -56,6 +56,24 @@ def test_blob_parity_u64_shapes(rs, orc, n, leaf, bucket):
     _check_build(rs, orc, inputs.u64_keys(n, 1000 + n + leaf), leaf, bucket)
 
 
+@pytest.mark.parametrize("n,leaf,bucket,T", [(20000, 8, 1000, 300), (6000, 5, 2000, 31), (9000, 12, 3000, 250),
+                                             (30000, 8, 100, 96)])
+def test_blob_parity_large_split_approximation(rs, orc, n, leaf, bucket, T):
+    """Golomb-Rice parameters of splits above T from the integer approximation
+    of Sec. 7.2: blob bytes, ranks, and a round trip through host bytes."""
+    keys = inputs.u64_keys(n, 4000 + T)
+    print(f"case gr approximation n={n} leaf={leaf} bucket={bucket} T={T}", flush=True)
+    blob = rs.build(rs.device_keys(keys), leaf, bucket, gr_table_max=T)
+    want = orc.build(keys, leaf, bucket, gr_table_max=T)
+    got = blob.to_bytes()
+    assert got == want, _first_difference(got, want, orc)
+    assert orc.header(got)["gr_table_max"] == T
+    ranks = rs.lookup(blob, rs.device_keys(keys)).cpu().numpy().view(np.uint64)
+    assert np.array_equal(ranks, orc.lookup(want, keys))
+    again = rs.from_bytes(want)
+    assert np.array_equal(rs.lookup(again, rs.device_keys(keys)).cpu().numpy().view(np.uint64), ranks)
+
+
 def test_blob_parity_cfg_100k_l8_b100(rs, orc):
     """100,000 uniform random 64-bit keys, l=8, b=100."""
     blob, want = _check_build(rs, orc, inputs.u64_keys(100_000, 1), 8, 100)
