@@ -56,22 +56,83 @@ def percentile(xs, q):
     return float(np.percentile(np.asarray(xs, dtype=np.float64), q))
 
 
-def cpu_baseline(keys_host, n_sample, leaf, bucket):
-    """The CPU oracle, single-threaded, on the first n_sample keys."""
-    import numpy as np
-
+def cpu_baseline(keys_host, n_sample, leaf, bucket, gpu_blob=None):
+    """The CPU oracle on the string workload: single-threaded on the first
+    n_sample keys, and bucket-parallel (the oracle's own per-bucket tree loop
+    in one process per host core, at most 16) on all keys, whose bytes are
+    compared with the GPU's structure."""
     import oracle
+    from oracle import parallel
 
     data, offsets = keys_host
+    n = len(offsets) - 1
     sub_off = offsets[: n_sample + 1].copy()
     sub = (data[: int(sub_off[-1])], sub_off)
     t0 = time.perf_counter()
     blob = oracle.build(sub, leaf, bucket)
     dt = time.perf_counter() - t0
+    workers = parallel.default_workers()
+    pblob, timing = parallel.build(keys_host, leaf, bucket, workers=workers)
     return {"value": n_sample / dt, "unit": "keys/s", "cores": 1, "kind": "oracle",
-            "sample": f"first {n_sample:,} of the {len(offsets) - 1:,} strings, l={leaf}, b={bucket}, "
-                      f"fingerprint to serialized blob in memory ({dt:.1f} s)",
-            "bits_per_key": 8.0 * len(blob) / n_sample}
+            "sample": f"first {n_sample:,} of the {n:,} strings, l={leaf}, b={bucket}, "
+                      f"fingerprint to serialized blob in memory ({dt:.1f} s, one thread)",
+            "bits_per_key": 8.0 * len(blob) / n_sample,
+            "all_cores": {"value": n / timing["wall_s"], "unit": "keys/s", "cores": timing["workers"],
+                          "sample": f"all {n:,} strings; trees of bucket ranges in {timing['workers']} processes, "
+                                    f"layout and encoding in one ({timing['wall_s']:.1f} s wall, "
+                                    f"{timing['tree_core_s']:.1f} core-s of trees)",
+                          "timing": timing,
+                          "same_bytes_as_gpu": None if gpu_blob is None else pblob == gpu_blob}}
+
+
+def cpu_baseline_l16(keys_host, n_sub, leaf, bucket, n_full, single_buckets):
+    """The oracle at l=16, b=2000 on the first n_sub keys of the workload
+    (n_sub / b buckets): every bucket's tree in one process per host core (at
+    most 16), and a few buckets one after another in one process; the rates
+    are extrapolated to n_full keys (construction time is linear in n, Sec. 5),
+    with standard errors from the per-bucket times."""
+    import numpy as np
+
+    from oracle import parallel
+
+    import oracle
+
+    sub = keys_host[:n_sub]
+    nb = -(-n_sub // bucket)
+    layout = oracle.bucket_layout(sub, nb)
+    s_ = layout[1]
+    sizes = (s_[1:] - s_[:-1]).astype(np.float64)
+    workers = parallel.default_workers()
+    t0 = time.perf_counter()
+    res = parallel.bucket_trees(sub, leaf, bucket, range(nb), workers=workers, layout=layout)
+    wall = time.perf_counter() - t0
+    per_key = np.array([res[i][2] / sizes[i] for i in range(nb)])  # core-s per key of each bucket
+    # single thread: the first buckets one after another in one process
+    t1 = time.perf_counter()
+    one = parallel.bucket_trees(sub, leaf, bucket, range(single_buckets), workers=1, layout=layout)
+    wall1 = time.perf_counter() - t1
+    per_key1 = np.array([one[i][2] / sizes[i] for i in range(single_buckets)])
+    rate1 = float(sizes[:single_buckets].sum() / sum(one[i][2] for i in range(single_buckets)))
+    rate_all = n_sub / wall
+
+    def proj(per_key_arr, scale):
+        se = float(per_key_arr.std(ddof=1) / np.sqrt(len(per_key_arr))) if len(per_key_arr) > 1 else None
+        return (float(per_key_arr.mean()) * n_full / scale, None if se is None else se * n_full / scale)
+
+    p1, se1 = proj(per_key1, 1.0)
+    pa, sea = proj(per_key, workers)
+    return {
+        "single_thread": {"value": rate1, "unit": "keys/s", "cores": 1,
+                          "sample": f"{single_buckets} buckets ({int(sizes[:single_buckets].sum()):,} keys) of the "
+                                    f"first {n_sub:,} keys, one after another ({wall1:.1f} s)",
+                          "projected_s_for_n": p1, "projected_se_s": se1},
+        "all_cores": {"value": rate_all, "unit": "keys/s", "cores": workers,
+                      "sample": f"all {nb} buckets of the first {n_sub:,} keys, one per task in {workers} processes "
+                                f"({wall:.1f} s wall)",
+                      "projected_s_for_n": n_full / rate_all, "projected_se_s": sea,
+                      "per_bucket_core_s_mean": float(np.mean([res[i][2] for i in range(nb)]))},
+        "n": n_full, "leaf": leaf, "bucket": bucket,
+    }
 
 
 def main():
@@ -83,12 +144,21 @@ def main():
     ap.add_argument("--l16-n", type=int, default=10_000_000, help="keys of the l=16, b=2000 build (0: skip)")
     ap.add_argument("--latency-builds", type=int, default=30, help="repeated 100,000-key builds for p50/p99")
     ap.add_argument("--cpu-sample", type=int, default=1_000_000, help="oracle sample size (0: skip)")
+    ap.add_argument("--cpu-l16-single", type=int, default=3,
+                    help="buckets of the l=16 oracle leg timed one after another in one process")
+    ap.add_argument("--l16-builds", type=int, default=3, help="timed l=16, b=2000 builds (p50/p99)")
     ap.add_argument("--workload", choices=["single", "batch", "serve", "table"], default="single",
                     help="single: 10M strings l=8 b=100 (+ l=16 point); batch: 4096 uneven builds, l=12 b=1000; "
                          "serve: Poisson stream of uneven build requests and 1M-key lookups; "
                          "table: the paper's Table tab:1M rows (10^6 random keys at four (l, b) points)")
     ap.add_argument("--table-n", type=int, default=1_000_000, help="table: keys per row")
     ap.add_argument("--batch-builds", type=int, default=4096)
+    ap.add_argument("--batch-steps", type=int, default=1, help="timed batched calls of the 4096-build workload")
+    ap.add_argument("--no-batch", action="store_true", help="single workload: skip the batched-build summary")
+    ap.add_argument("--no-serve", action="store_true", help="single workload: skip the serving summary")
+    ap.add_argument("--serve-requests", type=int, default=40, help="single workload: requests of the serving run")
+    ap.add_argument("--serve-load", type=float, default=1.2,
+                    help="single workload: offered load of the serving run (above 1 saturates the plain path)")
     ap.add_argument("--requests", type=int, default=60, help="serve: build requests")
     ap.add_argument("--load", type=float, default=0.6, help="serve: offered load (fraction of modelled capacity)")
     ap.add_argument("--lookup-cus", type=int, default=0,
@@ -123,10 +193,10 @@ def main():
     torch.cuda.set_device(0)
     recsplit.lib()
     if args.workload == "batch":
-        print(json.dumps(bench_batch(args)), flush=True)
+        print(json.dumps(bench_batch(args, args.steps)), flush=True)
         return
     if args.workload == "serve":
-        print(json.dumps(bench_serve(args)), flush=True)
+        print(json.dumps(bench_serve(args, args.requests, args.load)), flush=True)
         return
     if args.workload == "table":
         print(json.dumps(bench_table(args)), flush=True)
@@ -179,6 +249,7 @@ def main():
     srt, _ = torch.sort(ranks)
     assert torch.equal(srt, torch.arange(n, dtype=torch.int64, device="cuda")), "lookups are not a bijection"
     bits_per_key = blob.bits_per_key()
+    gpu_blob = blob.to_bytes() if args.cpu_sample else None
     blob.free()
 
     mean_build = float(np.mean(build_s))
@@ -279,35 +350,57 @@ def main():
             schedules["l16_b2000"] = tune(recsplit, 16, 2000, args, args.l16_n)
         warm = recsplit.build(recsplit.device_keys(inputs.u64_keys(4000, 5)), 16, 2000, timing=True, tuned=tuned)
         warm.free()
-        log(f"[bench] l=16 b=2000 build of {args.l16_n:,} keys ...")
-        torch.cuda.synchronize()
-        tb = time.perf_counter()
-        b16 = recsplit.build(d16, 16, 2000, timing=True, tuned=tuned)
-        dt16 = time.perf_counter() - tb
-        st16 = recsplit.last_build_stats()
-        bpk16 = b16.bits_per_key()
-        r16 = recsplit.lookup(b16, d16)
-        srt16, _ = torch.sort(r16)
-        assert torch.equal(srt16, torch.arange(args.l16_n, dtype=torch.int64, device="cuda"))
-        b16.free()
-        ev16 = EVALS_PER_KEY[(16, 2000)] * args.l16_n / (st16["ms_search"] * 1e-3)
+        t16, s16 = [], []
+        for k in range(max(1, args.l16_builds)):
+            log(f"[bench] l=16 b=2000 build {k + 1}/{args.l16_builds} of {args.l16_n:,} keys ...")
+            torch.cuda.synchronize()
+            tb = time.perf_counter()
+            b16 = recsplit.build(d16, 16, 2000, timing=True, tuned=tuned)
+            t16.append(time.perf_counter() - tb)
+            st16 = recsplit.last_build_stats()
+            s16.append(st16["ms_search"])
+            bpk16 = b16.bits_per_key()
+            r16 = recsplit.lookup(b16, d16)
+            srt16, _ = torch.sort(r16)
+            assert torch.equal(srt16, torch.arange(args.l16_n, dtype=torch.int64, device="cuda"))
+            b16.free()
+            del r16, srt16
+        dt16 = float(np.mean(t16))
+        ev16 = EVALS_PER_KEY[(16, 2000)] * args.l16_n / (float(np.mean(s16)) * 1e-3)
         result["l16_b2000"] = {
-            "n": args.l16_n, "keys_per_s": args.l16_n / dt16, "build_s": dt16, "search_ms": st16["ms_search"],
-            "bits_per_key": bpk16, "evals_per_s": ev16,
+            "n": args.l16_n, "keys_per_s": args.l16_n / dt16, "build_s": dt16, "builds": len(t16),
+            "build_p50_s": percentile(t16, 50), "build_p99_s": percentile(t16, 99), "build_s_all": t16,
+            "search_ms": float(np.mean(s16)), "bits_per_key": bpk16, "evals_per_s": ev16,
             "valu_frac": ev16 * slots / 1e12 / VALU_PEAK_TOPS if slots else None,
         }
         log(f"[bench] l=16: {args.l16_n / dt16:,.0f} keys/s, {bpk16:.4f} bits/key")
 
+    if not args.no_batch:
+        log("[bench] batched builds: 4096 builds, l=12, b=1000 (batched call, plan, one call per build)")
+        bb = bench_batch(args, args.batch_steps)
+        result["batch_4096_l12_b1000"] = {k: bb[k] for k in (
+            "value", "unit", "batched_s", "plain_s", "speedup_vs_plain", "plan_run_s", "plain_keys_per_s",
+            "bits_per_key", "search_ms", "plain_build_latency_ms", "roofline", "config")}
+    if not args.no_serve:
+        log(f"[bench] serving: {args.serve_requests} requests at offered load {args.serve_load}")
+        sv = bench_serve(args, args.serve_requests, args.serve_load, tuned=False)
+        result["serve"] = {k: sv[k] for k in ("value", "unit", "served", "plain", "config")}
+        result["serve"]["p99_vs_plain"] = sv["plain"]["p99_ms"] / sv["served"]["p99_ms"]
+        result["serve"]["makespan_vs_plain"] = sv["plain"]["makespan_s"] / sv["served"]["makespan_s"]
     result["schedules"] = schedules if tuned else "built-in"
     if args.cpu_sample:
-        log(f"[bench] CPU oracle on {args.cpu_sample:,} keys ...")
-        result["cpu_baseline"] = cpu_baseline(keys_host, args.cpu_sample, leaf, bucket)
+        log(f"[bench] CPU oracle on {args.cpu_sample:,} keys (one thread) and on all keys (all cores) ...")
+        result["cpu_baseline"] = cpu_baseline(keys_host, args.cpu_sample, leaf, bucket, gpu_blob)
         result["cpu_baseline"]["host_cpu"] = _cpu_model()
+        if args.l16_n:
+            log("[bench] CPU oracle at l=16, b=2000 on the first 100,000 keys ...")
+            result["cpu_baseline"]["l16_b2000"] = cpu_baseline_l16(k16, min(100_000, args.l16_n), 16, 2000,
+                                                                   args.l16_n, args.cpu_l16_single)
 
     print(json.dumps(result), flush=True)
 
 
-def bench_batch(args):
+def bench_batch(args, steps):
     """4096 independent builds of uniform random 64-bit keys, sizes log-uniform
     in [1e3, 1e6], l=12, b=1000: one batched call against one call per build."""
     import numpy as np
@@ -330,7 +423,7 @@ def bench_batch(args):
     # batched: warm-up on a small slice, then the timed call(s)
     recsplit.build_batch(sets[:8], leaf, bucket, tuned=tuned)
     times, stats = [], None
-    for k in range(max(1, args.steps)):
+    for k in range(max(1, steps)):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         blobs, status = recsplit.build_batch(sets, leaf, bucket, timing=True, tuned=tuned)
@@ -408,7 +501,7 @@ def bench_batch(args):
 EVALS_BY_LEAF = {8: 494.0, 12: 1.39e4, 16: 8.90e5}
 
 
-def bench_serve(args):
+def bench_serve(args, requests, load, tuned=None):
     """Poisson arrivals of build requests (sizes log-uniform in [1e4, 1e7], l in
     {8, 12, 16}, b in {100, 1000, 2000}) interleaved with 1M-key lookup batches,
     served with continuous batching; the same arrival schedule replayed through
@@ -419,12 +512,12 @@ def bench_serve(args):
     from paper_1910_06416_amd import inputs, recsplit
 
     rng = np.random.Generator(np.random.PCG64(6))
-    R = args.requests
+    R = requests
     sizes = inputs.log_uniform_sizes(R, 6, 1e4, 1e7)
     leafs = rng.choice([8, 12, 16], size=R)
     buckets = rng.choice([100, 1000, 2000], size=R)
     work_s = np.array([EVALS_BY_LEAF[int(l)] * int(n) for n, l in zip(sizes, leafs)]) / 1.3e12
-    rate = args.load / work_s.mean()
+    rate = load / work_s.mean()
     arrivals = np.cumsum(rng.exponential(1.0 / rate, size=R))
     lookup_times = np.cumsum(rng.exponential(1.0 / rate, size=R))
     total = int(sizes.sum())
@@ -433,7 +526,7 @@ def bench_serve(args):
     allkeys = recsplit.device_keys(inputs.u64_keys(total, 6))
     offs = np.concatenate([[0], np.cumsum(sizes)])
     sets = [allkeys[int(offs[i]):int(offs[i + 1])] for i in range(R)]
-    tuned = not args.no_tune
+    tuned = (not args.no_tune) if tuned is None else tuned
     schedules = {}
     if tuned:
         for l_ in (8, 12, 16):
@@ -505,7 +598,7 @@ def bench_serve(args):
         "ms_per_step": served_s * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "u64", "data": "synthetic",
         "config": {"workload": f"{R} Poisson build requests, sizes log-uniform [1e4, 1e7], l in {{8,12,16}}, "
-                               f"b in {{100,1000,2000}}, offered load {args.load}, plus 1M-key lookup batches",
+                               f"b in {{100,1000,2000}}, offered load {load}, plus 1M-key lookup batches",
                    "keys": total},
         "served": {"makespan_s": served_s, "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
                    "lookup_p50_ms": percentile(lk_lat, 50) if lk_lat else None,
@@ -534,11 +627,13 @@ def bench_table(args):
     from paper_1910_06416_amd import inputs, recsplit
 
     n = args.table_n
-    if n > 100_000_000:
-        # a 10^9-key run of this workload faulted the GPU on its l=12, b=9 row
-        # (cause not found); larger tables stay off until it is
-        raise SystemExit("--table-n above 10^8 is disabled")
-    keys = recsplit.device_keys(inputs.u64_keys(n, 7))
+    if n > 100_000_000:  # distinct draws checked on the device (a host-side pass would sort 8 GB)
+        keys = recsplit.device_keys(inputs.u64_keys_raw(n, 7))
+        srt, _ = torch.sort(keys)
+        assert not bool((srt[1:] == srt[:-1]).any()), "duplicate keys drawn; use another seed"
+        del srt
+    else:
+        keys = recsplit.device_keys(inputs.u64_keys(n, 7))
     ranks = torch.empty(n, dtype=torch.int64, device="cuda")
     rows = []
     for (leaf, bucket), (p_bits, p_build, p_lookup) in PAPER_TAB_1M.items():

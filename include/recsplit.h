@@ -367,6 +367,14 @@ int rs_tables(uint32_t leaf, uint32_t maxm, uint32_t* r, uint32_t* F, uint32_t* 
  * Sec. 7.2 (and F with it). */
 int rs_tables_ex(uint32_t leaf, uint32_t maxm, uint32_t gr_table_max, uint32_t* r, uint32_t* F, uint32_t* N);
 
+/* The same tables as one 32-bit word per size (footnote of Sec. 7.2: one such
+ * table suffices for l >= 4 and b <= 2000): bits 0-4 hold r[m], bits 5-15
+ * N[m] and bits 16-31 F[m].  Lookups read it instead of the three arrays when
+ * every size of the structure fits.  packed: host array of maxm+1 words.
+ * Errors: RS_EINVAL (l outside [1,24], NULL, or some size up to maxm does not
+ * fit the fields), RS_ENOMEM. */
+int rs_tables_packed(uint32_t leaf, uint32_t maxm, uint32_t gr_table_max, uint32_t* packed);
+
 /* Library version string. */
 const char* rs_version(void);
 

@@ -69,8 +69,11 @@ def _declare(L):
     L.orc_split_parts.restype = U32
     L.orc_tree.argtypes = [P, U32, U32, U64, P, P, P, P]
     L.orc_build.argtypes = [U32, P, P, U64, U32, U32, U64, P, U64, P]
-    L.orc_build_ex.argtypes = [U32, P, P, U64, U32, U32, U64, U32, P, U64, P]
+    L.orc_build_ex.argtypes = [U32, P, P, U64, U32, U32, U64, U32, U32, P, U64, P]
+    L.orc_tables_slack.argtypes = [U32, U32, U32, U32, P, P, P, P]
+    L.orc_tree_slack.argtypes = [P, U32, U32, U32, U64, P, P, P, P]
     L.orc_tables_ex.argtypes = [U32, U32, U32, P, P, P]
+    L.orc_packed_table.argtypes = [U32, U32, U32, P]
     L.orc_lambda.argtypes = [U64]
     L.orc_lambda.restype = U32
     L.orc_gr_param_approx.argtypes = [U32, U32]
@@ -98,7 +101,7 @@ def _declare(L):
     for f in ("orc_tables", "orc_tree", "orc_build", "orc_lookup", "orc_bucket_sizes", "orc_blob_bucket",
               "orc_bucket_ranks", "orc_blob_prefix", "orc_blob_check_inventory", "orc_trees",
               "orc_build_with_trees", "orc_bucket_layout", "orc_ranks_from_tree", "orc_build_ex",
-              "orc_tables_ex"):
+              "orc_tables_ex", "orc_packed_table", "orc_tables_slack", "orc_tree_slack"):
         getattr(L, f).restype = ctypes.c_int
 
 
@@ -140,6 +143,31 @@ def phi(x: int, depth: int, v: int, m: int) -> int:
     return int(lib().orc_phi(x, depth, v, m))
 
 
+def range_tables(leaf: int, maxm: int, leaf_slack: int, gr_table_max: int = 0):
+    """Tables of the non-minimal variant: (r, F, N, Q), Q[m] the output range
+    of a subtree of m keys."""
+    r = np.zeros(maxm + 1, dtype=np.uint32)
+    F = np.zeros(maxm + 1, dtype=np.uint32)
+    N = np.zeros(maxm + 1, dtype=np.uint32)
+    Q = np.zeros(maxm + 1, dtype=np.uint64)
+    rc = lib().orc_tables_slack(leaf, maxm, gr_table_max, leaf_slack, _ptr(r), _ptr(F), _ptr(N), _ptr(Q))
+    if rc:
+        raise OracleError(rc, "tables_slack")
+    return r, F, N, Q
+
+
+def packed_table(leaf: int, maxm: int, gr_table_max: int = 0):
+    """One 32-bit word per size (r | N << 5 | F << 16), or None when some
+    size does not fit."""
+    out = np.zeros(maxm + 1, dtype=np.uint32)
+    rc = lib().orc_packed_table(leaf, maxm, gr_table_max, _ptr(out))
+    if rc == EINVAL:
+        return None
+    if rc:
+        raise OracleError(rc, "packed_table")
+    return out
+
+
 def lam(x: int) -> int:
     """lambda(x) = floor(lg x), the index of the highest set bit (Sec. 2)."""
     return int(lib().orc_lambda(x))
@@ -179,7 +207,7 @@ def tables(leaf: int, maxm: int, gr_table_max: int = 0):
     return r, F, N
 
 
-def tree(lo: np.ndarray, leaf: int, seed_cap: int = 0):
+def tree(lo: np.ndarray, leaf: int, seed_cap: int = 0, leaf_slack: int = 0):
     """Splitting tree of one bucket: (v, m, depth) arrays in preorder."""
     lo = np.ascontiguousarray(lo, dtype=np.uint64)
     m = len(lo)
@@ -188,21 +216,23 @@ def tree(lo: np.ndarray, leaf: int, seed_cap: int = 0):
     mm = np.zeros(cap, dtype=np.uint32)
     d = np.zeros(cap, dtype=np.uint32)
     cnt = U64()
-    rc = lib().orc_tree(_ptr(lo if m else np.zeros(1, np.uint64)), m, leaf, seed_cap, _ptr(v), _ptr(mm), _ptr(d),
-                        ctypes.byref(cnt))
+    rc = lib().orc_tree_slack(_ptr(lo if m else np.zeros(1, np.uint64)), m, leaf, leaf_slack, seed_cap, _ptr(v),
+                              _ptr(mm), _ptr(d), ctypes.byref(cnt))
     if rc:
         raise OracleError(rc, "tree")
     c = cnt.value
     return v[:c].copy(), mm[:c].copy(), d[:c].copy()
 
 
-def build(keys, leaf: int, bucket: int, seed_cap: int = 0, gr_table_max: int = 0) -> bytes:
+def build(keys, leaf: int, bucket: int, seed_cap: int = 0, gr_table_max: int = 0, leaf_slack: int = 0) -> bytes:
     """The serialized structure (gr_table_max: splits of more than that many
-    keys take the integer Golomb-Rice approximation of Sec. 7.2; 0 = none)."""
+    keys take the integer Golomb-Rice approximation of Sec. 7.2; 0 = none;
+    leaf_slack > 0: the non-minimal variant, leaves of m keys map into
+    m + ceil(m leaf_slack / 256) values)."""
     kind, data, offs, n = _keys(keys)
     size = U64()
     op = _ptr(offs) if offs is not None else None
-    args = (kind, _ptr(data), op, n, leaf, bucket, seed_cap, gr_table_max)
+    args = (kind, _ptr(data), op, n, leaf, bucket, seed_cap, gr_table_max, leaf_slack)
     rc = lib().orc_build_ex(*args, None, 0, ctypes.byref(size))
     if rc:
         raise OracleError(rc, "build")
@@ -407,7 +437,8 @@ def header(blob: bytes) -> dict:
     return {
         "magic": int(w[0]), "version": int(w[1]) & 0xFFFFFFFF, "kind": int(w[1]) >> 32, "n": int(w[2]),
         "leaf": int(w[3]), "bucket": int(w[4]), "nb": int(w[5]), "maxm": int(w[6]), "Ws": int(w[7]) & 0xFF,
-        "Wz": (int(w[7]) >> 8) & 0xFF, "gr_table_max": int(w[7]) >> 16, "delta_s": int(w[8]), "delta_z": int(np.int64(w[9])), "beta": int(w[10]),
+        "Wz": (int(w[7]) >> 8) & 0xFF, "gr_table_max": (int(w[7]) >> 16) & 0xFFFFFF,
+        "leaf_slack": (int(w[7]) >> 40) & 0xFF, "delta_s": int(w[8]), "delta_z": int(np.int64(w[9])), "beta": int(w[10]),
         "us_words": int(w[11]), "uz_words": int(w[12]), "lower_words": int(w[13]), "tree_words": int(w[14]),
         "tree_bits": int(w[15]),
     }

@@ -130,10 +130,12 @@ uint32_t orc_phi(uint64_t x, uint32_t depth, uint64_t v, uint32_t m) {
 /* ------------------------------------------------------------------------ */
 typedef struct {
     uint32_t leaf, lower, upper;
+    uint32_t slack; /* non-minimal variant: leaves of m >= 2 keys map into m + ceil(m slack / 256) values */
 } strategy;
 
 static strategy make_strategy(uint32_t leaf) {
     strategy st;
+    st.slack = 0;
     /* s = max(2, ceil(0.35 l + 0.5)) and t = ceil(0.21 l + 0.9) (2 for l < 7),
      * written over the integers as ceil((35 l + 50)/100), ceil((21 l + 90)/100). */
     uint32_t s = (35 * leaf + 50 + 99) / 100;
@@ -165,6 +167,27 @@ static uint32_t split_parts(const strategy* st, uint32_t m, uint32_t* parts, uin
     return f;
 }
 
+/* Non-minimal variant (the extension Sec. 9 names: a larger codomain).  A
+ * leaf of m >= 2 keys searches the first index whose hash is injective into
+ * leaf_range(m) = m + ceil(m slack / 256) values, and a subtree of m keys
+ * covers range(m) output values: 1 for a single key, leaf_range(m) for a
+ * leaf, the sum over the parts for a split.  slack = 0 is the minimal
+ * structure (range(m) = m). */
+static uint32_t leaf_range(const strategy* st, uint32_t m) {
+    return m <= 1 ? m : m + (m * st->slack + 255) / 256;
+}
+
+static uint32_t split_parts(const strategy* st, uint32_t m, uint32_t* parts, uint32_t* unit);
+
+static uint64_t subtree_range(const strategy* st, uint32_t m) {
+    if (m <= st->leaf) return leaf_range(st, m);
+    uint32_t parts[ORC_MAX_FANOUT], unit;
+    uint32_t f = split_parts(st, m, parts, &unit);
+    uint64_t r = 0;
+    for (uint32_t j = 0; j < f; j++) r += subtree_range(st, parts[j]);
+    return r;
+}
+
 /* Child of a hash value: the part whose range [j u, (j+1) u) holds it; the
  * last part takes everything from (f-1) u on. */
 static uint32_t child_of(uint32_t phi, uint32_t unit, uint32_t fanout) {
@@ -184,6 +207,12 @@ static double ln_factorial(uint32_t m) {
 /* ln of the success probability of a node: m!/m^m for a leaf (Sec. 5,
  * bijections); (m!/m^m) prod_j k_j^{k_j}/k_j! for a split (eq. (2)). */
 static double ln_success(const strategy* st, uint32_t m) {
+    if (m <= st->leaf && st->slack) {
+        /* injective into M = leaf_range(m) values: prod_{i<m} (M - i) / M */
+        double M = (double)leaf_range(st, m), lq = 0.0;
+        for (uint32_t i = 0; i < m; i++) lq += log((M - (double)i) / M);
+        return lq;
+    }
     double lp = ln_factorial(m) - (double)m * log((double)m);
     if (m <= st->leaf) return lp;
     uint32_t parts[ORC_MAX_FANOUT], unit;
@@ -242,9 +271,11 @@ double orc_ln_success(uint32_t leaf, uint32_t m) {
  * r follows eq. (4) for every leaf and for splits of at most gr_max keys;
  * splits of more than gr_max keys take the integer approximation of Sec. 7.2
  * (gr_max = 0: eq. (4) everywhere). */
-int orc_tables_ex(uint32_t leaf, uint32_t maxm, uint32_t gr_max, uint32_t* r, uint32_t* F, uint32_t* N) {
+static int tables_impl(uint32_t leaf, uint32_t maxm, uint32_t gr_max, uint32_t slack, uint32_t* r, uint32_t* F,
+                       uint32_t* N) {
     if (leaf < 1 || leaf > 24) return ORC_EINVAL;
     strategy st = make_strategy(leaf);
+    st.slack = slack;
     for (uint32_t m = 0; m <= maxm; m++) {
         if (m <= 1) {
             r[m] = 0; F[m] = 0; N[m] = 0;
@@ -266,8 +297,42 @@ int orc_tables_ex(uint32_t leaf, uint32_t maxm, uint32_t gr_max, uint32_t* r, ui
     return ORC_OK;
 }
 
+int orc_tables_ex(uint32_t leaf, uint32_t maxm, uint32_t gr_max, uint32_t* r, uint32_t* F, uint32_t* N) {
+    return tables_impl(leaf, maxm, gr_max, 0, r, F, N);
+}
+
 int orc_tables(uint32_t leaf, uint32_t maxm, uint32_t* r, uint32_t* F, uint32_t* N) {
     return orc_tables_ex(leaf, maxm, 0, r, F, N);
+}
+
+/* Tables of the non-minimal variant: r, F, N as orc_tables_ex (leaf r from the
+ * probability of an injection), and the output range Q[m] of a subtree. */
+int orc_tables_slack(uint32_t leaf, uint32_t maxm, uint32_t gr_max, uint32_t slack, uint32_t* r, uint32_t* F,
+                     uint32_t* N, uint64_t* Q) {
+    int rc = tables_impl(leaf, maxm, gr_max, slack, r, F, N);
+    if (rc) return rc;
+    strategy st = make_strategy(leaf);
+    st.slack = slack;
+    for (uint32_t m = 0; m <= maxm; m++) Q[m] = subtree_range(&st, m);
+    return ORC_OK;
+}
+
+/* The per-size tables in one 32-bit word per size (footnote of Sec. 7.2):
+ * bits 0-4 hold r, bits 5-15 the coded nodes N of the subtree and bits 16-31
+ * its fixed bits F.  ORC_EINVAL if some size up to maxm does not fit (the
+ * paper states that one such table suffices for l >= 4 and b <= 2000). */
+int orc_packed_table(uint32_t leaf, uint32_t maxm, uint32_t gr_max, uint32_t* out) {
+    uint32_t* r = malloc((maxm + 1) * 4);
+    uint32_t* F = malloc((maxm + 1) * 4);
+    uint32_t* N = malloc((maxm + 1) * 4);
+    int rc = ORC_ENOMEM;
+    if (r && F && N) rc = orc_tables_ex(leaf, maxm, gr_max, r, F, N);
+    for (uint32_t m = 0; rc == ORC_OK && m <= maxm; m++) {
+        if (r[m] >= 32 || N[m] >= 2048 || F[m] >= 65536) rc = ORC_EINVAL;
+        else out[m] = r[m] | (N[m] << 5) | (F[m] << 16);
+    }
+    free(r); free(F); free(N);
+    return rc;
 }
 
 void orc_strategy(uint32_t leaf, uint32_t* lower, uint32_t* upper) {
@@ -286,17 +351,19 @@ uint32_t orc_split_parts(uint32_t leaf, uint32_t m, uint32_t* parts) {
 /* ------------------------------------------------------------------------ */
 /* Searches (Sec. 4): the FIRST index v = 0, 1, 2, ... that works.            */
 /* ------------------------------------------------------------------------ */
-static int search_leaf(const uint64_t* keys, uint32_t m, uint32_t depth, uint64_t cap, uint64_t* out) {
+/* The first v whose hash into cod values (cod = m for a bijection, more for
+ * the non-minimal variant; cod <= 64) is injective on the leaf's keys. */
+static int search_leaf(const uint64_t* keys, uint32_t m, uint32_t cod, uint32_t depth, uint64_t cap, uint64_t* out) {
     for (uint64_t v = 0; v < cap; v++) {
-        uint32_t seen = 0; /* m <= 24 */
+        uint64_t seen = 0;
         int ok = 1;
         for (uint32_t i = 0; i < m; i++) {
-            uint32_t phi = orc_phi(keys[i], depth, v, m);
-            if (seen & (1u << phi)) {
+            uint32_t phi = orc_phi(keys[i], depth, v, cod);
+            if (seen & (1ULL << phi)) {
                 ok = 0;
                 break;
             }
-            seen |= 1u << phi;
+            seen |= 1ULL << phi;
         }
         if (ok) {
             *out = v;
@@ -337,7 +404,7 @@ static int build_tree(const strategy* st, uint64_t* keys, uint32_t m, uint32_t d
     uint64_t v;
     int rc;
     if (m <= st->leaf) {
-        rc = search_leaf(keys, m, depth, e->cap, &v);
+        rc = search_leaf(keys, m, leaf_range(st, m), depth, e->cap, &v);
         if (rc) return rc;
         e->v[e->count] = v; e->m[e->count] = m; e->d[e->count] = depth; e->count++;
         return ORC_OK;
@@ -368,10 +435,11 @@ static int build_tree(const strategy* st, uint64_t* keys, uint32_t m, uint32_t d
 
 /* One bucket's tree from its lower signature words: preorder lists of index,
  * node size and depth.  out_* must hold at least m entries. */
-int orc_tree(const uint64_t* lo, uint32_t m, uint32_t leaf, uint64_t seed_cap, uint64_t* out_v, uint32_t* out_m,
-             uint32_t* out_d, uint64_t* out_count) {
+int orc_tree_slack(const uint64_t* lo, uint32_t m, uint32_t leaf, uint32_t slack, uint64_t seed_cap,
+                   uint64_t* out_v, uint32_t* out_m, uint32_t* out_d, uint64_t* out_count) {
     if (leaf < 1 || leaf > 24) return ORC_EINVAL;
     strategy st = make_strategy(leaf);
+    st.slack = slack;
     uint64_t* keys = malloc((size_t)(m ? m : 1) * sizeof(uint64_t));
     uint64_t* tmp = malloc((size_t)(m ? m : 1) * sizeof(uint64_t));
     if (!keys || !tmp) { free(keys); free(tmp); return ORC_ENOMEM; }
@@ -384,16 +452,23 @@ int orc_tree(const uint64_t* lo, uint32_t m, uint32_t leaf, uint64_t seed_cap, u
     return rc;
 }
 
+int orc_tree(const uint64_t* lo, uint32_t m, uint32_t leaf, uint64_t seed_cap, uint64_t* out_v, uint32_t* out_m,
+             uint32_t* out_d, uint64_t* out_count) {
+    return orc_tree_slack(lo, m, leaf, 0, seed_cap, out_v, out_m, out_d, out_count);
+}
+
 /* Trees of buckets first..last-1 of a bucket-contiguous array of lower words
  * (bucket i holds sorted[s[i] .. s[i+1])).  Bucket i's coded nodes go to
  * node_v / node_m / node_d from slot s[i] on (a tree on m keys has at most m-1
  * coded nodes) and their count to node_count[i].  This is the tree loop of
  * orc_build; a test harness may run disjoint bucket ranges in separate
  * processes and pass the results to orc_build_with_trees. */
-int orc_trees(const uint64_t* sorted, const uint64_t* s, uint64_t first, uint64_t last, uint32_t leaf,
-              uint64_t seed_cap, uint64_t* node_v, uint32_t* node_m, uint32_t* node_d, uint64_t* node_count) {
+static int trees_impl(const uint64_t* sorted, const uint64_t* s, uint64_t first, uint64_t last, uint32_t leaf,
+                      uint32_t slack, uint64_t seed_cap, uint64_t* node_v, uint32_t* node_m, uint32_t* node_d,
+                      uint64_t* node_count) {
     if (leaf < 1 || leaf > 24) return ORC_EINVAL;
     strategy st = make_strategy(leaf);
+    st.slack = slack;
     if (!seed_cap) seed_cap = ORC_DEFAULT_SEED_CAP;
     for (uint64_t i = first; i < last; i++) {
         uint64_t m = s[i + 1] - s[i];
@@ -409,6 +484,11 @@ int orc_trees(const uint64_t* sorted, const uint64_t* s, uint64_t first, uint64_
         node_count[i] = e.count;
     }
     return ORC_OK;
+}
+
+int orc_trees(const uint64_t* sorted, const uint64_t* s, uint64_t first, uint64_t last, uint32_t leaf,
+              uint64_t seed_cap, uint64_t* node_v, uint32_t* node_m, uint32_t* node_d, uint64_t* node_count) {
+    return trees_impl(sorted, s, first, last, leaf, 0, seed_cap, node_v, node_m, node_d, node_count);
 }
 
 /* ------------------------------------------------------------------------ */
@@ -489,10 +569,14 @@ static uint32_t ef_width(uint64_t N, uint64_t U) {
 /* if cap is too small only the size is reported.                            */
 /* ------------------------------------------------------------------------ */
 static int build_impl(uint32_t kind, const void* data, const uint64_t* offsets, uint64_t n, uint32_t leaf,
-                      uint32_t bucket, uint64_t seed_cap, uint32_t gr_max, const uint64_t* given_v,
+                      uint32_t bucket, uint64_t seed_cap, uint32_t gr_max, uint32_t slack, const uint64_t* given_v,
                       const uint32_t* given_m, const uint64_t* given_count, void* out, uint64_t cap,
                       uint64_t* size) {
     if (n == 0 || leaf < 1 || leaf > 24 || bucket == 0 || !data || !size) return ORC_EINVAL;
+    if (gr_max >= (1u << 24) || slack > 255) return ORC_EINVAL;
+    strategy sts = make_strategy(leaf);
+    sts.slack = slack;
+    if (leaf_range(&sts, leaf) > 32) return ORC_EINVAL; /* a leaf's values fit one 32-bit mask */
     if (kind != ORC_KEYS_U64 && kind != ORC_KEYS_BYTES) return ORC_EINVAL;
     if (kind == ORC_KEYS_BYTES) {
         if (!offsets) return ORC_EINVAL;
@@ -508,10 +592,11 @@ static int build_impl(uint32_t kind, const void* data, const uint64_t* offsets, 
     uint64_t* node_v = malloc(n * 8);
     uint32_t *node_m = malloc(n * 4), *node_d = malloc(n * 4);
     uint64_t* node_count = calloc(nb, 8);
+    uint64_t* qs = calloc(nb + 1, 8); /* the first Elias-Fano list: prefix sums of the buckets' output ranges */
     uint32_t *r = NULL, *F = NULL, *N = NULL;
     uint64_t *tree = NULL, *lower = NULL, *up_s = NULL, *up_z = NULL, *ys = NULL, *yz = NULL;
     int64_t* z = NULL;
-    if (!hi || !lo || !sorted || !sz || !s || !o || !cursor || !node_v || !node_m || !node_d || !node_count)
+    if (!hi || !lo || !sorted || !sz || !s || !o || !cursor || !node_v || !node_m || !node_d || !node_count || !qs)
         goto done;
 
     if (kind == ORC_KEYS_U64) orc_fingerprint_u64((const uint64_t*)data, n, hi, lo);
@@ -537,7 +622,13 @@ static int build_impl(uint32_t kind, const void* data, const uint64_t* offsets, 
 
     r = malloc((maxm + 1) * 4); F = malloc((maxm + 1) * 4); N = malloc((maxm + 1) * 4);
     if (!r || !F || !N) goto done;
-    orc_tables_ex(leaf, (uint32_t)maxm, gr_max, r, F, N);
+    tables_impl(leaf, (uint32_t)maxm, gr_max, slack, r, F, N);
+    /* output ranges: s_i itself for the minimal structure; the range of a
+     * subtree grows strictly with its size (checked), so lookups recover a
+     * bucket's size from its range */
+    for (uint64_t i = 0; i < nb; i++) qs[i + 1] = qs[i] + (slack ? subtree_range(&sts, (uint32_t)sz[i]) : sz[i]);
+    for (uint32_t m = 1; slack && m <= maxm; m++)
+        if (subtree_range(&sts, m) <= subtree_range(&sts, m - 1)) { rc = ORC_EINVAL; goto done; }
 
     /* trees; bucket i's coded nodes are stored from slot s_i on (a tree on m
      * keys has at most m-1 coded nodes), or taken as given */
@@ -546,7 +637,7 @@ static int build_impl(uint32_t kind, const void* data, const uint64_t* offsets, 
         memcpy(node_m, given_m, n * 4);
         memcpy(node_count, given_count, nb * 8);
     } else {
-        rc = orc_trees(sorted, s, 0, nb, leaf, seed_cap, node_v, node_m, node_d, node_count);
+        rc = trees_impl(sorted, s, 0, nb, leaf, slack, seed_cap, node_v, node_m, node_d, node_count);
         if (rc) goto done;
         rc = ORC_ENOMEM;
     }
@@ -582,18 +673,18 @@ static int build_impl(uint32_t kind, const void* data, const uint64_t* offsets, 
     /* double Elias-Fano of s_i and z_i = o_i - floor(beta s_i), beta in 16.16
      * fixed point; each list is rescaled by its minimum gap (Sec. 6.3). */
     uint64_t Nn = nb + 1;
-    uint64_t beta = (total_bits << 16) / n;
+    uint64_t beta = (total_bits << 16) / qs[nb];
     z = malloc(Nn * 8); ys = malloc(Nn * 8); yz = malloc(Nn * 8);
     if (!z || !ys || !yz) goto done;
-    for (uint64_t i = 0; i < Nn; i++) z[i] = (int64_t)o[i] - (int64_t)((beta * s[i]) >> 16);
+    for (uint64_t i = 0; i < Nn; i++) z[i] = (int64_t)o[i] - (int64_t)((beta * qs[i]) >> 16);
     uint64_t delta_s = UINT64_MAX;
     int64_t delta_z = INT64_MAX;
     for (uint64_t i = 0; i + 1 < Nn; i++) {
-        if (s[i + 1] - s[i] < delta_s) delta_s = s[i + 1] - s[i];
+        if (qs[i + 1] - qs[i] < delta_s) delta_s = qs[i + 1] - qs[i];
         if (z[i + 1] - z[i] < delta_z) delta_z = z[i + 1] - z[i];
     }
     for (uint64_t i = 0; i < Nn; i++) {
-        ys[i] = s[i] - i * delta_s;
+        ys[i] = qs[i] - i * delta_s;
         yz[i] = (uint64_t)(z[i] - (int64_t)i * delta_z);
     }
     uint32_t Ws = ef_width(Nn, ys[Nn - 1]), Wz = ef_width(Nn, yz[Nn - 1]);
@@ -612,7 +703,7 @@ static int build_impl(uint32_t kind, const void* data, const uint64_t* offsets, 
     w[0] = ORC_MAGIC;
     w[1] = ORC_VERSION | ((uint64_t)kind << 32);
     w[2] = n; w[3] = leaf; w[4] = bucket; w[5] = nb; w[6] = maxm;
-    w[7] = (uint64_t)Ws | ((uint64_t)Wz << 8) | ((uint64_t)gr_max << 16);
+    w[7] = (uint64_t)Ws | ((uint64_t)Wz << 8) | ((uint64_t)gr_max << 16) | ((uint64_t)slack << 40);
     w[8] = delta_s; w[9] = (uint64_t)delta_z; w[10] = beta;
     w[11] = us_words; w[12] = uz_words; w[13] = lower_words; w[14] = tree_words; w[15] = total_bits;
     lower = w + ORC_HEADER_WORDS;
@@ -636,22 +727,28 @@ static int build_impl(uint32_t kind, const void* data, const uint64_t* offsets, 
 
 done:
     free(hi); free(lo); free(sorted); free(sz); free(s); free(o); free(cursor);
-    free(node_v); free(node_m); free(node_d); free(node_count);
+    free(node_v); free(node_m); free(node_d); free(node_count); free(qs);
     free(r); free(F); free(N); free(tree); free(z); free(ys); free(yz);
     return rc;
 }
 
 int orc_build(uint32_t kind, const void* data, const uint64_t* offsets, uint64_t n, uint32_t leaf, uint32_t bucket,
               uint64_t seed_cap, void* out, uint64_t cap, uint64_t* size) {
-    return build_impl(kind, data, offsets, n, leaf, bucket, seed_cap, 0, NULL, NULL, NULL, out, cap, size);
+    return build_impl(kind, data, offsets, n, leaf, bucket, seed_cap, 0, 0, NULL, NULL, NULL, out, cap, size);
 }
 
 /* orc_build with the Golomb-Rice parameters of splits of more than gr_max keys
  * from the integer approximation of Sec. 7.2 (recorded in the header, bits
- * 16.. of word 7). */
+ * 16-39 of word 7), and, for slack > 0, the non-minimal variant: leaves map
+ * injectively into m + ceil(m slack / 256) values and the first Elias-Fano
+ * list holds the prefix sums of the buckets' output ranges instead of their
+ * sizes (slack in bits 40-47 of word 7).  Keys then map one-to-one into
+ * [0, N), N the last value of that list. */
 int orc_build_ex(uint32_t kind, const void* data, const uint64_t* offsets, uint64_t n, uint32_t leaf,
-                 uint32_t bucket, uint64_t seed_cap, uint32_t gr_max, void* out, uint64_t cap, uint64_t* size) {
-    return build_impl(kind, data, offsets, n, leaf, bucket, seed_cap, gr_max, NULL, NULL, NULL, out, cap, size);
+                 uint32_t bucket, uint64_t seed_cap, uint32_t gr_max, uint32_t slack, void* out, uint64_t cap,
+                 uint64_t* size) {
+    return build_impl(kind, data, offsets, n, leaf, bucket, seed_cap, gr_max, slack, NULL, NULL, NULL, out, cap,
+                      size);
 }
 
 /* orc_build with every bucket's tree supplied (as orc_trees writes them, for
@@ -662,7 +759,7 @@ int orc_build_with_trees(uint32_t kind, const void* data, const uint64_t* offset
                          uint32_t bucket, const uint64_t* node_v, const uint32_t* node_m, const uint64_t* node_count,
                          void* out, uint64_t cap, uint64_t* size) {
     if (!node_v || !node_m || !node_count) return ORC_EINVAL;
-    return build_impl(kind, data, offsets, n, leaf, bucket, 0, 0, node_v, node_m, node_count, out, cap, size);
+    return build_impl(kind, data, offsets, n, leaf, bucket, 0, 0, 0, node_v, node_m, node_count, out, cap, size);
 }
 
 /* Bucket-contiguous lower signature words of a key set (each bucket sorted
@@ -702,7 +799,8 @@ out:
 typedef struct {
     uint64_t n, leaf, nb, maxm, kind;
     strategy st;
-    uint64_t* s; /* nb+1 prefix sums */
+    uint64_t* Q; /* output range of a subtree of each size 0..maxm */
+    uint64_t* s; /* nb+1 prefix sums of the buckets' output ranges (of their sizes if minimal) */
     uint64_t* o; /* nb+1 bit offsets */
     const uint64_t* tree;
     uint32_t* r;
@@ -735,15 +833,15 @@ static uint64_t descend(const decoded* dc, uint64_t x, uint32_t m, uint32_t dept
                         uint32_t* idx) {
     if (m <= 1) return 0;
     uint64_t v = vs[(*idx)++];
+    if (m <= dc->st.leaf) return orc_phi(x, depth, v, leaf_range(&dc->st, m));
     uint32_t phi = orc_phi(x, depth, v, m);
-    if (m <= dc->st.leaf) return phi;
     uint32_t parts[ORC_MAX_FANOUT], unit;
     uint32_t f = split_parts(&dc->st, m, parts, &unit);
     uint32_t j = child_of(phi, unit, f);
-    uint64_t left = 0;
+    uint64_t left = 0; /* the output values of the parts before the chosen one */
     for (uint32_t t = 0; t < j; t++) {
         *idx += coded_nodes(&dc->st, parts[t]);
-        left += parts[t];
+        left += dc->Q[parts[t]];
     }
     return left + descend(dc, x, parts[j], depth + 1, vs, idx);
 }
@@ -759,7 +857,8 @@ static int blob_open(const void* blob, uint64_t bytes, decoded* dc) {
     if (dc->leaf < 1 || dc->leaf > 24) return ORC_EFORMAT;
     dc->st = make_strategy((uint32_t)dc->leaf);
     uint32_t Ws = (uint32_t)(w[7] & 0xff), Wz = (uint32_t)((w[7] >> 8) & 0xff);
-    uint32_t gr_max = (uint32_t)(w[7] >> 16);
+    uint32_t gr_max = (uint32_t)((w[7] >> 16) & 0xffffff), slack = (uint32_t)((w[7] >> 40) & 0xff);
+    dc->st.slack = slack;
     uint64_t delta_s = w[8];
     int64_t delta_z = (int64_t)w[9];
     uint64_t beta = w[10], us_words = w[11], uz_words = w[12], lower_words = w[13], tree_words = w[14];
@@ -780,13 +879,14 @@ static int blob_open(const void* blob, uint64_t bytes, decoded* dc) {
     dc->s = malloc(Nn * 8);
     dc->o = malloc(Nn * 8);
     dc->r = malloc((dc->maxm + 1) * 4);
+    dc->Q = malloc((dc->maxm + 1) * 8);
     uint32_t* Ft = malloc((dc->maxm + 1) * 4);
     uint32_t* Nt = malloc((dc->maxm + 1) * 4);
-    if (!dc->s || !dc->o || !dc->r || !Ft || !Nt) {
+    if (!dc->s || !dc->o || !dc->r || !dc->Q || !Ft || !Nt) {
         free(Ft); free(Nt);
         return ORC_ENOMEM;
     }
-    orc_tables_ex((uint32_t)dc->leaf, (uint32_t)dc->maxm, gr_max, dc->r, Ft, Nt);
+    orc_tables_slack((uint32_t)dc->leaf, (uint32_t)dc->maxm, gr_max, slack, dc->r, Ft, Nt, dc->Q);
     free(Ft);
     free(Nt);
 
@@ -807,15 +907,25 @@ static int blob_open(const void* blob, uint64_t bytes, decoded* dc) {
 }
 
 static void blob_close(decoded* dc) {
-    free(dc->s); free(dc->o); free(dc->r);
-    dc->s = dc->o = NULL;
+    free(dc->s); free(dc->o); free(dc->r); free(dc->Q);
+    dc->s = dc->o = dc->Q = NULL;
     dc->r = NULL;
+}
+
+/* Size of bucket bk: the size whose subtree range is the bucket's range (the
+ * range grows strictly with the size; for the minimal structure they are
+ * equal). */
+static uint32_t bucket_size(const decoded* dc, uint64_t bk) {
+    uint64_t range = dc->s[bk + 1] - dc->s[bk];
+    for (uint32_t m = 0; m <= dc->maxm; m++)
+        if (dc->Q[m] == range) return m;
+    return 0; /* not a range of this structure: a corrupted blob */
 }
 
 /* Indices of the coded nodes of bucket bk, in preorder (Sec. 6.2): all fixed
  * parts first, then all unary parts.  sizes/vs hold maxm+1 entries. */
 static uint32_t bucket_codes(const decoded* dc, uint64_t bk, uint32_t* sizes, uint64_t* vs) {
-    uint32_t m = (uint32_t)(dc->s[bk + 1] - dc->s[bk]);
+    uint32_t m = bucket_size(dc, bk);
     uint32_t cnt = 0;
     preorder_sizes(&dc->st, m, sizes, &cnt);
     uint64_t pos = dc->o[bk];
@@ -847,7 +957,7 @@ int orc_lookup(const void* blob, uint64_t bytes, uint32_t kind, const void* data
         if (kind == ORC_KEYS_U64) orc_fingerprint_u64((const uint64_t*)data + qi, 1, &hi, &lo);
         else fingerprint_bytes_one((const uint8_t*)data + offsets[qi], offsets[qi + 1] - offsets[qi], &hi, &lo);
         uint64_t bk = bucket_of(hi, dc.nb);
-        uint32_t m = (uint32_t)(dc.s[bk + 1] - dc.s[bk]);
+        uint32_t m = bucket_size(&dc, bk);
         bucket_codes(&dc, bk, sizes, vs);
         uint32_t idx = 0;
         ranks[qi] = dc.s[bk] + descend(&dc, lo, m, 0, vs, &idx);
@@ -929,10 +1039,14 @@ int orc_ranks_from_tree(const uint64_t* lo, uint32_t m, uint32_t leaf, const uin
     memset(&dc, 0, sizeof(dc));
     dc.leaf = leaf;
     dc.st = make_strategy(leaf);
+    dc.Q = malloc(((size_t)m + 1) * 8); /* minimal structure: a subtree's range is its size */
+    if (!dc.Q) return ORC_ENOMEM;
+    for (uint32_t k = 0; k <= m; k++) dc.Q[k] = k;
     for (uint32_t i = 0; i < m; i++) {
         uint32_t idx = 0;
         ranks[i] = descend(&dc, lo[i], m, 0, v, &idx);
     }
+    free(dc.Q);
     return ORC_OK;
 }
 

@@ -95,9 +95,12 @@ Layout layout_of(const uint64_t* h) {
 int upload_tables(uint32_t leaf, uint32_t maxm, uint32_t gr_max, uint32_t* dst, hipStream_t s) {
     TableView tv = host_tables(leaf, maxm, gr_max);
     if (!tv.data) return fail(RS_ENOMEM, "table allocation failed");
-    RS_HIP(hipMemcpyAsync(dst, tv.r(), (maxm + 1) * 4ull, hipMemcpyHostToDevice, s));
-    RS_HIP(hipMemcpyAsync(dst + (maxm + 1), tv.F(), (maxm + 1) * 4ull, hipMemcpyHostToDevice, s));
-    RS_HIP(hipMemcpyAsync(dst + 2 * (maxm + 1), tv.N(), (maxm + 1) * 4ull, hipMemcpyHostToDevice, s));
+    const size_t w = maxm + 1;
+    RS_HIP(hipMemcpyAsync(dst, tv.r(), w * 4, hipMemcpyHostToDevice, s));
+    RS_HIP(hipMemcpyAsync(dst + w, tv.F(), w * 4, hipMemcpyHostToDevice, s));
+    RS_HIP(hipMemcpyAsync(dst + 2 * w, tv.N(), w * 4, hipMemcpyHostToDevice, s));
+    RS_HIP(hipMemcpyAsync(dst + 3 * w, tv.G(), w * 4, hipMemcpyHostToDevice, s));
+    RS_HIP(hipMemcpyAsync(dst + 4 * w, tv.P(), w * 4, hipMemcpyHostToDevice, s));
     return RS_OK;
 }
 
@@ -111,6 +114,7 @@ struct LookupArgs {
     const uint32_t* R;
     const uint32_t* F;
     const uint32_t* N;
+    const uint32_t* P;  // r | N << 5 | F << 16 per size (used when every size fits)
     uint64_t nb, beta, delta_s;
     int64_t delta_z;
     uint32_t Ws, Wz;
@@ -234,7 +238,29 @@ __device__ __forceinline__ void inventory_start(const uint64_t* blob, const Look
     }
 }
 
+// Per-size table reads of the descent: one packed word per size (footnote of
+// Sec. 7.2) when every size of the structure fits it, else three arrays.
+template <bool PACKED>
+struct SizeTables {
+    const LookupArgs& a;
+    __device__ uint32_t r(uint32_t m) const { return PACKED ? packed_r(a.P[m]) : a.R[m]; }
+    __device__ uint32_t F(uint32_t m) const { return PACKED ? packed_F(a.P[m]) : a.F[m]; }
+    // fixed bits and coded nodes of a subtree of size m, in one read when packed
+    __device__ void FN(uint32_t m, uint32_t& f, uint32_t& n) const {
+        if (PACKED) {
+            const uint32_t w = a.P[m];
+            f = packed_F(w);
+            n = packed_N(w);
+        } else {
+            f = a.F[m];
+            n = a.N[m];
+        }
+    }
+};
+
+template <bool PACKED>
 __device__ uint64_t rank_of(const LookupArgs& a, uint64_t hi, uint64_t lo) {
+    const SizeTables<PACKED> T{a};
     const uint64_t* blob = a.blob;
     const uint64_t i = bucket_of(hi, a.nb);
     // Elias-Fano: the i-th one of the upper bits is at (y_i >> W) + i.
@@ -264,9 +290,9 @@ __device__ uint64_t rank_of(const LookupArgs& a, uint64_t hi, uint64_t lo) {
     const bool small = a.maxm < (1u << 20);
     uint64_t c = 0;
     uint32_t d = 0;
-    uint64_t fp = o_i, up = o_i + a.F[m];
+    uint64_t fp = o_i, up = o_i + T.F(m);
     while (m > a.leaf) {
-        uint32_t r = a.R[m];
+        uint32_t r = T.r(m);
         uint64_t fixed = get_bits(tree, fp, r);
         fp += r;
         uint64_t one = next_one(tree, a.tree_words, up);
@@ -289,8 +315,10 @@ __device__ uint64_t rank_of(const LookupArgs& a, uint64_t hi, uint64_t lo) {
         const uint32_t ph = phi(lo, d, v, m);
         uint32_t j = min(small ? div_small(ph, sh.unit) : ph / sh.unit, sh.fanout - 1);
         if (j) {
-            fp += (uint64_t)j * a.F[sh.unit];
-            uint64_t skip = (uint64_t)j * a.N[sh.unit];
+            uint32_t fu, nu;
+            T.FN(sh.unit, fu, nu);
+            fp += (uint64_t)j * fu;
+            const uint64_t skip = (uint64_t)j * nu;
             if (skip) up = select_from(tree, a.tree_words, up, skip - 1) + 1;
         }
         c += (uint64_t)j * sh.unit;
@@ -298,7 +326,7 @@ __device__ uint64_t rank_of(const LookupArgs& a, uint64_t hi, uint64_t lo) {
         d++;
     }
     if (m >= 2) {
-        uint32_t r = a.R[m];
+        uint32_t r = T.r(m);
         uint64_t fixed = get_bits(tree, fp, r);
         uint64_t one = next_one(tree, a.tree_words, up);
         uint64_t v = ((one - up) << r) | fixed;
@@ -309,15 +337,17 @@ __device__ uint64_t rank_of(const LookupArgs& a, uint64_t hi, uint64_t lo) {
 
 // One query per lane; q0 is the launch's first query (lookups of more
 // queries than one grid holds are launched in chunks).
+template <bool PACKED>
 __global__ void k_lookup_u64(LookupArgs a, const uint64_t* __restrict__ keys, uint64_t q, uint64_t q0,
                              uint64_t* __restrict__ ranks) {
     uint64_t t = q0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= q) return;
     uint64_t hi, lo;
     signature_u64(keys[t], hi, lo);
-    ranks[t] = rank_of(a, hi, lo);
+    ranks[t] = rank_of<PACKED>(a, hi, lo);
 }
 
+template <bool PACKED>
 __global__ void k_lookup_bytes(LookupArgs a, const uint8_t* __restrict__ data, const uint64_t* __restrict__ offsets,
                                uint64_t q, uint64_t q0, bool aligned, uint64_t* __restrict__ ranks) {
     uint64_t t = q0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -327,7 +357,7 @@ __global__ void k_lookup_bytes(LookupArgs a, const uint8_t* __restrict__ data, c
     if (e < s || e > total) e = s = min(s, total);
     uint64_t hi, lo;
     signature_bytes(data, total, aligned, s, e, hi, lo);
-    ranks[t] = rank_of(a, hi, lo);
+    ranks[t] = rank_of<PACKED>(a, hi, lo);
 }
 
 }  // namespace
@@ -347,7 +377,7 @@ extern "C" int rs_lookup(const rs_blob* blob, const rs_keys* queries, uint64_t* 
     if (queries->kind == RS_KEYS_BYTES && !queries->offsets) return fail(RS_EINVAL, "NULL offsets");
     Strategy st = make_strategy((uint32_t)L.leaf);
     LookupArgs a{blob->words, blob->tables, blob->tables + blob->tab_stride, blob->tables + 2 * blob->tab_stride,
-                 L.nb, L.beta, L.delta_s, L.delta_z, L.Ws, L.Wz, L.lower_off, L.us_off, L.uz_off, L.inv_hi_off,
+                 blob->tables + 4 * blob->tab_stride, L.nb, L.beta, L.delta_s, L.delta_z, L.Ws, L.Wz, L.lower_off, L.us_off, L.uz_off, L.inv_hi_off,
                  L.inv_lo_off, L.tree_off, L.us_words, L.uz_words, L.tree_words, (uint32_t)L.leaf, st.lower,
                  st.upper, (uint32_t)L.maxm};
     hipStream_t s = (hipStream_t)stream;
@@ -358,12 +388,17 @@ extern "C" int rs_lookup(const rs_blob* blob, const rs_keys* queries, uint64_t* 
     if (int rc = for_each_chunk(q, block, block, [&](uint64_t q0, uint64_t, uint64_t grid) -> int {
             if (!grid_fits(grid, block))
                 return fail(RS_EINVAL, "lookup grid of %llu blocks does not fit", (unsigned long long)grid);
-            if (queries->kind == RS_KEYS_U64)
-                k_lookup_u64<<<(uint32_t)grid, block, 0, s>>>(a, (const uint64_t*)queries->data, q, q0, ranks_dev);
+            const bool al = ((uintptr_t)queries->data & 7) == 0;
+            const uint8_t* bytes = (const uint8_t*)queries->data;
+            if (queries->kind == RS_KEYS_U64 && blob->packed)
+                k_lookup_u64<true><<<(uint32_t)grid, block, 0, s>>>(a, (const uint64_t*)bytes, q, q0, ranks_dev);
+            else if (queries->kind == RS_KEYS_U64)
+                k_lookup_u64<false><<<(uint32_t)grid, block, 0, s>>>(a, (const uint64_t*)bytes, q, q0, ranks_dev);
+            else if (blob->packed)
+                k_lookup_bytes<true><<<(uint32_t)grid, block, 0, s>>>(a, bytes, queries->offsets, q, q0, al, ranks_dev);
             else
-                k_lookup_bytes<<<(uint32_t)grid, block, 0, s>>>(a, (const uint8_t*)queries->data, queries->offsets,
-                                                                q, q0, ((uintptr_t)queries->data & 7) == 0,
-                                                                ranks_dev);
+                k_lookup_bytes<false><<<(uint32_t)grid, block, 0, s>>>(a, bytes, queries->offsets, q, q0, al,
+                                                                       ranks_dev);
             return RS_OK;
         }))
         return rc;
@@ -409,7 +444,7 @@ extern "C" int rs_blob_from_host(const void* src, uint64_t bytes, void* stream, 
     memcpy(b->header, h, sizeof b->header);
     b->al = current_alloc();
     int rc = b->al.get((void**)&b->words, bytes, s);
-    if (!rc) rc = b->al.get((void**)&b->tables, 3ull * (L.maxm + 1) * 4, s);
+    if (!rc) rc = b->al.get((void**)&b->tables, (size_t)kTableCount * (L.maxm + 1) * 4, s);
     if (!rc) rc = upload_tables((uint32_t)L.leaf, (uint32_t)L.maxm, L.gr_max, b->tables, s);
     if (!rc && hipMemcpyAsync(b->words, src, bytes, hipMemcpyHostToDevice, s) != hipSuccess)
         rc = fail(RS_EDEVICE, "copy to device failed");
@@ -422,6 +457,10 @@ extern "C" int rs_blob_from_host(const void* src, uint64_t bytes, void* stream, 
     }
     b->bytes = bytes;
     b->tab_stride = (uint32_t)(L.maxm + 1);
+    {
+        const TableView tv = host_tables((uint32_t)L.leaf, (uint32_t)L.maxm, L.gr_max);
+        b->packed = tv.data && packed_valid(tv.P(), (uint32_t)L.maxm);
+    }
     b->ready = nullptr;  // complete: the copy above was waited for
     (void)hipGetDevice(&b->device);
     *out = b;

@@ -104,7 +104,7 @@ __device__ __forceinline__ uint32_t find_build(const uint64_t* __restrict__ base
 constexpr uint32_t kSigItems = 32;                 // keys per thread in the signature and bin passes
 constexpr uint32_t kSigTile = kBlock * kSigItems;  // keys per block
 constexpr uint32_t kMaxBins = 4096;
-constexpr uint32_t kMaxBinShift = 14;              // at most 16384 buckets per bin (two pieces)
+constexpr uint32_t kMaxBinShift = 16;              // at most 65536 buckets per bin (eight pieces)
 constexpr uint32_t kSortSpan = 8192;               // buckets a per-bin sort counts at once in LDS
 constexpr uint32_t kSortBlock = 512;               // threads of the per-bin sort
 
@@ -1029,7 +1029,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_search(SearchArgs a) {
         const uint32_t group_cap = __builtin_amdgcn_readfirstlane(B.group_cap);
         // waves beyond the build's count only join the barriers
         const uint32_t active = __builtin_amdgcn_readfirstlane(min(B.waves, (uint32_t)WAVES));
-        const uint32_t* R = a.tables + (size_t)__builtin_amdgcn_readfirstlane(B.tab) * 4 * a.stride;
+        const uint32_t* R = a.tables + (size_t)__builtin_amdgcn_readfirstlane(B.tab) * kTableCount * a.stride;
         const uint32_t* Nt = R + 2 * a.stride;
         const uint32_t* Gt = R + 3 * a.stride;
         uint32_t* bflags = &a.wdescs[j].flags;
@@ -1400,7 +1400,7 @@ __global__ __launch_bounds__(kBlock) void k_tree_bits(FillArgs a) {
     const uint64_t start = a.bstart[g];
     const uint32_t m0 = (uint32_t)(a.bstart[g + 1] - start);
     if (m0 <= 1) return;
-    const uint32_t* R = a.tables + (size_t)B.tab * 4 * a.stride;
+    const uint32_t* R = a.tables + (size_t)B.tab * kTableCount * a.stride;
     const uint32_t* F = R + a.stride;
     const uint32_t nodes = R[2 * a.stride + m0];
     unsigned long long* tree = B.blob + B.tree_off;
@@ -2144,6 +2144,7 @@ int upload_batch_tables(Batch& b, uint32_t maxm, hipStream_t s) {
         RS_ENQ(hipMemcpyAsync(dst + b.stride, tv.F(), b.stride * 4ull, hipMemcpyHostToDevice, s));
         RS_ENQ(hipMemcpyAsync(dst + 2 * b.stride, tv.N(), b.stride * 4ull, hipMemcpyHostToDevice, s));
         RS_ENQ(hipMemcpyAsync(dst + 3 * b.stride, tv.G(), b.stride * 4ull, hipMemcpyHostToDevice, s));
+        RS_ENQ(hipMemcpyAsync(dst + 4 * b.stride, tv.P(), b.stride * 4ull, hipMemcpyHostToDevice, s));
     }
     b.lds = (size_t)maxm * 8 + (size_t)max_nodes * 16;
     return RS_OK;
@@ -2275,6 +2276,11 @@ void make_blobs(Batch& b, uint64_t* words, uint32_t* tables, uint32_t stride, co
         blob->bytes = b.h_raw[j] * 8;
         blob->tables = tables + (size_t)b.h_desc[j].tab * kTableCount * stride;
         blob->tab_stride = stride;
+        {
+            const auto& key = b.tab_keys[b.h_desc[j].tab];
+            const TableView tv = host_tables(key.first, stride - 1, key.second);
+            blob->packed = tv.data && packed_valid(tv.P(), (uint32_t)b.h_hdr[(size_t)j * kHeaderWords + 6]);
+        }
         memcpy(blob->header, b.h_hdr + (size_t)j * kHeaderWords, sizeof blob->header);
         blob->ready = arena->ready;
         blob->device = dev;

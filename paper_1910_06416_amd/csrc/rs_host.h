@@ -45,6 +45,7 @@ struct rs_blob {
     int device = 0;
     rs::BlobArena* arena = nullptr;  // shared with the other blobs of one build call (null: own memory)
     rs::Alloc al;                    // frees words and tables when the blob owns them
+    bool packed = false;             // the packed per-size words hold every size up to the largest bucket
 };
 
 namespace rs {

@@ -94,10 +94,12 @@ __host__ __device__ inline SplitShape split_shape(uint32_t m, uint32_t leaf, uin
 }
 
 // Per-size tables for sizes 0..cap (cap >= the requested maxm), laid out as
-// r[cap+1], F[cap+1], N[cap+1], G[cap+1]: Golomb-Rice parameter of a node,
-// fixed bits of a subtree, coded nodes of a subtree, and log2 of the lanes
-// that share one candidate in the split search of a node of that size.  The
-// host memory is pinned and stays valid for the life of the process.
+// r[cap+1], F[cap+1], N[cap+1], G[cap+1], P[cap+1]: Golomb-Rice parameter of
+// a node, fixed bits of a subtree, coded nodes of a subtree, log2 of the lanes
+// that share one candidate in the split search of a node of that size, and
+// r, N and F of the size packed into one word (footnote of Sec. 7.2: bits 0-4
+// r, 5-15 N, 16-31 F; kNoPacked where they do not fit).  The host memory is
+// pinned and stays valid for the life of the process.
 struct TableView {
     const uint32_t* data;
     uint32_t cap;
@@ -105,13 +107,20 @@ struct TableView {
     const uint32_t* F() const { return data + cap + 1; }
     const uint32_t* N() const { return data + 2 * (cap + 1); }
     const uint32_t* G() const { return data + 3 * (cap + 1); }
+    const uint32_t* P() const { return data + 4 * (cap + 1); }
 };
-constexpr int kTableCount = 4;
+constexpr int kTableCount = 5;
+constexpr uint32_t kNoPacked = 0xffffffffu;
+__host__ __device__ inline uint32_t packed_r(uint32_t w) { return w & 31u; }
+__host__ __device__ inline uint32_t packed_N(uint32_t w) { return (w >> 5) & 2047u; }
+__host__ __device__ inline uint32_t packed_F(uint32_t w) { return w >> 16; }
+// True if the packed words of sizes 0..maxm are all valid.
+bool packed_valid(const uint32_t* P, uint32_t maxm);
 // gr_max > 0: split nodes of more than gr_max keys take the integer
 // approximation of their Golomb-Rice parameter (Sec. 7.2) instead of eq. (4).
 TableView host_tables(uint32_t leaf, uint32_t maxm, uint32_t gr_max = 0);
-// The same four tables for sizes 0..maxm written into dst (kTableCount *
-// (maxm + 1) words, r then F then N then G), without any allocation.
+// The same tables for sizes 0..maxm written into dst (kTableCount * (maxm + 1)
+// words, r then F then N then G then P), without any allocation.
 void fill_tables(uint32_t leaf, uint32_t maxm, uint32_t* dst, uint32_t gr_max = 0);
 
 // ---------------------------------------------------------------------------

@@ -5,11 +5,12 @@
 // when its estimated device footprint fits in the free part of the budget (a
 // request is always admitted when nothing else is in flight, so an oversized
 // one cannot wait forever).  Each build worker owns a stream; when it is free
-// it takes every admissible request at the head of the queue and runs them as
-// one batched construction (rs_build_batch).  Requests that arrive while a
-// batch is on the device form the next worker's batch, so their work overlaps
-// on the device.  A lookup worker runs lookup requests on its own stream.  All
-// streams have the default priority.
+// it takes the request at the head of the queue and every admissible queued
+// request of the same leaf size, and runs them as one batched construction
+// (rs_build_batch).  Requests that arrive while a batch is on the device form
+// the next worker's batch, so their work overlaps on the device.  A lookup
+// worker runs lookup requests on its own stream.  All streams have the
+// default priority.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -101,14 +102,27 @@ void build_worker(rs_server* s) {
             std::unique_lock<std::mutex> lk(s->mu);
             for (;;) {
                 if (!s->builds.empty()) {
-                    // admit from the head while the budget allows (at least one if idle)
-                    while (!s->builds.empty()) {
-                        const Request& r = s->builds.front();
+                    // admit the head request (always, if nothing is in flight), then
+                    // the later requests of its leaf size while the budget allows.
+                    // The requests of one batch finish together, so a batch holds
+                    // one leaf size: a small l = 8 request never waits for an l = 16
+                    // search of seconds; other leaf sizes go to the next free worker.
+                    const uint32_t cls = s->builds.front().leaf;
+                    for (auto it = s->builds.begin(); it != s->builds.end();) {
+                        const Request& r = *it;
+                        if (r.leaf != cls) {
+                            ++it;
+                            continue;
+                        }
                         const bool fits = s->in_flight + bytes + r.footprint <= s->budget;
-                        if (!fits && !(s->in_flight == 0 && batch.empty())) break;
+                        if (!fits && !(s->in_flight == 0 && batch.empty())) {
+                            if (batch.empty()) break;  // the head waits for budget
+                            ++it;
+                            continue;
+                        }
                         bytes += r.footprint;
                         batch.push_back(r);
-                        s->builds.pop_front();
+                        it = s->builds.erase(it);
                     }
                     if (!batch.empty()) break;
                 }

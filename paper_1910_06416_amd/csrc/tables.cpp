@@ -95,11 +95,13 @@ uint32_t lanes_per_candidate(const Strategy& st, uint32_t m, double trials) {
     return best_g;
 }
 
-void fill(const Strategy& st, uint32_t cap, uint32_t* r, uint32_t* F, uint32_t* N, uint32_t* G, uint32_t gr_max) {
+void fill(const Strategy& st, uint32_t cap, uint32_t* r, uint32_t* F, uint32_t* N, uint32_t* G, uint32_t* P,
+          uint32_t gr_max) {
     for (uint32_t m = 0; m <= cap; m++) {
         G[m] = 0;
         if (m < 2) {
             r[m] = F[m] = N[m] = 0;
+            P[m] = 0;
             continue;
         }
         const double lp = log_success(st, m);
@@ -112,13 +114,21 @@ void fill(const Strategy& st, uint32_t cap, uint32_t* r, uint32_t* F, uint32_t* 
             F[m] += (sh.fanout - 1) * F[sh.unit] + F[sh.last];
             N[m] += (sh.fanout - 1) * N[sh.unit] + N[sh.last];
         }
+        P[m] = r[m] < 32 && N[m] < 2048 && F[m] < 65536 ? r[m] | N[m] << 5 | F[m] << 16 : kNoPacked;
     }
 }
 
 }  // namespace
 
 void fill_tables(uint32_t leaf, uint32_t maxm, uint32_t* dst, uint32_t gr_max) {
-    fill(make_strategy(leaf), maxm, dst, dst + maxm + 1, dst + 2 * (maxm + 1), dst + 3 * (maxm + 1), gr_max);
+    fill(make_strategy(leaf), maxm, dst, dst + maxm + 1, dst + 2 * (maxm + 1), dst + 3 * (maxm + 1),
+         dst + 4 * (maxm + 1), gr_max);
+}
+
+bool packed_valid(const uint32_t* P, uint32_t maxm) {
+    for (uint32_t m = 0; m <= maxm; m++)
+        if (P[m] == kNoPacked) return false;
+    return true;
 }
 
 TableView host_tables(uint32_t leaf, uint32_t maxm, uint32_t gr_max) {
@@ -134,7 +144,8 @@ TableView host_tables(uint32_t leaf, uint32_t maxm, uint32_t gr_max) {
             buf = static_cast<uint32_t*>(std::malloc(bytes));
             if (!buf) return TableView{nullptr, 0};
         }
-        fill(make_strategy(leaf), cap, buf, buf + cap + 1, buf + 2 * (cap + 1), buf + 3 * (cap + 1), gr_max);
+        fill(make_strategy(leaf), cap, buf, buf + cap + 1, buf + 2 * (cap + 1), buf + 3 * (cap + 1),
+             buf + 4 * (cap + 1), gr_max);
         t.cap = cap;
         t.data = buf;  // the previous buffer is intentionally kept alive
     }
@@ -145,6 +156,15 @@ TableView host_tables(uint32_t leaf, uint32_t maxm, uint32_t gr_max) {
 
 extern "C" int rs_tables(uint32_t leaf, uint32_t maxm, uint32_t* r, uint32_t* F, uint32_t* N) {
     return rs_tables_ex(leaf, maxm, 0, r, F, N);
+}
+
+extern "C" int rs_tables_packed(uint32_t leaf, uint32_t maxm, uint32_t gr_table_max, uint32_t* packed) {
+    if (leaf < 1 || leaf > rs::kMaxLeaf || !packed) return RS_EINVAL;
+    rs::TableView t = rs::host_tables(leaf, maxm, gr_table_max);
+    if (!t.data) return RS_ENOMEM;
+    if (!rs::packed_valid(t.P(), maxm)) return RS_EINVAL;
+    for (uint32_t m = 0; m <= maxm; m++) packed[m] = t.P()[m];
+    return RS_OK;
 }
 
 extern "C" int rs_tables_ex(uint32_t leaf, uint32_t maxm, uint32_t gr_table_max, uint32_t* r, uint32_t* F,

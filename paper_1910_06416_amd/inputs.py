@@ -30,6 +30,13 @@ def u64_keys(n: int, seed: int) -> np.ndarray:
         keys = np.concatenate([keys[keep], extra])
 
 
+def u64_keys_raw(n: int, seed: int) -> np.ndarray:
+    """n uniformly random 64-bit keys without the distinctness pass (for
+    10^9-key workloads, where that pass would sort 8 GB on the host; two of
+    10^9 draws coincide with probability about 3%, so callers check)."""
+    return _rng(seed).integers(0, 2**64, size=n, dtype=np.uint64, endpoint=False)
+
+
 def ascii_keys(n: int, seed: int, min_len: int = 8, max_len: int = 32):
     """n distinct random strings of printable ASCII (0x21..0x7e), lengths
     uniform in [min_len, max_len].  Returns (data uint8[], offsets uint64[n+1])."""

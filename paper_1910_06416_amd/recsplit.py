@@ -104,6 +104,7 @@ def lib() -> ctypes.CDLL:
         L.rs_version.restype = ctypes.c_char_p
         L.rs_tables.argtypes = [U32, U32, P, P, P]
         L.rs_tables_ex.argtypes = [U32, U32, U32, P, P, P]
+        L.rs_tables_packed.argtypes = [U32, U32, U32, P]
         L.rs_last_build_stats.argtypes = [ctypes.POINTER(rs_build_stats)]
         L.rs_build_batch.argtypes = [ctypes.POINTER(rs_keys), U32, P, P, ctypes.POINTER(rs_options), P, P, P]
         PU64, PI, PD, PU32 = (ctypes.POINTER(U64), ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
@@ -135,7 +136,7 @@ def lib() -> ctypes.CDLL:
                   "rs_tables", "rs_last_build_stats", "rs_build_batch", "rs_server_create", "rs_server_create_ex", "rs_server_submit_build",
                   "rs_server_submit_lookup", "rs_server_poll", "rs_server_wait", "rs_server_get_stats", "rs_autotune",
                   "rs_schedule_get", "rs_schedule_set", "rs_plan_create", "rs_plan_run", "rs_plan_info",
-                  "rs_set_allocator", "rs_tables_ex"):
+                  "rs_set_allocator", "rs_tables_ex", "rs_tables_packed"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
         use_torch_allocator()
@@ -402,6 +403,17 @@ def from_bytes(data: bytes, stream=None) -> Blob:
     h = ctypes.c_void_p()
     _check(lib().rs_blob_from_host(buf.ctypes.data, buf.size, _stream(stream), ctypes.byref(h)))
     return Blob(h)
+
+
+def packed_table(leaf: int, maxm: int, gr_table_max: int = 0):
+    """The library's per-size words r | N << 5 | F << 16, or None when some
+    size up to maxm does not fit."""
+    out = np.zeros(maxm + 1, dtype=np.uint32)
+    rc = lib().rs_tables_packed(leaf, maxm, gr_table_max, out.ctypes.data)
+    if rc == RS_EINVAL:
+        return None
+    _check(rc)
+    return out
 
 
 def tables(leaf: int, maxm: int, gr_table_max: int = 0):

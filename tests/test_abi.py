@@ -106,10 +106,10 @@ def test_autotune_argument_validation(lib):
 
 
 def test_too_many_buckets_is_refused_before_any_device_work(lib):
-    """More than 4096 bins of 16384 buckets is refused on the host."""
+    """More than 4096 bins of 65536 buckets is refused on the host."""
     from paper_1910_06416_amd import recsplit
 
-    keys = recsplit.rs_keys(recsplit.RS_KEYS_U64, 16, None, 4096 * 16384 + 1)
+    keys = recsplit.rs_keys(recsplit.RS_KEYS_U64, 16, None, 4096 * 65536 + 1)
     out = ctypes.c_void_p()
     assert lib.rs_build(ctypes.byref(keys), 8, 1, None, ctypes.byref(out)) == recsplit.RS_EINVAL
     assert b"too many buckets" in lib.rs_last_error()
@@ -142,3 +142,17 @@ def test_library_tables_with_large_split_approximation_equal_oracle(orc, leaf, T
     assert np.array_equal(r, r2) and np.array_equal(F, F2) and np.array_equal(N, N2)
     r0, _, _ = recsplit.tables(leaf, 4096)
     assert (r != r0).any()  # the approximation is in use above T
+
+
+@pytest.mark.parametrize("leaf,T", [(4, 0), (8, 0), (16, 0), (24, 0), (3, 0), (8, 500), (2, 0), (1, 0)])
+def test_library_packed_table_equals_oracle(orc, leaf, T):
+    """The packed per-size words (footnote of Sec. 7.2), written independently
+    on both sides, agree; both refuse where a size does not fit."""
+    from paper_1910_06416_amd import recsplit
+
+    got = recsplit.packed_table(leaf, 2600, T)
+    want = orc.packed_table(leaf, 2600, T)
+    if want is None:
+        assert got is None
+    else:
+        assert got is not None and np.array_equal(got, want)

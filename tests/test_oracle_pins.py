@@ -559,3 +559,115 @@ def test_structure_with_approximation_is_a_bijection(orc, n, leaf, bucket, T):
     assert np.array_equal(np.sort(ranks), np.arange(n, dtype=np.uint64))
     # the exact parameters are optimal (eq. (4)): the approximation never makes the trees smaller
     assert orc.header(blob)["tree_bits"] >= orc.header(orc.build(keys, leaf, bucket))["tree_bits"] - 64
+
+
+@pytest.mark.parametrize("leaf", range(1, 25))
+def test_one_32_bit_table_suffices_from_leaf_4(orc, leaf):
+    """Footnote of Sec. 7.2: for l >= 4 and b <= 2000 one table of 32-bit words
+    indexed by size holds a node's Golomb-Rice parameter, its subtree's fixed
+    bits and its subtree's coded nodes.  With r in 5 bits (r < 32, Sec. 5),
+    N in 11 and F in 16 it holds every size up to 2,600 keys (the largest
+    bucket of b = 2000 among 5e5 buckets is about 2,250) for l >= 3; the
+    nodes of l = 2 subtrees overflow 11 bits there."""
+    packed = orc.packed_table(leaf, 2600)
+    if leaf >= 3:
+        r, F, N = orc.tables(leaf, 2600)
+        assert packed is not None
+        assert np.array_equal(packed & 31, r)
+        assert np.array_equal((packed >> 5) & 2047, N)
+        assert np.array_equal(packed >> 16, F)
+    if leaf <= 2:
+        assert packed is None
+
+
+# ---------------------------------------------------------------------------
+# The non-minimal variant (Sec. 9: larger codomains): leaves of m keys map
+# injectively into M = m + ceil(m slack / 256) values.
+# ---------------------------------------------------------------------------
+def _leaf_range(m, slack):
+    return m if m <= 1 else m + -(-m * slack // 256)
+
+
+def _subtree_range(orc, leaf, m, slack):
+    if m <= leaf:
+        return _leaf_range(m, slack)
+    return sum(_subtree_range(orc, leaf, k, slack) for k in orc.split_parts(leaf, m))
+
+
+@pytest.mark.parametrize("n,leaf,bucket,slack", [(30000, 8, 100, 32), (20000, 5, 5, 128), (5000, 12, 300, 16),
+                                                 (3000, 1, 10, 255), (7, 8, 100, 64), (4000, 16, 40, 64)])
+def test_nonminimal_structure_is_injective_into_its_range(orc, n, leaf, bucket, slack):
+    keys = inputs.u64_keys(n, 900 + slack)
+    blob = orc.build(keys, leaf, bucket, leaf_slack=slack)
+    h = orc.header(blob)
+    assert h["leaf_slack"] == slack and h["n"] == n
+    nb = -(-n // bucket)
+    sizes = orc.bucket_sizes(keys, nb)
+    ranges = [_subtree_range(orc, leaf, int(m), slack) for m in sizes]
+    s_all, _ = orc.blob_prefix(blob)
+    assert np.array_equal(s_all, np.concatenate([[0], np.cumsum(ranges)]).astype(np.uint64))
+    total = int(s_all[-1])
+    ranks = orc.lookup(blob, keys)
+    assert len(np.unique(ranks)) == n and int(ranks.max()) < total
+    assert total >= n and (slack == 0 or leaf == 1 or total > n)
+
+
+def test_nonminimal_slack_zero_is_the_minimal_structure(orc):
+    keys = inputs.u64_keys(20000, 901)
+    assert orc.build(keys, 8, 100, leaf_slack=0) == orc.build(keys, 8, 100)
+
+
+def test_nonminimal_range_grows_strictly_with_size(orc):
+    """A bucket's size is recovered from its range, so the range of a subtree
+    must grow strictly with its size (every leaf size and slack the format
+    allows, sizes up to 4096)."""
+    for leaf in range(1, 25):
+        for slack in (1, 16, 64, 128, 255):
+            if _leaf_range(leaf, slack) > 32:
+                continue
+            _, _, _, Q = orc.range_tables(leaf, 4096, slack)
+            assert (np.diff(Q.astype(np.int64)) > 0).all(), (leaf, slack)
+            assert int(Q[leaf]) == _leaf_range(leaf, slack)
+
+
+@pytest.mark.parametrize("leaf,slack", [(8, 64), (5, 128), (8, 32)])
+def test_nonminimal_leaf_trials_match_injection_probability(orc, leaf, slack):
+    """Mean trials of the leaves of each size against 1/p, p = prod_{i<m} (M - i)
+    / M the chance that a random function into M values is injective on m
+    keys (|z| < 5 with the geometric standard error)."""
+    keys = inputs.u64_keys(60_000, 910 + slack)
+    nb = 60_000 // 100
+    trials = {}
+    for i in range(0, nb, 3):
+        v, m, _ = orc.tree(orc.bucket_keys(keys, nb, i), leaf, leaf_slack=slack)
+        for vv, mm in zip(v, m):
+            if mm <= leaf:
+                trials.setdefault(int(mm), []).append(int(vv) + 1)
+    checked = 0
+    for m, t in trials.items():
+        if len(t) < 200:
+            continue
+        M = _leaf_range(m, slack)
+        p = math.prod((M - i) / M for i in range(m))
+        se = math.sqrt(1 - p) / p / math.sqrt(len(t))
+        z = (np.mean(t) - 1 / p) / se
+        assert abs(z) < 5, (m, M, np.mean(t), 1 / p, z)
+        checked += 1
+    assert checked >= 1
+
+
+def test_nonminimal_leaf_parameters_follow_eq4(orc):
+    """Leaf Golomb-Rice parameters of the variant: eq. (4) with the injection
+    probability, checked against a 50-digit evaluation."""
+    getcontext().prec = 50
+    golden = (1 + Decimal(5).sqrt()) / 2
+    for leaf, slack in [(8, 64), (16, 32), (24, 85), (5, 255)]:
+        r, _, _, _ = orc.range_tables(leaf, leaf, slack)
+        for m in range(2, leaf + 1):
+            M = _leaf_range(m, slack)
+            p = Decimal(1)
+            for i in range(m):
+                p *= Decimal(M - i) / Decimal(M)
+            ratio = golden.ln() / -(1 - p).ln()
+            want = max(0, math.ceil(float(ratio.ln() / Decimal(2).ln())))
+            assert int(r[m]) == want, (leaf, slack, m)
