@@ -109,6 +109,17 @@ int rs_set_allocator(rs_alloc_fn alloc, rs_free_fn release, void* ctx);
  *               0.1 us with no progress at all, which the node order rules out
  *               in a correct build.  0 = 2^25 (several seconds).  Small values
  *               exist to exercise that error path.
+ *   leaf_slack: 0 builds the minimal structure.  A value in [1, 255] builds
+ *               the non-minimal variant that Sec. 9 proposes (a larger
+ *               codomain): every leaf of m >= 2 keys takes the first index
+ *               whose hash is injective into m + ceil(m leaf_slack / 256)
+ *               values, a subtree covers the sum of its parts' ranges, and
+ *               the first Elias-Fano list holds the prefix sums of the
+ *               buckets' ranges instead of their sizes.  Lookups then map the
+ *               n keys one-to-one into [0, R), R = the sum of all bucket
+ *               ranges (the last entry of that list); the value is recorded
+ *               in the structure (header word 7, bits 40-47).  RS_EINVAL when
+ *               l + ceil(l leaf_slack / 256) exceeds 32.
  * Schedules never change the result, only the time it takes. */
 enum { RS_OPT_TIMING = 1, RS_OPT_TUNED = 2 };
 typedef struct {
@@ -119,6 +130,7 @@ typedef struct {
     uint32_t waves;
     uint32_t wait_limit;
     uint32_t gr_table_max;
+    uint32_t leaf_slack;
 } rs_options;
 
 /* Search schedule of one (l, b) pair.  The seed search runs one workgroup per
@@ -374,6 +386,16 @@ int rs_tables_ex(uint32_t leaf, uint32_t maxm, uint32_t gr_table_max, uint32_t* 
  * Errors: RS_EINVAL (l outside [1,24], NULL, or some size up to maxm does not
  * fit the fields), RS_ENOMEM. */
 int rs_tables_packed(uint32_t leaf, uint32_t maxm, uint32_t gr_table_max, uint32_t* packed);
+
+/* rs_tables_ex of a structure built with rs_options.leaf_slack = leaf_slack,
+ * plus Q[m], the output values of a subtree of m keys (m for the minimal
+ * structure; leaves m + ceil(m leaf_slack / 256); splits the sum over their
+ * parts).  r of a leaf follows its injection probability
+ * prod_{i<m} (M - i) / M with M = Q[m].  Host arrays of maxm+1 entries.
+ * Errors: RS_EINVAL (l outside [1,24], leaf_slack > 255, a leaf range above
+ * 32, NULL), RS_ENOMEM. */
+int rs_tables_range(uint32_t leaf, uint32_t maxm, uint32_t gr_table_max, uint32_t leaf_slack, uint32_t* r,
+                    uint32_t* F, uint32_t* N, uint32_t* Q);
 
 /* Library version string. */
 const char* rs_version(void);

@@ -75,7 +75,8 @@ Layout layout_of(const uint64_t* h) {
     L.n = h[2]; L.leaf = h[3]; L.bucket = h[4]; L.nb = h[5]; L.maxm = h[6];
     L.Ws = (uint32_t)(h[7] & 0xff);
     L.Wz = (uint32_t)((h[7] >> 8) & 0xff);
-    L.gr_max = (uint32_t)(h[7] >> 16);
+    L.gr_max = (uint32_t)((h[7] >> 16) & 0xffffff);
+    L.slack = (uint32_t)((h[7] >> 40) & 0xff);
     L.delta_s = h[8];
     L.delta_z = (int64_t)h[9];
     L.beta = h[10];
@@ -92,15 +93,12 @@ Layout layout_of(const uint64_t* h) {
     return L;
 }
 
-int upload_tables(uint32_t leaf, uint32_t maxm, uint32_t gr_max, uint32_t* dst, hipStream_t s) {
-    TableView tv = host_tables(leaf, maxm, gr_max);
+int upload_tables(uint32_t leaf, uint32_t maxm, uint32_t gr_max, uint32_t slack, uint32_t* dst, hipStream_t s) {
+    TableView tv = host_tables(leaf, maxm, gr_max, slack);
     if (!tv.data) return fail(RS_ENOMEM, "table allocation failed");
     const size_t w = maxm + 1;
-    RS_HIP(hipMemcpyAsync(dst, tv.r(), w * 4, hipMemcpyHostToDevice, s));
-    RS_HIP(hipMemcpyAsync(dst + w, tv.F(), w * 4, hipMemcpyHostToDevice, s));
-    RS_HIP(hipMemcpyAsync(dst + 2 * w, tv.N(), w * 4, hipMemcpyHostToDevice, s));
-    RS_HIP(hipMemcpyAsync(dst + 3 * w, tv.G(), w * 4, hipMemcpyHostToDevice, s));
-    RS_HIP(hipMemcpyAsync(dst + 4 * w, tv.P(), w * 4, hipMemcpyHostToDevice, s));
+    for (int a = 0; a < kTableCount; a++)
+        RS_HIP(hipMemcpyAsync(dst + a * w, tv.data + (size_t)a * (tv.cap + 1), w * 4, hipMemcpyHostToDevice, s));
     return RS_OK;
 }
 
@@ -115,12 +113,13 @@ struct LookupArgs {
     const uint32_t* F;
     const uint32_t* N;
     const uint32_t* P;  // r | N << 5 | F << 16 per size (used when every size fits)
+    const uint32_t* Q;  // output values of a subtree per size (non-minimal structures)
     uint64_t nb, beta, delta_s;
     int64_t delta_z;
     uint32_t Ws, Wz;
     uint64_t lower_off, us_off, uz_off, inv_hi_off, inv_lo_off, tree_off;
     uint64_t us_words, uz_words, tree_words;
-    uint32_t leaf, lower, upper, maxm;
+    uint32_t leaf, lower, upper, maxm, slack;
 };
 
 // Position of the k-th set bit (k = 0, 1, ...) inside a 64-bit word (k is
@@ -258,7 +257,10 @@ struct SizeTables {
     }
 };
 
-template <bool PACKED>
+// Rank (minimal structure) or output value (WIDE: the non-minimal variant,
+// whose leaves map into leaf_range(m, slack) values and whose first
+// Elias-Fano list holds prefix sums of bucket ranges) of one key.
+template <bool PACKED, bool WIDE>
 __device__ uint64_t rank_of(const LookupArgs& a, uint64_t hi, uint64_t lo) {
     const SizeTables<PACKED> T{a};
     const uint64_t* blob = a.blob;
@@ -283,6 +285,16 @@ __device__ uint64_t rank_of(const LookupArgs& a, uint64_t hi, uint64_t lo) {
     uint64_t o_i = (uint64_t)(z + (int64_t)((a.beta * s_i) >> 16));
 
     uint32_t m = (uint32_t)min(s_i1 - s_i, (uint64_t)a.maxm);
+    if (WIDE) {  // the bucket's size: the one whose range is s_{i+1} - s_i (ranges grow with the size)
+        const uint64_t range = s_i1 - s_i;
+        uint32_t lo_m = 0, hi_m = a.maxm;
+        while (lo_m < hi_m) {
+            const uint32_t mid = (lo_m + hi_m + 1) >> 1;
+            if (a.Q[mid] <= range) lo_m = mid;
+            else hi_m = mid - 1;
+        }
+        m = lo_m;
+    }
     const uint64_t* tree = blob + a.tree_off;
     // node sizes below 2^20 (every structure this library builds; every
     // dividend below is then under 2^21): the split shapes and child indices
@@ -321,7 +333,7 @@ __device__ uint64_t rank_of(const LookupArgs& a, uint64_t hi, uint64_t lo) {
             const uint64_t skip = (uint64_t)j * nu;
             if (skip) up = select_from(tree, a.tree_words, up, skip - 1) + 1;
         }
-        c += (uint64_t)j * sh.unit;
+        c += (uint64_t)j * (WIDE ? a.Q[sh.unit] : sh.unit);
         m = j + 1 == sh.fanout ? sh.last : sh.unit;
         d++;
     }
@@ -330,24 +342,24 @@ __device__ uint64_t rank_of(const LookupArgs& a, uint64_t hi, uint64_t lo) {
         uint64_t fixed = get_bits(tree, fp, r);
         uint64_t one = next_one(tree, a.tree_words, up);
         uint64_t v = ((one - up) << r) | fixed;
-        c += phi(lo, d, v, m);
+        c += phi(lo, d, v, WIDE ? leaf_range(m, a.slack) : m);
     }
     return s_i + c;
 }
 
 // One query per lane; q0 is the launch's first query (lookups of more
 // queries than one grid holds are launched in chunks).
-template <bool PACKED>
+template <bool PACKED, bool WIDE>
 __global__ void k_lookup_u64(LookupArgs a, const uint64_t* __restrict__ keys, uint64_t q, uint64_t q0,
                              uint64_t* __restrict__ ranks) {
     uint64_t t = q0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= q) return;
     uint64_t hi, lo;
     signature_u64(keys[t], hi, lo);
-    ranks[t] = rank_of<PACKED>(a, hi, lo);
+    ranks[t] = rank_of<PACKED, WIDE>(a, hi, lo);
 }
 
-template <bool PACKED>
+template <bool PACKED, bool WIDE>
 __global__ void k_lookup_bytes(LookupArgs a, const uint8_t* __restrict__ data, const uint64_t* __restrict__ offsets,
                                uint64_t q, uint64_t q0, bool aligned, uint64_t* __restrict__ ranks) {
     uint64_t t = q0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -357,7 +369,7 @@ __global__ void k_lookup_bytes(LookupArgs a, const uint8_t* __restrict__ data, c
     if (e < s || e > total) e = s = min(s, total);
     uint64_t hi, lo;
     signature_bytes(data, total, aligned, s, e, hi, lo);
-    ranks[t] = rank_of<PACKED>(a, hi, lo);
+    ranks[t] = rank_of<PACKED, WIDE>(a, hi, lo);
 }
 
 }  // namespace
@@ -376,10 +388,12 @@ extern "C" int rs_lookup(const rs_blob* blob, const rs_keys* queries, uint64_t* 
                                              queries->kind, (uint32_t)L.kind);
     if (queries->kind == RS_KEYS_BYTES && !queries->offsets) return fail(RS_EINVAL, "NULL offsets");
     Strategy st = make_strategy((uint32_t)L.leaf);
-    LookupArgs a{blob->words, blob->tables, blob->tables + blob->tab_stride, blob->tables + 2 * blob->tab_stride,
-                 blob->tables + 4 * blob->tab_stride, L.nb, L.beta, L.delta_s, L.delta_z, L.Ws, L.Wz, L.lower_off, L.us_off, L.uz_off, L.inv_hi_off,
-                 L.inv_lo_off, L.tree_off, L.us_words, L.uz_words, L.tree_words, (uint32_t)L.leaf, st.lower,
-                 st.upper, (uint32_t)L.maxm};
+    const uint32_t* tab = blob->tables;
+    const size_t w = blob->tab_stride;
+    LookupArgs a{blob->words, tab, tab + w, tab + 2 * w, tab + 4 * w, tab + 5 * w, L.nb, L.beta, L.delta_s,
+                 L.delta_z, L.Ws, L.Wz, L.lower_off, L.us_off, L.uz_off, L.inv_hi_off, L.inv_lo_off, L.tree_off,
+                 L.us_words, L.uz_words, L.tree_words, (uint32_t)L.leaf, st.lower, st.upper, (uint32_t)L.maxm,
+                 L.slack};
     hipStream_t s = (hipStream_t)stream;
     if (blob->ready) RS_HIP(hipStreamWaitEvent(s, blob->ready, 0));  // built on another stream
     const uint32_t block = 256;
@@ -390,15 +404,25 @@ extern "C" int rs_lookup(const rs_blob* blob, const rs_keys* queries, uint64_t* 
                 return fail(RS_EINVAL, "lookup grid of %llu blocks does not fit", (unsigned long long)grid);
             const bool al = ((uintptr_t)queries->data & 7) == 0;
             const uint8_t* bytes = (const uint8_t*)queries->data;
-            if (queries->kind == RS_KEYS_U64 && blob->packed)
-                k_lookup_u64<true><<<(uint32_t)grid, block, 0, s>>>(a, (const uint64_t*)bytes, q, q0, ranks_dev);
-            else if (queries->kind == RS_KEYS_U64)
-                k_lookup_u64<false><<<(uint32_t)grid, block, 0, s>>>(a, (const uint64_t*)bytes, q, q0, ranks_dev);
-            else if (blob->packed)
-                k_lookup_bytes<true><<<(uint32_t)grid, block, 0, s>>>(a, bytes, queries->offsets, q, q0, al, ranks_dev);
-            else
-                k_lookup_bytes<false><<<(uint32_t)grid, block, 0, s>>>(a, bytes, queries->offsets, q, q0, al,
-                                                                       ranks_dev);
+            const uint64_t* u64 = (const uint64_t*)bytes;
+            const uint64_t* offs = queries->offsets;
+            // table reads: packed words, three arrays, or three arrays and the ranges
+            if (queries->kind == RS_KEYS_U64) {
+                if (L.slack)
+                    k_lookup_u64<false, true><<<(uint32_t)grid, block, 0, s>>>(a, u64, q, q0, ranks_dev);
+                else if (blob->packed)
+                    k_lookup_u64<true, false><<<(uint32_t)grid, block, 0, s>>>(a, u64, q, q0, ranks_dev);
+                else
+                    k_lookup_u64<false, false><<<(uint32_t)grid, block, 0, s>>>(a, u64, q, q0, ranks_dev);
+            } else {
+                if (L.slack)
+                    k_lookup_bytes<false, true><<<(uint32_t)grid, block, 0, s>>>(a, bytes, offs, q, q0, al, ranks_dev);
+                else if (blob->packed)
+                    k_lookup_bytes<true, false><<<(uint32_t)grid, block, 0, s>>>(a, bytes, offs, q, q0, al, ranks_dev);
+                else
+                    k_lookup_bytes<false, false><<<(uint32_t)grid, block, 0, s>>>(a, bytes, offs, q, q0, al,
+                                                                                   ranks_dev);
+            }
             return RS_OK;
         }))
         return rc;
@@ -436,8 +460,14 @@ extern "C" int rs_blob_from_host(const void* src, uint64_t bytes, void* stream, 
     if (h[0] != kMagic || (h[1] & 0xffffffffull) != kVersion) return fail(RS_EFORMAT, "bad magic or version");
     Layout L = layout_of(h);
     if (L.leaf < 1 || L.leaf > kMaxLeaf || L.nb == 0 || L.n == 0 || L.maxm > L.n ||
-        (L.kind != RS_KEYS_U64 && L.kind != RS_KEYS_BYTES) || L.total_words * 8 != bytes)
+        (L.kind != RS_KEYS_U64 && L.kind != RS_KEYS_BYTES) || L.total_words * 8 != bytes ||
+        leaf_range((uint32_t)L.leaf, L.slack) > kMaxLeafRange || (h[7] >> 48) != 0)
         return fail(RS_EFORMAT, "inconsistent header");
+    if (L.slack) {
+        const TableView tv = host_tables((uint32_t)L.leaf, (uint32_t)L.maxm, L.gr_max, L.slack);
+        if (!tv.data) return fail(RS_ENOMEM, "table allocation failed");
+        if (!ranges_increasing(tv.Q(), (uint32_t)L.maxm)) return fail(RS_EFORMAT, "inconsistent header");
+    }
     hipStream_t s = (hipStream_t)stream;
     rs_blob* b = new (std::nothrow) rs_blob;
     if (!b) return fail(RS_ENOMEM, "host allocation failed");
@@ -445,7 +475,7 @@ extern "C" int rs_blob_from_host(const void* src, uint64_t bytes, void* stream, 
     b->al = current_alloc();
     int rc = b->al.get((void**)&b->words, bytes, s);
     if (!rc) rc = b->al.get((void**)&b->tables, (size_t)kTableCount * (L.maxm + 1) * 4, s);
-    if (!rc) rc = upload_tables((uint32_t)L.leaf, (uint32_t)L.maxm, L.gr_max, b->tables, s);
+    if (!rc) rc = upload_tables((uint32_t)L.leaf, (uint32_t)L.maxm, L.gr_max, L.slack, b->tables, s);
     if (!rc && hipMemcpyAsync(b->words, src, bytes, hipMemcpyHostToDevice, s) != hipSuccess)
         rc = fail(RS_EDEVICE, "copy to device failed");
     if (!rc && hipStreamSynchronize(s) != hipSuccess) rc = fail(RS_EDEVICE, "stream synchronisation failed");
@@ -458,8 +488,8 @@ extern "C" int rs_blob_from_host(const void* src, uint64_t bytes, void* stream, 
     b->bytes = bytes;
     b->tab_stride = (uint32_t)(L.maxm + 1);
     {
-        const TableView tv = host_tables((uint32_t)L.leaf, (uint32_t)L.maxm, L.gr_max);
-        b->packed = tv.data && packed_valid(tv.P(), (uint32_t)L.maxm);
+        const TableView tv = host_tables((uint32_t)L.leaf, (uint32_t)L.maxm, L.gr_max, L.slack);
+        b->packed = !L.slack && tv.data && packed_valid(tv.P(), (uint32_t)L.maxm);
     }
     b->ready = nullptr;  // complete: the copy above was waited for
     (void)hipGetDevice(&b->device);

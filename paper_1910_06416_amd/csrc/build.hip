@@ -66,11 +66,13 @@ struct BuildDesc {
     uint32_t waves;       // wavefronts of the bucket's workgroup that take nodes
     uint32_t bucket;      // the caller's bucket size b (header word)
     uint32_t gr_max;      // splits above this size use the Sec. 7.2 approximation (0: none; header)
+    uint32_t slack;       // non-minimal variant: leaves map into leaf_range(m, slack) values (0: minimal)
     // written by the device
     uint32_t maxm, flags;
     unsigned long long delta_s;
     long long delta_z;
     unsigned long long total_bits;
+    unsigned long long range_total;  // last value of the first Elias-Fano list (n for the minimal structure)
     // written by the host once the sizes are known
     unsigned long long* blob;  // null: no blob for this build
     uint64_t beta;
@@ -503,7 +505,7 @@ struct SearchArgs {
     const uint64_t* bucket_base;
     uint32_t count;
     uint64_t nbuckets;
-    const uint32_t* tables;     // per leaf size: r, F, N, G, each `stride` words
+    const uint32_t* tables;     // per table set: kTableCount arrays of `stride` words (r, F, N, G, P, Q)
     uint32_t stride;
     uint64_t seed_cap;
     uint32_t key_words;   // 64-bit words of dynamic LDS before the node slots (largest bucket)
@@ -709,6 +711,39 @@ __device__ __forceinline__ uint64_t leaf_search(const uint64_t* keys, uint32_t d
     return kNoSeed;
 }
 
+// Bijection search of the non-minimal variant: the first index whose hash
+// sends the M keys to M distinct values out of `range` >= M (at most 32, so
+// one 32-bit mask per candidate holds them).  Same candidate order and early
+// exit as the plain loop of leaf_search.
+template <int M>
+__device__ __forceinline__ uint64_t leaf_search_wide(const uint64_t* keys, uint32_t depth, uint64_t cap,
+                                                     uint32_t range, uint32_t* flags, QueueState* qs) {
+    const uint32_t lane = lane_id();
+    const uint64_t step = 64ull * kGamma;
+    const uint64_t S = (((uint64_t)depth << 56) + lane) * kGamma;
+    uint64_t kl[M];
+#pragma unroll
+    for (int i = 0; i < M; i++) kl[i] = uniform64(keys[i]) + S;
+    const uint64_t last = cap ? (cap - 1) & ~63ull : 0;
+    uint64_t O = 0;
+    for (uint64_t base = 0; cap; base += 64, O += step) {
+        uint64_t Os = O;
+        asm volatile("" : "+s"(Os));
+        uint32_t mask = 0;
+#pragma unroll
+        for (int i = 0; i < M; i++) mask |= 1u << __umulhi(mix64_hi32(kl[i] + Os), range);
+        bool ok = __popc(mask) == M;
+        const bool at_end = base == last;
+        if (at_end) ok &= lane < (uint32_t)(cap - base);
+        const uint64_t bal = __ballot(ok);
+        if (bal) return base + (uint64_t)__builtin_ctzll(bal);
+        if (at_end) break;
+        if ((base & kLeafPollMask) == kLeafPollMask - 63 && search_poll(qs)) return kNoSeed;
+    }
+    if (lane == 0) atomicOr(flags, kFlagSearch);
+    return kNoSeed;
+}
+
 // True if two of the m <= 64 keys are equal (wave-uniform result).
 __device__ bool has_duplicate(const uint64_t* keys, uint32_t m) {
     uint32_t lane = lane_id();
@@ -720,10 +755,10 @@ __device__ bool has_duplicate(const uint64_t* keys, uint32_t m) {
 
 // Inlined into each search kernel: as a call shared by the kernels it costs
 // the calling convention's register saves and the uniformity of its arguments.
-template <int MAXL>
+template <int MAXL, bool WIDE>
 __device__ __forceinline__ uint64_t leaf_dispatch(const uint64_t* keys, uint32_t m, uint32_t depth, uint64_t cap,
                                                   uint32_t* flags, LeafQueues* q, uint32_t stage_from,
-                                                  QueueState* qs) {
+                                                  QueueState* qs, uint32_t range) {
     // Equal lower words never separate: copies that reach a leaf together are
     // caught here (more copies than any part of a split holds stop that split's
     // search instead, see split_search).
@@ -734,7 +769,9 @@ __device__ __forceinline__ uint64_t leaf_dispatch(const uint64_t* keys, uint32_t
     switch (m) {
 #define RS_LEAF_CASE(M)                                                                    \
     case M:                                                                                \
-        if constexpr (M <= MAXL) return leaf_search<M>(keys, depth, cap, flags, q, M > 16 || M >= stage_from, qs); \
+        if constexpr (M <= MAXL && WIDE) return leaf_search_wide<M>(keys, depth, cap, range, flags, qs); \
+        if constexpr (M <= MAXL && !WIDE)                                                  \
+            return leaf_search<M>(keys, depth, cap, flags, q, M > 16 || M >= stage_from, qs); \
         return kNoSeed;
         RS_LEAF_CASE(2) RS_LEAF_CASE(3) RS_LEAF_CASE(4) RS_LEAF_CASE(5) RS_LEAF_CASE(6) RS_LEAF_CASE(7)
         RS_LEAF_CASE(8) RS_LEAF_CASE(9) RS_LEAF_CASE(10) RS_LEAF_CASE(11) RS_LEAF_CASE(12) RS_LEAF_CASE(13)
@@ -1006,7 +1043,9 @@ struct NodeSlot {
 };
 
 
-template <int MAXL, int WAVES>
+// WIDE: the call holds a build of the non-minimal variant; leaves search
+// injections into their build's leaf_range (equal to m for slack 0).
+template <int MAXL, int WAVES, bool WIDE>
 __global__ __launch_bounds__(64 * WAVES) void k_search(SearchArgs a) {
     extern __shared__ uint64_t lds_dyn[];
     __shared__ QueueState qs;
@@ -1027,6 +1066,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_search(SearchArgs a) {
         const uint32_t upper = __builtin_amdgcn_readfirstlane(B.upper);
         const uint32_t stage_from = __builtin_amdgcn_readfirstlane(B.stage_from);
         const uint32_t group_cap = __builtin_amdgcn_readfirstlane(B.group_cap);
+        const uint32_t slack = WIDE ? __builtin_amdgcn_readfirstlane(B.slack) : 0;
         // waves beyond the build's count only join the barriers
         const uint32_t active = __builtin_amdgcn_readfirstlane(min(B.waves, (uint32_t)WAVES));
         const uint32_t* R = a.tables + (size_t)__builtin_amdgcn_readfirstlane(B.tab) * kTableCount * a.stride;
@@ -1107,7 +1147,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_search(SearchArgs a) {
             bool fail;
             SplitShape sh{};
             if (m <= leaf) {
-                v = leaf_dispatch<MAXL>(lds_keys + off, m, d, a.seed_cap, bflags, &queues[wave], stage_from, &qs);
+                v = leaf_dispatch<MAXL, WIDE>(lds_keys + off, m, d, a.seed_cap, bflags, &queues[wave], stage_from,
+                                              &qs, leaf_range(m, slack));
                 fail = v == kNoSeed;
             } else {
                 sh = split_shape(m, leaf, lower, upper);
@@ -1184,6 +1225,7 @@ __device__ __forceinline__ int64_t z_of(uint64_t o, uint64_t s, uint64_t beta) {
 
 struct GapArgs {
     const uint64_t* bstart;  // global prefix sums of bucket sizes (nbuckets + 1)
+    const uint64_t* qstart;  // global prefix sums of bucket output ranges (bstart for minimal builds)
     const uint64_t* ostart;  // global prefix sums of bucket bit lengths (nbuckets + 1)
     const BuildDesc* descs;
     BuildDesc* wdescs;
@@ -1201,15 +1243,19 @@ struct GapStat {
 
 __device__ __forceinline__ GapStat gap_of(const GapArgs& a, uint32_t j, uint64_t g) {
     const BuildDesc& B = a.descs[j];
-    const uint64_t bb = B.bucket_base, s0 = a.bstart[bb], o0 = a.ostart[bb];
+    const uint64_t bb = B.bucket_base, s0 = a.qstart[bb], o0 = a.ostart[bb];
     const uint64_t bits = a.ostart[bb + B.nb] - o0;
-    const uint64_t beta = (bits << 16) / B.n;
-    const uint64_t s_i = a.bstart[g] - s0, s_i1 = a.bstart[g + 1] - s0;
+    const uint64_t range = a.qstart[bb + B.nb] - s0;
+    const uint64_t beta = (bits << 16) / range;
+    const uint64_t s_i = a.qstart[g] - s0, s_i1 = a.qstart[g + 1] - s0;
     GapStat r;
     r.gs = s_i1 - s_i;
     r.gz = z_of(a.ostart[g + 1] - o0, s_i1, beta) - z_of(a.ostart[g] - o0, s_i, beta);
-    r.mx = (uint32_t)r.gs;
-    if (g == bb) a.wdescs[j].total_bits = bits;
+    r.mx = (uint32_t)(a.bstart[g + 1] - a.bstart[g]);
+    if (g == bb) {
+        a.wdescs[j].total_bits = bits;
+        a.wdescs[j].range_total = range;
+    }
     return r;
 }
 
@@ -1313,6 +1359,7 @@ __device__ __forceinline__ void or_bits_lds(unsigned long long* a, uint64_t pos,
 
 struct FillArgs {
     const uint64_t* bstart;
+    const uint64_t* qstart;  // first Elias-Fano list (bstart for minimal builds)
     const uint64_t* ostart;
     const uint64_t* seeds;
     const uint32_t* msz;
@@ -1335,7 +1382,7 @@ __global__ void k_ef_fill(FillArgs a) {
     if (!B.blob) return;
     const uint64_t i = e - a.entry_base[j];
     const uint64_t bb = B.bucket_base;
-    const uint64_t s = a.bstart[bb + i] - a.bstart[bb];
+    const uint64_t s = a.qstart[bb + i] - a.qstart[bb];
     const int64_t z = z_of(a.ostart[bb + i] - a.ostart[bb], s, B.beta);
     const uint64_t ys = s - i * B.delta_s;
     const uint64_t yz = (uint64_t)(z - (int64_t)i * B.delta_z);
@@ -1355,7 +1402,7 @@ __global__ void k_ef_fill(FillArgs a) {
     if ((i & ((1u << kInvLo) - 1)) == 0) {
         // the anchor: the one of index i rounded down to a multiple of 2^14
         const uint64_t an = i & ~(uint64_t)((1u << kInvHi) - 1);
-        const uint64_t sa = a.bstart[bb + an] - a.bstart[bb];
+        const uint64_t sa = a.qstart[bb + an] - a.qstart[bb];
         const int64_t za = z_of(a.ostart[bb + an] - a.ostart[bb], sa, B.beta);
         const uint64_t pa_s = ((sa - an * B.delta_s) >> B.Ws) + an;
         const uint64_t pa_z = ((uint64_t)(za - (int64_t)an * B.delta_z) >> B.Wz) + an;
@@ -1447,6 +1494,21 @@ __global__ __launch_bounds__(kBlock) void k_tree_bits(FillArgs a) {
     }
 }
 
+// Output range of every bucket of a call that holds a non-minimal build: Q of
+// the bucket's size under its build's tables (the size itself for minimal
+// builds, whose Q is the identity).  Their prefix sums are the first
+// Elias-Fano list.  A bucket above the tables' largest size fails its build
+// anyway (the search flags it), so it takes its size.
+__global__ void k_range_sizes(const uint64_t* __restrict__ bstart, const BuildDesc* __restrict__ descs,
+                              const uint64_t* __restrict__ bucket_base, uint32_t count, uint64_t nbuckets,
+                              const uint32_t* __restrict__ tables, uint32_t stride, uint64_t* __restrict__ out) {
+    const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= nbuckets) return;
+    const uint32_t j = find_build(bucket_base, count, g);
+    const uint64_t m = bstart[g + 1] - bstart[g];
+    out[g] = m < stride ? tables[((size_t)descs[j].tab * kTableCount + 5) * stride + m] : m;
+}
+
 // Headers: 16 words per build with a blob.
 __global__ void k_write_headers(const BuildDesc* descs, const uint64_t* headers, uint32_t count) {
     const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1468,10 +1530,10 @@ __device__ uint32_t ef_width(uint64_t N, uint64_t U) {
 // an error flag get no blob (size 0).  One block: builds are taken 256 at a
 // time and their rounded sizes are scanned into the arena offsets off[0..K].
 __device__ uint64_t geometry_of(BuildDesc& d, uint64_t* h) {
-    const uint64_t n = d.n, nb = d.nb, N = nb + 1, bits = d.total_bits;
-    const uint64_t beta = (bits << 16) / n;
-    const uint64_t ys_last = n - nb * (uint64_t)d.delta_s;
-    const int64_t z_last = (int64_t)bits - (int64_t)((beta * n) >> 16);
+    const uint64_t n = d.n, nb = d.nb, N = nb + 1, bits = d.total_bits, U = d.range_total;
+    const uint64_t beta = (bits << 16) / U;
+    const uint64_t ys_last = U - nb * (uint64_t)d.delta_s;
+    const int64_t z_last = (int64_t)bits - (int64_t)((beta * U) >> 16);
     const uint64_t yz_last = (uint64_t)(z_last - (int64_t)nb * (int64_t)d.delta_z);
     const uint32_t Ws = ef_width(N, ys_last), Wz = ef_width(N, yz_last);
     h[0] = kMagic;
@@ -1481,7 +1543,7 @@ __device__ uint64_t geometry_of(BuildDesc& d, uint64_t* h) {
     h[4] = d.bucket;
     h[5] = nb;
     h[6] = d.maxm;
-    h[7] = (uint64_t)Ws | ((uint64_t)Wz << 8) | ((uint64_t)d.gr_max << 16);
+    h[7] = (uint64_t)Ws | ((uint64_t)Wz << 8) | ((uint64_t)d.gr_max << 16) | ((uint64_t)d.slack << 40);
     h[8] = d.delta_s;
     h[9] = (uint64_t)d.delta_z;
     h[10] = beta;
@@ -1674,21 +1736,28 @@ uint32_t xcd_count() {
 // Search kernel of a (leaf-size class, wavefronts per workgroup) pair.
 using SearchKernel = void (*)(SearchArgs);
 
-template <int MAXL>
+template <int MAXL, bool WIDE>
 SearchKernel search_kernel_waves(uint32_t waves) {
     switch (waves) {
-        case 1: return k_search<MAXL, 1>;
-        case 2: return k_search<MAXL, 2>;
-        case 4: return k_search<MAXL, 4>;
-        default: return k_search<MAXL, 8>;
+        case 1: return k_search<MAXL, 1, WIDE>;
+        case 2: return k_search<MAXL, 2, WIDE>;
+        case 4: return k_search<MAXL, 4, WIDE>;
+        default: return k_search<MAXL, 8, WIDE>;
     }
 }
 
-SearchKernel search_kernel(uint32_t max_leaf, uint32_t waves) {
-    if (max_leaf <= 8) return search_kernel_waves<8>(waves);
-    if (max_leaf <= 12) return search_kernel_waves<12>(waves);
-    if (max_leaf <= 16) return search_kernel_waves<16>(waves);
-    return search_kernel_waves<24>(waves);
+// Calls with a non-minimal build take the kernels whose leaves search
+// injections into a larger range (three leaf-size classes).
+SearchKernel search_kernel(uint32_t max_leaf, uint32_t waves, bool wide) {
+    if (wide) {
+        if (max_leaf <= 8) return search_kernel_waves<8, true>(waves);
+        if (max_leaf <= 16) return search_kernel_waves<16, true>(waves);
+        return search_kernel_waves<24, true>(waves);
+    }
+    if (max_leaf <= 8) return search_kernel_waves<8, false>(waves);
+    if (max_leaf <= 12) return search_kernel_waves<12, false>(waves);
+    if (max_leaf <= 16) return search_kernel_waves<16, false>(waves);
+    return search_kernel_waves<24, false>(waves);
 }
 
 // One launch of the search over every bucket of the call: one workgroup of
@@ -1710,8 +1779,8 @@ int static_lds(const void* k, size_t* out) {
     return RS_OK;
 }
 
-int launch_search(uint32_t max_leaf, uint32_t waves, const SearchArgs& sa, size_t lds, hipStream_t s) {
-    SearchKernel k = search_kernel(max_leaf, waves);
+int launch_search(uint32_t max_leaf, uint32_t waves, bool wide, const SearchArgs& sa, size_t lds, hipStream_t s) {
+    SearchKernel k = search_kernel(max_leaf, waves, wide);
     size_t static_bytes = 0;
     if (int rc = static_lds(reinterpret_cast<const void*>(k), &static_bytes)) return rc;
     if (lds + static_bytes > (size_t)max_lds_bytes())
@@ -1801,7 +1870,7 @@ int tune_search(TuneCtx& t, uint32_t leaf, BuildDesc* hdesc, BuildDesc* d_desc, 
         hdesc[0].waves = sc.waves;
         RS_HIP(hipMemcpyAsync(d_desc, hdesc, sizeof(BuildDesc), hipMemcpyHostToDevice, s));
         RS_HIP(hipEventRecord(e0, s));
-        if (int rc = launch_search(leaf, sc.waves, sa, lds, s)) return rc;
+        if (int rc = launch_search(leaf, sc.waves, false, sa, lds, s)) return rc;
         RS_HIP(hipEventRecord(e1, s));
         RS_HIP(hipEventSynchronize(e1));
         float f = 0;
@@ -1837,7 +1906,7 @@ int tune_search(TuneCtx& t, uint32_t leaf, BuildDesc* hdesc, BuildDesc* d_desc, 
         (void)hipGetDevice(&dev);
         (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                &per_cu, reinterpret_cast<const void*>(search_kernel(leaf, cur.waves)), 64 * (int)cur.waves, lds) !=
+                &per_cu, reinterpret_cast<const void*>(search_kernel(leaf, cur.waves, false)), 64 * (int)cur.waves, lds) !=
             hipSuccess)
             per_cu = 1;
         t.resident = (uint64_t)std::max(per_cu, 1) * (uint64_t)std::max(cus, 1);
@@ -1896,13 +1965,21 @@ done:
 // A plan enqueues the same phases without the two host reads (sizes fixed by
 // caps) and captures them into one HIP graph.
 // ---------------------------------------------------------------------------
+// A set of per-size tables: they depend on the leaf size, the size above
+// which splits take the Sec. 7.2 approximation, and the non-minimal slack.
+struct TabKey {
+    uint32_t leaf, gr_max, slack;
+    bool operator==(const TabKey& o) const { return leaf == o.leaf && gr_max == o.gr_max && slack == o.slack; }
+};
+
 struct Batch {
     uint32_t count = 0;
     std::vector<int> st;
     std::vector<std::string> why;
     std::vector<BuildDesc> hd;
     std::vector<uint32_t> which;  // desc index -> position in the call
-    std::vector<std::pair<uint32_t, uint32_t>> tab_keys;  // (leaf, gr_max) of each table set
+    std::vector<TabKey> tab_keys;  // of each table set
+    bool wide = false;             // some build is non-minimal
     uint64_t total = 0, nbuckets = 0, seed_cap = kDefaultSeedCap;
     uint32_t wait_limit = kDefaultWaitLimit;
     uint32_t K = 0, max_leaf = 1, launch_waves = 1;
@@ -1912,6 +1989,7 @@ struct Batch {
     uint64_t *d_lo = nullptr, *d_bst = nullptr, *d_sorted = nullptr, *d_tmp = nullptr, *d_seeds = nullptr;
     uint64_t *d_blen = nullptr, *d_ost = nullptr, *d_tiles = nullptr, *d_kb = nullptr, *d_bb = nullptr;
     uint64_t *d_eb = nullptr, *d_hdr = nullptr, *d_raw = nullptr, *d_boff = nullptr;
+    uint64_t* d_qst = nullptr;  // prefix sums of bucket ranges (non-minimal calls; else d_bst)
     uint64_t* d_binst = nullptr;
     uint32_t* d_bid = nullptr;
     unsigned long long *d_bincnt = nullptr, *d_bincur = nullptr;
@@ -1948,6 +2026,10 @@ int batch_prepare(Batch& b, const rs_keys* sets, uint32_t count, const uint32_t*
         else if (!k.data) bad = "NULL key data";
         else if (k.kind != RS_KEYS_U64 && k.kind != RS_KEYS_BYTES) bad = "unknown key kind";
         else if (k.kind == RS_KEYS_BYTES && !k.offsets) bad = "NULL offsets for byte keys";
+        else if (opts && opts->gr_table_max >= (1u << 24)) bad = "gr_table_max must be below 2^24";
+        else if (opts && opts->leaf_slack > kMaxSlack) bad = "leaf_slack must be at most 255";
+        else if (opts && leaf_range(leaf, opts->leaf_slack) > kMaxLeafRange)
+            bad = "leaf_slack gives leaves more than 32 values";
         if (bad) {
             b.st[c] = RS_EINVAL;
             b.why[c] = bad;
@@ -1967,9 +2049,10 @@ int batch_prepare(Batch& b, const rs_keys* sets, uint32_t count, const uint32_t*
         d.upper = sg.upper;
         d.bucket = bucket;
         d.gr_max = opts ? opts->gr_table_max : 0;
-        const std::pair<uint32_t, uint32_t> key{leaf, d.gr_max};
+        d.slack = opts ? opts->leaf_slack : 0;
+        const TabKey key{leaf, d.gr_max, d.slack};
         uint32_t t = 0;
-        while (t < b.tab_keys.size() && b.tab_keys[t] != key) t++;
+        while (t < b.tab_keys.size() && !(b.tab_keys[t] == key)) t++;
         if (t == b.tab_keys.size()) b.tab_keys.push_back(key);
         d.tab = t;
         d.aligned = ((uintptr_t)k.data & 7) == 0;
@@ -1993,6 +2076,7 @@ int batch_prepare(Batch& b, const rs_keys* sets, uint32_t count, const uint32_t*
         b.total += d.n;
         b.nbuckets += d.nb;
         b.max_leaf = std::max(b.max_leaf, leaf);
+        b.wide |= d.slack != 0;
         b.hd.push_back(d);
         b.which.push_back(c);
     }
@@ -2053,6 +2137,7 @@ int batch_layout(Batch& b) {
     b.d_blen = (uint64_t*)carve(NB * 8);
     b.d_ost = (uint64_t*)carve((NB + 1) * 8);
     b.d_tiles = (uint64_t*)carve(ntiles * 8);
+    b.d_qst = b.wide ? (uint64_t*)carve((NB + 1) * 8) : nullptr;
     // one contiguous block, mirrored in the pinned staging, so that one copy
     // takes it in (bases, descriptors) and one brings it back (descriptors,
     // headers, blob sizes and offsets, status words)
@@ -2069,6 +2154,8 @@ void batch_bind(Batch& b, char* ws, char* pin) {
     auto at = [&](auto& p) { p = reinterpret_cast<std::remove_reference_t<decltype(p)>>(ws + (size_t)p); };
     at(b.d_lo); at(b.d_bid); at(b.d_bincnt); at(b.d_binst); at(b.d_bincur); at(b.d_bst); at(b.d_sorted);
     at(b.d_tmp); at(b.d_seeds); at(b.d_blen); at(b.d_ost); at(b.d_tiles); at(b.d_kb);
+    if (b.wide) at(b.d_qst);
+    else b.d_qst = b.d_bst;
     const uint32_t K = b.K;
     // [key bases | bucket bases | entry bases | descriptors | headers | raw words | offsets | status]
     auto lay = [K](char* base, uint64_t*& kb, BuildDesc*& desc, uint64_t*& hdr, uint64_t*& raw, uint64_t*& boff,
@@ -2136,15 +2223,17 @@ int upload_batch_tables(Batch& b, uint32_t maxm, hipStream_t s) {
     b.stride = maxm + 1;
     uint32_t max_nodes = 0;
     for (uint32_t t = 0; t < (uint32_t)b.tab_keys.size(); t++) {
-        TableView tv = host_tables(b.tab_keys[t].first, maxm, b.tab_keys[t].second);
+        const TabKey& key = b.tab_keys[t];
+        TableView tv = host_tables(key.leaf, maxm, key.gr_max, key.slack);
         if (!tv.data) return fail(RS_ENOMEM, "table allocation failed");
         for (uint32_t m = 0; m <= maxm; m++) max_nodes = std::max(max_nodes, tv.N()[m]);
         uint32_t* dst = b.d_tab + (size_t)t * kTableCount * b.stride;
-        RS_ENQ(hipMemcpyAsync(dst, tv.r(), b.stride * 4ull, hipMemcpyHostToDevice, s));
-        RS_ENQ(hipMemcpyAsync(dst + b.stride, tv.F(), b.stride * 4ull, hipMemcpyHostToDevice, s));
-        RS_ENQ(hipMemcpyAsync(dst + 2 * b.stride, tv.N(), b.stride * 4ull, hipMemcpyHostToDevice, s));
-        RS_ENQ(hipMemcpyAsync(dst + 3 * b.stride, tv.G(), b.stride * 4ull, hipMemcpyHostToDevice, s));
-        RS_ENQ(hipMemcpyAsync(dst + 4 * b.stride, tv.P(), b.stride * 4ull, hipMemcpyHostToDevice, s));
+        if (key.slack && !ranges_increasing(tv.Q(), maxm))
+            return fail(RS_EINVAL, "leaf_slack %u gives two bucket sizes the same range", key.slack);
+        // the cached tables hold cap + 1 >= stride entries per array
+        for (int a = 0; a < kTableCount; a++)
+            RS_ENQ(hipMemcpyAsync(dst + (size_t)a * b.stride, tv.data + (size_t)a * (tv.cap + 1), b.stride * 4ull,
+                                  hipMemcpyHostToDevice, s));
     }
     b.lds = (size_t)maxm * 8 + (size_t)max_nodes * 16;
     return RS_OK;
@@ -2165,10 +2254,15 @@ SearchArgs search_args(const Batch& b) {
 // and the arena offsets (d_boff[K] = arena words).
 int enqueue_back(Batch& b, hipStream_t s, PhaseEvents* pe) {
     if (pe) pe->record(3, s);
-    if (int rc = launch_search(b.max_leaf, b.launch_waves, search_args(b), b.lds, s)) return rc;
+    if (int rc = launch_search(b.max_leaf, b.launch_waves, b.wide, search_args(b), b.lds, s)) return rc;
     if (pe) pe->record(4, s);
     if (int rc = scan<uint64_t>(b.d_blen, b.nbuckets, b.d_ost, b.d_tiles, nullptr, s)) return rc;
-    GapArgs ga{b.d_bst, b.d_ost, b.d_desc, b.d_desc, b.d_bb, b.K, b.nbuckets};
+    if (b.wide) {  // bucket ranges into the bit lengths' array (scanned already), then their prefix sums
+        RS_LAUNCH(k_range_sizes, grid_for(b.nbuckets, kBlock), kBlock, 0, s, b.d_bst, b.d_desc, b.d_bb, b.K,
+                  b.nbuckets, b.d_tab, b.stride, b.d_blen);
+        if (int rc = scan<uint64_t>(b.d_blen, b.nbuckets, b.d_qst, b.d_tiles, nullptr, s)) return rc;
+    }
+    GapArgs ga{b.d_bst, b.d_qst, b.d_ost, b.d_desc, b.d_desc, b.d_bb, b.K, b.nbuckets};
     RS_LAUNCH(k_ef_gaps, grid_for(b.nbuckets, kGapTile), kBlock, 0, s, ga);
     RS_LAUNCH(k_layout, 1, kBlock, 0, s, b.d_desc, b.K, b.d_hdr, b.d_raw, b.d_boff);
     if (pe) pe->record(5, s);
@@ -2185,7 +2279,8 @@ int enqueue_fill(Batch& b, uint64_t* arena, uint64_t capacity, uint64_t clear_wo
     if (arena && clear_words)
         RS_LAUNCH(k_fill_u64, grid_for(clear_words, kBlock * 8), kBlock, 0, s, arena, clear_words, 0);
     RS_LAUNCH(k_write_headers, grid_for((uint64_t)K * kHeaderWords, kBlock), kBlock, 0, s, b.d_desc, b.d_hdr, K);
-    FillArgs fa{b.d_bst, b.d_ost, b.d_seeds, b.d_bid, b.d_desc, b.d_bb, b.d_eb, K, b.nbuckets, b.d_tab, b.stride, 0};
+    FillArgs fa{b.d_bst, b.d_qst, b.d_ost, b.d_seeds, b.d_bid, b.d_desc, b.d_bb, b.d_eb, K, b.nbuckets, b.d_tab,
+                b.stride, 0};
     RS_LAUNCH(k_ef_fill, grid_for(b.nbuckets + K, kBlock), kBlock, 0, s, fa);
     // kTreeLanes lanes per bucket, in launches of at most max_grid_blocks() blocks
     if (int rc = for_each_chunk(b.nbuckets, kBlock, kBlock / kTreeLanes, [&](uint64_t g0, uint64_t, uint64_t blocks) -> int {
@@ -2277,9 +2372,10 @@ void make_blobs(Batch& b, uint64_t* words, uint32_t* tables, uint32_t stride, co
         blob->tables = tables + (size_t)b.h_desc[j].tab * kTableCount * stride;
         blob->tab_stride = stride;
         {
-            const auto& key = b.tab_keys[b.h_desc[j].tab];
-            const TableView tv = host_tables(key.first, stride - 1, key.second);
-            blob->packed = tv.data && packed_valid(tv.P(), (uint32_t)b.h_hdr[(size_t)j * kHeaderWords + 6]);
+            const TabKey& key = b.tab_keys[b.h_desc[j].tab];
+            const TableView tv = host_tables(key.leaf, stride - 1, key.gr_max, key.slack);
+            blob->packed = !key.slack && tv.data &&
+                           packed_valid(tv.P(), (uint32_t)b.h_hdr[(size_t)j * kHeaderWords + 6]);
         }
         memcpy(blob->header, b.h_hdr + (size_t)j * kHeaderWords, sizeof blob->header);
         blob->ready = arena->ready;
@@ -2469,7 +2565,7 @@ void plan_release(rs_plan* p) {
 // Largest bucket of which the search still fits the LDS with the tables of
 // this batch (binary search over the dynamic LDS the launch would ask for).
 uint32_t lds_bucket_limit(Batch& b) {
-    SearchKernel k = search_kernel(b.max_leaf, b.launch_waves);
+    SearchKernel k = search_kernel(b.max_leaf, b.launch_waves, b.wide);
     size_t static_bytes = 0;
     if (static_lds(reinterpret_cast<const void*>(k), &static_bytes)) return 0;
     const size_t avail = (size_t)max_lds_bytes() - static_bytes;
@@ -2478,7 +2574,7 @@ uint32_t lds_bucket_limit(Batch& b) {
         const uint32_t mid = (lo + hi + 1) / 2;
         uint32_t nodes = 0;
         for (const auto& key : b.tab_keys) {
-            TableView tv = host_tables(key.first, mid, key.second);
+            TableView tv = host_tables(key.leaf, mid, key.gr_max, key.slack);
             if (!tv.data) return 0;
             for (uint32_t m = 0; m <= mid; m++) nodes = std::max(nodes, tv.N()[m]);
         }

@@ -60,6 +60,7 @@ struct Layout {
     uint64_t n, leaf, bucket, nb, maxm, kind;
     uint32_t Ws, Wz;
     uint32_t gr_max;  // splits above this size take the Sec. 7.2 parameter approximation (0: none)
+    uint32_t slack;   // non-minimal variant: leaves map into leaf_range(m, slack) values (0: minimal)
     uint64_t delta_s;
     int64_t delta_z;
     uint64_t beta;
@@ -70,8 +71,9 @@ struct Layout {
 };
 Layout layout_of(const uint64_t* header);
 
-// Upload the per-size tables of (leaf, maxm, gr_max) into dst (3 * (maxm + 1) u32).
-int upload_tables(uint32_t leaf, uint32_t maxm, uint32_t gr_max, uint32_t* dst, hipStream_t s);
+// Upload the per-size tables of (leaf, maxm, gr_max, slack) into dst
+// (kTableCount * (maxm + 1) u32).
+int upload_tables(uint32_t leaf, uint32_t maxm, uint32_t gr_max, uint32_t slack, uint32_t* dst, hipStream_t s);
 
 // Search schedules: the built-in one of a leaf size for a launch over
 // `buckets` buckets in all, range checks, and the process-wide table filled by

@@ -93,13 +93,22 @@ __host__ __device__ inline SplitShape split_shape(uint32_t m, uint32_t leaf, uin
     return s;
 }
 
+// Non-minimal variant (the larger codomain that Sec. 9 proposes): a leaf of
+// m >= 2 keys maps injectively into m + ceil(m slack / 256) values; slack = 0
+// is the minimal structure.
+__host__ __device__ inline uint32_t leaf_range(uint32_t m, uint32_t slack) {
+    return m <= 1 ? m : m + (m * slack + 255u) / 256u;
+}
+
 // Per-size tables for sizes 0..cap (cap >= the requested maxm), laid out as
-// r[cap+1], F[cap+1], N[cap+1], G[cap+1], P[cap+1]: Golomb-Rice parameter of
-// a node, fixed bits of a subtree, coded nodes of a subtree, log2 of the lanes
-// that share one candidate in the split search of a node of that size, and
-// r, N and F of the size packed into one word (footnote of Sec. 7.2: bits 0-4
-// r, 5-15 N, 16-31 F; kNoPacked where they do not fit).  The host memory is
-// pinned and stays valid for the life of the process.
+// r[cap+1], F[cap+1], N[cap+1], G[cap+1], P[cap+1], Q[cap+1]: Golomb-Rice
+// parameter of a node, fixed bits of a subtree, coded nodes of a subtree,
+// log2 of the lanes that share one candidate in the split search of a node of
+// that size, r, N and F of the size packed into one word (footnote of Sec.
+// 7.2: bits 0-4 r, 5-15 N, 16-31 F; kNoPacked where they do not fit), and the
+// number of output values of a subtree (m for the minimal structure; with
+// slack, leaf_range for a leaf and the sum over the parts for a split).  The
+// host memory is pinned and stays valid for the life of the process.
 struct TableView {
     const uint32_t* data;
     uint32_t cap;
@@ -108,8 +117,9 @@ struct TableView {
     const uint32_t* N() const { return data + 2 * (cap + 1); }
     const uint32_t* G() const { return data + 3 * (cap + 1); }
     const uint32_t* P() const { return data + 4 * (cap + 1); }
+    const uint32_t* Q() const { return data + 5 * (cap + 1); }
 };
-constexpr int kTableCount = 5;
+constexpr int kTableCount = 6;
 constexpr uint32_t kNoPacked = 0xffffffffu;
 __host__ __device__ inline uint32_t packed_r(uint32_t w) { return w & 31u; }
 __host__ __device__ inline uint32_t packed_N(uint32_t w) { return (w >> 5) & 2047u; }
@@ -118,10 +128,19 @@ __host__ __device__ inline uint32_t packed_F(uint32_t w) { return w >> 16; }
 bool packed_valid(const uint32_t* P, uint32_t maxm);
 // gr_max > 0: split nodes of more than gr_max keys take the integer
 // approximation of their Golomb-Rice parameter (Sec. 7.2) instead of eq. (4).
-TableView host_tables(uint32_t leaf, uint32_t maxm, uint32_t gr_max = 0);
+// slack > 0: leaves map into leaf_range(m, slack) values, which changes their
+// success probability (and so r) and the output ranges Q.
+TableView host_tables(uint32_t leaf, uint32_t maxm, uint32_t gr_max = 0, uint32_t slack = 0);
 // The same tables for sizes 0..maxm written into dst (kTableCount * (maxm + 1)
-// words, r then F then N then G then P), without any allocation.
-void fill_tables(uint32_t leaf, uint32_t maxm, uint32_t* dst, uint32_t gr_max = 0);
+// words, in the order above), without any allocation.
+void fill_tables(uint32_t leaf, uint32_t maxm, uint32_t* dst, uint32_t gr_max = 0, uint32_t slack = 0);
+// True if the output range Q grows strictly with the size for 0..maxm (the
+// lookup recovers a bucket's size from its range).
+bool ranges_increasing(const uint32_t* Q, uint32_t maxm);
+// Largest slack of the non-minimal variant: ranges stay below 2^32 and a
+// leaf's values fit one 32-bit mask.
+constexpr uint32_t kMaxSlack = 255;
+constexpr uint32_t kMaxLeafRange = 32;
 
 // ---------------------------------------------------------------------------
 // Device helpers.

@@ -7,6 +7,7 @@
 #include <cstdlib>
 #include <map>
 #include <mutex>
+#include <tuple>
 #include <vector>
 
 #include "rs_internal.h"
@@ -24,7 +25,13 @@ namespace {
 
 // ln of the probability that one trial succeeds at a node of m keys:
 // m!/m^m for a bijection, times prod k_j^k_j / k_j! for a split (eq. (2)).
-double log_success(const Strategy& st, uint32_t m) {
+// With slack, a leaf succeeds when its hash is injective into M =
+// leaf_range(m) values: prod_{i<m} (M - i) / M.
+double log_success(const Strategy& st, uint32_t m, uint32_t slack) {
+    if (m <= st.leaf && slack) {
+        const double M = (double)leaf_range(m, slack);
+        return std::lgamma(M + 1.0) - std::lgamma(M - (double)m + 1.0) - (double)m * std::log(M);
+    }
     double lp = std::lgamma((double)m + 1.0) - (double)m * std::log((double)m);
     if (m <= st.leaf) return lp;
     SplitShape sh = split_shape(m, st.leaf, st.lower, st.upper);
@@ -65,7 +72,7 @@ struct LeafTables {
 };
 
 std::mutex g_mu;
-std::map<std::pair<uint32_t, uint32_t>, LeafTables> g_cache;  // by (leaf, gr_max)
+std::map<std::tuple<uint32_t, uint32_t, uint32_t>, LeafTables> g_cache;  // by (leaf, gr_max, slack)
 
 // Lanes per candidate for the split search of a node of m keys: the 2^g
 // minimising expected VALU work = steps * (keys per lane * cost per key +
@@ -95,24 +102,28 @@ uint32_t lanes_per_candidate(const Strategy& st, uint32_t m, double trials) {
     return best_g;
 }
 
-void fill(const Strategy& st, uint32_t cap, uint32_t* r, uint32_t* F, uint32_t* N, uint32_t* G, uint32_t* P,
-          uint32_t gr_max) {
+void fill(const Strategy& st, uint32_t cap, uint32_t* dst, uint32_t gr_max, uint32_t slack) {
+    const size_t w = (size_t)cap + 1;
+    uint32_t *r = dst, *F = dst + w, *N = dst + 2 * w, *G = dst + 3 * w, *P = dst + 4 * w, *Q = dst + 5 * w;
     for (uint32_t m = 0; m <= cap; m++) {
         G[m] = 0;
         if (m < 2) {
             r[m] = F[m] = N[m] = 0;
             P[m] = 0;
+            Q[m] = m;
             continue;
         }
-        const double lp = log_success(st, m);
+        const double lp = log_success(st, m, slack);
         r[m] = gr_max && m > st.leaf && m > gr_max ? rice_parameter_large(st, m) : rice_parameter(std::exp(lp));
         if (m > st.leaf) G[m] = lanes_per_candidate(st, m, std::exp(-lp));
         F[m] = r[m];
         N[m] = 1;
+        Q[m] = leaf_range(m, slack);
         if (m > st.leaf) {
             SplitShape sh = split_shape(m, st.leaf, st.lower, st.upper);
             F[m] += (sh.fanout - 1) * F[sh.unit] + F[sh.last];
             N[m] += (sh.fanout - 1) * N[sh.unit] + N[sh.last];
+            Q[m] = (sh.fanout - 1) * Q[sh.unit] + Q[sh.last];
         }
         P[m] = r[m] < 32 && N[m] < 2048 && F[m] < 65536 ? r[m] | N[m] << 5 | F[m] << 16 : kNoPacked;
     }
@@ -120,9 +131,14 @@ void fill(const Strategy& st, uint32_t cap, uint32_t* r, uint32_t* F, uint32_t* 
 
 }  // namespace
 
-void fill_tables(uint32_t leaf, uint32_t maxm, uint32_t* dst, uint32_t gr_max) {
-    fill(make_strategy(leaf), maxm, dst, dst + maxm + 1, dst + 2 * (maxm + 1), dst + 3 * (maxm + 1),
-         dst + 4 * (maxm + 1), gr_max);
+void fill_tables(uint32_t leaf, uint32_t maxm, uint32_t* dst, uint32_t gr_max, uint32_t slack) {
+    fill(make_strategy(leaf), maxm, dst, gr_max, slack);
+}
+
+bool ranges_increasing(const uint32_t* Q, uint32_t maxm) {
+    for (uint32_t m = 1; m <= maxm; m++)
+        if (Q[m] <= Q[m - 1]) return false;
+    return true;
 }
 
 bool packed_valid(const uint32_t* P, uint32_t maxm) {
@@ -131,9 +147,9 @@ bool packed_valid(const uint32_t* P, uint32_t maxm) {
     return true;
 }
 
-TableView host_tables(uint32_t leaf, uint32_t maxm, uint32_t gr_max) {
+TableView host_tables(uint32_t leaf, uint32_t maxm, uint32_t gr_max, uint32_t slack) {
     std::lock_guard<std::mutex> lock(g_mu);
-    LeafTables& t = g_cache[{leaf, gr_max}];
+    LeafTables& t = g_cache[{leaf, gr_max, slack}];
     if (t.data == nullptr || t.cap < maxm) {
         uint32_t cap = std::max<uint32_t>(maxm, std::max<uint32_t>(1024u, t.cap * 2));
         uint32_t* buf = nullptr;
@@ -144,8 +160,7 @@ TableView host_tables(uint32_t leaf, uint32_t maxm, uint32_t gr_max) {
             buf = static_cast<uint32_t*>(std::malloc(bytes));
             if (!buf) return TableView{nullptr, 0};
         }
-        fill(make_strategy(leaf), cap, buf, buf + cap + 1, buf + 2 * (cap + 1), buf + 3 * (cap + 1),
-             buf + 4 * (cap + 1), gr_max);
+        fill(make_strategy(leaf), cap, buf, gr_max, slack);
         t.cap = cap;
         t.data = buf;  // the previous buffer is intentionally kept alive
     }
@@ -176,6 +191,21 @@ extern "C" int rs_tables_ex(uint32_t leaf, uint32_t maxm, uint32_t gr_table_max,
         r[m] = t.r()[m];
         F[m] = t.F()[m];
         N[m] = t.N()[m];
+    }
+    return RS_OK;
+}
+
+extern "C" int rs_tables_range(uint32_t leaf, uint32_t maxm, uint32_t gr_table_max, uint32_t leaf_slack, uint32_t* r,
+                               uint32_t* F, uint32_t* N, uint32_t* Q) {
+    if (leaf < 1 || leaf > rs::kMaxLeaf || leaf_slack > rs::kMaxSlack || !r || !F || !N || !Q) return RS_EINVAL;
+    if (rs::leaf_range(leaf, leaf_slack) > rs::kMaxLeafRange) return RS_EINVAL;
+    rs::TableView t = rs::host_tables(leaf, maxm, gr_table_max, leaf_slack);
+    if (!t.data) return RS_ENOMEM;
+    for (uint32_t m = 0; m <= maxm; m++) {
+        r[m] = t.r()[m];
+        F[m] = t.F()[m];
+        N[m] = t.N()[m];
+        Q[m] = t.Q()[m];
     }
     return RS_OK;
 }

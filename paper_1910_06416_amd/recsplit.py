@@ -41,7 +41,7 @@ class rs_keys(ctypes.Structure):
 class rs_options(ctypes.Structure):
     _fields_ = [("seed_cap", ctypes.c_uint64), ("flags", ctypes.c_uint32), ("stage_from", ctypes.c_uint32),
                 ("group_max", ctypes.c_uint32), ("waves", ctypes.c_uint32), ("wait_limit", ctypes.c_uint32),
-                ("gr_table_max", ctypes.c_uint32)]
+                ("gr_table_max", ctypes.c_uint32), ("leaf_slack", ctypes.c_uint32)]
 
 
 RS_OPT_TIMING, RS_OPT_TUNED = 1, 2
@@ -105,6 +105,7 @@ def lib() -> ctypes.CDLL:
         L.rs_tables.argtypes = [U32, U32, P, P, P]
         L.rs_tables_ex.argtypes = [U32, U32, U32, P, P, P]
         L.rs_tables_packed.argtypes = [U32, U32, U32, P]
+        L.rs_tables_range.argtypes = [U32, U32, U32, U32, P, P, P, P]
         L.rs_last_build_stats.argtypes = [ctypes.POINTER(rs_build_stats)]
         L.rs_build_batch.argtypes = [ctypes.POINTER(rs_keys), U32, P, P, ctypes.POINTER(rs_options), P, P, P]
         PU64, PI, PD, PU32 = (ctypes.POINTER(U64), ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
@@ -136,7 +137,7 @@ def lib() -> ctypes.CDLL:
                   "rs_tables", "rs_last_build_stats", "rs_build_batch", "rs_server_create", "rs_server_create_ex", "rs_server_submit_build",
                   "rs_server_submit_lookup", "rs_server_poll", "rs_server_wait", "rs_server_get_stats", "rs_autotune",
                   "rs_schedule_get", "rs_schedule_set", "rs_plan_create", "rs_plan_run", "rs_plan_info",
-                  "rs_set_allocator", "rs_tables_ex", "rs_tables_packed"):
+                  "rs_set_allocator", "rs_tables_ex", "rs_tables_packed", "rs_tables_range"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
         use_torch_allocator()
@@ -255,29 +256,30 @@ class Blob:
 
 
 def _options(seed_cap=0, timing=False, tuned=False, stage_from=0, group_max=0, waves=0, wait_limit=0,
-             gr_table_max=0) -> rs_options:
+             gr_table_max=0, leaf_slack=0) -> rs_options:
     flags = (RS_OPT_TIMING if timing else 0) | (RS_OPT_TUNED if tuned else 0)
-    return rs_options(seed_cap, flags, stage_from, group_max, waves, wait_limit, gr_table_max)
+    return rs_options(seed_cap, flags, stage_from, group_max, waves, wait_limit, gr_table_max, leaf_slack)
 
 
 def build(keys, leaf: int, bucket: int, seed_cap: int = 0, timing: bool = False, stage_from: int = 0,
           group_max: int = 0, waves: int = 0, tuned: bool = False, wait_limit: int = 0, gr_table_max: int = 0,
-          stream=None) -> Blob:
+          leaf_slack: int = 0, stream=None) -> Blob:
     """Build the minimal perfect hash function of a device key set.  With
     timing=True the per-phase device times are available from last_build_stats().
     tuned=True takes the search schedule of (leaf, bucket) from the schedule
     table (see autotune); stage_from / group_max / waves override it.  Schedules
-    never change the result.  wait_limit and gr_table_max are the rs_options
-    fields of those names."""
+    never change the result.  wait_limit, gr_table_max and leaf_slack are the
+    rs_options fields of those names."""
     k = _as_keys(keys)
     h = ctypes.c_void_p()
-    opts = _options(seed_cap, timing, tuned, stage_from, group_max, waves, wait_limit, gr_table_max)
+    opts = _options(seed_cap, timing, tuned, stage_from, group_max, waves, wait_limit, gr_table_max, leaf_slack)
     _check(lib().rs_build_ex(ctypes.byref(k), leaf, bucket, ctypes.byref(opts), _stream(stream), ctypes.byref(h)))
     return Blob(h)
 
 
 def build_batch(key_sets, leafs, buckets, seed_cap: int = 0, timing: bool = False, stage_from: int = 0,
-                group_max: int = 0, waves: int = 0, tuned: bool = False, gr_table_max: int = 0, stream=None):
+                group_max: int = 0, waves: int = 0, tuned: bool = False, gr_table_max: int = 0, leaf_slack: int = 0,
+                stream=None):
     """Build many MPHFs in one call.  Returns (blobs, statuses): blobs[i] is a
     Blob or None when statuses[i] != RS_OK.  Raises only when the call itself
     fails (no build could be attempted)."""
@@ -291,7 +293,7 @@ def build_batch(key_sets, leafs, buckets, seed_cap: int = 0, timing: bool = Fals
     bk = np.ascontiguousarray(buckets, dtype=np.uint32)
     outs = (ctypes.c_void_p * count)()
     status = np.zeros(count, dtype=np.int32)
-    opts = _options(seed_cap, timing, tuned, stage_from, group_max, waves, 0, gr_table_max)
+    opts = _options(seed_cap, timing, tuned, stage_from, group_max, waves, 0, gr_table_max, leaf_slack)
     rc = lib().rs_build_batch(arr, count, lf.ctypes.data, bk.ctypes.data, ctypes.byref(opts), _stream(stream),
                               ctypes.cast(outs, ctypes.c_void_p), status.ctypes.data)
     blobs = [Blob(ctypes.c_void_p(outs[i])) if outs[i] else None for i in range(count)]
@@ -424,6 +426,14 @@ def tables(leaf: int, maxm: int, gr_table_max: int = 0):
     N = np.zeros(maxm + 1, dtype=np.uint32)
     _check(lib().rs_tables_ex(leaf, maxm, gr_table_max, r.ctypes.data, F.ctypes.data, N.ctypes.data))
     return r, F, N
+
+
+def range_tables(leaf: int, maxm: int, leaf_slack: int, gr_table_max: int = 0):
+    """rs_tables_range: (r, F, N, Q) of the non-minimal variant with the given
+    slack, Q[m] being the output values of a subtree of m keys."""
+    out = [np.zeros(maxm + 1, dtype=np.uint32) for _ in range(4)]
+    _check(lib().rs_tables_range(leaf, maxm, gr_table_max, leaf_slack, *[a.ctypes.data for a in out]))
+    return tuple(out)
 
 
 class Server:

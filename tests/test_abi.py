@@ -156,3 +156,46 @@ def test_library_packed_table_equals_oracle(orc, leaf, T):
         assert got is None
     else:
         assert got is not None and np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("leaf,slack,T", [(8, 32, 0), (8, 255, 0), (5, 64, 0), (16, 16, 0), (16, 128, 500),
+                                          (24, 85, 0), (12, 1, 0), (2, 100, 0), (1, 255, 0)])
+def test_library_range_tables_equal_oracle(orc, leaf, slack, T):
+    """Non-minimal variant (Sec. 9): leaf parameters from the injection
+    probability into the larger range and the subtree ranges Q, written
+    independently on both sides, agree for sizes 0..4096."""
+    from paper_1910_06416_amd import recsplit
+
+    got = recsplit.range_tables(leaf, 4096, slack, T)
+    want = orc.range_tables(leaf, 4096, slack, T)
+    for g, w in zip(got, want):
+        assert np.array_equal(g.astype(np.uint64), w.astype(np.uint64))
+    Q = got[3].astype(np.int64)
+    assert (np.diff(Q) > 0).all() and Q[0] == 0 and Q[1] == 1
+    if leaf >= 2:
+        assert Q[leaf] == leaf + -(-leaf * slack // 256)
+
+
+def test_range_tables_refuse_leaves_over_32_values(lib):
+    from paper_1910_06416_amd import recsplit
+
+    with pytest.raises(recsplit.RecSplitError):
+        recsplit.range_tables(24, 100, 86)  # 24 + ceil(24 * 86 / 256) = 33 values
+    with pytest.raises(recsplit.RecSplitError):
+        recsplit.range_tables(8, 100, 256)
+    recsplit.range_tables(24, 100, 85)
+
+
+def test_build_option_validation_without_device(lib):
+    """Options the library refuses on the host, before any device work."""
+    from paper_1910_06416_amd import recsplit
+
+    keys = recsplit.rs_keys(recsplit.RS_KEYS_U64, 16, None, 10)
+    out = ctypes.c_void_p()
+    for opts in (recsplit._options(leaf_slack=256), recsplit._options(gr_table_max=1 << 24)):
+        assert lib.rs_build_ex(ctypes.byref(keys), 8, 100, ctypes.byref(opts), None, ctypes.byref(out)) == \
+            recsplit.RS_EINVAL
+    opts = recsplit._options(leaf_slack=86)
+    assert lib.rs_build_ex(ctypes.byref(keys), 24, 100, ctypes.byref(opts), None, ctypes.byref(out)) == \
+        recsplit.RS_EINVAL
+    assert b"32 values" in lib.rs_last_error()
