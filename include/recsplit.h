@@ -265,6 +265,31 @@ int rs_plan_info(const rs_plan* plan, uint32_t* bucket_cap, uint64_t* capacity_w
                  uint64_t* fallbacks);
 void rs_plan_destroy(rs_plan* plan);
 
+/* rs_build for callers that cannot allocate: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  It calls no hipMalloc,
+ * hipFree, pinned-host or other allocating device routine (host bookkeeping
+ * uses a few small heap objects).  The workspace and tables of the call live
+ * in a device array of 64 MiB that every GPU the library runs on holds from
+ * the time the library's kernels are loaded there until the process ends; key
+ * sets whose workspace (about 44 bytes per key plus 24 per bucket) and tables
+ * do not fit are refused with RS_EINVAL and a message, before any device work.
+ *   keys, leaf, bucket: as for rs_build.
+ *   blob_dev, blob_cap: the caller's device buffer and its size in bytes; the
+ *     serialized structure (the bytes rs_blob_to_host gives for rs_build's
+ *     blob of the same keys, l and b) is written there.
+ *   blob_bytes: receives the structure's size.  If blob_dev is NULL or
+ *     blob_cap is smaller, the call fails with RS_EINVAL and still sets
+ *     *blob_bytes to the size needed (after the whole search has run).
+ *   stream: all device work is enqueued on it; the call waits for it three
+ *     times and returns when the structure is complete.
+ * All calls on a GPU share that GPU's array, which keeps the last call's
+ * contents (every call rewrites what it reads).  Calls that overlapped on one
+ * GPU would race on it, so the library serializes them: one call at a time
+ * per process, and a call returns only once its device work is done.
+ * Errors: as rs_build, and RS_EINVAL for key sets beyond the array. */
+int rs_build_noalloc(const rs_keys* keys, uint32_t leaf, uint32_t bucket, void* blob_dev, uint64_t blob_cap,
+                     uint64_t* blob_bytes, void* stream);
+
 /* Rank of each query (lookup of Sec. 4 and Sec. 6.2): ranks_dev[i] = f(queries[i]).
  * Members of the built set get distinct values in [0, n).  Other keys get a
  * deterministic value in [0, n] (n only when their bucket is the last one and

@@ -2768,6 +2768,110 @@ extern "C" int rs_build(const rs_keys* keys, uint32_t leaf, uint32_t bucket, voi
     return rs_build_ex(keys, leaf, bucket, nullptr, stream, out);
 }
 
+// ---------------------------------------------------------------------------
+// Construction without allocation (rs_build_noalloc), for callers that cannot
+// allocate device memory.  The workspace and the per-size tables of the call
+// live in one file-scope device array, `scratch`; host-side staging lives in
+// static host buffers.  Each device holds its own copy of `scratch` from the
+// time the library's code object is loaded on it until the process ends.
+// Host code never uses the array's name as an address: its device address is
+// taken once per device with hipGetSymbolAddress and kept.
+// ---------------------------------------------------------------------------
+namespace rs {
+namespace {
+constexpr size_t kScratchBytes = 64ull << 20;  // workspace + tables of one call
+constexpr uint32_t kScratchDevices = 64;
+constexpr uint32_t kNoAllocMaxM = 16384;       // largest bucket (the search's LDS holds fewer keys)
+}  // namespace
+}  // namespace rs
+
+static __device__ __align__(256) unsigned char scratch[rs::kScratchBytes];
+
+namespace rs {
+namespace {
+
+std::mutex g_na_mu;  // one call at a time in this process: the host buffers below are shared
+alignas(256) char g_na_host[1 << 14];  // descriptors in, sizes and status out
+uint32_t g_na_tab[kTableCount * (kNoAllocMaxM + 1)];
+void* g_na_scratch[kScratchDevices] = {};
+
+// Device address of `scratch` on the current device (looked up once per device).
+int scratch_address(void** out) {
+    int dev = 0;
+    RS_HIP(hipGetDevice(&dev));
+    if (dev < 0 || (uint32_t)dev >= kScratchDevices) return fail(RS_EINVAL, "device %d out of range", dev);
+    if (!g_na_scratch[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(RS_EDEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+        g_na_scratch[dev] = p;
+    }
+    *out = g_na_scratch[dev];
+    return RS_OK;
+}
+
+}  // namespace
+}  // namespace rs
+
+extern "C" int rs_build_noalloc(const rs_keys* keys, uint32_t leaf, uint32_t bucket, void* blob_dev,
+                                uint64_t blob_cap, uint64_t* blob_bytes, void* stream) {
+    using namespace rs;
+    clear_error();
+    if (!keys || !blob_bytes) return fail(RS_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(g_na_mu);
+    hipStream_t s = (hipStream_t)stream;
+    char* base = nullptr;
+    if (int rc = scratch_address((void**)&base)) return rc;
+    Batch b;
+    if (int rc = batch_prepare(b, keys, 1, &leaf, &bucket, nullptr)) return rc;
+    if (b.K == 0) return batch_finish(b, nullptr, RS_OK);  // invalid arguments
+    if (int rc = batch_layout(b)) return rc;
+    const size_t ws_bytes = (b.ws_bytes + 255) & ~size_t(255);
+    if (ws_bytes > kScratchBytes)
+        return fail(RS_EINVAL, "%llu keys need %zu bytes of workspace; the allocation-free build holds %zu",
+                    (unsigned long long)keys->n, ws_bytes, kScratchBytes);
+    if (b.pin_bytes > sizeof g_na_host) return fail(RS_EINVAL, "host staging too small");
+    batch_bind(b, base, g_na_host);
+    // front: signatures and bucket order, then the largest bucket
+    if (int rc = enqueue_front(b, s, nullptr)) return rc;
+    RS_HIP(hipMemcpyAsync(b.h_st, b.d_st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
+    RS_HIP(hipStreamSynchronize(s));
+    const uint32_t maxm = b.h_st->maxm;
+    if (maxm > kNoAllocMaxM) return fail(RS_EINVAL, "largest bucket (%u keys) exceeds the local data share", maxm);
+    // tables after the workspace, filled on the host without allocating
+    const size_t tab_bytes = table_words(b, maxm) * 4;
+    if (ws_bytes + tab_bytes > kScratchBytes)
+        return fail(RS_EINVAL, "workspace and tables exceed the %zu bytes of the allocation-free build",
+                    kScratchBytes);
+    b.d_tab = reinterpret_cast<uint32_t*>(base + ws_bytes);
+    b.table_maxm = maxm;
+    b.stride = maxm + 1;
+    fill_tables(leaf, maxm, g_na_tab);
+    uint32_t max_nodes = 0;
+    for (uint32_t m = 0; m <= maxm; m++) max_nodes = std::max(max_nodes, g_na_tab[2 * (maxm + 1) + m]);
+    b.lds = (size_t)maxm * 8 + (size_t)max_nodes * 16;
+    RS_HIP(hipMemcpyAsync(b.d_tab, g_na_tab, tab_bytes, hipMemcpyHostToDevice, s));
+    // back: search, offsets, geometry; then the blob size
+    if (int rc = enqueue_back(b, s, nullptr)) return rc;
+    if (int rc = enqueue_readback(b, s)) return rc;
+    RS_HIP(hipStreamSynchronize(s));
+    collect_status(b);
+    if (b.st[0] != RS_OK) return batch_finish(b, nullptr, RS_OK);
+    const uint64_t raw = b.h_raw[0], rounded = b.h_boff[1];
+    if (!blob_dev || blob_cap < raw * 8) {
+        *blob_bytes = raw * 8;
+        return fail(RS_EINVAL, "blob buffer of %llu bytes; the structure needs %llu", (unsigned long long)blob_cap,
+                    (unsigned long long)(raw * 8));
+    }
+    // fill: the blob's own words are cleared and written (k_set_blobs sees the
+    // rounded size as capacity; every write stays inside the first raw words)
+    if (int rc = enqueue_fill(b, reinterpret_cast<uint64_t*>(blob_dev), rounded, raw, s)) return rc;
+    RS_HIP(hipStreamSynchronize(s));
+    *blob_bytes = raw * 8;
+    return RS_OK;
+}
+
 namespace rs {
 namespace {
 

@@ -133,11 +133,12 @@ def lib() -> ctypes.CDLL:
         L.rs_plan_destroy.argtypes = [P]
         L.rs_plan_destroy.restype = None
         L.rs_set_allocator.argtypes = [P, P, P]
+        L.rs_build_noalloc.argtypes = [ctypes.POINTER(rs_keys), U32, U32, P, U64, ctypes.POINTER(U64), P]
         for f in ("rs_build", "rs_build_ex", "rs_lookup", "rs_blob_to_host", "rs_blob_from_host", "rs_blob_info",
                   "rs_tables", "rs_last_build_stats", "rs_build_batch", "rs_server_create", "rs_server_create_ex", "rs_server_submit_build",
                   "rs_server_submit_lookup", "rs_server_poll", "rs_server_wait", "rs_server_get_stats", "rs_autotune",
                   "rs_schedule_get", "rs_schedule_set", "rs_plan_create", "rs_plan_run", "rs_plan_info",
-                  "rs_set_allocator", "rs_tables_ex", "rs_tables_packed", "rs_tables_range"):
+                  "rs_set_allocator", "rs_tables_ex", "rs_tables_packed", "rs_tables_range", "rs_build_noalloc"):
             getattr(L, f).restype = ctypes.c_int
         _lib = L
         use_torch_allocator()
@@ -385,6 +386,17 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+def build_noalloc(keys, leaf: int, bucket: int, out, stream=None) -> int:
+    """rs_build_noalloc: write the serialized structure into `out` (a CUDA
+    uint8 tensor) without any device allocation by the library; returns its
+    size in bytes."""
+    k = _as_keys(keys)
+    size = ctypes.c_uint64()
+    _check(lib().rs_build_noalloc(ctypes.byref(k), leaf, bucket, ctypes.c_void_p(out.data_ptr()), out.numel(),
+                                  ctypes.byref(size), _stream(stream)))
+    return size.value
 
 
 def lookup(blob: Blob, keys, out=None, stream=None):
