@@ -114,6 +114,8 @@ struct LookupArgs {
     const uint32_t* N;
     const uint32_t* P;  // r | N << 5 | F << 16 per size (used when every size fits)
     const uint32_t* Q;  // output values of a subtree per size (non-minimal structures)
+    const uint32_t* S;  // split shape per size: part size | fanout << 16
+    const uint32_t* C;  // ceil(2^32 / part size) per size
     uint64_t nb, beta, delta_s;
     int64_t delta_z;
     uint32_t Ws, Wz;
@@ -150,11 +152,11 @@ __device__ __forceinline__ uint32_t select_in_word(uint64_t x, uint32_t k) {
 // loads are independent, so a long scan costs one memory round trip per four
 // words instead of one per word); the loop only finds the word, and the one
 // in-word select runs after it.
-__device__ __forceinline__ uint64_t select_from(const uint64_t* a, uint64_t words, uint64_t p, uint64_t k) {
+__device__ __forceinline__ uint64_t select_from(const uint64_t* a, uint64_t words, uint64_t p, uint32_t k) {
     uint64_t w = p >> 6;
     if (w >= words) return words << 6;
     uint64_t x = a[w] & (~0ull << (p & 63));
-    uint32_t c = (uint32_t)__popcll(x);
+    const uint32_t c = (uint32_t)__popcll(x);
     if (k >= c) {
         k -= c;
         for (w++;; w += 4) {
@@ -162,20 +164,19 @@ __device__ __forceinline__ uint64_t select_from(const uint64_t* a, uint64_t word
             uint64_t y[4];
 #pragma unroll
             for (int u = 0; u < 4; u++) y[u] = w + u < words ? a[w + u] : 0;
-            const uint32_t c0 = (uint32_t)__popcll(y[0]), c1 = (uint32_t)__popcll(y[1]);
-            const uint32_t c2 = (uint32_t)__popcll(y[2]), c3 = (uint32_t)__popcll(y[3]);
-            const uint64_t s1 = c0, s2 = s1 + c1, s3 = s2 + c2, s4 = s3 + c3;
+            const uint32_t s1 = (uint32_t)__popcll(y[0]), s2 = s1 + (uint32_t)__popcll(y[1]);
+            const uint32_t s3 = s2 + (uint32_t)__popcll(y[2]), s4 = s3 + (uint32_t)__popcll(y[3]);
             if (k < s4) {  // in this group: pick the word without branches
                 const bool b1 = k >= s1, b2 = k >= s2, b3 = k >= s3;
                 x = b3 ? y[3] : b2 ? y[2] : b1 ? y[1] : y[0];
                 k -= b3 ? s3 : b2 ? s2 : b1 ? s1 : 0;
-                w += (uint64_t)b1 + b2 + b3;
+                w += (uint32_t)b1 + b2 + b3;
                 break;
             }
             k -= s4;
         }
     }
-    return (w << 6) + select_in_word(x, (uint32_t)k);
+    return (w << 6) + select_in_word(x, k);
 }
 
 // Position of the first set bit at or after bit p (the end of a unary code,
@@ -193,7 +194,7 @@ __device__ __forceinline__ uint64_t next_one(const uint64_t* a, uint64_t words, 
 }
 
 // Positions of the k-th and the (k+1)-th set bits at or after bit p.
-__device__ __forceinline__ void select_pair(const uint64_t* a, uint64_t words, uint64_t p, uint64_t k,
+__device__ __forceinline__ void select_pair(const uint64_t* a, uint64_t words, uint64_t p, uint32_t k,
                                             uint64_t& first, uint64_t& second) {
     first = select_from(a, words, p, k);
     second = first < (words << 6) ? next_one(a, words, first + 1) : words << 6;
@@ -212,29 +213,28 @@ __device__ __forceinline__ uint32_t div_small(uint32_t x, uint32_t d) {
     return q;
 }
 
+// nbits < 64 bits at bit position pos.  Both words are always read, without
+// a branch (lanes of a wavefront read at different offsets): every array read
+// this way (the Elias-Fano lower bits, the Golomb-Rice streams) ends with a
+// guard word.
 __device__ __forceinline__ uint64_t get_bits(const uint64_t* a, uint64_t pos, uint32_t nbits) {
-    if (nbits == 0) return 0;
-    uint64_t w = pos >> 6;
-    uint32_t o = (uint32_t)(pos & 63);
-    uint64_t v = a[w] >> o;
-    if (o + nbits > 64) v |= a[w + 1] << (64 - o);
-    return nbits == 64 ? v : v & ((1ull << nbits) - 1);
+    const uint64_t w = pos >> 6;
+    const uint32_t o = (uint32_t)(pos & 63);
+    const uint64_t v = (a[w] >> o) | ((a[w + 1] << 1) << (63 - o));
+    return v & ~(~0ull << nbits);
 }
 
 // Where to start looking for the i-th one of list 0 (s) or 1 (z): the
 // recorded one nearest below it in the two-level inventory, and how many ones
 // are left to skip from there (Sec. 7.4).
 __device__ __forceinline__ void inventory_start(const uint64_t* blob, const LookupArgs& a, uint64_t i, uint32_t list,
-                                                uint64_t& start, uint64_t& k) {
+                                                uint64_t& start, uint32_t& k) {
     start = blob[a.inv_hi_off + 2 * (i >> kInvHi) + list];
     const uint64_t e = 2 * (i >> kInvLo) + list;
     const uint32_t d = (uint32_t)(blob[a.inv_lo_off + e / 4] >> (16 * (e % 4))) & 0xffffu;
-    if (d != kInvOverflow) {
-        start += d;
-        k = i & ((1u << kInvLo) - 1);
-    } else {
-        k = i & ((1u << kInvHi) - 1);
-    }
+    const bool near = d != kInvOverflow;
+    start += near ? d : 0;
+    k = (uint32_t)i & (near ? (1u << kInvLo) - 1 : (1u << kInvHi) - 1);
 }
 
 // Per-size table reads of the descent: one packed word per size (footnote of
@@ -259,8 +259,11 @@ struct SizeTables {
 
 // Rank (minimal structure) or output value (WIDE: the non-minimal variant,
 // whose leaves map into leaf_range(m, slack) values and whose first
-// Elias-Fano list holds prefix sums of bucket ranges) of one key.
-template <bool PACKED, bool WIDE>
+// Elias-Fano list holds prefix sums of bucket ranges) of one key.  TAB16:
+// every node is below 2^16 keys (every structure this library builds), so
+// split shapes come from the per-size table and child indices from one
+// multiply with the part size's reciprocal (exact while ph * unit < 2^32).
+template <bool PACKED, bool WIDE, bool TAB16>
 __device__ uint64_t rank_of(const LookupArgs& a, uint64_t hi, uint64_t lo) {
     const SizeTables<PACKED> T{a};
     const uint64_t* blob = a.blob;
@@ -270,7 +273,8 @@ __device__ uint64_t rank_of(const LookupArgs& a, uint64_t hi, uint64_t lo) {
     const uint64_t* uz = blob + a.uz_off;
     const uint64_t* lower = blob + a.lower_off;
     const uint32_t wsz = a.Ws + a.Wz;
-    uint64_t start_s, k_s, start_z, k_z;
+    uint64_t start_s, start_z;
+    uint32_t k_s, k_z;
     inventory_start(blob, a, i, 0, start_s, k_s);
     inventory_start(blob, a, i, 1, start_z, k_z);
     uint64_t ps, ps1;
@@ -296,9 +300,8 @@ __device__ uint64_t rank_of(const LookupArgs& a, uint64_t hi, uint64_t lo) {
         m = lo_m;
     }
     const uint64_t* tree = blob + a.tree_off;
-    // node sizes below 2^20 (every structure this library builds; every
-    // dividend below is then under 2^21): the split shapes and child indices
-    // take div_small instead of integer division
+    // without the tables: node sizes below 2^20 take div_small (every
+    // dividend is then under 2^21), larger ones integer division
     const bool small = a.maxm < (1u << 20);
     uint64_t c = 0;
     uint32_t d = 0;
@@ -311,7 +314,12 @@ __device__ uint64_t rank_of(const LookupArgs& a, uint64_t hi, uint64_t lo) {
         uint64_t v = ((one - up) << r) | fixed;
         up = one + 1;
         SplitShape sh;
-        if (small) {
+        if (TAB16) {
+            const uint32_t sw = a.S[m];
+            sh.unit = sw & 0xffffu;
+            sh.fanout = sw >> 16;
+            sh.last = m - (sh.fanout - 1) * sh.unit;
+        } else if (small) {
             if (m > a.upper) {
                 sh.unit = div_small(m / 2 + a.upper - 1, a.upper) * a.upper;
                 sh.fanout = 2;
@@ -325,12 +333,19 @@ __device__ uint64_t rank_of(const LookupArgs& a, uint64_t hi, uint64_t lo) {
             sh = split_shape(m, a.leaf, a.lower, a.upper);
         }
         const uint32_t ph = phi(lo, d, v, m);
-        uint32_t j = min(small ? div_small(ph, sh.unit) : ph / sh.unit, sh.fanout - 1);
+        uint32_t q;
+        if (TAB16) {
+            const uint32_t rc = a.C[m];
+            q = rc ? __umulhi(ph, rc) : ph;  // the reciprocal is 0 for parts of one key
+        } else {
+            q = small ? div_small(ph, sh.unit) : ph / sh.unit;
+        }
+        const uint32_t j = min(q, sh.fanout - 1);
         if (j) {
             uint32_t fu, nu;
             T.FN(sh.unit, fu, nu);
             fp += (uint64_t)j * fu;
-            const uint64_t skip = (uint64_t)j * nu;
+            const uint32_t skip = j * nu;
             if (skip) up = select_from(tree, a.tree_words, up, skip - 1) + 1;
         }
         c += (uint64_t)j * (WIDE ? a.Q[sh.unit] : sh.unit);
@@ -349,17 +364,17 @@ __device__ uint64_t rank_of(const LookupArgs& a, uint64_t hi, uint64_t lo) {
 
 // One query per lane; q0 is the launch's first query (lookups of more
 // queries than one grid holds are launched in chunks).
-template <bool PACKED, bool WIDE>
+template <bool PACKED, bool WIDE, bool TAB16>
 __global__ void k_lookup_u64(LookupArgs a, const uint64_t* __restrict__ keys, uint64_t q, uint64_t q0,
                              uint64_t* __restrict__ ranks) {
     uint64_t t = q0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= q) return;
     uint64_t hi, lo;
     signature_u64(keys[t], hi, lo);
-    ranks[t] = rank_of<PACKED, WIDE>(a, hi, lo);
+    ranks[t] = rank_of<PACKED, WIDE, TAB16>(a, hi, lo);
 }
 
-template <bool PACKED, bool WIDE>
+template <bool PACKED, bool WIDE, bool TAB16>
 __global__ void k_lookup_bytes(LookupArgs a, const uint8_t* __restrict__ data, const uint64_t* __restrict__ offsets,
                                uint64_t q, uint64_t q0, bool aligned, uint64_t* __restrict__ ranks) {
     uint64_t t = q0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -369,7 +384,7 @@ __global__ void k_lookup_bytes(LookupArgs a, const uint8_t* __restrict__ data, c
     if (e < s || e > total) e = s = min(s, total);
     uint64_t hi, lo;
     signature_bytes(data, total, aligned, s, e, hi, lo);
-    ranks[t] = rank_of<PACKED, WIDE>(a, hi, lo);
+    ranks[t] = rank_of<PACKED, WIDE, TAB16>(a, hi, lo);
 }
 
 }  // namespace
@@ -390,7 +405,8 @@ extern "C" int rs_lookup(const rs_blob* blob, const rs_keys* queries, uint64_t* 
     Strategy st = make_strategy((uint32_t)L.leaf);
     const uint32_t* tab = blob->tables;
     const size_t w = blob->tab_stride;
-    LookupArgs a{blob->words, tab, tab + w, tab + 2 * w, tab + 4 * w, tab + 5 * w, L.nb, L.beta, L.delta_s,
+    LookupArgs a{blob->words, tab, tab + w, tab + 2 * w, tab + 4 * w, tab + 5 * w, tab + 6 * w, tab + 7 * w,
+                 L.nb, L.beta, L.delta_s,
                  L.delta_z, L.Ws, L.Wz, L.lower_off, L.us_off, L.uz_off, L.inv_hi_off, L.inv_lo_off, L.tree_off,
                  L.us_words, L.uz_words, L.tree_words, (uint32_t)L.leaf, st.lower, st.upper, (uint32_t)L.maxm,
                  L.slack};
@@ -406,22 +422,28 @@ extern "C" int rs_lookup(const rs_blob* blob, const rs_keys* queries, uint64_t* 
             const uint8_t* bytes = (const uint8_t*)queries->data;
             const uint64_t* u64 = (const uint64_t*)bytes;
             const uint64_t* offs = queries->offsets;
-            // table reads: packed words, three arrays, or three arrays and the ranges
+            // table reads: packed words (the packed table only exists up to
+            // 2600 keys, so with the shape tables), three arrays, or three
+            // arrays and the ranges; shape tables below 2^16 keys
+            const bool t16 = L.maxm < (1u << 16);
+            const dim3 g((uint32_t)grid), b(block);
             if (queries->kind == RS_KEYS_U64) {
-                if (L.slack)
-                    k_lookup_u64<false, true><<<(uint32_t)grid, block, 0, s>>>(a, u64, q, q0, ranks_dev);
-                else if (blob->packed)
-                    k_lookup_u64<true, false><<<(uint32_t)grid, block, 0, s>>>(a, u64, q, q0, ranks_dev);
-                else
-                    k_lookup_u64<false, false><<<(uint32_t)grid, block, 0, s>>>(a, u64, q, q0, ranks_dev);
+                if (blob->packed && !L.slack) k_lookup_u64<true, false, true><<<g, b, 0, s>>>(a, u64, q, q0, ranks_dev);
+                else if (L.slack && t16) k_lookup_u64<false, true, true><<<g, b, 0, s>>>(a, u64, q, q0, ranks_dev);
+                else if (L.slack) k_lookup_u64<false, true, false><<<g, b, 0, s>>>(a, u64, q, q0, ranks_dev);
+                else if (t16) k_lookup_u64<false, false, true><<<g, b, 0, s>>>(a, u64, q, q0, ranks_dev);
+                else k_lookup_u64<false, false, false><<<g, b, 0, s>>>(a, u64, q, q0, ranks_dev);
             } else {
-                if (L.slack)
-                    k_lookup_bytes<false, true><<<(uint32_t)grid, block, 0, s>>>(a, bytes, offs, q, q0, al, ranks_dev);
-                else if (blob->packed)
-                    k_lookup_bytes<true, false><<<(uint32_t)grid, block, 0, s>>>(a, bytes, offs, q, q0, al, ranks_dev);
+                if (blob->packed && !L.slack)
+                    k_lookup_bytes<true, false, true><<<g, b, 0, s>>>(a, bytes, offs, q, q0, al, ranks_dev);
+                else if (L.slack && t16)
+                    k_lookup_bytes<false, true, true><<<g, b, 0, s>>>(a, bytes, offs, q, q0, al, ranks_dev);
+                else if (L.slack)
+                    k_lookup_bytes<false, true, false><<<g, b, 0, s>>>(a, bytes, offs, q, q0, al, ranks_dev);
+                else if (t16)
+                    k_lookup_bytes<false, false, true><<<g, b, 0, s>>>(a, bytes, offs, q, q0, al, ranks_dev);
                 else
-                    k_lookup_bytes<false, false><<<(uint32_t)grid, block, 0, s>>>(a, bytes, offs, q, q0, al,
-                                                                                   ranks_dev);
+                    k_lookup_bytes<false, false, false><<<g, b, 0, s>>>(a, bytes, offs, q, q0, al, ranks_dev);
             }
             return RS_OK;
         }))

@@ -101,14 +101,17 @@ __host__ __device__ inline uint32_t leaf_range(uint32_t m, uint32_t slack) {
 }
 
 // Per-size tables for sizes 0..cap (cap >= the requested maxm), laid out as
-// r[cap+1], F[cap+1], N[cap+1], G[cap+1], P[cap+1], Q[cap+1]: Golomb-Rice
-// parameter of a node, fixed bits of a subtree, coded nodes of a subtree,
-// log2 of the lanes that share one candidate in the split search of a node of
-// that size, r, N and F of the size packed into one word (footnote of Sec.
-// 7.2: bits 0-4 r, 5-15 N, 16-31 F; kNoPacked where they do not fit), and the
-// number of output values of a subtree (m for the minimal structure; with
-// slack, leaf_range for a leaf and the sum over the parts for a split).  The
-// host memory is pinned and stays valid for the life of the process.
+// r[cap+1], F[cap+1], N[cap+1], G[cap+1], P[cap+1], Q[cap+1], S[cap+1],
+// C[cap+1]: Golomb-Rice parameter of a node, fixed bits of a subtree, coded
+// nodes of a subtree, log2 of the lanes that share one candidate in the split
+// search of a node of that size, r, N and F of the size packed into one word
+// (footnote of Sec. 7.2: bits 0-4 r, 5-15 N, 16-31 F; kNoPacked where they do
+// not fit), the number of output values of a subtree (m for the minimal
+// structure; with slack, leaf_range for a leaf and the sum over the parts for
+// a split), the split shape of a node (part size u in bits 0-15, fanout in
+// bits 16-23; 0 for leaves and where u >= 2^16), and ceil(2^32 / u) (0 for
+// u = 1 and leaves), with which floor(x / u) = umulhi(x, C) for x u < 2^32.
+// The host memory is pinned and stays valid for the life of the process.
 struct TableView {
     const uint32_t* data;
     uint32_t cap;
@@ -118,8 +121,10 @@ struct TableView {
     const uint32_t* G() const { return data + 3 * (cap + 1); }
     const uint32_t* P() const { return data + 4 * (cap + 1); }
     const uint32_t* Q() const { return data + 5 * (cap + 1); }
+    const uint32_t* S() const { return data + 6 * (cap + 1); }
+    const uint32_t* C() const { return data + 7 * (cap + 1); }
 };
-constexpr int kTableCount = 6;
+constexpr int kTableCount = 8;
 constexpr uint32_t kNoPacked = 0xffffffffu;
 __host__ __device__ inline uint32_t packed_r(uint32_t w) { return w & 31u; }
 __host__ __device__ inline uint32_t packed_N(uint32_t w) { return (w >> 5) & 2047u; }

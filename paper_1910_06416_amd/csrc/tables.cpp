@@ -105,8 +105,10 @@ uint32_t lanes_per_candidate(const Strategy& st, uint32_t m, double trials) {
 void fill(const Strategy& st, uint32_t cap, uint32_t* dst, uint32_t gr_max, uint32_t slack) {
     const size_t w = (size_t)cap + 1;
     uint32_t *r = dst, *F = dst + w, *N = dst + 2 * w, *G = dst + 3 * w, *P = dst + 4 * w, *Q = dst + 5 * w;
+    uint32_t *S = dst + 6 * w, *C = dst + 7 * w;
     for (uint32_t m = 0; m <= cap; m++) {
         G[m] = 0;
+        S[m] = C[m] = 0;
         if (m < 2) {
             r[m] = F[m] = N[m] = 0;
             P[m] = 0;
@@ -124,6 +126,8 @@ void fill(const Strategy& st, uint32_t cap, uint32_t* dst, uint32_t gr_max, uint
             F[m] += (sh.fanout - 1) * F[sh.unit] + F[sh.last];
             N[m] += (sh.fanout - 1) * N[sh.unit] + N[sh.last];
             Q[m] = (sh.fanout - 1) * Q[sh.unit] + Q[sh.last];
+            if (sh.unit < 65536u) S[m] = sh.unit | sh.fanout << 16;
+            if (sh.unit > 1) C[m] = (uint32_t)(((1ull << 32) + sh.unit - 1) / sh.unit);
         }
         P[m] = r[m] < 32 && N[m] < 2048 && F[m] < 65536 ? r[m] | N[m] << 5 | F[m] << 16 : kNoPacked;
     }

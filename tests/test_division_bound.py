@@ -50,3 +50,28 @@ def test_quotient_boundaries():
     x = np.arange((1 << 21) - 4096, 1 << 21, dtype=np.int64)
     for dd in (1, 2, 3, 7, 8, 96, 112, 560, 1 << 20):
         _check(x, np.full(x.size, dd))
+
+
+def test_reciprocal_multiply_is_exact_below_2_to_16():
+    """Lookups of structures whose nodes are all below 2^16 keys take the child
+    index as umulhi(ph, C) with C = ceil(2^32 / u): exact whenever ph * u <
+    2^32 (then the error term ph * (C - 2^32/u) / 2^32 stays below 1/u).
+    Checked for every part size u < 2^16 at the remainders that come closest
+    to the next quotient (ph = q u + u - 1) and at exact multiples, for ph up
+    to 2^16."""
+    u = np.arange(2, 1 << 16, dtype=np.uint64)
+    C = ((np.uint64(1) << np.uint64(32)) + u - np.uint64(1)) // u
+    for q in range(0, 40):
+        for off in (0, -1):
+            ph = np.uint64(q) * u + (u - np.uint64(1) if off else np.uint64(0))
+            keep = ph < (1 << 16)
+            if not keep.any():
+                continue
+            p, uu, cc = ph[keep], u[keep], C[keep]
+            got = (p * cc) >> np.uint64(32)
+            assert np.array_equal(got, p // uu)
+    # the largest quotients: small parts, ph near 2^16
+    for uu in range(2, 300):
+        p = np.arange((1 << 16) - 2 * uu, 1 << 16, dtype=np.uint64)
+        cc = np.uint64(((1 << 32) + uu - 1) // uu)
+        assert np.array_equal((p * cc) >> np.uint64(32), p // np.uint64(uu))
