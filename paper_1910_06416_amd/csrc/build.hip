@@ -282,6 +282,93 @@ __global__ __launch_bounds__(kBlock) void k_bin_scatter(const uint64_t* __restri
     }
 }
 
+// The same scatter with the tile reordered by bin in LDS first, so that the
+// writes of a block's run in each bin leave from consecutive lanes to
+// consecutive addresses (the plain scatter sends every lane's key to another
+// bin and its partial-line writes multiply the bytes written).  kScatterBlock
+// threads, kScatterItems keys each (the same 8192-key tile as the signature
+// pass); at most kScatterMaxBins bins.  Dynamic LDS: the tile's lower words
+// and bucket numbers (12 B per key), then per bin the global run base (u64),
+// the count (u32) and the tile-local start (u32).
+constexpr uint32_t kScatterBlock = 512;
+constexpr uint32_t kScatterItems = kSigTile / kScatterBlock;
+constexpr uint32_t kScatterMaxBins = 1024;
+static_assert(kScatterItems * kScatterBlock == kSigTile, "the scatter takes the signature pass's tiles");
+
+size_t staged_scatter_lds(uint32_t nbins) { return (size_t)kSigTile * 12 + (size_t)nbins * 16; }
+
+__global__ __launch_bounds__(kScatterBlock) void k_bin_scatter_staged(
+    const uint64_t* __restrict__ lo, const uint32_t* __restrict__ bid, uint64_t total, uint32_t shift, uint32_t nbins,
+    uint32_t nxcd, unsigned long long* __restrict__ bin_cur, uint64_t* __restrict__ bin_lo,
+    uint32_t* __restrict__ bin_bid) {
+    extern __shared__ uint64_t smem[];
+    uint64_t* s_lo = smem;
+    uint32_t* s_bid = reinterpret_cast<uint32_t*>(s_lo + kSigTile);
+    unsigned long long* bases = reinterpret_cast<unsigned long long*>(s_bid + kSigTile);
+    uint32_t* hist = reinterpret_cast<uint32_t*>(bases + nbins);
+    uint32_t* lstart = hist + nbins;
+    __shared__ uint32_t wsum[kScatterBlock / 64];
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    for (uint32_t c = tid; c < nbins; c += kScatterBlock) hist[c] = 0;
+    __syncthreads();
+    const uint64_t tile0 = (uint64_t)blockIdx.x * kSigTile;
+    const uint32_t count = (uint32_t)min<uint64_t>(kSigTile, total - tile0);
+    // bucket numbers in, and each key's rank among the tile's keys of its bin
+    uint32_t b[kScatterItems], r[kScatterItems];
+#pragma unroll
+    for (uint32_t it = 0; it < kScatterItems; it++) {
+        const uint32_t e = it * kScatterBlock + tid;
+        b[it] = e < count ? bid[tile0 + e] : ~0u;
+    }
+#pragma unroll
+    for (uint32_t it = 0; it < kScatterItems; it++)
+        r[it] = b[it] != ~0u ? atomicAdd(&hist[b[it] >> shift], 1u) : 0;
+    __syncthreads();
+    // tile-local bin starts (exclusive scan, two bins per thread) and the
+    // block's run in every bin it touches, inside its XCD's part of the bin
+    const uint32_t c0 = 2 * tid;
+    const uint32_t h0 = c0 < nbins ? hist[c0] : 0, h1 = c0 + 1 < nbins ? hist[c0 + 1] : 0;
+    uint32_t x = h0 + h1;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= (uint32_t)o) x += y;
+    }
+    if (lane == 63) wsum[wid] = x;
+    __syncthreads();
+    uint32_t pre = 0;
+#pragma unroll
+    for (uint32_t w = 0; w < kScatterBlock / 64; w++) pre += w < wid ? wsum[w] : 0;
+    const uint32_t ex = pre + x - (h0 + h1);
+    const uint32_t xcd = blockIdx.x % nxcd;
+    if (c0 < nbins) {
+        lstart[c0] = ex;
+        if (h0) bases[c0] = atomicAdd(&bin_cur[c0 * nxcd + xcd], (unsigned long long)h0);
+    }
+    if (c0 + 1 < nbins) {
+        lstart[c0 + 1] = ex + h0;
+        if (h1) bases[c0 + 1] = atomicAdd(&bin_cur[(c0 + 1) * nxcd + xcd], (unsigned long long)h1);
+    }
+    __syncthreads();
+    // the tile into LDS in bin order
+#pragma unroll
+    for (uint32_t it = 0; it < kScatterItems; it++) {
+        const uint32_t e = it * kScatterBlock + tid;
+        if (b[it] == ~0u) continue;
+        const uint32_t slot = lstart[b[it] >> shift] + r[it];
+        s_lo[slot] = lo[tile0 + e];
+        s_bid[slot] = b[it];
+    }
+    __syncthreads();
+    // out in bin order: consecutive lanes write consecutive positions of a run
+    for (uint32_t e = tid; e < count; e += kScatterBlock) {
+        const uint32_t bk = s_bid[e], c = bk >> shift;
+        const uint64_t pos = bases[c] + (e - lstart[c]);
+        bin_lo[pos] = s_lo[e];
+        bin_bid[pos] = bk;
+    }
+}
+
 // One workgroup per bin: bucket counts in LDS, their prefix sums (bstart of
 // the bin's buckets), the largest bucket, and the keys in bucket order.  A bin
 // of more than `piece` buckets is done `piece` buckets at a time (each
@@ -505,7 +592,7 @@ struct SearchArgs {
     const uint64_t* bucket_base;
     uint32_t count;
     uint64_t nbuckets;
-    const uint32_t* tables;     // per table set: kTableCount arrays of `stride` words (r, F, N, G, P, Q)
+    const uint32_t* tables;     // per table set: kTableCount arrays of `stride` words (r, F, N, G, P, Q, S, C)
     uint32_t stride;
     uint64_t seed_cap;
     uint32_t key_words;   // 64-bit words of dynamic LDS before the node slots (largest bucket)
@@ -2205,8 +2292,12 @@ int enqueue_front(Batch& b, hipStream_t s, PhaseEvents* pe) {
     uint64_t* bin_lo = b.d_tmp;
     uint32_t* bin_bid = (uint32_t*)b.d_seeds;
     RS_LAUNCH(k_bin_offsets, 1, kBlock, 0, s, b.d_bincnt, b.nbins, b.nxcd, b.d_binst, b.d_bincur);
-    RS_LAUNCH(k_bin_scatter, grid_for(b.total, kSigTile), kBlock, b.nbins * 12, s, b.d_lo, b.d_bid, b.total, b.shift,
-              b.nbins, b.nxcd, b.d_bincur, bin_lo, bin_bid);
+    if (b.nbins <= kScatterMaxBins && staged_scatter_lds(b.nbins) + 256 <= (size_t)max_lds_bytes())
+        RS_LAUNCH(k_bin_scatter_staged, grid_for(b.total, kSigTile), kScatterBlock, staged_scatter_lds(b.nbins), s,
+                  b.d_lo, b.d_bid, b.total, b.shift, b.nbins, b.nxcd, b.d_bincur, bin_lo, bin_bid);
+    else
+        RS_LAUNCH(k_bin_scatter, grid_for(b.total, kSigTile), kBlock, b.nbins * 12, s, b.d_lo, b.d_bid, b.total,
+                  b.shift, b.nbins, b.nxcd, b.d_bincur, bin_lo, bin_bid);
     const uint32_t piece = (uint32_t)std::min<uint64_t>(std::min(1u << b.shift, kSortSpan), b.nbuckets);
     RS_LAUNCH(k_bucket_sort, b.nbins, kSortBlock, 8u * piece, s, b.d_binst, bin_lo, bin_bid, b.shift, piece,
               b.nbuckets, b.d_bst, b.d_sorted, &b.d_st->maxm);
