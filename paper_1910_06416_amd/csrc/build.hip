@@ -927,9 +927,19 @@ constexpr uint32_t kSplitPollSteps = 16;
 // again each time that count doubles, the node's keys are compared pairwise,
 // and equal keys end the search with the duplicate flag.  The check changes
 // no result: without duplicates the search simply goes on.
+//
+// The search covers candidates [lo, min(hi, cap)) (lo a multiple of the
+// candidates per step) and returns the first that works there.  With best
+// null it is the node's whole search (lo = 0, hi = cap): duplicates are
+// checked as above and reaching the cap raises the search flag.  Otherwise
+// it is one chunk of a search shared by several wavefronts: it stops early
+// once *best (the smallest success any of them found) is at or below the
+// candidates still to try, and the owner of the node handles duplicates and
+// the cap.
 template <int NT, int MODE>
-__device__ uint64_t split_search(const uint64_t* keys, uint32_t depth, const SplitCtl& c, const uint32_t* T,
-                                 uint64_t cap, uint32_t* flags, QueueState* qs) {
+__device__ __forceinline__ uint64_t split_search(const uint64_t* keys, uint32_t depth, const SplitCtl& c, const uint32_t* T,
+                                 uint64_t lo, uint64_t hi, uint64_t cap, const unsigned long long* best,
+                                 uint32_t* flags, QueueState* qs) {
     constexpr int NA = NT > 0 ? NT : 1;  // NT = 0 in the packed modes
     uint32_t thr[NA];
 #pragma unroll
@@ -945,10 +955,14 @@ __device__ uint64_t split_search(const uint64_t* keys, uint32_t depth, const Spl
     // blocks, and the last m mod 4 G keys are dealt one at a time.
     const uint32_t quads = m / (4 * G);
     const uint32_t tail = quads * 4 * G;
-    uint64_t S = (((uint64_t)depth << 56) + gi) * kGamma;
+    uint64_t S = (((uint64_t)depth << 56) + lo + gi) * kGamma;
     uint64_t next_check = 64ull * m;
     uint32_t steps = 0;
-    for (uint64_t base = 0; base < cap; base += per_step, S += step) {
+    const uint64_t end = min(hi, cap);
+    for (uint64_t base = lo; base < end; base += per_step, S += step) {
+        // a success at or below `base` elsewhere makes the rest of the chunk useless
+        if (best && uniform64(__hip_atomic_load(best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) <= base)
+            return kNoSeed;
         uint32_t cnt[NA];
         uint64_t packed = 0;
         uint32_t onehot = 0;
@@ -1011,7 +1025,7 @@ __device__ uint64_t split_search(const uint64_t* keys, uint32_t depth, const Spl
             steps = 0;
             if (search_poll(qs)) return kNoSeed;
         }
-        if (base + per_step >= next_check) {
+        if (!best && base + per_step >= next_check) {
             if (node_has_duplicate(keys, m)) {
                 if (lane == 0) atomicOr(flags, kFlagDuplicate);
                 return kNoSeed;
@@ -1019,19 +1033,21 @@ __device__ uint64_t split_search(const uint64_t* keys, uint32_t depth, const Spl
             next_check *= 2;
         }
     }
-    if (lane == 0) atomicOr(flags, kFlagSearch);
+    if (!best && lane == 0) atomicOr(flags, kFlagSearch);
     return kNoSeed;
 }
 
 template <int MAXNT>
-__device__ uint64_t split_dispatch(const uint64_t* keys, uint32_t depth, const SplitCtl& c, const uint32_t* T,
-                                   uint32_t mode, uint64_t cap, uint32_t* flags, QueueState* qs) {
-    if (mode == kCountPacked) return split_search<0, kCountPacked>(keys, depth, c, T, cap, flags, qs);
-    if (mode == kCountOneHot) return split_search<0, kCountOneHot>(keys, depth, c, T, cap, flags, qs);
+__device__ __forceinline__ uint64_t split_dispatch(const uint64_t* keys, uint32_t depth, const SplitCtl& c, const uint32_t* T,
+                                   uint32_t mode, uint64_t lo, uint64_t hi, uint64_t cap,
+                                   const unsigned long long* best, uint32_t* flags, QueueState* qs) {
+    if (mode == kCountPacked) return split_search<0, kCountPacked>(keys, depth, c, T, lo, hi, cap, best, flags, qs);
+    if (mode == kCountOneHot) return split_search<0, kCountOneHot>(keys, depth, c, T, lo, hi, cap, best, flags, qs);
     switch (c.fanout - 1) {
-#define RS_SPLIT_CASE(NT)                                                                 \
-    case NT:                                                                              \
-        if constexpr (NT <= MAXNT) return split_search<NT, kCountThresholds>(keys, depth, c, T, cap, flags, qs); \
+#define RS_SPLIT_CASE(NT)                                                                                       \
+    case NT:                                                                                                    \
+        if constexpr (NT <= MAXNT)                                                                              \
+            return split_search<NT, kCountThresholds>(keys, depth, c, T, lo, hi, cap, best, flags, qs);         \
         return kNoSeed;
         RS_SPLIT_CASE(1) RS_SPLIT_CASE(2) RS_SPLIT_CASE(3) RS_SPLIT_CASE(4) RS_SPLIT_CASE(5) RS_SPLIT_CASE(6)
         RS_SPLIT_CASE(7) RS_SPLIT_CASE(8)
@@ -1129,6 +1145,98 @@ struct NodeSlot {
     uint32_t m;  // published last (release); 0 = not yet filled
 };
 
+// A split search shared by the wavefronts of a bucket.  The owner of a heavy
+// split node (the tables flag sizes whose expected trials x keys exceed
+// kCoopEvals) publishes it on its board entry; wavefronts that wait for a
+// slot meanwhile help.  Candidates are cut into chunks of kCoopSteps search
+// steps, claimed in increasing order from `next`; each chunk is searched from
+// its start, and `best` keeps the smallest success found.  Once a success is
+// known no chunk above it is started, and chunks above it that are running
+// stop at their next step, so when every claimed chunk has ended (the owner
+// stops claiming and waits for `outstanding` to return to zero) `best` is the
+// first index that works: the result of the plain search.
+constexpr uint32_t kCoopSteps = 32;
+struct CoopNode {
+    uint32_t active;       // chunks may be claimed (release / acquire)
+    uint32_t outstanding;  // helpers inside the node (never reset: returns to 0)
+    uint32_t failed;       // the owner stopped the search (duplicate keys)
+    uint32_t pad0;
+    unsigned long long next;  // next chunk
+    unsigned long long best;  // smallest success found (kNoSeed: none)
+    uint32_t off, depth, mode, pad;
+    SplitCtl c;
+};
+
+// Claim chunks of the shared search `cn` and search them until none below the
+// best success (or the cap) is left; returns the success this wavefront
+// found, if any.  The owner also compares the node's keys pairwise once its
+// chunks pass 64 m candidates and at each doubling (duplicate keys: the
+// search is stopped for every wavefront and the duplicate flag raised).
+template <int MAXNT>
+__device__ __forceinline__ uint64_t coop_search(CoopNode& cn, const uint64_t* keys, const uint32_t* T, uint64_t cap,
+                                uint32_t* flags, QueueState* qs, bool owner) {
+    const uint32_t lane = lane_id();
+    // the node's parameters, wave-uniform (scalar registers)
+    SplitCtl c;
+    c.m = __builtin_amdgcn_readfirstlane(cn.c.m);
+    c.unit = __builtin_amdgcn_readfirstlane(cn.c.unit);
+    c.fanout = __builtin_amdgcn_readfirstlane(cn.c.fanout);
+    c.last = __builtin_amdgcn_readfirstlane(cn.c.last);
+    c.g = __builtin_amdgcn_readfirstlane(cn.c.g);
+    c.w = __builtin_amdgcn_readfirstlane(cn.c.w);
+    c.recip = __builtin_amdgcn_readfirstlane(cn.c.recip);
+    c.want = uniform64(cn.c.want);
+    const uint32_t depth = __builtin_amdgcn_readfirstlane(cn.depth);
+    const uint32_t mode = __builtin_amdgcn_readfirstlane(cn.mode);
+    const uint64_t K = (uint64_t)(64u >> c.g) * kCoopSteps;
+    uint64_t next_check = 64ull * c.m;
+    for (;;) {
+        unsigned long long ci = 0;
+        if (lane == 0) ci = __hip_atomic_fetch_add(&cn.next, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        const uint64_t c64 = uniform64(ci);
+        const uint64_t lo = c64 < cap / K + 1 ? c64 * K : cap;  // (no product overflow)
+        const uint64_t bst = uniform64(__hip_atomic_load(&cn.best, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+        const uint32_t stop = __hip_atomic_load(&cn.failed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) |
+                              __hip_atomic_load(&qs->abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (lo >= min(bst, cap) || __builtin_amdgcn_readfirstlane(stop)) return kNoSeed;
+        if (owner && lo >= next_check) {
+            while (next_check <= lo) next_check *= 2;
+            if (node_has_duplicate(keys, c.m)) {
+                if (lane == 0) {
+                    atomicOr(flags, kFlagDuplicate);
+                    __hip_atomic_store(&cn.failed, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    __hip_atomic_store(&cn.best, 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                }
+                return kNoSeed;
+            }
+        }
+        const uint64_t v = split_dispatch<MAXNT>(keys, depth, c, T, mode, lo, lo + K, cap, &cn.best, flags, qs);
+        if (v != kNoSeed) {
+            if (lane == 0)
+                __hip_atomic_fetch_min(&cn.best, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            return v;  // every later chunk lies above this success
+        }
+    }
+}
+
+// A waiting wavefront's help with the shared search `cn` of another.  The
+// helper counts itself in before it looks at `active`, and the owner closes
+// the node before it reads the count (both sequentially consistent): a helper
+// that the owner did not see finds the node closed, and the owner waits for
+// every helper it saw.
+template <int MAXNT>
+__device__ __forceinline__ void coop_help(CoopNode& cn, const uint64_t* lds_keys, const uint32_t* T, uint64_t cap, uint32_t* flags,
+                          QueueState* qs) {
+    if (lane_id() == 0) __hip_atomic_fetch_add(&cn.outstanding, 1u, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_WORKGROUP);
+    const uint32_t open = __hip_atomic_load(&cn.active, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (__builtin_amdgcn_readfirstlane(open)) {
+        const uint32_t off = __builtin_amdgcn_readfirstlane(cn.off);
+        (void)coop_search<MAXNT>(cn, lds_keys + off, T, cap, flags, qs, false);
+    }
+    wave_lds_sync();
+    if (lane_id() == 0) __hip_atomic_fetch_sub(&cn.outstanding, 1u, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 
 // WIDE: the call holds a build of the non-minimal variant; leaves search
 // injections into their build's leaf_range (equal to m for slack 0).
@@ -1138,6 +1246,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_search(SearchArgs a) {
     __shared__ QueueState qs;
     __shared__ uint32_t thr_s[WAVES][kMaxThresholds];
     __shared__ LeafQueues queues[WAVES];
+    __shared__ CoopNode board[WAVES];
     const uint32_t lane = lane_id(), wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     uint64_t* lds_keys = lds_dyn;
     NodeSlot* slots = reinterpret_cast<NodeSlot*>(lds_dyn + a.key_words);
@@ -1173,6 +1282,10 @@ __global__ __launch_bounds__(64 * WAVES) void k_search(SearchArgs a) {
         for (uint32_t i = threadIdx.x; i < m0; i += 64 * WAVES) lds_keys[i] = a.sorted[start + i];
         for (uint32_t i = threadIdx.x; i < total; i += 64 * WAVES) slots[i].m = 0;
         __syncthreads();
+        if (threadIdx.x < WAVES) {
+            board[threadIdx.x].active = 0;
+            board[threadIdx.x].outstanding = 0;
+        }
         if (threadIdx.x == 0) {
             qs.head = 0;
             qs.tail = total ? 1 : 0;
@@ -1189,46 +1302,57 @@ __global__ __launch_bounds__(64 * WAVES) void k_search(SearchArgs a) {
         __syncthreads();
         unsigned long long bits = 0;
         for (; wave < active;) {
-            uint32_t h = 0, off = 0, m = 0, d = 0, idx = 0, stop = 0;
-            if (lane == 0) {
-                h = __hip_atomic_fetch_add(&qs.head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                if (h >= total) {
+            uint32_t h = 0;
+            if (lane == 0) h = __hip_atomic_fetch_add(&qs.head, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            h = __builtin_amdgcn_readfirstlane(h);
+            if (h >= total) break;
+            // wait for the slot while some wavefront of the bucket makes progress,
+            // and help the shared split searches of other wavefronts meanwhile
+            uint32_t m = 0, stop = 0, idle = 0;
+            uint32_t seen = __builtin_amdgcn_readfirstlane(
+                __hip_atomic_load(&qs.beat, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+            for (;;) {
+                m = __builtin_amdgcn_readfirstlane(
+                    __hip_atomic_load(&slots[h].m, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP));
+                if (m) break;
+                if (__builtin_amdgcn_readfirstlane(
+                        __hip_atomic_load(&qs.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))) {
                     stop = 1;
-                } else {
-                    // wait for the slot while some wavefront of the bucket makes progress
-                    uint32_t idle = 0;
-                    uint32_t seen = __hip_atomic_load(&qs.beat, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                    for (;;) {
-                        m = __hip_atomic_load(&slots[h].m, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
-                        if (m) break;
-                        if (__hip_atomic_load(&qs.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) {
-                            stop = 1;
-                            break;
-                        }
-                        const uint32_t now = __hip_atomic_load(&qs.beat, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                        if (now != seen) {
-                            seen = now;
-                            idle = 0;
-                        } else if (++idle >= a.wait_limit) {
-                            atomicOr(bflags, kFlagStack);
-                            __hip_atomic_store(&qs.abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-                            stop = 1;
-                            break;
-                        }
-                        __builtin_amdgcn_s_sleep(4);
-                    }
-                    if (!stop) {
-                        off = slots[h].off;
-                        d = slots[h].d;
-                        idx = slots[h].idx;
+                    break;
+                }
+                if constexpr (WAVES > 1) {
+                    uint32_t e = WAVES;
+                    for (uint32_t w2 = 0; w2 < WAVES; w2++)
+                        if (e == WAVES &&
+                            __hip_atomic_load(&board[w2].active, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP))
+                            e = w2;
+                    e = __builtin_amdgcn_readfirstlane(e);
+                    if (e < WAVES) {
+                        coop_help<max_thresholds(MAXL)>(board[e], lds_keys, thr_s[e], a.seed_cap, bflags, &qs);
+                        idle = 0;
+                        __builtin_amdgcn_s_sleep(1);  // (a node whose chunks are all taken is retried)
+                        continue;
                     }
                 }
+                const uint32_t now = __builtin_amdgcn_readfirstlane(
+                    __hip_atomic_load(&qs.beat, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+                if (now != seen) {
+                    seen = now;
+                    idle = 0;
+                } else if (++idle >= a.wait_limit) {
+                    if (lane == 0) {
+                        atomicOr(bflags, kFlagStack);
+                        __hip_atomic_store(&qs.abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
+                    stop = 1;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(4);
             }
-            if (__builtin_amdgcn_readfirstlane(stop)) break;
-            off = __builtin_amdgcn_readfirstlane(off);
-            m = __builtin_amdgcn_readfirstlane(m);
-            d = __builtin_amdgcn_readfirstlane(d);
-            idx = __builtin_amdgcn_readfirstlane(idx);
+            if (stop) break;
+            const uint32_t off = __builtin_amdgcn_readfirstlane(slots[h].off);
+            const uint32_t d = __builtin_amdgcn_readfirstlane(slots[h].d);
+            const uint32_t idx = __builtin_amdgcn_readfirstlane(slots[h].idx);
             wave_mem_sync();
             uint64_t v;
             bool fail;
@@ -1252,7 +1376,8 @@ __global__ __launch_bounds__(64 * WAVES) void k_search(SearchArgs a) {
                     c.unit = sh.unit;
                     c.fanout = sh.fanout;
                     c.last = sh.last;
-                    c.g = __builtin_amdgcn_readfirstlane(min(Gt[m], group_cap));
+                    const uint32_t gw = Gt[m];
+                    c.g = __builtin_amdgcn_readfirstlane(min(gw & kGroupMask, group_cap));
                     const uint32_t mode = split_count_mode(m, sh.fanout);
                     c.w = mode == kCountOneHot ? 8 : 32 - __clz(m);
                     c.recip = mode != kCountThresholds ? (uint32_t)(((1ull << 32) + sh.unit - 1) / sh.unit) : 0;
@@ -1260,8 +1385,54 @@ __global__ __launch_bounds__(64 * WAVES) void k_search(SearchArgs a) {
                     if (mode != kCountThresholds)
                         for (uint32_t q = 0; q < sh.fanout; q++)
                             c.want += (uint64_t)(q + 1 == sh.fanout ? sh.last : sh.unit) << (q * c.w);
-                    v = split_dispatch<max_thresholds(MAXL)>(lds_keys + off, d, c, thr, mode, a.seed_cap, bflags,
-                                                             &qs);
+                    if (WAVES > 1 && active > 1 && (gw & kCoopFlag)) {
+                        // a heavy node: searched in chunks with the help of waiting wavefronts
+                        CoopNode& cn = board[wave];
+                        if (lane == 0) {
+                            cn.c = c;
+                            cn.off = off;
+                            cn.depth = d;
+                            cn.mode = mode;
+                            cn.next = 0;
+                            cn.failed = 0;
+                            cn.best = kNoSeed;
+                            __hip_atomic_store(&cn.active, 1u, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        }
+                        wave_lds_sync();
+                        (void)coop_search<max_thresholds(MAXL)>(cn, lds_keys + off, thr, a.seed_cap, bflags, &qs,
+                                                                true);
+                        if (lane == 0)
+                            __hip_atomic_store(&cn.active, 0u, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        // every helper the node had ends its chunk (each stops at the next
+                        // step once the best success lies below it)
+                        uint32_t wait_idle = 0, wseen = 0;
+                        while (__builtin_amdgcn_readfirstlane(__hip_atomic_load(
+                            &cn.outstanding, __ATOMIC_SEQ_CST, __HIP_MEMORY_SCOPE_WORKGROUP))) {
+                            const uint32_t now = __builtin_amdgcn_readfirstlane(
+                                __hip_atomic_load(&qs.beat, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+                            if (now != wseen) {
+                                wseen = now;
+                                wait_idle = 0;
+                            } else if (++wait_idle >= a.wait_limit) {
+                                if (lane == 0) {
+                                    atomicOr(bflags, kFlagStack);
+                                    __hip_atomic_store(&qs.abort, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                                }
+                                break;
+                            }
+                            __builtin_amdgcn_s_sleep(1);
+                        }
+                        const uint32_t failed = __builtin_amdgcn_readfirstlane(
+                            __hip_atomic_load(&cn.failed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) |
+                            __hip_atomic_load(&qs.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+                        v = failed ? kNoSeed
+                                   : uniform64(__hip_atomic_load(&cn.best, __ATOMIC_RELAXED,
+                                                                 __HIP_MEMORY_SCOPE_WORKGROUP));
+                        if (!failed && v == kNoSeed && lane == 0) atomicOr(bflags, kFlagSearch);  // the cap
+                    } else {
+                        v = split_dispatch<max_thresholds(MAXL)>(lds_keys + off, d, c, thr, mode, 0, a.seed_cap,
+                                                                 a.seed_cap, nullptr, bflags, &qs);
+                    }
                     fail = v == kNoSeed;  // counts do not match the parts: no partition
                     if (!fail)
                         partition(lds_keys + off, m, d, v, thr, nt, sh.unit, reinterpret_cast<uint64_t*>(&queues[wave]),

@@ -125,6 +125,12 @@ struct TableView {
     const uint32_t* C() const { return data + 7 * (cap + 1); }
 };
 constexpr int kTableCount = 8;
+// G holds log2 lanes per split candidate in its low byte; kCoopFlag marks
+// split sizes whose expected work (trials x keys) reaches kCoopEvals: their
+// search is shared by the wavefronts of the bucket that are waiting.
+constexpr uint32_t kGroupMask = 0xffu;
+constexpr uint32_t kCoopFlag = 1u << 8;
+constexpr double kCoopEvals = 524288.0;
 constexpr uint32_t kNoPacked = 0xffffffffu;
 __host__ __device__ inline uint32_t packed_r(uint32_t w) { return w & 31u; }
 __host__ __device__ inline uint32_t packed_N(uint32_t w) { return (w >> 5) & 2047u; }

@@ -117,7 +117,11 @@ void fill(const Strategy& st, uint32_t cap, uint32_t* dst, uint32_t gr_max, uint
         }
         const double lp = log_success(st, m, slack);
         r[m] = gr_max && m > st.leaf && m > gr_max ? rice_parameter_large(st, m) : rice_parameter(std::exp(lp));
-        if (m > st.leaf) G[m] = lanes_per_candidate(st, m, std::exp(-lp));
+        if (m > st.leaf) {
+            const double trials = std::exp(-lp);
+            G[m] = lanes_per_candidate(st, m, trials);
+            if (trials * (double)m >= kCoopEvals) G[m] |= kCoopFlag;
+        }
         F[m] = r[m];
         N[m] = 1;
         Q[m] = leaf_range(m, slack);
