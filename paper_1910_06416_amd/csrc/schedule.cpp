@@ -22,9 +22,14 @@ rs_schedule builtin_schedule(uint32_t leaf, uint64_t buckets) {
     // wavefronts share each bucket's tree; with many buckets one wavefront per
     // bucket of small leaves keeps the most candidates in flight.  Measured on
     // MI355X at l = 8, b = 100: 4 wavefronts best up to ~1,000 buckets, 2 at
-    // 10,000-30,000, 1 at 100,000; at l = 12, b = 1000, 8 at 100 buckets.
+    // 10,000-30,000, 1 at 100,000; at l = 12, b = 1000, 8 at 100 buckets and
+    // 4 from 10,000 on.  From l = 16 on, splits are heavy enough that their
+    // shared search keeps 8 wavefronts busy (10^7 keys at l = 16, b = 2000:
+    // 5.93 s against 6.11 s with 4).
     if (leaf <= 8)
         s.waves = buckets <= 4096 ? 4 : buckets <= 40000 ? 2 : 1;
+    else if (leaf >= 16)
+        s.waves = 8;
     else
         s.waves = leaf <= 12 && buckets <= 256 ? 8 : 4;
     return s;

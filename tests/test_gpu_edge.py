@@ -142,8 +142,9 @@ def _golden_large_leaves():
 @pytest.mark.parametrize("row", _golden_large_leaves(), ids=lambda r: f"l{r[0]}_b{r[1]}_n{r[2]}" if r else "none")
 def test_split_nodes_at_large_leaf_sizes(rs, orc, row):
     """Blobs at l = 18, 20, 22, 24 with split nodes equal the stored oracle
-    structures, under the built-in schedule (four wavefronts, so waits through
-    searches of many seconds) and with one wavefront per bucket."""
+    structures, under the built-in schedule (several wavefronts, so waits
+    through searches of many seconds and shared split searches) and with one
+    wavefront per bucket."""
     leaf, bucket, n, seed, want = row
     keys = inputs.u64_keys(n, seed)
     h = orc.header(want)
