@@ -79,6 +79,10 @@ int upload_tables(uint32_t leaf, uint32_t maxm, uint32_t gr_max, uint32_t slack,
 // `buckets` buckets in all, range checks, and the process-wide table filled by
 // the autotuner.
 rs_schedule builtin_schedule(uint32_t leaf, uint64_t buckets);
+// Expected hash evaluations of the seed searches of n keys in buckets of b
+// (trials 1/p times keys for every node of the strategy, bucket sizes taken as
+// Poisson(n / ceil(n / b))); the serving loop's model of a request's device work.
+double expected_search_evals(uint32_t leaf, uint32_t bucket, uint64_t n);
 bool schedule_valid(const rs_schedule& s);
 bool schedule_lookup(uint32_t leaf, uint32_t bucket, rs_schedule* out);
 void schedule_store(uint32_t leaf, uint32_t bucket, const rs_schedule& s);

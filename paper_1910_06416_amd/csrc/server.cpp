@@ -5,12 +5,15 @@
 // when its estimated device footprint fits in the free part of the budget (a
 // request is always admitted when nothing else is in flight, so an oversized
 // one cannot wait forever).  Each build worker owns a stream; when it is free
-// it takes the request at the head of the queue and every admissible queued
+// it takes the first request that may start and every admissible queued
 // request of the same leaf size, and runs them as one batched construction
 // (rs_build_batch).  Requests that arrive while a batch is on the device form
-// the next worker's batch, so their work overlaps on the device.  A lookup
-// worker runs lookup requests on its own stream.  All streams have the
-// default priority.
+// the next worker's batch, so their work overlaps on the device.  A request
+// whose modelled search time reaches kHeavySeconds is heavy: at most one
+// batch with a heavy request is on the device at a time (two such searches
+// sharing the compute units would each take about twice as long, which only
+// delays both), while light requests start beside it.  A lookup worker runs
+// lookup requests on its own stream.  All streams have the default priority.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -36,6 +39,13 @@ uint64_t build_footprint(uint64_t n, uint32_t bucket) {
     return 56 * n + 24 * (n / std::max<uint32_t>(bucket, 1) + 1) + (1u << 20);
 }
 
+// Modelled search time: expected hash evaluations (every key of every trial)
+// at the rate that matches the measured searches on MI355X (10^7 keys: 6 s at
+// l = 16, b = 2000 and 0.1 s at l = 12, b = 1000; the bijection search stops
+// early in most trials, so it runs faster than one evaluation per slot).
+constexpr double kEvalsPerSecond = 2.4e12;
+constexpr double kHeavySeconds = 0.25;
+
 struct Request {
     uint64_t ticket;
     bool is_build;
@@ -44,6 +54,7 @@ struct Request {
     const rs_blob* blob = nullptr;
     uint64_t* ranks = nullptr;
     uint64_t footprint = 0;
+    bool heavy = false;
     Clock::time_point arrival;
 };
 
@@ -66,6 +77,7 @@ struct rs_server {
     uint64_t next_ticket = 1;
     uint64_t budget = 0, in_flight = 0, peak_in_flight = 0;
     uint64_t batches = 0, batched_requests = 0, max_batch = 0, concurrent = 0, max_concurrent = 0;
+    uint32_t heavy_in_flight = 0;  // batches with a heavy request on the device
     uint32_t max_queue = 0;
     bool stopping = false;
     int device = 0;
@@ -98,19 +110,25 @@ void build_worker(rs_server* s) {
     for (;;) {
         std::vector<Request> batch;
         uint64_t bytes = 0;
+        bool batch_heavy = false;
         {
             std::unique_lock<std::mutex> lk(s->mu);
             for (;;) {
-                if (!s->builds.empty()) {
-                    // admit the head request (always, if nothing is in flight), then
-                    // the later requests of its leaf size while the budget allows.
-                    // The requests of one batch finish together, so a batch holds
-                    // one leaf size: a small l = 8 request never waits for an l = 16
+                // the first request that may start: a heavy one only while no other
+                // heavy batch is on the device
+                auto head = s->builds.begin();
+                while (head != s->builds.end() && head->heavy && s->heavy_in_flight) ++head;
+                if (head != s->builds.end()) {
+                    // admit it (always, if nothing is in flight), then the later
+                    // requests of its leaf size while the budget allows.  The
+                    // requests of one batch finish together, so a batch holds one
+                    // leaf size: a small l = 8 request never waits for an l = 16
                     // search of seconds; other leaf sizes go to the next free worker.
-                    const uint32_t cls = s->builds.front().leaf;
-                    for (auto it = s->builds.begin(); it != s->builds.end();) {
+                    const uint32_t cls = head->leaf;
+                    bool heavy_batch = false;
+                    for (auto it = head; it != s->builds.end();) {
                         const Request& r = *it;
-                        if (r.leaf != cls) {
+                        if (r.leaf != cls || (r.heavy && s->heavy_in_flight)) {
                             ++it;
                             continue;
                         }
@@ -121,16 +139,21 @@ void build_worker(rs_server* s) {
                             continue;
                         }
                         bytes += r.footprint;
+                        heavy_batch |= r.heavy;
                         batch.push_back(r);
                         it = s->builds.erase(it);
                     }
-                    if (!batch.empty()) break;
+                    if (!batch.empty()) {
+                        batch_heavy = heavy_batch;
+                        break;
+                    }
                 }
                 if (s->stopping && s->builds.empty()) break;
                 s->cv_work.wait(lk);
             }
             if (batch.empty()) break;
             s->in_flight += bytes;
+            s->heavy_in_flight += batch_heavy ? 1 : 0;
             s->peak_in_flight = std::max(s->peak_in_flight, s->in_flight);
             s->batches++;
             s->batched_requests += batch.size();
@@ -159,6 +182,7 @@ void build_worker(rs_server* s) {
                 finish(s, batch[i], st, outs[i], count);
             }
             s->in_flight -= bytes;
+            s->heavy_in_flight -= batch_heavy ? 1 : 0;
             s->concurrent--;
         }
         s->cv_work.notify_all();
@@ -271,6 +295,7 @@ extern "C" int rs_server_submit_build(rs_server* s, const rs_keys* keys, uint32_
     r.leaf = leaf;
     r.bucket = bucket;
     r.footprint = build_footprint(keys->n, bucket);
+    r.heavy = rs::expected_search_evals(leaf, bucket, keys->n) / kEvalsPerSecond >= kHeavySeconds;
     return submit(s, r, ticket);
 }
 

@@ -139,6 +139,38 @@ void fill(const Strategy& st, uint32_t cap, uint32_t* dst, uint32_t gr_max, uint
 
 }  // namespace
 
+double expected_search_evals(uint32_t leaf, uint32_t bucket, uint64_t n) {
+    if (n == 0 || bucket == 0 || leaf < 1 || leaf > kMaxLeaf) return 0.0;
+    const Strategy st = make_strategy(leaf);
+    const uint64_t nb = (n + bucket - 1) / bucket;
+    const double lam = (double)n / (double)nb;
+    const uint32_t kmax = (uint32_t)(lam + 12.0 * std::sqrt(lam) + 16.0);
+    // E[m]: expected evaluations of the tree on m keys
+    std::vector<double> E(kmax + 1, 0.0);
+    for (uint32_t m = 2; m <= kmax; m++) {
+        E[m] = std::exp(-log_success(st, m, 0)) * (double)m;
+        if (m > st.leaf) {
+            const SplitShape sh = split_shape(m, st.leaf, st.lower, st.upper);
+            E[m] += (double)(sh.fanout - 1) * E[sh.unit] + E[sh.last];
+        }
+    }
+    // average over Poisson(lam) bucket sizes (summed from the mode both ways)
+    double per_bucket = 0.0;
+    const uint32_t mode = (uint32_t)lam;
+    const double lp0 = (double)mode * std::log(lam) - lam - std::lgamma((double)mode + 1.0);
+    double lp = lp0;
+    for (uint32_t k = mode; k <= kmax; k++) {
+        per_bucket += std::exp(lp) * E[k];
+        lp += std::log(lam) - std::log((double)k + 1.0);
+    }
+    lp = lp0;
+    for (uint32_t k = mode; k-- > 0;) {
+        lp += std::log((double)k + 1.0) - std::log(lam);
+        per_bucket += std::exp(lp) * E[k];
+    }
+    return per_bucket * (double)nb;
+}
+
 void fill_tables(uint32_t leaf, uint32_t maxm, uint32_t* dst, uint32_t gr_max, uint32_t slack) {
     fill(make_strategy(leaf), maxm, dst, gr_max, slack);
 }
