@@ -936,7 +936,12 @@ constexpr uint32_t kSplitPollSteps = 16;
 // once *best (the smallest success any of them found) is at or below the
 // candidates still to try, and the owner of the node handles duplicates and
 // the cap.
-template <int NT, int MODE>
+//
+// EXACT: every part has u keys (m = f u).  Then the part of a key,
+// floor(floor(h m / 2^32) / u), equals floor(h f / 2^32) (nested floors of
+// an integer division), one multiply instead of two: h >> 30 for the
+// one-hot mode's fanout of 4.
+template <int NT, int MODE, bool EXACT>
 __device__ __forceinline__ uint64_t split_search(const uint64_t* keys, uint32_t depth, const SplitCtl& c, const uint32_t* T,
                                  uint64_t lo, uint64_t hi, uint64_t cap, const unsigned long long* best,
                                  uint32_t* flags, QueueState* qs) {
@@ -976,10 +981,10 @@ __device__ __forceinline__ uint64_t split_search(const uint64_t* keys, uint32_t 
 #pragma unroll
             for (int u = 0; u < 4; u++) {
                 if constexpr (MODE == kCountPacked) {
-                    uint32_t j = __umulhi(__umulhi(h[u], m), c.recip);
+                    uint32_t j = EXACT ? __umulhi(h[u], c.fanout) : __umulhi(__umulhi(h[u], m), c.recip);
                     packed += 1ull << (j * c.w);
                 } else if constexpr (MODE == kCountOneHot) {
-                    uint32_t j = __umulhi(__umulhi(h[u], m), c.recip);
+                    uint32_t j = EXACT ? h[u] >> 30 : __umulhi(__umulhi(h[u], m), c.recip);
                     onehot += 1u << (j * c.w);
                 } else {
 #pragma unroll
@@ -990,10 +995,10 @@ __device__ __forceinline__ uint64_t split_search(const uint64_t* keys, uint32_t 
         for (uint32_t i = tail + gl; i < m; i += G) {
             uint32_t h = mix64_hi32(keys[i] + S);
             if constexpr (MODE == kCountPacked) {
-                uint32_t j = __umulhi(__umulhi(h, m), c.recip);
+                uint32_t j = EXACT ? __umulhi(h, c.fanout) : __umulhi(__umulhi(h, m), c.recip);
                 packed += 1ull << (j * c.w);
             } else if constexpr (MODE == kCountOneHot) {
-                uint32_t j = __umulhi(__umulhi(h, m), c.recip);
+                uint32_t j = EXACT ? h >> 30 : __umulhi(__umulhi(h, m), c.recip);
                 onehot += 1u << (j * c.w);
             } else {
 #pragma unroll
@@ -1041,13 +1046,18 @@ template <int MAXNT>
 __device__ __forceinline__ uint64_t split_dispatch(const uint64_t* keys, uint32_t depth, const SplitCtl& c, const uint32_t* T,
                                    uint32_t mode, uint64_t lo, uint64_t hi, uint64_t cap,
                                    const unsigned long long* best, uint32_t* flags, QueueState* qs) {
-    if (mode == kCountPacked) return split_search<0, kCountPacked>(keys, depth, c, T, lo, hi, cap, best, flags, qs);
-    if (mode == kCountOneHot) return split_search<0, kCountOneHot>(keys, depth, c, T, lo, hi, cap, best, flags, qs);
+    const bool exact = c.last == c.unit;
+    if (mode == kCountPacked)
+        return exact ? split_search<0, kCountPacked, true>(keys, depth, c, T, lo, hi, cap, best, flags, qs)
+                     : split_search<0, kCountPacked, false>(keys, depth, c, T, lo, hi, cap, best, flags, qs);
+    if (mode == kCountOneHot)
+        return exact ? split_search<0, kCountOneHot, true>(keys, depth, c, T, lo, hi, cap, best, flags, qs)
+                     : split_search<0, kCountOneHot, false>(keys, depth, c, T, lo, hi, cap, best, flags, qs);
     switch (c.fanout - 1) {
 #define RS_SPLIT_CASE(NT)                                                                                       \
     case NT:                                                                                                    \
         if constexpr (NT <= MAXNT)                                                                              \
-            return split_search<NT, kCountThresholds>(keys, depth, c, T, lo, hi, cap, best, flags, qs);         \
+            return split_search<NT, kCountThresholds, false>(keys, depth, c, T, lo, hi, cap, best, flags, qs);  \
         return kNoSeed;
         RS_SPLIT_CASE(1) RS_SPLIT_CASE(2) RS_SPLIT_CASE(3) RS_SPLIT_CASE(4) RS_SPLIT_CASE(5) RS_SPLIT_CASE(6)
         RS_SPLIT_CASE(7) RS_SPLIT_CASE(8)

@@ -75,3 +75,24 @@ def test_reciprocal_multiply_is_exact_below_2_to_16():
         p = np.arange((1 << 16) - 2 * uu, 1 << 16, dtype=np.uint64)
         cc = np.uint64(((1 << 32) + uu - 1) // uu)
         assert np.array_equal((p * cc) >> np.uint64(32), p // np.uint64(uu))
+
+
+def test_equal_parts_child_index_identity():
+    """Split searches whose parts all hold u keys (m = f u) take a key's part
+    as floor(h f / 2^32) instead of floor(floor(h m / 2^32) / u): the nested
+    floors of an integer division agree.  Checked for every fanout and part
+    size the strategy makes up to l = 24 (f <= 9, u <= 24 * 9 * 7), on random
+    and boundary 32-bit hash words."""
+    rng = np.random.default_rng(9)
+    h = np.concatenate([rng.integers(0, 1 << 32, 20000, dtype=np.uint64),
+                        np.array([0, 1, (1 << 32) - 1, 1 << 31], dtype=np.uint64)])
+    for f in range(2, 10):
+        for u in list(range(1, 65)) + [96, 112, 160, 216, 240, 560, 1512]:
+            m = np.uint64(f * u)
+            want = ((h * m) >> np.uint64(32)) // np.uint64(u)
+            got = (h * np.uint64(f)) >> np.uint64(32)
+            assert np.array_equal(got, want), (f, u)
+            # boundaries: the smallest h of every part
+            edges = (np.arange(1, f, dtype=np.uint64) << np.uint64(32)) // np.uint64(f)
+            for e in (edges, edges + np.uint64(1), np.maximum(edges, np.uint64(1)) - np.uint64(1)):
+                assert np.array_equal((e * np.uint64(f)) >> np.uint64(32), ((e * m) >> np.uint64(32)) // np.uint64(u))
