@@ -2116,6 +2116,7 @@ struct TuneCtx {
     bool probe_only = false;  // time the built-in schedule and report residency only
     double budget_ms = 0;     // search time allowed for the variants
     uint64_t buckets = 0;     // buckets of the calibration build (for the built-in schedule)
+    uint32_t bucket = 0;      // its bucket size
     // results
     rs_schedule best{};
     double default_ms = 0;
@@ -2158,7 +2159,7 @@ int tune_search(TuneCtx& t, uint32_t leaf, BuildDesc* hdesc, BuildDesc* d_desc, 
         return RS_OK;
     };
     int rc = RS_OK;
-    rs_schedule cur = builtin_schedule(leaf, t.buckets);
+    rs_schedule cur = builtin_schedule(leaf, t.buckets, t.bucket);
     double warm = 0, warm_total = 0, best_ms = 0;
     // warm-up: the first launches run slower (clocks still ramping), so search
     // for at least 100 ms (at most 20 launches) before timing anything
@@ -2182,7 +2183,7 @@ int tune_search(TuneCtx& t, uint32_t leaf, BuildDesc* hdesc, BuildDesc* d_desc, 
     }
     {
         // one knob at a time: wavefronts per bucket, staged-search threshold, lanes per split candidate
-        std::vector<uint32_t> waves_list = leaf <= 8 ? std::vector<uint32_t>{1, 2, 4} : std::vector<uint32_t>{2, 4, 8};
+        std::vector<uint32_t> waves_list = leaf <= 8 ? std::vector<uint32_t>{1, 2, 4} : std::vector<uint32_t>{1, 2, 4, 8};
         std::vector<uint32_t> stage_list;
         for (uint32_t v : {7u, 8u, 9u, 11u, 13u, 16u, 25u})
             if (v >= 7 && (v <= leaf || v == 25)) stage_list.push_back(v);
@@ -2351,7 +2352,7 @@ int batch_prepare(Batch& b, const rs_keys* sets, uint32_t count, const uint32_t*
     b.K = (uint32_t)b.hd.size();
     if (b.K && b.nbuckets >= (1ull << 32)) return fail(RS_EINVAL, "too many buckets in one call");
     for (BuildDesc& d : b.hd) {
-        if (!d.waves) d.waves = builtin_schedule(d.leaf, b.nbuckets).waves;
+        if (!d.waves) d.waves = builtin_schedule(d.leaf, b.nbuckets, d.bucket).waves;
         b.launch_waves = std::max(b.launch_waves, d.waves);
     }
     return RS_OK;
@@ -2737,6 +2738,7 @@ int build_batch_impl(const rs_keys* sets, uint32_t count, const uint32_t* leafs,
     if (int rc = upload_batch_tables(b, maxm, s)) return cleanup(rc);
     if (tune) {  // calibration only: no blob, the tables are not handed to an arena
         tune->buckets = b.nbuckets;
+        tune->bucket = b.hd.empty() ? 0 : b.hd[0].bucket;
         const int trc = tune_search(*tune, b.max_leaf, b.h_desc, b.d_desc, search_args(b), b.lds, s);
         al.put(b.d_tab, s);
         b.d_tab = nullptr;

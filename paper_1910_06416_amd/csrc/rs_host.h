@@ -78,7 +78,9 @@ int upload_tables(uint32_t leaf, uint32_t maxm, uint32_t gr_max, uint32_t slack,
 // Search schedules: the built-in one of a leaf size for a launch over
 // `buckets` buckets in all, range checks, and the process-wide table filled by
 // the autotuner.
-rs_schedule builtin_schedule(uint32_t leaf, uint64_t buckets);
+// Built-in search schedule of builds with leaf size `leaf` and bucket size
+// `bucket` (0: not known) in a call of `buckets` buckets.
+rs_schedule builtin_schedule(uint32_t leaf, uint64_t buckets, uint32_t bucket = 0);
 // Expected hash evaluations of the seed searches of n keys in buckets of b
 // (trials 1/p times keys for every node of the strategy, bucket sizes taken as
 // Poisson(n / ceil(n / b))); the serving loop's model of a request's device work.
