@@ -177,3 +177,38 @@ def test_bucket_above_the_estimated_cap_builds_again(rs, orc):
     blob = rs.build(rs.device_keys(keys), leaf, bucket, timing=True)
     assert rs.last_build_stats()["maxm"] == 400
     assert blob.to_bytes() == orc.build(keys, leaf, bucket)
+
+
+def test_shared_split_searches_keep_the_seed_cap_boundary(rs, orc):
+    """l=16, b=2000, two buckets: the heavy splits (112 and 560 keys) are
+    searched by several wavefronts in chunks (8 wavefronts per bucket) or by
+    one.  With the cap at the structure's largest index both fail with
+    RS_ESEARCH; one above it both give the oracle's bytes."""
+    keys = inputs.u64_keys(4000, 84)
+    want = orc.build(keys, 16, 2000)
+    nb = 2
+    top = 0
+    for i in range(nb):
+        _, _, v, m = orc.blob_bucket(want, i)
+        top = max(top, int(np.max(v)))
+    dk = rs.device_keys(keys)
+    for waves in (8, 1):
+        print(f"case shared splits seed cap waves={waves} cap={top}", flush=True)
+        with pytest.raises(rs.RecSplitError) as e:
+            rs.build(dk, 16, 2000, waves=waves, seed_cap=top)
+        assert e.value.code == rs.RS_ESEARCH, (waves, str(e.value))
+        assert rs.build(dk, 16, 2000, waves=waves, seed_cap=top + 1).to_bytes() == want
+
+
+def test_tiny_wait_limit_with_shared_split_searches(rs, orc):
+    """8 wavefronts per bucket at l=16: waits for slots and an owner's wait for
+    its helpers both give up after one sleep without progress; the build fails
+    cleanly with RS_EDEVICE and the next build works."""
+    keys = inputs.u64_keys(4000, 85)
+    dk = rs.device_keys(keys)
+    print("case wait limit 1, l=16", flush=True)
+    with pytest.raises(rs.RecSplitError) as e:
+        rs.build(dk, 16, 2000, waves=8, wait_limit=1)
+    assert e.value.code == rs.RS_EDEVICE and "scheduling" in str(e.value)
+    got = rs.build(dk, 16, 2000, waves=8).to_bytes()
+    assert got == orc.build(keys, 16, 2000)
