@@ -43,11 +43,6 @@ __global__ void k_reset(DevStatus* st, unsigned long long* counters, uint64_t n)
     for (; i < n; i += (uint64_t)gridDim.x * blockDim.x) counters[i] = 0;
 }
 
-__global__ void k_fill_u64(uint64_t* p, uint64_t n, uint64_t v) {
-    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (; i < n; i += (uint64_t)gridDim.x * blockDim.x) p[i] = v;
-}
-
 // ---------------------------------------------------------------------------
 // Builds of one call.  Several independent key sets are built together: their
 // keys and buckets are numbered consecutively (key_base, bucket_base) and every
@@ -1638,13 +1633,21 @@ struct FillArgs {
     uint64_t nbuckets;
     const uint32_t* tables;
     uint32_t stride;
-    uint64_t g0;  // k_tree_bits: bucket of the launch's first lane group
+    uint64_t g0;             // k_tree_bits: bucket of the launch's first lane group
+    const uint64_t* headers;  // k_ef_fill: kHeaderWords per build
 };
 
 // One thread per Elias-Fano entry i = 0..nb of every build.
 __global__ void k_ef_fill(FillArgs a) {
     const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= a.nbuckets + a.count) return;
+    if (e >= a.nbuckets + a.count) {  // the threads past the entries write the headers
+        const uint64_t hw = e - (a.nbuckets + a.count);
+        if (hw < (uint64_t)a.count * kHeaderWords) {
+            const uint32_t j = (uint32_t)(hw / kHeaderWords), w = (uint32_t)(hw % kHeaderWords);
+            if (a.descs[j].blob) a.descs[j].blob[w] = a.headers[hw];
+        }
+        return;
+    }
     const uint32_t j = find_build(a.entry_base, a.count, e);
     const BuildDesc& B = a.descs[j];
     if (!B.blob) return;
@@ -1769,20 +1772,13 @@ __global__ __launch_bounds__(kBlock) void k_tree_bits(FillArgs a) {
 // anyway (the search flags it), so it takes its size.
 __global__ void k_range_sizes(const uint64_t* __restrict__ bstart, const BuildDesc* __restrict__ descs,
                               const uint64_t* __restrict__ bucket_base, uint32_t count, uint64_t nbuckets,
-                              const uint32_t* __restrict__ tables, uint32_t stride, uint64_t* __restrict__ out) {
+                              const uint32_t* __restrict__ tables, uint32_t stride, uint32_t tab_maxm,
+                              uint64_t* __restrict__ out) {
     const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= nbuckets) return;
     const uint32_t j = find_build(bucket_base, count, g);
     const uint64_t m = bstart[g + 1] - bstart[g];
-    out[g] = m < stride ? tables[((size_t)descs[j].tab * kTableCount + 5) * stride + m] : m;
-}
-
-// Headers: 16 words per build with a blob.
-__global__ void k_write_headers(const BuildDesc* descs, const uint64_t* headers, uint32_t count) {
-    const uint32_t t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= count * kHeaderWords) return;
-    const uint32_t j = t / kHeaderWords, w = t % kHeaderWords;
-    if (descs[j].blob) descs[j].blob[w] = headers[t];
+    out[g] = m <= tab_maxm ? tables[((size_t)descs[j].tab * kTableCount + 5) * stride + m] : m;
 }
 
 // Elias-Fano lower width: the largest W >= 0 with N * 2^W <= U.
@@ -1863,20 +1859,28 @@ __global__ __launch_bounds__(kBlock) void k_layout(BuildDesc* __restrict__ descs
     if (threadIdx.x == 0) off[count] = carry_s;
 }
 
-// Blob addresses inside an arena of `capacity` words at the scanned offsets;
-// a build that does not fit gets no blob and raises the capacity flag.
+// Blob addresses inside an arena of `capacity` words at the scanned offsets
+// (a build that does not fit gets no blob and raises the capacity flag), and
+// the first clear_words words of the arena zeroed (the Elias-Fano and
+// Golomb-Rice writers OR their bits in).  One launch: the two parts touch
+// different memory.
 __global__ void k_set_blobs(BuildDesc* __restrict__ descs, uint32_t count, unsigned long long* arena,
-                            const uint64_t* __restrict__ off, uint64_t capacity, uint32_t* __restrict__ flags) {
-    const uint32_t j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= count) return;
-    if (!arena || off[j + 1] == off[j]) {
-        descs[j].blob = nullptr;
-    } else if (off[j + 1] > capacity) {
-        descs[j].blob = nullptr;
-        atomicOr(flags, kFlagCapacity);
-    } else {
-        descs[j].blob = arena + off[j];
+                            const uint64_t* __restrict__ off, uint64_t capacity, uint32_t* __restrict__ flags,
+                            uint64_t clear_words) {
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < count) {
+        const uint32_t j = (uint32_t)t;
+        if (!arena || off[j + 1] == off[j]) {
+            descs[j].blob = nullptr;
+        } else if (off[j + 1] > capacity) {
+            descs[j].blob = nullptr;
+            atomicOr(flags, kFlagCapacity);
+        } else {
+            descs[j].blob = arena + off[j];
+        }
     }
+    if (arena)
+        for (uint64_t i = t; i < clear_words; i += (uint64_t)gridDim.x * blockDim.x) arena[i] = 0;
 }
 
 uint64_t grid_for(uint64_t n, uint64_t block) { return std::max<uint64_t>(1, (n + block - 1) / block); }
@@ -2488,32 +2492,45 @@ int enqueue_front(Batch& b, hipStream_t s, PhaseEvents* pe) {
     return RS_OK;
 }
 
-// Per-size tables of every leaf size of the call for sizes 0..maxm (into
-// b.d_tab, which holds ntab * kTableCount * (maxm + 1) words) and the
+// Per-size tables of every table set of the call for sizes 0..maxm and the
 // search's dynamic LDS (keys + node slots of the largest possible bucket).
-int upload_batch_tables(Batch& b, uint32_t maxm, hipStream_t s) {
+// The device copy of a set has the layout of the host cache (kTableCount
+// arrays of cap + 1 >= maxm + 1 words), with the largest cap of the call as
+// stride, so a set goes up in one copy (one copy per array would launch eight
+// small copies per build).  table_words(b) words in b.d_tab.
+int prepare_tables(Batch& b, uint32_t maxm) {
     b.table_maxm = maxm;
     b.stride = maxm + 1;
     uint32_t max_nodes = 0;
-    for (uint32_t t = 0; t < (uint32_t)b.tab_keys.size(); t++) {
-        const TabKey& key = b.tab_keys[t];
-        TableView tv = host_tables(key.leaf, maxm, key.gr_max, key.slack);
+    for (const TabKey& key : b.tab_keys) {
+        const TableView tv = host_tables(key.leaf, maxm, key.gr_max, key.slack);
         if (!tv.data) return fail(RS_ENOMEM, "table allocation failed");
-        for (uint32_t m = 0; m <= maxm; m++) max_nodes = std::max(max_nodes, tv.N()[m]);
-        uint32_t* dst = b.d_tab + (size_t)t * kTableCount * b.stride;
         if (key.slack && !ranges_increasing(tv.Q(), maxm))
             return fail(RS_EINVAL, "leaf_slack %u gives two bucket sizes the same range", key.slack);
-        // the cached tables hold cap + 1 >= stride entries per array
-        for (int a = 0; a < kTableCount; a++)
-            RS_ENQ(hipMemcpyAsync(dst + (size_t)a * b.stride, tv.data + (size_t)a * (tv.cap + 1), b.stride * 4ull,
-                                  hipMemcpyHostToDevice, s));
+        for (uint32_t m = 0; m <= maxm; m++) max_nodes = std::max(max_nodes, tv.N()[m]);
+        b.stride = std::max(b.stride, tv.cap + 1);
     }
     b.lds = (size_t)maxm * 8 + (size_t)max_nodes * 16;
     return RS_OK;
 }
 
-size_t table_words(const Batch& b, uint32_t maxm) {
-    return b.tab_keys.size() * kTableCount * (size_t)(maxm + 1);
+size_t table_words(const Batch& b) { return b.tab_keys.size() * kTableCount * (size_t)b.stride; }
+
+int upload_batch_tables(Batch& b, hipStream_t s) {
+    for (uint32_t t = 0; t < (uint32_t)b.tab_keys.size(); t++) {
+        const TabKey& key = b.tab_keys[t];
+        const TableView tv = host_tables(key.leaf, b.table_maxm, key.gr_max, key.slack);
+        if (!tv.data) return fail(RS_ENOMEM, "table allocation failed");
+        uint32_t* dst = b.d_tab + (size_t)t * kTableCount * b.stride;
+        if (tv.cap + 1 == b.stride) {
+            RS_ENQ(hipMemcpyAsync(dst, tv.data, (size_t)kTableCount * b.stride * 4, hipMemcpyHostToDevice, s));
+        } else {  // a set cached with a smaller cap than another of the call
+            for (int a = 0; a < kTableCount; a++)
+                RS_ENQ(hipMemcpyAsync(dst + (size_t)a * b.stride, tv.data + (size_t)a * (tv.cap + 1),
+                                      (tv.cap + 1) * 4ull, hipMemcpyHostToDevice, s));
+        }
+    }
+    return RS_OK;
 }
 
 SearchArgs search_args(const Batch& b) {
@@ -2532,7 +2549,7 @@ int enqueue_back(Batch& b, hipStream_t s, PhaseEvents* pe) {
     if (int rc = scan<uint64_t>(b.d_blen, b.nbuckets, b.d_ost, b.d_tiles, nullptr, s)) return rc;
     if (b.wide) {  // bucket ranges into the bit lengths' array (scanned already), then their prefix sums
         RS_LAUNCH(k_range_sizes, grid_for(b.nbuckets, kBlock), kBlock, 0, s, b.d_bst, b.d_desc, b.d_bb, b.K,
-                  b.nbuckets, b.d_tab, b.stride, b.d_blen);
+                  b.nbuckets, b.d_tab, b.stride, b.table_maxm, b.d_blen);
         if (int rc = scan<uint64_t>(b.d_blen, b.nbuckets, b.d_qst, b.d_tiles, nullptr, s)) return rc;
     }
     GapArgs ga{b.d_bst, b.d_qst, b.d_ost, b.d_desc, b.d_desc, b.d_bb, b.K, b.nbuckets};
@@ -2547,14 +2564,13 @@ int enqueue_back(Batch& b, hipStream_t s, PhaseEvents* pe) {
 // zeroed first), headers, Elias-Fano bits and Golomb-Rice streams.
 int enqueue_fill(Batch& b, uint64_t* arena, uint64_t capacity, uint64_t clear_words, hipStream_t s) {
     const uint32_t K = b.K;
-    RS_LAUNCH(k_set_blobs, grid_for(K, kBlock), kBlock, 0, s, b.d_desc, K, (unsigned long long*)arena, b.d_boff,
-              capacity, &b.d_st->flags);
-    if (arena && clear_words)
-        RS_LAUNCH(k_fill_u64, grid_for(clear_words, kBlock * 8), kBlock, 0, s, arena, clear_words, 0);
-    RS_LAUNCH(k_write_headers, grid_for((uint64_t)K * kHeaderWords, kBlock), kBlock, 0, s, b.d_desc, b.d_hdr, K);
+    const uint64_t clear = arena ? clear_words : 0;
+    RS_LAUNCH(k_set_blobs, std::max(grid_for(K, kBlock), grid_for(clear, kBlock * 8)), kBlock, 0, s, b.d_desc, K,
+              (unsigned long long*)arena, b.d_boff, capacity, &b.d_st->flags, clear);
     FillArgs fa{b.d_bst, b.d_qst, b.d_ost, b.d_seeds, b.d_bid, b.d_desc, b.d_bb, b.d_eb, K, b.nbuckets, b.d_tab,
-                b.stride, 0};
-    RS_LAUNCH(k_ef_fill, grid_for(b.nbuckets + K, kBlock), kBlock, 0, s, fa);
+                b.stride, 0, b.d_hdr};
+    // Elias-Fano entries, then the header words of every build
+    RS_LAUNCH(k_ef_fill, grid_for(b.nbuckets + K + (uint64_t)K * kHeaderWords, kBlock), kBlock, 0, s, fa);
     // kTreeLanes lanes per bucket, in launches of at most max_grid_blocks() blocks
     if (int rc = for_each_chunk(b.nbuckets, kBlock, kBlock / kTreeLanes, [&](uint64_t g0, uint64_t, uint64_t blocks) -> int {
             fa.g0 = g0;
@@ -2734,8 +2750,9 @@ int build_batch_impl(const rs_keys* sets, uint32_t count, const uint32_t* leafs,
         maxm = b.h_st->maxm;
         RS_TRACE("largest bucket %u", maxm);
     }
-    if (int rc = al.get((void**)&b.d_tab, table_words(b, maxm) * 4, s)) return cleanup(rc);
-    if (int rc = upload_batch_tables(b, maxm, s)) return cleanup(rc);
+    if (int rc = prepare_tables(b, maxm)) return cleanup(rc);
+    if (int rc = al.get((void**)&b.d_tab, table_words(b) * 4, s)) return cleanup(rc);
+    if (int rc = upload_batch_tables(b, s)) return cleanup(rc);
     if (tune) {  // calibration only: no blob, the tables are not handed to an arena
         tune->buckets = b.nbuckets;
         tune->bucket = b.hd.empty() ? 0 : b.hd[0].bucket;
@@ -2925,10 +2942,11 @@ extern "C" int rs_plan_create(const rs_keys* sets, uint32_t count, const uint32_
     p->maxm_cap = std::min(maxm0 + margin, rs::lds_bucket_limit(b));
     if (p->maxm_cap < maxm0) return bail(rs::fail(RS_EINVAL, "largest bucket exceeds the local data share"));
     p->capacity = words0 + words0 / 8 + 64ull * b.K + 1024;
-    if ((rc = p->al.get((void**)&b.d_tab, rs::table_words(b, p->maxm_cap) * 4, p->cap_stream)) ||
+    if ((rc = rs::prepare_tables(b, p->maxm_cap)) ||
+        (rc = p->al.get((void**)&b.d_tab, rs::table_words(b) * 4, p->cap_stream)) ||
         (rc = p->al.get((void**)&p->arena, p->capacity * 8, p->cap_stream)))
         return bail(rc);
-    if ((rc = rs::upload_batch_tables(b, p->maxm_cap, p->cap_stream))) return bail(rc);
+    if ((rc = rs::upload_batch_tables(b, p->cap_stream))) return bail(rc);
     if (hipStreamSynchronize(p->cap_stream) != hipSuccess) return bail(rs::fail(RS_EDEVICE, "table upload failed"));
     // capture: every phase, no host read in between
     if (hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
@@ -2975,7 +2993,7 @@ extern "C" int rs_plan_run(rs_plan* p, void* stream, rs_blob** outs, int* per_bu
     const uint64_t words = b.h_boff[b.K];
     uint64_t* dst = nullptr;
     uint32_t* tab = nullptr;
-    const size_t tab_words = rs::table_words(b, b.table_maxm);
+    const size_t tab_words = rs::table_words(b);
     int rc = RS_OK;
     if (words) {
         if ((rc = p->al.get((void**)&dst, words * 8, s)) || (rc = p->al.get((void**)&tab, tab_words * 4, s))) {
@@ -3114,13 +3132,13 @@ extern "C" int rs_build_noalloc(const rs_keys* keys, uint32_t leaf, uint32_t buc
     const uint32_t maxm = b.h_st->maxm;
     if (maxm > kNoAllocMaxM) return fail(RS_EINVAL, "largest bucket (%u keys) exceeds the local data share", maxm);
     // tables after the workspace, filled on the host without allocating
-    const size_t tab_bytes = table_words(b, maxm) * 4;
+    b.table_maxm = maxm;
+    b.stride = maxm + 1;
+    const size_t tab_bytes = table_words(b) * 4;
     if (ws_bytes + tab_bytes > kScratchBytes)
         return fail(RS_EINVAL, "workspace and tables exceed the %zu bytes of the allocation-free build",
                     kScratchBytes);
     b.d_tab = reinterpret_cast<uint32_t*>(base + ws_bytes);
-    b.table_maxm = maxm;
-    b.stride = maxm + 1;
     fill_tables(leaf, maxm, g_na_tab);
     uint32_t max_nodes = 0;
     for (uint32_t m = 0; m <= maxm; m++) max_nodes = std::max(max_nodes, g_na_tab[2 * (maxm + 1) + m]);
