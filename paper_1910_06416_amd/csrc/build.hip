@@ -1638,8 +1638,7 @@ struct FillArgs {
 };
 
 // One thread per Elias-Fano entry i = 0..nb of every build.
-__global__ void k_ef_fill(FillArgs a) {
-    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void ef_fill_entry(const FillArgs& a, uint64_t e) {
     if (e >= a.nbuckets + a.count) {  // the threads past the entries write the headers
         const uint64_t hw = e - (a.nbuckets + a.count);
         if (hw < (uint64_t)a.count * kHeaderWords) {
@@ -1684,6 +1683,8 @@ __global__ void k_ef_fill(FillArgs a) {
     }
 }
 
+__global__ void k_ef_fill(FillArgs a) { ef_fill_entry(a, (uint64_t)blockIdx.x * blockDim.x + threadIdx.x); }
+
 // Golomb-Rice streams (Sec. 6.2): per bucket, the fixed parts of all coded
 // nodes in preorder, then their unary parts (q zeros and a one) in preorder.
 // A group of kTreeLanes lanes per bucket, one lane per coded node: the search
@@ -1707,9 +1708,9 @@ __device__ __forceinline__ uint64_t group_inclusive_sum(uint64_t x, uint32_t gl)
     return x;
 }
 
-__global__ __launch_bounds__(kBlock) void k_tree_bits(FillArgs a) {
-    __shared__ unsigned long long window[kBlock / kTreeLanes][kTreeWords];
-    const uint64_t g = a.g0 + ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kTreeLanes;
+__device__ __forceinline__ void tree_bits_block(const FillArgs& a, uint64_t block,
+                                                unsigned long long (*window)[kTreeWords]) {
+    const uint64_t g = a.g0 + (block * kBlock + threadIdx.x) / kTreeLanes;
     const uint32_t gl = threadIdx.x & (kTreeLanes - 1);
     if (g >= a.nbuckets) return;
     const uint32_t j = find_build(a.bucket_base, a.count, g);
@@ -1763,6 +1764,21 @@ __global__ __launch_bounds__(kBlock) void k_tree_bits(FillArgs a) {
             if (x) atomicOr(&tree[w0 + i], x);
         }
     }
+}
+
+__global__ __launch_bounds__(kBlock) void k_tree_bits(FillArgs a) {
+    __shared__ unsigned long long window[kBlock / kTreeLanes][kTreeWords];
+    tree_bits_block(a, blockIdx.x, window);
+}
+
+// Both writers in one launch: the first ef_blocks blocks take the
+// Elias-Fano entries and headers, the others the Golomb-Rice streams.  The
+// two write disjoint words of the blobs, and each is bound by the latency of
+// its loads and atomics, so running them side by side hides much of it.
+__global__ __launch_bounds__(kBlock) void k_fill(FillArgs a, uint32_t ef_blocks) {
+    __shared__ unsigned long long window[kBlock / kTreeLanes][kTreeWords];
+    if (blockIdx.x < ef_blocks) ef_fill_entry(a, (uint64_t)blockIdx.x * kBlock + threadIdx.x);
+    else tree_bits_block(a, blockIdx.x - ef_blocks, window);
 }
 
 // Output range of every bucket of a call that holds a non-minimal build: Q of
@@ -1920,10 +1936,10 @@ struct Staging {
     hipEvent_t done = nullptr;
     bool pending = false;
 };
-thread_local Staging g_staging;
+thread_local Staging g_staging;        // descriptors, bases, headers, sizes
+thread_local Staging g_table_staging;  // the call's per-size tables
 
-void* pinned(size_t bytes) {
-    Staging& st = g_staging;
+void* pinned(size_t bytes, Staging& st = g_staging) {
     if (st.pending) {
         (void)hipEventSynchronize(st.done);
         st.pending = false;
@@ -1931,7 +1947,7 @@ void* pinned(size_t bytes) {
     if (st.cap < bytes) {
         if (st.p) (void)hipHostFree(st.p);
         size_t want = std::max<size_t>(bytes, 1 << 16);
-        if (hipHostMalloc(&st.p, want, hipHostMallocDefault) != hipSuccess) {
+        if (hipHostMalloc(&st.p, want, hipHostMallocMapped) != hipSuccess) {  // (read by k_copy_words)
             st.p = nullptr;
             st.cap = 0;
             return nullptr;
@@ -1941,15 +1957,18 @@ void* pinned(size_t bytes) {
     return st.p;
 }
 
+// After the last copy of a call from either staging buffer.
 void pinned_release(hipStream_t s) {
-    Staging& st = g_staging;
-    if (!st.done && hipEventCreateWithFlags(&st.done, hipEventDisableTiming) != hipSuccess) {
-        st.done = nullptr;
-        (void)hipStreamSynchronize(s);
-        return;
+    for (Staging* st : {&g_staging, &g_table_staging}) {
+        if (!st->p) continue;
+        if (!st->done && hipEventCreateWithFlags(&st->done, hipEventDisableTiming) != hipSuccess) {
+            st->done = nullptr;
+            (void)hipStreamSynchronize(s);
+            return;
+        }
+        if (hipEventRecord(st->done, s) == hipSuccess) st->pending = true;
+        else (void)hipStreamSynchronize(s);
     }
-    if (hipEventRecord(st.done, s) == hipSuccess) st.pending = true;
-    else (void)hipStreamSynchronize(s);
 }
 
 thread_local rs_build_stats g_stats;
@@ -2492,12 +2511,11 @@ int enqueue_front(Batch& b, hipStream_t s, PhaseEvents* pe) {
     return RS_OK;
 }
 
-// Per-size tables of every table set of the call for sizes 0..maxm and the
-// search's dynamic LDS (keys + node slots of the largest possible bucket).
-// The device copy of a set has the layout of the host cache (kTableCount
-// arrays of cap + 1 >= maxm + 1 words), with the largest cap of the call as
-// stride, so a set goes up in one copy (one copy per array would launch eight
-// small copies per build).  table_words(b) words in b.d_tab.
+// Per-size tables of every table set of the call for sizes 0..maxm (each set
+// kTableCount arrays of maxm + 1 words, table_words(b) words in b.d_tab) and
+// the search's dynamic LDS (keys + node slots of the largest possible bucket).
+// The host cache may hold a set for many more sizes (the LDS limit probes up
+// to ~20,000): only the sizes the call can meet go up.
 int prepare_tables(Batch& b, uint32_t maxm) {
     b.table_maxm = maxm;
     b.stride = maxm + 1;
@@ -2508,7 +2526,6 @@ int prepare_tables(Batch& b, uint32_t maxm) {
         if (key.slack && !ranges_increasing(tv.Q(), maxm))
             return fail(RS_EINVAL, "leaf_slack %u gives two bucket sizes the same range", key.slack);
         for (uint32_t m = 0; m <= maxm; m++) max_nodes = std::max(max_nodes, tv.N()[m]);
-        b.stride = std::max(b.stride, tv.cap + 1);
     }
     b.lds = (size_t)maxm * 8 + (size_t)max_nodes * 16;
     return RS_OK;
@@ -2516,19 +2533,43 @@ int prepare_tables(Batch& b, uint32_t maxm) {
 
 size_t table_words(const Batch& b) { return b.tab_keys.size() * kTableCount * (size_t)b.stride; }
 
-int upload_batch_tables(Batch& b, hipStream_t s) {
+// Words from pinned host memory, read by the kernel itself.
+__global__ void k_copy_words(uint32_t* __restrict__ dst, const uint32_t* __restrict__ src, uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+// stage: null, or pinned host memory of table_words(b) words.  A copy from
+// pageable memory returns only once it has been made, i.e. after the work
+// queued before it.  From the pinned staging a small kernel reads the tables
+// in stream order: a copy engine would add its hand-over from the compute
+// queue and back (about 30 us between the bucketing and the search).
+int upload_batch_tables(Batch& b, hipStream_t s, uint32_t* stage) {
+    if (stage) {
+        for (uint32_t t = 0; t < (uint32_t)b.tab_keys.size(); t++) {
+            const TabKey& key = b.tab_keys[t];
+            const TableView tv = host_tables(key.leaf, b.table_maxm, key.gr_max, key.slack);
+            if (!tv.data) return fail(RS_ENOMEM, "table allocation failed");
+            for (int a = 0; a < kTableCount; a++)
+                memcpy(stage + ((size_t)t * kTableCount + a) * b.stride, tv.data + (size_t)a * (tv.cap + 1),
+                       (size_t)b.stride * 4);
+        }
+        void* src = nullptr;
+        RS_ENQ(hipHostGetDevicePointer(&src, stage, 0));
+        const uint64_t n = table_words(b);
+        RS_LAUNCH(k_copy_words, std::min<uint64_t>(grid_for(n, kBlock), 64), kBlock, 0, s, b.d_tab,
+                  static_cast<const uint32_t*>(src), n);
+        RS_ENQ(hipGetLastError());
+        return RS_OK;
+    }
     for (uint32_t t = 0; t < (uint32_t)b.tab_keys.size(); t++) {
         const TabKey& key = b.tab_keys[t];
         const TableView tv = host_tables(key.leaf, b.table_maxm, key.gr_max, key.slack);
         if (!tv.data) return fail(RS_ENOMEM, "table allocation failed");
         uint32_t* dst = b.d_tab + (size_t)t * kTableCount * b.stride;
-        if (tv.cap + 1 == b.stride) {
-            RS_ENQ(hipMemcpyAsync(dst, tv.data, (size_t)kTableCount * b.stride * 4, hipMemcpyHostToDevice, s));
-        } else {  // a set cached with a smaller cap than another of the call
-            for (int a = 0; a < kTableCount; a++)
-                RS_ENQ(hipMemcpyAsync(dst + (size_t)a * b.stride, tv.data + (size_t)a * (tv.cap + 1),
-                                      (tv.cap + 1) * 4ull, hipMemcpyHostToDevice, s));
-        }
+        for (int a = 0; a < kTableCount; a++)
+            RS_ENQ(hipMemcpyAsync(dst + (size_t)a * b.stride, tv.data + (size_t)a * (tv.cap + 1), b.stride * 4ull,
+                                  hipMemcpyHostToDevice, s));
     }
     return RS_OK;
 }
@@ -2569,9 +2610,17 @@ int enqueue_fill(Batch& b, uint64_t* arena, uint64_t capacity, uint64_t clear_wo
               (unsigned long long*)arena, b.d_boff, capacity, &b.d_st->flags, clear);
     FillArgs fa{b.d_bst, b.d_qst, b.d_ost, b.d_seeds, b.d_bid, b.d_desc, b.d_bb, b.d_eb, K, b.nbuckets, b.d_tab,
                 b.stride, 0, b.d_hdr};
-    // Elias-Fano entries, then the header words of every build
-    RS_LAUNCH(k_ef_fill, grid_for(b.nbuckets + K + (uint64_t)K * kHeaderWords, kBlock), kBlock, 0, s, fa);
-    // kTreeLanes lanes per bucket, in launches of at most max_grid_blocks() blocks
+    // Elias-Fano entries, then the header words of every build; kTreeLanes
+    // lanes per bucket for the trees.  One launch where both fit in one grid.
+    const uint64_t ef_blocks = grid_for(b.nbuckets + K + (uint64_t)K * kHeaderWords, kBlock);
+    const uint64_t tree_blocks = grid_for(b.nbuckets, kBlock / kTreeLanes);
+    if (ef_blocks + tree_blocks <= max_grid_blocks(kBlock)) {
+        RS_LAUNCH(k_fill, ef_blocks + tree_blocks, kBlock, 0, s, fa, (uint32_t)ef_blocks);
+        RS_ENQ(hipGetLastError());
+        return RS_OK;
+    }
+    RS_LAUNCH(k_ef_fill, ef_blocks, kBlock, 0, s, fa);
+    // trees in launches of at most max_grid_blocks() blocks
     if (int rc = for_each_chunk(b.nbuckets, kBlock, kBlock / kTreeLanes, [&](uint64_t g0, uint64_t, uint64_t blocks) -> int {
             fa.g0 = g0;
             RS_LAUNCH(k_tree_bits, blocks, kBlock, 0, s, fa);
@@ -2752,7 +2801,9 @@ int build_batch_impl(const rs_keys* sets, uint32_t count, const uint32_t* leafs,
     }
     if (int rc = prepare_tables(b, maxm)) return cleanup(rc);
     if (int rc = al.get((void**)&b.d_tab, table_words(b) * 4, s)) return cleanup(rc);
-    if (int rc = upload_batch_tables(b, s)) return cleanup(rc);
+    uint32_t* stage = static_cast<uint32_t*>(pinned(table_words(b) * 4, g_table_staging));
+    if (!stage) return cleanup(fail(RS_ENOMEM, "pinned host allocation failed"));
+    if (int rc = upload_batch_tables(b, s, stage)) return cleanup(rc);
     if (tune) {  // calibration only: no blob, the tables are not handed to an arena
         tune->buckets = b.nbuckets;
         tune->bucket = b.hd.empty() ? 0 : b.hd[0].bucket;
@@ -2946,7 +2997,7 @@ extern "C" int rs_plan_create(const rs_keys* sets, uint32_t count, const uint32_
         (rc = p->al.get((void**)&b.d_tab, rs::table_words(b) * 4, p->cap_stream)) ||
         (rc = p->al.get((void**)&p->arena, p->capacity * 8, p->cap_stream)))
         return bail(rc);
-    if ((rc = rs::upload_batch_tables(b, p->cap_stream))) return bail(rc);
+    if ((rc = rs::upload_batch_tables(b, p->cap_stream, nullptr))) return bail(rc);
     if (hipStreamSynchronize(p->cap_stream) != hipSuccess) return bail(rs::fail(RS_EDEVICE, "table upload failed"));
     // capture: every phase, no host read in between
     if (hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
