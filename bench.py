@@ -315,6 +315,7 @@ def main():
             torch.cuda.synchronize()
             tb = time.perf_counter()
             b = recsplit.build(small, 8, 100)
+            torch.cuda.synchronize()  # until the blob is complete (the call returns before its last kernels end)
             dt = time.perf_counter() - tb
             b.free()
             if i >= 3:

@@ -2728,20 +2728,28 @@ uint32_t lds_bucket_limit(Batch& b);
 // Largest bucket that n keys in nb buckets exceed with probability below
 // 1e-6: a bucket's count is Binomial(n, 1/nb), bounded by the heavier-tailed
 // Poisson(n / nb); the tail is summed downward from far above the mean.
+// The last (n, nb) of the calling thread is remembered: repeated builds of
+// one shape skip the sum.
 uint32_t bucket_size_cap(uint64_t n, uint64_t nb) {
+    thread_local uint64_t last_n = 0, last_nb = 0;
+    thread_local uint32_t last_cap = 0;
+    if (n == last_n && nb == last_nb && last_cap) return last_cap;
     const double lam = (double)n / (double)nb, target = 1e-6 / (double)nb;
     const uint64_t k0 = (uint64_t)lam;
     const uint64_t kmax = k0 + (uint64_t)(20.0 * std::sqrt(lam + 1.0)) + 40;
     std::vector<double> pmf(kmax - k0 + 1);
-    double lp = (double)k0 * std::log(lam) - lam - std::lgamma((double)k0 + 1.0);
-    for (uint64_t k = k0; k <= kmax; k++) {
-        pmf[k - k0] = std::exp(lp);
-        lp += std::log(lam) - std::log((double)k + 1.0);
+    double p = std::exp((double)k0 * std::log(lam) - lam - std::lgamma((double)k0 + 1.0));
+    for (uint64_t k = k0; k <= kmax; k++) {  // pmf(k + 1) = pmf(k) lam / (k + 1)
+        pmf[k - k0] = p;
+        p *= lam / (double)(k + 1);
     }
     double tail = 0;  // P(X > c)
     uint64_t c = kmax;
     while (c > k0 && tail + pmf[c - k0] < target) tail += pmf[c-- - k0];
-    return (uint32_t)std::min<uint64_t>(std::max<uint64_t>(c, 1), n);
+    last_cap = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(c, 1), n);
+    last_n = n;
+    last_nb = nb;
+    return last_cap;
 }
 
 // maxm_hint: 0 = size the tables and the search's LDS for a bucket-size cap
@@ -2905,9 +2913,23 @@ void plan_release(rs_plan* p) {
 }
 
 // Largest bucket of which the search still fits the LDS with the tables of
-// this batch (binary search over the dynamic LDS the launch would ask for).
+// this batch (binary search over the dynamic LDS the launch would ask for;
+// remembered per kernel and table sets, as the search takes ~60 us of host
+// time, which a small build would wait for).
 uint32_t lds_bucket_limit(Batch& b) {
     SearchKernel k = search_kernel(b.max_leaf, b.launch_waves, b.wide);
+    struct Known {
+        SearchKernel k;
+        std::vector<TabKey> keys;
+        uint32_t limit;
+    };
+    static std::mutex mu;
+    static std::vector<Known> known;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        for (const Known& e : known)
+            if (e.k == k && e.keys == b.tab_keys) return e.limit;
+    }
     size_t static_bytes = 0;
     if (static_lds(reinterpret_cast<const void*>(k), &static_bytes)) return 0;
     const size_t avail = (size_t)max_lds_bytes() - static_bytes;
@@ -2923,6 +2945,8 @@ uint32_t lds_bucket_limit(Batch& b) {
         if ((size_t)mid * 8 + (size_t)nodes * 16 <= avail) lo = mid;
         else hi = mid - 1;
     }
+    std::lock_guard<std::mutex> lk(mu);
+    if (known.size() < 256) known.push_back(Known{k, b.tab_keys, lo});
     return lo;
 }
 
