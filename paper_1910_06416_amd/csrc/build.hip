@@ -31,16 +31,20 @@ constexpr int kBlock = 256;
 constexpr int kScanItems = 8;
 constexpr int kScanTile = kBlock * kScanItems;
 
-// Status words of a call and n zeroed counters.
-__global__ void k_reset(DevStatus* st, unsigned long long* counters, uint64_t n) {
-    uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i == 0) {
+// Status words of a call and n zeroed counters; and in_words words of the
+// call's bases and descriptors read from pinned host memory (in_words = 0
+// when a copy brought them).
+__global__ void k_reset(DevStatus* st, unsigned long long* counters, uint64_t n, uint64_t* __restrict__ in_dst,
+                        const uint64_t* __restrict__ in_src, uint64_t in_words) {
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x, step = (uint64_t)gridDim.x * blockDim.x;
+    if (t == 0) {
         st->maxm = 0;
         st->flags = 0;
         st->delta_s = ~0ull;
         st->delta_z = 0x7fffffffffffffffll;
     }
-    for (; i < n; i += (uint64_t)gridDim.x * blockDim.x) counters[i] = 0;
+    for (uint64_t i = t; i < n; i += step) counters[i] = 0;
+    for (uint64_t i = t; i < in_words; i += step) in_dst[i] = in_src[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -1947,7 +1951,8 @@ void* pinned(size_t bytes, Staging& st = g_staging) {
     if (st.cap < bytes) {
         if (st.p) (void)hipHostFree(st.p);
         size_t want = std::max<size_t>(bytes, 1 << 16);
-        if (hipHostMalloc(&st.p, want, hipHostMallocMapped) != hipSuccess) {  // (read by k_copy_words)
+        // mapped and coherent: kernels read it directly (k_reset, k_copy_words)
+        if (hipHostMalloc(&st.p, want, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
             st.p = nullptr;
             st.cap = 0;
             return nullptr;
@@ -2484,12 +2489,16 @@ void batch_bind(Batch& b, char* ws, char* pin) {
 
 // Descriptors in, signatures, sort into bucket order (bstart, sorted keys,
 // largest bucket in d_st->maxm).  The descriptors are uploaded from h_desc.
-int enqueue_front(Batch& b, hipStream_t s, PhaseEvents* pe) {
+// in_src: null, or the device address of the pinned staging, from which the
+// first kernel reads the bases and descriptors (a copy would add the host's
+// time in the copy call before that kernel can start).
+int enqueue_front(Batch& b, hipStream_t s, PhaseEvents* pe, const void* in_src) {
     const uint32_t K = b.K;
     if (pe) pe->record(0, s);
-    RS_ENQ(hipMemcpyAsync(b.d_kb, b.h_kb, b.io_in, hipMemcpyHostToDevice, s));
-    const uint64_t ncnt = (uint64_t)b.nbins * b.nxcd;
-    RS_LAUNCH(k_reset, grid_for(ncnt, kBlock * 4), kBlock, 0, s, b.d_st, b.d_bincnt, ncnt);
+    if (!in_src) RS_ENQ(hipMemcpyAsync(b.d_kb, b.h_kb, b.io_in, hipMemcpyHostToDevice, s));
+    const uint64_t ncnt = (uint64_t)b.nbins * b.nxcd, in_words = in_src ? b.io_in / 8 : 0;
+    RS_LAUNCH(k_reset, grid_for(std::max(ncnt, in_words), kBlock * 4), kBlock, 0, s, b.d_st, b.d_bincnt, ncnt,
+              b.d_kb, static_cast<const uint64_t*>(in_src), in_words);
     RS_LAUNCH(k_signature, grid_for(b.total, kSigTile), kBlock, b.nbins * 4, s, b.d_desc, b.d_desc, b.d_kb, K,
               b.total, b.d_lo, b.d_bid, b.shift, b.nbins, b.nxcd, b.d_bincnt);
     if (pe) pe->record(1, s);
@@ -2792,8 +2801,10 @@ int build_batch_impl(const rs_keys* sets, uint32_t count, const uint32_t* leafs,
     char* pin = (char*)pinned(b.pin_bytes);
     if (!pin) return cleanup(fail(RS_ENOMEM, "pinned host allocation failed"));
     batch_bind(b, ws, pin);
+    void* pin_dev = nullptr;  // the bases and descriptors go in through k_reset
+    RS_TRY(hipHostGetDevicePointer(&pin_dev, pin, 0));
 
-    if (int rc = enqueue_front(b, s, &pe)) return cleanup(rc);
+    if (int rc = enqueue_front(b, s, &pe, pin_dev)) return cleanup(rc);
     uint32_t maxm = maxm_hint;
     const bool capped = !tune && !maxm_hint;
     if (capped) {
@@ -3026,7 +3037,7 @@ extern "C" int rs_plan_create(const rs_keys* sets, uint32_t count, const uint32_
     // capture: every phase, no host read in between
     if (hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
         return bail(rs::fail(RS_EDEVICE, "hipStreamBeginCapture failed"));
-    int crc = rs::enqueue_front(b, p->cap_stream, nullptr);
+    int crc = rs::enqueue_front(b, p->cap_stream, nullptr, nullptr);
     if (!crc) crc = rs::enqueue_back(b, p->cap_stream, nullptr);
     if (!crc) crc = rs::enqueue_fill(b, p->arena, p->capacity, p->capacity, p->cap_stream);
     if (!crc) crc = rs::enqueue_readback(b, p->cap_stream);
@@ -3201,7 +3212,7 @@ extern "C" int rs_build_noalloc(const rs_keys* keys, uint32_t leaf, uint32_t buc
     if (b.pin_bytes > sizeof g_na_host) return fail(RS_EINVAL, "host staging too small");
     batch_bind(b, base, g_na_host);
     // front: signatures and bucket order, then the largest bucket
-    if (int rc = enqueue_front(b, s, nullptr)) return rc;
+    if (int rc = enqueue_front(b, s, nullptr, nullptr)) return rc;
     RS_HIP(hipMemcpyAsync(b.h_st, b.d_st, sizeof(DevStatus), hipMemcpyDeviceToHost, s));
     RS_HIP(hipStreamSynchronize(s));
     const uint32_t maxm = b.h_st->maxm;
