@@ -198,6 +198,12 @@ typedef struct {
     double ms_fill;       /* Elias-Fano bits and Golomb-Rice streams */
     double ms_device;     /* first to last event */
     uint64_t n, nb, maxm, tree_bits, blob_bytes;
+    uint64_t arena_bytes; /* device memory the blob lives in: blob_bytes when the
+                             arena was sized after the search; larger when a single
+                             build of a shape seen before on this thread filled an
+                             arena guessed from it, before the call's one wait */
+    uint64_t refills;     /* 1 if the guessed arena was too small and the blob was
+                             filled again into an exact one */
 } rs_build_stats;
 
 int rs_last_build_stats(rs_build_stats* out);
@@ -212,7 +218,12 @@ int rs_last_build_stats(rs_build_stats* out);
  *            bucket-size cap estimated from n and b (a bucket count is
  *            exceeded with probability below 1e-6); if a bucket is larger
  *            (skewed keys), the construction runs again sized for the
- *            largest bucket, with the same result.
+ *            largest bucket, with the same result.  When the calling thread
+ *            has built this (leaf, bucket) shape before, the blob is written
+ *            before that wait into memory sized from the earlier build (with
+ *            a 1/8 margin; the environment variable RS_ARENA_GUESS scales it,
+ *            0 turns it off); a blob that does not fit is written again after
+ *            the wait into memory of its exact size.
  *   out    : receives the new blob; its device bytes are valid once the stream
  *            reaches the end of the enqueued work.
  * Errors: RS_EINVAL, RS_EDUPLICATE, RS_ENOMEM, RS_EDEVICE, RS_ESEARCH. */

@@ -2761,6 +2761,44 @@ uint32_t bucket_size_cap(uint64_t n, uint64_t nb) {
     return last_cap;
 }
 
+// Blob words per key of the calling thread's last single build of each
+// shape.  A later single build of that shape enqueues its fill into an arena
+// of n times that (with a margin) before its one wait on the stream, rather
+// than waiting for the exact sizes and then filling: the host's wake-up and
+// two launches leave the critical path.  A blob beyond the guessed arena is
+// flagged by k_set_blobs, and after the wait it is filled again into an
+// arena of the exact size (same bytes).  RS_ARENA_GUESS scales the margin
+// (0: never guess), read at each call.
+struct ArenaMemo {
+    uint32_t leaf = 0, bucket = 0, gr_max = 0, slack = 0;
+    double words_per_key = 0;
+};
+thread_local ArenaMemo g_arena_memo;
+
+uint64_t arena_guess(const Batch& b) {
+    if (b.K != 1) return 0;
+    const BuildDesc& d = b.hd[0];
+    const ArenaMemo& m = g_arena_memo;
+    if (m.words_per_key <= 0 || m.leaf != d.leaf || m.bucket != d.bucket || m.gr_max != d.gr_max ||
+        m.slack != d.slack)
+        return 0;
+    double scale = 1.125;
+    if (const char* e = std::getenv("RS_ARENA_GUESS"); e && *e) scale = std::atof(e);
+    if (!(scale > 0)) return 0;
+    return (uint64_t)std::ceil((double)d.n * m.words_per_key * scale) + 256;
+}
+
+void arena_remember(const Batch& b) {
+    if (b.K != 1 || b.h_boff[1] == 0) return;
+    const BuildDesc& d = b.hd[0];
+    ArenaMemo& m = g_arena_memo;
+    m.leaf = d.leaf;
+    m.bucket = d.bucket;
+    m.gr_max = d.gr_max;
+    m.slack = d.slack;
+    m.words_per_key = (double)b.h_boff[1] / (double)d.n;
+}
+
 // maxm_hint: 0 = size the tables and the search's LDS for a bucket-size cap
 // estimated from the key and bucket counts, so that the call waits on its
 // stream only once (for the blob sizes); if a bucket exceeds the cap, the call
@@ -2832,6 +2870,13 @@ int build_batch_impl(const rs_keys* sets, uint32_t count, const uint32_t* leafs,
         return cleanup(trc);
     }
     if (int rc = enqueue_back(b, s, &pe)) return cleanup(rc);
+    const uint64_t guess = arena_guess(b);
+    if (guess) {
+        if (int rc = al.get((void**)&d_blob, guess * 8, s)) return cleanup(rc);
+        if (int rc = enqueue_fill(b, d_blob, guess, guess, s)) return cleanup(rc);
+        pe.record(6, s);
+        RS_TRACE("fill enqueued into a guessed arena of %llu words", (unsigned long long)guess);
+    }
     if (int rc = enqueue_readback(b, s)) return cleanup(rc);
     RS_TRACE("search enqueued (class %u); waiting for the sizes", b.max_leaf);
     RS_TRY(hipStreamSynchronize(s));
@@ -2844,17 +2889,28 @@ int build_batch_impl(const rs_keys* sets, uint32_t count, const uint32_t* leafs,
             pinned_release(s);
             al.put(ws, s);
             al.put(b.d_tab, s);
+            al.put(d_blob, s);
             return build_batch_impl(sets, count, leafs, buckets, opts, s, outs, statuses, nullptr, exact);
         }
     }
     collect_status(b);
     const uint64_t arena_words = b.h_boff[b.K];
     RS_TRACE("sizes known (%llu blob words)", (unsigned long long)arena_words);
-    if (arena_words) {
-        if (int rc = al.get((void**)&d_blob, arena_words * 8, s)) return cleanup(rc);
-        if (int rc = enqueue_fill(b, d_blob, arena_words, arena_words, s)) return cleanup(rc);
+    arena_remember(b);
+    uint64_t arena_cap = guess;
+    uint32_t refills = 0;
+    if (!arena_words || arena_words > guess) {  // no guess, or a blob beyond it: fill an exact arena
+        refills = guess && arena_words ? 1 : 0;
+        if (refills) RS_TRACE("the guessed arena is too small; filled again");
+        al.put(d_blob, s);
+        d_blob = nullptr;
+        arena_cap = arena_words;
+        if (arena_words) {
+            if (int rc = al.get((void**)&d_blob, arena_words * 8, s)) return cleanup(rc);
+            if (int rc = enqueue_fill(b, d_blob, arena_words, arena_words, s)) return cleanup(rc);
+        }
+        pe.record(6, s);
     }
-    pe.record(6, s);
     if (timing) {
         RS_TRY(hipStreamSynchronize(s));
         g_stats.ms_signature = pe.ms(0, 1);
@@ -2869,6 +2925,8 @@ int build_batch_impl(const rs_keys* sets, uint32_t count, const uint32_t* leafs,
         g_stats.tree_bits = 0;
         for (uint32_t j = 0; j < b.K; j++) g_stats.tree_bits += b.h_desc[j].total_bits;
         g_stats.blob_bytes = arena_words * 8;
+        g_stats.arena_bytes = arena_cap * 8;
+        g_stats.refills = refills;
         g_stats_valid = true;
     }
     make_blobs(b, d_blob, b.d_tab, b.stride, al, s, outs);

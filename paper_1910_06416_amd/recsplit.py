@@ -57,7 +57,8 @@ class rs_build_stats(ctypes.Structure):
     _fields_ = [("ms_signature", ctypes.c_double), ("ms_scatter", ctypes.c_double), ("ms_search", ctypes.c_double),
                 ("ms_offsets", ctypes.c_double), ("ms_fill", ctypes.c_double), ("ms_device", ctypes.c_double),
                 ("n", ctypes.c_uint64), ("nb", ctypes.c_uint64), ("maxm", ctypes.c_uint64),
-                ("tree_bits", ctypes.c_uint64), ("blob_bytes", ctypes.c_uint64)]
+                ("tree_bits", ctypes.c_uint64), ("blob_bytes", ctypes.c_uint64), ("arena_bytes", ctypes.c_uint64),
+                ("refills", ctypes.c_uint64)]
 
 
 class rs_server_stats(ctypes.Structure):

@@ -80,6 +80,31 @@ def test_blob_parity_cfg_100k_l8_b100(rs, orc):
     assert 1.78 <= 8 * len(want) / 100_000 <= 1.82
 
 
+def test_guessed_arena_and_its_refill(rs, orc, monkeypatch):
+    """A single build of a shape this thread built before fills an arena
+    guessed from that build before the call's one wait; a guess that is too
+    small (RS_ARENA_GUESS scales it) is filled again into an exact arena.
+    Every path gives the oracle's bytes."""
+    keys = inputs.u64_keys(100_000, 31)
+    want = orc.build(keys, 8, 100)
+    dk = rs.device_keys(keys)
+    paths = []
+    for scale in ("0", None, None, "0.25", "0"):  # exact (and remembered), guessed twice, refilled, exact
+        if scale is None:
+            monkeypatch.delenv("RS_ARENA_GUESS", raising=False)
+        else:
+            monkeypatch.setenv("RS_ARENA_GUESS", scale)
+        print(f"case guessed arena, scale {scale}", flush=True)
+        blob = rs.build(dk, 8, 100, timing=True)
+        st = rs.last_build_stats()
+        got = blob.to_bytes()
+        blob.free()
+        assert got == want, _first_difference(got, want, orc)
+        assert st["blob_bytes"] >= len(want)  # (the arena rounds each blob up to 256 bytes)
+        paths.append((st["arena_bytes"] > st["blob_bytes"], int(st["refills"])))
+    assert paths == [(False, 0), (True, 0), (True, 0), (False, 1), (False, 0)]
+
+
 @pytest.mark.parametrize("n,leaf,bucket", [(1, 8, 100), (777, 8, 100), (100_000, 8, 100), (5000, 6, 50)])
 def test_blob_parity_strings(rs, orc, n, leaf, bucket):
     _check_build(rs, orc, inputs.ascii_keys(n, 2000 + n), leaf, bucket)
