@@ -108,6 +108,7 @@ constexpr uint32_t kMaxBins = 4096;
 constexpr uint32_t kMaxBinShift = 16;              // at most 65536 buckets per bin (eight pieces)
 constexpr uint32_t kSortSpan = 8192;               // buckets a per-bin sort counts at once in LDS
 constexpr uint32_t kSortBlock = 512;               // threads of the per-bin sort
+constexpr uint32_t kSortItems = 8;                 // keys a thread of the sort loads at once
 
 // dynamic LDS: nbins u32 counters
 __global__ __launch_bounds__(kBlock) void k_signature(const BuildDesc* __restrict__ descs, BuildDesc* __restrict__ wdescs,
@@ -393,9 +394,18 @@ __global__ __launch_bounds__(kSortBlock) void k_bucket_sort(const uint64_t* __re
         const uint32_t first = (uint32_t)(g0 + sub);  // global number of the piece's first bucket
         for (uint32_t j = tid; j < len; j += kSortBlock) cnt[j] = 0;
         __syncthreads();
-        for (uint64_t i = s + tid; i < e; i += kSortBlock) {
-            const uint32_t b = bin_bid[i] - first;  // wraps above len for buckets outside the piece
-            if (b < len) atomicAdd(&cnt[b], 1u);
+        // keys are taken kSortItems per thread at a time, every load issued
+        // before the first use (a loop of one key per step waits on each)
+        for (uint64_t i0 = s + tid; i0 < e; i0 += (uint64_t)kSortItems * kSortBlock) {
+            uint32_t b[kSortItems];
+#pragma unroll
+            for (uint32_t u = 0; u < kSortItems; u++) {
+                const uint64_t i = i0 + (uint64_t)u * kSortBlock;
+                b[u] = i < e ? bin_bid[i] - first : ~0u;  // wraps above len for buckets outside the piece
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < kSortItems; u++)
+                if (b[u] < len) atomicAdd(&cnt[b[u]], 1u);
         }
         __syncthreads();
         // exclusive scan of cnt[0, len): each thread sums a chunk, the block scans the chunk sums
@@ -430,9 +440,18 @@ __global__ __launch_bounds__(kSortBlock) void k_bucket_sort(const uint64_t* __re
         __syncthreads();
         for (uint32_t j = tid; j < len; j += kSortBlock) cnt[j] = 0;
         __syncthreads();
-        for (uint64_t i = s + tid; i < e; i += kSortBlock) {
-            const uint32_t b = bin_bid[i] - first;
-            if (b < len) sorted[base + offs[b] + atomicAdd(&cnt[b], 1u)] = bin_lo[i];
+        for (uint64_t i0 = s + tid; i0 < e; i0 += (uint64_t)kSortItems * kSortBlock) {
+            uint32_t b[kSortItems];
+            uint64_t lo[kSortItems];
+#pragma unroll
+            for (uint32_t u = 0; u < kSortItems; u++) {
+                const uint64_t i = i0 + (uint64_t)u * kSortBlock;
+                b[u] = i < e ? bin_bid[i] - first : ~0u;
+                lo[u] = i < e ? bin_lo[i] : 0;
+            }
+#pragma unroll
+            for (uint32_t u = 0; u < kSortItems; u++)
+                if (b[u] < len) sorted[base + offs[b[u]] + atomicAdd(&cnt[b[u]], 1u)] = lo[u];
         }
         base += piece_total;
         __syncthreads();
@@ -525,19 +544,36 @@ __global__ __launch_bounds__(kBlock) void k_bin_offsets(const unsigned long long
                                                        uint32_t nbins, uint32_t nxcd,
                                                        uint64_t* __restrict__ bin_start,
                                                        unsigned long long* __restrict__ bin_cur) {
+    // each thread takes kBinItems consecutive counters per round: their loads
+    // are independent (one memory round trip, not one per kBlock counters)
+    constexpr uint32_t kBinItems = 16;
     __shared__ uint64_t carry_s;
     if (threadIdx.x == 0) carry_s = 0;
     __syncthreads();
     const uint32_t n = nbins * nxcd;
-    for (uint32_t base = 0; base < n; base += kBlock) {
-        const uint32_t i = base + threadIdx.x;
-        const uint64_t v = i < n ? bin_cnt[i] : 0;
+    for (uint32_t base = 0; base < n; base += kBlock * kBinItems) {
+        const uint32_t i0 = base + threadIdx.x * kBinItems;
+        uint64_t v[kBinItems], sum = 0;
+#pragma unroll
+        for (uint32_t k = 0; k < kBinItems; k++) {
+            v[k] = i0 + k < n ? bin_cnt[i0 + k] : 0;
+            sum += v[k];
+        }
         uint64_t tot;
-        const uint64_t ex = block_exclusive_sum(v, &tot);
         const uint64_t carry = carry_s;
-        if (i < n) {
-            bin_cur[i] = carry + ex;
-            if (i % nxcd == 0) bin_start[i / nxcd] = carry + ex;
+        uint64_t run = carry + block_exclusive_sum(sum, &tot);
+        uint32_t bin = i0 / nxcd, x = i0 % nxcd;
+#pragma unroll
+        for (uint32_t k = 0; k < kBinItems; k++) {
+            if (i0 + k < n) {
+                bin_cur[i0 + k] = run;
+                if (x == 0) bin_start[bin] = run;
+            }
+            run += v[k];
+            if (++x == nxcd) {
+                x = 0;
+                bin++;
+            }
         }
         __syncthreads();
         if (threadIdx.x == 0) carry_s = carry + tot;
