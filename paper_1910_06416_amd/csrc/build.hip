@@ -1,11 +1,11 @@
 // Construction of a RecSplit structure on the GPU (Sec. 4-7 of the paper).
 //
 // Pipeline for one or many independent builds at once, all on the caller's
-// stream: signatures + bucket histogram -> exclusive scan (prefix sums s_i) ->
-// scatter into bucket-contiguous order -> seed search (a persistent grid, one
-// workgroup per bucket, one lane per candidate index) -> scan of bucket bit
-// lengths (offsets o_i) -> Elias-Fano minimum gaps per build -> [host: blob
-// geometry] -> Elias-Fano bits + Golomb-Rice streams written into the blobs.
+// stream: signatures + bin histogram -> bin offsets -> scatter into bin order
+// -> per-bin bucket sort (prefix sums s_i, keys in bucket order) -> seed search
+// (one workgroup per bucket, one lane per candidate index) -> scan of bucket
+// bit lengths (offsets o_i) -> Elias-Fano minimum gaps per build -> blob
+// geometry -> Elias-Fano bits + Golomb-Rice streams written into the blobs.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>

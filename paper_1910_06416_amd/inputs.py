@@ -39,26 +39,31 @@ def u64_keys_raw(n: int, seed: int) -> np.ndarray:
 
 def ascii_keys(n: int, seed: int, min_len: int = 8, max_len: int = 32):
     """n distinct random strings of printable ASCII (0x21..0x7e), lengths
-    uniform in [min_len, max_len].  Returns (data uint8[], offsets uint64[n+1])."""
+    uniform in [min_len, max_len] (max_len < 65536).  Returns (data uint8[],
+    offsets uint64[n+1])."""
+    assert 0 <= min_len <= max_len < 65536
     rng = _rng(seed)
-    width = max_len + 1
-    rows = np.zeros((0, width), dtype=np.uint8)
-    while rows.shape[0] < n:
-        need = n - rows.shape[0]
+    lens_all = np.zeros(0, dtype=np.int64)
+    chars_all = np.zeros((0, max_len), dtype=np.uint8)
+    while len(lens_all) < n:
+        need = n - len(lens_all)
         lens = rng.integers(min_len, max_len + 1, size=need, dtype=np.int64)
         chars = rng.integers(0x21, 0x7F, size=(need, max_len), dtype=np.uint8)
         chars[np.arange(max_len)[None, :] >= lens[:, None]] = 0
-        new = np.concatenate([lens.astype(np.uint8)[:, None], chars], axis=1)
-        rows = np.concatenate([rows, new])
-        view = np.ascontiguousarray(rows).view(np.dtype((np.void, width))).ravel()
+        lens_all = np.concatenate([lens_all, lens])
+        chars_all = np.concatenate([chars_all, chars])
+        # distinct strings, first occurrences kept in draw order (the length is
+        # part of the row: trailing zero bytes belong to no string)
+        rows = np.concatenate([lens_all.astype("<u2").view(np.uint8).reshape(-1, 2), chars_all], axis=1)
+        view = np.ascontiguousarray(rows).view(np.dtype((np.void, max_len + 2))).ravel()
         _, first = np.unique(view, return_index=True)
-        rows = rows[np.sort(first)]
-    rows = rows[:n]
-    lens = rows[:, 0].astype(np.uint64)
+        keep = np.sort(first)
+        lens_all, chars_all = lens_all[keep], chars_all[keep]
+    lens = lens_all[:n].astype(np.uint64)
     offsets = np.zeros(n + 1, dtype=np.uint64)
     np.cumsum(lens, out=offsets[1:])
     mask = np.arange(max_len)[None, :] < lens[:, None].astype(np.int64)
-    data = rows[:, 1:][mask]
+    data = chars_all[:n][mask]
     return np.ascontiguousarray(data, dtype=np.uint8), offsets
 
 

@@ -110,6 +110,26 @@ def test_blob_parity_strings(rs, orc, n, leaf, bucket):
     _check_build(rs, orc, inputs.ascii_keys(n, 2000 + n), leaf, bucket)
 
 
+def test_blob_parity_strings_long_and_mixed(rs, orc):
+    """Strings of 8-32 bytes mixed with 2% of 33-1,500 bytes at random places
+    (groups of a wavefront's strings that overflow the LDS staging take the
+    direct reads), and a buffer whose length is not a multiple of 8 (its last
+    word is partial)."""
+    rng = np.random.default_rng(4242)
+    sd, so = inputs.ascii_keys(20_000, 4243, 8, 32)
+    ld, lo = inputs.ascii_keys(400, 4244, 33, 1500)
+    strings = [sd[so[i]:so[i + 1]].tobytes() for i in range(len(so) - 1)]
+    strings += [ld[lo[i]:lo[i + 1]].tobytes() for i in range(len(lo) - 1)]
+    strings = [strings[i] for i in rng.permutation(len(strings))]
+    total = sum(len(x) for x in strings)
+    strings.append(b"tail!" if (total + 5) % 8 else b"tail!!")
+    offs = np.zeros(len(strings) + 1, dtype=np.uint64)
+    offs[1:] = np.cumsum([len(x) for x in strings])
+    assert int(offs[-1]) % 8
+    data = np.frombuffer(b"".join(strings), dtype=np.uint8)
+    _check_build(rs, orc, (data, offs), 8, 100)
+
+
 def test_blob_parity_strings_unaligned_and_short(rs, orc):
     import torch
 
