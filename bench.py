@@ -565,6 +565,7 @@ def bench_serve(args, requests, load, tuned=None):
     for j in range(R):
         r = tickets[j] if isinstance(tickets[j], dict) else srv.wait(tickets[j])
         assert r["status"] == 0
+        tickets[j] = r
         if j not in done_blobs:
             done_blobs[j] = r["blob"]
         lat.append(r["latency_ms"])
@@ -607,6 +608,10 @@ def bench_serve(args, requests, load, tuned=None):
                    "stats": stats},
         "plain": {"makespan_s": plain_s, "p50_ms": percentile(plat, 50), "p99_ms": percentile(plat, 99),
                   "keys_per_s": total / plain_s},
+        "requests": [{"n": int(sizes[i]), "leaf": int(leafs[i]), "bucket": int(buckets[i]),
+                      "arrival_s": float(arrivals[i]), "served_ms": float(lat[i]),
+                      "served_batch": int(tickets[i]["batch_size"]) if isinstance(tickets[i], dict) else None,
+                      "plain_ms": float(plat[i])} for i in range(R)],
         "bits_per_key": bits,
         "schedules": schedules if tuned else "built-in",
     }

@@ -363,11 +363,12 @@ int rs_server_create(uint64_t hbm_budget_bytes, uint32_t build_workers, const rs
 
 /* Server configuration for rs_server_create_ex.
  *   hbm_budget_bytes, build_workers: as for rs_server_create.
- *   lookup_cus: compute units the build streams never use (a CU mask on
- *     every build worker's stream), taken evenly from every XCD; lookups run
- *     on all CUs and so always find these free, even when every other CU
- *     runs long seed-search workgroups.  0 = none; at most the CU count of
- *     one XCD (32 on MI355X), best a multiple of the XCD count (8). */
+ *   lookup_cus: compute units that heavy builds (a modelled search of 0.25 s
+ *     or more) never use (a CU mask on the stream they run on), taken evenly
+ *     from every XCD; lookups and light builds run on all CUs and so always
+ *     find these free, even when every other CU runs long seed-search
+ *     workgroups.  0 = none; at most the CU count of one XCD (32 on
+ *     MI355X), best a multiple of the XCD count (8). */
 typedef struct {
     uint64_t hbm_budget_bytes;
     uint32_t build_workers;

@@ -12,8 +12,12 @@
 // whose modelled search time reaches kHeavySeconds is heavy: at most one
 // batch with a heavy request is on the device at a time (two such searches
 // sharing the compute units would each take about twice as long, which only
-// delays both), while light requests start beside it.  A lookup worker runs
-// lookup requests on its own stream.  All streams have the default priority.
+// delays both), while light requests start beside it.  A heavy search's
+// workgroups take every CU they can get for seconds, so work launched beside
+// it waits for CUs; with lookup_cus set, heavy batches run on a stream whose
+// CU mask leaves that many CUs out, and light batches and lookups, on streams
+// over every CU, always find those free.  A lookup worker runs lookup
+// requests on its own stream.  All streams have the default priority.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -100,13 +104,14 @@ void finish(rs_server* s, const Request& r, int status, rs_blob* blob, uint32_t 
 
 void build_worker(rs_server* s) {
     (void)hipSetDevice(s->device);
-    hipStream_t stream = nullptr;
-    if (!s->build_mask.empty()) {
-        if (hipExtStreamCreateWithCUMask(&stream, (uint32_t)s->build_mask.size(), s->build_mask.data()) != hipSuccess)
-            stream = nullptr;
-    } else if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) {
-        stream = nullptr;
-    }
+    // light batches on a stream over every CU; heavy ones, when CUs are kept
+    // free of them, on a second stream whose CU mask leaves those out
+    hipStream_t stream = nullptr, heavy_stream = nullptr;
+    if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) stream = nullptr;
+    if (!s->build_mask.empty() &&
+        hipExtStreamCreateWithCUMask(&heavy_stream, (uint32_t)s->build_mask.size(), s->build_mask.data()) !=
+            hipSuccess)
+        heavy_stream = nullptr;
     for (;;) {
         std::vector<Request> batch;
         uint64_t bytes = 0;
@@ -171,9 +176,10 @@ void build_worker(rs_server* s) {
             leafs[i] = batch[i].leaf;
             buckets[i] = batch[i].bucket;
         }
-        int rc = rs_build_batch(sets.data(), count, leafs.data(), buckets.data(), &s->opts, stream, outs.data(),
+        hipStream_t st = batch_heavy && heavy_stream ? heavy_stream : stream;
+        int rc = rs_build_batch(sets.data(), count, leafs.data(), buckets.data(), &s->opts, st, outs.data(),
                                 status.data());
-        if (hipStreamSynchronize(stream) != hipSuccess) rc = RS_EDEVICE;
+        if (hipStreamSynchronize(st) != hipSuccess) rc = RS_EDEVICE;
         {
             std::lock_guard<std::mutex> lk(s->mu);
             for (uint32_t i = 0; i < count; i++) {
@@ -189,6 +195,7 @@ void build_worker(rs_server* s) {
         s->cv_done.notify_all();
     }
     if (stream) (void)hipStreamDestroy(stream);
+    if (heavy_stream) (void)hipStreamDestroy(heavy_stream);
 }
 
 void lookup_worker(rs_server* s) {
