@@ -219,8 +219,9 @@ int rs_last_build_stats(rs_build_stats* out);
  *            exceeded with probability below 1e-6); if a bucket is larger
  *            (skewed keys), the construction runs again sized for the
  *            largest bucket, with the same result.  When the calling thread
- *            has built this (leaf, bucket) shape before, the blob is written
- *            before that wait into memory sized from the earlier build (with
+ *            has built this (leaf, bucket) shape before, with a key count
+ *            within a factor of two, the blob is written before that wait
+ *            into memory sized from the earlier build (with
  *            a 1/8 margin; the environment variable RS_ARENA_GUESS scales it,
  *            0 turns it off); a blob that does not fit is written again after
  *            the wait into memory of its exact size.

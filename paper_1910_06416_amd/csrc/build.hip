@@ -2798,8 +2798,10 @@ uint32_t bucket_size_cap(uint64_t n, uint64_t nb) {
 }
 
 // Blob words per key of the calling thread's last single build of each
-// shape.  A later single build of that shape enqueues its fill into an arena
-// of n times that (with a margin) before its one wait on the stream, rather
+// shape.  A later single build of that shape and of a similar key count
+// (within a factor of two: small sets spend more words per key on the header
+// and the index) enqueues its fill into an arena of n times that (with a
+// margin) before its one wait on the stream, rather
 // than waiting for the exact sizes and then filling: the host's wake-up and
 // two launches leave the critical path.  A blob beyond the guessed arena is
 // flagged by k_set_blobs, and after the wait it is filled again into an
@@ -2807,6 +2809,7 @@ uint32_t bucket_size_cap(uint64_t n, uint64_t nb) {
 // (0: never guess), read at each call.
 struct ArenaMemo {
     uint32_t leaf = 0, bucket = 0, gr_max = 0, slack = 0;
+    uint64_t n = 0;
     double words_per_key = 0;
 };
 thread_local ArenaMemo g_arena_memo;
@@ -2816,7 +2819,7 @@ uint64_t arena_guess(const Batch& b) {
     const BuildDesc& d = b.hd[0];
     const ArenaMemo& m = g_arena_memo;
     if (m.words_per_key <= 0 || m.leaf != d.leaf || m.bucket != d.bucket || m.gr_max != d.gr_max ||
-        m.slack != d.slack)
+        m.slack != d.slack || d.n > 2 * m.n || 2 * d.n < m.n)
         return 0;
     double scale = 1.125;
     if (const char* e = std::getenv("RS_ARENA_GUESS"); e && *e) scale = std::atof(e);
@@ -2832,6 +2835,7 @@ void arena_remember(const Batch& b) {
     m.bucket = d.bucket;
     m.gr_max = d.gr_max;
     m.slack = d.slack;
+    m.n = d.n;
     m.words_per_key = (double)b.h_boff[1] / (double)d.n;
 }
 
@@ -2906,9 +2910,14 @@ int build_batch_impl(const rs_keys* sets, uint32_t count, const uint32_t* leafs,
         return cleanup(trc);
     }
     if (int rc = enqueue_back(b, s, &pe)) return cleanup(rc);
-    const uint64_t guess = arena_guess(b);
+    uint64_t guess = arena_guess(b);
+    if (guess && al.get((void**)&d_blob, guess * 8, s) != RS_OK) {
+        clear_error();  // no room for a guess: the exact arena after the wait
+        (void)hipGetLastError();
+        d_blob = nullptr;
+        guess = 0;
+    }
     if (guess) {
-        if (int rc = al.get((void**)&d_blob, guess * 8, s)) return cleanup(rc);
         if (int rc = enqueue_fill(b, d_blob, guess, guess, s)) return cleanup(rc);
         pe.record(6, s);
         RS_TRACE("fill enqueued into a guessed arena of %llu words", (unsigned long long)guess);

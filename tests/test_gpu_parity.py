@@ -103,6 +103,18 @@ def test_guessed_arena_and_its_refill(rs, orc, monkeypatch):
         assert st["blob_bytes"] >= len(want)  # (the arena rounds each blob up to 256 bytes)
         paths.append((st["arena_bytes"] > st["blob_bytes"], int(st["refills"])))
     assert paths == [(False, 0), (True, 0), (True, 0), (False, 1), (False, 0)]
+    # a key count more than twice away from the remembered one takes no guess
+    # (a small set spends many more words per key on its header and index)
+    monkeypatch.delenv("RS_ARENA_GUESS", raising=False)
+    for n, guessed in ((500, False), (100_000, False), (100_000, True)):
+        sub = keys[:n]
+        print(f"case guessed arena, n {n}", flush=True)
+        blob = rs.build(rs.device_keys(sub), 8, 100, timing=True)
+        st = rs.last_build_stats()
+        got = blob.to_bytes()
+        blob.free()
+        assert got == orc.build(sub, 8, 100)
+        assert (st["arena_bytes"] > st["blob_bytes"], int(st["refills"])) == (guessed, 0)
 
 
 @pytest.mark.parametrize("n,leaf,bucket", [(1, 8, 100), (777, 8, 100), (100_000, 8, 100), (5000, 6, 50)])
