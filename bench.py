@@ -34,8 +34,9 @@ EVALS_PER_KEY = {(8, 100): 494.0, (12, 1000): 1.39e4, (16, 2000): 8.90e5}
 # (measured), so this is also the number of full-rate VALU slots.
 VALU_SLOTS_PER_EVAL = 18.0
 # HBM bytes of one k_search launch on the 10M-string workload, from rocprofv3
-# FETCH_SIZE (x2.0) / WRITE_SIZE (x1.0), the factors a 1 GiB device copy gives;
-# to be set to None whenever the search kernel changes until re-measured.
+# FETCH_SIZE (x2.0) / WRITE_SIZE (x1.0), the factors a 1 GiB device copy gives
+# (51,438 and 29,034 KiB for the current kernel); to be set to None whenever the
+# search kernel changes until re-measured.
 SEARCH_TRAFFIC_BYTES = 135.0e6
 # VALU lane-instructions that k_lookup_bytes executes per string query (rocprofv3
 # SQ_INSTS_VALU x 64 / queries on the 10M-string workload): lookups are bound by
