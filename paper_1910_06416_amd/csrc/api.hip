@@ -116,6 +116,7 @@ struct LookupArgs {
     const uint32_t* Q;  // output values of a subtree per size (non-minimal structures)
     const uint32_t* S;  // split shape per size: part size | fanout << 16
     const uint32_t* C;  // ceil(2^32 / part size) per size
+    const uint32_t* samples;  // select samples (null: start at the inventory)
     uint64_t nb, beta, delta_s;
     int64_t delta_z;
     uint32_t Ws, Wz;
@@ -275,8 +276,15 @@ __device__ uint64_t rank_of(const LookupArgs& a, uint64_t hi, uint64_t lo) {
     const uint32_t wsz = a.Ws + a.Wz;
     uint64_t start_s, start_z;
     uint32_t k_s, k_z;
-    inventory_start(blob, a, i, 0, start_s, k_s);
-    inventory_start(blob, a, i, 1, start_z, k_z);
+    if (a.samples) {  // (the same for every lane)
+        const uint64_t g = i / kSelectSample;
+        start_s = a.samples[g];
+        start_z = a.samples[select_sample_groups(a.nb + 1) + g];
+        k_s = k_z = (uint32_t)(i % kSelectSample);
+    } else {
+        inventory_start(blob, a, i, 0, start_s, k_s);
+        inventory_start(blob, a, i, 1, start_z, k_z);
+    }
     uint64_t ps, ps1;
     select_pair(us, a.us_words, start_s, k_s, ps, ps1);
     uint64_t ys = ((ps - i) << a.Ws) | get_bits(lower, i * wsz, a.Ws);
@@ -406,7 +414,7 @@ extern "C" int rs_lookup(const rs_blob* blob, const rs_keys* queries, uint64_t* 
     const uint32_t* tab = blob->tables;
     const size_t w = blob->tab_stride;
     LookupArgs a{blob->words, tab, tab + w, tab + 2 * w, tab + 4 * w, tab + 5 * w, tab + 6 * w, tab + 7 * w,
-                 L.nb, L.beta, L.delta_s,
+                 blob->samples, L.nb, L.beta, L.delta_s,
                  L.delta_z, L.Ws, L.Wz, L.lower_off, L.us_off, L.uz_off, L.inv_hi_off, L.inv_lo_off, L.tree_off,
                  L.us_words, L.uz_words, L.tree_words, (uint32_t)L.leaf, st.lower, st.upper, (uint32_t)L.maxm,
                  L.slack};

@@ -76,6 +76,7 @@ struct BuildDesc {
     unsigned long long* blob;  // null: no blob for this build
     uint64_t beta;
     uint64_t lower_off, us_off, uz_off, inv_hi_off, inv_lo_off, tree_off;
+    uint64_t samples_off;  // select samples after the blob in its arena slot (0: none)
     uint32_t Ws, Wz;
 };
 
@@ -1704,6 +1705,13 @@ __device__ __forceinline__ void ef_fill_entry(const FillArgs& a, uint64_t e) {
     const uint64_t ps = (ys >> B.Ws) + i, pz = (yz >> B.Wz) + i;
     or_bits(blob + B.us_off, ps, 1, 1);
     or_bits(blob + B.uz_off, pz, 1, 1);
+    if (B.samples_off && (i & (kSelectSample - 1)) == 0) {
+        // positions below 2^32: an upper-bits array has N ones and at most 2 N zeros
+        uint32_t* smp = reinterpret_cast<uint32_t*>(blob + B.samples_off);
+        const uint64_t groups = select_sample_groups(B.nb + 1);
+        smp[i / kSelectSample] = (uint32_t)ps;
+        smp[groups + i / kSelectSample] = (uint32_t)pz;
+    }
     // two-level inventory (Sec. 7.4), s and z interleaved
     if ((i & ((1u << kInvHi) - 1)) == 0) {
         blob[B.inv_hi_off + 2 * (i >> kInvHi)] = ps;
@@ -1887,9 +1895,11 @@ __device__ uint64_t geometry_of(BuildDesc& d, uint64_t* h) {
     return d.tree_off + tree_words;
 }
 
+// with_samples: each arena slot also holds the build's select samples
+// (select_samples_words after the blob, which is rounded to 256 bytes).
 __global__ __launch_bounds__(kBlock) void k_layout(BuildDesc* __restrict__ descs, uint32_t count,
                                                   uint64_t* __restrict__ hdr, uint64_t* __restrict__ raw_words,
-                                                  uint64_t* __restrict__ off) {
+                                                  uint64_t* __restrict__ off, uint32_t with_samples) {
     __shared__ uint64_t carry_s;
     if (threadIdx.x == 0) carry_s = 0;
     __syncthreads();
@@ -1903,6 +1913,8 @@ __global__ __launch_bounds__(kBlock) void k_layout(BuildDesc* __restrict__ descs
                 raw = geometry_of(d, hdr + (size_t)j * kHeaderWords);
             raw_words[j] = raw;
             w = (raw + 31) & ~uint64_t(31);
+            d.samples_off = with_samples && raw ? w : 0;
+            if (d.samples_off) w += (select_samples_words(d.nb + 1) + 31) & ~uint64_t(31);
         }
         uint64_t tot;
         const uint64_t ex = block_exclusive_sum(w, &tot);
@@ -2313,6 +2325,7 @@ struct Batch {
     std::vector<uint32_t> which;  // desc index -> position in the call
     std::vector<TabKey> tab_keys;  // of each table set
     bool wide = false;             // some build is non-minimal
+    bool samples = true;           // arena slots hold select samples (not in allocation-free builds)
     uint64_t total = 0, nbuckets = 0, seed_cap = kDefaultSeedCap;
     uint32_t wait_limit = kDefaultWaitLimit;
     uint32_t K = 0, max_leaf = 1, launch_waves = 1;
@@ -2640,7 +2653,7 @@ int enqueue_back(Batch& b, hipStream_t s, PhaseEvents* pe) {
     }
     GapArgs ga{b.d_bst, b.d_qst, b.d_ost, b.d_desc, b.d_desc, b.d_bb, b.K, b.nbuckets};
     RS_LAUNCH(k_ef_gaps, grid_for(b.nbuckets, kGapTile), kBlock, 0, s, ga);
-    RS_LAUNCH(k_layout, 1, kBlock, 0, s, b.d_desc, b.K, b.d_hdr, b.d_raw, b.d_boff);
+    RS_LAUNCH(k_layout, 1, kBlock, 0, s, b.d_desc, b.K, b.d_hdr, b.d_raw, b.d_boff, (uint32_t)b.samples);
     if (pe) pe->record(5, s);
     RS_ENQ(hipGetLastError());
     return RS_OK;
@@ -2752,6 +2765,9 @@ void make_blobs(Batch& b, uint64_t* words, uint32_t* tables, uint32_t stride, co
         }
         blob->words = words + b.h_boff[j];
         blob->bytes = b.h_raw[j] * 8;
+        blob->samples = b.h_desc[j].samples_off
+                            ? reinterpret_cast<const uint32_t*>(words + b.h_boff[j] + b.h_desc[j].samples_off)
+                            : nullptr;
         blob->tables = tables + (size_t)b.h_desc[j].tab * kTableCount * stride;
         blob->tab_stride = stride;
         {
@@ -3313,6 +3329,7 @@ extern "C" int rs_build_noalloc(const rs_keys* keys, uint32_t leaf, uint32_t buc
         return fail(RS_EINVAL, "%llu keys need %zu bytes of workspace; the allocation-free build holds %zu",
                     (unsigned long long)keys->n, ws_bytes, kScratchBytes);
     if (b.pin_bytes > sizeof g_na_host) return fail(RS_EINVAL, "host staging too small");
+    b.samples = false;  // the caller's buffer holds the blob alone
     batch_bind(b, base, g_na_host);
     // front: signatures and bucket order, then the largest bucket
     if (int rc = enqueue_front(b, s, nullptr, nullptr)) return rc;

@@ -40,6 +40,7 @@ struct rs_blob {
     uint64_t bytes = 0;
     uint32_t* tables = nullptr;  // device r, F, N for sizes 0..tab_stride-1, tab_stride words each
     uint32_t tab_stride = 0;
+    const uint32_t* samples = nullptr;  // select samples on the device (null: the inventory alone)
     uint64_t header[rs::kHeaderWords] = {};
     hipEvent_t ready = nullptr;      // recorded after the last write of the blob (shared with the arena)
     int device = 0;

@@ -37,6 +37,16 @@ __host__ __device__ inline uint64_t inv_hi_words(uint64_t N) { return 2 * ((N + 
 __host__ __device__ inline uint64_t inv_lo_words(uint64_t N) {
     return (2 * ((N + (1ull << kInvLo) - 1) >> kInvLo) + 3) / 4;
 }
+
+// Select samples (not part of the serialized structure; kept by the library
+// beside a blob it builds): the positions of every kSelectSample-th one of the
+// two upper-bits arrays, as 32-bit words, s list then z list.  A lookup starts
+// its selects there instead of at the two-level inventory, so it scans at
+// most kSelectSample - 1 ones instead of up to 255.
+constexpr uint32_t kSelectSample = 16;
+__host__ __device__ inline uint64_t select_sample_groups(uint64_t N) { return (N + kSelectSample - 1) / kSelectSample; }
+__host__ __device__ inline uint64_t select_samples_words(uint64_t N) { return select_sample_groups(N); }
+
 constexpr uint64_t kDefaultSeedCap = 1ull << 56;
 constexpr uint32_t kMaxLeaf = 24;
 
