@@ -180,6 +180,20 @@ __device__ __forceinline__ uint64_t select_from(const uint64_t* a, uint64_t word
     return (w << 6) + select_in_word(x, k);
 }
 
+// select_from for a start at most a few dozen bits before the one sought (a
+// select sample): the first two words are read together, and the scan goes
+// on only if the one lies beyond them.
+__device__ __forceinline__ uint64_t select_near(const uint64_t* a, uint64_t words, uint64_t p, uint32_t k) {
+    const uint64_t w = p >> 6;
+    if (w + 1 >= words) return select_from(a, words, p, k);
+    const uint64_t x0 = a[w] & (~0ull << (p & 63)), x1 = a[w + 1];
+    const uint32_t c0 = (uint32_t)__popcll(x0);
+    if (k < c0) return (w << 6) + select_in_word(x0, k);
+    const uint32_t c1 = (uint32_t)__popcll(x1);
+    if (k - c0 < c1) return ((w + 1) << 6) + select_in_word(x1, k - c0);
+    return select_from(a, words, (w + 2) << 6, k - c0 - c1);
+}
+
 // Position of the first set bit at or after bit p (the end of a unary code,
 // or the next one of an Elias-Fano upper-bits array); a position past the end
 // if there is none (only in a corrupted structure).
@@ -286,12 +300,17 @@ __device__ uint64_t rank_of(const LookupArgs& a, uint64_t hi, uint64_t lo) {
         inventory_start(blob, a, i, 1, start_z, k_z);
     }
     uint64_t ps, ps1;
-    select_pair(us, a.us_words, start_s, k_s, ps, ps1);
+    if (a.samples) {
+        ps = select_near(us, a.us_words, start_s, k_s);
+        ps1 = ps < (a.us_words << 6) ? next_one(us, a.us_words, ps + 1) : a.us_words << 6;
+    } else {
+        select_pair(us, a.us_words, start_s, k_s, ps, ps1);
+    }
     uint64_t ys = ((ps - i) << a.Ws) | get_bits(lower, i * wsz, a.Ws);
     uint64_t ys1 = ((ps1 - i - 1) << a.Ws) | get_bits(lower, (i + 1) * wsz, a.Ws);
     uint64_t s_i = ys + i * a.delta_s;
     uint64_t s_i1 = ys1 + (i + 1) * a.delta_s;
-    uint64_t pz = select_from(uz, a.uz_words, start_z, k_z);
+    uint64_t pz = a.samples ? select_near(uz, a.uz_words, start_z, k_z) : select_from(uz, a.uz_words, start_z, k_z);
     uint64_t yz = ((pz - i) << a.Wz) | get_bits(lower, i * wsz + a.Ws, a.Wz);
     int64_t z = (int64_t)yz + (int64_t)i * a.delta_z;
     uint64_t o_i = (uint64_t)(z + (int64_t)((a.beta * s_i) >> 16));
