@@ -373,7 +373,7 @@ __device__ uint64_t rank_of(const LookupArgs& a, uint64_t hi, uint64_t lo) {
             T.FN(sh.unit, fu, nu);
             fp += (uint64_t)j * fu;
             const uint32_t skip = j * nu;
-            if (skip) up = select_from(tree, a.tree_words, up, skip - 1) + 1;
+            if (skip) up = select_near(tree, a.tree_words, up, skip - 1) + 1;
         }
         c += (uint64_t)j * (WIDE ? a.Q[sh.unit] : sh.unit);
         m = j + 1 == sh.fanout ? sh.last : sh.unit;
