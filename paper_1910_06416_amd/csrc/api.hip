@@ -414,6 +414,30 @@ __global__ void k_lookup_bytes(LookupArgs a, const uint8_t* __restrict__ data, c
     ranks[t] = rank_of<PACKED, WIDE, TAB16>(a, hi, lo);
 }
 
+// Select samples of a structure that came as bytes: one thread per group of
+// kSelectSample entries finds their first one from the two-level inventory.
+__global__ void k_select_samples(LookupArgs a, uint32_t* __restrict__ out, uint64_t groups) {
+    const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= groups) return;
+    const uint64_t i = g * kSelectSample;
+    uint64_t start;
+    uint32_t k;
+    inventory_start(a.blob, a, i, 0, start, k);
+    out[g] = (uint32_t)select_from(a.blob + a.us_off, a.us_words, start, k);
+    inventory_start(a.blob, a, i, 1, start, k);
+    out[groups + g] = (uint32_t)select_from(a.blob + a.uz_off, a.uz_words, start, k);
+}
+
+LookupArgs lookup_args(const rs_blob* blob, const Layout& L) {
+    const Strategy st = make_strategy((uint32_t)L.leaf);
+    const uint32_t* tab = blob->tables;
+    const size_t w = blob->tab_stride;
+    return LookupArgs{blob->words, tab, tab + w, tab + 2 * w, tab + 4 * w, tab + 5 * w, tab + 6 * w, tab + 7 * w,
+                      blob->samples, L.nb, L.beta, L.delta_s, L.delta_z, L.Ws, L.Wz, L.lower_off, L.us_off,
+                      L.uz_off, L.inv_hi_off, L.inv_lo_off, L.tree_off, L.us_words, L.uz_words, L.tree_words,
+                      (uint32_t)L.leaf, st.lower, st.upper, (uint32_t)L.maxm, L.slack};
+}
+
 }  // namespace
 
 }  // namespace rs
@@ -429,14 +453,7 @@ extern "C" int rs_lookup(const rs_blob* blob, const rs_keys* queries, uint64_t* 
     if (queries->kind != L.kind) return fail(RS_EINVAL, "query kind %u differs from the blob's (%u)",
                                              queries->kind, (uint32_t)L.kind);
     if (queries->kind == RS_KEYS_BYTES && !queries->offsets) return fail(RS_EINVAL, "NULL offsets");
-    Strategy st = make_strategy((uint32_t)L.leaf);
-    const uint32_t* tab = blob->tables;
-    const size_t w = blob->tab_stride;
-    LookupArgs a{blob->words, tab, tab + w, tab + 2 * w, tab + 4 * w, tab + 5 * w, tab + 6 * w, tab + 7 * w,
-                 blob->samples, L.nb, L.beta, L.delta_s,
-                 L.delta_z, L.Ws, L.Wz, L.lower_off, L.us_off, L.uz_off, L.inv_hi_off, L.inv_lo_off, L.tree_off,
-                 L.us_words, L.uz_words, L.tree_words, (uint32_t)L.leaf, st.lower, st.upper, (uint32_t)L.maxm,
-                 L.slack};
+    const LookupArgs a = lookup_args(blob, L);
     hipStream_t s = (hipStream_t)stream;
     if (blob->ready) RS_HIP(hipStreamWaitEvent(s, blob->ready, 0));  // built on another stream
     const uint32_t block = 256;
@@ -522,11 +539,25 @@ extern "C" int rs_blob_from_host(const void* src, uint64_t bytes, void* stream, 
     if (!b) return fail(RS_ENOMEM, "host allocation failed");
     memcpy(b->header, h, sizeof b->header);
     b->al = current_alloc();
-    int rc = b->al.get((void**)&b->words, bytes, s);
+    // the structure, then (from a 256-byte boundary) its select samples
+    const uint64_t smp_off = (bytes / 8 + 31) & ~uint64_t(31), smp_groups = select_sample_groups(L.nb + 1);
+    int rc = b->al.get((void**)&b->words, (smp_off + select_samples_words(L.nb + 1)) * 8, s);
     if (!rc) rc = b->al.get((void**)&b->tables, (size_t)kTableCount * (L.maxm + 1) * 4, s);
     if (!rc) rc = upload_tables((uint32_t)L.leaf, (uint32_t)L.maxm, L.gr_max, L.slack, b->tables, s);
     if (!rc && hipMemcpyAsync(b->words, src, bytes, hipMemcpyHostToDevice, s) != hipSuccess)
         rc = fail(RS_EDEVICE, "copy to device failed");
+    if (!rc) {
+        b->tab_stride = (uint32_t)(L.maxm + 1);
+        uint32_t* smp = reinterpret_cast<uint32_t*>(b->words + smp_off);
+        const uint64_t grid = (smp_groups + 255) / 256;
+        if (!grid_fits(grid, 256)) {
+            rc = fail(RS_EINVAL, "select-sample grid of %llu blocks does not fit", (unsigned long long)grid);
+        } else {
+            k_select_samples<<<dim3((uint32_t)grid), dim3(256), 0, s>>>(lookup_args(b, L), smp, smp_groups);
+            if (hipGetLastError() != hipSuccess) rc = fail(RS_EDEVICE, "select-sample launch failed");
+            else b->samples = smp;
+        }
+    }
     if (!rc && hipStreamSynchronize(s) != hipSuccess) rc = fail(RS_EDEVICE, "stream synchronisation failed");
     if (rc) {
         b->al.put(b->words, s);

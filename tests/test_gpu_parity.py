@@ -174,13 +174,22 @@ def test_lookup_non_members_match_oracle(rs, orc):
     assert got.max() <= 50_000
 
 
-def test_roundtrip_from_bytes(rs, orc):
-    keys = inputs.u64_keys(30_000, 9)
-    want = orc.build(keys, 8, 100)
+@pytest.mark.parametrize("n,bucket", [(30_000, 100), (300_000, 10)])
+def test_roundtrip_from_bytes(rs, orc, n, bucket):
+    """A structure loaded from its bytes (its select samples computed from
+    the inventory; 30,000 buckets span two 2^14-one blocks) gives the
+    oracle's ranks, as does the same structure built on the device."""
+    keys = inputs.u64_keys(n, 9)
+    print(f"case from bytes n={n} bucket={bucket}", flush=True)
+    want = orc.build(keys, 8, bucket)
     blob = rs.from_bytes(want)
     assert blob.to_bytes() == want
-    ranks = rs.lookup(blob, rs.device_keys(keys)).cpu().numpy().view(np.uint64)
+    dk = rs.device_keys(keys)
+    ranks = rs.lookup(blob, dk).cpu().numpy().view(np.uint64)
     assert np.array_equal(ranks, orc.lookup(want, keys))
+    built = rs.build(dk, 8, bucket)
+    assert built.to_bytes() == want
+    assert np.array_equal(rs.lookup(built, dk).cpu().numpy().view(np.uint64), ranks)
 
 
 def test_errors(rs, orc):
