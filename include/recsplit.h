@@ -312,14 +312,19 @@ int rs_build_noalloc(const rs_keys* keys, uint32_t leaf, uint32_t bucket, void* 
  * Errors: RS_EINVAL (NULL, kind mismatch), RS_EDEVICE. */
 int rs_lookup(const rs_blob* blob, const rs_keys* queries, uint64_t* ranks_dev, void* stream);
 
-/* Size in bytes of the serialized structure (header + Elias-Fano + trees). */
+/* Size in bytes of the serialized structure (header + Elias-Fano + trees).  A blob
+ * also holds, in device memory beside the structure, its select samples (the
+ * position of every 16th one of both Elias-Fano upper-bits arrays, 4 bytes each,
+ * about 0.5 byte per bucket), from which rs_lookup starts its selects; they are not
+ * part of the serialized bytes. */
 uint64_t rs_blob_bytes(const rs_blob* blob);
 
 /* Copy the serialized structure to host memory dst (capacity cap bytes); waits until
  * the blob is complete.  Errors: RS_EINVAL (cap too small, NULL). */
 int rs_blob_to_host(const rs_blob* blob, void* dst, uint64_t cap);
 
-/* Load a serialized structure from host memory into a new device blob.
+/* Load a serialized structure from host memory into a new device blob (its select
+ * samples are computed from the structure's inventory).
  * Errors: RS_EFORMAT (magic, version, size), RS_ENOMEM, RS_EDEVICE. */
 int rs_blob_from_host(const void* src, uint64_t bytes, void* stream, rs_blob** out);
 
