@@ -252,6 +252,61 @@ __device__ __forceinline__ void inventory_start(const uint64_t* blob, const Look
     k = (uint32_t)i & (near ? (1u << kInvLo) - 1 : (1u << kInvHi) - 1);
 }
 
+// The words of a query's Golomb-Rice bucket stream, read once: kTreeWin words
+// from the bucket's first one, loaded together into the lane's LDS slots (one
+// memory round trip), so that the descent's dependent reads of fixed parts,
+// unary codes and skipped codes mostly hit LDS.  Words outside the window
+// are read from the structure.
+constexpr uint32_t kLookupBlock = 256;
+constexpr uint32_t kTreeWin = 8;
+struct TreeWin {
+    const uint64_t* g;  // the Golomb-Rice streams
+    uint64_t words;     // their length in words (with the guard word)
+    uint64_t* l;        // this lane's slots: l[k * kLookupBlock] holds word w0 + k
+    uint64_t w0;
+    __device__ __forceinline__ void load(uint64_t first) {
+        w0 = first;
+        uint64_t x[kTreeWin];
+#pragma unroll
+        for (uint32_t k = 0; k < kTreeWin; k++) x[k] = w0 + k < words ? g[w0 + k] : 0;
+#pragma unroll
+        for (uint32_t k = 0; k < kTreeWin; k++) l[k * kLookupBlock] = x[k];
+    }
+    __device__ __forceinline__ uint64_t word(uint64_t w) const {
+        const uint64_t k = w - w0;
+        return k < kTreeWin ? l[k * kLookupBlock] : g[w];
+    }
+    // as get_bits (the guard word keeps w + 1 inside the array)
+    __device__ __forceinline__ uint64_t bits(uint64_t pos, uint32_t nbits) const {
+        const uint64_t w = pos >> 6;
+        const uint32_t o = (uint32_t)(pos & 63);
+        const uint64_t v = (word(w) >> o) | ((word(w + 1) << 1) << (63 - o));
+        return v & ~(~0ull << nbits);
+    }
+    // as next_one
+    __device__ __forceinline__ uint64_t next_one(uint64_t p) const {
+        uint64_t w = p >> 6;
+        if (w >= words) return words << 6;
+        uint64_t x = word(w) & (~0ull << (p & 63));
+        while (!x) {
+            if (++w >= words) return words << 6;
+            x = word(w);
+        }
+        return (w << 6) + (uint64_t)__builtin_ctzll(x);
+    }
+    // as select_near: the first two words from the window, the rest by select_from
+    __device__ __forceinline__ uint64_t select(uint64_t p, uint32_t k) const {
+        const uint64_t w = p >> 6;
+        if (w + 1 >= words) return select_from(g, words, p, k);
+        const uint64_t x0 = word(w) & (~0ull << (p & 63)), x1 = word(w + 1);
+        const uint32_t c0 = (uint32_t)__popcll(x0);
+        if (k < c0) return (w << 6) + select_in_word(x0, k);
+        const uint32_t c1 = (uint32_t)__popcll(x1);
+        if (k - c0 < c1) return ((w + 1) << 6) + select_in_word(x1, k - c0);
+        return select_from(g, words, (w + 2) << 6, k - c0 - c1);
+    }
+};
+
 // Per-size table reads of the descent: one packed word per size (footnote of
 // Sec. 7.2) when every size of the structure fits it, else three arrays.
 template <bool PACKED>
@@ -279,7 +334,7 @@ struct SizeTables {
 // split shapes come from the per-size table and child indices from one
 // multiply with the part size's reciprocal (exact while ph * unit < 2^32).
 template <bool PACKED, bool WIDE, bool TAB16>
-__device__ uint64_t rank_of(const LookupArgs& a, uint64_t hi, uint64_t lo) {
+__device__ uint64_t rank_of(const LookupArgs& a, uint64_t hi, uint64_t lo, uint64_t* win) {
     const SizeTables<PACKED> T{a};
     const uint64_t* blob = a.blob;
     const uint64_t i = bucket_of(hi, a.nb);
@@ -326,7 +381,8 @@ __device__ uint64_t rank_of(const LookupArgs& a, uint64_t hi, uint64_t lo) {
         }
         m = lo_m;
     }
-    const uint64_t* tree = blob + a.tree_off;
+    TreeWin tw{blob + a.tree_off, a.tree_words, win, 0};
+    tw.load(o_i >> 6);
     // without the tables: node sizes below 2^20 take div_small (every
     // dividend is then under 2^21), larger ones integer division
     const bool small = a.maxm < (1u << 20);
@@ -335,9 +391,9 @@ __device__ uint64_t rank_of(const LookupArgs& a, uint64_t hi, uint64_t lo) {
     uint64_t fp = o_i, up = o_i + T.F(m);
     while (m > a.leaf) {
         uint32_t r = T.r(m);
-        uint64_t fixed = get_bits(tree, fp, r);
+        uint64_t fixed = tw.bits(fp, r);
         fp += r;
-        uint64_t one = next_one(tree, a.tree_words, up);
+        uint64_t one = tw.next_one(up);
         uint64_t v = ((one - up) << r) | fixed;
         up = one + 1;
         SplitShape sh;
@@ -373,7 +429,7 @@ __device__ uint64_t rank_of(const LookupArgs& a, uint64_t hi, uint64_t lo) {
             T.FN(sh.unit, fu, nu);
             fp += (uint64_t)j * fu;
             const uint32_t skip = j * nu;
-            if (skip) up = select_near(tree, a.tree_words, up, skip - 1) + 1;
+            if (skip) up = tw.select(up, skip - 1) + 1;
         }
         c += (uint64_t)j * (WIDE ? a.Q[sh.unit] : sh.unit);
         m = j + 1 == sh.fanout ? sh.last : sh.unit;
@@ -381,8 +437,8 @@ __device__ uint64_t rank_of(const LookupArgs& a, uint64_t hi, uint64_t lo) {
     }
     if (m >= 2) {
         uint32_t r = T.r(m);
-        uint64_t fixed = get_bits(tree, fp, r);
-        uint64_t one = next_one(tree, a.tree_words, up);
+        uint64_t fixed = tw.bits(fp, r);
+        uint64_t one = tw.next_one(up);
         uint64_t v = ((one - up) << r) | fixed;
         c += phi(lo, d, v, WIDE ? leaf_range(m, a.slack) : m);
     }
@@ -396,9 +452,10 @@ __global__ void k_lookup_u64(LookupArgs a, const uint64_t* __restrict__ keys, ui
                              uint64_t* __restrict__ ranks) {
     uint64_t t = q0 + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= q) return;
+    __shared__ uint64_t win[kTreeWin * kLookupBlock];
     uint64_t hi, lo;
     signature_u64(keys[t], hi, lo);
-    ranks[t] = rank_of<PACKED, WIDE, TAB16>(a, hi, lo);
+    ranks[t] = rank_of<PACKED, WIDE, TAB16>(a, hi, lo, win + threadIdx.x);
 }
 
 template <bool PACKED, bool WIDE, bool TAB16>
@@ -411,7 +468,8 @@ __global__ void k_lookup_bytes(LookupArgs a, const uint8_t* __restrict__ data, c
     if (e < s || e > total) e = s = min(s, total);
     uint64_t hi, lo;
     signature_bytes(data, total, aligned, s, e, hi, lo);
-    ranks[t] = rank_of<PACKED, WIDE, TAB16>(a, hi, lo);
+    __shared__ uint64_t win[kTreeWin * kLookupBlock];
+    ranks[t] = rank_of<PACKED, WIDE, TAB16>(a, hi, lo, win + threadIdx.x);
 }
 
 // Select samples of a structure that came as bytes: one thread per group of
@@ -456,7 +514,7 @@ extern "C" int rs_lookup(const rs_blob* blob, const rs_keys* queries, uint64_t* 
     const LookupArgs a = lookup_args(blob, L);
     hipStream_t s = (hipStream_t)stream;
     if (blob->ready) RS_HIP(hipStreamWaitEvent(s, blob->ready, 0));  // built on another stream
-    const uint32_t block = 256;
+    const uint32_t block = kLookupBlock;
     const uint64_t q = queries->n;
     // one query per lane, in launches of at most max_grid_blocks() blocks
     if (int rc = for_each_chunk(q, block, block, [&](uint64_t q0, uint64_t, uint64_t grid) -> int {
