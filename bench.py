@@ -41,7 +41,7 @@ SEARCH_TRAFFIC_BYTES = 135.0e6
 # VALU lane-instructions that k_lookup_bytes executes per string query (rocprofv3
 # SQ_INSTS_VALU x 64 / queries on the 10M-string workload): lookups are bound by
 # the VALU and by dependent loads, not by HBM.
-LOOKUP_VALU_PER_QUERY = 1260.0
+LOOKUP_VALU_PER_QUERY = 1437.0
 # MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz full-rate 32-bit VALU lane-ops.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 HBM_PEAK_GBS = 8000.0
