@@ -386,7 +386,7 @@ def main():
     if not args.no_serve:
         log(f"[bench] serving: {args.serve_requests} requests at offered load {args.serve_load}")
         sv = bench_serve(args, args.serve_requests, args.serve_load, tuned=False)
-        result["serve"] = {k: sv[k] for k in ("value", "unit", "served", "plain", "config")}
+        result["serve"] = {k: sv[k] for k in ("value", "unit", "served", "plain", "config", "requests")}
         result["serve"]["p99_vs_plain"] = sv["plain"]["p99_ms"] / sv["served"]["p99_ms"]
         result["serve"]["makespan_vs_plain"] = sv["plain"]["makespan_s"] / sv["served"]["makespan_s"]
     result["schedules"] = schedules if tuned else "built-in"
