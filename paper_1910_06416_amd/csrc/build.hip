@@ -1999,8 +1999,10 @@ void* pinned(size_t bytes, Staging& st = g_staging) {
     if (st.cap < bytes) {
         if (st.p) (void)hipHostFree(st.p);
         size_t want = std::max<size_t>(bytes, 1 << 16);
-        // mapped and coherent: kernels read it directly (k_reset, k_copy_words)
-        if (hipHostMalloc(&st.p, want, hipHostMallocMapped | hipHostMallocCoherent) != hipSuccess) {
+        // mapped (on every device) and coherent: kernels read it directly
+        // (k_reset, k_copy_words)
+        const unsigned flags = hipHostMallocMapped | hipHostMallocCoherent | hipHostMallocPortable;
+        if (hipHostMalloc(&st.p, want, flags) != hipSuccess) {
             st.p = nullptr;
             st.cap = 0;
             return nullptr;
