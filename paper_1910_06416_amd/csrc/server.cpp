@@ -183,9 +183,9 @@ void build_worker(rs_server* s) {
         {
             std::lock_guard<std::mutex> lk(s->mu);
             for (uint32_t i = 0; i < count; i++) {
-                int st = status[i];
-                if (st == RS_OK && !outs[i]) st = rc != RS_OK ? rc : RS_EDEVICE;
-                finish(s, batch[i], st, outs[i], count);
+                int code = status[i];
+                if (code == RS_OK && !outs[i]) code = rc != RS_OK ? rc : RS_EDEVICE;
+                finish(s, batch[i], code, outs[i], count);
             }
             s->in_flight -= bytes;
             s->heavy_in_flight -= batch_heavy ? 1 : 0;
