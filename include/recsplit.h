@@ -316,7 +316,9 @@ int rs_lookup(const rs_blob* blob, const rs_keys* queries, uint64_t* ranks_dev, 
  * also holds, in device memory beside the structure, its select samples (the
  * position of every 16th one of both Elias-Fano upper-bits arrays, 4 bytes each,
  * about 0.5 byte per bucket), from which rs_lookup starts its selects; they are not
- * part of the serialized bytes. */
+ * part of the serialized bytes.  A structure of more than (2^32 - 1) / 3 - 1 buckets,
+ * whose bit positions would not fit 32 bits, has none: its lookups start at the
+ * two-level inventory. */
 uint64_t rs_blob_bytes(const rs_blob* blob);
 
 /* Copy the serialized structure to host memory dst (capacity cap bytes); waits until
@@ -324,7 +326,8 @@ uint64_t rs_blob_bytes(const rs_blob* blob);
 int rs_blob_to_host(const rs_blob* blob, void* dst, uint64_t cap);
 
 /* Load a serialized structure from host memory into a new device blob (its select
- * samples are computed from the structure's inventory).
+ * samples, within the bucket bound given at rs_blob_bytes, are computed from the
+ * structure's inventory).
  * Errors: RS_EFORMAT (magic, version, size), RS_ENOMEM, RS_EDEVICE. */
 int rs_blob_from_host(const void* src, uint64_t bytes, void* stream, rs_blob** out);
 

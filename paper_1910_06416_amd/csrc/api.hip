@@ -598,14 +598,16 @@ extern "C" int rs_blob_from_host(const void* src, uint64_t bytes, void* stream, 
     memcpy(b->header, h, sizeof b->header);
     b->al = current_alloc();
     // the structure, then (from a 256-byte boundary) its select samples
+    const bool with_samples = select_samples_fit(L.nb + 1);
     const uint64_t smp_off = (bytes / 8 + 31) & ~uint64_t(31), smp_groups = select_sample_groups(L.nb + 1);
-    int rc = b->al.get((void**)&b->words, (smp_off + select_samples_words(L.nb + 1)) * 8, s);
+    const uint64_t words = with_samples ? smp_off + select_samples_words(L.nb + 1) : bytes / 8;
+    int rc = b->al.get((void**)&b->words, words * 8, s);
     if (!rc) rc = b->al.get((void**)&b->tables, (size_t)kTableCount * (L.maxm + 1) * 4, s);
     if (!rc) rc = upload_tables((uint32_t)L.leaf, (uint32_t)L.maxm, L.gr_max, L.slack, b->tables, s);
     if (!rc && hipMemcpyAsync(b->words, src, bytes, hipMemcpyHostToDevice, s) != hipSuccess)
         rc = fail(RS_EDEVICE, "copy to device failed");
-    if (!rc) {
-        b->tab_stride = (uint32_t)(L.maxm + 1);
+    b->tab_stride = (uint32_t)(L.maxm + 1);
+    if (!rc && with_samples) {
         uint32_t* smp = reinterpret_cast<uint32_t*>(b->words + smp_off);
         const uint64_t grid = (smp_groups + 255) / 256;
         if (!grid_fits(grid, 256)) {
@@ -624,7 +626,6 @@ extern "C" int rs_blob_from_host(const void* src, uint64_t bytes, void* stream, 
         return rc;
     }
     b->bytes = bytes;
-    b->tab_stride = (uint32_t)(L.maxm + 1);
     {
         const TableView tv = host_tables((uint32_t)L.leaf, (uint32_t)L.maxm, L.gr_max, L.slack);
         b->packed = !L.slack && tv.data && packed_valid(tv.P(), (uint32_t)L.maxm);

@@ -1706,7 +1706,7 @@ __device__ __forceinline__ void ef_fill_entry(const FillArgs& a, uint64_t e) {
     or_bits(blob + B.us_off, ps, 1, 1);
     or_bits(blob + B.uz_off, pz, 1, 1);
     if (B.samples_off && (i & (kSelectSample - 1)) == 0) {
-        // positions below 2^32: an upper-bits array has N ones and at most 2 N zeros
+        // positions below 2^32 (select_samples_fit)
         uint32_t* smp = reinterpret_cast<uint32_t*>(blob + B.samples_off);
         const uint64_t groups = select_sample_groups(B.nb + 1);
         smp[i / kSelectSample] = (uint32_t)ps;
@@ -1913,7 +1913,7 @@ __global__ __launch_bounds__(kBlock) void k_layout(BuildDesc* __restrict__ descs
                 raw = geometry_of(d, hdr + (size_t)j * kHeaderWords);
             raw_words[j] = raw;
             w = (raw + 31) & ~uint64_t(31);
-            d.samples_off = with_samples && raw ? w : 0;
+            d.samples_off = with_samples && raw && select_samples_fit(d.nb + 1) ? w : 0;
             if (d.samples_off) w += (select_samples_words(d.nb + 1) + 31) & ~uint64_t(31);
         }
         uint64_t tot;

@@ -46,6 +46,10 @@ __host__ __device__ inline uint64_t inv_lo_words(uint64_t N) {
 constexpr uint32_t kSelectSample = 16;
 __host__ __device__ inline uint64_t select_sample_groups(uint64_t N) { return (N + kSelectSample - 1) / kSelectSample; }
 __host__ __device__ inline uint64_t select_samples_words(uint64_t N) { return select_sample_groups(N); }
+// An upper-bits array of N entries spans fewer than 3 N bits, so its
+// positions fit the 32-bit samples while 3 N < 2^32; a larger structure
+// keeps none and its lookups start at the inventory.
+__host__ __device__ inline bool select_samples_fit(uint64_t N) { return N <= 0xffffffffull / 3; }
 
 constexpr uint64_t kDefaultSeedCap = 1ull << 56;
 constexpr uint32_t kMaxLeaf = 24;
