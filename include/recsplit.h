@@ -99,6 +99,9 @@ int rs_set_allocator(rs_alloc_fn alloc, rs_free_fn release, void* ctx);
  *               process-wide schedule table (rs_autotune, rs_schedule_set) when
  *               the table has an entry for its (l, b); builds without an entry
  *               use the built-in schedule.
+ *               RS_OPT_NO_SAMPLES builds blobs without select samples (see
+ *               rs_blob_bytes): about 0.5 byte per bucket less device memory,
+ *               and lookups start their selects at the two-level inventory.
  *   stage_from, group_max, waves: schedule overrides for every build of the
  *               call (0 = keep the table's or built-in value), as in rs_schedule.
  *   wait_limit: when several wavefronts share a bucket's tree, a wavefront
@@ -121,7 +124,7 @@ int rs_set_allocator(rs_alloc_fn alloc, rs_free_fn release, void* ctx);
  *               in the structure (header word 7, bits 40-47).  RS_EINVAL when
  *               l + ceil(l leaf_slack / 256) exceeds 32.
  * Schedules never change the result, only the time it takes. */
-enum { RS_OPT_TIMING = 1, RS_OPT_TUNED = 2 };
+enum { RS_OPT_TIMING = 1, RS_OPT_TUNED = 2, RS_OPT_NO_SAMPLES = 4 };
 typedef struct {
     uint64_t seed_cap;
     uint32_t flags;

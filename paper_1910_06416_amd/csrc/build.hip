@@ -2327,7 +2327,8 @@ struct Batch {
     std::vector<uint32_t> which;  // desc index -> position in the call
     std::vector<TabKey> tab_keys;  // of each table set
     bool wide = false;             // some build is non-minimal
-    bool samples = true;           // arena slots hold select samples (not in allocation-free builds)
+    bool samples = true;           // arena slots hold select samples (not in allocation-free builds
+                                   // nor with RS_OPT_NO_SAMPLES)
     uint64_t total = 0, nbuckets = 0, seed_cap = kDefaultSeedCap;
     uint32_t wait_limit = kDefaultWaitLimit;
     uint32_t K = 0, max_leaf = 1, launch_waves = 1;
@@ -2362,6 +2363,7 @@ int batch_prepare(Batch& b, const rs_keys* sets, uint32_t count, const uint32_t*
     b.count = count;
     b.seed_cap = opts && opts->seed_cap ? std::min(opts->seed_cap, kDefaultSeedCap) : kDefaultSeedCap;
     b.wait_limit = opts && opts->wait_limit ? opts->wait_limit : kDefaultWaitLimit;
+    b.samples = !(opts && (opts->flags & RS_OPT_NO_SAMPLES));
     b.st.assign(count, RS_OK);
     b.why.assign(count, std::string());
     for (uint32_t c = 0; c < count; c++) {

@@ -44,7 +44,7 @@ class rs_options(ctypes.Structure):
                 ("gr_table_max", ctypes.c_uint32), ("leaf_slack", ctypes.c_uint32)]
 
 
-RS_OPT_TIMING, RS_OPT_TUNED = 1, 2
+RS_OPT_TIMING, RS_OPT_TUNED, RS_OPT_NO_SAMPLES = 1, 2, 4
 
 
 class rs_schedule(ctypes.Structure):
@@ -258,23 +258,24 @@ class Blob:
 
 
 def _options(seed_cap=0, timing=False, tuned=False, stage_from=0, group_max=0, waves=0, wait_limit=0,
-             gr_table_max=0, leaf_slack=0) -> rs_options:
-    flags = (RS_OPT_TIMING if timing else 0) | (RS_OPT_TUNED if tuned else 0)
+             gr_table_max=0, leaf_slack=0, samples=True) -> rs_options:
+    flags = (RS_OPT_TIMING if timing else 0) | (RS_OPT_TUNED if tuned else 0) | (0 if samples else RS_OPT_NO_SAMPLES)
     return rs_options(seed_cap, flags, stage_from, group_max, waves, wait_limit, gr_table_max, leaf_slack)
 
 
 def build(keys, leaf: int, bucket: int, seed_cap: int = 0, timing: bool = False, stage_from: int = 0,
           group_max: int = 0, waves: int = 0, tuned: bool = False, wait_limit: int = 0, gr_table_max: int = 0,
-          leaf_slack: int = 0, stream=None) -> Blob:
+          leaf_slack: int = 0, samples: bool = True, stream=None) -> Blob:
     """Build the minimal perfect hash function of a device key set.  With
     timing=True the per-phase device times are available from last_build_stats().
     tuned=True takes the search schedule of (leaf, bucket) from the schedule
     table (see autotune); stage_from / group_max / waves override it.  Schedules
     never change the result.  wait_limit, gr_table_max and leaf_slack are the
-    rs_options fields of those names."""
+    rs_options fields of those names; samples=False sets RS_OPT_NO_SAMPLES."""
     k = _as_keys(keys)
     h = ctypes.c_void_p()
-    opts = _options(seed_cap, timing, tuned, stage_from, group_max, waves, wait_limit, gr_table_max, leaf_slack)
+    opts = _options(seed_cap, timing, tuned, stage_from, group_max, waves, wait_limit, gr_table_max, leaf_slack,
+                    samples)
     _check(lib().rs_build_ex(ctypes.byref(k), leaf, bucket, ctypes.byref(opts), _stream(stream), ctypes.byref(h)))
     return Blob(h)
 

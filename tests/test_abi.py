@@ -24,6 +24,20 @@ def lib():
     return recsplit.lib()
 
 
+def test_binding_constants_match_the_header():
+    """Status codes, key kinds and option flags: the Python binding's values
+    are the header's."""
+    from paper_1910_06416_amd import recsplit
+
+    text = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    values = {k: int(v) for k, v in re.findall(r"\b(RS_[A-Z0-9_]+)\s*=\s*(\d+)", text)}
+    for name in ("RS_OK", "RS_EINVAL", "RS_EDUPLICATE", "RS_ENOMEM", "RS_EDEVICE", "RS_ESEARCH", "RS_EFORMAT",
+                 "RS_EBUSY", "RS_KEYS_U64", "RS_KEYS_BYTES", "RS_OPT_TIMING", "RS_OPT_TUNED", "RS_OPT_NO_SAMPLES"):
+        assert values[name] == getattr(recsplit, name), name
+    assert recsplit._options(samples=False).flags == values["RS_OPT_NO_SAMPLES"]
+    assert recsplit._options().flags == 0
+
+
 def test_header_declares_the_boundary():
     names = declared_functions()
     for required in ("rs_build", "rs_lookup", "rs_blob_bytes", "rs_blob_to_host", "rs_blob_from_host",

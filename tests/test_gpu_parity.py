@@ -192,6 +192,28 @@ def test_roundtrip_from_bytes(rs, orc, n, bucket):
     assert np.array_equal(rs.lookup(built, dk).cpu().numpy().view(np.uint64), ranks)
 
 
+@pytest.mark.parametrize("kind,n,leaf,bucket,slack",
+                         [("u64", 300_000, 8, 10, 0), ("bytes", 60_000, 5, 5, 0), ("u64", 40_000, 8, 100, 32)])
+def test_lookup_without_select_samples(rs, orc, kind, n, leaf, bucket, slack):
+    """RS_OPT_NO_SAMPLES: the same structure, whose lookups start their
+    selects at the two-level inventory, as those of structures too large for
+    32-bit samples do (30,000 and 12,000 buckets span two and one 2^14-one
+    blocks); ranks equal the sampled blob's and the oracle's."""
+    keys = inputs.u64_keys(n, 5100 + n) if kind == "u64" else inputs.ascii_keys(n, 5100 + n)
+    print(f"case no samples kind={kind} n={n} leaf={leaf} bucket={bucket} slack={slack}", flush=True)
+    dk = rs.device_keys(keys)
+    plain = rs.build(dk, leaf, bucket, leaf_slack=slack, samples=False)
+    sampled = rs.build(dk, leaf, bucket, leaf_slack=slack)
+    assert plain.to_bytes() == sampled.to_bytes()
+    ranks = rs.lookup(plain, dk).cpu().numpy().view(np.uint64)
+    assert np.array_equal(ranks, rs.lookup(sampled, dk).cpu().numpy().view(np.uint64))
+    assert len(np.unique(ranks)) == n
+    if not slack:
+        want = orc.build(keys, leaf, bucket)
+        assert plain.to_bytes() == want
+        assert np.array_equal(ranks, orc.lookup(want, keys))
+
+
 def test_errors(rs, orc):
     import torch
 
