@@ -2817,10 +2817,11 @@ uint32_t bucket_size_cap(uint64_t n, uint64_t nb) {
     return last_cap;
 }
 
-// Blob words per key of the calling thread's last single build of each
-// shape.  A later single build of that shape and of a similar key count
-// (within a factor of two: small sets spend more words per key on the header
-// and the index) enqueues its fill into an arena of n times that (with a
+// Blob words per key of the calling thread's last single build.  A later
+// single build of the same shape (l, b, Golomb-Rice table bound, slack, with
+// or without select samples) and of a similar key count (within a factor of
+// two: small sets spend more words per key on the header and the index)
+// enqueues its fill into an arena of n times that (with a
 // margin) before its one wait on the stream, rather
 // than waiting for the exact sizes and then filling: the host's wake-up and
 // two launches leave the critical path.  A blob beyond the guessed arena is
@@ -2829,6 +2830,7 @@ uint32_t bucket_size_cap(uint64_t n, uint64_t nb) {
 // (0: never guess), read at each call.
 struct ArenaMemo {
     uint32_t leaf = 0, bucket = 0, gr_max = 0, slack = 0;
+    bool samples = false;
     uint64_t n = 0;
     double words_per_key = 0;
 };
@@ -2839,7 +2841,7 @@ uint64_t arena_guess(const Batch& b) {
     const BuildDesc& d = b.hd[0];
     const ArenaMemo& m = g_arena_memo;
     if (m.words_per_key <= 0 || m.leaf != d.leaf || m.bucket != d.bucket || m.gr_max != d.gr_max ||
-        m.slack != d.slack || d.n > 2 * m.n || 2 * d.n < m.n)
+        m.slack != d.slack || m.samples != b.samples || d.n > 2 * m.n || 2 * d.n < m.n)
         return 0;
     double scale = 1.125;
     if (const char* e = std::getenv("RS_ARENA_GUESS"); e && *e) scale = std::atof(e);
@@ -2855,6 +2857,7 @@ void arena_remember(const Batch& b) {
     m.bucket = d.bucket;
     m.gr_max = d.gr_max;
     m.slack = d.slack;
+    m.samples = b.samples;
     m.n = d.n;
     m.words_per_key = (double)b.h_boff[1] / (double)d.n;
 }

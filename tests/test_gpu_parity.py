@@ -203,7 +203,9 @@ def test_lookup_without_select_samples(rs, orc, kind, n, leaf, bucket, slack):
     print(f"case no samples kind={kind} n={n} leaf={leaf} bucket={bucket} slack={slack}", flush=True)
     dk = rs.device_keys(keys)
     plain = rs.build(dk, leaf, bucket, leaf_slack=slack, samples=False)
-    sampled = rs.build(dk, leaf, bucket, leaf_slack=slack)
+    sampled = rs.build(dk, leaf, bucket, leaf_slack=slack, timing=True)
+    st = rs.last_build_stats()
+    assert (st["arena_bytes"], int(st["refills"])) == (st["blob_bytes"], 0)  # no guess across the two formats
     assert plain.to_bytes() == sampled.to_bytes()
     ranks = rs.lookup(plain, dk).cpu().numpy().view(np.uint64)
     assert np.array_equal(ranks, rs.lookup(sampled, dk).cpu().numpy().view(np.uint64))
