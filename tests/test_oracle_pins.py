@@ -436,6 +436,26 @@ def test_inventory_finds_every_one(orc, n, leaf, bucket):
     assert orc.blob_check_inventory(blob) == 0
 
 
+@pytest.mark.parametrize("n,leaf,bucket,slack", [(1, 8, 100, 0), (17, 2, 3, 0), (70_000, 2, 1, 0), (200_000, 5, 5, 0),
+                                                 (100_000, 8, 100, 0), (40_000, 4, 2000, 0), (50_000, 8, 100, 64)])
+def test_upper_bits_lie_below_three_bits_per_entry(orc, n, leaf, bucket, slack):
+    """Both Elias-Fano upper-bits arrays (Sec. 7.4) hold exactly nb + 1 ones,
+    the i-th at (y_i >> W) + i, and the last lies below bit 3 (nb + 1): with W
+    the floor of lg(largest y / entries), y >> W stays below twice the entry
+    count.  32-bit select samples rely on this bound."""
+    blob = orc.build(inputs.u64_keys(n, 70 + leaf + slack), leaf, bucket, leaf_slack=slack)
+    h = orc.header(blob)
+    w = np.frombuffer(blob, dtype=np.uint64)
+    N = h["nb"] + 1
+    us = 16 + h["lower_words"]
+    uz = us + h["us_words"]
+    for lo_w, count in ((us, h["us_words"]), (uz, h["uz_words"])):
+        bits = np.unpackbits(w[lo_w:lo_w + count].view(np.uint8), bitorder="little")
+        ones = np.flatnonzero(bits)
+        assert len(ones) == N
+        assert ones[-1] < 3 * N
+
+
 def test_inventory_offsets_that_overflow_16_bits(orc):
     """A one more than 65534 positions past its 2^14-block anchor gets the
     overflow mark, and the search from the anchor still finds it."""
