@@ -1,0 +1,74 @@
+"""Strength of the oracle's pins: each plausible mistake planted in a copy of
+the oracle (on the CPU, never in the oracle itself) makes some pin of
+test_oracle_pins.py or test_oracle_parallel.py fail, and the unchanged copy
+passes them all.  About 5 minutes on 6 cores, so it runs only with
+RS_MUTATION_TESTS=1."""
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+pytestmark = pytest.mark.skipif(os.environ.get("RS_MUTATION_TESTS") != "1",
+                                reason="set RS_MUTATION_TESTS=1 (about 5 minutes)")
+
+# name -> (text of the oracle, its mistaken replacement)
+MUTANTS = {
+    "unchanged": ("", ""),
+    # strategy (Sec. 5): s rounded down, t's small-leaf case one too far, interval bounds
+    "strategy_s_floor": ("uint32_t s = (35 * leaf + 50 + 99) / 100;", "uint32_t s = (35 * leaf + 50) / 100;"),
+    "strategy_t_le7": ("uint32_t t = leaf < 7 ?", "uint32_t t = leaf <= 7 ?"),
+    "split_upper_inclusive": ("    if (m > st->upper) {\n        u = ((m / 2", "    if (m >= st->upper) {\n        u = ((m / 2"),
+    "split_lower_inclusive": ("u = m > st->lower ? st->lower : st->leaf;", "u = m >= st->lower ? st->lower : st->leaf;"),
+    "split_two_way_floor": ("u = ((m / 2 + st->upper - 1) / st->upper) * st->upper;",
+                            "u = ((m / 2) / st->upper) * st->upper; if (!u) u = st->upper;"),
+    # eq. (4)
+    "gr_floor_not_ceil": ("double x = ceil(log2(ratio));", "double x = floor(log2(ratio));"),
+    "gr_log_p": ("double ratio = log(golden) / -log1p(-p);", "double ratio = log(golden) / -log(p);"),
+    # searches take the first index from 0 (Sec. 4)
+    "leaf_search_from_1": ("uint32_t depth, uint64_t cap, uint64_t* out) {\n    for (uint64_t v = 0;",
+                           "uint32_t depth, uint64_t cap, uint64_t* out) {\n    for (uint64_t v = 1;"),
+    "split_search_from_1": ("uint32_t unit, uint64_t cap, uint64_t* out) {\n    for (uint64_t v = 0;",
+                            "uint32_t unit, uint64_t cap, uint64_t* out) {\n    for (uint64_t v = 1;"),
+    # hash family: functions reused along a root-to-leaf path (Sec. 7.3)
+    "phi_no_depth": ("uint64_t index = ((uint64_t)depth << 56) | v;", "uint64_t index = v;"),
+    # Golomb-Rice streams (Sec. 6.2)
+    "unary_one_extra_zero": ("pos += node_v[s[i] + k] >> rr; /* zeros */",
+                             "pos += (node_v[s[i] + k] >> rr) + 1; /* zeros */"),
+    "fixed_part_high_bits": ("put_bits(tree, pos, node_v[s[i] + k] & ((1ULL << rr) - 1), rr);",
+                             "put_bits(tree, pos, (node_v[s[i] + k] >> 1) & ((1ULL << rr) - 1), rr);"),
+    # double Elias-Fano (Sec. 6.3, 7.4)
+    "beta_shift_17": ("z[i] = (int64_t)o[i] - (int64_t)((beta * qs[i]) >> 16);",
+                      "z[i] = (int64_t)o[i] - (int64_t)((beta * qs[i]) >> 17);"),
+    "inventory_lo_stride_2_7": ("if (k % (1ULL << ORC_INV_LO) == 0) {", "if (k % (1ULL << (ORC_INV_LO - 1)) == 0) {"),
+}
+
+
+@pytest.mark.parametrize("name", list(MUTANTS))
+def test_planted_mistake_fails_a_pin(name, tmp_path):
+    for d in ("oracle", "tests"):
+        shutil.copytree(os.path.join(ROOT, d), tmp_path / d,
+                        ignore=shutil.ignore_patterns("__pycache__", "*.so", "sanitize"))
+    pkg = tmp_path / "paper_1910_06416_amd"
+    pkg.mkdir()
+    for f in ("__init__.py", "inputs.py"):
+        shutil.copy(os.path.join(ROOT, "paper_1910_06416_amd", f), pkg / f)
+    src = open(os.path.join(ROOT, "oracle", "recsplit_oracle.c")).read()
+    old, new = MUTANTS[name]
+    if old:
+        assert src.count(old) == 1, f"mutation site of {name} not found once"
+        src = src.replace(old, new)
+    (tmp_path / "oracle" / "recsplit_oracle.c").write_text(src)
+    subprocess.run(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", str(tmp_path / "oracle" / "liboracle.so"),
+                    str(tmp_path / "oracle" / "recsplit_oracle.c"), "-lm"], check=True)
+    r = subprocess.run([sys.executable, "-m", "pytest", "tests/test_oracle_pins.py", "tests/test_oracle_parallel.py",
+                        "-x", "-q", "-n", "6", "-p", "no:cacheprovider"],
+                       cwd=tmp_path, capture_output=True, text=True, timeout=900)
+    summary = [line for line in r.stdout.splitlines() if line.strip()][-1:]
+    if old:
+        assert r.returncode != 0 and any(" failed" in s for s in summary), f"{name} survived: {summary}"
+    else:
+        assert r.returncode == 0, summary
