@@ -1,7 +1,7 @@
 """Strength of the oracle's pins: each plausible mistake planted in a copy of
 the oracle (on the CPU, never in the oracle itself) makes some pin of
 test_oracle_pins.py or test_oracle_parallel.py fail, and the unchanged copy
-passes them all.  About 5 minutes on 6 cores, so it runs only with
+passes them all.  About 6 minutes on 6 cores, so it runs only with
 RS_MUTATION_TESTS=1."""
 import os
 import shutil
@@ -13,11 +13,15 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 pytestmark = pytest.mark.skipif(os.environ.get("RS_MUTATION_TESTS") != "1",
-                                reason="set RS_MUTATION_TESTS=1 (about 5 minutes)")
+                                reason="set RS_MUTATION_TESTS=1 (about 6 minutes)")
 
 # name -> (text of the oracle, its mistaken replacement)
 MUTANTS = {
     "unchanged": ("", ""),
+    # the string fingerprint (the library's own design)
+    "string_no_length_fold": ("uint64_t a = FP_HI ^ len, b = FP_LO ^ len;", "uint64_t a = FP_HI, b = FP_LO;"),
+    "string_last_word_dropped": ("for (uint64_t w = 0; w < nwords; w++)", "for (uint64_t w = 0; w + 1 < nwords; w++)"),
+    "string_byte_shift_wrong": ("word |= (uint64_t)p[pos] << (8 * k);", "word |= (uint64_t)p[pos] << (7 * k);"),
     # strategy (Sec. 5): s rounded down, t's small-leaf case one too far, interval bounds
     "strategy_s_floor": ("uint32_t s = (35 * leaf + 50 + 99) / 100;", "uint32_t s = (35 * leaf + 50) / 100;"),
     "strategy_t_le7": ("uint32_t t = leaf < 7 ?", "uint32_t t = leaf <= 7 ?"),
