@@ -22,6 +22,10 @@ MUTANTS = {
     "string_no_length_fold": ("uint64_t a = FP_HI ^ len, b = FP_LO ^ len;", "uint64_t a = FP_HI, b = FP_LO;"),
     "string_last_word_dropped": ("for (uint64_t w = 0; w < nwords; w++)", "for (uint64_t w = 0; w + 1 < nwords; w++)"),
     "string_byte_shift_wrong": ("word |= (uint64_t)p[pos] << (8 * k);", "word |= (uint64_t)p[pos] << (7 * k);"),
+    # buckets (Sec. 6.1) and the non-minimal leaf range (Sec. 9)
+    "bucket_modulo": ("return (uint64_t)(((unsigned __int128)hi * nb) >> 64);", "return hi % nb;"),
+    "nonminimal_range_floor": ("return m <= 1 ? m : m + (m * st->slack + 255) / 256;",
+                               "return m <= 1 ? m : m + (m * st->slack) / 256;"),
     # strategy (Sec. 5): s rounded down, t's small-leaf case one too far, interval bounds
     "strategy_s_floor": ("uint32_t s = (35 * leaf + 50 + 99) / 100;", "uint32_t s = (35 * leaf + 50) / 100;"),
     "strategy_t_le7": ("uint32_t t = leaf < 7 ?", "uint32_t t = leaf <= 7 ?"),

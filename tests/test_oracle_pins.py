@@ -330,6 +330,28 @@ def test_root_split_index_matches_tree(orc):
 # --------------------------------------------------------------------------
 # Buckets: sizes are Binomial(n, 1/nb) (Sec. 5).
 # --------------------------------------------------------------------------
+@pytest.mark.parametrize("nb", [1, 7, 1000, 123_457, (1 << 40) + 3])
+def test_bucket_of_is_monotone_fixed_point(orc, nb):
+    """Buckets come from the fixed-point product of the upper signature word
+    by the bucket count (Sec. 6.1), so sorted signatures fall into
+    non-decreasing buckets, the property that lets a construction scan sorted
+    signatures (Sec. 9); 0 maps to the first bucket, 2^64 - 1 to the last, and
+    the words just below a bucket's first value ceil(j 2^64 / nb) belong to the
+    previous bucket."""
+    rng = np.random.default_rng(12)
+    hi = np.sort(rng.integers(0, np.iinfo(np.uint64).max, size=100_000, dtype=np.uint64, endpoint=True))
+    hi = np.concatenate([np.array([0], np.uint64), hi, np.array([np.iinfo(np.uint64).max], np.uint64)])
+    ids = orc.bucket_ids(hi, nb)
+    assert int(ids[0]) == 0 and int(ids[-1]) == nb - 1
+    assert (ids[1:] >= ids[:-1]).all()
+    for j in [1, nb - 1] + [int(x) for x in rng.integers(1, max(nb, 2), size=40)]:
+        if not 1 <= j < nb:
+            continue
+        first = -(-(j << 64) // nb)
+        got = orc.bucket_ids(np.array([first - 1, first], dtype=np.uint64), nb)
+        assert [int(got[0]), int(got[1])] == [j - 1, j]
+
+
 @pytest.mark.parametrize("kind", ["u64", "ascii"])
 def test_bucket_sizes_are_binomial(orc, kind):
     n, nb = 400_000, 4000
