@@ -1,7 +1,7 @@
 """Strength of the oracle's pins: each plausible mistake planted in a copy of
 the oracle (on the CPU, never in the oracle itself) makes some pin of
 test_oracle_pins.py or test_oracle_parallel.py fail, and the unchanged copy
-passes them all.  About 6 minutes on 6 cores, so it runs only with
+passes them all.  About 8 minutes on 6 cores, so it runs only with
 RS_MUTATION_TESTS=1."""
 import os
 import shutil
@@ -13,7 +13,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 pytestmark = pytest.mark.skipif(os.environ.get("RS_MUTATION_TESTS") != "1",
-                                reason="set RS_MUTATION_TESTS=1 (about 6 minutes)")
+                                reason="set RS_MUTATION_TESTS=1 (about 8 minutes)")
 
 # name -> (text of the oracle, its mistaken replacement)
 MUTANTS = {
@@ -49,6 +49,12 @@ MUTANTS = {
     "fixed_part_high_bits": ("put_bits(tree, pos, node_v[s[i] + k] & ((1ULL << rr) - 1), rr);",
                              "put_bits(tree, pos, (node_v[s[i] + k] >> 1) & ((1ULL << rr) - 1), rr);"),
     # double Elias-Fano (Sec. 6.3, 7.4)
+    "rescale_s_skipped": ("    for (uint64_t i = 0; i < Nn; i++) {\n        ys[i] = qs[i] - i * delta_s;",
+                          "    delta_s = 0;\n    for (uint64_t i = 0; i < Nn; i++) {\n        ys[i] = qs[i] - i * delta_s;"),
+    "rescale_z_positive_skipped": ("    for (uint64_t i = 0; i < Nn; i++) {\n        ys[i] = qs[i] - i * delta_s;",
+                                   "    if (delta_z > 0) delta_z = 0;\n    for (uint64_t i = 0; i < Nn; i++) {\n"
+                                   "        ys[i] = qs[i] - i * delta_s;"),
+    "beta_zero": ("uint64_t beta = (total_bits << 16) / qs[nb];", "uint64_t beta = 0 * ((total_bits << 16) / qs[nb]);"),
     "beta_shift_17": ("z[i] = (int64_t)o[i] - (int64_t)((beta * qs[i]) >> 16);",
                       "z[i] = (int64_t)o[i] - (int64_t)((beta * qs[i]) >> 17);"),
     "inventory_lo_stride_2_7": ("if (k % (1ULL << ORC_INV_LO) == 0) {", "if (k % (1ULL << (ORC_INV_LO - 1)) == 0) {"),

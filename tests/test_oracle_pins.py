@@ -494,6 +494,23 @@ def test_inventory_finds_every_one(orc, n, leaf, bucket):
     assert orc.blob_check_inventory(blob) == 0
 
 
+@pytest.mark.parametrize("n,leaf,bucket", [(100_000, 8, 100), (40_000, 4, 2000), (50_000, 5, 5), (50, 8, 100),
+                                           (1000, 8, 2000)])
+def test_elias_fano_lists_rescaled_by_their_minimum_gaps(orc, n, leaf, bucket):
+    """Both lists are rescaled by their smallest gap before encoding (Sec.
+    6.3): the header's delta_s is the smallest bucket size of the decoded
+    first list, and delta_z the smallest step of z_i = o_i - floor(beta s_i)
+    (beta in 16.16 fixed point, Sec. 6.3) over the decoded lists: negative
+    for most shapes, positive (1) for the single-bucket ones here."""
+    blob = orc.build(inputs.u64_keys(n, 80 + leaf), leaf, bucket)
+    h = orc.header(blob)
+    s_, o_ = orc.blob_prefix(blob)
+    z = [int(o) - ((h["beta"] * int(s)) >> 16) for s, o in zip(s_, o_)]
+    assert h["delta_s"] == min(int(s_[i + 1]) - int(s_[i]) for i in range(len(s_) - 1))
+    assert h["delta_z"] == min(z[i + 1] - z[i] for i in range(len(z) - 1))
+    assert int(s_[-1]) == n and int(o_[-1]) == h["tree_bits"]
+
+
 @pytest.mark.parametrize("n,leaf,bucket,slack", [(1, 8, 100, 0), (17, 2, 3, 0), (70_000, 2, 1, 0), (200_000, 5, 5, 0),
                                                  (100_000, 8, 100, 0), (40_000, 4, 2000, 0), (50_000, 8, 100, 64)])
 def test_upper_bits_lie_below_three_bits_per_entry(orc, n, leaf, bucket, slack):
