@@ -511,6 +511,35 @@ def test_elias_fano_lists_rescaled_by_their_minimum_gaps(orc, n, leaf, bucket):
     assert int(s_[-1]) == n and int(o_[-1]) == h["tree_bits"]
 
 
+def _width(U: int, N: int) -> int:
+    """floor(lg(U / N)) for U >= N, else 0: the largest W with N 2^W <= U."""
+    W = 0
+    while N << (W + 1) <= U:
+        W += 1
+    return W
+
+
+@pytest.mark.parametrize("n,leaf,bucket,seed,U_s", [(20, 8, 10, 9007, 6), (20, 8, 10, 9048, 12),
+                                                    (100_000, 8, 100, 88, None), (50_000, 5, 5, 88, None),
+                                                    (40_000, 4, 2000, 88, None), (3000, 12, 9, 88, None)])
+def test_lower_width_is_floor_lg_of_range_over_entries(orc, n, leaf, bucket, seed, U_s):
+    """Each Elias-Fano list keeps floor(lg(U/N)) lower bits (Sec. 7.4), N
+    its entry count and U its largest rescaled value (0 bits when U < N).
+    The two 20-key sets (seeds found by a scan) have two buckets whose first
+    list ends exactly at U = 3 * 2 and 3 * 4, where the bound is attained."""
+    blob = orc.build(inputs.u64_keys(n, seed), leaf, bucket)
+    h = orc.header(blob)
+    s_, o_ = orc.blob_prefix(blob)
+    nb = h["nb"]
+    z = [int(o) - ((h["beta"] * int(s)) >> 16) for s, o in zip(s_, o_)]
+    us = int(s_[-1]) - nb * h["delta_s"]
+    uz = z[-1] - nb * h["delta_z"]
+    if U_s is not None:
+        assert nb == 2 and us == U_s
+    assert h["Ws"] == _width(us, nb + 1)
+    assert h["Wz"] == _width(uz, nb + 1)
+
+
 @pytest.mark.parametrize("n,leaf,bucket,slack", [(1, 8, 100, 0), (17, 2, 3, 0), (70_000, 2, 1, 0), (200_000, 5, 5, 0),
                                                  (100_000, 8, 100, 0), (40_000, 4, 2000, 0), (50_000, 8, 100, 64)])
 def test_upper_bits_lie_below_three_bits_per_entry(orc, n, leaf, bucket, slack):
