@@ -12,7 +12,11 @@
  *
  * Pins (checked by the CPU test-suite, not by re-typing these formulas):
  *   mixer            published SplitMix64 outputs (Steele, Lea, Flood 2014)
- *   buckets          chi-square against Binomial(n, 1/nb)         (Sec. 5)
+ *   string keys      length folded in; one flipped bit changes about half
+ *                    of both signature words (avalanche)
+ *   buckets          chi-square against Binomial(n, 1/nb)         (Sec. 5);
+ *                    ids monotone in the upper word, each bucket starting at
+ *                    ceil(j 2^64 / nb)                           (Sec. 6.1)
  *   search           minimality by brute force; mean trials per
  *                    leaf/split size against m^m/m! and 1/p of eq. (2)
  *   strategy + r     Theorem 1 (invariance) and 50-digit evaluation of eq. (4)
@@ -20,6 +24,12 @@
  *   space            bits/key against the values printed in Table tab:1M
  *   inventory        every one found through it equals a plain scan, also
  *                    with 16-bit offsets that overflow       (Sec. 7.4)
+ *   Elias-Fano       rescaling constants are the decoded lists' minimum
+ *                    gaps; lower widths floor(lg(U/N)), also on the power-of-
+ *                    two boundary; nb + 1 upper ones, all below bit 3 (nb + 1)
+ *                                                      (Sec. 6.3, Sec. 7.4)
+ * A separate test plants plausible mistakes in a copy of this file and checks
+ * that each makes one of these pins fail.
  * Exact seeds and blob bytes beyond that are "parity unpinned" by the paper
  * (its worked examples, Figs. 1-2, are not available); they are defined by
  * this file and the format readings.
