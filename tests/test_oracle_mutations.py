@@ -1,7 +1,7 @@
 """Strength of the oracle's pins: each plausible mistake planted in a copy of
 the oracle (on the CPU, never in the oracle itself) makes some pin of
 test_oracle_pins.py or test_oracle_parallel.py fail, and the unchanged copy
-passes them all.  About 13 minutes on 6 cores, so it runs only with
+passes them all.  About 15 minutes on 6 cores, so it runs only with
 RS_MUTATION_TESTS=1."""
 import os
 import shutil
@@ -13,7 +13,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 pytestmark = pytest.mark.skipif(os.environ.get("RS_MUTATION_TESTS") != "1",
-                                reason="set RS_MUTATION_TESTS=1 (about 13 minutes)")
+                                reason="set RS_MUTATION_TESTS=1 (about 15 minutes)")
 
 # name -> (text of the oracle, its mistaken replacement)
 MUTANTS = {
@@ -48,6 +48,11 @@ MUTANTS = {
                              "pos += (node_v[s[i] + k] >> rr) + 1; /* zeros */"),
     "fixed_part_high_bits": ("put_bits(tree, pos, node_v[s[i] + k] & ((1ULL << rr) - 1), rr);",
                              "put_bits(tree, pos, (node_v[s[i] + k] >> 1) & ((1ULL << rr) - 1), rr);"),
+    # lookup descent (Sec. 4): a leaf's rank reversed, earlier parts counted by size not range
+    "lookup_leaf_rank_reversed": ("if (m <= dc->st.leaf) return orc_phi(x, depth, v, leaf_range(&dc->st, m));",
+                                  "if (m <= dc->st.leaf) return leaf_range(&dc->st, m) - 1 - "
+                                  "orc_phi(x, depth, v, leaf_range(&dc->st, m));"),
+    "lookup_left_by_size": ("        left += dc->Q[parts[t]];", "        left += parts[t];"),
     # double Elias-Fano (Sec. 6.3, 7.4)
     "rescale_s_skipped": ("    for (uint64_t i = 0; i < Nn; i++) {\n        ys[i] = qs[i] - i * delta_s;",
                           "    delta_s = 0;\n    for (uint64_t i = 0; i < Nn; i++) {\n        ys[i] = qs[i] - i * delta_s;"),
