@@ -215,15 +215,18 @@ int rs_last_build_stats(rs_build_stats* out);
  *   keys   : device key set, n >= 1 distinct keys.
  *   leaf   : leaf size l, 1 <= l <= 24 (Sec. 5: l <= 24 keeps Golomb-Rice parameters
  *            below 32).
- *   bucket : average bucket size b >= 1; nb = ceil(n / b) buckets (Sec. 6.1).
+ *   bucket : average bucket size b >= 1; nb = ceil(n / b) buckets (Sec. 6.1), at
+ *            most 2^28 (268,435,456) in one call, counting every build of a
+ *            batch (RS_EINVAL beyond).
  *   stream : HIP stream; all device work is enqueued on it.  The call waits on the
  *            stream once, for the blob size: the search is sized for a
  *            bucket-size cap estimated from n and b (a bucket count is
  *            exceeded with probability below 1e-6); if a bucket is larger
  *            (skewed keys), the construction runs again sized for the
- *            largest bucket, with the same result.  When the calling thread
- *            has built this (leaf, bucket) shape before, with a key count
- *            within a factor of two, the blob is written before that wait
+ *            largest bucket, with the same result.  When the calling thread's
+ *            last single build had this shape (leaf, bucket, gr_table_max,
+ *            leaf_slack, select samples or not) and a key count within a
+ *            factor of two, the blob is written before that wait
  *            into memory sized from the earlier build (with
  *            a 1/8 margin; the environment variable RS_ARENA_GUESS scales it,
  *            0 turns it off); a blob that does not fit is written again after
