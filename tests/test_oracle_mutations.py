@@ -1,7 +1,7 @@
 """Strength of the oracle's pins: each plausible mistake planted in a copy of
 the oracle (on the CPU, never in the oracle itself) makes some pin of
 test_oracle_pins.py or test_oracle_parallel.py fail, and the unchanged copy
-passes them all.  About 15 minutes on 6 cores, so it runs only with
+passes them all.  About 17 minutes on 6 cores, so it runs only with
 RS_MUTATION_TESTS=1."""
 import os
 import shutil
@@ -13,7 +13,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 pytestmark = pytest.mark.skipif(os.environ.get("RS_MUTATION_TESTS") != "1",
-                                reason="set RS_MUTATION_TESTS=1 (about 15 minutes)")
+                                reason="set RS_MUTATION_TESTS=1 (about 17 minutes)")
 
 # name -> (text of the oracle, its mistaken replacement)
 MUTANTS = {
@@ -36,6 +36,12 @@ MUTANTS = {
     # eq. (4)
     "gr_floor_not_ceil": ("double x = ceil(log2(ratio));", "double x = floor(log2(ratio));"),
     "gr_log_p": ("double ratio = log(golden) / -log1p(-p);", "double ratio = log(golden) / -log(p);"),
+    # Sec. 7.1-7.2: the large-split approximation, lambda, the packed 32-bit table
+    "approx_fanout_term_halved": ("int64_t acc = (int64_t)(((f - 1) * 5) >> 1) - (int64_t)lambda_of(m);",
+                                  "int64_t acc = (int64_t)(((f - 1) * 5) >> 2) - (int64_t)lambda_of(m);"),
+    "lambda_plus_one": ("    while (x > 1) {\n        x >>= 1;\n        l++;", "    while (x > 0) {\n        x >>= 1;\n        l++;"),
+    "packed_count_field_shifted": ("else out[m] = r[m] | (N[m] << 5) | (F[m] << 16);",
+                                   "else out[m] = r[m] | (N[m] << 6) | (F[m] << 16);"),
     # searches take the first index from 0 (Sec. 4)
     "leaf_search_from_1": ("uint32_t depth, uint64_t cap, uint64_t* out) {\n    for (uint64_t v = 0;",
                            "uint32_t depth, uint64_t cap, uint64_t* out) {\n    for (uint64_t v = 1;"),
