@@ -1,7 +1,7 @@
 """Strength of the oracle's pins: each plausible mistake planted in a copy of
 the oracle (on the CPU, never in the oracle itself) makes some pin of
 test_oracle_pins.py or test_oracle_parallel.py fail, and the unchanged copy
-passes them all.  About 17 minutes on 6 cores, so it runs only with
+passes them all.  About 19 minutes on 6 cores, so it runs only with
 RS_MUTATION_TESTS=1."""
 import os
 import shutil
@@ -13,7 +13,7 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 pytestmark = pytest.mark.skipif(os.environ.get("RS_MUTATION_TESTS") != "1",
-                                reason="set RS_MUTATION_TESTS=1 (about 17 minutes)")
+                                reason="set RS_MUTATION_TESTS=1 (about 19 minutes)")
 
 # name -> (text of the oracle, its mistaken replacement)
 MUTANTS = {
